@@ -1,0 +1,272 @@
+"""Seeded synthetic inputs for the DEM step: positions, radii, velocities and
+the parameter dictionaries of the benchmark workloads.
+
+This module is shared by the GPU path's tests and by the oracle's tests, so it
+holds no part of the method's arithmetic (no grid, no contact test, no contact
+law, no integrator): only random numbers, lattices and the recipe numbers.
+
+The paper's own workload (Sec. 5: 2^17 equal spheres falling from a box
+through a slit, run until at rest) gives no geometry, so every workload here
+is synthetic.  Sizes are powers of two like the paper's 2^17.
+
+Parameter dictionary keys (each side marshals them into its own structure):
+  box_lo, box_hi     domain corners (m)
+  wall_mask          bit 2a: wall at box_lo[a]; bit 2a+1: wall at box_hi[a]
+  gravity            (m/s^2), added once per particle
+  dt, density        time step (s), particle density (kg/m^3)
+  law                "linear" (constant kn, kt), "hertz" (Eqs. 8-9: kn, kt are
+                     C_kn, C_kt) or "simple" (Eq. 1: simple_k = k_sp, k_da, k_sh)
+  kn, kt             normal / tangential spring
+  restitution        e, fixes the restitution parameter alpha of Eq. 10
+  eta_t_ratio        tangential damping as a fraction of the normal one
+  mu                 Coulomb friction coefficient (Eq. 5)
+  cell_size          requested cell width of the collision-detection grid
+  contacts_per_particle  history capacity per particle (GPU only)
+  precision          "fp64" or "mixed" (FP32 forces, FP64 positions; GPU only)
+"""
+import math
+
+import numpy as np
+
+RHO = 2500.0
+KN = 1.0e5
+E_REST = 0.9
+MU = 0.3
+G = (0.0, 0.0, -9.81)
+ALL_WALLS = 0x3F
+
+
+def base_params(**kw) -> dict:
+    p = dict(box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0), wall_mask=ALL_WALLS, gravity=G,
+             dt=1.0e-5, density=RHO, law="linear", kn=KN, kt=2.0 / 7.0 * KN, restitution=E_REST,
+             eta_t_ratio=0.0, mu=MU, simple_k=(0.0, 0.0, 0.0), cell_size=None,
+             contacts_per_particle=16, precision="fp64")
+    p.update(kw)
+    return p
+
+
+def linear_contact_time(kn: float, e: float, m_eff: float) -> float:
+    """Duration of a linear spring-dashpot contact of restitution e (the
+    damped half-period); used only to choose a stable time step."""
+    le = math.log(e)
+    zeta = -le / math.sqrt(math.pi ** 2 + le * le)
+    w0 = math.sqrt(kn / m_eff)
+    return math.pi / (w0 * math.sqrt(1.0 - zeta * zeta))
+
+
+def stable_dt(kn: float, e: float, r_min: float, rho: float = RHO, cap: float = 1.0e-5) -> float:
+    """dt = min(cap, t_c / 10) for the contact of the two smallest spheres."""
+    m = rho * 4.0 / 3.0 * math.pi * r_min ** 3
+    return min(cap, linear_contact_time(kn, e, 0.5 * m) / 10.0)
+
+
+def fp32_radii(r) -> np.ndarray:
+    """Radii as both paths store them (rounded to FP32)."""
+    return np.asarray(r, dtype=np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------- placements
+
+
+def rsa_positions(rng, radii, lo, hi, max_tries=200000):
+    """Random sequential addition of non-overlapping spheres inside walls.
+    Slow (pure Python loop over particles); for a few thousand spheres."""
+    radii = np.asarray(radii, dtype=np.float64)
+    n = radii.shape[0]
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    cell = 2.0 * radii.max()
+    dims = np.maximum(1, np.floor((hi - lo) / cell).astype(int))
+    buckets = {}
+    x = np.zeros((n, 3))
+    for i in range(n):
+        ri = radii[i]
+        for _ in range(max_tries):
+            p = lo + ri + rng.random(3) * (hi - lo - 2 * ri)
+            c = np.minimum(((p - lo) / (hi - lo) * dims).astype(int), dims - 1)
+            ok = True
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        for j in buckets.get((c[0] + dx, c[1] + dy, c[2] + dz), ()):
+                            if np.sum((x[j] - p) ** 2) <= (radii[j] + ri) ** 2:
+                                ok = False
+                                break
+                        if not ok:
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                x[i] = p
+                buckets.setdefault(tuple(c), []).append(i)
+                break
+        else:
+            raise RuntimeError("rsa_positions: box too full")
+    return x
+
+
+def fcc_sites(lo, hi, d_nn, margin):
+    """All face-centred-cubic sites with nearest-neighbour distance d_nn whose
+    distance to every face of [lo, hi] is at least margin."""
+    lo = np.asarray(lo, float) + margin
+    hi = np.asarray(hi, float) - margin
+    b = d_nn * math.sqrt(2.0)
+    counts = np.floor((hi - lo) / b).astype(int) + 1
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    ix = np.arange(counts[0])
+    iy = np.arange(counts[1])
+    iz = np.arange(counts[2])
+    out = []
+    for bv in basis:
+        X = lo[0] + (ix + bv[0]) * b
+        Y = lo[1] + (iy + bv[1]) * b
+        Z = lo[2] + (iz + bv[2]) * b
+        X = X[X <= hi[0]]
+        Y = Y[Y <= hi[1]]
+        Z = Z[Z <= hi[2]]
+        gz, gy, gx = np.meshgrid(Z, Y, X, indexing="ij")
+        out.append(np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1))
+    return np.concatenate(out, axis=0)
+
+
+def fcc_fill(rng, n, lo, hi, margin, jitter_frac=0.0, d_nn=None):
+    """n sites of an FCC lattice filling [lo, hi] (minus margin), chosen at
+    random when the lattice holds more, each jittered uniformly by up to
+    jitter_frac * (d_nn/2 - margin) per axis.  Returns (positions, d_nn)."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    vol = np.prod(hi - lo - 2 * margin)
+    if d_nn is None:
+        d_nn = (math.sqrt(2.0) * vol / n) ** (1.0 / 3.0)
+    while True:
+        sites = fcc_sites(lo, hi, d_nn, margin)
+        if sites.shape[0] >= n:
+            break
+        d_nn *= 0.995
+    pick = np.sort(rng.choice(sites.shape[0], size=n, replace=False))
+    x = sites[pick]
+    if jitter_frac > 0.0:
+        amp = jitter_frac * max(0.0, 0.5 * d_nn - margin)
+        x = x + rng.uniform(-amp, amp, size=x.shape)
+    return x, d_nn
+
+
+def lognormal_radii(rng, n, median, sigma, clip_sigmas=3.0):
+    z = np.clip(rng.standard_normal(n), -clip_sigmas, clip_sigmas)
+    return median * np.exp(sigma * z)
+
+
+# ---------------------------------------------------------------- workloads
+
+
+def plain_fp64(seed=1000, n=4096):
+    """4,096 equal spheres (r = 1/64) at random non-overlapping positions in a
+    walled unit box, v ~ N(0, 0.1^2) per axis, gravity -9.81 z, linear law
+    kn = 1e5, e = 0.9, kt = 2/7 kn, mu = 0.3, dt = 1e-5, FP64."""
+    rng = np.random.default_rng(seed)
+    r = fp32_radii(np.full(n, 1.0 / 64.0))
+    x = rsa_positions(rng, r, (0, 0, 0), (1, 1, 1))
+    v = rng.normal(0.0, 0.1, size=(n, 3))
+    w = np.zeros((n, 3))
+    p = base_params(cell_size=2.0 * r.max(), precision="fp64", dt=1.0e-5)
+    return dict(name=f"plain_fp64_{n}", params=p, x=x, v=v, omega=w, r=r)
+
+
+def gas_mixed(seed=2000, n=1 << 20, law="linear"):
+    """2^20 spheres, radii U[0.8, 1.2] / 256, a gas at packing fraction 0.3
+    filling the bottom of a walled unit box (jittered FCC), v ~ N(0, 0.1^2),
+    settling under gravity; FP32 forces with FP64 positions, dt = 1e-5."""
+    rng = np.random.default_rng(seed)
+    r0 = 1.0 / 256.0
+    r = fp32_radii(rng.uniform(0.8 * r0, 1.2 * r0, size=n))
+    vol = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
+    h = min(1.0, vol / 0.3)
+    x, _ = fcc_fill(rng, n, (0, 0, 0), (1, 1, h), margin=r.max(), jitter_frac=0.9)
+    v = rng.normal(0.0, 0.1, size=(n, 3))
+    w = np.zeros((n, 3))
+    p = base_params(cell_size=2.0 * r.max(), precision="mixed", dt=1.0e-5, law=law)
+    if law == "simple":
+        p["simple_k"] = simple_coefficients(r0)
+    return dict(name=f"gas_mixed_{n}", params=p, x=x, v=v, omega=w, r=r)
+
+
+def simple_coefficients(r_med, kn=KN, e=E_REST, rho=RHO):
+    """Constant coefficients of Eq. 1 for the comparison run: k_sp = kn and
+    k_da = k_sh = the damping of a median-radius linear contact of
+    restitution e (critical-damping fraction times 2 sqrt(kn M))."""
+    m = rho * 4.0 / 3.0 * math.pi * r_med ** 3
+    le = math.log(e)
+    zeta = -le / math.sqrt(math.pi ** 2 + le * le)
+    eta = 2.0 * zeta * math.sqrt(kn * 0.5 * m)
+    return (kn, eta, eta)
+
+
+def dense_bed_geometry(seed=3000, n=1 << 24, phi=0.55, median=1.0 / 512.0, sigma=0.2):
+    """Radii and box of the dense granular bed: log-normal radii (median
+    1/512, sigma 0.2, clipped to +-3 sigma), box of aspect 4:1:1 whose volume
+    is the total sphere volume / phi, gravity along the short z axis."""
+    rng = np.random.default_rng(seed)
+    r = fp32_radii(lognormal_radii(rng, n, median, sigma))
+    vol = float(np.sum(4.0 / 3.0 * math.pi * r ** 3)) / phi
+    ly = (vol / 4.0) ** (1.0 / 3.0)
+    hi = (4.0 * ly, ly, ly)
+    return rng, r, hi
+
+
+def dense_bed_params(r, hi, **kw):
+    r_min = float(np.min(r))
+    p = base_params(box_hi=hi, cell_size=2.0 * float(np.max(r)), precision="mixed",
+                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=16)
+    p.update(kw)
+    return p
+
+
+def dense_bed_lattice(seed=3000, n=1 << 24, phi=0.55):
+    """Starting point of the dense bed: every sphere on an FCC site of the
+    4:1:1 box, at rest.  With full radii neighbouring large spheres overlap;
+    the bed is prepared by growing the radii from the lattice's touching
+    scale (see ``lattice_scale``) to full size with strong damping."""
+    rng, r, hi = dense_bed_geometry(seed, n, phi)
+    x, d_nn = fcc_fill(rng, n, (0, 0, 0), hi, margin=float(r.max()), jitter_frac=0.0)
+    # the lattice is filled in a fixed order; shuffle which radius sits where
+    perm = rng.permutation(n)
+    r = r[perm]
+    p = dense_bed_params(r, hi)
+    z = np.zeros((n, 3))
+    return dict(name=f"dense_bed_{n}", params=p, x=x, v=z, omega=z.copy(), r=r, d_nn=d_nn)
+
+
+def lattice_scale(r, d_nn):
+    """Largest common radius scale at which no two lattice neighbours overlap."""
+    return min(1.0, d_nn / (2.0 * float(np.max(r))))
+
+
+def overlapping_cloud(seed, n, box=(1.0, 1.0, 1.0), r_mean=0.03, r_spread=0.2, spacing=0.95,
+                      v_sigma=0.1, w_sigma=10.0, law="linear", precision="fp64", walls=ALL_WALLS,
+                      jitter=0.3, **kw):
+    """A small, crowded test state: spheres on a jittered simple-cubic lattice
+    whose spacing is `spacing` times the mean diameter, so that many pairs and
+    the walls overlap; random velocities and spins.  For parity tests."""
+    rng = np.random.default_rng(seed)
+    r = fp32_radii(r_mean * (1.0 + r_spread * rng.uniform(-1, 1, size=n)))
+    a = spacing * 2.0 * r_mean
+    box = np.asarray(box, float)
+    dims = np.maximum(1, np.floor(box / a).astype(int))
+    if np.prod(dims) < n:
+        raise ValueError("overlapping_cloud: box too small for n")
+    idx = np.sort(rng.choice(int(np.prod(dims)), size=n, replace=False))
+    ijk = np.stack([idx % dims[0], (idx // dims[0]) % dims[1], idx // (dims[0] * dims[1])], axis=1)
+    x = (ijk + 0.5) * a + rng.uniform(-jitter * a, jitter * a, size=(n, 3))
+    x = np.clip(x, 0.5 * r_mean, box - 0.5 * r_mean)
+    v = rng.normal(0.0, v_sigma, size=(n, 3))
+    w = rng.normal(0.0, w_sigma, size=(n, 3))
+    p = base_params(box_hi=tuple(box), cell_size=2.0 * float(r.max()), law=law, precision=precision,
+                    wall_mask=walls, **kw)
+    if law == "simple":
+        p["simple_k"] = simple_coefficients(r_mean)
+    if law == "hertz":
+        p["kn"] = kw.get("kn", 1.0e7)
+        p["kt"] = kw.get("kt", 2.0 / 7.0 * p["kn"])
+    return dict(name=f"cloud_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r)

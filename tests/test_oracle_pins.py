@@ -1,0 +1,492 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix,
+independently of the oracle's own code: closed-form collisions, brute-force
+contact search, invariants and special cases.  CPU only.
+
+A plausible mistake in the oracle (a dropped term, a wrong sign, a transposed
+operand) breaks at least one of these:
+  - grid / sort (Sec. 4.1, Eq. 11): permutation, order, Eq. 11, containment
+  - detection (Eq. 12): brute-force O(N^2) set equality, pairs and walls
+  - normal spring + damping (Eqs. 4, 10): two-sphere and sphere-wall
+    closed forms (restitution and contact time)
+  - Hertz stiffness (Eqs. 8-9): undamped peak overlap and contact time
+  - tangential spring, torque and inertia (Eqs. 3, 4, 6, 7): stick
+    oscillation frequency sqrt(7 k_t / 2m)
+  - Coulomb cap + torque (Eqs. 3, 5): slide-to-roll at 5/7 v0
+  - simple model (Eq. 1): damped-oscillator closed form
+  - history orientation and Eq. 6 symmetry: relabelling invariance
+  - Eq. 7 projection: delta_t orthogonal to n
+  - whole step: momentum, energy, free fall, static rest, restart identity
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from scipy.special import beta as beta_fn
+
+from oracle.oracle import OracleError, OracleSystem
+from paper_1301_1714_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sphere_mass(r, rho=2500.0):
+    r = float(np.float32(r))
+    return rho * 4.0 / 3.0 * math.pi * r ** 3
+
+
+def zeta_of_e(e):
+    """Damping ratio of a linear oscillator whose half-period restitution is e,
+    found numerically from e = exp(-pi z / sqrt(1 - z^2))."""
+    if e >= 1.0:
+        return 0.0
+    return brentq(lambda z: math.exp(-math.pi * z / math.sqrt(1 - z * z)) - e, 1e-15, 0.999999)
+
+
+def two_spheres(params, r, u, gap=1e-7, center=0.5, rb=None):
+    rb = r if rb is None else rb
+    x = np.array([[center - r - gap, center, center], [center + rb + gap, center, center]])
+    v = np.array([[u, 0, 0], [-u, 0, 0]], float)
+    return OracleSystem(params, x, v, np.zeros((2, 3)), [r, rb])
+
+
+def crossing_times(sys_, nsteps, dt, fn):
+    """Step one at a time; return the interpolated times where fn(state)
+    changes sign, and the state sequence."""
+    vals = []
+    states = []
+    for _ in range(nsteps):
+        st = sys_.read_state()
+        vals.append(fn(st))
+        states.append(st)
+        sys_.step(1)
+    vals = np.array(vals)
+    t = []
+    for k in range(1, len(vals)):
+        if (vals[k - 1] < 0) != (vals[k] < 0):
+            f = vals[k - 1] / (vals[k - 1] - vals[k])
+            t.append((k - 1 + f) * dt)
+    return t, states
+
+
+# ---------------------------------------------------------------- grid
+
+
+def test_grid_invariants_eq11():
+    c = W.overlapping_cloud(7, 700, box=(0.5, 0.4, 0.45), r_mean=0.012, spacing=1.1)
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    cm, sccm, start = o.read_grid()
+    n = len(c["r"])
+    dims = o.grid_dims()
+    assert sorted(sccm.tolist()) == list(range(n))  # a permutation
+    scm = cm[sccm]  # Eq. 11: SCM[j] = CM[SCCM[j]]
+    assert np.all(np.diff(scm) >= 0)
+    same = np.diff(scm) == 0
+    assert np.all(np.diff(sccm)[same] > 0)  # ties broken by id
+    assert start[0] == 0 and start[-1] == n and np.all(np.diff(start) >= 0)
+    counts = np.bincount(cm, minlength=len(start) - 1)
+    assert np.array_equal(np.diff(start), counts)
+    assert np.array_equal(np.repeat(np.arange(len(counts)), counts), scm)
+    # every particle lies inside the box of its cell
+    lo = np.array(c["params"]["box_lo"])
+    hi = np.array(c["params"]["box_hi"])
+    width = (hi - lo) / np.array(dims)
+    ijk = np.stack([cm % dims[0], (cm // dims[0]) % dims[1], cm // (dims[0] * dims[1])], axis=1)
+    assert np.all(width >= c["params"]["cell_size"])
+    assert np.all(c["x"] >= lo + ijk * width - 1e-12)
+    assert np.all(c["x"] < lo + (ijk + 1) * width + 1e-12)
+
+
+def test_grid_clamps_near_box_and_rejects_far_outside():
+    p = W.base_params(cell_size=0.1, gravity=(0, 0, 0), wall_mask=0)
+    x = np.array([[-0.05, 0.5, 0.5], [1.05, 0.5, 0.5], [0.5, 0.5, 0.5]])
+    o = OracleSystem(p, x, np.zeros((3, 3)), np.zeros((3, 3)), [0.01] * 3)
+    cm, _, _ = o.read_grid()
+    dims = o.grid_dims()
+    assert cm[0] % dims[0] == 0 and cm[1] % dims[0] == dims[0] - 1
+    x[0, 0] = -0.11  # more than one cell outside
+    with pytest.raises(OracleError) as e:
+        OracleSystem(p, x, np.zeros((3, 3)), np.zeros((3, 3)), [0.01] * 3)
+    assert e.value.code == -4
+
+
+def test_cell_narrower_than_contact_distance_is_rejected():
+    p = W.base_params(cell_size=0.015)
+    with pytest.raises(OracleError) as e:
+        OracleSystem(p, [[0.5, 0.5, 0.5]], [[0, 0, 0]], [[0, 0, 0]], [0.01])
+    assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- detection
+
+
+def brute_force_contacts(x, r, lo, hi, wall_mask):
+    r = np.asarray(r, dtype=np.float32).astype(np.float64)
+    out = []
+    n = len(r)
+    for a in range(n):
+        d = x[a + 1:] - x[a]
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        S = r[a] + r[a + 1:]
+        for b in np.nonzero(d2 < S * S)[0]:
+            out.append((a, a + 1 + int(b)))
+        for w in range(6):
+            if (wall_mask >> w) & 1:
+                ax = w >> 1
+                gap = (hi[ax] - x[a, ax]) if (w & 1) else (x[a, ax] - lo[ax])
+                if gap < r[a]:
+                    out.append((a, -1 - w))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("seed,n,box,rm,spread,spacing,walls,cellfac", [
+    (1, 400, (0.3, 0.3, 0.3), 0.012, 0.0, 0.97, 0x3F, 1.0),
+    (2, 900, (0.5, 0.3, 0.4), 0.01, 0.3, 0.95, 0x3F, 1.0),
+    (3, 1500, (0.4, 0.4, 0.4), 0.008, 0.5, 0.9, 0x15, 1.0),
+    (4, 600, (0.25, 0.5, 0.2), 0.009, 0.2, 1.0, 0x2A, 1.7),
+    (5, 2000, (0.25, 0.18, 0.12), 0.007, 0.4, 0.93, 0x3F, 1.0),
+])
+def test_detection_equals_brute_force(seed, n, box, rm, spread, spacing, walls, cellfac):
+    c = W.overlapping_cloud(seed, n, box=box, r_mean=rm, r_spread=spread, spacing=spacing, walls=walls)
+    p = dict(c["params"])
+    p["cell_size"] *= cellfac
+    x = c["x"].copy()
+    rng = np.random.default_rng(seed)
+    # push a few particles into corners and slightly outside the box
+    for k in range(min(8, n)):
+        corner = np.where(rng.random(3) < 0.5, -0.3 * rm, np.array(box) + 0.3 * rm)
+        x[k] = corner + rng.uniform(-0.2 * rm, 0.2 * rm, size=3)
+    o = OracleSystem(p, x, c["v"], c["omega"], c["r"])
+    got = [tuple(t) for t in o.contacts().tolist()]
+    want = brute_force_contacts(x, c["r"], p["box_lo"], p["box_hi"], walls)
+    assert len(want) > n // 4
+    assert got == want
+
+
+def test_close_packing_twelve_contacts():
+    g = json.load(open(os.path.join(HERE, "golden", "close_packing.json")))
+    r = 0.01
+    x = W.fcc_sites((0, 0, 0), (0.2, 0.2, 0.2), 2 * r * 0.999, margin=r)
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), wall_mask=0, gravity=(0, 0, 0))
+    n = len(x)
+    o = OracleSystem(p, x, np.zeros((n, 3)), np.zeros((n, 3)), [r] * n)
+    pairs = o.contacts()
+    cnt = np.bincount(pairs.ravel(), minlength=n)
+    interior = np.all((x > 3 * r) & (x < 0.2 - 3 * r), axis=1)
+    assert interior.sum() > 20
+    assert np.all(cnt[interior] == g["max_contacts_equal_spheres"])
+    assert cnt.max() == g["max_contacts_equal_spheres"]
+
+
+# ---------------------------------------------------------------- closed forms
+
+
+def test_linear_two_sphere_head_on():
+    r, e, kn = 1.0 / 64.0, 0.9, 1.0e5
+    M = sphere_mass(r) / 2
+    z = zeta_of_e(e)
+    tc = math.pi / (math.sqrt(kn / M) * math.sqrt(1 - z * z))
+    assert abs(tc - 1.4048e-3) / 1.4048e-3 < 2e-4  # the value of the config-1 spheres
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=e)
+    u = 0.05
+    s = two_spheres(p, r, u)
+    S = 2 * float(np.float32(r))
+    t, states = crossing_times(s, 6000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - S)
+    assert len(t) == 2
+    tc_meas = t[1] - t[0]
+    v = states[-1]["v"]
+    e_meas = (v[1, 0] - v[0, 0]) / (2 * u)
+    assert abs(tc_meas - tc) / tc < 1e-3
+    assert abs(e_meas - e) / e < 1e-3
+    # a separated pair keeps no history
+    assert len(s.read_contacts()[0]) == 0
+
+
+def test_linear_sphere_wall_head_on():
+    r, e, kn = 1.0 / 64.0, 0.7, 1.0e5
+    m = sphere_mass(r)
+    z = zeta_of_e(e)
+    tc = math.pi / (math.sqrt(kn / m) * math.sqrt(1 - z * z))
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=1 << 4, dt=dt, restitution=e)
+    u = 0.05
+    rr = float(np.float32(r))
+    s = OracleSystem(p, [[0.5, 0.5, rr + 1e-7]], [[0, 0, -u]], [[0, 0, 0]], [r])
+    t, states = crossing_times(s, 6000, dt, lambda st: st["x"][0, 2] - rr)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    assert abs(states[-1]["v"][0, 2] / u - e) / e < 1e-3
+
+
+def test_static_rest_overlap():
+    r, kn = 1.0 / 64.0, 1.0e5
+    m = sphere_mass(r)
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=0.5, dt=1e-5)
+    rr = float(np.float32(r))
+    s = OracleSystem(p, [[0.1, 0.1, rr]], [[0, 0, 0]], [[0, 0, 0]], [r])
+    s.step(8000)
+    st = s.read_state()
+    delta = rr - st["x"][0, 2]
+    assert abs(delta - m * 9.81 / kn) / (m * 9.81 / kn) < 1e-6
+
+
+def test_free_fall_is_exact():
+    p = W.base_params(cell_size=0.1, wall_mask=0, dt=1e-5)
+    x0 = np.array([0.3, 0.4, 0.6])
+    v0 = np.array([0.1, -0.2, 1.0])
+    s = OracleSystem(p, [x0], [v0], [[0, 0, 0]], [0.01])
+    s.step(1000)
+    t = 1000 * 1e-5
+    want = x0 + v0 * t + 0.5 * np.array([0, 0, -9.81]) * t * t
+    st = s.read_state()
+    assert np.allclose(st["x"][0], want, rtol=0, atol=1e-12)  # 1000 steps of FP64 rounding
+    assert np.allclose(st["v"][0], v0 + np.array([0, 0, -9.81]) * t, rtol=0, atol=1e-12)
+
+
+def test_hertz_undamped_peak_and_duration():
+    r, C = 1.0 / 64.0, 1.0e7
+    rr = float(np.float32(r))
+    M = sphere_mass(r) / 2
+    K = C * math.sqrt(rr / 2)
+    u = 0.1
+    v0 = 2 * u
+    dmax = (5 * M * v0 ** 2 / (4 * K)) ** 0.4
+    tc = 0.8 * beta_fn(0.4, 0.5) * dmax / v0
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=1.0,
+                      law="hertz", kn=C, kt=0.0)
+    s = two_spheres(p, r, u)
+    t, states = crossing_times(s, 6000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - 2 * rr)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    dm = max(2 * rr - np.linalg.norm(st["x"][1] - st["x"][0]) for st in states)
+    assert abs(dm - dmax) / dmax < 1e-3
+    v = states[-1]["v"]
+    assert abs((v[1, 0] - v[0, 0]) / v0 - 1.0) < 1e-3
+
+
+def test_hertz_damped_restitution_independent_of_speed():
+    r, C = 1.0 / 64.0, 1.0e7
+    rr = float(np.float32(r))
+    es = []
+    for u in (0.05, 0.2):
+        M = sphere_mass(r) / 2
+        K = C * math.sqrt(rr / 2)
+        tc = 0.8 * beta_fn(0.4, 0.5) * (5 * M * (2 * u) ** 2 / (4 * K)) ** 0.4 / (2 * u)
+        dt = tc / 4000
+        p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=0.6,
+                          law="hertz", kn=C, kt=0.0)
+        s = two_spheres(p, r, u)
+        s.step(7000)
+        v = s.read_state()["v"]
+        es.append((v[1, 0] - v[0, 0]) / (2 * u))
+    assert 0.3 < es[0] < 0.95
+    assert abs(es[0] - es[1]) / es[0] < 1e-3
+
+
+def test_stick_oscillation_frequency():
+    r, kn = 1.0 / 64.0, 1.0e5
+    kt = 2.0 / 7.0 * kn
+    m = sphere_mass(r)
+    wt = math.sqrt(7 * kt / (2 * m))
+    assert abs(wt - math.sqrt(kn / m)) / wt < 1e-12
+    period = 2 * math.pi / wt
+    dt = period / 4000
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=1.0, mu=10.0, kt=kt, dt=dt,
+                      eta_t_ratio=0.0)
+    rr = float(np.float32(r))
+    z0 = rr - m * 9.81 / kn
+    s = OracleSystem(p, [[0.1, 0.1, z0]], [[1e-3, 0, 0]], [[0, 0, 0]], [r])
+    # the slip velocity v_x - r w_y oscillates about zero (the rolling mode
+    # v_x = r w_y has zero frequency and carries the mean)
+    t, _ = crossing_times(s, 9000, dt, lambda st: st["v"][0, 0] - rr * st["omega"][0, 1])
+    assert len(t) >= 4
+    measured = t[3] - t[1]  # alternate crossings are one period apart
+    assert abs(measured - period) / period < 1e-3
+
+
+def test_slide_to_roll_five_sevenths():
+    """A sphere launched sliding on the floor with no spin: friction mu m g
+    decelerates it (dv/dt = -mu g) and its torque spins it up
+    (r dw/dt = 5/2 mu g, from I = 2/5 m r^2) until the contact point sticks
+    at t* = 2 v0 / (7 mu g); it then rolls at 5/7 v0."""
+    r, mu, g = 1.0 / 64.0, 0.3, 9.81
+    m = sphere_mass(r)
+    v0 = 0.1
+    tstar = 2 * v0 / (7 * mu * g)
+    dt = 2e-6
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=0.5, mu=mu, dt=dt,
+                      eta_t_ratio=1.0)
+    rr = float(np.float32(r))
+    z0 = rr - m * g / p["kn"]
+    s = OracleSystem(p, [[0.05, 0.1, z0]], [[v0, 0, 0]], [[0, 0, 0]], [r])
+    ts, vx, rw = [], [], []
+    chunk = 100
+    for k in range(int(0.8 * tstar / dt) // chunk):
+        st = s.read_state()
+        ts.append(k * chunk * dt)
+        vx.append(st["v"][0, 0])
+        rw.append(rr * st["omega"][0, 1])
+        s.step(chunk)
+    a_v = np.polyfit(ts, vx, 1)
+    a_w = np.polyfit(ts, rw, 1)
+    assert abs(a_v[0] + mu * g) / (mu * g) < 1e-3
+    assert abs(a_w[0] - 2.5 * mu * g) / (2.5 * mu * g) < 1e-3
+    t_stick = (a_v[1] - a_w[1]) / (a_w[0] - a_v[0])  # where the two lines meet
+    assert abs(t_stick - tstar) / tstar < 1e-2
+    s.step(int(2.5 * tstar / dt))
+    st = s.read_state()
+    assert abs(st["v"][0, 0] - 5.0 / 7.0 * v0) / (5.0 / 7.0 * v0) < 1e-3
+    assert abs(rr * st["omega"][0, 1] - st["v"][0, 0]) / st["v"][0, 0] < 1e-3
+
+
+def test_simple_model_head_on():
+    r, kn = 1.0 / 64.0, 1.0e5
+    M = sphere_mass(r) / 2
+    kda = 5.0
+    gamma = kda / (2 * M)
+    wd = math.sqrt(kn / M - gamma ** 2)
+    tc = math.pi / wd
+    e = math.exp(-gamma * tc)
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, law="simple",
+                      simple_k=(kn, kda, 3.0))
+    u = 0.05
+    s = two_spheres(p, r, u)
+    rr = float(np.float32(r))
+    t, states = crossing_times(s, 6000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - 2 * rr)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    v = states[-1]["v"]
+    assert abs((v[1, 0] - v[0, 0]) / (2 * u) - e) / e < 1e-3
+    assert np.all(states[-1]["omega"] == 0.0)
+
+
+# ---------------------------------------------------------------- invariants
+
+
+def free_cloud(seed, n=300, law="linear", **kw):
+    c = W.overlapping_cloud(seed, n, box=(0.28, 0.28, 0.28), r_mean=0.02, spacing=0.98, jitter=0.05,
+                            walls=0, law=law, w_sigma=20.0, **kw)
+    p = dict(c["params"])
+    p.update(box_lo=(-0.4, -0.4, -0.4), box_hi=(1.0, 1.0, 1.0), gravity=(0.0, 0.0, 0.0))
+    c["params"] = p
+    return c
+
+
+@pytest.mark.parametrize("law", ["linear", "hertz", "simple"])
+def test_momentum_conservation(law):
+    c = free_cloud(11, law=law)
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    d0 = o.diagnostics()
+    m = np.array([sphere_mass(t) for t in c["r"]])
+    scale = np.sum(m * np.linalg.norm(c["v"], axis=1))
+    assert d0[7] > 50
+    for _ in range(10):
+        o.step(100)
+        d = o.diagnostics()
+        assert np.linalg.norm(d[:3] - d0[:3]) <= 1e-6 * scale
+
+
+def test_relabelling_invariance_with_history():
+    """Forces must not depend on particle labels: permute the ids (and
+    re-orient the history, stored as seen from the lower id) and compare."""
+    c = free_cloud(12)
+    p = dict(c["params"], mu=0.3, eta_t_ratio=0.5)
+    o = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    o.step(30)
+    st = o.read_state()
+    pairs, dts = o.read_contacts()
+    assert len(pairs) > 100
+    F, T = o.forces()
+    n = len(c["r"])
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(n)  # new id k holds old particle perm[k]
+    inv = np.argsort(perm)
+    np_pairs = []
+    np_dts = []
+    for (a, b), d in zip(pairs, dts):
+        if b < 0:
+            np_pairs.append((inv[a], b))
+            np_dts.append(d)
+        else:
+            na, nb = inv[a], inv[b]
+            if na < nb:
+                np_pairs.append((na, nb))
+                np_dts.append(d)
+            else:
+                np_pairs.append((nb, na))
+                np_dts.append(-d)
+    o2 = OracleSystem(p, st["x"][perm], st["v"][perm], st["omega"][perm], np.asarray(c["r"])[perm],
+                      hist_pairs=np_pairs, hist_dt=np_dts)
+    F2, T2 = o2.forces()
+    scale = np.abs(F).max()
+    assert np.allclose(F2, F[perm], rtol=0, atol=1e-12 * scale)
+    assert np.allclose(T2, T[perm], rtol=0, atol=1e-12 * np.abs(T).max())
+
+
+def test_galilean_invariance():
+    c = free_cloud(13)
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    F, T = o.forces()
+    shift_v = np.array([0.3, -0.2, 0.1])
+    o2 = OracleSystem(c["params"], c["x"], c["v"] + shift_v, c["omega"], c["r"])
+    F2, T2 = o2.forces()
+    assert np.allclose(F2, F, rtol=0, atol=1e-11 * np.abs(F).max())
+    assert np.allclose(T2, T, rtol=0, atol=1e-11 * np.abs(T).max())
+
+
+def test_history_stays_tangential():
+    c = free_cloud(14)
+    p = dict(c["params"], mu=0.3, eta_t_ratio=1.0)
+    o = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    o.step(25)
+    st = o.read_state()
+    pairs, dts = o.read_contacts()
+    assert len(pairs) > 100 and np.abs(dts).max() > 0
+    for (a, b), d in zip(pairs, dts):
+        assert b >= 0  # walls are off
+        nv = st["x"][b] - st["x"][a]
+        nv /= np.linalg.norm(nv)
+        assert abs(np.dot(d, nv)) <= 1e-12 * max(np.linalg.norm(d), 1e-300)
+
+
+def test_restart_is_bit_identical():
+    c = free_cloud(15)
+    p = dict(c["params"], mu=0.3)
+    a = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    a.step(40)
+    b = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    b.step(20)
+    st = b.read_state()
+    pairs, dts = b.read_contacts()
+    b2 = OracleSystem(p, st["x"], st["v"], st["omega"], c["r"], F0=st["F"], T0=st["T"], hist_pairs=pairs,
+                      hist_dt=dts)
+    b2.step(20)
+    sa, sb = a.read_state(), b2.read_state()
+    for k in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(sa[k], sb[k]), k
+    pa, da = a.read_contacts()
+    pb, db = b2.read_contacts()
+    assert np.array_equal(pa, pb) and np.array_equal(da, db)
+
+
+@pytest.mark.slow
+def test_energy_drift_plain_fp64_workload():
+    w = W.plain_fp64(seed=1000)
+    p = dict(w["params"], restitution=1.0, kt=0.0, mu=0.0)
+    o = OracleSystem(p, w["x"], w["v"], w["omega"], w["r"])
+    E = []
+    kin = []
+    for _ in range(100):
+        d = o.diagnostics()
+        E.append(d[3] + d[4] + d[5] + d[6])
+        kin.append(d[3])
+        o.step(100)
+    E = np.array(E)
+    assert np.max(np.abs(E - E[0])) / E[0] < 1e-4
+    # the same drift against the kinetic energy, a far tighter scale
+    assert np.max(np.abs(E - E[0])) / kin[0] < 1e-3
