@@ -1,0 +1,166 @@
+/*
+ * dem.h -- C ABI of libdem.so: one timestep of soft-sphere DEM on an AMD
+ * Instinct MI355X (gfx950), after Washizawa & Nakahara, "Parallel Computing
+ * of Discrete Element Method on GPU" (arXiv:1301.1714).
+ *
+ * The problem (Sec. 3 and Sec. 4.2): particles with position x, velocity v,
+ * angular velocity w, radius r and mass m; a contact law with spring,
+ * damping and friction parameters (Eqs. 2-10, or the simple law of Eq. 1);
+ * walls treated as particles of infinite radius (Step 8); a time step dt.
+ * One step runs Steps 1-8 of Sec. 4.2: update (kick-drift), cell hash,
+ * sort by cell, reorder, 27-cell sweep (Eq. 12), pair and wall forces, and
+ * the closing half kick.
+ *
+ * Conventions shared by every call:
+ *  - Host arrays are borrowed for the duration of the call; per-particle
+ *    vectors are row-major n x 3 (x0 y0 z0 x1 ...), FP64, in the caller's
+ *    particle order ("original order"; particle k has id k).
+ *  - Device memory: the caller allocates one workspace of at least
+ *    dem_workspace_bytes() bytes (any device allocation, 256-byte aligned)
+ *    and keeps it alive until dem_destroy().  The library never allocates
+ *    device memory itself.
+ *  - Streams: every device operation is enqueued on the hipStream_t given to
+ *    dem_create() (NULL = the legacy default stream).  dem_step() is
+ *    asynchronous; every call that returns host data synchronises that stream.
+ *  - Errors: status codes only, nothing throws across the ABI.  Errors found
+ *    on the device (contact-table overflow, particle out of domain,
+ *    non-finite force) are sticky: they are reported by the next synchronous
+ *    call and by every call after it.
+ *  - Radii are rounded to FP32 on input.
+ *  - Thread safety: calls on one system must not overlap; distinct systems
+ *    are independent.
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DEM_OK = 0,
+    DEM_E_INVALID = -1,          /* bad argument or parameter */
+    DEM_E_WORKSPACE = -2,        /* workspace missing or too small */
+    DEM_E_CONTACT_OVERFLOW = -3, /* a particle had more history entries than contacts_per_particle */
+    DEM_E_OUT_OF_DOMAIN = -4,    /* a particle went more than one cell outside the box */
+    DEM_E_NONFINITE = -5,        /* non-finite state or force */
+    DEM_E_HIP = -6,              /* a HIP runtime call failed */
+    DEM_E_STATE = -7,            /* system handle unusable (destroyed or failed) */
+    DEM_E_CAPACITY = -9          /* caller's output array too small; *n_out holds the size needed */
+} dem_status;
+
+typedef enum {
+    DEM_LAW_LINEAR = 0, /* Eqs. 2-7, 10 with constant kn, kt */
+    DEM_LAW_HERTZ = 1,  /* Eqs. 2-10: kn, kt are C_kn, C_kt of Eqs. 8-9 */
+    DEM_LAW_SIMPLE = 2  /* Eq. 1: F = -k_sp d n - k_da v - k_sh v_t, no torque, no history */
+} dem_law;
+
+typedef enum {
+    DEM_PREC_FP64 = 0,  /* everything FP64 (radii FP32) */
+    DEM_PREC_MIXED = 1  /* FP64 positions and reductions; FP32 v, w, forces, history */
+} dem_precision;
+
+/* Parameters of one system.  Sec. 3 names the contact-law inputs; the rest
+ * (box, walls, gravity, cell, capacity, precision) is the setting of Sec. 4. */
+typedef struct {
+    double box_lo[3], box_hi[3]; /* domain; the grid covers exactly this box */
+    uint32_t wall_mask;          /* bit 2a: wall at box_lo[a]; bit 2a+1: wall at box_hi[a] */
+    int32_t law;                 /* dem_law */
+    double gravity[3];           /* m/s^2, added once per particle */
+    double dt;                   /* time step, > 0 */
+    double density;              /* m = density 4/3 pi r^3, I = 2/5 m r^2 */
+    double kn, kt;               /* normal / tangential spring (Hertz: C_kn, C_kt) */
+    double restitution;          /* e in (0, 1]; alpha = -2 ln e / sqrt(pi^2 + ln^2 e) (Eq. 10) */
+    double eta_t_ratio;          /* tangential damping = eta_t_ratio * normal damping (Eq. 4) */
+    double mu;                   /* Coulomb coefficient (Eq. 5), >= 0 */
+    double simple_k[3];          /* k_sp, k_da, k_sh of Eq. 1 (DEM_LAW_SIMPLE only) */
+    double cell_size;            /* requested cell width (Sec. 4.1), >= 2 max radius */
+    int32_t contacts_per_particle; /* history capacity per particle: contacts with higher-id
+                                      partners plus walls; >= 1 */
+    int32_t precision;           /* dem_precision */
+} dem_params;
+
+typedef struct dem_system dem_system; /* opaque host-side handle */
+
+/* Device bytes needed for n particles with these parameters (grid size,
+ * capacity and precision all enter).  Errors: DEM_E_INVALID. */
+dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes);
+
+/* Create a system from host arrays (original order).
+ *   x, v, omega : n x 3; r : n (rounded to FP32).
+ *   F0, T0      : n x 3 contact force / torque of the state (from
+ *                 dem_read_state, for an exact restart) or both NULL: then
+ *                 they are evaluated on the state with the given history,
+ *                 and that evaluation's new history is not kept.
+ *   hist_pairs  : n_hist x 2 keys (a, b), a < b, of the tangential history
+ *                 of pair contacts, or (a, -1-w) for wall w; hist_dt its
+ *                 n_hist x 3 tangential displacements seen from a (Eq. 7).
+ *                 n_hist = 0 and NULLs for none.
+ *   workspace   : device memory of ws_bytes >= dem_workspace_bytes().
+ *   hip_stream  : hipStream_t for all work of this system.
+ * Synchronous.  Errors: DEM_E_INVALID (parameters, radii, keys, cell narrower
+ * than the largest contact distance), DEM_E_WORKSPACE, DEM_E_NONFINITE,
+ * DEM_E_OUT_OF_DOMAIN, DEM_E_CONTACT_OVERFLOW (history rows), DEM_E_HIP. */
+dem_status dem_create(const dem_params *p, int64_t n, const double *x, const double *v, const double *omega,
+                      const double *r, const double *F0, const double *T0, int64_t n_hist,
+                      const int64_t *hist_pairs, const double *hist_dt, void *workspace, size_t ws_bytes,
+                      void *hip_stream, dem_system **out);
+
+/* Enqueue nsteps kick-drift-kick steps (Sec. 4.2, Steps 1-8 each).
+ * Asynchronous; returns the sticky error if one is already known. */
+dem_status dem_step(dem_system *s, int64_t nsteps);
+
+/* Contact force and torque (gravity excluded) on every particle of the
+ * current state with the committed history, in original order; nothing is
+ * committed.  F, T: n x 3.  Synchronous. */
+dem_status dem_forces(dem_system *s, double *F, double *T);
+
+/* Current state in original order.  Any pointer may be NULL.  F, T are the
+ * contact forces of the last evaluation (those the next step's first half
+ * kick uses).  Synchronous. */
+dem_status dem_read_state(dem_system *s, double *x, double *v, double *omega, double *F, double *T);
+
+/* Committed tangential history: n_out entries, keys (a, b) as in dem_create,
+ * sorted by (a, b) ascending as signed integers, with their n x 3 delta_t.
+ * If cap < *n_out nothing is written and DEM_E_CAPACITY is returned.
+ * Synchronous. */
+dem_status dem_read_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs, double *delta_t);
+
+/* Contacts of the current positions (Steps 5-8 detection: pairs a < b with
+ * d^2 < (r_a + r_b)^2, walls as (a, -1-w)), sorted like dem_read_contacts.
+ * Synchronous. */
+dem_status dem_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs);
+
+/* Collision-detection grid of the current positions (Sec. 4.1, Eq. 11):
+ * cell_of_id[k] = CM[k]; id_at_slot[j] = SCCM[j] (ids sorted by (cell, id));
+ * cell_start: ncell + 1 entries, cell c holds slots [start[c], start[c+1]).
+ * Any pointer may be NULL.  Synchronous. */
+dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot, int32_t *cell_start);
+
+/* Cells per axis (x fastest in the cell index); ncell = product. */
+dem_status dem_grid_dims(dem_system *s, int32_t dims[3]);
+
+/* FP64 diagnostics of the current state, reduced in a fixed order:
+ *  out[0..2] momentum sum m v   out[3] kinetic energy   out[4] rotational
+ *  kinetic energy   out[5] potential energy -sum m g.(x - box_lo)
+ *  out[6] elastic energy of the current contacts (normal spring energy plus
+ *  1/2 k_t |delta_t|^2 with the committed history)   out[7] pair contacts
+ *  out[8] wall contacts   out[9] largest overlap.  Synchronous. */
+dem_status dem_diagnostics(dem_system *s, double out[10]);
+
+/* Wait for the system's stream; report any sticky error. */
+dem_status dem_sync(dem_system *s);
+
+/* Free the host handle (the workspace stays the caller's).  Waits for the
+ * stream first. */
+dem_status dem_destroy(dem_system *s);
+
+const char *dem_status_string(dem_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEM_H */

@@ -392,7 +392,7 @@ static const orc_hentry *hist_find(const orc_sys *s, int64_t a, int64_t b)
  * When commit is set the new history replaces the old one.              */
 
 static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, int64_t *npair,
-                    int64_t *nwall, double *dmax)
+                    int64_t *nwall, double *dmax, double *Fabs, double *Tabs)
 {
     orc_grid g;
     orc_clist L;
@@ -414,6 +414,8 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
     }
     memset(F, 0, sizeof(double) * 3 * (size_t)s->n);
     memset(T, 0, sizeof(double) * 3 * (size_t)s->n);
+    if (Fabs) memset(Fabs, 0, sizeof(double) * (size_t)s->n);
+    if (Tabs) memset(Tabs, 0, sizeof(double) * (size_t)s->n);
     double E = 0.0, Ec = 0.0, dm = 0.0;
     int64_t np = 0, nw = 0;
     for (int64_t k = 0; k < L.n; k++) {
@@ -445,6 +447,15 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
                 F[3 * b + q] -= Fc[q];
                 T[3 * b + q] += s->r[b] * nxft[q];
             }
+        }
+        if (Fabs) {
+            double fm = norm3(Fc);
+            Fabs[a] += fm;
+            if (b >= 0) Fabs[b] += fm;
+        }
+        if (Tabs) {
+            Tabs[a] += s->r[a] * norm3(nxft);
+            if (b >= 0) Tabs[b] += s->r[b] * norm3(nxft);
         }
         if (Hn) {
             Hn[k].a = a;
@@ -644,7 +655,7 @@ int orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
         st = grid_build(s, &g); /* domain check */
         if (st == ORC_OK) grid_free(&g);
     } else {
-        st = evaluate(s, s->F, s->T, 0, NULL, NULL, NULL, NULL);
+        st = evaluate(s, s->F, s->T, 0, NULL, NULL, NULL, NULL, NULL, NULL);
     }
     if (st != ORC_OK) {
         orc_destroy(s);
@@ -662,7 +673,7 @@ int orc_step(orc_sys *s, int64_t nsteps)
     for (int64_t k = 0; k < nsteps; k++) {
         half_kick(s);
         for (int64_t i = 0; i < 3 * s->n; i++) s->x[i] += s->p.dt * s->v[i];
-        int st = evaluate(s, s->F, s->T, 1, NULL, NULL, NULL, NULL);
+        int st = evaluate(s, s->F, s->T, 1, NULL, NULL, NULL, NULL, NULL, NULL);
         if (st != ORC_OK) return st;
         half_kick(s);
         s->steps++;
@@ -675,7 +686,16 @@ int orc_step(orc_sys *s, int64_t nsteps)
 int orc_forces(orc_sys *s, double *F, double *T)
 {
     if (!s || !F || !T) return ORC_E_INVALID;
-    return evaluate(s, F, T, 0, NULL, NULL, NULL, NULL);
+    return evaluate(s, F, T, 0, NULL, NULL, NULL, NULL, NULL, NULL);
+}
+
+/* The same, plus the error scale of every particle's force and torque:
+ * the sums of the magnitudes of the contact forces (and torques) acting on
+ * it.  A particle without contacts has scale 0. */
+int orc_forces_scale(orc_sys *s, double *F, double *T, double *Fabs, double *Tabs)
+{
+    if (!s || !F || !T) return ORC_E_INVALID;
+    return evaluate(s, F, T, 0, NULL, NULL, NULL, NULL, Fabs, Tabs);
 }
 
 int orc_read_state(const orc_sys *s, double *x, double *v, double *w, double *F, double *T)
@@ -797,7 +817,7 @@ int orc_diagnostics(orc_sys *s, double out[10])
     }
     double E, dm;
     int64_t np, nw;
-    int st = evaluate(s, F, T, 0, &E, &np, &nw, &dm);
+    int st = evaluate(s, F, T, 0, &E, &np, &nw, &dm, NULL, NULL);
     free(F);
     free(T);
     if (st != ORC_OK) return st;

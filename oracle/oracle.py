@@ -51,6 +51,8 @@ def lib():
         L.orc_step.restype = C.c_int
         L.orc_forces.argtypes = [P, P, P]
         L.orc_forces.restype = C.c_int
+        L.orc_forces_scale.argtypes = [P, P, P, P, P]
+        L.orc_forces_scale.restype = C.c_int
         L.orc_read_state.argtypes = [P, P, P, P, P, P]
         L.orc_read_state.restype = C.c_int
         L.orc_read_contacts.argtypes = [P, I64, C.POINTER(I64), P, P]
@@ -145,6 +147,16 @@ class OracleSystem:
         T = np.zeros((self.n, 3))
         self._check(lib().orc_forces(self._h, _ptr(F), _ptr(T)), "forces")
         return F, T
+
+    def forces_scale(self):
+        """Forces, torques and their per-particle error scales (sum of the
+        magnitudes of the contact forces / torques on each particle)."""
+        F = np.zeros((self.n, 3))
+        T = np.zeros((self.n, 3))
+        Fa = np.zeros(self.n)
+        Ta = np.zeros(self.n)
+        self._check(lib().orc_forces_scale(self._h, _ptr(F), _ptr(T), _ptr(Fa), _ptr(Ta)), "forces_scale")
+        return F, T, Fa, Ta
 
     def read_state(self):
         out = [np.zeros((self.n, 3)) for _ in range(5)]

@@ -1,0 +1,664 @@
+// dem_api.hip -- the C ABI of libdem.so (declared in include/dem.h).
+//
+// Host side of one system: parameter validation, carving of the caller's
+// workspace into the arrays of dem_internal.h, the per-step launch sequence
+// of Sec. 4.2 (Steps 1-8), and the synchronous read-back calls, which return
+// everything in the caller's original particle order.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "dem_internal.h"
+
+using namespace dem;
+
+struct dem_system {
+  dem_params p;
+  int32_t n;
+  int32_t K;
+  int prec;
+  size_t rsz;  // sizeof(Real)
+  Grid grid;
+  Consts c;
+  PosBuf pos[2];
+  VelBuf vel[2];
+  int cp, cv, ch;
+  void *F[3], *T[3], *Fe[3], *Te[3];
+  int32_t *cell, *rank, *perm, *scell, *counts, *cell_start;
+  ScanScratch scan;
+  HistBuf hist[2];
+  DiagBuf diag;
+  int32_t *err;
+  hipStream_t stream;
+  dem_status sticky;
+  int64_t steps;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  void *take_bytes(size_t bytes) { return take<char>(bytes); }
+};
+
+dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
+  if (!p || n < 0 || n >= (int64_t)INT32_MAX - 1) return DEM_E_INVALID;
+  if (!(p->dt > 0.0) || !isfinite(p->dt) || !(p->density > 0.0) || !(p->cell_size > 0.0)) return DEM_E_INVALID;
+  if (p->law < DEM_LAW_LINEAR || p->law > DEM_LAW_SIMPLE) return DEM_E_INVALID;
+  if (!(p->restitution > 0.0 && p->restitution <= 1.0) || !(p->mu >= 0.0)) return DEM_E_INVALID;
+  if (p->precision != DEM_PREC_FP64 && p->precision != DEM_PREC_MIXED) return DEM_E_INVALID;
+  if (p->contacts_per_particle < 1 || p->contacts_per_particle > 1024) return DEM_E_INVALID;
+  if (p->wall_mask > 0x3F) return DEM_E_INVALID;
+  if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
+  int64_t ncell = 1;
+  for (int a = 0; a < 3; a++) {
+    const double L = p->box_hi[a] - p->box_lo[a];
+    if (!(L > 0.0) || !isfinite(L)) return DEM_E_INVALID;
+    const double nf = floor(L / p->cell_size);
+    if (nf < 1.0 || nf > 1.0e6) return DEM_E_INVALID;
+    g->nc[a] = (int32_t)nf;
+    g->sc[a] = (double)g->nc[a] / L;
+    g->lo[a] = p->box_lo[a];
+    g->hi[a] = p->box_hi[a];
+    ncell *= g->nc[a];
+  }
+  if (ncell >= (int64_t)INT32_MAX - 1) return DEM_E_INVALID;
+  g->ncell = ncell;
+  return DEM_OK;
+}
+
+// Lay the arrays out in the workspace; with base == nullptr only sizes.
+size_t carve(dem_system *s, char *base) {
+  Carver cv{base};
+  const size_t N = (size_t)(s->n > 0 ? s->n : 1);
+  const size_t K = (size_t)s->K;
+  const size_t R = s->rsz;
+  for (int b = 0; b < 2; b++) {
+    s->pos[b].x = cv.take<double>(N);
+    s->pos[b].y = cv.take<double>(N);
+    s->pos[b].z = cv.take<double>(N);
+    s->pos[b].r = cv.take<float>(N);
+    s->pos[b].id = cv.take<int32_t>(N);
+    for (int k = 0; k < 3; k++) s->vel[b].v[k] = cv.take_bytes(R * N);
+    for (int k = 0; k < 3; k++) s->vel[b].w[k] = cv.take_bytes(R * N);
+  }
+  for (int k = 0; k < 3; k++) s->F[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) s->T[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) s->Fe[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) s->Te[k] = cv.take_bytes(R * N);
+  s->cell = cv.take<int32_t>(N);
+  s->rank = cv.take<int32_t>(N);
+  s->perm = cv.take<int32_t>(N);
+  s->scell = cv.take<int32_t>(N);
+  s->counts = cv.take<int32_t>((size_t)s->grid.ncell);
+  s->cell_start = cv.take<int32_t>((size_t)s->grid.ncell + 1);
+  int64_t lens[4] = {0, 0, 0, 0};
+  int nl = 0;
+  scan_scratch_len(s->grid.ncell, lens, &nl);
+  s->scan.nlevels = nl;
+  for (int l = 0; l < 4; l++) {
+    s->scan.len[l] = lens[l];
+    s->scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
+  }
+  for (int b = 0; b < 2; b++) {
+    s->hist[b].cnt = cv.take<int32_t>(N);
+    s->hist[b].partner = cv.take<int32_t>(K * N);
+    s->hist[b].d = cv.take_bytes(3 * K * N * R);
+  }
+  s->diag.e_el = cv.take<double>(N);
+  s->diag.npair = cv.take<int32_t>(N);
+  s->diag.nwall = cv.take<int32_t>(N);
+  s->diag.dmax = cv.take<double>(N);
+  s->diag.partial = cv.take<double>((size_t)diag_blocks(s->n) * 10);
+  s->diag.out = cv.take<double>(10);
+  s->err = cv.take<int32_t>(64);
+  return (cv.off + 255) & ~size_t(255);
+}
+
+void fill_consts(dem_system *s) {
+  const dem_params &p = s->p;
+  Consts &c = s->c;
+  c.dt = p.dt;
+  c.half_dt = 0.5 * p.dt;
+  c.mass_c = p.density * (4.0 / 3.0) * kPi;
+  const double le = log(p.restitution);
+  c.alpha = p.restitution >= 1.0 ? 0.0 : -2.0 * le / sqrt(kPi * kPi + le * le);
+  c.eta_t_ratio = p.eta_t_ratio;
+  c.kn = p.kn;
+  c.kt = p.kt;
+  c.mu = p.mu;
+  c.k_sp = p.simple_k[0];
+  c.k_da = p.simple_k[1];
+  c.k_sh = p.simple_k[2];
+  for (int k = 0; k < 3; k++) c.g[k] = p.gravity[k];
+  c.wall_mask = p.wall_mask;
+  c.law = p.law;
+}
+
+dem_status map_err(int32_t bits) {
+  if (bits & ERR_DOMAIN) return DEM_E_OUT_OF_DOMAIN;
+  if (bits & ERR_NONFINITE) return DEM_E_NONFINITE;
+  if (bits & ERR_OVERFLOW) return DEM_E_CONTACT_OVERFLOW;
+  return DEM_OK;
+}
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    if ((expr) != hipSuccess) {            \
+      (void)hipGetLastError();             \
+      return DEM_E_HIP;                    \
+    }                                      \
+  } while (0)
+
+dem_status sync_and_check(dem_system *s) {
+  if (s->sticky != DEM_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    return s->sticky;
+  }
+  int32_t bits = 0;
+  if (hipMemcpyAsync(&bits, s->err, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    s->sticky = DEM_E_HIP;
+    return s->sticky;
+  }
+  s->sticky = map_err(bits);
+  return s->sticky;
+}
+
+ForceArgs force_args(dem_system *s, int mode, void *const F[3], void *const T[3], const HistBuf &hnew) {
+  ForceArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pos = s->pos[s->cp];
+  a.vel_in = s->vel[s->cv];
+  a.vel_out = s->vel[s->cv ^ 1];
+  a.scell = s->scell;
+  a.cell_start = s->cell_start;
+  a.perm = s->perm;
+  a.hold = s->hist[s->ch];
+  a.hnew = hnew;
+  for (int k = 0; k < 3; k++) {
+    a.F[k] = F[k];
+    a.T[k] = T[k];
+  }
+  a.diag = s->diag;
+  a.K = s->K;
+  a.n = s->n;
+  a.mode = mode;
+  a.grid = s->grid;
+  a.c = s->c;
+  a.err = s->err;
+  return a;
+}
+
+// device -> host copy of a Real array as doubles
+dem_status d2h_real(dem_system *s, const void *src, std::vector<double> &out) {
+  out.resize((size_t)s->n);
+  if (s->n == 0) return DEM_OK;
+  if (s->prec == DEM_PREC_FP64) {
+    HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<float> tmp((size_t)s->n);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), src, sizeof(float) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int32_t i = 0; i < s->n; i++) out[i] = (double)tmp[i];
+  }
+  return DEM_OK;
+}
+
+template <typename T>
+dem_status d2h(dem_system *s, const T *src, std::vector<T> &out, size_t count) {
+  out.resize(count);
+  if (count == 0) return DEM_OK;
+  HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return DEM_OK;
+}
+
+dem_status h2d_real(dem_system *s, void *dst, const std::vector<double> &src) {
+  if (src.empty()) return DEM_OK;
+  if (s->prec == DEM_PREC_FP64) {
+    HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::vector<float> tmp(src.size());
+    for (size_t i = 0; i < src.size(); i++) tmp[i] = (float)src[i];
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return DEM_OK;
+}
+
+// per-particle vector (n x 3, original order) -> three SoA arrays in slot order
+void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, std::vector<double> &out) {
+  out.resize(id_at_slot.size());
+  for (size_t s = 0; s < id_at_slot.size(); s++) out[s] = src[3 * (size_t)id_at_slot[s] + k];
+}
+
+struct Entry {
+  int64_t a, b;
+  double d[3];
+};
+
+// Read a history table (rows in slot order) as sorted (a, b) entries.
+dem_status read_table(dem_system *s, const HistBuf &hb, bool with_d, std::vector<Entry> &out) {
+  out.clear();
+  if (s->n == 0) return DEM_OK;
+  const size_t N = (size_t)s->n, K = (size_t)s->K;
+  std::vector<int32_t> cnt, partner, id;
+  dem_status st;
+  if ((st = d2h(s, hb.cnt, cnt, N)) != DEM_OK) return st;
+  if ((st = d2h(s, hb.partner, partner, K * N)) != DEM_OK) return st;
+  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  std::vector<double> d;
+  if (with_d) {
+    d.resize(3 * K * N);
+    if (s->prec == DEM_PREC_FP64) {
+      HIP_TRY(hipMemcpyAsync(d.data(), hb.d, sizeof(double) * d.size(), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+    } else {
+      std::vector<float> tmp(3 * K * N);
+      HIP_TRY(hipMemcpyAsync(tmp.data(), hb.d, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(hipStreamSynchronize(s->stream));
+      for (size_t i = 0; i < tmp.size(); i++) d[i] = (double)tmp[i];
+    }
+  }
+  for (size_t slot = 0; slot < N; slot++) {
+    const int32_t c = std::min<int32_t>(cnt[slot], (int32_t)K);
+    for (int32_t k = 0; k < c; k++) {
+      Entry e;
+      e.a = id[slot];
+      e.b = partner[(size_t)k * N + slot];
+      for (int q = 0; q < 3; q++) e.d[q] = with_d ? d[((size_t)q * K + k) * N + slot] : 0.0;
+      out.push_back(e);
+    }
+  }
+  std::sort(out.begin(), out.end(), [](const Entry &x, const Entry &y) {
+    return x.a != y.a ? x.a < y.a : x.b < y.b;
+  });
+  return DEM_OK;
+}
+
+dem_status fill_i32(dem_system *s, int32_t *p, size_t count, int32_t value) {
+  if (count == 0) return DEM_OK;
+  if (value == 0) {
+    HIP_TRY(hipMemsetAsync(p, 0, count * sizeof(int32_t), s->stream));
+  } else {
+    std::vector<int32_t> tmp(count, value);
+    HIP_TRY(hipMemcpyAsync(p, tmp.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dem_status_string(dem_status st) {
+  switch (st) {
+    case DEM_OK: return "ok";
+    case DEM_E_INVALID: return "invalid argument";
+    case DEM_E_WORKSPACE: return "workspace missing or too small";
+    case DEM_E_CONTACT_OVERFLOW: return "contact history table overflow";
+    case DEM_E_OUT_OF_DOMAIN: return "particle out of domain";
+    case DEM_E_NONFINITE: return "non-finite state or force";
+    case DEM_E_HIP: return "HIP runtime error";
+    case DEM_E_STATE: return "system handle unusable";
+    case DEM_E_CAPACITY: return "output capacity too small";
+  }
+  return "unknown status";
+}
+
+dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes) {
+  if (!bytes) return DEM_E_INVALID;
+  dem_system s;
+  memset(&s, 0, sizeof(s));
+  dem_status st = check_params(p, n, &s.grid);
+  if (st != DEM_OK) return st;
+  s.n = (int32_t)n;
+  s.K = p->contacts_per_particle;
+  s.prec = p->precision;
+  s.rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  *bytes = carve(&s, nullptr);
+  return DEM_OK;
+}
+
+dem_status dem_create(const dem_params *p, int64_t n, const double *x, const double *v, const double *omega,
+                      const double *r, const double *F0, const double *T0, int64_t n_hist,
+                      const int64_t *hist_pairs, const double *hist_dt, void *workspace, size_t ws_bytes,
+                      void *hip_stream, dem_system **out) {
+  if (!out) return DEM_E_INVALID;
+  *out = nullptr;
+  Grid g;
+  dem_status st = check_params(p, n, &g);
+  if (st != DEM_OK) return st;
+  if (n > 0 && (!x || !v || !omega || !r)) return DEM_E_INVALID;
+  if ((F0 == nullptr) != (T0 == nullptr)) return DEM_E_INVALID;
+  if (n_hist < 0 || (n_hist > 0 && (!hist_pairs || !hist_dt))) return DEM_E_INVALID;
+  // radii (FP32), the cell width needed by the 27-cell search, finiteness
+  std::vector<float> rf((size_t)n);
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; i++) {
+    const float q = (float)r[i];
+    if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
+    rf[i] = q;
+    rmax = std::max(rmax, (double)q);
+  }
+  if (p->cell_size < 2.0 * rmax) return DEM_E_INVALID;
+  for (int64_t i = 0; i < 3 * n; i++)
+    if (!isfinite(x[i]) || !isfinite(v[i]) || !isfinite(omega[i])) return DEM_E_NONFINITE;
+  if (F0)
+    for (int64_t i = 0; i < 3 * n; i++)
+      if (!isfinite(F0[i]) || !isfinite(T0[i])) return DEM_E_NONFINITE;
+  const bool keep_hist = p->law != DEM_LAW_SIMPLE && n_hist > 0;
+  if (keep_hist) {
+    for (int64_t k = 0; k < n_hist; k++) {
+      const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
+      const bool ok = a >= 0 && a < n && ((b > a && b < n) || (b < 0 && b >= -6));
+      if (!ok) return DEM_E_INVALID;
+      for (int q = 0; q < 3; q++)
+        if (!isfinite(hist_dt[3 * k + q])) return DEM_E_NONFINITE;
+    }
+  }
+
+  dem_system *s = new (std::nothrow) dem_system;
+  if (!s) return DEM_E_INVALID;
+  memset(s, 0, sizeof(*s));
+  s->p = *p;
+  s->n = (int32_t)n;
+  s->K = p->contacts_per_particle;
+  s->prec = p->precision;
+  s->rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  s->grid = g;
+  s->stream = (hipStream_t)hip_stream;
+  fill_consts(s);
+  const size_t need = carve(s, nullptr);
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) {
+    delete s;
+    return DEM_E_WORKSPACE;
+  }
+  carve(s, (char *)workspace);
+
+  auto fail = [&](dem_status e) {
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+    return e;
+  };
+  const size_t N = (size_t)n;
+  if (fill_i32(s, s->err, 64, 0) != DEM_OK) return fail(DEM_E_HIP);
+  // upload in original order into buffer 0
+  std::vector<int32_t> ids(N);
+  std::iota(ids.begin(), ids.end(), 0);
+  {
+    std::vector<double> tmp;
+    const PosBuf &pb = s->pos[0];
+    double *dst[3] = {pb.x, pb.y, pb.z};
+    for (int k = 0; k < 3; k++) {
+      gather3(x, ids, k, tmp);
+      if (N && (hipMemcpyAsync(dst[k], tmp.data(), 8 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+                hipStreamSynchronize(s->stream) != hipSuccess))
+        return fail(DEM_E_HIP);
+    }
+    for (int k = 0; k < 3; k++) {
+      gather3(v, ids, k, tmp);
+      if (h2d_real(s, s->vel[0].v[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
+      gather3(omega, ids, k, tmp);
+      if (h2d_real(s, s->vel[0].w[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
+    }
+    if (N && (hipMemcpyAsync(pb.r, rf.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+              hipMemcpyAsync(pb.id, ids.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+              hipStreamSynchronize(s->stream) != hipSuccess))
+      return fail(DEM_E_HIP);
+  }
+  // Steps 2-4 on the initial positions
+  if (launch_hash(s->pos[0], s->n, s->grid, s->cell, s->err, s->stream) != hipSuccess) return fail(DEM_E_HIP);
+  if (launch_sort(s->cell, s->pos[0].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
+                  s->scan, s->stream) != hipSuccess)
+    return fail(DEM_E_HIP);
+  if (launch_reorder(s->prec, s->pos[0], s->vel[0], s->pos[1], s->vel[1], s->perm, s->cell, s->scell, s->n,
+                     s->stream) != hipSuccess)
+    return fail(DEM_E_HIP);
+  s->cp = 1;
+  s->cv = 1;
+  s->ch = 0;
+  st = sync_and_check(s);
+  if (st != DEM_OK) return fail(st);
+  std::vector<int32_t> id_at_slot;
+  if (d2h(s, s->pos[1].id, id_at_slot, N) != DEM_OK) return fail(DEM_E_HIP);
+  // history rows, in sorted-slot order
+  for (int b = 0; b < 2; b++)
+    if (fill_i32(s, s->hist[b].cnt, N, 0) != DEM_OK) return fail(DEM_E_HIP);
+  if (keep_hist) {
+    std::vector<int32_t> slot_of(N);
+    for (size_t sl = 0; sl < N; sl++) slot_of[id_at_slot[sl]] = (int32_t)sl;
+    const size_t K = (size_t)s->K;
+    std::vector<int32_t> cnt(N, 0), partner(K * N, 0);
+    std::vector<double> d(3 * K * N, 0.0);
+    for (int64_t k = 0; k < n_hist; k++) {
+      const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
+      const int32_t sl = slot_of[a];
+      const int32_t e = cnt[sl]++;
+      if (e >= (int32_t)K) return fail(DEM_E_CONTACT_OVERFLOW);
+      for (int32_t q = 0; q < e; q++)
+        if (partner[(size_t)q * N + sl] == (int32_t)b) return fail(DEM_E_INVALID);  // duplicate key
+      partner[(size_t)e * N + sl] = (int32_t)b;
+      for (int q = 0; q < 3; q++) d[((size_t)q * K + e) * N + sl] = hist_dt[3 * k + q];
+    }
+    const HistBuf &hb = s->hist[0];
+    if (hipMemcpyAsync(hb.cnt, cnt.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(hb.partner, partner.data(), 4 * K * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return fail(DEM_E_HIP);
+    if (h2d_real(s, hb.d, d) != DEM_OK) return fail(DEM_E_HIP);
+  }
+  // forces of the initial state
+  if (F0) {
+    std::vector<double> tmp;
+    for (int k = 0; k < 3; k++) {
+      gather3(F0, id_at_slot, k, tmp);
+      if (h2d_real(s, s->F[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
+      gather3(T0, id_at_slot, k, tmp);
+      if (h2d_real(s, s->T[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
+    }
+  } else {
+    ForceArgs a = force_args(s, 0, s->F, s->T, s->hist[s->ch ^ 1]);
+    if (launch_force(s->prec, a, s->stream) != hipSuccess) return fail(DEM_E_HIP);
+  }
+  st = sync_and_check(s);
+  if (st != DEM_OK) return fail(st);
+  *out = s;
+  return DEM_OK;
+}
+
+dem_status dem_step(dem_system *s, int64_t nsteps) {
+  if (!s) return DEM_E_STATE;
+  if (nsteps < 0) return DEM_E_INVALID;
+  if (s->sticky != DEM_OK) return s->sticky;
+  for (int64_t k = 0; k < nsteps; k++) {
+    // Step 1 (opening half kick, drift) fused with Step 2 (hash)
+    if (launch_kick_drift_hash(s->prec, s->pos[s->cp], s->vel[s->cv], s->F, s->T, s->n, s->c, s->grid, s->cell,
+                               s->err, s->stream) != hipSuccess)
+      return s->sticky = DEM_E_HIP;
+    // Step 3
+    if (launch_sort(s->cell, s->pos[s->cp].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
+                    s->scan, s->stream) != hipSuccess)
+      return s->sticky = DEM_E_HIP;
+    // Step 4
+    if (launch_reorder(s->prec, s->pos[s->cp], s->vel[s->cv], s->pos[s->cp ^ 1], s->vel[s->cv ^ 1], s->perm,
+                       s->cell, s->scell, s->n, s->stream) != hipSuccess)
+      return s->sticky = DEM_E_HIP;
+    s->cp ^= 1;
+    s->cv ^= 1;
+    // Steps 5-8 and the closing half kick
+    ForceArgs a = force_args(s, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, s->F, s->T, s->hist[s->ch ^ 1]);
+    if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+    s->cv ^= 1;
+    s->ch ^= 1;
+    s->steps++;
+  }
+  return DEM_OK;
+}
+
+dem_status dem_sync(dem_system *s) {
+  if (!s) return DEM_E_STATE;
+  return sync_and_check(s);
+}
+
+dem_status dem_forces(dem_system *s, double *F, double *T) {
+  if (!s) return DEM_E_STATE;
+  if (!F || !T) return DEM_E_INVALID;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  ForceArgs a = force_args(s, 0, s->Fe, s->Te, s->hist[s->ch ^ 1]);
+  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+  if ((st = sync_and_check(s)) != DEM_OK) return st;
+  std::vector<int32_t> id;
+  if ((st = d2h(s, s->pos[s->cp].id, id, (size_t)s->n)) != DEM_OK) return st;
+  std::vector<double> tmp;
+  for (int k = 0; k < 3; k++) {
+    if ((st = d2h_real(s, s->Fe[k], tmp)) != DEM_OK) return st;
+    for (int32_t i = 0; i < s->n; i++) F[3 * (size_t)id[i] + k] = tmp[i];
+    if ((st = d2h_real(s, s->Te[k], tmp)) != DEM_OK) return st;
+    for (int32_t i = 0; i < s->n; i++) T[3 * (size_t)id[i] + k] = tmp[i];
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_state(dem_system *s, double *x, double *v, double *omega, double *F, double *T) {
+  if (!s) return DEM_E_STATE;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  const size_t N = (size_t)s->n;
+  std::vector<int32_t> id;
+  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if (x) {
+    std::vector<double> tmp;
+    const double *src[3] = {s->pos[s->cp].x, s->pos[s->cp].y, s->pos[s->cp].z};
+    for (int k = 0; k < 3; k++) {
+      if ((st = d2h(s, src[k], tmp, N)) != DEM_OK) return st;
+      for (size_t i = 0; i < N; i++) x[3 * (size_t)id[i] + k] = tmp[i];
+    }
+  }
+  void *const *arrs[4] = {s->vel[s->cv].v, s->vel[s->cv].w, s->F, s->T};
+  double *outs[4] = {v, omega, F, T};
+  for (int q = 0; q < 4; q++) {
+    if (!outs[q]) continue;
+    std::vector<double> tmp;
+    for (int k = 0; k < 3; k++) {
+      if ((st = d2h_real(s, arrs[q][k], tmp)) != DEM_OK) return st;
+      for (size_t i = 0; i < N; i++) outs[q][3 * (size_t)id[i] + k] = tmp[i];
+    }
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs, double *delta_t) {
+  if (!s) return DEM_E_STATE;
+  if (!n_out) return DEM_E_INVALID;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  std::vector<Entry> e;
+  if ((st = read_table(s, s->hist[s->ch], true, e)) != DEM_OK) return st;
+  *n_out = (int64_t)e.size();
+  if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
+  for (size_t k = 0; k < e.size(); k++) {
+    if (pairs) {
+      pairs[2 * k] = e[k].a;
+      pairs[2 * k + 1] = e[k].b;
+    }
+    if (delta_t)
+      for (int q = 0; q < 3; q++) delta_t[3 * k + q] = e[k].d[q];
+  }
+  return DEM_OK;
+}
+
+dem_status dem_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs) {
+  if (!s) return DEM_E_STATE;
+  if (!n_out) return DEM_E_INVALID;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  // detection into the spare history table (overwritten by the next step)
+  const HistBuf &spare = s->hist[s->ch ^ 1];
+  ForceArgs a = force_args(s, MODE_WRITE_HIST | MODE_LIST, s->Fe, s->Te, spare);
+  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+  if ((st = sync_and_check(s)) != DEM_OK) return st;
+  std::vector<Entry> e;
+  if ((st = read_table(s, spare, false, e)) != DEM_OK) return st;
+  *n_out = (int64_t)e.size();
+  if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
+  for (size_t k = 0; k < e.size() && pairs; k++) {
+    pairs[2 * k] = e[k].a;
+    pairs[2 * k + 1] = e[k].b;
+  }
+  return DEM_OK;
+}
+
+dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot, int32_t *cell_start) {
+  if (!s) return DEM_E_STATE;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  const size_t N = (size_t)s->n;
+  std::vector<int32_t> id, sc;
+  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if (cell_of_id) {
+    if ((st = d2h(s, (const int32_t *)s->scell, sc, N)) != DEM_OK) return st;
+    for (size_t i = 0; i < N; i++) cell_of_id[id[i]] = sc[i];
+  }
+  if (id_at_slot) memcpy(id_at_slot, id.data(), 4 * N);
+  if (cell_start) {
+    std::vector<int32_t> cs;
+    if ((st = d2h(s, (const int32_t *)s->cell_start, cs, (size_t)s->grid.ncell + 1)) != DEM_OK) return st;
+    memcpy(cell_start, cs.data(), 4 * cs.size());
+  }
+  return DEM_OK;
+}
+
+dem_status dem_grid_dims(dem_system *s, int32_t dims[3]) {
+  if (!s) return DEM_E_STATE;
+  if (!dims) return DEM_E_INVALID;
+  for (int a = 0; a < 3; a++) dims[a] = s->grid.nc[a];
+  return DEM_OK;
+}
+
+dem_status dem_diagnostics(dem_system *s, double out[10]) {
+  if (!s) return DEM_E_STATE;
+  if (!out) return DEM_E_INVALID;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  ForceArgs a = force_args(s, MODE_DIAG, s->Fe, s->Te, s->hist[s->ch ^ 1]);
+  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+  if (launch_diag_reduce(s->prec, s->pos[s->cp], s->vel[s->cv], s->diag, s->n, s->c, s->grid, s->stream) !=
+      hipSuccess)
+    return s->sticky = DEM_E_HIP;
+  if ((st = sync_and_check(s)) != DEM_OK) return st;
+  std::vector<double> o;
+  if ((st = d2h(s, (const double *)s->diag.out, o, 10)) != DEM_OK) return st;
+  memcpy(out, o.data(), 10 * sizeof(double));
+  return DEM_OK;
+}
+
+dem_status dem_destroy(dem_system *s) {
+  if (!s) return DEM_E_STATE;
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+  return DEM_OK;
+}
+
+}  // extern "C"

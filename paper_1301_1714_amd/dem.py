@@ -1,0 +1,265 @@
+"""Python binding of libdem.so: argument marshalling only.
+
+Every step of the DEM path runs in the HIP kernels behind the C ABI of
+``include/dem.h``; PyTorch provides the device workspace and the stream.  The
+functions keep the C names (``dem_create``, ``dem_step``, ...); ``System`` is
+a thin owner of one handle and its workspace.  There is no CPU fallback: if
+the library is missing or no GPU is present the calls raise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LAWS = {"linear": 0, "hertz": 1, "simple": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+DEM_OK = 0
+DEM_E_INVALID = -1
+DEM_E_WORKSPACE = -2
+DEM_E_CONTACT_OVERFLOW = -3
+DEM_E_OUT_OF_DOMAIN = -4
+DEM_E_NONFINITE = -5
+DEM_E_HIP = -6
+DEM_E_STATE = -7
+DEM_E_CAPACITY = -9
+
+_LIB = None
+
+
+class DemError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().dem_status_string(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+class DemParams(C.Structure):
+    _fields_ = [
+        ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+        ("wall_mask", C.c_uint32), ("law", C.c_int32),
+        ("gravity", C.c_double * 3),
+        ("dt", C.c_double), ("density", C.c_double),
+        ("kn", C.c_double), ("kt", C.c_double),
+        ("restitution", C.c_double), ("eta_t_ratio", C.c_double), ("mu", C.c_double),
+        ("simple_k", C.c_double * 3),
+        ("cell_size", C.c_double),
+        ("contacts_per_particle", C.c_int32), ("precision", C.c_int32),
+    ]
+
+
+def lib():
+    """Load libdem.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError(f"libdem.so not built at {_build.LIB}; run __graft_entry__.build() first")
+        L = C.CDLL(_build.LIB)
+        P, I64, S = C.c_void_p, C.c_int64, C.c_size_t
+        st = C.c_int
+        sig = {
+            "dem_workspace_bytes": ([C.POINTER(DemParams), I64, C.POINTER(S)], st),
+            "dem_create": ([C.POINTER(DemParams), I64, P, P, P, P, P, P, I64, P, P, P, S, P, C.POINTER(P)], st),
+            "dem_step": ([P, I64], st),
+            "dem_forces": ([P, P, P], st),
+            "dem_read_state": ([P, P, P, P, P, P], st),
+            "dem_read_contacts": ([P, I64, C.POINTER(I64), P, P], st),
+            "dem_contacts": ([P, I64, C.POINTER(I64), P], st),
+            "dem_read_grid": ([P, P, P, P], st),
+            "dem_grid_dims": ([P, C.POINTER(C.c_int32)], st),
+            "dem_diagnostics": ([P, C.POINTER(C.c_double)], st),
+            "dem_sync": ([P], st),
+            "dem_destroy": ([P], st),
+            "dem_status_string": ([st], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def make_params(p: dict) -> DemParams:
+    o = DemParams()
+    o.box_lo[:] = [float(t) for t in p["box_lo"]]
+    o.box_hi[:] = [float(t) for t in p["box_hi"]]
+    o.wall_mask = int(p.get("wall_mask", 0x3F))
+    o.law = LAWS[p.get("law", "linear")]
+    o.gravity[:] = [float(t) for t in p.get("gravity", (0.0, 0.0, -9.81))]
+    o.dt = float(p["dt"])
+    o.density = float(p.get("density", 2500.0))
+    o.kn = float(p["kn"])
+    o.kt = float(p.get("kt", 0.0))
+    o.restitution = float(p.get("restitution", 1.0))
+    o.eta_t_ratio = float(p.get("eta_t_ratio", 0.0))
+    o.mu = float(p.get("mu", 0.0))
+    o.simple_k[:] = [float(t) for t in p.get("simple_k", (0.0, 0.0, 0.0))]
+    o.cell_size = float(p["cell_size"])
+    o.contacts_per_particle = int(p.get("contacts_per_particle", 16))
+    o.precision = PRECISIONS[p.get("precision", "fp64")]
+    return o
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _d3(a, n):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n, 3))
+
+
+def _check(code, where):
+    if code != DEM_OK:
+        raise DemError(code, where)
+
+
+def dem_workspace_bytes(params: dict, n: int) -> int:
+    b = C.c_size_t()
+    _check(lib().dem_workspace_bytes(C.byref(make_params(params)), int(n), C.byref(b)), "dem_workspace_bytes")
+    return b.value
+
+
+class System:
+    """One DEM system on the GPU: the handle of ``dem_create`` plus the torch
+    workspace that backs it."""
+
+    def __init__(self, params: dict, x, v, omega, r, F0=None, T0=None, hist_pairs=None, hist_dt=None,
+                 device="cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdem needs a GPU: torch.cuda.is_available() is False")
+        L = lib()
+        r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1))
+        n = r.shape[0]
+        self.n = n
+        self.params = dict(params)
+        self._p = make_params(params)
+        x, v, omega = _d3(x, n), _d3(v, n), _d3(omega, n)
+        F0 = None if F0 is None else _d3(F0, n)
+        T0 = None if T0 is None else _d3(T0, n)
+        nh = 0
+        if hist_pairs is not None and len(hist_pairs) > 0:
+            hist_pairs = np.ascontiguousarray(np.asarray(hist_pairs, dtype=np.int64).reshape(-1, 2))
+            hist_dt = np.ascontiguousarray(np.asarray(hist_dt, dtype=np.float64).reshape(-1, 3))
+            nh = hist_pairs.shape[0]
+        else:
+            hist_pairs = hist_dt = None
+        self.device = torch.device(device)
+        nbytes = dem_workspace_bytes(params, n)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L.dem_create(C.byref(self._p), n, _ptr(x), _ptr(v), _ptr(omega), _ptr(r), _ptr(F0), _ptr(T0), nh,
+                            _ptr(hist_pairs), _ptr(hist_dt), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                            C.c_void_p(self.stream.cuda_stream), C.byref(h)), "dem_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            self._h = None
+            _LIB.dem_destroy(h)
+
+    __del__ = close
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise DemError(DEM_E_STATE, "system")
+        return self._h
+
+    def step(self, nsteps: int = 1):
+        _check(lib().dem_step(self.handle, int(nsteps)), "dem_step")
+
+    def sync(self):
+        _check(lib().dem_sync(self.handle), "dem_sync")
+
+    def forces(self):
+        F = np.zeros((self.n, 3))
+        T = np.zeros((self.n, 3))
+        _check(lib().dem_forces(self.handle, _ptr(F), _ptr(T)), "dem_forces")
+        return F, T
+
+    def read_state(self):
+        out = [np.zeros((self.n, 3)) for _ in range(5)]
+        _check(lib().dem_read_state(self.handle, *[_ptr(a) for a in out]), "dem_read_state")
+        x, v, w, F, T = out
+        return {"x": x, "v": v, "omega": w, "F": F, "T": T}
+
+    def read_contacts(self):
+        n = C.c_int64()
+        st = lib().dem_read_contacts(self.handle, 0, C.byref(n), None, None)
+        if st not in (DEM_OK, DEM_E_CAPACITY):
+            _check(st, "dem_read_contacts")
+        pairs = np.zeros((max(n.value, 1), 2), dtype=np.int64)
+        dt = np.zeros((max(n.value, 1), 3))
+        _check(lib().dem_read_contacts(self.handle, n.value, C.byref(n), _ptr(pairs), _ptr(dt)), "dem_read_contacts")
+        return pairs[: n.value], dt[: n.value]
+
+    def contacts(self):
+        n = C.c_int64()
+        st = lib().dem_contacts(self.handle, 0, C.byref(n), None)
+        if st not in (DEM_OK, DEM_E_CAPACITY):
+            _check(st, "dem_contacts")
+        pairs = np.zeros((max(n.value, 1), 2), dtype=np.int64)
+        _check(lib().dem_contacts(self.handle, n.value, C.byref(n), _ptr(pairs)), "dem_contacts")
+        return pairs[: n.value]
+
+    def grid_dims(self):
+        d = (C.c_int32 * 3)()
+        _check(lib().dem_grid_dims(self.handle, d), "dem_grid_dims")
+        return tuple(int(t) for t in d)
+
+    def read_grid(self):
+        dims = self.grid_dims()
+        nc = dims[0] * dims[1] * dims[2]
+        cell = np.zeros(self.n, dtype=np.int32)
+        order = np.zeros(self.n, dtype=np.int32)
+        start = np.zeros(nc + 1, dtype=np.int32)
+        _check(lib().dem_read_grid(self.handle, _ptr(cell), _ptr(order), _ptr(start)), "dem_read_grid")
+        return cell, order, start
+
+    def diagnostics(self):
+        out = (C.c_double * 10)()
+        _check(lib().dem_diagnostics(self.handle, out), "dem_diagnostics")
+        return np.array(out[:])
+
+
+def dem_create(params, x, v, omega, r, **kw) -> System:
+    return System(params, x, v, omega, r, **kw)
+
+
+def dem_step(system: System, nsteps: int = 1):
+    system.step(nsteps)
+
+
+def dem_forces(system: System):
+    return system.forces()
+
+
+def dem_read_state(system: System):
+    return system.read_state()
+
+
+def dem_read_contacts(system: System):
+    return system.read_contacts()
+
+
+def dem_contacts(system: System):
+    return system.contacts()
+
+
+def dem_read_grid(system: System):
+    return system.read_grid()
+
+
+def dem_diagnostics(system: System):
+    return system.diagnostics()
+
+
+def dem_destroy(system: System):
+    system.close()

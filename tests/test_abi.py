@@ -1,0 +1,103 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/dem.h declares, its parameter struct matches the binding, and the
+host-only calls work without a GPU.  Also: the oracle and the HIP path share
+no source."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dem.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dem_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1301_1714_amd import build, dem
+    if not os.path.exists(build.LIB):
+        build.build()
+    return dem.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "dem_create" in names and "dem_step" in names and len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_params_layout_matches_header(tmp_path):
+    from paper_1301_1714_amd.dem import DemParams
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dem.h"\n'
+                   'int main(void){printf("%zu", sizeof(dem_params));'
+                   + "".join(f'printf(" %zu", offsetof(dem_params, {f}));' for f, _ in DemParams._fields_)
+                   + "return 0;}\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == C.sizeof(DemParams)
+    for (f, _), off in zip(DemParams._fields_, out[1:]):
+        assert getattr(DemParams, f).offset == int(off), f
+
+
+def test_workspace_bytes_and_validation_on_host(L):
+    from paper_1301_1714_amd import dem, workloads as W
+    p = W.base_params(cell_size=1.0 / 32.0)
+    b1 = dem.dem_workspace_bytes(p, 4096)
+    b2 = dem.dem_workspace_bytes(p, 8192)
+    assert 0 < b1 < b2
+    assert b1 % 256 == 0
+    pm = dict(p, precision="mixed")
+    assert dem.dem_workspace_bytes(pm, 4096) < b1
+    with pytest.raises(dem.DemError) as e:
+        dem.dem_workspace_bytes(dict(p, cell_size=2.0), 10)  # cell wider than the box
+    assert e.value.code == dem.DEM_E_INVALID
+    with pytest.raises(dem.DemError):
+        dem.dem_workspace_bytes(dict(p, dt=0.0), 10)
+    with pytest.raises(dem.DemError):
+        dem.dem_workspace_bytes(dict(p, restitution=1.5), 10)
+    with pytest.raises(dem.DemError):
+        dem.dem_workspace_bytes(p, -1)
+    assert L.dem_status_string(-3) == b"contact history table overflow"
+
+
+def test_create_rejects_bad_input_before_touching_the_gpu(L):
+    from paper_1301_1714_amd import dem, workloads as W
+    p = dem.make_params(W.base_params(cell_size=0.05))
+    x = (C.c_double * 3)(0.5, 0.5, 0.5)
+    z = (C.c_double * 3)(0, 0, 0)
+    r = (C.c_double * 1)(0.03)  # 2r > cell
+    h = C.c_void_p()
+    st = L.dem_create(C.byref(p), 1, x, z, z, r, None, None, 0, None, None, None, 0, None, C.byref(h))
+    assert st == dem.DEM_E_INVALID
+    r[0] = 0.01
+    nan = (C.c_double * 3)(float("nan"), 0, 0)
+    st = L.dem_create(C.byref(p), 1, x, nan, z, r, None, None, 0, None, None, None, 0, None, C.byref(h))
+    assert st == dem.DEM_E_NONFINITE
+    st = L.dem_create(C.byref(p), 1, x, z, z, r, None, None, 0, None, None, None, 0, None, C.byref(h))
+    assert st == dem.DEM_E_WORKSPACE
+
+
+def test_oracle_and_hip_path_share_no_source():
+    csrc = os.path.join(ROOT, "paper_1301_1714_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in txt.lower(), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".c", ".h")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            incs = re.findall(r'#include\s*[<"]([^>"]+)[>"]', txt)
+            assert all(i in ("math.h", "stdint.h", "stdlib.h", "string.h") for i in incs), incs
+    for f in ("dem.py", "build.py", "workloads.py"):
+        txt = open(os.path.join(ROOT, "paper_1301_1714_amd", f)).read()
+        assert "import oracle" not in txt and "from oracle" not in txt, f

@@ -1,0 +1,258 @@
+"""GPU-vs-oracle parity through the C ABI (needs an MI355X).
+
+Integer results (cell ids, sorted order, cell starts, contact lists) must be
+bit-exact; forces on identical states agree per particle within
+tol * (sum of the magnitudes of the contact forces on it), tol = 1e-5 with FP32
+forces; a particle without contacts gets exactly 0.  In FP64 the bound is
+1e-12 relative plus an absolute floor of 1e-14 times the largest particle
+scale: the overlap of a barely touching pair carries an absolute rounding
+error of about one ulp of r_i + r_j (S - d on one side, (S^2 - d^2)/(S + d) on
+the other), which is large relative to that pair's tiny force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSystem
+from paper_1301_1714_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}  # the floor below applies 1e-2 * tol
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1301_1714_amd import dem as D
+    D.lib()
+    return D
+
+
+def cloud(seed, n, precision="fp64", law="linear", walls=W.ALL_WALLS, spread=0.3, spacing=0.95, **kw):
+    side = (n * 1.3) ** (1.0 / 3.0) * spacing * 2 * 0.01
+    return W.overlapping_cloud(seed, n, box=(side, 0.8 * side, 1.2 * side), r_mean=0.01, r_spread=spread,
+                               spacing=spacing, law=law, precision=precision, walls=walls, **kw)
+
+
+CASES = {
+    "fp64_linear_3001": dict(seed=1, n=3001),
+    "mixed_linear_3001": dict(seed=2, n=3001, precision="mixed"),
+    "fp64_hertz_2500": dict(seed=3, n=2500, law="hertz"),
+    "mixed_hertz_2500": dict(seed=4, n=2500, law="hertz", precision="mixed"),
+    "fp64_simple_1777": dict(seed=5, n=1777, law="simple"),
+    "mixed_simple_1777": dict(seed=6, n=1777, law="simple", precision="mixed"),
+    "fp64_partial_walls_5000": dict(seed=7, n=5000, walls=0x15, spread=0.5),
+    "mixed_nowalls_poly_4097": dict(seed=8, n=4097, walls=0, spread=0.6, precision="mixed"),
+}
+
+
+def make(dem, c, **kw):
+    g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"], **kw)
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"], **kw)
+    return g, o
+
+
+def assert_forces_close(Fg, Tg, F, T, Fa, Ta, tol):
+    dF = np.linalg.norm(Fg - F, axis=1)
+    dT = np.linalg.norm(Tg - T, axis=1)
+    free = Fa == 0
+    assert np.all(Fg[free] == 0.0) and np.all(Tg[Ta == 0] == 0.0)
+    floor = 1e-2 * tol  # only matters in FP64 (see the module docstring)
+    if np.any(~free):
+        bound = tol * Fa[~free] + floor * Fa.max()
+        worst = np.max(dF[~free] / bound)
+        assert worst <= 1.0, f"force error {worst:.3f} x the bound (tol {tol:.1e})"
+    has_t = Ta > 0
+    if np.any(has_t):
+        bound = tol * Ta[has_t] + floor * Ta.max()
+        wt = np.max(dT[has_t] / bound)
+        assert wt <= 1.0, f"torque error {wt:.3f} x the bound (tol {tol:.1e})"
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_grid_and_contacts_bit_exact(dem, name):
+    c = cloud(**CASES[name])
+    g, o = make(dem, c)
+    assert g.grid_dims() == o.grid_dims()
+    cg, og, sg = g.read_grid()
+    co, oo, so = o.read_grid()
+    assert np.array_equal(cg, co)
+    assert np.array_equal(og, oo)
+    assert np.array_equal(sg, so)
+    pg = g.contacts()
+    po = o.contacts()
+    assert len(po) > len(c["r"]) // 3
+    assert np.array_equal(pg, po)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_forces_on_identical_state(dem, name):
+    c = cloud(**CASES[name])
+    g, o = make(dem, c)
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL[c["params"]["precision"]])
+    # the creation-time evaluation is the same evaluation
+    st = g.read_state()
+    assert_forces_close(st["F"], st["T"], F, T, Fa, Ta, TOL[c["params"]["precision"]])
+
+
+@pytest.mark.parametrize("name", ["fp64_linear_3001", "mixed_linear_3001", "fp64_hertz_2500",
+                                  "fp64_partial_walls_5000"])
+def test_forces_with_history(dem, name):
+    c = cloud(**CASES[name])
+    p = dict(c["params"], mu=0.2, eta_t_ratio=0.5, dt=2e-6)
+    o = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    o.step(15)
+    st = o.read_state()
+    pairs, dts = o.read_contacts()
+    assert len(pairs) > 100 and np.abs(dts).max() > 0
+    kw = dict(F0=st["F"], T0=st["T"], hist_pairs=pairs, hist_dt=dts)
+    g = dem.System(p, st["x"], st["v"], st["omega"], c["r"], **kw)
+    o2 = OracleSystem(p, st["x"], st["v"], st["omega"], c["r"], **kw)
+    gp, gd = g.read_contacts()
+    assert np.array_equal(gp, pairs)
+    tol = TOL[p["precision"]]
+    assert np.allclose(gd, dts, rtol=0, atol=(1e-15 if tol < 1e-9 else 1e-6) * np.abs(dts).max())
+    F, T, Fa, Ta = o2.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, tol)
+
+
+@pytest.mark.parametrize("name", ["fp64_linear_3001", "fp64_hertz_2500", "fp64_simple_1777",
+                                  "fp64_partial_walls_5000"])
+def test_fp64_steps_track_the_oracle(dem, name):
+    c = cloud(**CASES[name])
+    p = dict(c["params"], mu=0.2, eta_t_ratio=0.5, dt=2e-6)
+    c["params"] = p
+    g, o = make(dem, c)
+    for _ in range(4):
+        g.step(5)
+        o.step(5)
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-12
+    vs = np.abs(so["v"]).max()
+    assert np.max(np.abs(sg["v"] - so["v"])) < 1e-9 * vs
+    pg, dg = g.read_contacts()
+    po, do = o.read_contacts()
+    assert np.array_equal(pg, po)
+    if len(do):
+        assert np.max(np.abs(dg - do)) <= 1e-9 * max(np.abs(do).max(), 1e-300)
+    dg_, do_ = g.diagnostics(), o.diagnostics()
+    assert np.array_equal(dg_[7:9], do_[7:9])
+    assert np.allclose(dg_[[3, 4, 5, 6, 9]], do_[[3, 4, 5, 6, 9]], rtol=1e-9, atol=0)
+    assert np.allclose(dg_[:3], do_[:3], rtol=0, atol=1e-9 * np.abs(do_[:3]).max() + 1e-12)
+
+
+def test_mixed_steps_stay_close(dem):
+    c = cloud(**CASES["mixed_linear_3001"])
+    p = dict(c["params"], mu=0.2, dt=2e-6)
+    c["params"] = p
+    g, o = make(dem, c)
+    g.step(20)
+    o.step(20)
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-9
+    assert np.max(np.abs(sg["v"] - so["v"])) < 1e-4 * np.abs(so["v"]).max()
+
+
+def test_plain_fp64_workload_trajectory(dem):
+    w = W.plain_fp64(seed=1000)
+    g = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    o = OracleSystem(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    g.step(1000)
+    o.step(1000)
+    sg, so = g.read_state(), o.read_state()
+    err = np.max(np.abs(sg["x"] - so["x"]))
+    print(f"plain fp64 4096 x 1000 steps: max |x_gpu - x_oracle| = {err:.3e}")
+    assert err <= 1e-9
+
+
+def test_restart_is_bit_identical(dem):
+    c = cloud(**CASES["fp64_linear_3001"])
+    p = dict(c["params"], mu=0.3, dt=2e-6)
+    a = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    a.step(20)
+    b = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    b.step(10)
+    st = b.read_state()
+    pairs, dts = b.read_contacts()
+    b2 = dem.System(p, st["x"], st["v"], st["omega"], c["r"], F0=st["F"], T0=st["T"], hist_pairs=pairs,
+                    hist_dt=dts)
+    b2.step(10)
+    sa, sb = a.read_state(), b2.read_state()
+    for k in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_runs_are_deterministic(dem, precision):
+    c = cloud(**dict(CASES["fp64_partial_walls_5000"], precision=precision))
+    out = []
+    for _ in range(2):
+        g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+        g.step(25)
+        out.append((g.read_state(), g.read_contacts(), g.diagnostics()))
+    for k in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert np.array_equal(out[0][1][0], out[1][1][0]) and np.array_equal(out[0][1][1], out[1][1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
+# ---------------------------------------------------------------- edge cases
+
+
+def test_single_particle_and_empty(dem):
+    p = W.base_params(cell_size=0.1, dt=1e-5)
+    g = dem.System(p, [[0.5, 0.5, 0.02]], [[0.1, 0, 0]], [[0, 0, 1.0]], [0.03])
+    o = OracleSystem(p, [[0.5, 0.5, 0.02]], [[0.1, 0, 0]], [[0, 0, 1.0]], [0.03])
+    g.step(50)
+    o.step(50)
+    sg, so = g.read_state(), o.read_state()
+    assert np.allclose(sg["x"], so["x"], rtol=0, atol=1e-13)
+    e = dem.System(p, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0))
+    e.step(3)
+    assert e.read_state()["x"].shape == (0, 3)
+    assert len(e.contacts()) == 0
+    assert np.all(e.diagnostics() == 0.0)
+
+
+def test_one_cell_grid(dem):
+    c = W.overlapping_cloud(9, 300, box=(0.3, 0.3, 0.3), r_mean=0.012, spacing=0.95)
+    p = dict(c["params"], cell_size=0.3)
+    g = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    o = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    assert g.grid_dims() == (1, 1, 1)
+    assert np.array_equal(g.contacts(), o.contacts())
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["fp64"])
+
+
+def test_out_of_domain_is_reported(dem):
+    p = W.base_params(cell_size=0.1, wall_mask=0, gravity=(0, 0, 0))
+    x = np.array([[0.5, 0.5, 0.5], [1.2, 0.5, 0.5]])
+    with pytest.raises(dem.DemError) as e:
+        dem.System(p, x, np.zeros((2, 3)), np.zeros((2, 3)), [0.01, 0.01])
+    assert e.value.code == dem.DEM_E_OUT_OF_DOMAIN
+    # a particle that flies out during the run: sticky error at the next sync
+    g = dem.System(p, [[0.5, 0.5, 0.95]], [[0, 0, 50.0]], [[0, 0, 0]], [0.01], )
+    g.step(400)
+    with pytest.raises(dem.DemError) as e:
+        g.read_state()
+    assert e.value.code == dem.DEM_E_OUT_OF_DOMAIN
+    with pytest.raises(dem.DemError):
+        g.step(1)
+
+
+def test_history_overflow_is_reported(dem):
+    c = cloud(**CASES["fp64_linear_3001"])
+    p = dict(c["params"], contacts_per_particle=1)
+    g = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    g.step(1)
+    with pytest.raises(dem.DemError) as e:
+        g.sync()
+    assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
