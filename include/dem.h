@@ -151,6 +151,25 @@ dem_status dem_grid_dims(dem_system *s, int32_t dims[3]);
  *  out[8] wall contacts   out[9] largest overlap.  Synchronous. */
 dem_status dem_diagnostics(dem_system *s, double out[10]);
 
+/* Replace the radii (original order, rounded to FP32), e.g. to grow a packing
+ * by steps.  Takes effect at the next step; the stored forces are not
+ * re-evaluated.  Errors: DEM_E_INVALID (a radius <= 0 or not finite, or twice
+ * the largest radius wider than cell_size).  Synchronous. */
+dem_status dem_set_radii(dem_system *s, const double *r);
+
+/* Phase timing.  With enable != 0 every later dem_step brackets each of its
+ * phases with HIP events on the system's stream; dem_profile_read waits for
+ * the stream, returns the milliseconds spent in each phase summed over the
+ * steps timed since the previous read (and their number), then clears them.
+ * Phases: 0 kick-drift-hash (Steps 1-2), 1 sort and cell starts (Step 3),
+ * 2 reorder (Step 4), 3 contact detection over the 27 cells (Steps 5-6),
+ * 4 contact forces and closing kick (Steps 7-8).  At most
+ * DEM_PROFILE_CAPACITY steps are timed between two reads. */
+#define DEM_NUM_PHASES 5
+#define DEM_PROFILE_CAPACITY 4096
+dem_status dem_profile(dem_system *s, int enable);
+dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps);
+
 /* Wait for the system's stream; report any sticky error. */
 dem_status dem_sync(dem_system *s);
 

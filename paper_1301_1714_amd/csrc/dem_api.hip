@@ -32,11 +32,16 @@ struct dem_system {
   int32_t *cell, *rank, *perm, *scell, *counts, *cell_start;
   ScanScratch scan;
   HistBuf hist[2];
+  NbrBuf nbr;
   DiagBuf diag;
   int32_t *err;
   hipStream_t stream;
   dem_status sticky;
   int64_t steps;
+  // phase timing (dem_profile)
+  bool profiling;
+  std::vector<hipEvent_t> *events;  // DEM_PROFILE_CAPACITY x (DEM_NUM_PHASES + 1)
+  int64_t timed;
 };
 
 namespace {
@@ -82,6 +87,26 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   return DEM_OK;
 }
 
+// Capacity of each contact list (forward and backward) per particle.
+int32_t list_capacity(int32_t K) { return std::max<int32_t>(16, K + 8); }
+
+// Margin of the FP32 detection prefilter.  Coordinates relative to the box
+// corner lie in (-w, L + w) for cells of width w, so each is rounded to FP32
+// with an error of at most half an ulp of U = max(L + 2w); a difference of two
+// of them is off by at most one ulp(U) plus an ulp of the cell, the norm by
+// sqrt(3) times that, and the FP32 squares add a relative 2.4e-7 of the
+// contact distance (<= cell).  4 ulp(U) + 1e-6 cell covers all of it, so the
+// prefilter never rejects a pair that the exact FP64 test accepts.
+float prefilter_eps(const Grid &g, double cell) {
+  double U = 0.0;
+  for (int a = 0; a < 3; a++) {
+    const double L = g.hi[a] - g.lo[a];
+    U = std::max(U, L + 2.0 * L / g.nc[a]);
+  }
+  const double ulp = ldexp(1.0, ilogb(U) - 23);
+  return (float)(4.0 * ulp + 1.0e-6 * cell);
+}
+
 // Lay the arrays out in the workspace; with base == nullptr only sizes.
 size_t carve(dem_system *s, char *base) {
   Carver cv{base};
@@ -115,6 +140,11 @@ size_t carve(dem_system *s, char *base) {
     s->scan.len[l] = lens[l];
     s->scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
   }
+  s->nbr.xyzr = cv.take<float4>(N);
+  s->nbr.cnt_f = cv.take<int32_t>(N);
+  s->nbr.nb_f = cv.take<int32_t>((size_t)s->nbr.Kd * N);
+  s->nbr.cnt_b = cv.take<int32_t>(N);
+  s->nbr.nb_b = cv.take<int32_t>((size_t)s->nbr.Kd * N);
   for (int b = 0; b < 2; b++) {
     s->hist[b].cnt = cv.take<int32_t>(N);
     s->hist[b].partner = cv.take<int32_t>(K * N);
@@ -185,6 +215,7 @@ ForceArgs force_args(dem_system *s, int mode, void *const F[3], void *const T[3]
   ForceArgs a;
   memset(&a, 0, sizeof(a));
   a.pos = s->pos[s->cp];
+  a.nbr = s->nbr;
   a.vel_in = s->vel[s->cv];
   a.vel_out = s->vel[s->cv ^ 1];
   a.scell = s->scell;
@@ -334,6 +365,7 @@ dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes) {
   if (st != DEM_OK) return st;
   s.n = (int32_t)n;
   s.K = p->contacts_per_particle;
+  s.nbr.Kd = list_capacity(s.K);
   s.prec = p->precision;
   s.rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
   *bytes = carve(&s, nullptr);
@@ -384,6 +416,8 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
   s->p = *p;
   s->n = (int32_t)n;
   s->K = p->contacts_per_particle;
+  s->nbr.Kd = list_capacity(s->K);
+  s->nbr.eps = prefilter_eps(g, p->cell_size);
   s->prec = p->precision;
   s->rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
   s->grid = g;
@@ -432,12 +466,14 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
   if (launch_sort(s->cell, s->pos[0].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
                   s->scan, s->stream) != hipSuccess)
     return fail(DEM_E_HIP);
-  if (launch_reorder(s->prec, s->pos[0], s->vel[0], s->pos[1], s->vel[1], s->perm, s->cell, s->scell, s->n,
-                     s->stream) != hipSuccess)
+  if (launch_reorder(s->prec, s->pos[0], s->vel[0], s->pos[1], s->vel[1], s->perm, s->cell, s->scell,
+                     s->nbr.xyzr, s->grid, s->n, s->stream) != hipSuccess)
     return fail(DEM_E_HIP);
   s->cp = 1;
   s->cv = 1;
   s->ch = 0;
+  if (launch_detect(s->pos[1], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream) != hipSuccess)
+    return fail(DEM_E_HIP);
   st = sync_and_check(s);
   if (st != DEM_OK) return fail(st);
   std::vector<int32_t> id_at_slot;
@@ -492,23 +528,41 @@ dem_status dem_step(dem_system *s, int64_t nsteps) {
   if (nsteps < 0) return DEM_E_INVALID;
   if (s->sticky != DEM_OK) return s->sticky;
   for (int64_t k = 0; k < nsteps; k++) {
+    hipEvent_t *ev = nullptr;
+    if (s->profiling && s->timed < DEM_PROFILE_CAPACITY) {
+      ev = s->events->data() + (size_t)s->timed * (DEM_NUM_PHASES + 1);
+      s->timed++;
+    }
+    auto mark = [&](int phase) {
+      if (ev) (void)hipEventRecord(ev[phase], s->stream);
+    };
+    mark(0);
     // Step 1 (opening half kick, drift) fused with Step 2 (hash)
     if (launch_kick_drift_hash(s->prec, s->pos[s->cp], s->vel[s->cv], s->F, s->T, s->n, s->c, s->grid, s->cell,
                                s->err, s->stream) != hipSuccess)
       return s->sticky = DEM_E_HIP;
+    mark(1);
     // Step 3
     if (launch_sort(s->cell, s->pos[s->cp].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
                     s->scan, s->stream) != hipSuccess)
       return s->sticky = DEM_E_HIP;
+    mark(2);
     // Step 4
     if (launch_reorder(s->prec, s->pos[s->cp], s->vel[s->cv], s->pos[s->cp ^ 1], s->vel[s->cv ^ 1], s->perm,
-                       s->cell, s->scell, s->n, s->stream) != hipSuccess)
+                       s->cell, s->scell, s->nbr.xyzr, s->grid, s->n, s->stream) != hipSuccess)
       return s->sticky = DEM_E_HIP;
     s->cp ^= 1;
     s->cv ^= 1;
+    mark(3);
+    // Steps 5-6
+    if (launch_detect(s->pos[s->cp], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream) !=
+        hipSuccess)
+      return s->sticky = DEM_E_HIP;
+    mark(4);
     // Steps 5-8 and the closing half kick
     ForceArgs a = force_args(s, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, s->F, s->T, s->hist[s->ch ^ 1]);
     if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+    mark(5);
     s->cv ^= 1;
     s->ch ^= 1;
     s->steps++;
@@ -654,9 +708,81 @@ dem_status dem_diagnostics(dem_system *s, double out[10]) {
   return DEM_OK;
 }
 
+dem_status dem_set_radii(dem_system *s, const double *r) {
+  if (!s) return DEM_E_STATE;
+  if (s->n > 0 && !r) return DEM_E_INVALID;
+  dem_status st = sync_and_check(s);
+  if (st != DEM_OK) return st;
+  const size_t N = (size_t)s->n;
+  std::vector<float> rf(N);
+  double rmax = 0.0;
+  for (size_t i = 0; i < N; i++) {
+    const float q = (float)r[i];
+    if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
+    rf[i] = q;
+    rmax = std::max(rmax, (double)q);
+  }
+  if (s->p.cell_size < 2.0 * rmax) return DEM_E_INVALID;
+  std::vector<int32_t> id;
+  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  std::vector<float> slot_r(N);
+  for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
+  if (N) {
+    HIP_TRY(hipMemcpyAsync(s->pos[s->cp].r, slot_r.data(), 4 * N, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_xyzr(s->pos[s->cp], s->nbr.xyzr, s->grid, s->n, s->stream));
+    HIP_TRY(launch_detect(s->pos[s->cp], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  return sync_and_check(s);
+}
+
+static void free_events(dem_system *s) {
+  if (!s->events) return;
+  for (hipEvent_t e : *s->events) (void)hipEventDestroy(e);
+  delete s->events;
+  s->events = nullptr;
+}
+
+dem_status dem_profile(dem_system *s, int enable) {
+  if (!s) return DEM_E_STATE;
+  if (enable && !s->events) {
+    const size_t cnt = (size_t)DEM_PROFILE_CAPACITY * (DEM_NUM_PHASES + 1);
+    s->events = new (std::nothrow) std::vector<hipEvent_t>(cnt, nullptr);
+    if (!s->events) return DEM_E_INVALID;
+    for (size_t k = 0; k < cnt; k++)
+      if (hipEventCreate(&(*s->events)[k]) != hipSuccess) {
+        (void)hipGetLastError();
+        free_events(s);
+        return DEM_E_HIP;
+      }
+  }
+  s->profiling = enable != 0;
+  s->timed = 0;
+  return DEM_OK;
+}
+
+dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps) {
+  if (!s) return DEM_E_STATE;
+  if (!ms || !steps) return DEM_E_INVALID;
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  for (int p = 0; p < DEM_NUM_PHASES; p++) ms[p] = 0.0;
+  for (int64_t k = 0; k < s->timed; k++) {
+    hipEvent_t *ev = s->events->data() + (size_t)k * (DEM_NUM_PHASES + 1);
+    for (int p = 0; p < DEM_NUM_PHASES; p++) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
+      ms[p] += (double)t;
+    }
+  }
+  *steps = s->timed;
+  s->timed = 0;
+  return DEM_OK;
+}
+
 dem_status dem_destroy(dem_system *s) {
   if (!s) return DEM_E_STATE;
   (void)hipStreamSynchronize(s->stream);
+  free_events(s);
   delete s;
   return DEM_OK;
 }

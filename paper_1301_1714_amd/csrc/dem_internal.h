@@ -10,6 +10,10 @@
 //   hist[2]  tangential-history rows, one per slot: cnt, partner[K][N] and
 //            delta_t[3][K][N] (Real); a row holds the contacts of its particle
 //            with higher-id partners and with walls (partner = -1 - w)
+//   nbr      contact lists of the current positions: xyzr (FP32 copy of
+//            x - lo and r, the detection prefilter's input), forward partners
+//            (higher slots, found by the particle itself, ascending) and
+//            backward partners (lower slots, appended by them)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -65,6 +69,16 @@ struct HistBuf {
   void *d;           // [3][K][N] Real
 };
 
+struct NbrBuf {
+  float4 *xyzr;    // [N] (x - lo, y - lo, z - lo, r), FP32
+  int32_t *cnt_f;  // [N]
+  int32_t *nb_f;   // [Kd][N] partner slots > own slot, ascending
+  int32_t *cnt_b;  // [N]
+  int32_t *nb_b;   // [Kd][N] partner slots < own slot, in arrival order
+  int32_t Kd;
+  float eps;       // prefilter margin: bounds the FP32 error of |x_j - x_i|
+};
+
 struct DiagBuf {
   double *e_el;     // [N] elastic energy of the contacts a particle owns
   int32_t *npair;   // [N]
@@ -76,6 +90,7 @@ struct DiagBuf {
 
 struct ForceArgs {
   PosBuf pos;
+  NbrBuf nbr;
   VelBuf vel_in, vel_out;
   const int32_t *scell;
   const int32_t *cell_start;
@@ -108,7 +123,10 @@ hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, in
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
 hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          int32_t n, hipStream_t st);
+                          float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
+hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
+hipError_t launch_detect(const PosBuf &p, const NbrBuf &nb, const int32_t *scell, const int32_t *cell_start,
+                         const Grid &g, int32_t n, int32_t *err, hipStream_t st);
 hipError_t launch_force(int precision, const ForceArgs &a, hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const PosBuf &p, const VelBuf &v, const DiagBuf &d, int32_t n,
                               const Consts &c, const Grid &g, hipStream_t st);

@@ -8,12 +8,17 @@
 //                holds with one unique order; the paper's bitonic sort is
 //                replaced by this O(N) sort (any correct sort of unique keys
 //                gives the same permutation)
-//   Step 4       k_reorder: gather every array into the sorted order
-//   Steps 5-8    k_force: one lane per sorted particle sweeps the 27 cells of
-//                Eq. 12, tests contacts exactly in FP64, evaluates the contact
-//                law (Eqs. 2-10, or Eq. 1) and the walls, sums the forces of a
-//                particle in a fixed order (ascending partner slot, walls
-//                last; no atomics), updates the tangential history and applies
+//   Step 4       k_reorder: gather every array into the sorted order, plus an
+//                FP32 copy of (x - lo, r) for the detection prefilter
+//   Steps 5-6    k_detect: one lane per sorted particle sweeps the forward
+//                half of the 27 cells of Eq. 12 (each pair is tested once),
+//                rejects with a conservative FP32 test and decides the rest
+//                exactly in FP64; hits go to the particle's own forward list
+//                (ascending, no atomics) and to the partner's backward list
+//   Steps 7-8    k_force: one lane per sorted particle walks its compact
+//                contact list in ascending partner slot, evaluates the contact
+//                law (Eqs. 2-10, or Eq. 1) and the walls, sums in that fixed
+//                order (no atomics), updates the tangential history and applies
 //                the closing half kick
 // No step is a dense contraction, so nothing here uses the matrix cores.
 #include <math.h>
@@ -294,19 +299,26 @@ hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, in
 // --------------------------------------------------------------------------
 // Step 4: gather into the sorted order
 
+__device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, double z, float r) {
+  return make_float4((float)(x - g.lo[0]), (float)(y - g.lo[1]), (float)(z - g.lo[2]), r);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
-                                                    int32_t n) {
+                                                    float4 *__restrict__ xyzr, Grid g, int32_t n) {
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
   const int32_t p = perm[s];
-  dst.x[s] = src.x[p];
-  dst.y[s] = src.y[p];
-  dst.z[s] = src.z[p];
-  dst.r[s] = src.r[p];
+  const double x = src.x[p], y = src.y[p], z = src.z[p];
+  const float r = src.r[p];
+  dst.x[s] = x;
+  dst.y[s] = y;
+  dst.z[s] = z;
+  dst.r[s] = r;
   dst.id[s] = src.id[p];
+  xyzr[s] = make_xyzr(g, x, y, z, r);
 #pragma unroll
   for (int k = 0; k < 3; k++) {
     ((Real *)vdst.v[k])[s] = ((const Real *)vsrc.v[k])[p];
@@ -315,8 +327,166 @@ __global__ __launch_bounds__(kBlock) void k_reorder(PosBuf src, VelBuf vsrc, Pos
   scell[s] = cell[p];
 }
 
+
+__global__ __launch_bounds__(kBlock) void k_xyzr(PosBuf p, float4 *__restrict__ xyzr, Grid g, int32_t n) {
+  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n) return;
+  xyzr[s] = make_xyzr(g, p.x[s], p.y[s], p.z[s], p.r[s]);
+}
+
 // --------------------------------------------------------------------------
-// Steps 5-8: contact law
+// Steps 5-6: contact detection over the forward half of the 27-cell stencil.
+// A pair in neighbouring cells is tested by the particle whose cell comes
+// first in (z, y, x) order; a pair in one cell by the lower slot.  Every
+// partner found this way has a higher slot, so the forward list comes out
+// ascending without atomics.
+
+constexpr int kSurv = 16;  // LDS survivor slots per lane
+
+// exact FP64 decision on one prefilter survivor, and its recording: the
+// particle's own forward list (in order) and the partner's backward list
+__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
+                                                 float ri, double xi, double yi, double zi, int32_t t,
+                                                 int32_t &nf, bool &overflow) {
+  const double ex = pos.x[t] - xi, ey = pos.y[t] - yi, ez = pos.z[t] - zi;
+  const double S = (double)ri + (double)pos.r[t];
+  if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
+  if (nf < nb.Kd) {
+    nb.nb_f[(int64_t)nf * N + s] = t;
+  } else {
+    overflow = true;
+  }
+  nf++;
+  const int32_t kb = atomicAdd(&nb.cnt_b[t], 1);
+  if (kb < nb.Kd) {
+    nb.nb_b[(int64_t)kb * N + t] = s;
+  } else {
+    overflow = true;
+  }
+}
+
+// Prefilter one slot range; survivors wait in the lane's LDS slots so that
+// the rare exact test does not sit inside the candidate loop (where any one
+// lane taking it would hold the whole wave).  A lane whose slots fill up
+// drains them itself, in order.
+__device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
+                                                const float4 p, double xi, double yi, double zi, int32_t beg,
+                                                int32_t end, int32_t *surv, int32_t &ns, int32_t &nf,
+                                                bool &overflow) {
+  for (int32_t t = beg; t < end; t++) {
+    const float4 q = nb.xyzr[t];
+    const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+    const float sf = p.w + q.w + nb.eps;
+    if (dx * dx + dy * dy + dz * dz < sf * sf) {
+      if (ns == kSurv) {
+        for (int k = 0; k < kSurv; k++)
+          exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[k * kBlock], nf, overflow);
+        ns = 0;
+      }
+      surv[ns * kBlock] = t;
+      ns++;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const int32_t *__restrict__ scell,
+                                                   const int32_t *__restrict__ cell_start, Grid g, int32_t n,
+                                                   int32_t *err) {
+  __shared__ int32_t surv_all[kSurv * kBlock];
+  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n) return;
+  int32_t *surv = surv_all + threadIdx.x;  // slot k at surv[k * kBlock]
+  const float4 p = nb.xyzr[s];
+  const double xi = pos.x[s], yi = pos.y[s], zi = pos.z[s];
+  const int32_t nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+  const int32_t cc = scell[s];
+  const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
+  const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
+  int32_t nf = 0, ns = 0;
+  bool overflow = false;
+  // own row: the rest of the own cell and the next cell along x
+  const int32_t row0 = (cz * ny + cy) * nx;
+  prefilter_range(nb, pos, n, s, p, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf, overflow);
+  // next row along y in the same plane
+  if (cy + 1 < ny) {
+    const int32_t row = (cz * ny + cy + 1) * nx;
+    prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns, nf,
+                    overflow);
+  }
+  // the three rows of the next plane along z
+  if (cz + 1 < nz) {
+    for (int32_t dy = -1; dy <= 1; dy++) {
+      const int32_t yy = cy + dy;
+      if (yy < 0 || yy >= ny) continue;
+      const int32_t row = ((cz + 1) * ny + yy) * nx;
+      prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns,
+                      nf, overflow);
+    }
+  }
+  // exact tests of the survivors, in slot order
+  for (int32_t k = 0; k < ns; k++)
+    exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[k * kBlock], nf, overflow);
+  nb.cnt_f[s] = nf;
+  if (overflow) raise_err(err, ERR_OVERFLOW);
+}
+
+// fixed-size bitonic network on registers (indices are compile-time)
+template <int M>
+__device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
+#pragma unroll
+  for (int k = 2; k <= M; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < M; i++) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const int32_t u = L[i], w = L[l];
+          const bool sw = up ? (u > w) : (u < w);
+          L[i] = sw ? w : u;
+          L[l] = sw ? u : w;
+        }
+      }
+    }
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void sort_small(int32_t *list, int64_t stride, int32_t cnt) {
+  int32_t L[M];
+#pragma unroll
+  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i * stride] : INT32_MAX;
+  bitonic_sort<M>(L);
+#pragma unroll
+  for (int i = 0; i < M; i++)
+    if (i < cnt) list[i * stride] = L[i];
+}
+
+// ascending order of a particle's backward list (entries arrive by atomics)
+__device__ __forceinline__ void sort_list(int32_t *list, int64_t stride, int32_t cnt) {
+  if (cnt <= 1) return;
+  if (cnt <= 4) {
+    sort_small<4>(list, stride, cnt);
+  } else if (cnt <= 8) {
+    sort_small<8>(list, stride, cnt);
+  } else if (cnt <= 16) {
+    sort_small<16>(list, stride, cnt);
+  } else {
+    for (int32_t k = 1; k < cnt; k++) {
+      const int32_t v = list[k * stride];
+      int32_t j = k - 1;
+      while (j >= 0 && list[j * stride] > v) {
+        list[(j + 1) * stride] = list[j * stride];
+        j--;
+      }
+      list[(j + 1) * stride] = v;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Steps 7-8: contact law
 
 template <typename Real>
 struct LawOut {
@@ -440,11 +610,6 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const int32_t row_i = old_perm ? a.perm[s] : s;
 
-  const int32_t nx = a.grid.nc[0], ny = a.grid.nc[1], nz = a.grid.nc[2];
-  const int32_t cc = a.scell[s];
-  const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
-  const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
-
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   int32_t nnew = 0;
   bool overflow = false;
@@ -452,20 +617,17 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
   int32_t npair = 0, nwall = 0;
   Real *hd = (Real *)a.hnew.d;
 
-  for (int32_t dz = -1; dz <= 1; dz++) {
-    const int32_t zz = cz + dz;
-    if (zz < 0 || zz >= nz) continue;
-    for (int32_t dy = -1; dy <= 1; dy++) {
-      const int32_t yy = cy + dy;
-      if (yy < 0 || yy >= ny) continue;
-      const int32_t row = (zz * ny + yy) * nx;
-      const int32_t beg = a.cell_start[row + x0], end = a.cell_start[row + x1 + 1];
-      for (int32_t t = beg; t < end; t++) {
-        if (t == s) continue;
-        const double dx = a.pos.x[t] - xi, dy_ = a.pos.y[t] - yi, dz_ = a.pos.z[t] - zi;
-        const double d2 = dist2_exact(dx, dy_, dz_);
-        const double S = rid + (double)a.pos.r[t];
-        if (!(d2 < sq_exact(S))) continue;
+  // contact partners in ascending slot: the backward list (lower slots,
+  // sorted here) then the forward list (higher slots, ascending)
+  const int32_t Kd = a.nbr.Kd;
+  const int32_t nbk = min(a.nbr.cnt_b[s], Kd), nfk = min(a.nbr.cnt_f[s], Kd);
+  sort_list(a.nbr.nb_b + s, N, nbk);
+  for (int32_t k = 0; k < nbk + nfk; k++) {
+    const int32_t t = k < nbk ? a.nbr.nb_b[(int64_t)k * N + s] : a.nbr.nb_f[(int64_t)(k - nbk) * N + s];
+    const double dx = a.pos.x[t] - xi, dy_ = a.pos.y[t] - yi, dz_ = a.pos.z[t] - zi;
+    const double d2 = dist2_exact(dx, dy_, dz_);
+    const double S = rid + (double)a.pos.r[t];
+    {
         // a contact: evaluate it in the canonical orientation (lower id first)
         // so that both particles compute bit-identical values
         const int32_t idj = a.pos.id[t];
@@ -485,11 +647,11 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const Real M = ma * mb / (ma + mb);
         Real v[3], spin[3];
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-          const Real va = low ? vi[k] : vj[k], vb = low ? vj[k] : vi[k];
-          const Real wa = low ? wi[k] : wj[k], wb = low ? wj[k] : wi[k];
-          v[k] = va - vb;
-          spin[k] = ra * wa + rb * wb;
+        for (int q = 0; q < 3; q++) {
+          const Real va = low ? vi[q] : vj[q], vb = low ? vj[q] : vi[q];
+          const Real wa = low ? wi[q] : wj[q], wb = low ? wj[q] : wi[q];
+          v[q] = va - vb;
+          spin[q] = ra * wa + rb * wb;
         }
         Real h[3] = {0, 0, 0};
         if (LAW != DEM_LAW_SIMPLE) {
@@ -502,9 +664,9 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
         const Real nxft[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
                               n[0] * o.Ft[1] - n[1] * o.Ft[0]};
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-          F[k] += sg * o.F[k];
-          T[k] += ri * nxft[k];  // Eq. 3; same sign on both bodies
+        for (int q = 0; q < 3; q++) {
+          F[q] += sg * o.F[q];
+          T[q] += ri * nxft[q];  // Eq. 3; same sign on both bodies
         }
         if (low) {
           if (write_hist) {
@@ -523,7 +685,6 @@ __global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
             dmax = fmax(dmax, (double)delta);
           }
         }
-      }
     }
   }
 
@@ -717,12 +878,25 @@ hipError_t launch_kick(int precision, const PosBuf &p, const VelBuf &v, void *co
 
 hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          int32_t n, hipStream_t st) {
+                          float4 *xyzr, const Grid &g, int32_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    k_reorder<double><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, n);
+    k_reorder<double><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, xyzr, g, n);
   else
-    k_reorder<float><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, n);
+    k_reorder<float><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, xyzr, g, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, hipStream_t st) {
+  if (n > 0) k_xyzr<<<blocks_for(n), kBlock, 0, st>>>(p, xyzr, g, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_detect(const PosBuf &p, const NbrBuf &nb, const int32_t *scell, const int32_t *cell_start,
+                         const Grid &g, int32_t n, int32_t *err, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<blocks_for(n), kBlock, 0, st>>>(nb.cnt_b, n, 0);
+  k_detect<<<blocks_for(n), kBlock, 0, st>>>(p, nb, scell, cell_start, g, n, err);
   return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ DEM_E_HIP = -6
 DEM_E_STATE = -7
 DEM_E_CAPACITY = -9
 
+NUM_PHASES = 5
+PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "force")
+
 _LIB = None
 
 
@@ -71,6 +74,9 @@ def lib():
             "dem_grid_dims": ([P, C.POINTER(C.c_int32)], st),
             "dem_diagnostics": ([P, C.POINTER(C.c_double)], st),
             "dem_sync": ([P], st),
+            "dem_set_radii": ([P, P], st),
+            "dem_profile": ([P, C.c_int], st),
+            "dem_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(I64)], st),
             "dem_destroy": ([P], st),
             "dem_status_string": ([st], C.c_char_p),
         }
@@ -227,6 +233,23 @@ class System:
         out = (C.c_double * 10)()
         _check(lib().dem_diagnostics(self.handle, out), "dem_diagnostics")
         return np.array(out[:])
+
+    def set_radii(self, r):
+        r = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1))
+        if r.shape[0] != self.n:
+            raise ValueError("set_radii: one radius per particle")
+        _check(lib().dem_set_radii(self.handle, _ptr(r)), "dem_set_radii")
+
+    def profile(self, enable: bool = True):
+        _check(lib().dem_profile(self.handle, int(bool(enable))), "dem_profile")
+
+    def profile_read(self):
+        """(milliseconds per phase summed over the timed steps, number of
+        timed steps); phases: kick-drift-hash, sort, reorder, detect, force."""
+        ms = (C.c_double * NUM_PHASES)()
+        n = C.c_int64()
+        _check(lib().dem_profile_read(self.handle, ms, C.byref(n)), "dem_profile_read")
+        return np.array(ms[:]), n.value
 
 
 def dem_create(params, x, v, omega, r, **kw) -> System:

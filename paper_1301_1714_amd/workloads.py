@@ -218,24 +218,27 @@ def dense_bed_geometry(seed=3000, n=1 << 24, phi=0.55, median=1.0 / 512.0, sigma
 def dense_bed_params(r, hi, **kw):
     r_min = float(np.min(r))
     p = base_params(box_hi=hi, cell_size=2.0 * float(np.max(r)), precision="mixed",
-                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=16)
+                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=32)
     p.update(kw)
     return p
 
 
-def dense_bed_lattice(seed=3000, n=1 << 24, phi=0.55):
+def dense_bed_lattice(seed=3000, n=1 << 24, phi=0.55, fill_height=1.0):
     """Starting point of the dense bed: every sphere on an FCC site of the
-    4:1:1 box, at rest.  With full radii neighbouring large spheres overlap;
-    the bed is prepared by growing the radii from the lattice's touching
-    scale (see ``lattice_scale``) to full size with strong damping."""
+    4:1:1 box (its lower fill_height fraction), at rest.  With full radii
+    neighbouring large spheres overlap; the bed is prepared by growing the
+    radii from the lattice's touching scale (see ``lattice_scale``) to full
+    size with strong damping."""
     rng, r, hi = dense_bed_geometry(seed, n, phi)
-    x, d_nn = fcc_fill(rng, n, (0, 0, 0), hi, margin=float(r.max()), jitter_frac=0.0)
+    top = (hi[0], hi[1], hi[2] * fill_height)
+    x, d_nn = fcc_fill(rng, n, (0, 0, 0), top, margin=float(r.max()), jitter_frac=0.0)
     # the lattice is filled in a fixed order; shuffle which radius sits where
     perm = rng.permutation(n)
     r = r[perm]
     p = dense_bed_params(r, hi)
     z = np.zeros((n, 3))
-    return dict(name=f"dense_bed_{n}", params=p, x=x, v=z, omega=z.copy(), r=r, d_nn=d_nn)
+    return dict(name=f"dense_bed_{n}", params=p, x=x, v=z, omega=z.copy(), r=r, d_nn=d_nn,
+                fill_height=fill_height)
 
 
 def lattice_scale(r, d_nn):
