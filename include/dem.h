@@ -44,7 +44,7 @@ typedef enum {
     DEM_OK = 0,
     DEM_E_INVALID = -1,          /* bad argument or parameter */
     DEM_E_WORKSPACE = -2,        /* workspace missing or too small */
-    DEM_E_CONTACT_OVERFLOW = -3, /* a particle had more history entries than contacts_per_particle */
+    DEM_E_CONTACT_OVERFLOW = -3, /* more contacts than the contact list can hold */
     DEM_E_OUT_OF_DOMAIN = -4,    /* a particle went more than one cell outside the box */
     DEM_E_NONFINITE = -5,        /* non-finite state or force */
     DEM_E_HIP = -6,              /* a HIP runtime call failed */
@@ -78,8 +78,10 @@ typedef struct {
     double mu;                   /* Coulomb coefficient (Eq. 5), >= 0 */
     double simple_k[3];          /* k_sp, k_da, k_sh of Eq. 1 (DEM_LAW_SIMPLE only) */
     double cell_size;            /* requested cell width (Sec. 4.1), >= 2 max radius */
-    int32_t contacts_per_particle; /* history capacity per particle: contacts with higher-id
-                                      partners plus walls; >= 1 */
+    int32_t contacts_per_particle; /* contact-list capacity: n * this many contacts (each pair
+                                      once, plus wall contacts) may be held; 1..64.  One
+                                      particle may hold at most 64 (its pairs with higher
+                                      slots plus its walls) */
     int32_t precision;           /* dem_precision */
 } dem_params;
 
@@ -103,7 +105,7 @@ dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes);
  *   hip_stream  : hipStream_t for all work of this system.
  * Synchronous.  Errors: DEM_E_INVALID (parameters, radii, keys, cell narrower
  * than the largest contact distance), DEM_E_WORKSPACE, DEM_E_NONFINITE,
- * DEM_E_OUT_OF_DOMAIN, DEM_E_CONTACT_OVERFLOW (history rows), DEM_E_HIP. */
+ * DEM_E_OUT_OF_DOMAIN, DEM_E_CONTACT_OVERFLOW, DEM_E_HIP.  n <= 2^31 / 64. */
 dem_status dem_create(const dem_params *p, int64_t n, const double *x, const double *v, const double *omega,
                       const double *r, const double *F0, const double *T0, int64_t n_hist,
                       const int64_t *hist_pairs, const double *hist_dt, void *workspace, size_t ws_bytes,

@@ -20,19 +20,21 @@ using namespace dem;
 struct dem_system {
   dem_params p;
   int32_t n;
-  int32_t K;
   int prec;
   size_t rsz;  // sizeof(Real)
   Grid grid;
   Consts c;
   PosBuf pos[2];
   VelBuf vel[2];
-  int cp, cv, ch;
+  int cp, cv;  // current position / velocity buffers
+  int gc;      // generation holding the committed tangential history
+  int gs;      // generation holding the contact list of the current positions
   void *F[3], *T[3], *Fe[3], *Te[3];
   int32_t *cell, *rank, *perm, *scell, *counts, *cell_start;
   ScanScratch scan;
-  HistBuf hist[2];
   NbrBuf nbr;
+  PairGen gen[2];
+  PairWork work;
   DiagBuf diag;
   int32_t *err;
   hipStream_t stream;
@@ -62,14 +64,16 @@ struct Carver {
 };
 
 dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
-  if (!p || n < 0 || n >= (int64_t)INT32_MAX - 1) return DEM_E_INVALID;
+  // contact-list offsets are int32: n * kListCap must stay below 2^31
+  if (!p || n < 0 || n > (int64_t)(INT32_MAX / kListCap)) return DEM_E_INVALID;
   if (!(p->dt > 0.0) || !isfinite(p->dt) || !(p->density > 0.0) || !(p->cell_size > 0.0)) return DEM_E_INVALID;
   if (p->law < DEM_LAW_LINEAR || p->law > DEM_LAW_SIMPLE) return DEM_E_INVALID;
   if (!(p->restitution > 0.0 && p->restitution <= 1.0) || !(p->mu >= 0.0)) return DEM_E_INVALID;
   if (p->precision != DEM_PREC_FP64 && p->precision != DEM_PREC_MIXED) return DEM_E_INVALID;
-  if (p->contacts_per_particle < 1 || p->contacts_per_particle > 1024) return DEM_E_INVALID;
+  if (p->contacts_per_particle < 1 || p->contacts_per_particle > kListCap) return DEM_E_INVALID;
   if (p->wall_mask > 0x3F) return DEM_E_INVALID;
   if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
+  if ((int64_t)p->contacts_per_particle * n >= (int64_t)INT32_MAX) return DEM_E_INVALID;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
     const double L = p->box_hi[a] - p->box_lo[a];
@@ -86,9 +90,6 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   g->ncell = ncell;
   return DEM_OK;
 }
-
-// Capacity of each contact list (forward and backward) per particle.
-int32_t list_capacity(int32_t K) { return std::max<int32_t>(16, K + 8); }
 
 // Margin of the FP32 detection prefilter.  Coordinates relative to the box
 // corner lie in (-w, L + w) for cells of width w, so each is rounded to FP32
@@ -111,8 +112,8 @@ float prefilter_eps(const Grid &g, double cell) {
 size_t carve(dem_system *s, char *base) {
   Carver cv{base};
   const size_t N = (size_t)(s->n > 0 ? s->n : 1);
-  const size_t K = (size_t)s->K;
   const size_t R = s->rsz;
+  const size_t P = (size_t)s->work.Pcap;
   for (int b = 0; b < 2; b++) {
     s->pos[b].x = cv.take<double>(N);
     s->pos[b].y = cv.take<double>(N);
@@ -134,22 +135,29 @@ size_t carve(dem_system *s, char *base) {
   s->cell_start = cv.take<int32_t>((size_t)s->grid.ncell + 1);
   int64_t lens[4] = {0, 0, 0, 0};
   int nl = 0;
-  scan_scratch_len(s->grid.ncell, lens, &nl);
+  scan_scratch_len(std::max<int64_t>(s->grid.ncell, (int64_t)N), lens, &nl);
   s->scan.nlevels = nl;
   for (int l = 0; l < 4; l++) {
     s->scan.len[l] = lens[l];
     s->scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
   }
   s->nbr.xyzr = cv.take<float4>(N);
-  s->nbr.cnt_f = cv.take<int32_t>(N);
-  s->nbr.nb_f = cv.take<int32_t>((size_t)s->nbr.Kd * N);
-  s->nbr.cnt_b = cv.take<int32_t>(N);
-  s->nbr.nb_b = cv.take<int32_t>((size_t)s->nbr.Kd * N);
+  s->nbr.cnt = cv.take<int32_t>(N);
+  s->nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
   for (int b = 0; b < 2; b++) {
-    s->hist[b].cnt = cv.take<int32_t>(N);
-    s->hist[b].partner = cv.take<int32_t>(K * N);
-    s->hist[b].d = cv.take_bytes(3 * K * N * R);
+    s->gen[b].ofs = cv.take<int32_t>(N + 1);
+    s->gen[b].s = cv.take<int32_t>(P);
+    s->gen[b].t = cv.take<int32_t>(P);
+    s->gen[b].key = cv.take<int32_t>(P);
+    s->gen[b].dt = cv.take_bytes(4 * R * P);
   }
+  s->work.pf = cv.take_bytes(8 * R * P);
+  s->work.brank = cv.take<int32_t>(P);
+  s->work.pe = cv.take<double>(P);
+  s->work.pd = cv.take<double>(P);
+  s->work.bcnt = cv.take<int32_t>(N);
+  s->work.bofs = cv.take<int32_t>(N + 1);
+  s->work.bwd = cv.take<int32_t>(P);
   s->diag.e_el = cv.take<double>(N);
   s->diag.npair = cv.take<int32_t>(N);
   s->diag.nwall = cv.take<int32_t>(N);
@@ -158,6 +166,13 @@ size_t carve(dem_system *s, char *base) {
   s->diag.out = cv.take<double>(10);
   s->err = cv.take<int32_t>(64);
   return (cv.off + 255) & ~size_t(255);
+}
+
+void init_sizes(dem_system *s, const dem_params *p, int64_t n) {
+  s->n = (int32_t)n;
+  s->prec = p->precision;
+  s->rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  s->work.Pcap = std::max<int64_t>((int64_t)p->contacts_per_particle * n, 256);
 }
 
 void fill_consts(dem_system *s) {
@@ -187,12 +202,12 @@ dem_status map_err(int32_t bits) {
   return DEM_OK;
 }
 
-#define HIP_TRY(expr)                      \
-  do {                                     \
-    if ((expr) != hipSuccess) {            \
-      (void)hipGetLastError();             \
-      return DEM_E_HIP;                    \
-    }                                      \
+#define HIP_TRY(expr)           \
+  do {                          \
+    if ((expr) != hipSuccess) { \
+      (void)hipGetLastError();  \
+      return DEM_E_HIP;         \
+    }                           \
   } while (0)
 
 dem_status sync_and_check(dem_system *s) {
@@ -211,24 +226,31 @@ dem_status sync_and_check(dem_system *s) {
   return s->sticky;
 }
 
-ForceArgs force_args(dem_system *s, int mode, void *const F[3], void *const T[3], const HistBuf &hnew) {
-  ForceArgs a;
+// Steps 5-6 on the current positions, into generation `g`
+hipError_t build_contacts(dem_system *s, int g) {
+  s->gs = g;
+  return launch_contacts(s->pos[s->cp], s->nbr, s->gen[g], s->work, s->scell, s->cell_start, s->grid,
+                         s->c.wall_mask, s->n, s->scan, s->err, s->stream);
+}
+
+// Steps 7-8 on the contact list of generation gs, with the committed history
+// of generation gc
+PairArgs pair_args(dem_system *s, int mode, void *const F[3], void *const T[3]) {
+  PairArgs a;
   memset(&a, 0, sizeof(a));
   a.pos = s->pos[s->cp];
-  a.nbr = s->nbr;
   a.vel_in = s->vel[s->cv];
   a.vel_out = s->vel[s->cv ^ 1];
-  a.scell = s->scell;
-  a.cell_start = s->cell_start;
+  a.cur = s->gen[s->gs];
+  a.old = s->gen[s->gc];
+  a.w = s->work;
   a.perm = s->perm;
-  a.hold = s->hist[s->ch];
-  a.hnew = hnew;
+  a.cell = s->cell;
   for (int k = 0; k < 3; k++) {
     a.F[k] = F[k];
     a.T[k] = T[k];
   }
   a.diag = s->diag;
-  a.K = s->K;
   a.n = s->n;
   a.mode = mode;
   a.grid = s->grid;
@@ -238,17 +260,17 @@ ForceArgs force_args(dem_system *s, int mode, void *const F[3], void *const T[3]
 }
 
 // device -> host copy of a Real array as doubles
-dem_status d2h_real(dem_system *s, const void *src, std::vector<double> &out) {
-  out.resize((size_t)s->n);
-  if (s->n == 0) return DEM_OK;
+dem_status d2h_real(dem_system *s, const void *src, std::vector<double> &out, size_t count) {
+  out.resize(count);
+  if (count == 0) return DEM_OK;
   if (s->prec == DEM_PREC_FP64) {
-    HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(double) * count, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
   } else {
-    std::vector<float> tmp((size_t)s->n);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), src, sizeof(float) * s->n, hipMemcpyDeviceToHost, s->stream));
+    std::vector<float> tmp(count);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    for (int32_t i = 0; i < s->n; i++) out[i] = (double)tmp[i];
+    for (size_t i = 0; i < count; i++) out[i] = (double)tmp[i];
   }
   return DEM_OK;
 }
@@ -276,7 +298,15 @@ dem_status h2d_real(dem_system *s, void *dst, const std::vector<double> &src) {
   return DEM_OK;
 }
 
-// per-particle vector (n x 3, original order) -> three SoA arrays in slot order
+template <typename T>
+dem_status h2d(dem_system *s, T *dst, const std::vector<T> &src) {
+  if (src.empty()) return DEM_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return DEM_OK;
+}
+
+// per-particle vector (n x 3, original order) -> one component in slot order
 void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, std::vector<double> &out) {
   out.resize(id_at_slot.size());
   for (size_t s = 0; s < id_at_slot.size(); s++) out[s] = src[3 * (size_t)id_at_slot[s] + k];
@@ -287,36 +317,28 @@ struct Entry {
   double d[3];
 };
 
-// Read a history table (rows in slot order) as sorted (a, b) entries.
-dem_status read_table(dem_system *s, const HistBuf &hb, bool with_d, std::vector<Entry> &out) {
+// The contacts of a generation as sorted (a, b) keys: (lower id, higher id)
+// for pairs, (id, -1 - w) for walls; with_d also reads delta_t.
+dem_status read_gen(dem_system *s, const PairGen &g, bool with_d, std::vector<Entry> &out) {
   out.clear();
   if (s->n == 0) return DEM_OK;
-  const size_t N = (size_t)s->n, K = (size_t)s->K;
-  std::vector<int32_t> cnt, partner, id;
+  const size_t N = (size_t)s->n;
+  std::vector<int32_t> ofs, key, id;
   dem_status st;
-  if ((st = d2h(s, hb.cnt, cnt, N)) != DEM_OK) return st;
-  if ((st = d2h(s, hb.partner, partner, K * N)) != DEM_OK) return st;
-  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if ((st = d2h(s, (const int32_t *)g.ofs, ofs, N + 1)) != DEM_OK) return st;
+  const size_t P = (size_t)std::min<int64_t>(ofs[N], s->work.Pcap);
+  if ((st = d2h(s, (const int32_t *)g.key, key, P)) != DEM_OK) return st;
+  if ((st = d2h(s, (const int32_t *)s->pos[s->cp].id, id, N)) != DEM_OK) return st;
   std::vector<double> d;
-  if (with_d) {
-    d.resize(3 * K * N);
-    if (s->prec == DEM_PREC_FP64) {
-      HIP_TRY(hipMemcpyAsync(d.data(), hb.d, sizeof(double) * d.size(), hipMemcpyDeviceToHost, s->stream));
-      HIP_TRY(hipStreamSynchronize(s->stream));
-    } else {
-      std::vector<float> tmp(3 * K * N);
-      HIP_TRY(hipMemcpyAsync(tmp.data(), hb.d, sizeof(float) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
-      HIP_TRY(hipStreamSynchronize(s->stream));
-      for (size_t i = 0; i < tmp.size(); i++) d[i] = (double)tmp[i];
-    }
-  }
+  if (with_d && (st = d2h_real(s, g.dt, d, 4 * P)) != DEM_OK) return st;
+  out.reserve(P);
   for (size_t slot = 0; slot < N; slot++) {
-    const int32_t c = std::min<int32_t>(cnt[slot], (int32_t)K);
-    for (int32_t k = 0; k < c; k++) {
+    for (size_t q = (size_t)ofs[slot]; q < std::min<size_t>((size_t)ofs[slot + 1], P); q++) {
       Entry e;
-      e.a = id[slot];
-      e.b = partner[(size_t)k * N + slot];
-      for (int q = 0; q < 3; q++) e.d[q] = with_d ? d[((size_t)q * K + k) * N + slot] : 0.0;
+      const int64_t me = id[slot], other = key[q];
+      e.a = other >= 0 ? std::min(me, other) : me;
+      e.b = other >= 0 ? std::max(me, other) : other;
+      for (int c = 0; c < 3; c++) e.d[c] = with_d ? d[4 * q + c] : 0.0;
       out.push_back(e);
     }
   }
@@ -328,14 +350,15 @@ dem_status read_table(dem_system *s, const HistBuf &hb, bool with_d, std::vector
 
 dem_status fill_i32(dem_system *s, int32_t *p, size_t count, int32_t value) {
   if (count == 0) return DEM_OK;
-  if (value == 0) {
-    HIP_TRY(hipMemsetAsync(p, 0, count * sizeof(int32_t), s->stream));
-  } else {
-    std::vector<int32_t> tmp(count, value);
-    HIP_TRY(hipMemcpyAsync(p, tmp.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-  }
-  return DEM_OK;
+  std::vector<int32_t> tmp(count, value);
+  return h2d(s, p, tmp);
+}
+
+static void free_events(dem_system *s) {
+  if (!s->events) return;
+  for (hipEvent_t e : *s->events) (void)hipEventDestroy(e);
+  delete s->events;
+  s->events = nullptr;
 }
 
 }  // namespace
@@ -363,11 +386,7 @@ dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes) {
   memset(&s, 0, sizeof(s));
   dem_status st = check_params(p, n, &s.grid);
   if (st != DEM_OK) return st;
-  s.n = (int32_t)n;
-  s.K = p->contacts_per_particle;
-  s.nbr.Kd = list_capacity(s.K);
-  s.prec = p->precision;
-  s.rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  init_sizes(&s, p, n);
   *bytes = carve(&s, nullptr);
   return DEM_OK;
 }
@@ -412,16 +431,12 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
 
   dem_system *s = new (std::nothrow) dem_system;
   if (!s) return DEM_E_INVALID;
-  memset(s, 0, sizeof(*s));
+  memset((void *)s, 0, sizeof(*s));
   s->p = *p;
-  s->n = (int32_t)n;
-  s->K = p->contacts_per_particle;
-  s->nbr.Kd = list_capacity(s->K);
-  s->nbr.eps = prefilter_eps(g, p->cell_size);
-  s->prec = p->precision;
-  s->rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  init_sizes(s, p, n);
   s->grid = g;
   s->stream = (hipStream_t)hip_stream;
+  s->nbr.eps = prefilter_eps(g, p->cell_size);
   fill_consts(s);
   const size_t need = carve(s, nullptr);
   if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) {
@@ -432,6 +447,7 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
 
   auto fail = [&](dem_status e) {
     (void)hipStreamSynchronize(s->stream);
+    free_events(s);
     delete s;
     return e;
   };
@@ -446,9 +462,7 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
     double *dst[3] = {pb.x, pb.y, pb.z};
     for (int k = 0; k < 3; k++) {
       gather3(x, ids, k, tmp);
-      if (N && (hipMemcpyAsync(dst[k], tmp.data(), 8 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-                hipStreamSynchronize(s->stream) != hipSuccess))
-        return fail(DEM_E_HIP);
+      if (h2d(s, dst[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
     }
     for (int k = 0; k < 3; k++) {
       gather3(v, ids, k, tmp);
@@ -456,10 +470,7 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
       gather3(omega, ids, k, tmp);
       if (h2d_real(s, s->vel[0].w[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
     }
-    if (N && (hipMemcpyAsync(pb.r, rf.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-              hipMemcpyAsync(pb.id, ids.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-              hipStreamSynchronize(s->stream) != hipSuccess))
-      return fail(DEM_E_HIP);
+    if (h2d(s, pb.r, rf) != DEM_OK || h2d(s, pb.id, ids) != DEM_OK) return fail(DEM_E_HIP);
   }
   // Steps 2-4 on the initial positions
   if (launch_hash(s->pos[0], s->n, s->grid, s->cell, s->err, s->stream) != hipSuccess) return fail(DEM_E_HIP);
@@ -471,38 +482,56 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
     return fail(DEM_E_HIP);
   s->cp = 1;
   s->cv = 1;
-  s->ch = 0;
-  if (launch_detect(s->pos[1], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream) != hipSuccess)
-    return fail(DEM_E_HIP);
+  s->gc = 0;
+  // Steps 5-6: the contacts of the initial positions go to generation 1
+  if (build_contacts(s, 1) != hipSuccess) return fail(DEM_E_HIP);
   st = sync_and_check(s);
   if (st != DEM_OK) return fail(st);
   std::vector<int32_t> id_at_slot;
   if (d2h(s, s->pos[1].id, id_at_slot, N) != DEM_OK) return fail(DEM_E_HIP);
-  // history rows, in sorted-slot order
-  for (int b = 0; b < 2; b++)
-    if (fill_i32(s, s->hist[b].cnt, N, 0) != DEM_OK) return fail(DEM_E_HIP);
-  if (keep_hist) {
+  // the given history becomes generation 0, filed under the lower slot of
+  // each pair (the particle for a wall) in the sorted order
+  {
     std::vector<int32_t> slot_of(N);
     for (size_t sl = 0; sl < N; sl++) slot_of[id_at_slot[sl]] = (int32_t)sl;
-    const size_t K = (size_t)s->K;
-    std::vector<int32_t> cnt(N, 0), partner(K * N, 0);
-    std::vector<double> d(3 * K * N, 0.0);
-    for (int64_t k = 0; k < n_hist; k++) {
-      const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
-      const int32_t sl = slot_of[a];
-      const int32_t e = cnt[sl]++;
-      if (e >= (int32_t)K) return fail(DEM_E_CONTACT_OVERFLOW);
-      for (int32_t q = 0; q < e; q++)
-        if (partner[(size_t)q * N + sl] == (int32_t)b) return fail(DEM_E_INVALID);  // duplicate key
-      partner[(size_t)e * N + sl] = (int32_t)b;
-      for (int q = 0; q < 3; q++) d[((size_t)q * K + e) * N + sl] = hist_dt[3 * k + q];
+    std::vector<int32_t> cnt(N + 1, 0);
+    struct Rec {
+      int32_t owner, key;
+      double d[3];
+    };
+    std::vector<Rec> recs;
+    if (keep_hist) {
+      recs.reserve((size_t)n_hist);
+      for (int64_t k = 0; k < n_hist; k++) {
+        const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
+        Rec rc;
+        if (b >= 0) {
+          const int32_t sa = slot_of[a], sb = slot_of[b];
+          rc.owner = std::min(sa, sb);
+          rc.key = (int32_t)(sa < sb ? b : a);
+        } else {
+          rc.owner = slot_of[a];
+          rc.key = (int32_t)b;
+        }
+        memcpy(rc.d, hist_dt + 3 * k, sizeof(rc.d));
+        recs.push_back(rc);
+      }
+      std::stable_sort(recs.begin(), recs.end(), [](const Rec &u, const Rec &w) { return u.owner < w.owner; });
+      for (size_t k = 1; k < recs.size(); k++)
+        if (recs[k].owner == recs[k - 1].owner && recs[k].key == recs[k - 1].key) return fail(DEM_E_INVALID);
     }
-    const HistBuf &hb = s->hist[0];
-    if (hipMemcpyAsync(hb.cnt, cnt.data(), 4 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(hb.partner, partner.data(), 4 * K * N, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
+    if ((int64_t)recs.size() > s->work.Pcap) return fail(DEM_E_CONTACT_OVERFLOW);
+    std::vector<int32_t> ofs(N + 1, 0), key(recs.size());
+    std::vector<double> d(4 * recs.size(), 0.0);
+    for (const Rec &rc : recs) ofs[rc.owner + 1]++;
+    for (size_t k = 0; k < N; k++) ofs[k + 1] += ofs[k];
+    for (size_t k = 0; k < recs.size(); k++) {
+      key[k] = recs[k].key;
+      for (int c = 0; c < 3; c++) d[4 * k + c] = recs[k].d[c];
+    }
+    const PairGen &g0 = s->gen[0];
+    if (h2d(s, g0.ofs, ofs) != DEM_OK || h2d(s, g0.key, key) != DEM_OK || h2d_real(s, g0.dt, d) != DEM_OK)
       return fail(DEM_E_HIP);
-    if (h2d_real(s, hb.d, d) != DEM_OK) return fail(DEM_E_HIP);
   }
   // forces of the initial state
   if (F0) {
@@ -514,8 +543,8 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
       if (h2d_real(s, s->T[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
     }
   } else {
-    ForceArgs a = force_args(s, 0, s->F, s->T, s->hist[s->ch ^ 1]);
-    if (launch_force(s->prec, a, s->stream) != hipSuccess) return fail(DEM_E_HIP);
+    PairArgs a = pair_args(s, 0, s->F, s->T);
+    if (launch_forces(s->prec, a, s->stream) != hipSuccess) return fail(DEM_E_HIP);
   }
   st = sync_and_check(s);
   if (st != DEM_OK) return fail(st);
@@ -527,6 +556,7 @@ dem_status dem_step(dem_system *s, int64_t nsteps) {
   if (!s) return DEM_E_STATE;
   if (nsteps < 0) return DEM_E_INVALID;
   if (s->sticky != DEM_OK) return s->sticky;
+  bool drifted = false;  // the previous step's closing pass already ran Steps 1-2
   for (int64_t k = 0; k < nsteps; k++) {
     hipEvent_t *ev = nullptr;
     if (s->profiling && s->timed < DEM_PROFILE_CAPACITY) {
@@ -538,8 +568,8 @@ dem_status dem_step(dem_system *s, int64_t nsteps) {
     };
     mark(0);
     // Step 1 (opening half kick, drift) fused with Step 2 (hash)
-    if (launch_kick_drift_hash(s->prec, s->pos[s->cp], s->vel[s->cv], s->F, s->T, s->n, s->c, s->grid, s->cell,
-                               s->err, s->stream) != hipSuccess)
+    if (!drifted && launch_kick_drift_hash(s->prec, s->pos[s->cp], s->vel[s->cv], s->F, s->T, s->n, s->c,
+                                           s->grid, s->cell, s->err, s->stream) != hipSuccess)
       return s->sticky = DEM_E_HIP;
     mark(1);
     // Step 3
@@ -554,17 +584,19 @@ dem_status dem_step(dem_system *s, int64_t nsteps) {
     s->cp ^= 1;
     s->cv ^= 1;
     mark(3);
-    // Steps 5-6
-    if (launch_detect(s->pos[s->cp], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream) !=
-        hipSuccess)
-      return s->sticky = DEM_E_HIP;
+    // Steps 5-6 into the generation that does not hold the committed history
+    if (build_contacts(s, s->gc ^ 1) != hipSuccess) return s->sticky = DEM_E_HIP;
     mark(4);
-    // Steps 5-8 and the closing half kick
-    ForceArgs a = force_args(s, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, s->F, s->T, s->hist[s->ch ^ 1]);
-    if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+    // Steps 7-8 and the closing half kick; the new history is committed.
+    // Between two steps of this call the closing pass also runs the next
+    // step's opening kick, drift and hash (the state stays in registers).
+    drifted = k + 1 < nsteps;
+    PairArgs a = pair_args(s, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM | (drifted ? MODE_DRIFT : 0), s->F,
+                           s->T);
+    if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
     mark(5);
     s->cv ^= 1;
-    s->ch ^= 1;
+    s->gc = s->gs;
     s->steps++;
   }
   return DEM_OK;
@@ -580,17 +612,18 @@ dem_status dem_forces(dem_system *s, double *F, double *T) {
   if (!F || !T) return DEM_E_INVALID;
   dem_status st = sync_and_check(s);
   if (st != DEM_OK) return st;
-  ForceArgs a = force_args(s, 0, s->Fe, s->Te, s->hist[s->ch ^ 1]);
-  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+  PairArgs a = pair_args(s, 0, s->Fe, s->Te);
+  if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
   if ((st = sync_and_check(s)) != DEM_OK) return st;
+  const size_t N = (size_t)s->n;
   std::vector<int32_t> id;
-  if ((st = d2h(s, s->pos[s->cp].id, id, (size_t)s->n)) != DEM_OK) return st;
+  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
   std::vector<double> tmp;
   for (int k = 0; k < 3; k++) {
-    if ((st = d2h_real(s, s->Fe[k], tmp)) != DEM_OK) return st;
-    for (int32_t i = 0; i < s->n; i++) F[3 * (size_t)id[i] + k] = tmp[i];
-    if ((st = d2h_real(s, s->Te[k], tmp)) != DEM_OK) return st;
-    for (int32_t i = 0; i < s->n; i++) T[3 * (size_t)id[i] + k] = tmp[i];
+    if ((st = d2h_real(s, s->Fe[k], tmp, N)) != DEM_OK) return st;
+    for (size_t i = 0; i < N; i++) F[3 * (size_t)id[i] + k] = tmp[i];
+    if ((st = d2h_real(s, s->Te[k], tmp, N)) != DEM_OK) return st;
+    for (size_t i = 0; i < N; i++) T[3 * (size_t)id[i] + k] = tmp[i];
   }
   return DEM_OK;
 }
@@ -616,7 +649,7 @@ dem_status dem_read_state(dem_system *s, double *x, double *v, double *omega, do
     if (!outs[q]) continue;
     std::vector<double> tmp;
     for (int k = 0; k < 3; k++) {
-      if ((st = d2h_real(s, arrs[q][k], tmp)) != DEM_OK) return st;
+      if ((st = d2h_real(s, arrs[q][k], tmp, N)) != DEM_OK) return st;
       for (size_t i = 0; i < N; i++) outs[q][3 * (size_t)id[i] + k] = tmp[i];
     }
   }
@@ -629,7 +662,7 @@ dem_status dem_read_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t
   dem_status st = sync_and_check(s);
   if (st != DEM_OK) return st;
   std::vector<Entry> e;
-  if ((st = read_table(s, s->hist[s->ch], true, e)) != DEM_OK) return st;
+  if (s->p.law != DEM_LAW_SIMPLE && (st = read_gen(s, s->gen[s->gc], true, e)) != DEM_OK) return st;
   *n_out = (int64_t)e.size();
   if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
   for (size_t k = 0; k < e.size(); k++) {
@@ -648,13 +681,8 @@ dem_status dem_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pai
   if (!n_out) return DEM_E_INVALID;
   dem_status st = sync_and_check(s);
   if (st != DEM_OK) return st;
-  // detection into the spare history table (overwritten by the next step)
-  const HistBuf &spare = s->hist[s->ch ^ 1];
-  ForceArgs a = force_args(s, MODE_WRITE_HIST | MODE_LIST, s->Fe, s->Te, spare);
-  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
-  if ((st = sync_and_check(s)) != DEM_OK) return st;
   std::vector<Entry> e;
-  if ((st = read_table(s, spare, false, e)) != DEM_OK) return st;
+  if ((st = read_gen(s, s->gen[s->gs], false, e)) != DEM_OK) return st;
   *n_out = (int64_t)e.size();
   if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
   for (size_t k = 0; k < e.size() && pairs; k++) {
@@ -675,7 +703,7 @@ dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot
     if ((st = d2h(s, (const int32_t *)s->scell, sc, N)) != DEM_OK) return st;
     for (size_t i = 0; i < N; i++) cell_of_id[id[i]] = sc[i];
   }
-  if (id_at_slot) memcpy(id_at_slot, id.data(), 4 * N);
+  if (id_at_slot && N) memcpy(id_at_slot, id.data(), 4 * N);
   if (cell_start) {
     std::vector<int32_t> cs;
     if ((st = d2h(s, (const int32_t *)s->cell_start, cs, (size_t)s->grid.ncell + 1)) != DEM_OK) return st;
@@ -696,8 +724,8 @@ dem_status dem_diagnostics(dem_system *s, double out[10]) {
   if (!out) return DEM_E_INVALID;
   dem_status st = sync_and_check(s);
   if (st != DEM_OK) return st;
-  ForceArgs a = force_args(s, MODE_DIAG, s->Fe, s->Te, s->hist[s->ch ^ 1]);
-  if (launch_force(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
+  PairArgs a = pair_args(s, MODE_DIAG, s->Fe, s->Te);
+  if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
   if (launch_diag_reduce(s->prec, s->pos[s->cp], s->vel[s->cv], s->diag, s->n, s->c, s->grid, s->stream) !=
       hipSuccess)
     return s->sticky = DEM_E_HIP;
@@ -728,19 +756,12 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
   std::vector<float> slot_r(N);
   for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
   if (N) {
-    HIP_TRY(hipMemcpyAsync(s->pos[s->cp].r, slot_r.data(), 4 * N, hipMemcpyHostToDevice, s->stream));
+    if ((st = h2d(s, s->pos[s->cp].r, slot_r)) != DEM_OK) return st;
     HIP_TRY(launch_xyzr(s->pos[s->cp], s->nbr.xyzr, s->grid, s->n, s->stream));
-    HIP_TRY(launch_detect(s->pos[s->cp], s->nbr, s->scell, s->cell_start, s->grid, s->n, s->err, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    // the contact list of the new radii, beside the committed history
+    HIP_TRY(build_contacts(s, s->gc ^ 1));
   }
   return sync_and_check(s);
-}
-
-static void free_events(dem_system *s) {
-  if (!s->events) return;
-  for (hipEvent_t e : *s->events) (void)hipEventDestroy(e);
-  delete s->events;
-  s->events = nullptr;
 }
 
 dem_status dem_profile(dem_system *s, int enable) {

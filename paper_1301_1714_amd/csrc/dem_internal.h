@@ -1,19 +1,23 @@
 // dem_internal.h -- device data layout and kernel launchers of libdem.so.
 //
-// Layout in HBM (structure of arrays, every array indexed by the sorted slot
-// of the last cell sort, Sec. 4.1 / Step 4):
+// Layout in HBM (structure of arrays, every per-particle array indexed by
+// the sorted slot of the last cell sort, Sec. 4.1 / Step 4):
 //   pos[2]   x, y, z (FP64), r (FP32), id (int32)          -- double-buffered
 //   vel[2]   vx, vy, vz, wx, wy, wz (Real)                   -- double-buffered
 //   F, T     contact force / torque of the last evaluation (Real)
 //   cell     CM of the pre-sort order; rank, perm (new slot -> old slot)
 //   scell    cell of each sorted slot; cell_start[ncell + 1]
-//   hist[2]  tangential-history rows, one per slot: cnt, partner[K][N] and
-//            delta_t[3][K][N] (Real); a row holds the contacts of its particle
-//            with higher-id partners and with walls (partner = -1 - w)
-//   nbr      contact lists of the current positions: xyzr (FP32 copy of
-//            x - lo and r, the detection prefilter's input), forward partners
-//            (higher slots, found by the particle itself, ascending) and
-//            backward partners (lower slots, appended by them)
+//   nbr      detection output: xyzr (FP32 copy of x - lo and r, the
+//            prefilter's input) and, per particle, its contacts with higher
+//            slots in ascending order followed by its walls (-1 - w)
+//   gen[2]   two generations of the compact contact list, CSR by owner slot
+//            (the lower slot of a pair): ofs[N + 1], then per contact the
+//            owner s, partner t (slot or -1 - w), history key (partner id or
+//            -1 - w) and the tangential displacement delta_t (Real4, as seen
+//            from the lower particle id).  One generation holds the committed
+//            history, the other is rebuilt for the new positions.
+//   work     per-contact force on the owner and n x F_t (2 x Real4), and the
+//            backward CSR (contacts of each particle as the partner)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -26,14 +30,16 @@ namespace dem {
 
 enum ErrBits : int32_t { ERR_DOMAIN = 1, ERR_OVERFLOW = 2, ERR_NONFINITE = 4 };
 
-// force-kernel modes
+// contact-evaluation modes
 enum ModeBits : int32_t {
-  MODE_WRITE_HIST = 1,  // write the new history rows
+  MODE_WRITE_HIST = 1,  // write the new tangential displacements
   MODE_KICK = 2,        // closing half kick into the other velocity buffer
   MODE_DIAG = 4,        // per-particle elastic energy / contact counts / max overlap
-  MODE_OLD_PERM = 8,    // old history rows are found through perm (after a re-sort)
-  MODE_LIST = 16        // with MODE_WRITE_HIST: record contacts even for the simple law
+  MODE_OLD_PERM = 8,    // committed history is in the pre-sort slot order (use perm)
+  MODE_DRIFT = 16       // with MODE_KICK: also the next step's opening kick, drift and hash
 };
+
+constexpr int32_t kListCap = 64;  // detection: contacts per particle (forward + walls)
 
 struct Grid {
   double lo[3], hi[3];
@@ -63,20 +69,30 @@ struct VelBuf {
   void *v[3], *w[3];
 };
 
-struct HistBuf {
-  int32_t *cnt;      // [N]
-  int32_t *partner;  // [K][N]
-  void *d;           // [3][K][N] Real
+struct NbrBuf {
+  float4 *xyzr;  // [N] (x - lo, y - lo, z - lo, r), FP32
+  int32_t *cnt;  // [N] entries used in nb (clamped to kListCap)
+  int32_t *nb;   // [kListCap][N]
+  float eps;     // prefilter margin: bounds the FP32 error of |x_j - x_i|
 };
 
-struct NbrBuf {
-  float4 *xyzr;    // [N] (x - lo, y - lo, z - lo, r), FP32
-  int32_t *cnt_f;  // [N]
-  int32_t *nb_f;   // [Kd][N] partner slots > own slot, ascending
-  int32_t *cnt_b;  // [N]
-  int32_t *nb_b;   // [Kd][N] partner slots < own slot, in arrival order
-  int32_t Kd;
-  float eps;       // prefilter margin: bounds the FP32 error of |x_j - x_i|
+struct PairGen {
+  int32_t *ofs;  // [N + 1]
+  int32_t *s;    // [Pcap]
+  int32_t *t;    // [Pcap]
+  int32_t *key;  // [Pcap]
+  void *dt;      // [Pcap] Real4
+};
+
+struct PairWork {
+  void *pf;       // [2 Pcap] Real4: force on the owner, then n x F_t (canonical orientation)
+  int32_t *brank; // [Pcap] rank of the contact in its partner's backward list
+  double *pe;     // [Pcap] elastic energy (diagnostics)
+  double *pd;     // [Pcap] overlap (diagnostics)
+  int32_t *bcnt;  // [N] backward counts, then fill counters
+  int32_t *bofs;  // [N + 1]
+  int32_t *bwd;   // [Pcap] contact indices grouped by partner
+  int64_t Pcap;
 };
 
 struct DiagBuf {
@@ -88,17 +104,15 @@ struct DiagBuf {
   double *out;      // [10]
 };
 
-struct ForceArgs {
+struct PairArgs {
   PosBuf pos;
-  NbrBuf nbr;
   VelBuf vel_in, vel_out;
-  const int32_t *scell;
-  const int32_t *cell_start;
-  const int32_t *perm;
-  HistBuf hold, hnew;
+  PairGen cur, old;     // cur: contacts of the current positions; old: committed history
+  PairWork w;
+  const int32_t *perm;  // with MODE_OLD_PERM: current slot -> slot of `old`
   void *F[3], *T[3];
   DiagBuf diag;
-  int32_t K;
+  int32_t *cell;        // with MODE_DRIFT: the cells of the drifted positions
   int32_t n;
   int32_t mode;
   Grid grid;
@@ -117,17 +131,18 @@ hipError_t launch_hash(const PosBuf &p, int32_t n, const Grid &g, int32_t *cell,
 hipError_t launch_kick_drift_hash(int precision, const PosBuf &p, const VelBuf &v, void *const F[3],
                                   void *const T[3], int32_t n, const Consts &c, const Grid &g, int32_t *cell,
                                   int32_t *err, hipStream_t st);
-hipError_t launch_kick(int precision, const PosBuf &p, const VelBuf &v, void *const F[3], void *const T[3],
-                       int32_t n, const Consts &c, hipStream_t st);
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
 hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
 hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
-hipError_t launch_detect(const PosBuf &p, const NbrBuf &nb, const int32_t *scell, const int32_t *cell_start,
-                         const Grid &g, int32_t n, int32_t *err, hipStream_t st);
-hipError_t launch_force(int precision, const ForceArgs &a, hipStream_t st);
+// Steps 5-6: detection and the compact contact list (structure of `gen`)
+hipError_t launch_contacts(const PosBuf &p, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                           const int32_t *scell, const int32_t *cell_start, const Grid &g, uint32_t wall_mask,
+                           int32_t n, const ScanScratch &sc, int32_t *err, hipStream_t st);
+// Steps 7-8: contact forces on the list of a.cur, per-particle sums, kick
+hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const PosBuf &p, const VelBuf &v, const DiagBuf &d, int32_t n,
                               const Consts &c, const Grid &g, hipStream_t st);
 int64_t scan_scratch_len(int64_t n, int64_t *lens, int *nlevels);

@@ -13,13 +13,18 @@
 //   Steps 5-6    k_detect: one lane per sorted particle sweeps the forward
 //                half of the 27 cells of Eq. 12 (each pair is tested once),
 //                rejects with a conservative FP32 test and decides the rest
-//                exactly in FP64; hits go to the particle's own forward list
-//                (ascending, no atomics) and to the partner's backward list
-//   Steps 7-8    k_force: one lane per sorted particle walks its compact
-//                contact list in ascending partner slot, evaluates the contact
-//                law (Eqs. 2-10, or Eq. 1) and the walls, sums in that fixed
-//                order (no atomics), updates the tangential history and applies
-//                the closing half kick
+//                exactly in FP64; its contacts (ascending partner slot) and
+//                walls form its list.  k_pairs / k_bwd: the lists become one
+//                compact contact array (CSR by owner slot, from a scan) and a
+//                backward index per partner (counting sort)
+//   Steps 7-8    k_pair_force: one lane per contact -- every lane of a wave
+//                evaluates a real contact, whatever the particles' contact
+//                counts -- looks up the tangential history in the owner's
+//                segment of the previous step's array and evaluates the law
+//                (Eqs. 2-10, or Eq. 1) once per pair.  k_gather: one lane per
+//                particle sums its contacts in a fixed order (lower partners,
+//                higher partners, walls; no atomics) and applies the closing
+//                half kick
 // No step is a dense contraction, so nothing here uses the matrix cores.
 #include <math.h>
 
@@ -92,6 +97,22 @@ __device__ __forceinline__ void half_kick(const Consts &c, Real m, Real I, const
   }
 }
 
+// Step 1 drift x += dt v and Step 2 hash of the new position
+template <typename Real>
+__device__ __forceinline__ void drift_hash(const PosBuf &p, int32_t i, const Real v[3], const Consts &c,
+                                           const Grid &g, int32_t *cell, int32_t *err) {
+#pragma clang fp contract(off)
+  const double x = p.x[i] + c.dt * (double)v[0];
+  const double y = p.y[i] + c.dt * (double)v[1];
+  const double z = p.z[i] + c.dt * (double)v[2];
+  p.x[i] = x;
+  p.y[i] = y;
+  p.z[i] = z;
+  int32_t cc;
+  if (!hash_cell(g, x, y, z, &cc)) raise_err(err, ERR_DOMAIN);
+  cell[i] = cc;
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_kick_drift_hash(PosBuf p, VelBuf vb, const Real *__restrict__ Fx,
                                                             const Real *__restrict__ Fy,
@@ -118,39 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift_hash(PosBuf p, VelBuf vb,
     V[k][i] = v[k];
     Wv[k][i] = w[k];
   }
-  const double x = p.x[i] + c.dt * (double)v[0];
-  const double y = p.y[i] + c.dt * (double)v[1];
-  const double z = p.z[i] + c.dt * (double)v[2];
-  p.x[i] = x;
-  p.y[i] = y;
-  p.z[i] = z;
-  int32_t cc;
-  if (!hash_cell(g, x, y, z, &cc)) raise_err(err, ERR_DOMAIN);
-  cell[i] = cc;
-}
-
-template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_kick(PosBuf p, VelBuf vb, const Real *__restrict__ Fx,
-                                                 const Real *__restrict__ Fy, const Real *__restrict__ Fz,
-                                                 const Real *__restrict__ Tx, const Real *__restrict__ Ty,
-                                                 const Real *__restrict__ Tz, int32_t n, Consts c) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  Real *V[3] = {(Real *)vb.v[0], (Real *)vb.v[1], (Real *)vb.v[2]};
-  Real *Wv[3] = {(Real *)vb.w[0], (Real *)vb.w[1], (Real *)vb.w[2]};
-  const Real r = (Real)p.r[i];
-  const Real m = mass_of<Real>(c, r);
-  const Real I = (Real)0.4 * m * r * r;
-  Real v[3] = {V[0][i], V[1][i], V[2][i]};
-  Real w[3] = {Wv[0][i], Wv[1][i], Wv[2][i]};
-  const Real F[3] = {Fx[i], Fy[i], Fz[i]};
-  const Real T[3] = {Tx[i], Ty[i], Tz[i]};
-  half_kick<Real>(c, m, I, F, T, v, w);
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    V[k][i] = v[k];
-    Wv[k][i] = w[k];
-  }
+  drift_hash(p, i, v, c, g, cell, err);
 }
 
 // --------------------------------------------------------------------------
@@ -161,11 +150,26 @@ __global__ __launch_bounds__(kBlock) void k_fill(int32_t *a, int64_t len, int32_
   if (i < len) a[i] = value;
 }
 
+// Cell counts and each particle's rank in its cell.  The input is in the
+// previous step's sorted order, so neighbouring lanes mostly share a cell:
+// each run of equal cells within a wave takes one atomic for its length.
 __global__ __launch_bounds__(kBlock) void k_count(const int32_t *__restrict__ cell, int32_t *__restrict__ rank,
                                                   int32_t *counts, int32_t n) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  rank[i] = atomicAdd(&counts[cell[i]], 1);
+  const bool valid = i < n;
+  const int32_t c = valid ? cell[i] : -1;
+  const int lane = threadIdx.x & 63;
+  const int32_t prev = __shfl_up(c, 1);
+  const bool head = !valid || lane == 0 || prev != c;  // invalid lanes end every run
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const int start = 63 - __clzll(heads & upto);
+  const unsigned long long above = heads & ~upto;
+  const int next = above ? __ffsll((long long)above) - 1 : 64;
+  int32_t base = 0;
+  if (valid && head) base = atomicAdd(&counts[c], next - lane);
+  base = __shfl(base, start);
+  if (valid) rank[i] = base + (lane - start);
 }
 
 constexpr int kScanItems = 16;
@@ -338,31 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(PosBuf p, float4 *__restrict__ 
 // Steps 5-6: contact detection over the forward half of the 27-cell stencil.
 // A pair in neighbouring cells is tested by the particle whose cell comes
 // first in (z, y, x) order; a pair in one cell by the lower slot.  Every
-// partner found this way has a higher slot, so the forward list comes out
-// ascending without atomics.
+// partner found this way has a higher slot, so the list comes out ascending
+// without atomics.
 
 constexpr int kSurv = 16;  // LDS survivor slots per lane
 
-// exact FP64 decision on one prefilter survivor, and its recording: the
-// particle's own forward list (in order) and the partner's backward list
+// exact FP64 decision on one prefilter survivor (Steps 6-7: the contact test)
 __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
                                                  float ri, double xi, double yi, double zi, int32_t t,
-                                                 int32_t &nf, bool &overflow) {
+                                                 int32_t &nf) {
   const double ex = pos.x[t] - xi, ey = pos.y[t] - yi, ez = pos.z[t] - zi;
   const double S = (double)ri + (double)pos.r[t];
   if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
-  if (nf < nb.Kd) {
-    nb.nb_f[(int64_t)nf * N + s] = t;
-  } else {
-    overflow = true;
-  }
+  if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = t;
   nf++;
-  const int32_t kb = atomicAdd(&nb.cnt_b[t], 1);
-  if (kb < nb.Kd) {
-    nb.nb_b[(int64_t)kb * N + t] = s;
-  } else {
-    overflow = true;
-  }
 }
 
 // Prefilter one slot range; survivors wait in the lane's LDS slots so that
@@ -371,16 +364,14 @@ __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf 
 // drains them itself, in order.
 __device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
                                                 const float4 p, double xi, double yi, double zi, int32_t beg,
-                                                int32_t end, int32_t *surv, int32_t &ns, int32_t &nf,
-                                                bool &overflow) {
+                                                int32_t end, int32_t *surv, int32_t &ns, int32_t &nf) {
   for (int32_t t = beg; t < end; t++) {
     const float4 q = nb.xyzr[t];
     const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
     const float sf = p.w + q.w + nb.eps;
     if (dx * dx + dy * dy + dz * dz < sf * sf) {
       if (ns == kSurv) {
-        for (int k = 0; k < kSurv; k++)
-          exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[k * kBlock], nf, overflow);
+        for (int k = 0; k < kSurv; k++) exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[k * kBlock], nf);
         ns = 0;
       }
       surv[ns * kBlock] = t;
@@ -390,8 +381,8 @@ __device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &
 }
 
 __global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const int32_t *__restrict__ scell,
-                                                   const int32_t *__restrict__ cell_start, Grid g, int32_t n,
-                                                   int32_t *err) {
+                                                   const int32_t *__restrict__ cell_start, Grid g,
+                                                   uint32_t wall_mask, int32_t n, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
@@ -403,15 +394,13 @@ __global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const 
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
   int32_t nf = 0, ns = 0;
-  bool overflow = false;
   // own row: the rest of the own cell and the next cell along x
   const int32_t row0 = (cz * ny + cy) * nx;
-  prefilter_range(nb, pos, n, s, p, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf, overflow);
+  prefilter_range(nb, pos, n, s, p, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf);
   // next row along y in the same plane
   if (cy + 1 < ny) {
     const int32_t row = (cz * ny + cy + 1) * nx;
-    prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns, nf,
-                    overflow);
+    prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns, nf);
   }
   // the three rows of the next plane along z
   if (cz + 1 < nz) {
@@ -420,14 +409,63 @@ __global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const 
       if (yy < 0 || yy >= ny) continue;
       const int32_t row = ((cz + 1) * ny + yy) * nx;
       prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns,
-                      nf, overflow);
+                      nf);
     }
   }
   // exact tests of the survivors, in slot order
-  for (int32_t k = 0; k < ns; k++)
-    exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[k * kBlock], nf, overflow);
-  nb.cnt_f[s] = nf;
-  if (overflow) raise_err(err, ERR_OVERFLOW);
+  for (int32_t k = 0; k < ns; k++) exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[k * kBlock], nf);
+  // Step 8: walls, particles of infinite radius, after the pairs
+  if (wall_mask) {
+    const double xs[3] = {xi, yi, zi};
+    const double rid = (double)p.w;
+    for (int w = 0; w < 6; w++) {
+      if (!((wall_mask >> w) & 1)) continue;
+      const int ax = w >> 1;
+      const double gap = (w & 1) ? (g.hi[ax] - xs[ax]) : (xs[ax] - g.lo[ax]);
+      if (gap < rid) {
+        if (nf < kListCap) nb.nb[(int64_t)nf * n + s] = -1 - w;
+        nf++;
+      }
+    }
+  }
+  if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
+  nb.cnt[s] = nf < kListCap ? nf : kListCap;
+}
+
+// The lists become the compact contact array of `gen` (offsets from a scan of
+// the counts); each pair also counts towards its partner's backward list.
+__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PosBuf pos, PairGen gen, PairWork w, int32_t n,
+                                                  int32_t *err) {
+  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n) return;
+  const int32_t cnt = nb.cnt[s];
+  const int64_t base = gen.ofs[s];
+  if (base + cnt > w.Pcap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
+  for (int32_t k = 0; k < cnt; k++) {
+    const int32_t t = nb.nb[(int64_t)k * n + s];
+    const int64_t q = base + k;
+    if (q >= w.Pcap) break;
+    gen.s[q] = s;
+    gen.t[q] = t;
+    gen.key[q] = t >= 0 ? pos.id[t] : t;
+    if (t >= 0) w.brank[q] = atomicAdd(&w.bcnt[t], 1);
+  }
+}
+
+__device__ __forceinline__ int32_t num_pairs(const PairGen &gen, int32_t n, int64_t cap) {
+  const int32_t P = gen.ofs[n];
+  return (int64_t)P < cap ? P : (int32_t)cap;
+}
+
+// backward index: contact q is filed under its partner at the rank its
+// count drew (arrival order; the gather sorts each short segment)
+__global__ __launch_bounds__(kBlock) void k_bwd(PairGen gen, PairWork w, int32_t n) {
+  const int32_t P = num_pairs(gen, n, w.Pcap);
+  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
+    const int32_t t = gen.t[q];
+    if (t < 0) continue;
+    w.bwd[w.bofs[t] + w.brank[q]] = q;
+  }
 }
 
 // fixed-size bitonic network on registers (indices are compile-time)
@@ -442,10 +480,10 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
         const int l = i ^ j;
         if (l > i) {
           const bool up = (i & k) == 0;
-          const int32_t u = L[i], w = L[l];
-          const bool sw = up ? (u > w) : (u < w);
-          L[i] = sw ? w : u;
-          L[l] = sw ? u : w;
+          const int32_t u = L[i], v = L[l];
+          const bool sw = up ? (u > v) : (u < v);
+          L[i] = sw ? v : u;
+          L[l] = sw ? u : v;
         }
       }
     }
@@ -453,34 +491,34 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
 }
 
 template <int M>
-__device__ __forceinline__ void sort_small(int32_t *list, int64_t stride, int32_t cnt) {
+__device__ __forceinline__ void sort_small(int32_t *list, int32_t cnt) {
   int32_t L[M];
 #pragma unroll
-  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i * stride] : INT32_MAX;
+  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i] : INT32_MAX;
   bitonic_sort<M>(L);
 #pragma unroll
   for (int i = 0; i < M; i++)
-    if (i < cnt) list[i * stride] = L[i];
+    if (i < cnt) list[i] = L[i];
 }
 
-// ascending order of a particle's backward list (entries arrive by atomics)
-__device__ __forceinline__ void sort_list(int32_t *list, int64_t stride, int32_t cnt) {
+// ascending order of a short contiguous list (entries arrived by atomics)
+__device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
   if (cnt <= 1) return;
   if (cnt <= 4) {
-    sort_small<4>(list, stride, cnt);
+    sort_small<4>(list, cnt);
   } else if (cnt <= 8) {
-    sort_small<8>(list, stride, cnt);
+    sort_small<8>(list, cnt);
   } else if (cnt <= 16) {
-    sort_small<16>(list, stride, cnt);
+    sort_small<16>(list, cnt);
   } else {
     for (int32_t k = 1; k < cnt; k++) {
-      const int32_t v = list[k * stride];
+      const int32_t v = list[k];
       int32_t j = k - 1;
-      while (j >= 0 && list[j * stride] > v) {
-        list[(j + 1) * stride] = list[j * stride];
+      while (j >= 0 && list[j] > v) {
+        list[j + 1] = list[j];
         j--;
       }
-      list[(j + 1) * stride] = v;
+      list[j + 1] = v;
     }
   }
 }
@@ -571,180 +609,211 @@ __device__ __forceinline__ double elastic_energy(const Consts &c, Real delta, Re
   return 0.5 * (double)o.kn * d * d + 0.5 * (double)o.kt * hh;
 }
 
-// history lookup: the entry with partner `key` in row `row`, or zero
 template <typename Real>
-__device__ __forceinline__ void hist_find(const HistBuf &hb, int32_t K, int32_t N, int32_t row, int32_t key,
-                                          Real h[3]) {
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+  using type = float4;
+};
+template <>
+struct Vec4T<double> {
+  using type = double4;
+};
+
+// committed tangential displacement of the contact with history key `key`
+// in segment `owner` of the previous array (zero for a new contact)
+template <typename Real>
+__device__ __forceinline__ void hist_lookup(const PairGen &old, int64_t cap, int32_t owner, int32_t key,
+                                            Real h[3]) {
+  using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
-  const int32_t cnt = hb.cnt[row];
-  const Real *d = (const Real *)hb.d;
-  for (int32_t k = 0; k < cnt; k++) {
-    if (hb.partner[(int64_t)k * N + row] == key) {
-#pragma unroll
-      for (int q = 0; q < 3; q++) h[q] = d[((int64_t)q * K + k) * N + row];
+  int64_t q = old.ofs[owner];
+  const int64_t e = old.ofs[owner + 1] < cap ? old.ofs[owner + 1] : cap;
+  for (; q < e; q++) {
+    if (old.key[q] == key) {
+      const V4 d = ((const V4 *)old.dt)[q];
+      h[0] = d.x;
+      h[1] = d.y;
+      h[2] = d.z;
       break;
     }
   }
 }
 
+// One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
+// pair in the canonical orientation (lower particle id first), stored as the
+// force on the owner and n x F_t.
 template <typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_force(ForceArgs a) {
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= a.n) return;
-  const int32_t N = a.n;
+__global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
+  using V4 = typename Vec4T<Real>::type;
   const Consts &c = a.c;
+  const int32_t P = num_pairs(a.cur, a.n, a.w.Pcap);
   const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
   const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
-
-  const double xi = a.pos.x[s], yi = a.pos.y[s], zi = a.pos.z[s];
-  const float rif = a.pos.r[s];
-  const double rid = (double)rif;
-  const Real ri = (Real)rif;
-  const int32_t idi = a.pos.id[s];
-  const Real vi[3] = {VI[0][s], VI[1][s], VI[2][s]};
-  const Real wi[3] = {WI[0][s], WI[1][s], WI[2][s]};
-  const Real mi = mass_of<Real>(c, ri);
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
-  const bool write_hist =
-      (a.mode & MODE_WRITE_HIST) != 0 && (LAW != DEM_LAW_SIMPLE || (a.mode & MODE_LIST) != 0);
+  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
-  const int32_t row_i = old_perm ? a.perm[s] : s;
-
-  Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  int32_t nnew = 0;
-  bool overflow = false;
-  double e_el = 0.0, dmax = 0.0;
-  int32_t npair = 0, nwall = 0;
-  Real *hd = (Real *)a.hnew.d;
-
-  // contact partners in ascending slot: the backward list (lower slots,
-  // sorted here) then the forward list (higher slots, ascending)
-  const int32_t Kd = a.nbr.Kd;
-  const int32_t nbk = min(a.nbr.cnt_b[s], Kd), nfk = min(a.nbr.cnt_f[s], Kd);
-  sort_list(a.nbr.nb_b + s, N, nbk);
-  for (int32_t k = 0; k < nbk + nfk; k++) {
-    const int32_t t = k < nbk ? a.nbr.nb_b[(int64_t)k * N + s] : a.nbr.nb_f[(int64_t)(k - nbk) * N + s];
-    const double dx = a.pos.x[t] - xi, dy_ = a.pos.y[t] - yi, dz_ = a.pos.z[t] - zi;
-    const double d2 = dist2_exact(dx, dy_, dz_);
-    const double S = rid + (double)a.pos.r[t];
-    {
-        // a contact: evaluate it in the canonical orientation (lower id first)
-        // so that both particles compute bit-identical values
-        const int32_t idj = a.pos.id[t];
-        const bool low = idi < idj;
-        const Real rj = (Real)a.pos.r[t];
-        const Real vj[3] = {VI[0][t], VI[1][t], VI[2][t]};
-        const Real wj[3] = {WI[0][t], WI[1][t], WI[2][t]};
-        const Real mj = mass_of<Real>(c, rj);
-        const Real ra = low ? ri : rj, rb = low ? rj : ri;
-        const Real ma = low ? mi : mj, mb = low ? mj : mi;
-        const double ex = low ? dx : -dx, ey = low ? dy_ : -dy_, ez = low ? dz_ : -dz_;
-        const Real dd = sqrt((Real)d2);
-        const Real invd = (Real)1 / dd;
-        const Real n[3] = {(Real)ex * invd, (Real)ey * invd, (Real)ez * invd};
-        const Real delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
-        const Real R = ra * rb / (ra + rb);
-        const Real M = ma * mb / (ma + mb);
-        Real v[3], spin[3];
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-          const Real va = low ? vi[q] : vj[q], vb = low ? vj[q] : vi[q];
-          const Real wa = low ? wi[q] : wj[q], wb = low ? wj[q] : wi[q];
-          v[q] = va - vb;
-          spin[q] = ra * wa + rb * wb;
-        }
-        Real h[3] = {0, 0, 0};
-        if (LAW != DEM_LAW_SIMPLE) {
-          const int32_t hrow = low ? row_i : (old_perm ? a.perm[t] : t);
-          hist_find<Real>(a.hold, a.K, N, hrow, low ? idj : idi, h);
-        }
-        LawOut<Real> o;
-        contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
-        const Real sg = low ? (Real)1 : (Real)-1;
-        const Real nxft[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
-                              n[0] * o.Ft[1] - n[1] * o.Ft[0]};
-#pragma unroll
-        for (int q = 0; q < 3; q++) {
-          F[q] += sg * o.F[q];
-          T[q] += ri * nxft[q];  // Eq. 3; same sign on both bodies
-        }
-        if (low) {
-          if (write_hist) {
-            if (nnew < a.K) {
-              a.hnew.partner[(int64_t)nnew * N + s] = idj;
-#pragma unroll
-              for (int q = 0; q < 3; q++) hd[((int64_t)q * a.K + nnew) * N + s] = o.dtn[q];
-              nnew++;
-            } else {
-              overflow = true;
-            }
-          }
-          if (diag) {
-            e_el += elastic_energy<Real, LAW>(c, delta, R, o, h);
-            npair++;
-            dmax = fmax(dmax, (double)delta);
-          }
-        }
-    }
-  }
-
-  // Step 8: walls, particles of infinite radius
-  if (c.wall_mask) {
-    const double pos[3] = {xi, yi, zi};
-    for (int w = 0; w < 6; w++) {
-      if (!((c.wall_mask >> w) & 1)) continue;
-      const int ax = w >> 1;
-      const double gap = (w & 1) ? (a.grid.hi[ax] - pos[ax]) : (pos[ax] - a.grid.lo[ax]);
-      if (!(gap < rid)) continue;
-      Real n[3] = {0, 0, 0};
-      n[ax] = (w & 1) ? (Real)1 : (Real)-1;
-      const Real delta = (Real)(rid - gap);
-      Real spin[3];
-#pragma unroll
-      for (int k = 0; k < 3; k++) spin[k] = ri * wi[k];
-      Real h[3] = {0, 0, 0};
-      if (LAW != DEM_LAW_SIMPLE) hist_find<Real>(a.hold, a.K, N, row_i, -1 - w, h);
-      LawOut<Real> o;
-      contact_law<Real, LAW>(c, n, delta, ri, mi, vi, spin, h, o);
-      const Real nxft[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
-                            n[0] * o.Ft[1] - n[1] * o.Ft[0]};
+  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
+    const int32_t s = a.cur.s[q], t = a.cur.t[q];
+    const double xs = a.pos.x[s], ys = a.pos.y[s], zs = a.pos.z[s];
+    const float rsf = a.pos.r[s];
+    const Real rs = (Real)rsf;
+    const Real ms = mass_of<Real>(c, rs);
+    const Real vs[3] = {VI[0][s], VI[1][s], VI[2][s]};
+    const Real ws[3] = {WI[0][s], WI[1][s], WI[2][s]};
+    const int32_t ps = old_perm ? a.perm[s] : s;
+    LawOut<Real> o;
+    Real n[3], h[3] = {0, 0, 0}, Fown[3], delta, R;
+    if (t >= 0) {
+      const int32_t ids = a.pos.id[s], idt = a.pos.id[t];
+      const double dx = a.pos.x[t] - xs, dy = a.pos.y[t] - ys, dz = a.pos.z[t] - zs;
+      const double d2 = dist2_exact(dx, dy, dz);
+      const double S = (double)rsf + (double)a.pos.r[t];
+      const Real rt = (Real)a.pos.r[t];
+      const Real vt_[3] = {VI[0][t], VI[1][t], VI[2][t]};
+      const Real wt_[3] = {WI[0][t], WI[1][t], WI[2][t]};
+      const Real mt = mass_of<Real>(c, rt);
+      const bool low = ids < idt;  // s is the canonical first body
+      const Real ra = low ? rs : rt, rb = low ? rt : rs;
+      const Real ma = low ? ms : mt, mb = low ? mt : ms;
+      const double ex = low ? dx : -dx, ey = low ? dy : -dy, ez = low ? dz : -dz;
+      const Real dd = sqrt((Real)d2);
+      const Real invd = (Real)1 / dd;
+      n[0] = (Real)ex * invd;
+      n[1] = (Real)ey * invd;
+      n[2] = (Real)ez * invd;
+      delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
+      R = ra * rb / (ra + rb);
+      const Real M = ma * mb / (ma + mb);
+      Real v[3], spin[3];
 #pragma unroll
       for (int k = 0; k < 3; k++) {
-        F[k] += o.F[k];
-        T[k] += ri * nxft[k];
+        const Real va = low ? vs[k] : vt_[k], vb = low ? vt_[k] : vs[k];
+        const Real wa = low ? ws[k] : wt_[k], wb = low ? wt_[k] : ws[k];
+        v[k] = va - vb;
+        spin[k] = ra * wa + rb * wb;
       }
-      if (write_hist) {
-        if (nnew < a.K) {
-          a.hnew.partner[(int64_t)nnew * N + s] = -1 - w;
+      if (LAW != DEM_LAW_SIMPLE) {
+        // the previous step filed this pair under its lower slot then
+        const int32_t pt = old_perm ? a.perm[t] : t;
+        hist_lookup<Real>(a.old, a.w.Pcap, ps < pt ? ps : pt, ps < pt ? idt : ids, h);
+      }
+      contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
 #pragma unroll
-          for (int q = 0; q < 3; q++) hd[((int64_t)q * a.K + nnew) * N + s] = o.dtn[q];
-          nnew++;
-        } else {
-          overflow = true;
-        }
-      }
-      if (diag) {
-        e_el += elastic_energy<Real, LAW>(c, delta, ri, o, h);
-        nwall++;
-        dmax = fmax(dmax, (double)delta);
-      }
+      for (int k = 0; k < 3; k++) Fown[k] = low ? o.F[k] : -o.F[k];
+    } else {
+      // Step 8: wall -1 - t, a particle of infinite radius
+      const int w = -1 - t;
+      const int ax = w >> 1;
+      const double xw[3] = {xs, ys, zs};
+      const double gap = (w & 1) ? (a.grid.hi[ax] - xw[ax]) : (xw[ax] - a.grid.lo[ax]);
+      n[0] = n[1] = n[2] = 0;
+      n[ax] = (w & 1) ? (Real)1 : (Real)-1;
+      delta = (Real)((double)rsf - gap);
+      R = rs;
+      Real spin[3];
+#pragma unroll
+      for (int k = 0; k < 3; k++) spin[k] = rs * ws[k];
+      if (LAW != DEM_LAW_SIMPLE) hist_lookup<Real>(a.old, a.w.Pcap, ps, t, h);
+      contact_law<Real, LAW>(c, n, delta, rs, ms, vs, spin, h, o);
+#pragma unroll
+      for (int k = 0; k < 3; k++) Fown[k] = o.F[k];
+    }
+    V4 f, tq;
+    f.x = Fown[0];
+    f.y = Fown[1];
+    f.z = Fown[2];
+    f.w = 0;
+    tq.x = n[1] * o.Ft[2] - n[2] * o.Ft[1];
+    tq.y = n[2] * o.Ft[0] - n[0] * o.Ft[2];
+    tq.z = n[0] * o.Ft[1] - n[1] * o.Ft[0];
+    tq.w = 0;
+    ((V4 *)a.w.pf)[2 * (int64_t)q] = f;
+    ((V4 *)a.w.pf)[2 * (int64_t)q + 1] = tq;
+    if (write_hist) {
+      V4 d;
+      d.x = o.dtn[0];
+      d.y = o.dtn[1];
+      d.z = o.dtn[2];
+      d.w = 0;
+      ((V4 *)a.cur.dt)[q] = d;
+    }
+    if (diag) {
+      a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
+      a.w.pd[q] = (double)delta;
     }
   }
+}
 
+// One lane per particle: contact sums in a fixed order (contacts with lower
+// slots, ascending; with higher slots, ascending; walls), then the closing
+// half kick of Step 1.
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
+  using V4 = typename Vec4T<Real>::type;
+  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= a.n) return;
+  const Consts &c = a.c;
+  const int64_t cap = a.w.Pcap;
+  const Real rs = (Real)a.pos.r[s];
+  const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
+  Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  const int32_t b0 = a.w.bofs[s], b1 = a.w.bofs[s + 1];
+  const int32_t nb = (int64_t)b1 <= cap ? b1 - b0 : 0;
+  sort_list(a.w.bwd + b0, nb);
+  for (int32_t k = 0; k < nb; k++) {
+    const int32_t q = a.w.bwd[b0 + k];
+    const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
+    F[0] -= f.x;
+    F[1] -= f.y;
+    F[2] -= f.z;
+    T[0] += rs * m.x;  // Eq. 3; the same n x F_t on both bodies
+    T[1] += rs * m.y;
+    T[2] += rs * m.z;
+  }
+  const int64_t f0 = a.cur.ofs[s];
+  const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
+  double e_el = 0.0, dmax = 0.0;
+  int32_t npair = 0, nwall = 0;
+  const bool diag = (a.mode & MODE_DIAG) != 0;
+  for (int64_t q = f0; q < f1; q++) {
+    const V4 f = pf[2 * q], m = pf[2 * q + 1];
+    F[0] += f.x;
+    F[1] += f.y;
+    F[2] += f.z;
+    T[0] += rs * m.x;
+    T[1] += rs * m.y;
+    T[2] += rs * m.z;
+    if (diag) {
+      e_el += a.w.pe[q];
+      dmax = fmax(dmax, a.w.pd[q]);
+      if (a.cur.t[q] >= 0)
+        npair++;
+      else
+        nwall++;
+    }
+  }
   if (!(isfinite((double)F[0]) && isfinite((double)F[1]) && isfinite((double)F[2]) &&
         isfinite((double)T[0]) && isfinite((double)T[1]) && isfinite((double)T[2])))
     raise_err(a.err, ERR_NONFINITE);
-  if (overflow) raise_err(a.err, ERR_OVERFLOW);
-  if (write_hist) a.hnew.cnt[s] = nnew;
 #pragma unroll
   for (int k = 0; k < 3; k++) {
     ((Real *)a.F[k])[s] = F[k];
     ((Real *)a.T[k])[s] = T[k];
   }
   if (a.mode & MODE_KICK) {
-    Real v[3] = {vi[0], vi[1], vi[2]}, w[3] = {wi[0], wi[1], wi[2]};
-    const Real I = (Real)0.4 * mi * ri * ri;
-    half_kick<Real>(c, mi, I, F, T, v, w);
+    const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
+    const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
+    Real v[3] = {VI[0][s], VI[1][s], VI[2][s]}, w[3] = {WI[0][s], WI[1][s], WI[2][s]};
+    const Real m = mass_of<Real>(c, rs);
+    const Real I = (Real)0.4 * m * rs * rs;
+    half_kick<Real>(c, m, I, F, T, v, w);
+    if (a.mode & MODE_DRIFT) {
+      // the next step's Steps 1-2 with the same forces: the same operations
+      // as k_kick_drift_hash, so fusing changes no bit
+      half_kick<Real>(c, m, I, F, T, v, w);
+      drift_hash(a.pos, s, v, c, a.grid, a.cell, a.err);
+    }
 #pragma unroll
     for (int k = 0; k < 3; k++) {
       ((Real *)a.vel_out.v[k])[s] = v[k];
@@ -862,20 +931,6 @@ hipError_t launch_kick_drift_hash(int precision, const PosBuf &p, const VelBuf &
   return hipGetLastError();
 }
 
-hipError_t launch_kick(int precision, const PosBuf &p, const VelBuf &v, void *const F[3], void *const T[3],
-                       int32_t n, const Consts &c, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (precision == DEM_PREC_FP64)
-    k_kick<double><<<blocks_for(n), kBlock, 0, st>>>(p, v, (const double *)F[0], (const double *)F[1],
-                                                     (const double *)F[2], (const double *)T[0],
-                                                     (const double *)T[1], (const double *)T[2], n, c);
-  else
-    k_kick<float><<<blocks_for(n), kBlock, 0, st>>>(p, v, (const float *)F[0], (const float *)F[1],
-                                                    (const float *)F[2], (const float *)T[0],
-                                                    (const float *)T[1], (const float *)T[2], n, c);
-  return hipGetLastError();
-}
-
 hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           float4 *xyzr, const Grid &g, int32_t n, hipStream_t st) {
@@ -892,35 +947,56 @@ hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_detect(const PosBuf &p, const NbrBuf &nb, const int32_t *scell, const int32_t *cell_start,
-                         const Grid &g, int32_t n, int32_t *err, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  k_fill<<<blocks_for(n), kBlock, 0, st>>>(nb.cnt_b, n, 0);
-  k_detect<<<blocks_for(n), kBlock, 0, st>>>(p, nb, scell, cell_start, g, n, err);
+static hipError_t scan_with_total(const int32_t *in, int32_t *out, int64_t len, const ScanScratch &sc,
+                                  hipStream_t st) {
+  hipError_t e = scan_exclusive(in, out, len, sc, 0, st);
+  if (e != hipSuccess) return e;
+  k_scan_total<<<1, 64, 0, st>>>(in, out, len);
+  return hipGetLastError();
+}
+
+static unsigned pair_blocks() { return 2048; }  // grid-stride over the contacts (count known on device)
+
+hipError_t launch_contacts(const PosBuf &p, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                           const int32_t *scell, const int32_t *cell_start, const Grid &g, uint32_t wall_mask,
+                           int32_t n, const ScanScratch &sc, int32_t *err, hipStream_t st) {
+  if (n <= 0) {
+    k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
+    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
+    return hipGetLastError();
+  }
+  k_detect<<<blocks_for(n), kBlock, 0, st>>>(p, nb, scell, cell_start, g, wall_mask, n, err);
+  hipError_t e = scan_with_total(nb.cnt, gen.ofs, n, sc, st);
+  if (e != hipSuccess) return e;
+  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
+  k_pairs<<<blocks_for(n), kBlock, 0, st>>>(nb, p, gen, w, n, err);
+  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
+  k_bwd<<<pair_blocks(), kBlock, 0, st>>>(gen, w, n);
   return hipGetLastError();
 }
 
 template <typename Real>
-static void force_t(const ForceArgs &a, hipStream_t st) {
+static void forces_t(const PairArgs &a, hipStream_t st) {
   switch (a.c.law) {
     case DEM_LAW_HERTZ:
-      k_force<Real, DEM_LAW_HERTZ><<<blocks_for(a.n), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_HERTZ><<<pair_blocks(), kBlock, 0, st>>>(a);
       break;
     case DEM_LAW_SIMPLE:
-      k_force<Real, DEM_LAW_SIMPLE><<<blocks_for(a.n), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_SIMPLE><<<pair_blocks(), kBlock, 0, st>>>(a);
       break;
     default:
-      k_force<Real, DEM_LAW_LINEAR><<<blocks_for(a.n), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_LINEAR><<<pair_blocks(), kBlock, 0, st>>>(a);
       break;
   }
+  k_gather<Real><<<blocks_for(a.n), kBlock, 0, st>>>(a);
 }
 
-hipError_t launch_force(int precision, const ForceArgs &a, hipStream_t st) {
+hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    force_t<double>(a, st);
+    forces_t<double>(a, st);
   else
-    force_t<float>(a, st);
+    forces_t<float>(a, st);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ Parameter dictionary keys (each side marshals them into its own structure):
   eta_t_ratio        tangential damping as a fraction of the normal one
   mu                 Coulomb friction coefficient (Eq. 5)
   cell_size          requested cell width of the collision-detection grid
-  contacts_per_particle  history capacity per particle (GPU only)
+  contacts_per_particle  contact-list capacity per particle, on average (GPU only)
   precision          "fp64" or "mixed" (FP32 forces, FP64 positions; GPU only)
 """
 import math
@@ -218,7 +218,7 @@ def dense_bed_geometry(seed=3000, n=1 << 24, phi=0.55, median=1.0 / 512.0, sigma
 def dense_bed_params(r, hi, **kw):
     r_min = float(np.min(r))
     p = base_params(box_hi=hi, cell_size=2.0 * float(np.max(r)), precision="mixed",
-                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=32)
+                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=8)
     p.update(kw)
     return p
 

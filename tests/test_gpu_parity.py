@@ -248,11 +248,13 @@ def test_out_of_domain_is_reported(dem):
         g.step(1)
 
 
-def test_history_overflow_is_reported(dem):
+def test_contact_list_overflow_is_reported(dem):
     c = cloud(**CASES["fp64_linear_3001"])
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    assert len(o.contacts()) > len(c["r"])  # more than one contact per particle
     p = dict(c["params"], contacts_per_particle=1)
-    g = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
-    g.step(1)
     with pytest.raises(dem.DemError) as e:
+        g = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+        g.step(1)
         g.sync()
     assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
