@@ -172,6 +172,14 @@ dem_status dem_set_radii(dem_system *s, const double *r);
 dem_status dem_profile(dem_system *s, int enable);
 dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps);
 
+/* Capture one time step (Steps 2-8 and the closing kick) into two HIP
+ * graphs, one per buffer parity, and replay them in dem_step from then on.
+ * The stream given to dem_create must not be the NULL stream (graph capture
+ * needs a created stream).  Phase timing then covers whole steps (phase 4).
+ * Results are identical with and without graphs.  enable = 0 goes back to
+ * plain launches. */
+dem_status dem_use_graph(dem_system *s, int enable);
+
 /* Wait for the system's stream; report any sticky error. */
 dem_status dem_sync(dem_system *s);
 
@@ -180,6 +188,45 @@ dem_status dem_sync(dem_system *s);
 dem_status dem_destroy(dem_system *s);
 
 const char *dem_status_string(dem_status st);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent systems of uneven size stepped together.  All
+ * systems of a batch share one workspace, one stream and one set of kernel
+ * launches per step (each kernel serves every system; no system waits for
+ * another's launch), and must share the contact law and the precision; every
+ * other parameter (box, walls, gravity, dt, material, cell) is per system.
+ * A system's results do not depend on the other systems of its batch: they
+ * are bitwise those of the same system created alone with dem_create.
+ * Host arrays are the systems' arrays concatenated in system order; ids in
+ * contact keys are local to a system. */
+typedef struct dem_batch dem_batch;
+
+/* Device bytes for systems k = 0..n_sys-1 of n[k] particles, parameters p[k]. */
+dem_status dem_batch_workspace_bytes(int32_t n_sys, const dem_params *p, const int64_t *n, size_t *bytes);
+
+/* Create a batch (no initial history; forces evaluated on the given state).
+ * Synchronous.  Errors as dem_create, plus DEM_E_INVALID when the systems'
+ * laws or precisions differ. */
+dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n, const double *x,
+                            const double *v, const double *omega, const double *r, void *workspace,
+                            size_t ws_bytes, void *hip_stream, dem_batch **out);
+
+/* Advance system k by steps[k] >= 0 steps (0: it does not move).  The batch
+ * runs max(steps) steps; a system that has done its steps stays unchanged
+ * (state and history) while the others go on.  Asynchronous. */
+dem_status dem_batch_step(dem_batch *b, const int64_t *steps);
+
+dem_status dem_batch_read_state(dem_batch *b, int32_t k, double *x, double *v, double *omega, double *F,
+                                double *T);
+dem_status dem_batch_read_contacts(dem_batch *b, int32_t k, int64_t cap, int64_t *n_out, int64_t *pairs,
+                                   double *delta_t);
+/* Diagnostics of every system: out[10 * k + j] as dem_diagnostics. */
+dem_status dem_batch_diagnostics(dem_batch *b, double *out);
+dem_status dem_batch_use_graph(dem_batch *b, int enable);
+dem_status dem_batch_profile(dem_batch *b, int enable);
+dem_status dem_batch_profile_read(dem_batch *b, double ms[DEM_NUM_PHASES], int64_t *steps);
+dem_status dem_batch_sync(dem_batch *b);
+dem_status dem_batch_destroy(dem_batch *b);
 
 #ifdef __cplusplus
 }

@@ -1,9 +1,11 @@
 // dem_api.hip -- the C ABI of libdem.so (declared in include/dem.h).
 //
-// Host side of one system: parameter validation, carving of the caller's
-// workspace into the arrays of dem_internal.h, the per-step launch sequence
-// of Sec. 4.2 (Steps 1-8), and the synchronous read-back calls, which return
-// everything in the caller's original particle order.
+// Host side of an engine of S independent systems (one for dem_system, many
+// for dem_batch): parameter validation, carving of the caller's workspace
+// into the arrays of dem_internal.h, the per-step launch sequence of
+// Sec. 4.2 (Steps 1-8), optional replay of a step from HIP graphs, and the
+// synchronous read-back calls, which return everything in the caller's
+// original particle order.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -17,38 +19,68 @@
 
 using namespace dem;
 
-struct dem_system {
-  dem_params p;
-  int32_t n;
-  int prec;
-  size_t rsz;  // sizeof(Real)
-  Grid grid;
-  Consts c;
-  PosBuf pos[2];
-  VelBuf vel[2];
-  int cp, cv;  // current position / velocity buffers
-  int gc;      // generation holding the committed tangential history
-  int gs;      // generation holding the contact list of the current positions
-  void *F[3], *T[3], *Fe[3], *Te[3];
-  int32_t *cell, *rank, *perm, *scell, *counts, *cell_start;
-  ScanScratch scan;
-  NbrBuf nbr;
-  PairGen gen[2];
-  PairWork work;
-  DiagBuf diag;
-  int32_t *err;
-  hipStream_t stream;
-  dem_status sticky;
-  int64_t steps;
-  // phase timing (dem_profile)
-  bool profiling;
-  std::vector<hipEvent_t> *events;  // DEM_PROFILE_CAPACITY x (DEM_NUM_PHASES + 1)
-  int64_t timed;
-};
-
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+
+// contact-list offsets are int32: n * kListCap must stay below 2^31
+constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
+
+struct Engine {
+  int32_t S = 0;
+  int32_t n = 0;  // particles of all systems
+  int prec = 0;
+  int law = 0;
+  size_t rsz = 0;  // sizeof(Real)
+  std::vector<dem_params> params;
+  std::vector<SysInfo> info;  // host copy of the system table
+  std::vector<int32_t> bsys_h, bfirst_h;
+  int64_t ncell = 0;  // cells of all systems
+  int64_t Pcap = 0;
+  // device
+  SysInfo *tab = nullptr;
+  int32_t *psys = nullptr, *bsys = nullptr, *bfirst = nullptr;
+  StepCtl ctl{};
+  std::vector<int32_t> left_h;  // source of the ctl.left upload
+  hipEvent_t left_ev = nullptr;  // that upload has been read
+  bool left_pending = false;
+  PosBuf pos[2];
+  VelBuf vel[2];
+  int cp = 0, cv = 0;  // current position / velocity buffers
+  int gc = 0;          // generation holding the committed tangential history
+  int gs = 0;          // generation holding the contact list of the current positions
+  void *F[3], *T[3], *Fe[3], *Te[3];
+  int32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *scell = nullptr, *counts = nullptr,
+          *cell_start = nullptr;
+  ScanScratch scan{};
+  NbrBuf nbr{};
+  PairGen gen[2];
+  PairWork work{};
+  DiagBuf diag{};
+  int32_t *err = nullptr;
+  hipStream_t stream = nullptr;
+  dem_status sticky = DEM_OK;
+  // phase timing
+  bool profiling = false;
+  std::vector<hipEvent_t> events;  // DEM_PROFILE_CAPACITY x (DEM_NUM_PHASES + 1)
+  int64_t timed = 0;
+  // graph replay of Steps 3-8, one graph per position-buffer parity
+  bool use_graph = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gexec_gc[2] = {-1, -1};  // the history generation each graph was captured with
+
+  Layout layout() const {
+    Layout L;
+    L.tab = tab;
+    L.psys = psys;
+    L.bsys = bsys;
+    L.bfirst = bfirst;
+    L.nblocks = (int32_t)bsys_h.size();
+    L.n = n;
+    L.S = S;
+    return L;
+  }
+};
 
 struct Carver {
   char *base;
@@ -64,8 +96,7 @@ struct Carver {
 };
 
 dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
-  // contact-list offsets are int32: n * kListCap must stay below 2^31
-  if (!p || n < 0 || n > (int64_t)(INT32_MAX / kListCap)) return DEM_E_INVALID;
+  if (!p || n < 0 || n > kMaxParticles) return DEM_E_INVALID;
   if (!(p->dt > 0.0) || !isfinite(p->dt) || !(p->density > 0.0) || !(p->cell_size > 0.0)) return DEM_E_INVALID;
   if (p->law < DEM_LAW_LINEAR || p->law > DEM_LAW_SIMPLE) return DEM_E_INVALID;
   if (!(p->restitution > 0.0 && p->restitution <= 1.0) || !(p->mu >= 0.0)) return DEM_E_INVALID;
@@ -73,7 +104,6 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   if (p->contacts_per_particle < 1 || p->contacts_per_particle > kListCap) return DEM_E_INVALID;
   if (p->wall_mask > 0x3F) return DEM_E_INVALID;
   if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
-  if ((int64_t)p->contacts_per_particle * n >= (int64_t)INT32_MAX) return DEM_E_INVALID;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
     const double L = p->box_hi[a] - p->box_lo[a];
@@ -87,7 +117,7 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
     ncell *= g->nc[a];
   }
   if (ncell >= (int64_t)INT32_MAX - 1) return DEM_E_INVALID;
-  g->ncell = ncell;
+  g->ncell = (int32_t)ncell;
   return DEM_OK;
 }
 
@@ -108,76 +138,7 @@ float prefilter_eps(const Grid &g, double cell) {
   return (float)(4.0 * ulp + 1.0e-6 * cell);
 }
 
-// Lay the arrays out in the workspace; with base == nullptr only sizes.
-size_t carve(dem_system *s, char *base) {
-  Carver cv{base};
-  const size_t N = (size_t)(s->n > 0 ? s->n : 1);
-  const size_t R = s->rsz;
-  const size_t P = (size_t)s->work.Pcap;
-  for (int b = 0; b < 2; b++) {
-    s->pos[b].x = cv.take<double>(N);
-    s->pos[b].y = cv.take<double>(N);
-    s->pos[b].z = cv.take<double>(N);
-    s->pos[b].r = cv.take<float>(N);
-    s->pos[b].id = cv.take<int32_t>(N);
-    for (int k = 0; k < 3; k++) s->vel[b].v[k] = cv.take_bytes(R * N);
-    for (int k = 0; k < 3; k++) s->vel[b].w[k] = cv.take_bytes(R * N);
-  }
-  for (int k = 0; k < 3; k++) s->F[k] = cv.take_bytes(R * N);
-  for (int k = 0; k < 3; k++) s->T[k] = cv.take_bytes(R * N);
-  for (int k = 0; k < 3; k++) s->Fe[k] = cv.take_bytes(R * N);
-  for (int k = 0; k < 3; k++) s->Te[k] = cv.take_bytes(R * N);
-  s->cell = cv.take<int32_t>(N);
-  s->rank = cv.take<int32_t>(N);
-  s->perm = cv.take<int32_t>(N);
-  s->scell = cv.take<int32_t>(N);
-  s->counts = cv.take<int32_t>((size_t)s->grid.ncell);
-  s->cell_start = cv.take<int32_t>((size_t)s->grid.ncell + 1);
-  int64_t lens[4] = {0, 0, 0, 0};
-  int nl = 0;
-  scan_scratch_len(std::max<int64_t>(s->grid.ncell, (int64_t)N), lens, &nl);
-  s->scan.nlevels = nl;
-  for (int l = 0; l < 4; l++) {
-    s->scan.len[l] = lens[l];
-    s->scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
-  }
-  s->nbr.xyzr = cv.take<float4>(N);
-  s->nbr.cnt = cv.take<int32_t>(N);
-  s->nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
-  for (int b = 0; b < 2; b++) {
-    s->gen[b].ofs = cv.take<int32_t>(N + 1);
-    s->gen[b].s = cv.take<int32_t>(P);
-    s->gen[b].t = cv.take<int32_t>(P);
-    s->gen[b].key = cv.take<int32_t>(P);
-    s->gen[b].dt = cv.take_bytes(4 * R * P);
-  }
-  s->work.pf = cv.take_bytes(8 * R * P);
-  s->work.brank = cv.take<int32_t>(P);
-  s->work.pe = cv.take<double>(P);
-  s->work.pd = cv.take<double>(P);
-  s->work.bcnt = cv.take<int32_t>(N);
-  s->work.bofs = cv.take<int32_t>(N + 1);
-  s->work.bwd = cv.take<int32_t>(P);
-  s->diag.e_el = cv.take<double>(N);
-  s->diag.npair = cv.take<int32_t>(N);
-  s->diag.nwall = cv.take<int32_t>(N);
-  s->diag.dmax = cv.take<double>(N);
-  s->diag.partial = cv.take<double>((size_t)diag_blocks(s->n) * 10);
-  s->diag.out = cv.take<double>(10);
-  s->err = cv.take<int32_t>(64);
-  return (cv.off + 255) & ~size_t(255);
-}
-
-void init_sizes(dem_system *s, const dem_params *p, int64_t n) {
-  s->n = (int32_t)n;
-  s->prec = p->precision;
-  s->rsz = p->precision == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
-  s->work.Pcap = std::max<int64_t>((int64_t)p->contacts_per_particle * n, 256);
-}
-
-void fill_consts(dem_system *s) {
-  const dem_params &p = s->p;
-  Consts &c = s->c;
+void fill_consts(const dem_params &p, Consts &c) {
   c.dt = p.dt;
   c.half_dt = 0.5 * p.dt;
   c.mass_c = p.density * (4.0 / 3.0) * kPi;
@@ -195,6 +156,117 @@ void fill_consts(dem_system *s) {
   c.law = p.law;
 }
 
+// Validate the systems and lay out slot, cell and block ranges (no device
+// memory yet).  All systems share one precision and one contact law.
+dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
+  if (S < 1 || !p || !n) return DEM_E_INVALID;
+  e.S = S;
+  e.params.assign(p, p + S);
+  e.info.assign(S, SysInfo{});
+  e.prec = p[0].precision;
+  e.law = p[0].law;
+  int64_t ntot = 0, ctot = 0, pcap = 0;
+  e.bsys_h.clear();
+  e.bfirst_h.clear();
+  for (int32_t k = 0; k < S; k++) {
+    SysInfo &si = e.info[k];
+    memset(&si, 0, sizeof(si));
+    dem_status st = check_params(&p[k], n[k], &si.g);
+    if (st != DEM_OK) return st;
+    if (p[k].precision != e.prec || p[k].law != e.law) return DEM_E_INVALID;
+    fill_consts(p[k], si.c);
+    si.eps = prefilter_eps(si.g, p[k].cell_size);
+    si.p0 = (int32_t)ntot;
+    si.n = (int32_t)n[k];
+    si.g.c0 = (int32_t)ctot;
+    // per-particle kernels: blocks of kBlock slots that never straddle systems
+    for (int64_t b = 0; b < n[k]; b += kBlock) {
+      e.bsys_h.push_back(k);
+      e.bfirst_h.push_back((int32_t)(ntot + b));
+    }
+    ntot += n[k];
+    ctot += si.g.ncell;
+    pcap += (int64_t)p[k].contacts_per_particle * n[k];
+    if (ntot > kMaxParticles || ctot >= (int64_t)INT32_MAX - 1 || pcap >= (int64_t)INT32_MAX)
+      return DEM_E_INVALID;
+  }
+  e.n = (int32_t)ntot;
+  e.ncell = ctot;
+  e.Pcap = std::max<int64_t>(pcap, 256);
+  e.rsz = e.prec == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  e.left_h.assign(S, 0);
+  return DEM_OK;
+}
+
+// Lay the arrays out in the workspace; with base == nullptr only sizes.
+size_t carve(Engine &e, char *base) {
+  Carver cv{base};
+  const size_t N = (size_t)(e.n > 0 ? e.n : 1);
+  const size_t R = e.rsz;
+  const size_t P = (size_t)e.Pcap;
+  const size_t S = (size_t)e.S;
+  const size_t B = std::max<size_t>(e.bsys_h.size(), 1);
+  e.tab = cv.take<SysInfo>(S);
+  e.psys = cv.take<int32_t>(N);
+  e.bsys = cv.take<int32_t>(B);
+  e.bfirst = cv.take<int32_t>(B);
+  e.ctl.step = cv.take<int32_t>(64);
+  e.ctl.left = cv.take<int32_t>(S);
+  for (int b = 0; b < 2; b++) {
+    e.pos[b].x = cv.take<double>(N);
+    e.pos[b].y = cv.take<double>(N);
+    e.pos[b].z = cv.take<double>(N);
+    e.pos[b].r = cv.take<float>(N);
+    e.pos[b].id = cv.take<int32_t>(N);
+    for (int k = 0; k < 3; k++) e.vel[b].v[k] = cv.take_bytes(R * N);
+    for (int k = 0; k < 3; k++) e.vel[b].w[k] = cv.take_bytes(R * N);
+  }
+  for (int k = 0; k < 3; k++) e.F[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) e.T[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) e.Fe[k] = cv.take_bytes(R * N);
+  for (int k = 0; k < 3; k++) e.Te[k] = cv.take_bytes(R * N);
+  e.cell = cv.take<int32_t>(N);
+  e.rank = cv.take<int32_t>(N);
+  e.perm = cv.take<int32_t>(N);
+  e.scell = cv.take<int32_t>(N);
+  e.counts = cv.take<int32_t>((size_t)e.ncell);
+  e.cell_start = cv.take<int32_t>((size_t)e.ncell + 1);
+  int64_t lens[4] = {0, 0, 0, 0};
+  int nl = 0;
+  scan_scratch_len(std::max<int64_t>(e.ncell, (int64_t)N), lens, &nl);
+  e.scan.nlevels = nl;
+  for (int l = 0; l < 4; l++) {
+    e.scan.len[l] = lens[l];
+    e.scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
+  }
+  e.nbr.xyzr = cv.take<float4>(N);
+  e.nbr.cnt = cv.take<int32_t>(N);
+  e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
+  for (int b = 0; b < 2; b++) {
+    e.gen[b].ofs = cv.take<int32_t>(N + 1);
+    e.gen[b].s = cv.take<int32_t>(P);
+    e.gen[b].t = cv.take<int32_t>(P);
+    e.gen[b].key = cv.take<int32_t>(P);
+    e.gen[b].dt = cv.take_bytes(4 * R * P);
+  }
+  e.work.Pcap = e.Pcap;
+  e.work.pf = cv.take_bytes(8 * R * P);
+  e.work.brank = cv.take<int32_t>(P);
+  e.work.pe = cv.take<double>(P);
+  e.work.pd = cv.take<double>(P);
+  e.work.bcnt = cv.take<int32_t>(N);
+  e.work.bofs = cv.take<int32_t>(N + 1);
+  e.work.bwd = cv.take<int32_t>(P);
+  e.diag.e_el = cv.take<double>(N);
+  e.diag.npair = cv.take<int32_t>(N);
+  e.diag.nwall = cv.take<int32_t>(N);
+  e.diag.dmax = cv.take<double>(N);
+  e.diag.partial = cv.take<double>(B * 10);
+  e.diag.out = cv.take<double>(S * 10);
+  e.err = cv.take<int32_t>(64);
+  return (cv.off + 255) & ~size_t(255);
+}
+
 dem_status map_err(int32_t bits) {
   if (bits & ERR_DOMAIN) return DEM_E_OUT_OF_DOMAIN;
   if (bits & ERR_NONFINITE) return DEM_E_NONFINITE;
@@ -210,106 +282,105 @@ dem_status map_err(int32_t bits) {
     }                           \
   } while (0)
 
-dem_status sync_and_check(dem_system *s) {
-  if (s->sticky != DEM_OK) {
-    (void)hipStreamSynchronize(s->stream);
-    return s->sticky;
+// Wait for the stream and fold the device error flags into the sticky status.
+dem_status sync_and_check(Engine &e) {
+  if (e.sticky != DEM_OK) {
+    (void)hipStreamSynchronize(e.stream);
+    return e.sticky;
   }
   int32_t bits = 0;
-  if (hipMemcpyAsync(&bits, s->err, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-      hipStreamSynchronize(s->stream) != hipSuccess) {
+  if (hipMemcpyAsync(&bits, e.err, sizeof(int32_t), hipMemcpyDeviceToHost, e.stream) != hipSuccess ||
+      hipStreamSynchronize(e.stream) != hipSuccess) {
     (void)hipGetLastError();
-    s->sticky = DEM_E_HIP;
-    return s->sticky;
+    e.sticky = DEM_E_HIP;
+    return e.sticky;
   }
-  s->sticky = map_err(bits);
-  return s->sticky;
+  e.sticky = map_err(bits);
+  return e.sticky;
 }
 
-// Steps 5-6 on the current positions, into generation `g`
-hipError_t build_contacts(dem_system *s, int g) {
-  s->gs = g;
-  return launch_contacts(s->pos[s->cp], s->nbr, s->gen[g], s->work, s->scell, s->cell_start, s->grid,
-                         s->c.wall_mask, s->n, s->scan, s->err, s->stream);
-}
-
-// Steps 7-8 on the contact list of generation gs, with the committed history
-// of generation gc
-PairArgs pair_args(dem_system *s, int mode, void *const F[3], void *const T[3]) {
-  PairArgs a;
-  memset(&a, 0, sizeof(a));
-  a.pos = s->pos[s->cp];
-  a.vel_in = s->vel[s->cv];
-  a.vel_out = s->vel[s->cv ^ 1];
-  a.cur = s->gen[s->gs];
-  a.old = s->gen[s->gc];
-  a.w = s->work;
-  a.perm = s->perm;
-  a.cell = s->cell;
-  for (int k = 0; k < 3; k++) {
-    a.F[k] = F[k];
-    a.T[k] = T[k];
-  }
-  a.diag = s->diag;
-  a.n = s->n;
-  a.mode = mode;
-  a.grid = s->grid;
-  a.c = s->c;
-  a.err = s->err;
-  return a;
-}
-
-// device -> host copy of a Real array as doubles
-dem_status d2h_real(dem_system *s, const void *src, std::vector<double> &out, size_t count) {
+template <typename T>
+dem_status d2h(Engine &e, const T *src, std::vector<T> &out, size_t count) {
   out.resize(count);
   if (count == 0) return DEM_OK;
-  if (s->prec == DEM_PREC_FP64) {
-    HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(double) * count, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+  HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  return DEM_OK;
+}
+
+// `count` Reals from element `first` of a device array, as doubles
+dem_status d2h_real(Engine &e, const void *src, size_t first, size_t count, std::vector<double> &out) {
+  out.resize(count);
+  if (count == 0) return DEM_OK;
+  if (e.prec == DEM_PREC_FP64) {
+    HIP_TRY(hipMemcpyAsync(out.data(), (const double *)src + first, sizeof(double) * count,
+                           hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
   } else {
     std::vector<float> tmp(count);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpyAsync(tmp.data(), (const float *)src + first, sizeof(float) * count, hipMemcpyDeviceToHost,
+                           e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
     for (size_t i = 0; i < count; i++) out[i] = (double)tmp[i];
   }
   return DEM_OK;
 }
 
 template <typename T>
-dem_status d2h(dem_system *s, const T *src, std::vector<T> &out, size_t count) {
-  out.resize(count);
-  if (count == 0) return DEM_OK;
-  HIP_TRY(hipMemcpyAsync(out.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  return DEM_OK;
-}
-
-dem_status h2d_real(dem_system *s, void *dst, const std::vector<double> &src) {
+dem_status h2d(Engine &e, T *dst, const std::vector<T> &src) {
   if (src.empty()) return DEM_OK;
-  if (s->prec == DEM_PREC_FP64) {
-    HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-  } else {
-    std::vector<float> tmp(src.size());
-    for (size_t i = 0; i < src.size(); i++) tmp[i] = (float)src[i];
-    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), sizeof(float) * tmp.size(), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-  }
+  HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
   return DEM_OK;
 }
 
-template <typename T>
-dem_status h2d(dem_system *s, T *dst, const std::vector<T> &src) {
+dem_status h2d_real(Engine &e, void *dst, const std::vector<double> &src) {
   if (src.empty()) return DEM_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  return DEM_OK;
+  if (e.prec == DEM_PREC_FP64) return h2d(e, (double *)dst, src);
+  std::vector<float> tmp(src.size());
+  for (size_t i = 0; i < src.size(); i++) tmp[i] = (float)src[i];
+  return h2d(e, (float *)dst, tmp);
 }
 
-// per-particle vector (n x 3, original order) -> one component in slot order
+// component k of an n x 3 array in original order, arranged by slot
 void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, std::vector<double> &out) {
   out.resize(id_at_slot.size());
   for (size_t s = 0; s < id_at_slot.size(); s++) out[s] = src[3 * (size_t)id_at_slot[s] + k];
+}
+
+// Steps 5-6 on the current positions into generation g (with ctl only the
+// systems still stepping detect again; the others keep their lists)
+hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl) {
+  e.gs = g;
+  return launch_contacts(e.layout(), ctl, e.pos[e.cp], e.nbr, e.gen[g], e.work, e.scell, e.cell_start, e.scan,
+                         e.err, e.stream);
+}
+
+// Steps 7-8 on the contact list of generation gs, with the committed history
+// of generation gc
+PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
+  PairArgs a;
+  memset(&a, 0, sizeof(a));
+  a.L = e.layout();
+  a.ctl = e.ctl;
+  a.pos = e.pos[e.cp];
+  a.vel_in = e.vel[e.cv];
+  a.vel_out = e.vel[e.cv ^ 1];
+  a.cur = e.gen[e.gs];
+  a.old = e.gen[e.gc];
+  a.w = e.work;
+  a.perm = e.perm;
+  for (int k = 0; k < 3; k++) {
+    a.F[k] = F[k];
+    a.T[k] = T[k];
+  }
+  a.diag = e.diag;
+  a.cell = e.cell;
+  a.scell = e.scell;
+  a.mode = mode;
+  a.law = e.law;
+  a.err = e.err;
+  return a;
 }
 
 struct Entry {
@@ -317,51 +388,516 @@ struct Entry {
   double d[3];
 };
 
-// The contacts of a generation as sorted (a, b) keys: (lower id, higher id)
-// for pairs, (id, -1 - w) for walls; with_d also reads delta_t.
-dem_status read_gen(dem_system *s, const PairGen &g, bool with_d, std::vector<Entry> &out) {
+// The contacts of system k in a generation as sorted (a, b) keys with ids
+// local to the system: (lower id, higher id) for a pair, (id, -1 - w) for a
+// wall; with_d also reads delta_t, turned to the view of the lower id.
+dem_status read_gen(Engine &e, const PairGen &g, int32_t k, bool with_d, std::vector<Entry> &out) {
   out.clear();
-  if (s->n == 0) return DEM_OK;
-  const size_t N = (size_t)s->n;
+  const SysInfo &si = e.info[k];
+  if (si.n == 0) return DEM_OK;
+  const size_t N = (size_t)e.n;
   std::vector<int32_t> ofs, key, id;
   dem_status st;
-  if ((st = d2h(s, (const int32_t *)g.ofs, ofs, N + 1)) != DEM_OK) return st;
-  const size_t P = (size_t)std::min<int64_t>(ofs[N], s->work.Pcap);
-  if ((st = d2h(s, (const int32_t *)g.key, key, P)) != DEM_OK) return st;
-  if ((st = d2h(s, (const int32_t *)s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if ((st = d2h(e, (const int32_t *)g.ofs, ofs, N + 1)) != DEM_OK) return st;
+  const size_t P = (size_t)std::min<int64_t>(ofs[N], e.Pcap);
+  // a system's contacts are owned by its own slots: one contiguous range
+  const size_t q0 = std::min<size_t>((size_t)ofs[si.p0], P);
+  const size_t q1 = std::min<size_t>((size_t)ofs[si.p0 + si.n], P);
+  if ((st = d2h(e, (const int32_t *)g.key, key, P)) != DEM_OK) return st;
+  if ((st = d2h(e, (const int32_t *)e.pos[e.cp].id, id, N)) != DEM_OK) return st;
   std::vector<double> d;
-  if (with_d && (st = d2h_real(s, g.dt, d, 4 * P)) != DEM_OK) return st;
-  out.reserve(P);
-  for (size_t slot = 0; slot < N; slot++) {
-    for (size_t q = (size_t)ofs[slot]; q < std::min<size_t>((size_t)ofs[slot + 1], P); q++) {
-      Entry e;
-      const int64_t me = id[slot], other = key[q];
-      e.a = other >= 0 ? std::min(me, other) : me;
-      e.b = other >= 0 ? std::max(me, other) : other;
-      for (int c = 0; c < 3; c++) e.d[c] = with_d ? d[4 * q + c] : 0.0;
-      out.push_back(e);
+  if (with_d && (st = d2h_real(e, g.dt, 4 * q0, 4 * (q1 - q0), d)) != DEM_OK) return st;
+  out.reserve(q1 - q0);
+  for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++) {
+    const size_t e0 = std::min<size_t>((size_t)ofs[slot], P), e1 = std::min<size_t>((size_t)ofs[slot + 1], P);
+    for (size_t q = e0; q < e1; q++) {
+      Entry en;
+      const int64_t me = id[slot] - si.p0;
+      const int32_t other = key[q];
+      const bool pair = other >= 0;
+      const int64_t them = pair ? id[other] - si.p0 : other;
+      en.a = pair ? std::min(me, them) : me;
+      en.b = pair ? std::max(me, them) : them;
+      const double sg = (pair && me > them) ? -1.0 : 1.0;  // stored as seen from the owner slot
+      for (int c = 0; c < 3; c++) en.d[c] = with_d ? sg * d[4 * (q - q0) + c] : 0.0;
+      out.push_back(en);
     }
   }
-  std::sort(out.begin(), out.end(), [](const Entry &x, const Entry &y) {
-    return x.a != y.a ? x.a < y.a : x.b < y.b;
-  });
+  std::sort(out.begin(), out.end(),
+            [](const Entry &x, const Entry &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; });
   return DEM_OK;
 }
 
-dem_status fill_i32(dem_system *s, int32_t *p, size_t count, int32_t value) {
-  if (count == 0) return DEM_OK;
-  std::vector<int32_t> tmp(count, value);
-  return h2d(s, p, tmp);
+void free_graphs(Engine &e) {
+  for (int p = 0; p < 2; p++) {
+    if (e.gexec[p]) (void)hipGraphExecDestroy(e.gexec[p]);
+    e.gexec[p] = nullptr;
+    e.gexec_gc[p] = -1;
+  }
 }
 
-static void free_events(dem_system *s) {
-  if (!s->events) return;
-  for (hipEvent_t e : *s->events) (void)hipEventDestroy(e);
-  delete s->events;
-  s->events = nullptr;
+void free_events(Engine &e) {
+  for (hipEvent_t ev : e.events) (void)hipEventDestroy(ev);
+  e.events.clear();
+}
+
+void release(Engine *e) {
+  if (!e) return;
+  (void)hipStreamSynchronize(e->stream);
+  free_graphs(*e);
+  free_events(*e);
+  if (e->left_ev) (void)hipEventDestroy(e->left_ev);
+  delete e;
+}
+
+// ----------------------------------------------------------------- create
+
+struct HistIn {
+  int64_t n = 0;
+  const int64_t *pairs = nullptr;
+  const double *dt = nullptr;
+};
+
+dem_status validate_inputs(const Engine &e, const double *x, const double *v, const double *omega,
+                           const double *r, const double *F0, const double *T0, const HistIn &hist,
+                           std::vector<float> &rf) {
+  const size_t N = (size_t)e.n;
+  if (N > 0 && (!x || !v || !omega || !r)) return DEM_E_INVALID;
+  // radii in FP32; the cell must hold the largest contact distance (27-cell search)
+  rf.assign(N, 0.0f);
+  for (int32_t k = 0; k < e.S; k++) {
+    double rmax = 0.0;
+    const SysInfo &si = e.info[k];
+    for (int64_t i = si.p0; i < (int64_t)si.p0 + si.n; i++) {
+      const float q = (float)r[i];
+      if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
+      rf[i] = q;
+      rmax = std::max(rmax, (double)q);
+    }
+    if (e.params[k].cell_size < 2.0 * rmax) return DEM_E_INVALID;
+  }
+  for (size_t i = 0; i < 3 * N; i++)
+    if (!isfinite(x[i]) || !isfinite(v[i]) || !isfinite(omega[i])) return DEM_E_NONFINITE;
+  if (F0)
+    for (size_t i = 0; i < 3 * N; i++)
+      if (!isfinite(F0[i]) || !isfinite(T0[i])) return DEM_E_NONFINITE;
+  if (e.law != DEM_LAW_SIMPLE) {
+    for (int64_t k = 0; k < hist.n; k++) {
+      const int64_t a = hist.pairs[2 * k], b = hist.pairs[2 * k + 1];
+      const bool ok = a >= 0 && a < (int64_t)N && ((b > a && b < (int64_t)N) || (b < 0 && b >= -6));
+      if (!ok) return DEM_E_INVALID;
+      for (int q = 0; q < 3; q++)
+        if (!isfinite(hist.dt[3 * k + q])) return DEM_E_NONFINITE;
+    }
+  }
+  return DEM_OK;
+}
+
+// The given history becomes generation 0: each contact filed under the lower
+// slot of its pair (the particle for a wall) with delta_t seen from it.
+dem_status upload_history(Engine &e, const HistIn &hist, const std::vector<int32_t> &id_at_slot) {
+  const size_t N = (size_t)e.n;
+  struct Rec {
+    int32_t owner, key;
+    double d[3];
+  };
+  std::vector<Rec> recs;
+  if (e.law != DEM_LAW_SIMPLE && hist.n > 0) {
+    std::vector<int32_t> slot_of(N);
+    for (size_t sl = 0; sl < N; sl++) slot_of[id_at_slot[sl]] = (int32_t)sl;
+    recs.reserve((size_t)hist.n);
+    for (int64_t k = 0; k < hist.n; k++) {
+      const int64_t a = hist.pairs[2 * k], b = hist.pairs[2 * k + 1];
+      Rec rc;
+      double sg = 1.0;
+      if (b >= 0) {
+        const int32_t sa = slot_of[a], sb = slot_of[b];
+        rc.owner = std::min(sa, sb);
+        rc.key = std::max(sa, sb);
+        sg = sa < sb ? 1.0 : -1.0;  // given as seen from the lower id a
+      } else {
+        rc.owner = slot_of[a];
+        rc.key = (int32_t)b;
+      }
+      for (int c = 0; c < 3; c++) rc.d[c] = sg * hist.dt[3 * k + c];
+      recs.push_back(rc);
+    }
+    std::stable_sort(recs.begin(), recs.end(), [](const Rec &u, const Rec &w) {
+      return u.owner != w.owner ? u.owner < w.owner : u.key < w.key;
+    });
+    for (size_t k = 1; k < recs.size(); k++)
+      if (recs[k].owner == recs[k - 1].owner && recs[k].key == recs[k - 1].key) return DEM_E_INVALID;
+  }
+  if ((int64_t)recs.size() > e.Pcap) return DEM_E_CONTACT_OVERFLOW;
+  std::vector<int32_t> ofs(N + 1, 0), key(recs.size());
+  std::vector<double> d(4 * recs.size(), 0.0);
+  for (const Rec &rc : recs) ofs[rc.owner + 1]++;
+  for (size_t k = 0; k < N; k++) ofs[k + 1] += ofs[k];
+  for (size_t k = 0; k < recs.size(); k++) {
+    key[k] = recs[k].key;
+    for (int c = 0; c < 3; c++) d[4 * k + c] = recs[k].d[c];
+  }
+  const PairGen &g0 = e.gen[0];
+  dem_status st;
+  if ((st = h2d(e, g0.ofs, ofs)) != DEM_OK) return st;
+  if ((st = h2d(e, g0.key, key)) != DEM_OK) return st;
+  return h2d_real(e, g0.dt, d);
+}
+
+dem_status engine_init(Engine &e, const double *x, const double *v, const double *omega,
+                       const std::vector<float> &rf, const double *F0, const double *T0, const HistIn &hist) {
+  const size_t N = (size_t)e.n;
+  dem_status st;
+  HIP_TRY(hipEventCreateWithFlags(&e.left_ev, hipEventDisableTiming));
+  // tables
+  std::vector<int32_t> zeros(64, 0);
+  std::vector<int32_t> psys(N);
+  for (int32_t k = 0; k < e.S; k++)
+    for (int32_t i = 0; i < e.info[k].n; i++) psys[(size_t)e.info[k].p0 + i] = k;
+  HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo) * e.info.size(), hipMemcpyHostToDevice, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  if ((st = h2d(e, e.psys, psys)) != DEM_OK || (st = h2d(e, e.bsys, e.bsys_h)) != DEM_OK ||
+      (st = h2d(e, e.bfirst, e.bfirst_h)) != DEM_OK || (st = h2d(e, e.err, zeros)) != DEM_OK ||
+      (st = h2d(e, e.ctl.step, zeros)) != DEM_OK)
+    return st;
+  // state in original order into buffer 0
+  std::vector<int32_t> ids(N);
+  std::iota(ids.begin(), ids.end(), 0);
+  std::vector<double> tmp;
+  double *dst[3] = {e.pos[0].x, e.pos[0].y, e.pos[0].z};
+  for (int k = 0; k < 3; k++) {
+    gather3(x, ids, k, tmp);
+    if ((st = h2d(e, dst[k], tmp)) != DEM_OK) return st;
+    gather3(v, ids, k, tmp);
+    if ((st = h2d_real(e, e.vel[0].v[k], tmp)) != DEM_OK) return st;
+    gather3(omega, ids, k, tmp);
+    if ((st = h2d_real(e, e.vel[0].w[k], tmp)) != DEM_OK) return st;
+  }
+  if ((st = h2d(e, e.pos[0].r, rf)) != DEM_OK || (st = h2d(e, e.pos[0].id, ids)) != DEM_OK) return st;
+  const Layout L = e.layout();
+  // Steps 2-4 on the initial positions
+  HIP_TRY(launch_hash(L, e.pos[0], e.cell, e.err, e.stream));
+  HIP_TRY(launch_sort(e.cell, e.pos[0].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
+                      e.stream));
+  HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], e.perm, e.cell, e.scell, e.nbr.xyzr,
+                         e.stream));
+  e.cp = 1;
+  e.cv = 1;
+  e.gc = 0;
+  // Steps 5-6: the contacts of the initial positions go to generation 1
+  HIP_TRY(build_contacts(e, 1, nullptr));
+  if ((st = sync_and_check(e)) != DEM_OK) return st;
+  std::vector<int32_t> id_at_slot;
+  if ((st = d2h(e, e.pos[1].id, id_at_slot, N)) != DEM_OK) return st;
+  if ((st = upload_history(e, hist, id_at_slot)) != DEM_OK) return st;
+  // forces of the initial state: given, or evaluated with the given history
+  if (F0) {
+    for (int k = 0; k < 3; k++) {
+      gather3(F0, id_at_slot, k, tmp);
+      if ((st = h2d_real(e, e.F[k], tmp)) != DEM_OK) return st;
+      gather3(T0, id_at_slot, k, tmp);
+      if ((st = h2d_real(e, e.T[k], tmp)) != DEM_OK) return st;
+    }
+  } else {
+    PairArgs a = pair_args(e, 0, e.F, e.T);
+    HIP_TRY(launch_forces(e.prec, a, e.stream));
+  }
+  return sync_and_check(e);
+}
+
+dem_status engine_create(int32_t S, const dem_params *p, const int64_t *n, const double *x, const double *v,
+                         const double *omega, const double *r, const double *F0, const double *T0,
+                         const HistIn &hist, void *workspace, size_t ws_bytes, void *hip_stream, Engine **out) {
+  *out = nullptr;
+  Engine *e = new (std::nothrow) Engine;
+  if (!e) return DEM_E_INVALID;
+  dem_status st = plan(*e, S, p, n);
+  std::vector<float> rf;
+  if (st == DEM_OK) st = validate_inputs(*e, x, v, omega, r, F0, T0, hist, rf);
+  if (st == DEM_OK) {
+    const size_t need = carve(*e, nullptr);
+    if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) st = DEM_E_WORKSPACE;
+  }
+  if (st != DEM_OK) {
+    delete e;
+    return st;
+  }
+  e->stream = (hipStream_t)hip_stream;
+  carve(*e, (char *)workspace);
+  st = engine_init(*e, x, v, omega, rf, F0, T0, hist);
+  if (st != DEM_OK) {
+    release(e);
+    return st;
+  }
+  *out = e;
+  return DEM_OK;
+}
+
+// ----------------------------------------------------------------- step
+
+// Steps 3-8 of one time step.  Steps 1-2 (opening kick, drift, hash) run
+// before the first step of a call and, after that, inside the previous
+// step's gather for every system that steps again.
+hipError_t step_body(Engine &e, hipEvent_t *ev) {
+  auto mark = [&](int phase) {
+    if (ev) (void)hipEventRecord(ev[phase], e.stream);
+  };
+  const Layout L = e.layout();
+  hipError_t r;
+  // Step 3
+  if ((r = launch_sort(e.cell, e.pos[e.cp].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
+                       e.stream)) != hipSuccess)
+    return r;
+  mark(2);
+  // Step 4
+  if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], e.perm, e.cell,
+                          e.scell, e.nbr.xyzr, e.stream)) != hipSuccess)
+    return r;
+  e.cp ^= 1;
+  e.cv ^= 1;
+  mark(3);
+  // Steps 5-6 into the generation that does not hold the committed history
+  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl)) != hipSuccess) return r;
+  mark(4);
+  // Steps 7-8 and the closing half kick; the new history is committed
+  PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);
+  if ((r = launch_forces(e.prec, a, e.stream)) != hipSuccess) return r;
+  if ((r = launch_step_end(e.ctl, e.stream)) != hipSuccess) return r;
+  mark(5);
+  e.cv ^= 1;
+  e.gc = e.gs;
+  return hipSuccess;
+}
+
+// Capture the step body for the current position parity.  Every argument of
+// every launch is fixed by (cp, cv, gc), so the graph replays any later step
+// that starts from the same three.
+dem_status capture(Engine &e) {
+  const int cp = e.cp, cv = e.cv, gc = e.gc, gs = e.gs;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t r = step_body(e, nullptr);
+  const hipError_t r2 = hipStreamEndCapture(e.stream, &graph);
+  e.cp = cp;
+  e.cv = cv;
+  e.gc = gc;
+  e.gs = gs;
+  if (r != hipSuccess || r2 != hipSuccess || !graph) {
+    (void)hipGetLastError();
+    if (graph) (void)hipGraphDestroy(graph);
+    return DEM_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t r3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (r3 != hipSuccess) {
+    (void)hipGetLastError();
+    return DEM_E_HIP;
+  }
+  if (e.gexec[cp]) (void)hipGraphExecDestroy(e.gexec[cp]);
+  e.gexec[cp] = exec;
+  e.gexec_gc[cp] = gc;
+  return DEM_OK;
+}
+
+dem_status engine_step(Engine &e, const int64_t *steps) {
+  if (e.sticky != DEM_OK) return e.sticky;
+  int64_t maxs = 0;
+  for (int32_t k = 0; k < e.S; k++) {
+    if (steps[k] < 0 || steps[k] > (int64_t)INT32_MAX / 2) return DEM_E_INVALID;
+    maxs = std::max(maxs, steps[k]);
+  }
+  if (maxs == 0) return DEM_OK;
+  // the previous call's upload of left[] must have been read before the
+  // host array is overwritten
+  if (e.left_pending && hipEventSynchronize(e.left_ev) != hipSuccess) return e.sticky = DEM_E_HIP;
+  for (int32_t k = 0; k < e.S; k++) e.left_h[k] = (int32_t)steps[k];
+  if (hipMemcpyAsync(e.ctl.left, e.left_h.data(), sizeof(int32_t) * e.S, hipMemcpyHostToDevice, e.stream) !=
+          hipSuccess ||
+      hipEventRecord(e.left_ev, e.stream) != hipSuccess || launch_fill(e.ctl.step, 1, 0, e.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return e.sticky = DEM_E_HIP;
+  }
+  e.left_pending = true;
+  const Layout L = e.layout();
+  for (int64_t k = 0; k < maxs; k++) {
+    hipEvent_t *ev = nullptr;
+    if (e.profiling && e.timed < DEM_PROFILE_CAPACITY) {
+      ev = e.events.data() + (size_t)e.timed * (DEM_NUM_PHASES + 1);
+      e.timed++;
+    }
+    if (ev) (void)hipEventRecord(ev[0], e.stream);
+    // Steps 1-2 for the first step of the call
+    if (k == 0 && launch_kick_drift_hash(e.prec, L, e.ctl, e.pos[e.cp], e.vel[e.cv], e.F, e.T, e.scell, e.cell,
+                                         e.err, e.stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return e.sticky = DEM_E_HIP;
+    }
+    if (ev) (void)hipEventRecord(ev[1], e.stream);
+    if (e.use_graph) {
+      const int par = e.cp;
+      if (!e.gexec[par] || e.gexec_gc[par] != e.gc) {
+        const dem_status st = capture(e);
+        if (st != DEM_OK) return e.sticky = st;
+      }
+      if (ev)
+        for (int p = 2; p <= 4; p++) (void)hipEventRecord(ev[p], e.stream);
+      if (hipGraphLaunch(e.gexec[par], e.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return e.sticky = DEM_E_HIP;
+      }
+      if (ev) (void)hipEventRecord(ev[5], e.stream);
+      // what the replayed body does to the buffer indices (cv comes back)
+      e.cp ^= 1;
+      e.gs = e.gc ^ 1;
+      e.gc = e.gs;
+    } else if (step_body(e, ev) != hipSuccess) {
+      (void)hipGetLastError();
+      return e.sticky = DEM_E_HIP;
+    }
+  }
+  return DEM_OK;
+}
+
+dem_status engine_use_graph(Engine &e, int enable) {
+  if (enable && e.stream == nullptr) return DEM_E_INVALID;  // no capture on the null stream
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  e.use_graph = enable != 0;
+  if (!e.use_graph) free_graphs(e);
+  return DEM_OK;
+}
+
+dem_status engine_forces(Engine &e, double *F, double *T) {
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  PairArgs a = pair_args(e, 0, e.Fe, e.Te);
+  if (launch_forces(e.prec, a, e.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return e.sticky = DEM_E_HIP;
+  }
+  if ((st = sync_and_check(e)) != DEM_OK) return st;
+  const size_t N = (size_t)e.n;
+  std::vector<int32_t> id;
+  if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
+  std::vector<double> tmp;
+  for (int k = 0; k < 3; k++) {
+    if ((st = d2h_real(e, e.Fe[k], 0, N, tmp)) != DEM_OK) return st;
+    for (size_t i = 0; i < N; i++) F[3 * (size_t)id[i] + k] = tmp[i];
+    if ((st = d2h_real(e, e.Te[k], 0, N, tmp)) != DEM_OK) return st;
+    for (size_t i = 0; i < N; i++) T[3 * (size_t)id[i] + k] = tmp[i];
+  }
+  return DEM_OK;
+}
+
+// state of system k, in the system's own original order
+dem_status engine_read_state(Engine &e, int32_t k, double *x, double *v, double *omega, double *F, double *T) {
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  const SysInfo &si = e.info[k];
+  const size_t p0 = (size_t)si.p0, n = (size_t)si.n;
+  std::vector<int32_t> id;
+  if ((st = d2h(e, e.pos[e.cp].id + p0, id, n)) != DEM_OK) return st;
+  for (size_t i = 0; i < n; i++) id[i] -= (int32_t)p0;
+  std::vector<double> tmp;
+  if (x) {
+    const double *src[3] = {e.pos[e.cp].x, e.pos[e.cp].y, e.pos[e.cp].z};
+    for (int c = 0; c < 3; c++) {
+      if ((st = d2h(e, src[c] + p0, tmp, n)) != DEM_OK) return st;
+      for (size_t i = 0; i < n; i++) x[3 * (size_t)id[i] + c] = tmp[i];
+    }
+  }
+  void *const *arrs[4] = {e.vel[e.cv].v, e.vel[e.cv].w, e.F, e.T};
+  double *outs[4] = {v, omega, F, T};
+  for (int q = 0; q < 4; q++) {
+    if (!outs[q]) continue;
+    for (int c = 0; c < 3; c++) {
+      if ((st = d2h_real(e, arrs[q][c], p0, n, tmp)) != DEM_OK) return st;
+      for (size_t i = 0; i < n; i++) outs[q][3 * (size_t)id[i] + c] = tmp[i];
+    }
+  }
+  return DEM_OK;
+}
+
+// committed: the tangential history; otherwise the contacts of the current
+// positions (keys only)
+dem_status engine_read_contacts(Engine &e, int32_t k, bool committed, int64_t cap, int64_t *n_out,
+                                int64_t *pairs, double *delta_t) {
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  std::vector<Entry> ent;
+  if (!(committed && e.law == DEM_LAW_SIMPLE) &&
+      (st = read_gen(e, e.gen[committed ? e.gc : e.gs], k, committed, ent)) != DEM_OK)
+    return st;
+  *n_out = (int64_t)ent.size();
+  if ((int64_t)ent.size() > cap) return DEM_E_CAPACITY;
+  for (size_t q = 0; q < ent.size(); q++) {
+    if (pairs) {
+      pairs[2 * q] = ent[q].a;
+      pairs[2 * q + 1] = ent[q].b;
+    }
+    if (delta_t)
+      for (int c = 0; c < 3; c++) delta_t[3 * q + c] = ent[q].d[c];
+  }
+  return DEM_OK;
+}
+
+dem_status engine_diagnostics(Engine &e, double *out) {
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  PairArgs a = pair_args(e, MODE_DIAG, e.Fe, e.Te);
+  if (launch_forces(e.prec, a, e.stream) != hipSuccess ||
+      launch_diag_reduce(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.diag, e.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return e.sticky = DEM_E_HIP;
+  }
+  if ((st = sync_and_check(e)) != DEM_OK) return st;
+  std::vector<double> o;
+  if ((st = d2h(e, (const double *)e.diag.out, o, 10 * (size_t)e.S)) != DEM_OK) return st;
+  memcpy(out, o.data(), o.size() * sizeof(double));
+  return DEM_OK;
+}
+
+dem_status engine_profile(Engine &e, int enable) {
+  if (enable && e.events.empty()) {
+    const size_t cnt = (size_t)DEM_PROFILE_CAPACITY * (DEM_NUM_PHASES + 1);
+    e.events.assign(cnt, nullptr);
+    for (size_t k = 0; k < cnt; k++)
+      if (hipEventCreate(&e.events[k]) != hipSuccess) {
+        (void)hipGetLastError();
+        e.events.resize(k);
+        free_events(e);
+        return DEM_E_HIP;
+      }
+  }
+  e.profiling = enable != 0;
+  e.timed = 0;
+  return DEM_OK;
+}
+
+dem_status engine_profile_read(Engine &e, double ms[DEM_NUM_PHASES], int64_t *steps) {
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  for (int p = 0; p < DEM_NUM_PHASES; p++) ms[p] = 0.0;
+  for (int64_t k = 0; k < e.timed; k++) {
+    hipEvent_t *ev = e.events.data() + (size_t)k * (DEM_NUM_PHASES + 1);
+    for (int p = 0; p < DEM_NUM_PHASES; p++) {
+      float t = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
+      ms[p] += (double)t;
+    }
+  }
+  *steps = e.timed;
+  e.timed = 0;
+  return DEM_OK;
 }
 
 }  // namespace
+
+struct dem_system {
+  Engine *e;
+};
+struct dem_batch {
+  Engine *e;
+};
 
 extern "C" {
 
@@ -369,26 +905,21 @@ const char *dem_status_string(dem_status st) {
   switch (st) {
     case DEM_OK: return "ok";
     case DEM_E_INVALID: return "invalid argument";
-    case DEM_E_WORKSPACE: return "workspace missing or too small";
-    case DEM_E_CONTACT_OVERFLOW: return "contact history table overflow";
+    case DEM_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case DEM_E_CONTACT_OVERFLOW: return "contact list overflow";
     case DEM_E_OUT_OF_DOMAIN: return "particle out of domain";
     case DEM_E_NONFINITE: return "non-finite state or force";
     case DEM_E_HIP: return "HIP runtime error";
-    case DEM_E_STATE: return "system handle unusable";
+    case DEM_E_STATE: return "handle unusable";
     case DEM_E_CAPACITY: return "output capacity too small";
   }
   return "unknown status";
 }
 
+// ----------------------------------------------------------------- one system
+
 dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes) {
-  if (!bytes) return DEM_E_INVALID;
-  dem_system s;
-  memset(&s, 0, sizeof(s));
-  dem_status st = check_params(p, n, &s.grid);
-  if (st != DEM_OK) return st;
-  init_sizes(&s, p, n);
-  *bytes = carve(&s, nullptr);
-  return DEM_OK;
+  return dem_batch_workspace_bytes(1, p, &n, bytes);
 }
 
 dem_status dem_create(const dem_params *p, int64_t n, const double *x, const double *v, const double *omega,
@@ -397,316 +928,79 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
                       void *hip_stream, dem_system **out) {
   if (!out) return DEM_E_INVALID;
   *out = nullptr;
-  Grid g;
-  dem_status st = check_params(p, n, &g);
-  if (st != DEM_OK) return st;
-  if (n > 0 && (!x || !v || !omega || !r)) return DEM_E_INVALID;
   if ((F0 == nullptr) != (T0 == nullptr)) return DEM_E_INVALID;
   if (n_hist < 0 || (n_hist > 0 && (!hist_pairs || !hist_dt))) return DEM_E_INVALID;
-  // radii (FP32), the cell width needed by the 27-cell search, finiteness
-  std::vector<float> rf((size_t)n);
-  double rmax = 0.0;
-  for (int64_t i = 0; i < n; i++) {
-    const float q = (float)r[i];
-    if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
-    rf[i] = q;
-    rmax = std::max(rmax, (double)q);
-  }
-  if (p->cell_size < 2.0 * rmax) return DEM_E_INVALID;
-  for (int64_t i = 0; i < 3 * n; i++)
-    if (!isfinite(x[i]) || !isfinite(v[i]) || !isfinite(omega[i])) return DEM_E_NONFINITE;
-  if (F0)
-    for (int64_t i = 0; i < 3 * n; i++)
-      if (!isfinite(F0[i]) || !isfinite(T0[i])) return DEM_E_NONFINITE;
-  const bool keep_hist = p->law != DEM_LAW_SIMPLE && n_hist > 0;
-  if (keep_hist) {
-    for (int64_t k = 0; k < n_hist; k++) {
-      const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
-      const bool ok = a >= 0 && a < n && ((b > a && b < n) || (b < 0 && b >= -6));
-      if (!ok) return DEM_E_INVALID;
-      for (int q = 0; q < 3; q++)
-        if (!isfinite(hist_dt[3 * k + q])) return DEM_E_NONFINITE;
-    }
-  }
-
+  HistIn h;
+  h.n = n_hist;
+  h.pairs = hist_pairs;
+  h.dt = hist_dt;
+  Engine *e = nullptr;
+  const dem_status st = engine_create(1, p, &n, x, v, omega, r, F0, T0, h, workspace, ws_bytes, hip_stream, &e);
+  if (st != DEM_OK) return st;
   dem_system *s = new (std::nothrow) dem_system;
-  if (!s) return DEM_E_INVALID;
-  memset((void *)s, 0, sizeof(*s));
-  s->p = *p;
-  init_sizes(s, p, n);
-  s->grid = g;
-  s->stream = (hipStream_t)hip_stream;
-  s->nbr.eps = prefilter_eps(g, p->cell_size);
-  fill_consts(s);
-  const size_t need = carve(s, nullptr);
-  if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255)) {
-    delete s;
-    return DEM_E_WORKSPACE;
+  if (!s) {
+    release(e);
+    return DEM_E_INVALID;
   }
-  carve(s, (char *)workspace);
-
-  auto fail = [&](dem_status e) {
-    (void)hipStreamSynchronize(s->stream);
-    free_events(s);
-    delete s;
-    return e;
-  };
-  const size_t N = (size_t)n;
-  if (fill_i32(s, s->err, 64, 0) != DEM_OK) return fail(DEM_E_HIP);
-  // upload in original order into buffer 0
-  std::vector<int32_t> ids(N);
-  std::iota(ids.begin(), ids.end(), 0);
-  {
-    std::vector<double> tmp;
-    const PosBuf &pb = s->pos[0];
-    double *dst[3] = {pb.x, pb.y, pb.z};
-    for (int k = 0; k < 3; k++) {
-      gather3(x, ids, k, tmp);
-      if (h2d(s, dst[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
-    }
-    for (int k = 0; k < 3; k++) {
-      gather3(v, ids, k, tmp);
-      if (h2d_real(s, s->vel[0].v[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
-      gather3(omega, ids, k, tmp);
-      if (h2d_real(s, s->vel[0].w[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
-    }
-    if (h2d(s, pb.r, rf) != DEM_OK || h2d(s, pb.id, ids) != DEM_OK) return fail(DEM_E_HIP);
-  }
-  // Steps 2-4 on the initial positions
-  if (launch_hash(s->pos[0], s->n, s->grid, s->cell, s->err, s->stream) != hipSuccess) return fail(DEM_E_HIP);
-  if (launch_sort(s->cell, s->pos[0].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
-                  s->scan, s->stream) != hipSuccess)
-    return fail(DEM_E_HIP);
-  if (launch_reorder(s->prec, s->pos[0], s->vel[0], s->pos[1], s->vel[1], s->perm, s->cell, s->scell,
-                     s->nbr.xyzr, s->grid, s->n, s->stream) != hipSuccess)
-    return fail(DEM_E_HIP);
-  s->cp = 1;
-  s->cv = 1;
-  s->gc = 0;
-  // Steps 5-6: the contacts of the initial positions go to generation 1
-  if (build_contacts(s, 1) != hipSuccess) return fail(DEM_E_HIP);
-  st = sync_and_check(s);
-  if (st != DEM_OK) return fail(st);
-  std::vector<int32_t> id_at_slot;
-  if (d2h(s, s->pos[1].id, id_at_slot, N) != DEM_OK) return fail(DEM_E_HIP);
-  // the given history becomes generation 0, filed under the lower slot of
-  // each pair (the particle for a wall) in the sorted order
-  {
-    std::vector<int32_t> slot_of(N);
-    for (size_t sl = 0; sl < N; sl++) slot_of[id_at_slot[sl]] = (int32_t)sl;
-    std::vector<int32_t> cnt(N + 1, 0);
-    struct Rec {
-      int32_t owner, key;
-      double d[3];
-    };
-    std::vector<Rec> recs;
-    if (keep_hist) {
-      recs.reserve((size_t)n_hist);
-      for (int64_t k = 0; k < n_hist; k++) {
-        const int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
-        Rec rc;
-        if (b >= 0) {
-          const int32_t sa = slot_of[a], sb = slot_of[b];
-          rc.owner = std::min(sa, sb);
-          rc.key = (int32_t)(sa < sb ? b : a);
-        } else {
-          rc.owner = slot_of[a];
-          rc.key = (int32_t)b;
-        }
-        memcpy(rc.d, hist_dt + 3 * k, sizeof(rc.d));
-        recs.push_back(rc);
-      }
-      std::stable_sort(recs.begin(), recs.end(), [](const Rec &u, const Rec &w) { return u.owner < w.owner; });
-      for (size_t k = 1; k < recs.size(); k++)
-        if (recs[k].owner == recs[k - 1].owner && recs[k].key == recs[k - 1].key) return fail(DEM_E_INVALID);
-    }
-    if ((int64_t)recs.size() > s->work.Pcap) return fail(DEM_E_CONTACT_OVERFLOW);
-    std::vector<int32_t> ofs(N + 1, 0), key(recs.size());
-    std::vector<double> d(4 * recs.size(), 0.0);
-    for (const Rec &rc : recs) ofs[rc.owner + 1]++;
-    for (size_t k = 0; k < N; k++) ofs[k + 1] += ofs[k];
-    for (size_t k = 0; k < recs.size(); k++) {
-      key[k] = recs[k].key;
-      for (int c = 0; c < 3; c++) d[4 * k + c] = recs[k].d[c];
-    }
-    const PairGen &g0 = s->gen[0];
-    if (h2d(s, g0.ofs, ofs) != DEM_OK || h2d(s, g0.key, key) != DEM_OK || h2d_real(s, g0.dt, d) != DEM_OK)
-      return fail(DEM_E_HIP);
-  }
-  // forces of the initial state
-  if (F0) {
-    std::vector<double> tmp;
-    for (int k = 0; k < 3; k++) {
-      gather3(F0, id_at_slot, k, tmp);
-      if (h2d_real(s, s->F[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
-      gather3(T0, id_at_slot, k, tmp);
-      if (h2d_real(s, s->T[k], tmp) != DEM_OK) return fail(DEM_E_HIP);
-    }
-  } else {
-    PairArgs a = pair_args(s, 0, s->F, s->T);
-    if (launch_forces(s->prec, a, s->stream) != hipSuccess) return fail(DEM_E_HIP);
-  }
-  st = sync_and_check(s);
-  if (st != DEM_OK) return fail(st);
+  s->e = e;
   *out = s;
   return DEM_OK;
 }
 
 dem_status dem_step(dem_system *s, int64_t nsteps) {
   if (!s) return DEM_E_STATE;
-  if (nsteps < 0) return DEM_E_INVALID;
-  if (s->sticky != DEM_OK) return s->sticky;
-  bool drifted = false;  // the previous step's closing pass already ran Steps 1-2
-  for (int64_t k = 0; k < nsteps; k++) {
-    hipEvent_t *ev = nullptr;
-    if (s->profiling && s->timed < DEM_PROFILE_CAPACITY) {
-      ev = s->events->data() + (size_t)s->timed * (DEM_NUM_PHASES + 1);
-      s->timed++;
-    }
-    auto mark = [&](int phase) {
-      if (ev) (void)hipEventRecord(ev[phase], s->stream);
-    };
-    mark(0);
-    // Step 1 (opening half kick, drift) fused with Step 2 (hash)
-    if (!drifted && launch_kick_drift_hash(s->prec, s->pos[s->cp], s->vel[s->cv], s->F, s->T, s->n, s->c,
-                                           s->grid, s->cell, s->err, s->stream) != hipSuccess)
-      return s->sticky = DEM_E_HIP;
-    mark(1);
-    // Step 3
-    if (launch_sort(s->cell, s->pos[s->cp].id, s->n, s->grid.ncell, s->counts, s->rank, s->cell_start, s->perm,
-                    s->scan, s->stream) != hipSuccess)
-      return s->sticky = DEM_E_HIP;
-    mark(2);
-    // Step 4
-    if (launch_reorder(s->prec, s->pos[s->cp], s->vel[s->cv], s->pos[s->cp ^ 1], s->vel[s->cv ^ 1], s->perm,
-                       s->cell, s->scell, s->nbr.xyzr, s->grid, s->n, s->stream) != hipSuccess)
-      return s->sticky = DEM_E_HIP;
-    s->cp ^= 1;
-    s->cv ^= 1;
-    mark(3);
-    // Steps 5-6 into the generation that does not hold the committed history
-    if (build_contacts(s, s->gc ^ 1) != hipSuccess) return s->sticky = DEM_E_HIP;
-    mark(4);
-    // Steps 7-8 and the closing half kick; the new history is committed.
-    // Between two steps of this call the closing pass also runs the next
-    // step's opening kick, drift and hash (the state stays in registers).
-    drifted = k + 1 < nsteps;
-    PairArgs a = pair_args(s, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM | (drifted ? MODE_DRIFT : 0), s->F,
-                           s->T);
-    if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
-    mark(5);
-    s->cv ^= 1;
-    s->gc = s->gs;
-    s->steps++;
-  }
-  return DEM_OK;
+  return engine_step(*s->e, &nsteps);
 }
 
 dem_status dem_sync(dem_system *s) {
   if (!s) return DEM_E_STATE;
-  return sync_and_check(s);
+  return sync_and_check(*s->e);
+}
+
+dem_status dem_use_graph(dem_system *s, int enable) {
+  if (!s) return DEM_E_STATE;
+  return engine_use_graph(*s->e, enable);
 }
 
 dem_status dem_forces(dem_system *s, double *F, double *T) {
   if (!s) return DEM_E_STATE;
-  if (!F || !T) return DEM_E_INVALID;
-  dem_status st = sync_and_check(s);
-  if (st != DEM_OK) return st;
-  PairArgs a = pair_args(s, 0, s->Fe, s->Te);
-  if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
-  if ((st = sync_and_check(s)) != DEM_OK) return st;
-  const size_t N = (size_t)s->n;
-  std::vector<int32_t> id;
-  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
-  std::vector<double> tmp;
-  for (int k = 0; k < 3; k++) {
-    if ((st = d2h_real(s, s->Fe[k], tmp, N)) != DEM_OK) return st;
-    for (size_t i = 0; i < N; i++) F[3 * (size_t)id[i] + k] = tmp[i];
-    if ((st = d2h_real(s, s->Te[k], tmp, N)) != DEM_OK) return st;
-    for (size_t i = 0; i < N; i++) T[3 * (size_t)id[i] + k] = tmp[i];
-  }
-  return DEM_OK;
+  if (s->e->n > 0 && (!F || !T)) return DEM_E_INVALID;
+  return engine_forces(*s->e, F, T);
 }
 
 dem_status dem_read_state(dem_system *s, double *x, double *v, double *omega, double *F, double *T) {
   if (!s) return DEM_E_STATE;
-  dem_status st = sync_and_check(s);
-  if (st != DEM_OK) return st;
-  const size_t N = (size_t)s->n;
-  std::vector<int32_t> id;
-  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
-  if (x) {
-    std::vector<double> tmp;
-    const double *src[3] = {s->pos[s->cp].x, s->pos[s->cp].y, s->pos[s->cp].z};
-    for (int k = 0; k < 3; k++) {
-      if ((st = d2h(s, src[k], tmp, N)) != DEM_OK) return st;
-      for (size_t i = 0; i < N; i++) x[3 * (size_t)id[i] + k] = tmp[i];
-    }
-  }
-  void *const *arrs[4] = {s->vel[s->cv].v, s->vel[s->cv].w, s->F, s->T};
-  double *outs[4] = {v, omega, F, T};
-  for (int q = 0; q < 4; q++) {
-    if (!outs[q]) continue;
-    std::vector<double> tmp;
-    for (int k = 0; k < 3; k++) {
-      if ((st = d2h_real(s, arrs[q][k], tmp, N)) != DEM_OK) return st;
-      for (size_t i = 0; i < N; i++) outs[q][3 * (size_t)id[i] + k] = tmp[i];
-    }
-  }
-  return DEM_OK;
+  return engine_read_state(*s->e, 0, x, v, omega, F, T);
 }
 
 dem_status dem_read_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs, double *delta_t) {
   if (!s) return DEM_E_STATE;
   if (!n_out) return DEM_E_INVALID;
-  dem_status st = sync_and_check(s);
-  if (st != DEM_OK) return st;
-  std::vector<Entry> e;
-  if (s->p.law != DEM_LAW_SIMPLE && (st = read_gen(s, s->gen[s->gc], true, e)) != DEM_OK) return st;
-  *n_out = (int64_t)e.size();
-  if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
-  for (size_t k = 0; k < e.size(); k++) {
-    if (pairs) {
-      pairs[2 * k] = e[k].a;
-      pairs[2 * k + 1] = e[k].b;
-    }
-    if (delta_t)
-      for (int q = 0; q < 3; q++) delta_t[3 * k + q] = e[k].d[q];
-  }
-  return DEM_OK;
+  return engine_read_contacts(*s->e, 0, true, cap, n_out, pairs, delta_t);
 }
 
 dem_status dem_contacts(dem_system *s, int64_t cap, int64_t *n_out, int64_t *pairs) {
   if (!s) return DEM_E_STATE;
   if (!n_out) return DEM_E_INVALID;
-  dem_status st = sync_and_check(s);
-  if (st != DEM_OK) return st;
-  std::vector<Entry> e;
-  if ((st = read_gen(s, s->gen[s->gs], false, e)) != DEM_OK) return st;
-  *n_out = (int64_t)e.size();
-  if ((int64_t)e.size() > cap) return DEM_E_CAPACITY;
-  for (size_t k = 0; k < e.size() && pairs; k++) {
-    pairs[2 * k] = e[k].a;
-    pairs[2 * k + 1] = e[k].b;
-  }
-  return DEM_OK;
+  return engine_read_contacts(*s->e, 0, false, cap, n_out, pairs, nullptr);
 }
 
 dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot, int32_t *cell_start) {
   if (!s) return DEM_E_STATE;
-  dem_status st = sync_and_check(s);
+  Engine &e = *s->e;
+  dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
-  const size_t N = (size_t)s->n;
+  const size_t N = (size_t)e.n;
   std::vector<int32_t> id, sc;
-  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
   if (cell_of_id) {
-    if ((st = d2h(s, (const int32_t *)s->scell, sc, N)) != DEM_OK) return st;
+    if ((st = d2h(e, (const int32_t *)e.scell, sc, N)) != DEM_OK) return st;
     for (size_t i = 0; i < N; i++) cell_of_id[id[i]] = sc[i];
   }
   if (id_at_slot && N) memcpy(id_at_slot, id.data(), 4 * N);
   if (cell_start) {
     std::vector<int32_t> cs;
-    if ((st = d2h(s, (const int32_t *)s->cell_start, cs, (size_t)s->grid.ncell + 1)) != DEM_OK) return st;
+    if ((st = d2h(e, (const int32_t *)e.cell_start, cs, (size_t)e.ncell + 1)) != DEM_OK) return st;
     memcpy(cell_start, cs.data(), 4 * cs.size());
   }
   return DEM_OK;
@@ -715,33 +1009,23 @@ dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot
 dem_status dem_grid_dims(dem_system *s, int32_t dims[3]) {
   if (!s) return DEM_E_STATE;
   if (!dims) return DEM_E_INVALID;
-  for (int a = 0; a < 3; a++) dims[a] = s->grid.nc[a];
+  for (int a = 0; a < 3; a++) dims[a] = s->e->info[0].g.nc[a];
   return DEM_OK;
 }
 
 dem_status dem_diagnostics(dem_system *s, double out[10]) {
   if (!s) return DEM_E_STATE;
   if (!out) return DEM_E_INVALID;
-  dem_status st = sync_and_check(s);
-  if (st != DEM_OK) return st;
-  PairArgs a = pair_args(s, MODE_DIAG, s->Fe, s->Te);
-  if (launch_forces(s->prec, a, s->stream) != hipSuccess) return s->sticky = DEM_E_HIP;
-  if (launch_diag_reduce(s->prec, s->pos[s->cp], s->vel[s->cv], s->diag, s->n, s->c, s->grid, s->stream) !=
-      hipSuccess)
-    return s->sticky = DEM_E_HIP;
-  if ((st = sync_and_check(s)) != DEM_OK) return st;
-  std::vector<double> o;
-  if ((st = d2h(s, (const double *)s->diag.out, o, 10)) != DEM_OK) return st;
-  memcpy(out, o.data(), 10 * sizeof(double));
-  return DEM_OK;
+  return engine_diagnostics(*s->e, out);
 }
 
 dem_status dem_set_radii(dem_system *s, const double *r) {
   if (!s) return DEM_E_STATE;
-  if (s->n > 0 && !r) return DEM_E_INVALID;
-  dem_status st = sync_and_check(s);
+  Engine &e = *s->e;
+  if (e.n > 0 && !r) return DEM_E_INVALID;
+  dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
-  const size_t N = (size_t)s->n;
+  const size_t N = (size_t)e.n;
   std::vector<float> rf(N);
   double rmax = 0.0;
   for (size_t i = 0; i < N; i++) {
@@ -750,61 +1034,118 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
     rf[i] = q;
     rmax = std::max(rmax, (double)q);
   }
-  if (s->p.cell_size < 2.0 * rmax) return DEM_E_INVALID;
+  if (e.params[0].cell_size < 2.0 * rmax) return DEM_E_INVALID;
+  if (N == 0) return DEM_OK;
   std::vector<int32_t> id;
-  if ((st = d2h(s, s->pos[s->cp].id, id, N)) != DEM_OK) return st;
+  if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
   std::vector<float> slot_r(N);
   for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
-  if (N) {
-    if ((st = h2d(s, s->pos[s->cp].r, slot_r)) != DEM_OK) return st;
-    HIP_TRY(launch_xyzr(s->pos[s->cp], s->nbr.xyzr, s->grid, s->n, s->stream));
-    // the contact list of the new radii, beside the committed history
-    HIP_TRY(build_contacts(s, s->gc ^ 1));
-  }
-  return sync_and_check(s);
+  if ((st = h2d(e, e.pos[e.cp].r, slot_r)) != DEM_OK) return st;
+  HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr.xyzr, e.stream));
+  // the contact list of the new radii, beside the committed history
+  HIP_TRY(build_contacts(e, e.gc ^ 1, nullptr));
+  return sync_and_check(e);
 }
 
 dem_status dem_profile(dem_system *s, int enable) {
   if (!s) return DEM_E_STATE;
-  if (enable && !s->events) {
-    const size_t cnt = (size_t)DEM_PROFILE_CAPACITY * (DEM_NUM_PHASES + 1);
-    s->events = new (std::nothrow) std::vector<hipEvent_t>(cnt, nullptr);
-    if (!s->events) return DEM_E_INVALID;
-    for (size_t k = 0; k < cnt; k++)
-      if (hipEventCreate(&(*s->events)[k]) != hipSuccess) {
-        (void)hipGetLastError();
-        free_events(s);
-        return DEM_E_HIP;
-      }
-  }
-  s->profiling = enable != 0;
-  s->timed = 0;
-  return DEM_OK;
+  return engine_profile(*s->e, enable);
 }
 
 dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps) {
   if (!s) return DEM_E_STATE;
   if (!ms || !steps) return DEM_E_INVALID;
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  for (int p = 0; p < DEM_NUM_PHASES; p++) ms[p] = 0.0;
-  for (int64_t k = 0; k < s->timed; k++) {
-    hipEvent_t *ev = s->events->data() + (size_t)k * (DEM_NUM_PHASES + 1);
-    for (int p = 0; p < DEM_NUM_PHASES; p++) {
-      float t = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&t, ev[p], ev[p + 1]));
-      ms[p] += (double)t;
-    }
-  }
-  *steps = s->timed;
-  s->timed = 0;
-  return DEM_OK;
+  return engine_profile_read(*s->e, ms, steps);
 }
 
 dem_status dem_destroy(dem_system *s) {
   if (!s) return DEM_E_STATE;
-  (void)hipStreamSynchronize(s->stream);
-  free_events(s);
+  release(s->e);
   delete s;
+  return DEM_OK;
+}
+
+// ----------------------------------------------------------------- batches
+
+dem_status dem_batch_workspace_bytes(int32_t n_sys, const dem_params *p, const int64_t *n, size_t *bytes) {
+  if (!bytes) return DEM_E_INVALID;
+  Engine e;
+  const dem_status st = plan(e, n_sys, p, n);
+  if (st != DEM_OK) return st;
+  *bytes = carve(e, nullptr);
+  return DEM_OK;
+}
+
+dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n, const double *x,
+                            const double *v, const double *omega, const double *r, void *workspace,
+                            size_t ws_bytes, void *hip_stream, dem_batch **out) {
+  if (!out) return DEM_E_INVALID;
+  *out = nullptr;
+  Engine *e = nullptr;
+  const dem_status st = engine_create(n_sys, p, n, x, v, omega, r, nullptr, nullptr, HistIn{}, workspace,
+                                      ws_bytes, hip_stream, &e);
+  if (st != DEM_OK) return st;
+  dem_batch *b = new (std::nothrow) dem_batch;
+  if (!b) {
+    release(e);
+    return DEM_E_INVALID;
+  }
+  b->e = e;
+  *out = b;
+  return DEM_OK;
+}
+
+dem_status dem_batch_step(dem_batch *b, const int64_t *steps) {
+  if (!b) return DEM_E_STATE;
+  if (!steps) return DEM_E_INVALID;
+  return engine_step(*b->e, steps);
+}
+
+dem_status dem_batch_read_state(dem_batch *b, int32_t k, double *x, double *v, double *omega, double *F,
+                                double *T) {
+  if (!b) return DEM_E_STATE;
+  if (k < 0 || k >= b->e->S) return DEM_E_INVALID;
+  return engine_read_state(*b->e, k, x, v, omega, F, T);
+}
+
+dem_status dem_batch_read_contacts(dem_batch *b, int32_t k, int64_t cap, int64_t *n_out, int64_t *pairs,
+                                   double *delta_t) {
+  if (!b) return DEM_E_STATE;
+  if (k < 0 || k >= b->e->S || !n_out) return DEM_E_INVALID;
+  return engine_read_contacts(*b->e, k, true, cap, n_out, pairs, delta_t);
+}
+
+dem_status dem_batch_diagnostics(dem_batch *b, double *out) {
+  if (!b) return DEM_E_STATE;
+  if (!out) return DEM_E_INVALID;
+  return engine_diagnostics(*b->e, out);
+}
+
+dem_status dem_batch_use_graph(dem_batch *b, int enable) {
+  if (!b) return DEM_E_STATE;
+  return engine_use_graph(*b->e, enable);
+}
+
+dem_status dem_batch_profile(dem_batch *b, int enable) {
+  if (!b) return DEM_E_STATE;
+  return engine_profile(*b->e, enable);
+}
+
+dem_status dem_batch_profile_read(dem_batch *b, double ms[DEM_NUM_PHASES], int64_t *steps) {
+  if (!b) return DEM_E_STATE;
+  if (!ms || !steps) return DEM_E_INVALID;
+  return engine_profile_read(*b->e, ms, steps);
+}
+
+dem_status dem_batch_sync(dem_batch *b) {
+  if (!b) return DEM_E_STATE;
+  return sync_and_check(*b->e);
+}
+
+dem_status dem_batch_destroy(dem_batch *b) {
+  if (!b) return DEM_E_STATE;
+  release(b->e);
+  delete b;
   return DEM_OK;
 }
 

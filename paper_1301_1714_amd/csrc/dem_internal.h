@@ -1,21 +1,28 @@
 // dem_internal.h -- device data layout and kernel launchers of libdem.so.
 //
-// Layout in HBM (structure of arrays, every per-particle array indexed by
-// the sorted slot of the last cell sort, Sec. 4.1 / Step 4):
-//   pos[2]   x, y, z (FP64), r (FP32), id (int32)          -- double-buffered
-//   vel[2]   vx, vy, vz, wx, wy, wz (Real)                   -- double-buffered
+// One engine holds S >= 1 independent systems.  Their particles occupy fixed,
+// consecutive slot ranges [p0, p0 + n) and their cells consecutive global
+// cell ranges [c0, c0 + ncell); the cell sort keeps every particle inside its
+// system's slot range, so the particle -> system map never changes.
+//
+// Layout in HBM (structure of arrays, per-particle arrays indexed by the
+// sorted slot of the last cell sort, Sec. 4.1 / Step 4):
+//   pos[2]   x, y, z (FP64), r (FP32), id (int32; unique over the engine)
+//   vel[2]   vx, vy, vz, wx, wy, wz (Real)
 //   F, T     contact force / torque of the last evaluation (Real)
-//   cell     CM of the pre-sort order; rank, perm (new slot -> old slot)
-//   scell    cell of each sorted slot; cell_start[ncell + 1]
+//   cell     global cell of the pre-sort order; rank, perm (new -> old slot)
+//   scell    global cell of each sorted slot; cell_start[ncell_total + 1]
+//   psys     system of each slot; bsys/bfirst: system and first slot of each
+//            kernel block (blocks never straddle two systems)
 //   nbr      detection output: xyzr (FP32 copy of x - lo and r, the
 //            prefilter's input) and, per particle, its contacts with higher
 //            slots in ascending order followed by its walls (-1 - w)
 //   gen[2]   two generations of the compact contact list, CSR by owner slot
-//            (the lower slot of a pair): ofs[N + 1], then per contact the
-//            owner s, partner t (slot or -1 - w), history key (partner id or
-//            -1 - w) and the tangential displacement delta_t (Real4, as seen
-//            from the lower particle id).  One generation holds the committed
-//            history, the other is rebuilt for the new positions.
+//            (the lower slot of a pair; the particle for a wall): ofs[N + 1],
+//            per contact the owner s, partner t (slot or -1 - w), history key
+//            (partner slot or -1 - w) and delta_t (Real4, as seen from the
+//            owner).  One generation holds the committed history, the other
+//            is rebuilt for the new positions.
 //   work     per-contact force on the owner and n x F_t (2 x Real4), and the
 //            backward CSR (contacts of each particle as the partner)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
@@ -33,19 +40,20 @@ enum ErrBits : int32_t { ERR_DOMAIN = 1, ERR_OVERFLOW = 2, ERR_NONFINITE = 4 };
 // contact-evaluation modes
 enum ModeBits : int32_t {
   MODE_WRITE_HIST = 1,  // write the new tangential displacements
-  MODE_KICK = 2,        // closing half kick into the other velocity buffer
+  MODE_KICK = 2,        // a time step: closing half kick (active systems only)
   MODE_DIAG = 4,        // per-particle elastic energy / contact counts / max overlap
-  MODE_OLD_PERM = 8,    // committed history is in the pre-sort slot order (use perm)
-  MODE_DRIFT = 16       // with MODE_KICK: also the next step's opening kick, drift and hash
+  MODE_OLD_PERM = 8     // committed history is in the pre-sort slot order (use perm)
 };
 
+constexpr int32_t kBlock = 256;
 constexpr int32_t kListCap = 64;  // detection: contacts per particle (forward + walls)
 
 struct Grid {
   double lo[3], hi[3];
   double sc[3];  // cells per unit length: n_a / (hi_a - lo_a)
   int32_t nc[3];
-  int64_t ncell;
+  int32_t c0;     // first global cell of the system
+  int32_t ncell;  // cells of the system
 };
 
 struct Consts {
@@ -57,6 +65,22 @@ struct Consts {
   double g[3];
   uint32_t wall_mask;
   int32_t law;
+};
+
+struct SysInfo {
+  Grid g;
+  Consts c;
+  int32_t p0, n;  // slot range
+  float eps;      // detection prefilter margin
+  int32_t pad;
+};
+
+// Step control on the device, so that one captured step can be replayed:
+// system k is active while step < left[k]; a step after which it stays
+// active also runs the next step's opening kick, drift and hash.
+struct StepCtl {
+  int32_t *step;  // [1] steps done in the current call
+  int32_t *left;  // [S] steps requested for each system in the current call
 };
 
 struct PosBuf {
@@ -73,7 +97,6 @@ struct NbrBuf {
   float4 *xyzr;  // [N] (x - lo, y - lo, z - lo, r), FP32
   int32_t *cnt;  // [N] entries used in nb (clamped to kListCap)
   int32_t *nb;   // [kListCap][N]
-  float eps;     // prefilter margin: bounds the FP32 error of |x_j - x_i|
 };
 
 struct PairGen {
@@ -85,13 +108,13 @@ struct PairGen {
 };
 
 struct PairWork {
-  void *pf;       // [2 Pcap] Real4: force on the owner, then n x F_t (canonical orientation)
-  int32_t *brank; // [Pcap] rank of the contact in its partner's backward list
-  double *pe;     // [Pcap] elastic energy (diagnostics)
-  double *pd;     // [Pcap] overlap (diagnostics)
-  int32_t *bcnt;  // [N] backward counts, then fill counters
-  int32_t *bofs;  // [N + 1]
-  int32_t *bwd;   // [Pcap] contact indices grouped by partner
+  void *pf;        // [2 Pcap] Real4: force on the owner, then n x F_t
+  int32_t *brank;  // [Pcap] rank of the contact in its partner's backward list
+  double *pe;      // [Pcap] elastic energy (diagnostics)
+  double *pd;      // [Pcap] overlap (diagnostics)
+  int32_t *bcnt;   // [N] backward counts
+  int32_t *bofs;   // [N + 1]
+  int32_t *bwd;    // [Pcap] contact indices grouped by partner
   int64_t Pcap;
 };
 
@@ -101,10 +124,23 @@ struct DiagBuf {
   int32_t *nwall;   // [N]
   double *dmax;     // [N]
   double *partial;  // [blocks][10]
-  double *out;      // [10]
+  double *out;      // [S][10]
+};
+
+// what every per-particle kernel needs to find its system
+struct Layout {
+  const SysInfo *tab;     // [S]
+  const int32_t *psys;    // [N]
+  const int32_t *bsys;    // [nblocks]
+  const int32_t *bfirst;  // [nblocks]
+  int32_t nblocks;
+  int32_t n;
+  int32_t S;
 };
 
 struct PairArgs {
+  Layout L;
+  StepCtl ctl;
   PosBuf pos;
   VelBuf vel_in, vel_out;
   PairGen cur, old;     // cur: contacts of the current positions; old: committed history
@@ -112,11 +148,10 @@ struct PairArgs {
   const int32_t *perm;  // with MODE_OLD_PERM: current slot -> slot of `old`
   void *F[3], *T[3];
   DiagBuf diag;
-  int32_t *cell;        // with MODE_DRIFT: the cells of the drifted positions
-  int32_t n;
+  int32_t *cell;         // cells for the next sort (drifted positions, or unchanged ones)
+  const int32_t *scell;  // cells of the current slots
   int32_t mode;
-  Grid grid;
-  Consts c;
+  int32_t law;
   int32_t *err;
 };
 
@@ -127,25 +162,27 @@ struct ScanScratch {
 };
 
 // launchers (dem_kernels.hip); all enqueue on `st` and return hipError_t
-hipError_t launch_hash(const PosBuf &p, int32_t n, const Grid &g, int32_t *cell, int32_t *err, hipStream_t st);
-hipError_t launch_kick_drift_hash(int precision, const PosBuf &p, const VelBuf &v, void *const F[3],
-                                  void *const T[3], int32_t n, const Consts &c, const Grid &g, int32_t *cell,
-                                  int32_t *err, hipStream_t st);
+hipError_t launch_hash(const Layout &L, const PosBuf &p, int32_t *cell, int32_t *err, hipStream_t st);
+hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl &ctl, const PosBuf &p,
+                                  const VelBuf &v, void *const F[3], void *const T[3], const int32_t *scell,
+                                  int32_t *cell, int32_t *err, hipStream_t st);
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
-hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
+hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
-hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, hipStream_t st);
-// Steps 5-6: detection and the compact contact list (structure of `gen`)
-hipError_t launch_contacts(const PosBuf &p, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                           const int32_t *scell, const int32_t *cell_start, const Grid &g, uint32_t wall_mask,
-                           int32_t n, const ScanScratch &sc, int32_t *err, hipStream_t st);
+                          float4 *xyzr, hipStream_t st);
+hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st);
+// Steps 5-6: detection (all systems, or with ctl only the active ones; the
+// others keep their lists) and the compact contact list of `gen`
+hipError_t launch_contacts(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+                           const PairGen &gen, const PairWork &w, const int32_t *scell, const int32_t *cell_start,
+                           const ScanScratch &sc, int32_t *err, hipStream_t st);
 // Steps 7-8: contact forces on the list of a.cur, per-particle sums, kick
 hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st);
-hipError_t launch_diag_reduce(int precision, const PosBuf &p, const VelBuf &v, const DiagBuf &d, int32_t n,
-                              const Consts &c, const Grid &g, hipStream_t st);
+hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st);
+hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,
+                              hipStream_t st);
+hipError_t launch_fill(int32_t *a, int64_t len, int32_t value, hipStream_t st);
 int64_t scan_scratch_len(int64_t n, int64_t *lens, int *nlevels);
-int diag_blocks(int32_t n);
 
 }  // namespace dem

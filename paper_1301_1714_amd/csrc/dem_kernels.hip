@@ -1,9 +1,12 @@
 // dem_kernels.hip -- HIP kernels of one DEM timestep for gfx950 (wave64).
 //
-// Steps of Sec. 4.2 and the kernels that run them:
-//   Step 1       k_kick_drift_hash: opening half kick, drift and Step 2's
-//                cell hash fused (one pass over the state)
-//   Steps 2-3    k_count / scan / k_scatter / k_canon: counting sort by cell,
+// Steps of Sec. 4.2 and the kernels that run them (every kernel serves all
+// systems of an engine at once; per-particle kernels run blocks that never
+// straddle two systems, so a block reads its system's constants once):
+//   Steps 1-2    k_kick_drift_hash: opening half kick, drift and the cell
+//                hash (CM) fused; between two steps of one call the closing
+//                pass k_gather does it instead
+//   Step 3       k_count / scan / k_scatter / k_canon: counting sort by cell,
 //                ties ordered by particle id, so SCM[j] = CM[SCCM[j]] (Eq. 11)
 //                holds with one unique order; the paper's bitonic sort is
 //                replaced by this O(N) sort (any correct sort of unique keys
@@ -32,9 +35,9 @@
 
 namespace dem {
 
-constexpr int kBlock = 256;
-
 __device__ __forceinline__ void raise_err(int32_t *err, int32_t bit) { atomicOr(err, bit); }
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // --------------------------------------------------------------------------
 // exact arithmetic shared by detection and hashing: no contraction into FMA,
@@ -50,8 +53,8 @@ __device__ __forceinline__ double sq_exact(double s) {
   return s * s;
 }
 
-// Step 2: cell of a position (Sec. 4.1).  Returns false when the particle is
-// more than one cell outside the box (or not finite).
+// Step 2: global cell of a position (Sec. 4.1).  Returns false when the
+// particle is more than one cell outside the box (or not finite).
 __device__ __forceinline__ bool hash_cell(const Grid &g, double x, double y, double z, int32_t *cell) {
 #pragma clang fp contract(off)
   const double p[3] = {x, y, z};
@@ -65,7 +68,7 @@ __device__ __forceinline__ bool hash_cell(const Grid &g, double x, double y, dou
     int32_t i = f < 0.0 ? 0 : (f > (double)(g.nc[a] - 1) ? g.nc[a] - 1 : (int32_t)f);
     ijk[a] = i;
   }
-  *cell = ijk[0] + g.nc[0] * (ijk[1] + g.nc[1] * ijk[2]);
+  *cell = g.c0 + ijk[0] + g.nc[0] * (ijk[1] + g.nc[1] * ijk[2]);
   return ok;
 }
 
@@ -74,14 +77,25 @@ __device__ __forceinline__ Real mass_of(const Consts &c, Real r) {
   return (Real)c.mass_c * r * r * r;
 }
 
+// the slot of this thread in a per-particle launch, or -1; k: its system
+__device__ __forceinline__ int32_t block_slot(const Layout &L, int32_t &k) {
+  k = L.bsys[blockIdx.x];
+  const int32_t s = L.bfirst[blockIdx.x] + (int32_t)threadIdx.x;
+  const SysInfo &si = L.tab[k];
+  return s < si.p0 + si.n ? s : -1;
+}
+
+__device__ __forceinline__ bool is_active(const StepCtl &ctl, int32_t k) { return *ctl.step < ctl.left[k]; }
+
 // --------------------------------------------------------------------------
 // Steps 1-2
 
-__global__ __launch_bounds__(kBlock) void k_hash(PosBuf p, int32_t n, Grid g, int32_t *cell, int32_t *err) {
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+__global__ __launch_bounds__(kBlock) void k_hash(Layout L, PosBuf p, int32_t *cell, int32_t *err) {
+  int32_t k;
+  const int32_t i = block_slot(L, k);
+  if (i < 0) return;
   int32_t c;
-  if (!hash_cell(g, p.x[i], p.y[i], p.z[i], &c)) raise_err(err, ERR_DOMAIN);
+  if (!hash_cell(L.tab[k].g, p.x[i], p.y[i], p.z[i], &c)) raise_err(err, ERR_DOMAIN);
   cell[i] = c;
 }
 
@@ -114,32 +128,39 @@ __device__ __forceinline__ void drift_hash(const PosBuf &p, int32_t i, const Rea
 }
 
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_kick_drift_hash(PosBuf p, VelBuf vb, const Real *__restrict__ Fx,
+__global__ __launch_bounds__(kBlock) void k_kick_drift_hash(Layout L, StepCtl ctl, PosBuf p, VelBuf vb,
+                                                            const Real *__restrict__ Fx,
                                                             const Real *__restrict__ Fy,
                                                             const Real *__restrict__ Fz,
                                                             const Real *__restrict__ Tx,
                                                             const Real *__restrict__ Ty,
-                                                            const Real *__restrict__ Tz, int32_t n, Consts c,
-                                                            Grid g, int32_t *cell, int32_t *err) {
-#pragma clang fp contract(off)
-  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+                                                            const Real *__restrict__ Tz,
+                                                            const int32_t *__restrict__ scell, int32_t *cell,
+                                                            int32_t *err) {
+  int32_t k;
+  const int32_t i = block_slot(L, k);
+  if (i < 0) return;
+  if (!is_active(ctl, k)) {
+    cell[i] = scell[i];  // not moving: the next sort sees its current cell
+    return;
+  }
+  const SysInfo &si = L.tab[k];
   Real *V[3] = {(Real *)vb.v[0], (Real *)vb.v[1], (Real *)vb.v[2]};
   Real *Wv[3] = {(Real *)vb.w[0], (Real *)vb.w[1], (Real *)vb.w[2]};
   const Real r = (Real)p.r[i];
-  const Real m = mass_of<Real>(c, r);
+  const Real m = mass_of<Real>(si.c, r);
   const Real I = (Real)0.4 * m * r * r;
   Real v[3] = {V[0][i], V[1][i], V[2][i]};
   Real w[3] = {Wv[0][i], Wv[1][i], Wv[2][i]};
   const Real F[3] = {Fx[i], Fy[i], Fz[i]};
   const Real T[3] = {Tx[i], Ty[i], Tz[i]};
-  half_kick<Real>(c, m, I, F, T, v, w);
+  half_kick<Real>(si.c, m, I, F, T, v, w);
 #pragma unroll
-  for (int k = 0; k < 3; k++) {
-    V[k][i] = v[k];
-    Wv[k][i] = w[k];
+  for (int q = 0; q < 3; q++) {
+    V[q][i] = v[q];
+    Wv[q][i] = w[q];
   }
-  drift_hash(p, i, v, c, g, cell, err);
+  drift_hash(p, i, v, si.c, si.g, cell, err);
 }
 
 // --------------------------------------------------------------------------
@@ -239,6 +260,15 @@ static hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t len, c
   return hipGetLastError();
 }
 
+// exclusive scan with the total in out[len]
+static hipError_t scan_with_total(const int32_t *in, int32_t *out, int64_t len, const ScanScratch &sc,
+                                  hipStream_t st) {
+  hipError_t e = scan_exclusive(in, out, len, sc, 0, st);
+  if (e != hipSuccess) return e;
+  k_scan_total<<<1, 64, 0, st>>>(in, out, len);
+  return hipGetLastError();
+}
+
 int64_t scan_scratch_len(int64_t n, int64_t *lens, int *nlevels) {
   int64_t total = 0;
   int l = 0;
@@ -283,20 +313,22 @@ __global__ __launch_bounds__(kBlock) void k_canon(const int32_t *__restrict__ ce
   }
 }
 
-static unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc,
                        hipStream_t st) {
   k_fill<<<blocks_for(ncell), kBlock, 0, st>>>(counts, ncell, 0);
   if (n > 0) k_count<<<blocks_for(n), kBlock, 0, st>>>(cell, rank, counts, n);
-  hipError_t e = scan_exclusive(counts, cell_start, ncell, sc, 0, st);
+  hipError_t e = scan_with_total(counts, cell_start, ncell, sc, st);
   if (e != hipSuccess) return e;
-  k_scan_total<<<1, 64, 0, st>>>(counts, cell_start, ncell);
   if (n > 0) {
     k_scatter<<<blocks_for(n), kBlock, 0, st>>>(cell, rank, cell_start, perm, n);
     k_canon<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, id_old, perm, ncell);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int32_t *a, int64_t len, int32_t value, hipStream_t st) {
+  if (len > 0) k_fill<<<blocks_for(len), kBlock, 0, st>>>(a, len, value);
   return hipGetLastError();
 }
 
@@ -308,12 +340,13 @@ __device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, d
 }
 
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_reorder(PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
+__global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
-                                                    float4 *__restrict__ xyzr, Grid g, int32_t n) {
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= n) return;
+                                                    float4 *__restrict__ xyzr) {
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  if (s < 0) return;
   const int32_t p = perm[s];
   const double x = src.x[p], y = src.y[p], z = src.z[p];
   const float r = src.r[p];
@@ -322,20 +355,20 @@ __global__ __launch_bounds__(kBlock) void k_reorder(PosBuf src, VelBuf vsrc, Pos
   dst.z[s] = z;
   dst.r[s] = r;
   dst.id[s] = src.id[p];
-  xyzr[s] = make_xyzr(g, x, y, z, r);
+  xyzr[s] = make_xyzr(L.tab[k].g, x, y, z, r);
 #pragma unroll
-  for (int k = 0; k < 3; k++) {
-    ((Real *)vdst.v[k])[s] = ((const Real *)vsrc.v[k])[p];
-    ((Real *)vdst.w[k])[s] = ((const Real *)vsrc.w[k])[p];
+  for (int q = 0; q < 3; q++) {
+    ((Real *)vdst.v[q])[s] = ((const Real *)vsrc.v[q])[p];
+    ((Real *)vdst.w[q])[s] = ((const Real *)vsrc.w[q])[p];
   }
   scell[s] = cell[p];
 }
 
-
-__global__ __launch_bounds__(kBlock) void k_xyzr(PosBuf p, float4 *__restrict__ xyzr, Grid g, int32_t n) {
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= n) return;
-  xyzr[s] = make_xyzr(g, p.x[s], p.y[s], p.z[s], p.r[s]);
+__global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__restrict__ xyzr) {
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  if (s < 0) return;
+  xyzr[s] = make_xyzr(L.tab[k].g, p.x[s], p.y[s], p.z[s], p.r[s]);
 }
 
 // --------------------------------------------------------------------------
@@ -347,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(PosBuf p, float4 *__restrict__ 
 
 constexpr int kSurv = 16;  // LDS survivor slots per lane
 
-// exact FP64 decision on one prefilter survivor (Steps 6-7: the contact test)
+// exact FP64 decision on one prefilter survivor (the contact test of Step 7)
 __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
                                                  float ri, double xi, double yi, double zi, int32_t t,
                                                  int32_t &nf) {
@@ -363,12 +396,13 @@ __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf 
 // lane taking it would hold the whole wave).  A lane whose slots fill up
 // drains them itself, in order.
 __device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
-                                                const float4 p, double xi, double yi, double zi, int32_t beg,
-                                                int32_t end, int32_t *surv, int32_t &ns, int32_t &nf) {
+                                                const float4 p, float eps, double xi, double yi, double zi,
+                                                int32_t beg, int32_t end, int32_t *surv, int32_t &ns,
+                                                int32_t &nf) {
   for (int32_t t = beg; t < end; t++) {
     const float4 q = nb.xyzr[t];
     const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-    const float sf = p.w + q.w + nb.eps;
+    const float sf = p.w + q.w + eps;
     if (dx * dx + dy * dy + dz * dz < sf * sf) {
       if (ns == kSurv) {
         for (int k = 0; k < kSurv; k++) exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[k * kBlock], nf);
@@ -380,48 +414,56 @@ __device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const int32_t *__restrict__ scell,
-                                                   const int32_t *__restrict__ cell_start, Grid g,
-                                                   uint32_t wall_mask, int32_t n, int32_t *err) {
+__global__ __launch_bounds__(kBlock) void k_detect(Layout L, StepCtl ctl, int32_t only_active, PosBuf pos,
+                                                   NbrBuf nb, const int32_t *__restrict__ scell,
+                                                   const int32_t *__restrict__ cell_start, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= n) return;
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  if (s < 0) return;
+  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
+  const SysInfo &si = L.tab[k];
+  const int32_t n = L.n;
   int32_t *surv = surv_all + threadIdx.x;  // slot k at surv[k * kBlock]
   const float4 p = nb.xyzr[s];
+  const float eps = si.eps;
   const double xi = pos.x[s], yi = pos.y[s], zi = pos.z[s];
-  const int32_t nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
-  const int32_t cc = scell[s];
+  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
+  const int32_t c0 = si.g.c0;
+  const int32_t cc = scell[s] - c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
   int32_t nf = 0, ns = 0;
   // own row: the rest of the own cell and the next cell along x
-  const int32_t row0 = (cz * ny + cy) * nx;
-  prefilter_range(nb, pos, n, s, p, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf);
+  const int32_t row0 = c0 + (cz * ny + cy) * nx;
+  prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf);
   // next row along y in the same plane
   if (cy + 1 < ny) {
-    const int32_t row = (cz * ny + cy + 1) * nx;
-    prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns, nf);
+    const int32_t row = c0 + (cz * ny + cy + 1) * nx;
+    prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns,
+                    nf);
   }
   // the three rows of the next plane along z
   if (cz + 1 < nz) {
     for (int32_t dy = -1; dy <= 1; dy++) {
       const int32_t yy = cy + dy;
       if (yy < 0 || yy >= ny) continue;
-      const int32_t row = ((cz + 1) * ny + yy) * nx;
-      prefilter_range(nb, pos, n, s, p, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns,
-                      nf);
+      const int32_t row = c0 + ((cz + 1) * ny + yy) * nx;
+      prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv,
+                      ns, nf);
     }
   }
   // exact tests of the survivors, in slot order
-  for (int32_t k = 0; k < ns; k++) exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[k * kBlock], nf);
+  for (int32_t q = 0; q < ns; q++) exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[q * kBlock], nf);
   // Step 8: walls, particles of infinite radius, after the pairs
+  const uint32_t wall_mask = si.c.wall_mask;
   if (wall_mask) {
     const double xs[3] = {xi, yi, zi};
     const double rid = (double)p.w;
     for (int w = 0; w < 6; w++) {
       if (!((wall_mask >> w) & 1)) continue;
       const int ax = w >> 1;
-      const double gap = (w & 1) ? (g.hi[ax] - xs[ax]) : (xs[ax] - g.lo[ax]);
+      const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
       if (gap < rid) {
         if (nf < kListCap) nb.nb[(int64_t)nf * n + s] = -1 - w;
         nf++;
@@ -433,9 +475,8 @@ __global__ __launch_bounds__(kBlock) void k_detect(PosBuf pos, NbrBuf nb, const 
 }
 
 // The lists become the compact contact array of `gen` (offsets from a scan of
-// the counts); each pair also counts towards its partner's backward list.
-__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PosBuf pos, PairGen gen, PairWork w, int32_t n,
-                                                  int32_t *err) {
+// the counts); each pair also draws its rank in the partner's backward list.
+__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int32_t n, int32_t *err) {
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
   const int32_t cnt = nb.cnt[s];
@@ -447,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PosBuf pos, PairGen
     if (q >= w.Pcap) break;
     gen.s[q] = s;
     gen.t[q] = t;
-    gen.key[q] = t >= 0 ? pos.id[t] : t;
+    gen.key[q] = t;
     if (t >= 0) w.brank[q] = atomicAdd(&w.bcnt[t], 1);
   }
 }
@@ -521,6 +562,26 @@ __device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
       list[j + 1] = v;
     }
   }
+}
+
+hipError_t launch_contacts(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+                           const PairGen &gen, const PairWork &w, const int32_t *scell, const int32_t *cell_start,
+                           const ScanScratch &sc, int32_t *err, hipStream_t st) {
+  const int32_t n = L.n;
+  if (n <= 0) {
+    k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
+    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
+    return hipGetLastError();
+  }
+  StepCtl none{nullptr, nullptr};
+  k_detect<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start, err);
+  hipError_t e = scan_with_total(nb.cnt, gen.ofs, n, sc, st);
+  if (e != hipSuccess) return e;
+  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
+  k_pairs<<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, n, err);
+  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
+  k_bwd<<<2048, kBlock, 0, st>>>(gen, w, n);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
@@ -641,31 +702,63 @@ __device__ __forceinline__ void hist_lookup(const PairGen &old, int64_t cap, int
 }
 
 // One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
-// pair in the canonical orientation (lower particle id first), stored as the
-// force on the owner and n x F_t.
+// pair, seen from the owner (the lower slot), stored as the force on the
+// owner and n x F_t.  The partner receives the exact negation.  In a time
+// step, the contacts of a system that has finished its steps only carry
+// their history forward.
 template <typename Real, int LAW>
 __global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
   using V4 = typename Vec4T<Real>::type;
-  const Consts &c = a.c;
-  const int32_t P = num_pairs(a.cur, a.n, a.w.Pcap);
+  const int32_t P = num_pairs(a.cur, a.L.n, a.w.Pcap);
   const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
   const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
+  const bool stepping = (a.mode & MODE_KICK) != 0;
+  const bool one_sys = a.L.S == 1;
   for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
     const int32_t s = a.cur.s[q], t = a.cur.t[q];
+    const int32_t k = one_sys ? 0 : a.L.psys[s];
+    const SysInfo &si = a.L.tab[k];
+    const Consts &c = si.c;
+    const int32_t ps = old_perm ? a.perm[s] : s;
+    const int32_t pt = t >= 0 ? (old_perm ? a.perm[t] : t) : t;
+    // the previous step filed this contact under its lower slot then, with
+    // delta_t seen from that particle
+    Real h[3];
+    if (LAW != DEM_LAW_SIMPLE) {
+      const bool flip = t >= 0 && ps > pt;
+      hist_lookup<Real>(a.old, a.w.Pcap, flip ? pt : ps, flip ? ps : pt, h);
+      if (flip) {
+        h[0] = -h[0];
+        h[1] = -h[1];
+        h[2] = -h[2];
+      }
+    } else {
+      h[0] = h[1] = h[2] = 0;
+    }
+    if (stepping && !is_active(a.ctl, k)) {
+      // a finished system: its state does not move, its history is kept
+      if (write_hist) {
+        V4 d;
+        d.x = h[0];
+        d.y = h[1];
+        d.z = h[2];
+        d.w = 0;
+        ((V4 *)a.cur.dt)[q] = d;
+      }
+      continue;
+    }
     const double xs = a.pos.x[s], ys = a.pos.y[s], zs = a.pos.z[s];
     const float rsf = a.pos.r[s];
     const Real rs = (Real)rsf;
     const Real ms = mass_of<Real>(c, rs);
     const Real vs[3] = {VI[0][s], VI[1][s], VI[2][s]};
     const Real ws[3] = {WI[0][s], WI[1][s], WI[2][s]};
-    const int32_t ps = old_perm ? a.perm[s] : s;
     LawOut<Real> o;
-    Real n[3], h[3] = {0, 0, 0}, Fown[3], delta, R;
+    Real n[3], delta, R;
     if (t >= 0) {
-      const int32_t ids = a.pos.id[s], idt = a.pos.id[t];
       const double dx = a.pos.x[t] - xs, dy = a.pos.y[t] - ys, dz = a.pos.z[t] - zs;
       const double d2 = dist2_exact(dx, dy, dz);
       const double S = (double)rsf + (double)a.pos.r[t];
@@ -673,56 +766,40 @@ __global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
       const Real vt_[3] = {VI[0][t], VI[1][t], VI[2][t]};
       const Real wt_[3] = {WI[0][t], WI[1][t], WI[2][t]};
       const Real mt = mass_of<Real>(c, rt);
-      const bool low = ids < idt;  // s is the canonical first body
-      const Real ra = low ? rs : rt, rb = low ? rt : rs;
-      const Real ma = low ? ms : mt, mb = low ? mt : ms;
-      const double ex = low ? dx : -dx, ey = low ? dy : -dy, ez = low ? dz : -dz;
       const Real dd = sqrt((Real)d2);
       const Real invd = (Real)1 / dd;
-      n[0] = (Real)ex * invd;
-      n[1] = (Real)ey * invd;
-      n[2] = (Real)ez * invd;
+      n[0] = (Real)dx * invd;
+      n[1] = (Real)dy * invd;
+      n[2] = (Real)dz * invd;
       delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
-      R = ra * rb / (ra + rb);
-      const Real M = ma * mb / (ma + mb);
+      R = rs * rt / (rs + rt);
+      const Real M = ms * mt / (ms + mt);
       Real v[3], spin[3];
 #pragma unroll
-      for (int k = 0; k < 3; k++) {
-        const Real va = low ? vs[k] : vt_[k], vb = low ? vt_[k] : vs[k];
-        const Real wa = low ? ws[k] : wt_[k], wb = low ? wt_[k] : ws[k];
-        v[k] = va - vb;
-        spin[k] = ra * wa + rb * wb;
-      }
-      if (LAW != DEM_LAW_SIMPLE) {
-        // the previous step filed this pair under its lower slot then
-        const int32_t pt = old_perm ? a.perm[t] : t;
-        hist_lookup<Real>(a.old, a.w.Pcap, ps < pt ? ps : pt, ps < pt ? idt : ids, h);
+      for (int i = 0; i < 3; i++) {
+        v[i] = vs[i] - vt_[i];
+        spin[i] = rs * ws[i] + rt * wt_[i];
       }
       contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
-#pragma unroll
-      for (int k = 0; k < 3; k++) Fown[k] = low ? o.F[k] : -o.F[k];
     } else {
       // Step 8: wall -1 - t, a particle of infinite radius
       const int w = -1 - t;
       const int ax = w >> 1;
       const double xw[3] = {xs, ys, zs};
-      const double gap = (w & 1) ? (a.grid.hi[ax] - xw[ax]) : (xw[ax] - a.grid.lo[ax]);
+      const double gap = (w & 1) ? (si.g.hi[ax] - xw[ax]) : (xw[ax] - si.g.lo[ax]);
       n[0] = n[1] = n[2] = 0;
       n[ax] = (w & 1) ? (Real)1 : (Real)-1;
       delta = (Real)((double)rsf - gap);
       R = rs;
       Real spin[3];
 #pragma unroll
-      for (int k = 0; k < 3; k++) spin[k] = rs * ws[k];
-      if (LAW != DEM_LAW_SIMPLE) hist_lookup<Real>(a.old, a.w.Pcap, ps, t, h);
+      for (int i = 0; i < 3; i++) spin[i] = rs * ws[i];
       contact_law<Real, LAW>(c, n, delta, rs, ms, vs, spin, h, o);
-#pragma unroll
-      for (int k = 0; k < 3; k++) Fown[k] = o.F[k];
     }
     V4 f, tq;
-    f.x = Fown[0];
-    f.y = Fown[1];
-    f.z = Fown[2];
+    f.x = o.F[0];
+    f.y = o.F[1];
+    f.z = o.F[2];
     f.w = 0;
     tq.x = n[1] * o.Ft[2] - n[2] * o.Ft[1];
     tq.y = n[2] * o.Ft[0] - n[0] * o.Ft[2];
@@ -747,13 +824,28 @@ __global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
 
 // One lane per particle: contact sums in a fixed order (contacts with lower
 // slots, ascending; with higher slots, ascending; walls), then the closing
-// half kick of Step 1.
+// half kick of Step 1 and, when the system steps again in this call, the
+// next step's opening kick, drift and hash.
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   using V4 = typename Vec4T<Real>::type;
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= a.n) return;
-  const Consts &c = a.c;
+  int32_t k;
+  const int32_t s = block_slot(a.L, k);
+  if (s < 0) return;
+  const SysInfo &si = a.L.tab[k];
+  const Consts &c = si.c;
+  const bool stepping = (a.mode & MODE_KICK) != 0;
+  if (stepping && !is_active(a.ctl, k)) {
+    // a finished system: carry its velocities into the other buffer; the
+    // next sort sees its current cells
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      ((Real *)a.vel_out.v[q])[s] = ((const Real *)a.vel_in.v[q])[s];
+      ((Real *)a.vel_out.w[q])[s] = ((const Real *)a.vel_in.w[q])[s];
+    }
+    a.cell[s] = a.scell[s];
+    return;
+  }
   const int64_t cap = a.w.Pcap;
   const Real rs = (Real)a.pos.r[s];
   const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
@@ -761,8 +853,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   const int32_t b0 = a.w.bofs[s], b1 = a.w.bofs[s + 1];
   const int32_t nb = (int64_t)b1 <= cap ? b1 - b0 : 0;
   sort_list(a.w.bwd + b0, nb);
-  for (int32_t k = 0; k < nb; k++) {
-    const int32_t q = a.w.bwd[b0 + k];
+  for (int32_t i = 0; i < nb; i++) {
+    const int32_t q = a.w.bwd[b0 + i];
     const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
     F[0] -= f.x;
     F[1] -= f.y;
@@ -797,27 +889,29 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
         isfinite((double)T[0]) && isfinite((double)T[1]) && isfinite((double)T[2])))
     raise_err(a.err, ERR_NONFINITE);
 #pragma unroll
-  for (int k = 0; k < 3; k++) {
-    ((Real *)a.F[k])[s] = F[k];
-    ((Real *)a.T[k])[s] = T[k];
+  for (int q = 0; q < 3; q++) {
+    ((Real *)a.F[q])[s] = F[q];
+    ((Real *)a.T[q])[s] = T[q];
   }
-  if (a.mode & MODE_KICK) {
+  if (stepping) {
     const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
     const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
     Real v[3] = {VI[0][s], VI[1][s], VI[2][s]}, w[3] = {WI[0][s], WI[1][s], WI[2][s]};
     const Real m = mass_of<Real>(c, rs);
     const Real I = (Real)0.4 * m * rs * rs;
     half_kick<Real>(c, m, I, F, T, v, w);
-    if (a.mode & MODE_DRIFT) {
+    if (*a.ctl.step + 1 < a.ctl.left[k]) {
       // the next step's Steps 1-2 with the same forces: the same operations
       // as k_kick_drift_hash, so fusing changes no bit
       half_kick<Real>(c, m, I, F, T, v, w);
-      drift_hash(a.pos, s, v, c, a.grid, a.cell, a.err);
+      drift_hash(a.pos, s, v, c, si.g, a.cell, a.err);
+    } else {
+      a.cell[s] = a.scell[s];  // its last step in this call: it stops here
     }
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-      ((Real *)a.vel_out.v[k])[s] = v[k];
-      ((Real *)a.vel_out.w[k])[s] = w[k];
+    for (int q = 0; q < 3; q++) {
+      ((Real *)a.vel_out.v[q])[s] = v[q];
+      ((Real *)a.vel_out.w[q])[s] = w[q];
     }
   }
   if (diag) {
@@ -828,171 +922,146 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   }
 }
 
+__global__ void k_step_end(StepCtl ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctl.step += 1;
+}
+
 // --------------------------------------------------------------------------
-// FP64 diagnostics: per-block partial sums in a fixed tree, then one block
+// FP64 diagnostics: per-block partial sums in a fixed tree (a block holds
+// one system's particles), then per system over its blocks in order
 
 constexpr int kDiag = 10;
 
-int diag_blocks(int32_t n) {
-  int b = (int)((n + kBlock - 1) / kBlock);
-  return b < 1 ? 1 : b;
-}
-
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_diag_partial(PosBuf p, VelBuf vb, DiagBuf d, int32_t n, Consts c,
-                                                         Grid g) {
+__global__ __launch_bounds__(kBlock) void k_diag_partial(Layout L, PosBuf p, VelBuf vb, DiagBuf d) {
   __shared__ double sh[kDiag][kBlock];
   const int tid = threadIdx.x;
-  const int32_t i = blockIdx.x * kBlock + tid;
+  int32_t k;
+  const int32_t i = block_slot(L, k);
+  const SysInfo &si = L.tab[k];
   double t[kDiag];
 #pragma unroll
-  for (int k = 0; k < kDiag; k++) t[k] = 0.0;
-  if (i < n) {
+  for (int q = 0; q < kDiag; q++) t[q] = 0.0;
+  if (i >= 0) {
+    const Consts &c = si.c;
     const double r = (double)p.r[i];
     const double m = c.mass_c * r * r * r;
     const double I = 0.4 * m * r * r;
     double v[3], w[3];
-    for (int k = 0; k < 3; k++) {
-      v[k] = (double)((const Real *)vb.v[k])[i];
-      w[k] = (double)((const Real *)vb.w[k])[i];
+    for (int q = 0; q < 3; q++) {
+      v[q] = (double)((const Real *)vb.v[q])[i];
+      w[q] = (double)((const Real *)vb.w[q])[i];
     }
     const double x[3] = {p.x[i], p.y[i], p.z[i]};
-    for (int k = 0; k < 3; k++) t[k] = m * v[k];
+    for (int q = 0; q < 3; q++) t[q] = m * v[q];
     t[3] = 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     t[4] = 0.5 * I * (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     double pe = 0.0;
-    for (int k = 0; k < 3; k++) pe -= m * c.g[k] * (x[k] - g.lo[k]);
+    for (int q = 0; q < 3; q++) pe -= m * c.g[q] * (x[q] - si.g.lo[q]);
     t[5] = pe;
     t[6] = d.e_el[i];
     t[7] = (double)d.npair[i];
     t[8] = (double)d.nwall[i];
     t[9] = d.dmax[i];
   }
-  for (int k = 0; k < kDiag; k++) sh[k][tid] = t[k];
+  for (int q = 0; q < kDiag; q++) sh[q][tid] = t[q];
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
     if (tid < off) {
-      for (int k = 0; k < 9; k++) sh[k][tid] += sh[k][tid + off];
+      for (int q = 0; q < 9; q++) sh[q][tid] += sh[q][tid + off];
       sh[9][tid] = fmax(sh[9][tid], sh[9][tid + off]);
     }
     __syncthreads();
   }
   if (tid == 0)
-    for (int k = 0; k < kDiag; k++) d.partial[(int64_t)blockIdx.x * kDiag + k] = sh[k][0];
+    for (int q = 0; q < kDiag; q++) d.partial[(int64_t)blockIdx.x * kDiag + q] = sh[q][0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_diag_final(DiagBuf d, int nblocks) {
+// one block per system; a system's blocks are consecutive, in system order
+__global__ __launch_bounds__(kBlock) void k_diag_final(Layout L, DiagBuf d) {
   __shared__ double sh[kDiag][kBlock];
   const int tid = threadIdx.x;
+  const int32_t k = blockIdx.x;
+  const SysInfo &si = L.tab[k];
+  int32_t b0 = 0;
+  for (int32_t j = 0; j < k; j++) b0 += (L.tab[j].n + kBlock - 1) / kBlock;
+  const int32_t nb = (si.n + kBlock - 1) / kBlock;
   double t[kDiag];
-  for (int k = 0; k < kDiag; k++) t[k] = 0.0;
-  for (int b = tid; b < nblocks; b += kBlock) {
-    for (int k = 0; k < 9; k++) t[k] += d.partial[(int64_t)b * kDiag + k];
-    t[9] = fmax(t[9], d.partial[(int64_t)b * kDiag + 9]);
+  for (int q = 0; q < kDiag; q++) t[q] = 0.0;
+  for (int32_t b = tid; b < nb; b += kBlock) {
+    for (int q = 0; q < 9; q++) t[q] += d.partial[(int64_t)(b0 + b) * kDiag + q];
+    t[9] = fmax(t[9], d.partial[(int64_t)(b0 + b) * kDiag + 9]);
   }
-  for (int k = 0; k < kDiag; k++) sh[k][tid] = t[k];
+  for (int q = 0; q < kDiag; q++) sh[q][tid] = t[q];
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
     if (tid < off) {
-      for (int k = 0; k < 9; k++) sh[k][tid] += sh[k][tid + off];
+      for (int q = 0; q < 9; q++) sh[q][tid] += sh[q][tid + off];
       sh[9][tid] = fmax(sh[9][tid], sh[9][tid + off]);
     }
     __syncthreads();
   }
   if (tid == 0)
-    for (int k = 0; k < kDiag; k++) d.out[k] = sh[k][0];
+    for (int q = 0; q < kDiag; q++) d.out[(int64_t)k * kDiag + q] = sh[q][0];
 }
 
 // --------------------------------------------------------------------------
 // launchers
 
-hipError_t launch_hash(const PosBuf &p, int32_t n, const Grid &g, int32_t *cell, int32_t *err, hipStream_t st) {
-  if (n > 0) k_hash<<<blocks_for(n), kBlock, 0, st>>>(p, n, g, cell, err);
+hipError_t launch_hash(const Layout &L, const PosBuf &p, int32_t *cell, int32_t *err, hipStream_t st) {
+  if (L.n > 0) k_hash<<<L.nblocks, kBlock, 0, st>>>(L, p, cell, err);
   return hipGetLastError();
 }
 
-template <typename Real>
-static void kdh_t(const PosBuf &p, const VelBuf &v, void *const F[3], void *const T[3], int32_t n,
-                  const Consts &c, const Grid &g, int32_t *cell, int32_t *err, hipStream_t st) {
-  k_kick_drift_hash<Real><<<blocks_for(n), kBlock, 0, st>>>(p, v, (const Real *)F[0], (const Real *)F[1],
-                                                            (const Real *)F[2], (const Real *)T[0],
-                                                            (const Real *)T[1], (const Real *)T[2], n, c, g,
-                                                            cell, err);
-}
-
-hipError_t launch_kick_drift_hash(int precision, const PosBuf &p, const VelBuf &v, void *const F[3],
-                                  void *const T[3], int32_t n, const Consts &c, const Grid &g, int32_t *cell,
-                                  int32_t *err, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl &ctl, const PosBuf &p,
+                                  const VelBuf &v, void *const F[3], void *const T[3], const int32_t *scell,
+                                  int32_t *cell, int32_t *err, hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    kdh_t<double>(p, v, F, T, n, c, g, cell, err, st);
+    k_kick_drift_hash<double><<<L.nblocks, kBlock, 0, st>>>(
+        L, ctl, p, v, (const double *)F[0], (const double *)F[1], (const double *)F[2], (const double *)T[0],
+        (const double *)T[1], (const double *)T[2], scell, cell, err);
   else
-    kdh_t<float>(p, v, F, T, n, c, g, cell, err, st);
+    k_kick_drift_hash<float><<<L.nblocks, kBlock, 0, st>>>(
+        L, ctl, p, v, (const float *)F[0], (const float *)F[1], (const float *)F[2], (const float *)T[0],
+        (const float *)T[1], (const float *)T[2], scell, cell, err);
   return hipGetLastError();
 }
 
-hipError_t launch_reorder(int precision, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
+hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          float4 *xyzr, const Grid &g, int32_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
+                          float4 *xyzr, hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    k_reorder<double><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, xyzr, g, n);
+    k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, xyzr);
   else
-    k_reorder<float><<<blocks_for(n), kBlock, 0, st>>>(src, vsrc, dst, vdst, perm, cell, scell, xyzr, g, n);
+    k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, xyzr);
   return hipGetLastError();
 }
 
-hipError_t launch_xyzr(const PosBuf &p, float4 *xyzr, const Grid &g, int32_t n, hipStream_t st) {
-  if (n > 0) k_xyzr<<<blocks_for(n), kBlock, 0, st>>>(p, xyzr, g, n);
-  return hipGetLastError();
-}
-
-static hipError_t scan_with_total(const int32_t *in, int32_t *out, int64_t len, const ScanScratch &sc,
-                                  hipStream_t st) {
-  hipError_t e = scan_exclusive(in, out, len, sc, 0, st);
-  if (e != hipSuccess) return e;
-  k_scan_total<<<1, 64, 0, st>>>(in, out, len);
-  return hipGetLastError();
-}
-
-static unsigned pair_blocks() { return 2048; }  // grid-stride over the contacts (count known on device)
-
-hipError_t launch_contacts(const PosBuf &p, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                           const int32_t *scell, const int32_t *cell_start, const Grid &g, uint32_t wall_mask,
-                           int32_t n, const ScanScratch &sc, int32_t *err, hipStream_t st) {
-  if (n <= 0) {
-    k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
-    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
-    return hipGetLastError();
-  }
-  k_detect<<<blocks_for(n), kBlock, 0, st>>>(p, nb, scell, cell_start, g, wall_mask, n, err);
-  hipError_t e = scan_with_total(nb.cnt, gen.ofs, n, sc, st);
-  if (e != hipSuccess) return e;
-  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
-  k_pairs<<<blocks_for(n), kBlock, 0, st>>>(nb, p, gen, w, n, err);
-  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
-  k_bwd<<<pair_blocks(), kBlock, 0, st>>>(gen, w, n);
+hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st) {
+  if (L.n > 0) k_xyzr<<<L.nblocks, kBlock, 0, st>>>(L, p, xyzr);
   return hipGetLastError();
 }
 
 template <typename Real>
 static void forces_t(const PairArgs &a, hipStream_t st) {
-  switch (a.c.law) {
+  switch (a.law) {
     case DEM_LAW_HERTZ:
-      k_pair_force<Real, DEM_LAW_HERTZ><<<pair_blocks(), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
       break;
     case DEM_LAW_SIMPLE:
-      k_pair_force<Real, DEM_LAW_SIMPLE><<<pair_blocks(), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
       break;
     default:
-      k_pair_force<Real, DEM_LAW_LINEAR><<<pair_blocks(), kBlock, 0, st>>>(a);
+      k_pair_force<Real, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
       break;
   }
-  k_gather<Real><<<blocks_for(a.n), kBlock, 0, st>>>(a);
+  k_gather<Real><<<a.L.nblocks, kBlock, 0, st>>>(a);
 }
 
 hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
+  if (a.L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
     forces_t<double>(a, st);
   else
@@ -1000,14 +1069,20 @@ hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_diag_reduce(int precision, const PosBuf &p, const VelBuf &v, const DiagBuf &d, int32_t n,
-                              const Consts &c, const Grid &g, hipStream_t st) {
-  const int nb = diag_blocks(n);
-  if (precision == DEM_PREC_FP64)
-    k_diag_partial<double><<<nb, kBlock, 0, st>>>(p, v, d, n, c, g);
-  else
-    k_diag_partial<float><<<nb, kBlock, 0, st>>>(p, v, d, n, c, g);
-  k_diag_final<<<1, kBlock, 0, st>>>(d, nb);
+hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st) {
+  k_step_end<<<1, 64, 0, st>>>(ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,
+                              hipStream_t st) {
+  if (L.n > 0) {
+    if (precision == DEM_PREC_FP64)
+      k_diag_partial<double><<<L.nblocks, kBlock, 0, st>>>(L, p, v, d);
+    else
+      k_diag_partial<float><<<L.nblocks, kBlock, 0, st>>>(L, p, v, d);
+  }
+  k_diag_final<<<L.S, kBlock, 0, st>>>(L, d);
   return hipGetLastError();
 }
 

@@ -77,8 +77,20 @@ def lib():
             "dem_set_radii": ([P, P], st),
             "dem_profile": ([P, C.c_int], st),
             "dem_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(I64)], st),
+            "dem_use_graph": ([P, C.c_int], st),
             "dem_destroy": ([P], st),
             "dem_status_string": ([st], C.c_char_p),
+            "dem_batch_workspace_bytes": ([C.c_int32, P, P, C.POINTER(S)], st),
+            "dem_batch_create": ([C.c_int32, P, P, P, P, P, P, P, S, P, C.POINTER(P)], st),
+            "dem_batch_step": ([P, P], st),
+            "dem_batch_read_state": ([P, C.c_int32, P, P, P, P, P], st),
+            "dem_batch_read_contacts": ([P, C.c_int32, I64, C.POINTER(I64), P, P], st),
+            "dem_batch_diagnostics": ([P, P], st),
+            "dem_batch_use_graph": ([P, C.c_int], st),
+            "dem_batch_profile": ([P, C.c_int], st),
+            "dem_batch_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(I64)], st),
+            "dem_batch_sync": ([P], st),
+            "dem_batch_destroy": ([P], st),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -240,6 +252,10 @@ class System:
             raise ValueError("set_radii: one radius per particle")
         _check(lib().dem_set_radii(self.handle, _ptr(r)), "dem_set_radii")
 
+    def use_graph(self, enable: bool = True):
+        """Replay each time step from a HIP graph (needs a non-default stream)."""
+        _check(lib().dem_use_graph(self.handle, int(bool(enable))), "dem_use_graph")
+
     def profile(self, enable: bool = True):
         _check(lib().dem_profile(self.handle, int(bool(enable))), "dem_profile")
 
@@ -249,6 +265,123 @@ class System:
         ms = (C.c_double * NUM_PHASES)()
         n = C.c_int64()
         _check(lib().dem_profile_read(self.handle, ms, C.byref(n)), "dem_profile_read")
+        return np.array(ms[:]), n.value
+
+
+def _params_array(params_list):
+    arr = (DemParams * len(params_list))()
+    for k, p in enumerate(params_list):
+        arr[k] = make_params(p)
+    return arr
+
+
+def dem_batch_workspace_bytes(params_list, ns) -> int:
+    b = C.c_size_t()
+    n = np.ascontiguousarray(np.asarray(ns, dtype=np.int64).reshape(-1))
+    if n.shape[0] != len(params_list):
+        raise ValueError("one particle count per system")
+    _check(lib().dem_batch_workspace_bytes(len(params_list), _params_array(params_list), _ptr(n), C.byref(b)),
+           "dem_batch_workspace_bytes")
+    return b.value
+
+
+class Batch:
+    """Several independent systems stepped by one launch sequence: the handle
+    of ``dem_batch_create`` plus its torch workspace and its own stream.
+
+    ``systems`` is a list of dicts with keys params, x, v, omega, r (one
+    system each; ids are local to the system).  All systems share the
+    contact law and the precision."""
+
+    def __init__(self, systems, device="cuda", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdem needs a GPU: torch.cuda.is_available() is False")
+        L = lib()
+        if len(systems) == 0:
+            raise ValueError("a batch holds at least one system")
+        rs = [np.ascontiguousarray(np.asarray(s["r"], dtype=np.float64).reshape(-1)) for s in systems]
+        self.ns = [int(r.shape[0]) for r in rs]
+        self.S = len(systems)
+        self.params = [dict(s["params"]) for s in systems]
+        cat3 = lambda key: np.ascontiguousarray(np.concatenate(
+            [_d3(s[key], n) for s, n in zip(systems, self.ns)]) if sum(self.ns) else np.zeros((0, 3)))
+        x, v, w = cat3("x"), cat3("v"), cat3("omega")
+        r = np.ascontiguousarray(np.concatenate(rs))
+        n = np.asarray(self.ns, dtype=np.int64)
+        self.device = torch.device(device)
+        nbytes = dem_batch_workspace_bytes(self.params, n)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.device)
+            stream.wait_stream(torch.cuda.current_stream(self.device))
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.dem_batch_create(self.S, _params_array(self.params), _ptr(n), _ptr(x), _ptr(v), _ptr(w), _ptr(r),
+                                  C.c_void_p(self.workspace.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream),
+                                  C.byref(h)), "dem_batch_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            self._h = None
+            _LIB.dem_batch_destroy(h)
+
+    __del__ = close
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise DemError(DEM_E_STATE, "batch")
+        return self._h
+
+    def step(self, steps):
+        """Advance system k by steps[k] (an int applies to every system)."""
+        if np.isscalar(steps):
+            steps = [int(steps)] * self.S
+        s = np.ascontiguousarray(np.asarray(steps, dtype=np.int64).reshape(-1))
+        if s.shape[0] != self.S:
+            raise ValueError("one step count per system")
+        _check(lib().dem_batch_step(self.handle, _ptr(s)), "dem_batch_step")
+
+    def sync(self):
+        _check(lib().dem_batch_sync(self.handle), "dem_batch_sync")
+
+    def use_graph(self, enable: bool = True):
+        _check(lib().dem_batch_use_graph(self.handle, int(bool(enable))), "dem_batch_use_graph")
+
+    def read_state(self, k: int):
+        n = self.ns[k]
+        out = [np.zeros((n, 3)) for _ in range(5)]
+        _check(lib().dem_batch_read_state(self.handle, int(k), *[_ptr(a) for a in out]), "dem_batch_read_state")
+        x, v, w, F, T = out
+        return {"x": x, "v": v, "omega": w, "F": F, "T": T}
+
+    def read_contacts(self, k: int):
+        n = C.c_int64()
+        st = lib().dem_batch_read_contacts(self.handle, int(k), 0, C.byref(n), None, None)
+        if st not in (DEM_OK, DEM_E_CAPACITY):
+            _check(st, "dem_batch_read_contacts")
+        pairs = np.zeros((max(n.value, 1), 2), dtype=np.int64)
+        dt = np.zeros((max(n.value, 1), 3))
+        _check(lib().dem_batch_read_contacts(self.handle, int(k), n.value, C.byref(n), _ptr(pairs), _ptr(dt)),
+               "dem_batch_read_contacts")
+        return pairs[: n.value], dt[: n.value]
+
+    def diagnostics(self):
+        out = np.zeros((self.S, 10))
+        _check(lib().dem_batch_diagnostics(self.handle, _ptr(out)), "dem_batch_diagnostics")
+        return out
+
+    def profile(self, enable: bool = True):
+        _check(lib().dem_batch_profile(self.handle, int(bool(enable))), "dem_batch_profile")
+
+    def profile_read(self):
+        ms = (C.c_double * NUM_PHASES)()
+        n = C.c_int64()
+        _check(lib().dem_batch_profile_read(self.handle, ms, C.byref(n)), "dem_batch_profile_read")
         return np.array(ms[:]), n.value
 
 

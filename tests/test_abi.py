@@ -68,7 +68,7 @@ def test_workspace_bytes_and_validation_on_host(L):
         dem.dem_workspace_bytes(dict(p, restitution=1.5), 10)
     with pytest.raises(dem.DemError):
         dem.dem_workspace_bytes(p, -1)
-    assert L.dem_status_string(-3) == b"contact history table overflow"
+    assert L.dem_status_string(-3) == b"contact list overflow"
 
 
 def test_create_rejects_bad_input_before_touching_the_gpu(L):
