@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the DEM step (practical contact model, linear law) on one GPU.
 
-Workload (default): the dense granular bed -- 2^24 = 16,777,216 spheres with
+Headline workload: the dense granular bed -- 2^24 = 16,777,216 spheres with
 log-normal radii (median 1/512, sigma 0.2, clipped to +-3 sigma) at packing
 fraction 0.55 in a walled 4:1:1 box, gravity along the short axis, FP32 forces
 with FP64 positions, dt = t_c,min / 10.  The bed is prepared untimed (radius
@@ -9,13 +9,24 @@ growth in the lower 93% of the box, then quenched relaxation under gravity;
 see paper_1301_1714_amd/prepare.py); the timed steps run with kn = 1e5,
 e = 0.9, kt = 2/7 kn, mu = 0.3.
 
-Prints one JSON line: particle-steps/s over the timed steps, the roofline of
-the dominant kernel (timed live with HIP events on the library's stream) and
-the FP64 CPU oracle timed on a bounded sample of the same recipe.
+Also measured (unless skipped):
+  batched  256 independent systems (sizes log-uniform in [1k, 256k], materials
+           and packing fractions drawn per system), cells from the autotuner,
+           all stepped together with graph replay, 1,000 steps each; against
+           the same systems run one at a time through the plain path.
+  serving  requests (sizes log-uniform in [1k, 1M], steps in [100, 1e4]) with
+           Poisson arrivals at 70% of the one-at-a-time server's capacity,
+           served by the continuous-batching loop; p50/p99 completion latency
+           and throughput against the one-at-a-time FIFO baseline on the same
+           arrivals, and a check that every served result is bit-identical.
+
+Prints one JSON line: particle-steps/s of the dense bed, the roofline of its
+dominant kernel (timed live with HIP events on the library's stream), the
+per-phase times, the batched and serving results, and the FP64 CPU oracle
+timed on a bounded sample of the dense-bed recipe.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,37 +38,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (practical model) at 16M"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "force")
-FILL_HEIGHT = 0.93  # the prepared bed fills the lower 93% of the box
+FILL_HEIGHT = 0.93     # the prepared bed fills the lower 93% of the box
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def force_kernel_bytes(n, ncell, z_own, real_bytes):
-    """Algorithmic HBM bytes of one force-sweep launch: every particle's own
-    state read once (x, y, z FP64; r FP32; id, perm, cell int32; v, w Real),
-    its forces, torques and kicked v, w written once, its history row (count
-    plus z_own owned entries of partner id + 3 Real) read and written once,
-    and the cell starts read once.  Neighbour data is reuse (LDS / cache)."""
-    R = real_bytes
-    own = 24 + 4 + 4 + 4 + 4 + 6 * R
-    out = 12 * R
-    hist = 2 * (4 + z_own * (4 + 3 * R))
-    return n * (own + out + hist) + 4 * (ncell + 1)
+# ------------------------------------------------------------ byte models
+# Algorithmic bytes: what a kernel must move at least, each item once per
+# launch; neighbour data reused from LDS or cache is not counted.  R is the
+# size of a Real (4 with FP32 forces, 8 in FP64).
+
+def detect_bytes(n, ncell, c_own):
+    """k_detect: per particle its FP32 copy (x, y, z, r: 16 B), its FP64
+    position (24 B) and cell (4 B) read, its count (4 B) and c_own list
+    entries (4 B each) written; the cell starts read once."""
+    return n * (48 + 4 * c_own) + 4 * (ncell + 1)
 
 
-def step_algorithmic_bytes(n, z, real_bytes):
+def pair_force_bytes(n, P, R):
+    """k_pair_force: per contact its two slots (8 B), the history key (4 B),
+    delta_t read and written (2 x 3R) and the force and torque term written
+    (6R); per particle its state read once (x 24 B, r 4 B, v and w 6R), its
+    old slot (4 B) and its old history offsets (8 B)."""
+    return P * (12 + 12 * R) + n * (40 + 6 * R)
+
+
+def step_algorithmic_bytes(n, z, R):
     """Minimum HBM bytes of a whole step per the method: the particle state
-    read and written once (x 24 B, v and w 6 Real, r 4, id 4), cell id and
+    read and written once (x 24 B, v and w 6R, r 4, id 4), cell id and
     permutation written and read (16 B), cell starts (about 3 B), and the
     tangential history of the Z/2 pairs of each particle read and written
-    (Z/2 x (4 + 3 Real) x 2)."""
-    R = real_bytes
+    (Z/2 x (4 + 3R) x 2)."""
     state = 24 + 6 * R + 4 + 4
     return n * (2 * state + 16 + 3 + z * (4 + 3 * R))
 
+
+# ------------------------------------------------------------ CPU oracle
 
 def cpu_baseline(target_seconds):
     """The FP64 oracle, single-threaded, on 2^15 spheres of the same recipe
@@ -82,29 +100,14 @@ def cpu_baseline(target_seconds):
                       f"{k} steps, {dt:.1f} s, FP64, single thread"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=1 << 24, help="particles (default 2^24)")
-    ap.add_argument("--seed", type=int, default=3000)
-    ap.add_argument("--cache", default=None, help="npz file holding the prepared bed (written if missing)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
+# ------------------------------------------------------------ dense bed
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU slab decomposition is a "
-                                   "design, not built (run with --gpus 1)"}))
-        sys.exit(2)
-
+def bench_dense(args):
     import torch
 
     from paper_1301_1714_amd import dem, prepare
     from paper_1301_1714_amd import workloads as W
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.time()
     w = W.dense_bed_lattice(seed=args.seed, n=args.n, fill_height=FILL_HEIGHT)
     log(f"[bench] generated {args.n} spheres in {time.time() - t0:.1f}s; box {w['params']['box_hi']}")
@@ -133,33 +136,211 @@ def main():
     elapsed = time.perf_counter() - t0
     ms, timed = s.profile_read()
     d1 = s.diagnostics()
+    s.close()
     n = args.n
     value = n * args.steps / elapsed
     ms_per_step = elapsed * 1e3 / args.steps
-    phase_ms = {ph: float(ms[i] / max(timed, 1)) for i, ph in enumerate(PHASES)}
-    z_own = 0.5 * (d0[7] + d1[7]) / n + 0.5 * (d0[8] + d1[8]) / n
-    Z = 2.0 * 0.5 * (d0[7] + d1[7]) / n
-    real = 4 if p["precision"] == "mixed" else 8
-    fb = force_kernel_bytes(n, ncell, z_own, real)
-    f_ms = phase_ms["force"]
-    roof = {"kernel": "k_force (Steps 5-8)", "bound": "hbm", "achieved": fb / (f_ms * 1e-3) / 1e9,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None,
-            "bytes_per_launch": fb, "avg_ms": f_ms}
+    phase_ms = {ph: float(ms[i] / max(timed, 1)) for i, ph in enumerate(dem.PHASES)}
+    # contacts owned per particle (pairs once, walls) and coordination number
+    pairs = 0.5 * (d0[7] + d1[7])
+    walls = 0.5 * (d0[8] + d1[8])
+    P = pairs + walls
+    Z = 2.0 * pairs / n
+    R = 4 if p["precision"] == "mixed" else 8
+    kernels = {
+        "k_detect": ("detect", detect_bytes(n, ncell, P / n)),
+        "k_pair_force": ("pair_force", pair_force_bytes(n, P, R)),
+    }
+    name = max(kernels, key=lambda k: phase_ms[kernels[k][0]])
+    ph, nbytes = kernels[name]
+    avg = phase_ms[ph]
+    roof = {"kernel": name, "bound": "hbm", "achieved": nbytes / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "traffic": None, "bytes_per_launch": nbytes, "avg_ms": avg}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    sb = step_algorithmic_bytes(n, Z, real)
+    others = {k: {"avg_ms": phase_ms[v[0]], "bytes_per_launch": v[1],
+                  "achieved_GBs": v[1] / (phase_ms[v[0]] * 1e-3) / 1e9} for k, v in kernels.items()}
+    sb = step_algorithmic_bytes(n, Z, R)
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 forces, f64 positions", "data": "synthetic",
         "config": {"workload": f"dense_bed_{n}", "n_particles": n, "law": p["law"], "precision": p["precision"],
                    "phi": 0.55, "box": list(p["box_hi"]), "dt": p["dt"], "cell": p["cell_size"],
-                   "grid": list(dims), "Z": Z, "prep": prep},
+                   "grid": list(dims), "Z": Z, "contacts_per_particle": P / n, "prep": prep},
         "roofline": roof,
+        "kernels": others,
         "phases_ms": phase_ms,
         "step_hbm": {"algorithmic_bytes_per_step": sb, "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9,
                      "frac": sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
-    if not args.no_cpu_baseline:
+    return out
+
+
+# ------------------------------------------------------------ batched
+
+def bench_batched(args):
+    import torch
+
+    from paper_1301_1714_amd import autotune, dem
+    from paper_1301_1714_amd import workloads as W
+
+    draws = W.batched_draws(seed=args.batch_seed, count=args.batch_systems)
+    t0 = time.time()
+    table = autotune.Table.load(args.tune_cache)
+    keys = [autotune.system_class(d["n"], d["phi"]) for d in draws]
+    table = autotune.tune(keys, table, steps=20, log=log)
+    table.save(args.tune_cache)
+    t_tune = time.time() - t0
+    factors = autotune.factors_for(draws, table)
+    t0 = time.time()
+    systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors)
+    ns = np.array([len(s["r"]) for s in systems])
+    log(f"[bench] batched: {len(systems)} systems, {ns.sum()} spheres, generated in {time.time() - t0:.1f}s, "
+        f"tuned in {t_tune:.1f}s")
+    b = dem.Batch(systems)
+    b.use_graph(True)
+    b.step(10)
+    b.sync()
+    b.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.batch_steps)
+    b.sync()
+    elapsed = time.perf_counter() - t0
+    ms, timed = b.profile_read()
+    diag = b.diagnostics()
+    b.close()
+    del b
+    work = float(ns.sum()) * args.batch_steps
+    batched_rate = work / elapsed
+    # the same systems one at a time through the plain single-system path
+    t_plain = 0.0
+    for s in systems:
+        one = dem.System(s["params"], s["x"], s["v"], s["omega"], s["r"])
+        one.step(2)
+        one.sync()
+        t0 = time.perf_counter()
+        one.step(args.plain_steps)
+        one.sync()
+        t_plain += time.perf_counter() - t0
+        one.close()
+    plain_rate = float(ns.sum()) * args.plain_steps / t_plain
+    fac, cnt = np.unique(factors, return_counts=True)
+    return {
+        "workload": f"batched_{len(systems)}_systems", "systems": len(systems), "n_total": int(ns.sum()),
+        "n_min": int(ns.min()), "n_max": int(ns.max()), "steps": args.batch_steps,
+        "value": batched_rate, "unit": "particle-steps/s", "ms_per_step": elapsed * 1e3 / args.batch_steps,
+        "graph": True, "plain_one_at_a_time": {"value": plain_rate, "unit": "particle-steps/s",
+                                              "steps_per_system": args.plain_steps},
+        "speedup_vs_plain": batched_rate / plain_rate,
+        "cell_factors": {str(f): int(c) for f, c in zip(fac, cnt)},
+        "Z_mean": float(2.0 * diag[:, 7].sum() / ns.sum()),
+        "tune_seconds": t_tune,
+    }
+
+
+# ------------------------------------------------------------ serving
+
+def bench_serving(args):
+    import torch
+
+    from paper_1301_1714_amd import serve
+    from paper_1301_1714_amd import workloads as W
+
+    specs = W.serving_requests(seed=args.serve_seed, count=args.serve_requests)
+    t0 = time.time()
+    systems = [W.unit_box_system(d["seed"], d["n"], d["kn"], d["restitution"], d["mu"], d["phi"]) for d in specs]
+    log(f"[bench] serving: {len(specs)} requests, {sum(d['n'] for d in specs)} spheres, "
+        f"{sum(d['n'] * d['steps'] for d in specs):.3e} particle-steps, generated in {time.time() - t0:.1f}s")
+    ex = serve.GpuExecutor(use_graph=True)
+    # one at a time, plain path: measured service times (create, step, read back)
+    ex.run_alone(systems[0], 5)  # warm the code paths
+    ref = []
+    service = []
+    for d, s in zip(specs, systems):
+        t0 = time.perf_counter()
+        st = ex.run_alone(s, d["steps"])
+        service.append(time.perf_counter() - t0)
+        ref.append(st["x"])
+    service = np.array(service)
+    work = np.array([d["n"] * d["steps"] for d in specs], dtype=float)
+    plain_rate = work.sum() / service.sum()
+    rate = serve.rate_for_load(args.serve_load, plain_rate, work.mean())
+    arrivals = W.poisson_arrivals(args.serve_seed, len(specs), rate)
+    base_lat = serve.fifo_latencies(arrivals, service)
+    base_span = max(arrivals[k] + base_lat[k] for k in range(len(specs))) - arrivals[0]
+    log(f"[bench] serving: one-at-a-time busy {service.sum():.1f}s; arrival rate {rate:.3f}/s")
+    reqs = [serve.Request(k, s, d["steps"], a) for k, (d, s, a) in enumerate(zip(specs, systems, arrivals))]
+    torch.cuda.empty_cache()
+    budget = int(args.serve_hbm_frac * ex.free_bytes())
+    srv = serve.Server(ex, hbm_budget=budget, max_slots=args.serve_slots, chunk=args.serve_chunk)
+    done = srv.run(reqs)
+    by_id = {r.rid: r for r in done}
+    identical = all(by_id[k].error is None and np.array_equal(by_id[k].result["x"], ref[k])
+                    for k in range(len(specs)))
+    lat = np.array([by_id[k].latency for k in range(len(specs))])
+    span = max(by_id[k].t_done for k in range(len(specs))) - arrivals[0]
+    return {
+        "workload": f"serving_{len(specs)}_requests", "requests": len(specs),
+        "arrival_rate_per_s": rate, "load_vs_one_at_a_time": args.serve_load,
+        "served": {**serve.percentiles(lat), "throughput": work.sum() / span, "unit_latency": "s",
+                   "unit_throughput": "particle-steps/s", "peak_slots": srv.peak_slots,
+                   "peak_bytes": srv.peak_bytes, "iterations": srv.iterations, "chunk_steps": args.serve_chunk},
+        "one_at_a_time": {**serve.percentiles(base_lat), "throughput": work.sum() / base_span,
+                          "busy_throughput": plain_rate, "unit_latency": "s"},
+        "results_bit_identical_to_alone": bool(identical),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1 << 24, help="particles of the dense bed (default 2^24)")
+    ap.add_argument("--seed", type=int, default=3000)
+    ap.add_argument("--cache", default=None, help="npz file holding the prepared bed (written if missing)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-systems", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-seed", type=int, default=4000)
+    ap.add_argument("--plain-steps", type=int, default=50)
+    ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache",
+                                                         "paper_1301_1714_amd", "autotune.json"))
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-seed", type=int, default=5000)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--serve-hbm-frac", type=float, default=0.8)
+    ap.add_argument("--only-dense", action="store_true", help="skip batched, serving and the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: multi-GPU runs are a design, not "
+                                   "built (run with --gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1301_1714_amd import dem
+    dem.lib()
+    out = bench_dense(args)
+    log(f"[bench] dense bed: {out['value']:.4g} particle-steps/s, {out['ms_per_step']:.3f} ms/step")
+    if not (args.no_batched or args.only_dense):
+        out["batched"] = bench_batched(args)
+        log(f"[bench] batched: {out['batched']['value']:.4g} particle-steps/s "
+            f"({out['batched']['speedup_vs_plain']:.2f}x plain)")
+    if not (args.no_serve or args.only_dense):
+        out["serving"] = bench_serving(args)
+        sv = out["serving"]
+        log(f"[bench] serving: p50 {sv['served']['p50']:.3f}s p99 {sv['served']['p99']:.3f}s vs one at a time "
+            f"p50 {sv['one_at_a_time']['p50']:.3f}s p99 {sv['one_at_a_time']['p99']:.3f}s")
+    if not (args.no_cpu_baseline or args.only_dense):
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -163,11 +163,15 @@ dem_status dem_set_radii(dem_system *s, const double *r);
  * phases with HIP events on the system's stream; dem_profile_read waits for
  * the stream, returns the milliseconds spent in each phase summed over the
  * steps timed since the previous read (and their number), then clears them.
- * Phases: 0 kick-drift-hash (Steps 1-2), 1 sort and cell starts (Step 3),
- * 2 reorder (Step 4), 3 contact detection over the 27 cells (Steps 5-6),
- * 4 contact forces and closing kick (Steps 7-8).  At most
- * DEM_PROFILE_CAPACITY steps are timed between two reads. */
-#define DEM_NUM_PHASES 5
+ * Phases: 0 kick-drift-hash of a call's first step (Steps 1-2; later steps
+ * do it inside phase 6), 1 sort and cell starts (Step 3), 2 reorder
+ * (Step 4), 3 contact detection over the neighbouring cells (Steps 5-6),
+ * 4 compact contact list and its backward index, 5 contact law once per
+ * contact (Steps 7-8), 6 per-particle sums, closing kick and the next
+ * step's kick-drift-hash.  Phase 3 and phase 5 are one kernel each.  With
+ * graph replay the whole step after phase 0 is counted in phase 6.  At
+ * most DEM_PROFILE_CAPACITY steps are timed between two reads. */
+#define DEM_NUM_PHASES 7
 #define DEM_PROFILE_CAPACITY 4096
 dem_status dem_profile(dem_system *s, int enable);
 dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps);

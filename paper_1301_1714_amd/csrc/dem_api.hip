@@ -350,10 +350,21 @@ void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, s
 
 // Steps 5-6 on the current positions into generation g (with ctl only the
 // systems still stepping detect again; the others keep their lists)
-hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl) {
+hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after_detect = nullptr) {
   e.gs = g;
-  return launch_contacts(e.layout(), ctl, e.pos[e.cp], e.nbr, e.gen[g], e.work, e.scell, e.cell_start, e.scan,
-                         e.err, e.stream);
+  const Layout L = e.layout();
+  hipError_t r = launch_detect(L, ctl, e.pos[e.cp], e.nbr, e.scell, e.cell_start, e.err, e.stream);
+  if (r != hipSuccess) return r;
+  if (after_detect) (void)hipEventRecord(after_detect, e.stream);
+  return launch_list(L, e.nbr, e.gen[g], e.work, e.scan, e.err, e.stream);
+}
+
+// Steps 7-8 then the per-particle sums (and, in a time step, the kicks)
+hipError_t run_forces(Engine &e, const PairArgs &a, hipEvent_t after_law = nullptr) {
+  hipError_t r = launch_pair_force(e.prec, a, e.stream);
+  if (r != hipSuccess) return r;
+  if (after_law) (void)hipEventRecord(after_law, e.stream);
+  return launch_gather(e.prec, a, e.stream);
 }
 
 // Steps 7-8 on the contact list of generation gs, with the committed history
@@ -600,7 +611,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
     }
   } else {
     PairArgs a = pair_args(e, 0, e.F, e.T);
-    HIP_TRY(launch_forces(e.prec, a, e.stream));
+    HIP_TRY(run_forces(e, a));
   }
   return sync_and_check(e);
 }
@@ -657,13 +668,13 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   e.cv ^= 1;
   mark(3);
   // Steps 5-6 into the generation that does not hold the committed history
-  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl)) != hipSuccess) return r;
-  mark(4);
+  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl, ev ? ev[4] : nullptr)) != hipSuccess) return r;
+  mark(5);
   // Steps 7-8 and the closing half kick; the new history is committed
   PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);
-  if ((r = launch_forces(e.prec, a, e.stream)) != hipSuccess) return r;
+  if ((r = run_forces(e, a, ev ? ev[6] : nullptr)) != hipSuccess) return r;
   if ((r = launch_step_end(e.ctl, e.stream)) != hipSuccess) return r;
-  mark(5);
+  mark(7);
   e.cv ^= 1;
   e.gc = e.gs;
   return hipSuccess;
@@ -741,12 +752,12 @@ dem_status engine_step(Engine &e, const int64_t *steps) {
         if (st != DEM_OK) return e.sticky = st;
       }
       if (ev)
-        for (int p = 2; p <= 4; p++) (void)hipEventRecord(ev[p], e.stream);
+        for (int p = 2; p < DEM_NUM_PHASES; p++) (void)hipEventRecord(ev[p], e.stream);
       if (hipGraphLaunch(e.gexec[par], e.stream) != hipSuccess) {
         (void)hipGetLastError();
         return e.sticky = DEM_E_HIP;
       }
-      if (ev) (void)hipEventRecord(ev[5], e.stream);
+      if (ev) (void)hipEventRecord(ev[DEM_NUM_PHASES], e.stream);
       // what the replayed body does to the buffer indices (cv comes back)
       e.cp ^= 1;
       e.gs = e.gc ^ 1;
@@ -771,7 +782,7 @@ dem_status engine_forces(Engine &e, double *F, double *T) {
   dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, 0, e.Fe, e.Te);
-  if (launch_forces(e.prec, a, e.stream) != hipSuccess) {
+  if (run_forces(e, a) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;
   }
@@ -845,7 +856,7 @@ dem_status engine_diagnostics(Engine &e, double *out) {
   dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, MODE_DIAG, e.Fe, e.Te);
-  if (launch_forces(e.prec, a, e.stream) != hipSuccess ||
+  if (run_forces(e, a) != hipSuccess ||
       launch_diag_reduce(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.diag, e.stream) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;

@@ -173,12 +173,14 @@ hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, con
                           float4 *xyzr, hipStream_t st);
 hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st);
 // Steps 5-6: detection (all systems, or with ctl only the active ones; the
-// others keep their lists) and the compact contact list of `gen`
-hipError_t launch_contacts(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
-                           const PairGen &gen, const PairWork &w, const int32_t *scell, const int32_t *cell_start,
-                           const ScanScratch &sc, int32_t *err, hipStream_t st);
-// Steps 7-8: contact forces on the list of a.cur, per-particle sums, kick
-hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st);
+// others keep their lists), then the compact contact list of `gen`
+hipError_t launch_detect(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+                         const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st);
+hipError_t launch_list(const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                       const ScanScratch &sc, int32_t *err, hipStream_t st);
+// Steps 7-8: the law once per contact of a.cur, then per-particle sums and kick
+hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st);
+hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st);
 hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,
                               hipStream_t st);

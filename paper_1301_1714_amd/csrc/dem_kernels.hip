@@ -564,17 +564,22 @@ __device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
   }
 }
 
-hipError_t launch_contacts(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
-                           const PairGen &gen, const PairWork &w, const int32_t *scell, const int32_t *cell_start,
-                           const ScanScratch &sc, int32_t *err, hipStream_t st) {
+hipError_t launch_detect(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+                         const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
+  StepCtl none{nullptr, nullptr};
+  k_detect<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_list(const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                       const ScanScratch &sc, int32_t *err, hipStream_t st) {
   const int32_t n = L.n;
   if (n <= 0) {
     k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
     k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
     return hipGetLastError();
   }
-  StepCtl none{nullptr, nullptr};
-  k_detect<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start, err);
   hipError_t e = scan_with_total(nb.cnt, gen.ofs, n, sc, st);
   if (e != hipSuccess) return e;
   k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
@@ -1044,28 +1049,38 @@ hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream
   return hipGetLastError();
 }
 
-template <typename Real>
-static void forces_t(const PairArgs &a, hipStream_t st) {
+hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st) {
+  if (a.L.n <= 0) return hipSuccess;
+  const bool f64 = precision == DEM_PREC_FP64;
   switch (a.law) {
     case DEM_LAW_HERTZ:
-      k_pair_force<Real, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
+      if (f64)
+        k_pair_force<double, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
+      else
+        k_pair_force<float, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
       break;
     case DEM_LAW_SIMPLE:
-      k_pair_force<Real, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
+      if (f64)
+        k_pair_force<double, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
+      else
+        k_pair_force<float, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
       break;
     default:
-      k_pair_force<Real, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
+      if (f64)
+        k_pair_force<double, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
+      else
+        k_pair_force<float, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
       break;
   }
-  k_gather<Real><<<a.L.nblocks, kBlock, 0, st>>>(a);
+  return hipGetLastError();
 }
 
-hipError_t launch_forces(int precision, const PairArgs &a, hipStream_t st) {
+hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st) {
   if (a.L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    forces_t<double>(a, st);
+    k_gather<double><<<a.L.nblocks, kBlock, 0, st>>>(a);
   else
-    forces_t<float>(a, st);
+    k_gather<float><<<a.L.nblocks, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

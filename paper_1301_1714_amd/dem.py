@@ -26,8 +26,8 @@ DEM_E_HIP = -6
 DEM_E_STATE = -7
 DEM_E_CAPACITY = -9
 
-NUM_PHASES = 5
-PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "force")
+NUM_PHASES = 7
+PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "pair_force", "gather")
 
 _LIB = None
 
@@ -261,7 +261,7 @@ class System:
 
     def profile_read(self):
         """(milliseconds per phase summed over the timed steps, number of
-        timed steps); phases: kick-drift-hash, sort, reorder, detect, force."""
+        timed steps); phases as ``PHASES``."""
         ms = (C.c_double * NUM_PHASES)()
         n = C.c_int64()
         _check(lib().dem_profile_read(self.handle, ms, C.byref(n)), "dem_profile_read")

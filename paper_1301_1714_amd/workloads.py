@@ -273,3 +273,86 @@ def overlapping_cloud(seed, n, box=(1.0, 1.0, 1.0), r_mean=0.03, r_spread=0.2, s
         p["kn"] = kw.get("kn", 1.0e7)
         p["kt"] = kw.get("kt", 2.0 / 7.0 * p["kn"])
     return dict(name=f"cloud_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r)
+
+
+# ------------------------------------------------- many independent systems
+
+E_U3 = (1.2 ** 4 - 0.8 ** 4) / (4.0 * 0.4)  # E[u^3] for u ~ U[0.8, 1.2]
+
+
+def system_draw(rng, n_lo, n_hi):
+    """Size and material of one independent system: n log-uniform in
+    [n_lo, n_hi], kn log-uniform in [1e4, 1e6], e ~ U[0.5, 0.95],
+    mu ~ U[0.1, 0.6], packing fraction phi ~ U[0.2, 0.55]."""
+    n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+    kn = math.exp(rng.uniform(math.log(1.0e4), math.log(1.0e6)))
+    e = rng.uniform(0.5, 0.95)
+    mu = rng.uniform(0.1, 0.6)
+    phi = rng.uniform(0.2, 0.55)
+    return dict(n=n, kn=kn, restitution=e, mu=mu, phi=phi)
+
+
+def unit_box_system(seed, n, kn, restitution, mu, phi, precision="mixed", law="linear", cell_factor=1.0,
+                    contacts_per_particle=8):
+    """One system of the batched and serving workloads: n spheres with radii
+    U[0.8, 1.2] r_s in a walled unit box, r_s set so that the spheres fill the
+    packing fraction phi, on a jittered FCC lattice, v ~ N(0, 0.1^2) per axis,
+    omega = 0, gravity -9.81 z, kt = 2/7 kn, dt = t_c,min / 10 (at most
+    1e-5), cell = cell_factor x the largest diameter.  Where the lattice
+    cannot hold the spheres at phi without overlaps, every radius is scaled
+    down to the touching scale (the achieved phi is returned as phi_start)."""
+    rng = np.random.default_rng(seed)
+    r_s = (phi / (n * 4.0 / 3.0 * math.pi * E_U3)) ** (1.0 / 3.0)
+    r = rng.uniform(0.8 * r_s, 1.2 * r_s, size=n)
+    r_max = float(r.max()) if n else r_s
+    x, d_nn = fcc_fill(rng, n, (0, 0, 0), (1, 1, 1), margin=r_max, jitter_frac=0.9)
+    lam = lattice_scale(r, d_nn) if n else 1.0
+    r = fp32_radii(r * lam)
+    v = rng.normal(0.0, 0.1, size=(n, 3))
+    w = np.zeros((n, 3))
+    r_min = float(r.min()) if n else r_s
+    dmax = 2.0 * (float(r.max()) if n else r_s)
+    p = base_params(kn=kn, kt=2.0 / 7.0 * kn, restitution=restitution, mu=mu, law=law, precision=precision,
+                    dt=stable_dt(kn, restitution, r_min), cell_size=min(1.0, cell_factor * dmax),
+                    contacts_per_particle=contacts_per_particle)
+    phi_start = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
+    return dict(name=f"system_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r, phi=phi, phi_start=phi_start)
+
+
+def batched_draws(seed=4000, count=256, n_lo=1024, n_hi=262144):
+    """Sizes and materials of the batched workload's systems."""
+    rng = np.random.default_rng(seed)
+    return [system_draw(rng, n_lo, n_hi) for _ in range(count)]
+
+
+def batched_systems(seed=4000, count=256, n_lo=1024, n_hi=262144, precision="mixed", law="linear",
+                    cell_factors=None):
+    """The batched workload: `count` independent systems, each drawn by
+    ``system_draw`` and built by ``unit_box_system`` with seed seed + 1 + k.
+    cell_factors (one per system) come from the autotuner; default 1."""
+    out = []
+    for k, d in enumerate(batched_draws(seed, count, n_lo, n_hi)):
+        cf = 1.0 if cell_factors is None else float(cell_factors[k])
+        out.append(unit_box_system(seed + 1 + k, d["n"], d["kn"], d["restitution"], d["mu"], d["phi"],
+                                   precision=precision, law=law, cell_factor=cf))
+    return out
+
+
+def serving_requests(seed=5000, count=512, n_lo=1024, n_hi=1 << 20, steps_lo=100, steps_hi=10000):
+    """Request specifications of the serving workload (built lazily with
+    ``unit_box_system``): size log-uniform in [n_lo, n_hi], step count
+    log-uniform in [steps_lo, steps_hi], materials as the batched systems."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(count):
+        d = system_draw(rng, n_lo, n_hi)
+        d["steps"] = int(round(math.exp(rng.uniform(math.log(steps_lo), math.log(steps_hi)))))
+        d["seed"] = seed + 1 + k
+        reqs.append(d)
+    return reqs
+
+
+def poisson_arrivals(seed, count, rate):
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
