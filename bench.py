@@ -45,24 +45,70 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    """sha256 of the kernel source: HBM traffic counted for an older version
+    of the kernels is not reported for this one."""
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1301_1714_amd", "csrc", "dem_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE scaled by what the same counters read
+    for a plain copy of known size), or None when there is none for the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_dense_bed_16M.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
+def copy_probe(mib, reps):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    counters of the profiler (run under rocprofv3 --pmc)."""
+    import torch
+
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "reps": reps}), flush=True)
+
+
 # ------------------------------------------------------------ byte models
 # Algorithmic bytes: what a kernel must move at least, each item once per
 # launch; neighbour data reused from LDS or cache is not counted.  R is the
 # size of a Real (4 with FP32 forces, 8 in FP64).
 
-def detect_bytes(n, ncell, c_own):
+def detect_bytes(n, ncell, c_list):
     """k_detect: per particle its FP32 copy (x, y, z, r: 16 B), its FP64
-    position (24 B) and cell (4 B) read, its count (4 B) and c_own list
-    entries (4 B each) written; the cell starts read once."""
-    return n * (48 + 4 * c_own) + 4 * (ncell + 1)
+    position (24 B) and cell (4 B) read, its two counts (8 B) and c_list
+    list entries (4 B each: every partner, both ways, and the walls)
+    written; the cell starts read once."""
+    return n * (52 + 4 * c_list) + 4 * (ncell + 1)
 
 
-def pair_force_bytes(n, P, R):
-    """k_pair_force: per contact its two slots (8 B), the history key (4 B),
-    delta_t read and written (2 x 3R) and the force and torque term written
-    (6R); per particle its state read once (x 24 B, r 4 B, v and w 6R), its
-    old slot (4 B) and its old history offsets (8 B)."""
-    return P * (12 + 12 * R) + n * (40 + 6 * R)
+def force_bytes(n, c_list, c_own, R):
+    """k_force: per particle its state read (x 24 B, r 4, id 4, v and w 6R),
+    its old slot and history offset (8 B), its two counts (8 B) and its list
+    (4 B per entry); written: force and torque (6R), v and w (6R), the
+    position for the next step (x, r, id: 32 B) and its cell (4 B); per
+    owned contact the committed history read (key 4 B, delta_t 3R) and the
+    new delta_t written (3R).  Partner state is reuse (cache)."""
+    per = (32 + 6 * R) + 8 + 8 + 6 * R + 6 * R + 32 + 4
+    return n * (per + 4 * c_list) + n * c_own * (4 + 6 * R)
 
 
 def step_algorithmic_bytes(n, z, R):
@@ -147,15 +193,16 @@ def bench_dense(args):
     P = pairs + walls
     Z = 2.0 * pairs / n
     R = 4 if p["precision"] == "mixed" else 8
+    c_list = (2.0 * pairs + walls) / n
     kernels = {
-        "k_detect": ("detect", detect_bytes(n, ncell, P / n)),
-        "k_pair_force": ("pair_force", pair_force_bytes(n, P, R)),
+        "k_detect": ("detect", detect_bytes(n, ncell, c_list)),
+        "k_force": ("force", force_bytes(n, c_list, P / n, R)),
     }
     name = max(kernels, key=lambda k: phase_ms[kernels[k][0]])
     ph, nbytes = kernels[name]
     avg = phase_ms[ph]
     roof = {"kernel": name, "bound": "hbm", "achieved": nbytes / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "traffic": None, "bytes_per_launch": nbytes, "avg_ms": avg}
+            "unit": "GB/s", "traffic": measured_traffic(name), "bytes_per_launch": nbytes, "avg_ms": avg}
     roof["frac"] = roof["achieved"] / roof["peak"]
     others = {k: {"avg_ms": phase_ms[v[0]], "bytes_per_launch": v[1],
                   "achieved_GBs": v[1] / (phase_ms[v[0]] * 1e-3) / 1e9} for k, v in kernels.items()}
@@ -192,8 +239,9 @@ def bench_batched(args):
     table.save(args.tune_cache)
     t_tune = time.time() - t0
     factors = autotune.factors_for(draws, table)
+    tiles = autotune.tiles_for(draws, table)
     t0 = time.time()
-    systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors)
+    systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors, tiles=tiles)
     ns = np.array([len(s["r"]) for s in systems])
     log(f"[bench] batched: {len(systems)} systems, {ns.sum()} spheres, generated in {time.time() - t0:.1f}s, "
         f"tuned in {t_tune:.1f}s")
@@ -226,6 +274,7 @@ def bench_batched(args):
         one.close()
     plain_rate = float(ns.sum()) * args.plain_steps / t_plain
     fac, cnt = np.unique(factors, return_counts=True)
+    til, tcnt = np.unique(tiles, return_counts=True)
     return {
         "workload": f"batched_{len(systems)}_systems", "systems": len(systems), "n_total": int(ns.sum()),
         "n_min": int(ns.min()), "n_max": int(ns.max()), "steps": args.batch_steps,
@@ -234,6 +283,7 @@ def bench_batched(args):
                                               "steps_per_system": args.plain_steps},
         "speedup_vs_plain": batched_rate / plain_rate,
         "cell_factors": {str(f): int(c) for f, c in zip(fac, cnt)},
+        "detect_tiles": {str(t): int(c) for t, c in zip(til, tcnt)},
         "Z_mean": float(2.0 * diag[:, 7].sum() / ns.sum()),
         "tune_seconds": t_tune,
     }
@@ -317,6 +367,8 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--serve-hbm-frac", type=float, default=0.8)
     ap.add_argument("--only-dense", action="store_true", help="skip batched, serving and the CPU baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this size (profiler counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -327,6 +379,9 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 5)
+        return
     from paper_1301_1714_amd import dem
     dem.lib()
     out = bench_dense(args)

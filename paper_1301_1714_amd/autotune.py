@@ -1,14 +1,20 @@
 """Autotuner of the per-system launch shape of the DEM step.
 
-The knob is the cell width of the detection grid (Sec. 4.1 requires only that
-a cell holds the largest contact distance, so any width >= 2 r_max gives the
-same contacts): a wider cell means fewer, fuller cells -- fewer empty cells
-to count and scan in a dilute system, more candidate pairs to reject in a
-dense one.  The tuner times short runs of a representative system of each
-class (size octave x packing-fraction band) for every candidate width and
-keeps the fastest.  The choice for a system is then a pure function of its
-class and the table, so the same system always gets the same grid, alone or
-in a batch, and its results do not depend on what it runs with.
+Two knobs, neither of which changes the contacts found:
+  cell width  Sec. 4.1 requires only that a cell holds the largest contact
+              distance, so any width >= 2 r_max gives the same contacts: a
+              wider cell means fewer, fuller cells -- fewer empty cells to
+              count and scan in a dilute system, more candidates to reject
+              in a dense one;
+  tile        the detection launch shape: one lane per particle reading its
+              neighbours through the caches (0), or workgroups over runs of
+              that many cells staging the neighbouring rows in LDS.
+The tuner times short runs of a representative system of each class (size
+octave x packing-fraction band) for every candidate pair and keeps the
+fastest.  The choice for a system is then a pure function of its class and
+the table, so the same system always gets the same grid and launch shape,
+alone or in a batch.  (The cell width does change the slot order and so the
+rounding of the sums; the tile never changes a bit.)
 """
 import json
 import math
@@ -16,6 +22,7 @@ import os
 import time
 
 CANDIDATES = (1.0, 1.25, 1.5, 2.0)  # cell width / largest diameter
+TILES = (0, 8, 16)                   # detection launch shape (tile_cells)
 PHI_BANDS = (0.3, 0.42)              # band edges of the packing fraction
 DEFAULT_PATH = os.path.join(os.path.expanduser("~"), ".cache", "paper_1301_1714_amd", "autotune.json")
 
@@ -46,6 +53,10 @@ class Table:
         e = self.entries.get(system_class(n, phi))
         return float(e["factor"]) if e else default
 
+    def tile(self, n: int, phi: float, default: int = 0) -> int:
+        e = self.entries.get(system_class(n, phi))
+        return int(e.get("tile", default)) if e else default
+
     def save(self, path=DEFAULT_PATH):
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:
@@ -59,7 +70,7 @@ class Table:
             return cls(json.load(f))
 
 
-def time_candidate(spec, factor, steps, precision="mixed", seed=1):
+def time_candidate(spec, factor, steps, precision="mixed", seed=1, tile=0):
     """Seconds per step of one system alone (graph replay, after warm-up)."""
     import torch
 
@@ -67,7 +78,7 @@ def time_candidate(spec, factor, steps, precision="mixed", seed=1):
     from . import workloads as W
 
     s = W.unit_box_system(seed, spec["n"], spec["kn"], spec["restitution"], spec["mu"], spec["phi"],
-                          precision=precision, cell_factor=factor)
+                          precision=precision, cell_factor=factor, tile_cells=tile)
     st = torch.cuda.Stream()
     sysm = dem.System(s["params"], s["x"], s["v"], s["omega"], s["r"], stream=st)
     try:
@@ -82,25 +93,32 @@ def time_candidate(spec, factor, steps, precision="mixed", seed=1):
         sysm.close()
 
 
-def tune(keys, table=None, steps=20, precision="mixed", log=None):
-    """Time every candidate for each class not yet in the table; the fastest
-    wins (the smaller factor on a tie within 2%)."""
+def tune(keys, table=None, steps=20, precision="mixed", log=None, factors=CANDIDATES, tiles=TILES):
+    """Time every candidate (cell factor, tile) for each class not yet in the
+    table; the fastest wins (on a tie within 2%, the first in the order of
+    the candidate lists)."""
     table = table or Table()
     for key in sorted(set(keys)):
         if key in table.entries:
             continue
         spec = representative(key)
-        times = {}
-        for f in CANDIDATES:
-            times[f] = time_candidate(spec, f, steps, precision)
+        cands = [(f, t) for f in factors for t in tiles]
+        times = {c: time_candidate(spec, c[0], steps, precision, tile=c[1]) for c in cands}
         best = min(times.values())
-        choice = min(f for f in CANDIDATES if times[f] <= 1.02 * best)
-        table.entries[key] = {"factor": choice, "ms_per_step": {str(f): 1e3 * t for f, t in times.items()}}
+        choice = next(c for c in cands if times[c] <= 1.02 * best)
+        table.entries[key] = {"factor": choice[0], "tile": choice[1],
+                              "ms_per_step": {f"{f}/{t}": 1e3 * v for (f, t), v in times.items()}}
         if log:
-            log(f"[autotune] {key}: factor {choice} ({', '.join(f'{f}: {1e3 * t:.3f} ms' for f, t in times.items())})")
+            log(f"[autotune] {key}: cell x{choice[0]} tile {choice[1]} ({1e3 * times[choice]:.3f} ms/step; "
+                f"worst {1e3 * max(times.values()):.3f})")
     return table
 
 
 def factors_for(draws, table):
     """Cell factor of each system drawn by workloads.system_draw."""
     return [table.factor(d["n"], d["phi"]) for d in draws]
+
+
+def tiles_for(draws, table):
+    """Detection launch shape of each system drawn by workloads.system_draw."""
+    return [table.tile(d["n"], d["phi"]) for d in draws]

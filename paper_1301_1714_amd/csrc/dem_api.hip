@@ -35,11 +35,13 @@ struct Engine {
   std::vector<dem_params> params;
   std::vector<SysInfo> info;  // host copy of the system table
   std::vector<int32_t> bsys_h, bfirst_h;
+  std::vector<int4> tiles_h;  // detection work items
   int64_t ncell = 0;  // cells of all systems
   int64_t Pcap = 0;
   // device
   SysInfo *tab = nullptr;
   int32_t *psys = nullptr, *bsys = nullptr, *bfirst = nullptr;
+  int4 *tiles = nullptr;
   StepCtl ctl{};
   std::vector<int32_t> left_h;  // source of the ctl.left upload
   hipEvent_t left_ev = nullptr;  // that upload has been read
@@ -55,7 +57,6 @@ struct Engine {
   ScanScratch scan{};
   NbrBuf nbr{};
   PairGen gen[2];
-  PairWork work{};
   DiagBuf diag{};
   int32_t *err = nullptr;
   hipStream_t stream = nullptr;
@@ -64,10 +65,11 @@ struct Engine {
   bool profiling = false;
   std::vector<hipEvent_t> events;  // DEM_PROFILE_CAPACITY x (DEM_NUM_PHASES + 1)
   int64_t timed = 0;
-  // graph replay of Steps 3-8, one graph per position-buffer parity
+  // graph replay of Steps 3-8, one graph per history generation
   bool use_graph = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int gexec_gc[2] = {-1, -1};  // the history generation each graph was captured with
+  int gexec_cp[2] = {-1, -1};  // the position buffer each graph was captured with
+  int32_t ndirect = 0;         // systems swept by the direct detection kernel
 
   Layout layout() const {
     Layout L;
@@ -75,7 +77,10 @@ struct Engine {
     L.psys = psys;
     L.bsys = bsys;
     L.bfirst = bfirst;
+    L.tiles = tiles;
     L.nblocks = (int32_t)bsys_h.size();
+    L.ntiles = (int32_t)tiles_h.size();
+    L.ndirect = ndirect;
     L.n = n;
     L.S = S;
     return L;
@@ -104,6 +109,7 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   if (p->contacts_per_particle < 1 || p->contacts_per_particle > kListCap) return DEM_E_INVALID;
   if (p->wall_mask > 0x3F) return DEM_E_INVALID;
   if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
+  if (p->tile_cells < 0 || p->tile_cells > kMaxTile) return DEM_E_INVALID;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
     const double L = p->box_hi[a] - p->box_lo[a];
@@ -168,6 +174,8 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   int64_t ntot = 0, ctot = 0, pcap = 0;
   e.bsys_h.clear();
   e.bfirst_h.clear();
+  e.tiles_h.clear();
+  e.ndirect = 0;
   for (int32_t k = 0; k < S; k++) {
     SysInfo &si = e.info[k];
     memset(&si, 0, sizeof(si));
@@ -183,6 +191,17 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     for (int64_t b = 0; b < n[k]; b += kBlock) {
       e.bsys_h.push_back(k);
       e.bfirst_h.push_back((int32_t)(ntot + b));
+    }
+    // detection tiles: runs of T cells along x in every (y, z) row
+    const int32_t T = p[k].tile_cells;
+    const int32_t nx = si.g.nc[0], rows = si.g.nc[1] * si.g.nc[2];
+    si.tile = T;
+    if (n[k] > 0 && T == 0) e.ndirect++;
+    if (n[k] > 0 && T > 0) {
+      if ((int64_t)e.tiles_h.size() + (int64_t)rows * ((nx + T - 1) / T) >= (int64_t)INT32_MAX)
+        return DEM_E_INVALID;
+      for (int32_t row = 0; row < rows; row++)
+        for (int32_t x0 = 0; x0 < nx; x0 += T) e.tiles_h.push_back(make_int4(k, row, x0, std::min(x0 + T, nx) - 1));
     }
     ntot += n[k];
     ctot += si.g.ncell;
@@ -210,6 +229,7 @@ size_t carve(Engine &e, char *base) {
   e.psys = cv.take<int32_t>(N);
   e.bsys = cv.take<int32_t>(B);
   e.bfirst = cv.take<int32_t>(B);
+  e.tiles = cv.take<int4>(std::max<size_t>(e.tiles_h.size(), 1));
   e.ctl.step = cv.take<int32_t>(64);
   e.ctl.left = cv.take<int32_t>(S);
   for (int b = 0; b < 2; b++) {
@@ -240,23 +260,15 @@ size_t carve(Engine &e, char *base) {
     e.scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
   }
   e.nbr.xyzr = cv.take<float4>(N);
-  e.nbr.cnt = cv.take<int32_t>(N);
+  e.nbr.nlow = cv.take<int32_t>(N);
+  e.nbr.fcnt = cv.take<int32_t>(N);
+  e.nbr.pst = cv.take_bytes((e.prec == DEM_PREC_FP64 ? sizeof(PState<double>) : sizeof(PState<float>)) * N);
+  e.nbr.hix = cv.take<int4>(N);
   e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
   for (int b = 0; b < 2; b++) {
     e.gen[b].ofs = cv.take<int32_t>(N + 1);
-    e.gen[b].s = cv.take<int32_t>(P);
-    e.gen[b].t = cv.take<int32_t>(P);
-    e.gen[b].key = cv.take<int32_t>(P);
-    e.gen[b].dt = cv.take_bytes(4 * R * P);
+    e.gen[b].ent = cv.take_bytes(4 * R * P);
   }
-  e.work.Pcap = e.Pcap;
-  e.work.pf = cv.take_bytes(8 * R * P);
-  e.work.brank = cv.take<int32_t>(P);
-  e.work.pe = cv.take<double>(P);
-  e.work.pd = cv.take<double>(P);
-  e.work.bcnt = cv.take<int32_t>(N);
-  e.work.bofs = cv.take<int32_t>(N + 1);
-  e.work.bwd = cv.take<int32_t>(P);
   e.diag.e_el = cv.take<double>(N);
   e.diag.npair = cv.take<int32_t>(N);
   e.diag.nwall = cv.take<int32_t>(N);
@@ -356,16 +368,11 @@ hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after
   hipError_t r = launch_detect(L, ctl, e.pos[e.cp], e.nbr, e.scell, e.cell_start, e.err, e.stream);
   if (r != hipSuccess) return r;
   if (after_detect) (void)hipEventRecord(after_detect, e.stream);
-  return launch_list(L, e.nbr, e.gen[g], e.work, e.scan, e.err, e.stream);
+  return launch_list(e.prec, L, e.nbr, e.gen[g], e.Pcap, e.scan, e.err, e.stream);
 }
 
-// Steps 7-8 then the per-particle sums (and, in a time step, the kicks)
-hipError_t run_forces(Engine &e, const PairArgs &a, hipEvent_t after_law = nullptr) {
-  hipError_t r = launch_pair_force(e.prec, a, e.stream);
-  if (r != hipSuccess) return r;
-  if (after_law) (void)hipEventRecord(after_law, e.stream);
-  return launch_gather(e.prec, a, e.stream);
-}
+// Steps 7-8, the per-particle sums and (in a time step) the kicks
+hipError_t run_forces(Engine &e, const PairArgs &a) { return launch_force(e.prec, a, e.stream); }
 
 // Steps 7-8 on the contact list of generation gs, with the committed history
 // of generation gc
@@ -375,11 +382,13 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.L = e.layout();
   a.ctl = e.ctl;
   a.pos = e.pos[e.cp];
+  a.pos_out = e.pos[e.cp ^ 1];
   a.vel_in = e.vel[e.cv];
   a.vel_out = e.vel[e.cv ^ 1];
+  a.nb = e.nbr;
   a.cur = e.gen[e.gs];
   a.old = e.gen[e.gc];
-  a.w = e.work;
+  a.cap = e.Pcap;
   a.perm = e.perm;
   for (int k = 0; k < 3; k++) {
     a.F[k] = F[k];
@@ -402,35 +411,66 @@ struct Entry {
 // The contacts of system k in a generation as sorted (a, b) keys with ids
 // local to the system: (lower id, higher id) for a pair, (id, -1 - w) for a
 // wall; with_d also reads delta_t, turned to the view of the lower id.
+// entries [q0, q1) of a history table: keys and delta_t
+dem_status read_entries(Engine &e, const PairGen &g, size_t q0, size_t q1, std::vector<int32_t> &key,
+                        std::vector<double> &d) {
+  const size_t m = q1 - q0;
+  key.assign(m, 0);
+  d.assign(3 * m, 0.0);
+  if (m == 0) return DEM_OK;
+  if (e.prec == DEM_PREC_FP64) {
+    std::vector<double> raw(4 * m);
+    HIP_TRY(hipMemcpyAsync(raw.data(), (const double *)g.ent + 4 * q0, 32 * m, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    for (size_t q = 0; q < m; q++) {
+      int64_t bits;
+      memcpy(&bits, &raw[4 * q + 3], 8);
+      key[q] = (int32_t)bits;
+      for (int c = 0; c < 3; c++) d[3 * q + c] = raw[4 * q + c];
+    }
+  } else {
+    std::vector<float> raw(4 * m);
+    HIP_TRY(hipMemcpyAsync(raw.data(), (const float *)g.ent + 4 * q0, 16 * m, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    for (size_t q = 0; q < m; q++) {
+      memcpy(&key[q], &raw[4 * q + 3], 4);
+      for (int c = 0; c < 3; c++) d[3 * q + c] = (double)raw[4 * q + c];
+    }
+  }
+  return DEM_OK;
+}
+
+// The contacts of system k in a table as sorted (a, b) keys with ids local
+// to the system: (lower id, higher id) for a pair, (id, -1 - w) for a wall;
+// with_d also returns delta_t, turned to the view of the lower id.
 dem_status read_gen(Engine &e, const PairGen &g, int32_t k, bool with_d, std::vector<Entry> &out) {
   out.clear();
   const SysInfo &si = e.info[k];
   if (si.n == 0) return DEM_OK;
   const size_t N = (size_t)e.n;
   std::vector<int32_t> ofs, key, id;
+  std::vector<double> d;
   dem_status st;
   if ((st = d2h(e, (const int32_t *)g.ofs, ofs, N + 1)) != DEM_OK) return st;
   const size_t P = (size_t)std::min<int64_t>(ofs[N], e.Pcap);
   // a system's contacts are owned by its own slots: one contiguous range
   const size_t q0 = std::min<size_t>((size_t)ofs[si.p0], P);
   const size_t q1 = std::min<size_t>((size_t)ofs[si.p0 + si.n], P);
-  if ((st = d2h(e, (const int32_t *)g.key, key, P)) != DEM_OK) return st;
+  if ((st = read_entries(e, g, q0, q1, key, d)) != DEM_OK) return st;
   if ((st = d2h(e, (const int32_t *)e.pos[e.cp].id, id, N)) != DEM_OK) return st;
-  std::vector<double> d;
-  if (with_d && (st = d2h_real(e, g.dt, 4 * q0, 4 * (q1 - q0), d)) != DEM_OK) return st;
   out.reserve(q1 - q0);
   for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++) {
     const size_t e0 = std::min<size_t>((size_t)ofs[slot], P), e1 = std::min<size_t>((size_t)ofs[slot + 1], P);
     for (size_t q = e0; q < e1; q++) {
       Entry en;
       const int64_t me = id[slot] - si.p0;
-      const int32_t other = key[q];
+      const int32_t other = key[q - q0];
       const bool pair = other >= 0;
       const int64_t them = pair ? id[other] - si.p0 : other;
       en.a = pair ? std::min(me, them) : me;
       en.b = pair ? std::max(me, them) : them;
       const double sg = (pair && me > them) ? -1.0 : 1.0;  // stored as seen from the owner slot
-      for (int c = 0; c < 3; c++) en.d[c] = with_d ? sg * d[4 * (q - q0) + c] : 0.0;
+      for (int c = 0; c < 3; c++) en.d[c] = with_d ? sg * d[3 * (q - q0) + c] : 0.0;
       out.push_back(en);
     }
   }
@@ -443,7 +483,7 @@ void free_graphs(Engine &e) {
   for (int p = 0; p < 2; p++) {
     if (e.gexec[p]) (void)hipGraphExecDestroy(e.gexec[p]);
     e.gexec[p] = nullptr;
-    e.gexec_gc[p] = -1;
+    e.gexec_cp[p] = -1;
   }
 }
 
@@ -469,7 +509,7 @@ struct HistIn {
   const double *dt = nullptr;
 };
 
-dem_status validate_inputs(const Engine &e, const double *x, const double *v, const double *omega,
+dem_status validate_inputs(Engine &e, const double *x, const double *v, const double *omega,
                            const double *r, const double *F0, const double *T0, const HistIn &hist,
                            std::vector<float> &rf) {
   const size_t N = (size_t)e.n;
@@ -477,15 +517,16 @@ dem_status validate_inputs(const Engine &e, const double *x, const double *v, co
   // radii in FP32; the cell must hold the largest contact distance (27-cell search)
   rf.assign(N, 0.0f);
   for (int32_t k = 0; k < e.S; k++) {
-    double rmax = 0.0;
-    const SysInfo &si = e.info[k];
+    float rmax = 0.0f;
+    SysInfo &si = e.info[k];
     for (int64_t i = si.p0; i < (int64_t)si.p0 + si.n; i++) {
       const float q = (float)r[i];
       if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
       rf[i] = q;
-      rmax = std::max(rmax, (double)q);
+      rmax = std::max(rmax, q);
     }
-    if (e.params[k].cell_size < 2.0 * rmax) return DEM_E_INVALID;
+    if (e.params[k].cell_size < 2.0 * (double)rmax) return DEM_E_INVALID;
+    si.rmax = rmax;
   }
   for (size_t i = 0; i < 3 * N; i++)
     if (!isfinite(x[i]) || !isfinite(v[i]) || !isfinite(omega[i])) return DEM_E_NONFINITE;
@@ -540,19 +581,29 @@ dem_status upload_history(Engine &e, const HistIn &hist, const std::vector<int32
       if (recs[k].owner == recs[k - 1].owner && recs[k].key == recs[k - 1].key) return DEM_E_INVALID;
   }
   if ((int64_t)recs.size() > e.Pcap) return DEM_E_CONTACT_OVERFLOW;
-  std::vector<int32_t> ofs(N + 1, 0), key(recs.size());
-  std::vector<double> d(4 * recs.size(), 0.0);
+  std::vector<int32_t> ofs(N + 1, 0);
   for (const Rec &rc : recs) ofs[rc.owner + 1]++;
   for (size_t k = 0; k < N; k++) ofs[k + 1] += ofs[k];
-  for (size_t k = 0; k < recs.size(); k++) {
-    key[k] = recs[k].key;
-    for (int c = 0; c < 3; c++) d[4 * k + c] = recs[k].d[c];
-  }
   const PairGen &g0 = e.gen[0];
   dem_status st;
   if ((st = h2d(e, g0.ofs, ofs)) != DEM_OK) return st;
-  if ((st = h2d(e, g0.key, key)) != DEM_OK) return st;
-  return h2d_real(e, g0.dt, d);
+  if (recs.empty()) return DEM_OK;
+  // entries: delta_t in x, y, z, the key's bits in w
+  if (e.prec == DEM_PREC_FP64) {
+    std::vector<double> raw(4 * recs.size());
+    for (size_t k = 0; k < recs.size(); k++) {
+      for (int c = 0; c < 3; c++) raw[4 * k + c] = recs[k].d[c];
+      const int64_t bits = (int64_t)recs[k].key;
+      memcpy(&raw[4 * k + 3], &bits, 8);
+    }
+    return h2d(e, (double *)g0.ent, raw);
+  }
+  std::vector<float> raw(4 * recs.size());
+  for (size_t k = 0; k < recs.size(); k++) {
+    for (int c = 0; c < 3; c++) raw[4 * k + c] = (float)recs[k].d[c];
+    memcpy(&raw[4 * k + 3], &recs[k].key, 4);
+  }
+  return h2d(e, (float *)g0.ent, raw);
 }
 
 dem_status engine_init(Engine &e, const double *x, const double *v, const double *omega,
@@ -568,6 +619,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo) * e.info.size(), hipMemcpyHostToDevice, e.stream));
   HIP_TRY(hipStreamSynchronize(e.stream));
   if ((st = h2d(e, e.psys, psys)) != DEM_OK || (st = h2d(e, e.bsys, e.bsys_h)) != DEM_OK ||
+      (st = h2d(e, e.tiles, e.tiles_h)) != DEM_OK ||
       (st = h2d(e, e.bfirst, e.bfirst_h)) != DEM_OK || (st = h2d(e, e.err, zeros)) != DEM_OK ||
       (st = h2d(e, e.ctl.step, zeros)) != DEM_OK)
     return st;
@@ -590,8 +642,8 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   HIP_TRY(launch_hash(L, e.pos[0], e.cell, e.err, e.stream));
   HIP_TRY(launch_sort(e.cell, e.pos[0].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
                       e.stream));
-  HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], e.perm, e.cell, e.scell, e.nbr.xyzr,
-                         e.stream));
+  HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], e.perm, e.cell, e.scell, e.nbr,
+                         nullptr, e.stream));
   e.cp = 1;
   e.cv = 1;
   e.gc = 0;
@@ -648,7 +700,9 @@ dem_status engine_create(int32_t S, const dem_params *p, const int64_t *n, const
 
 // Steps 3-8 of one time step.  Steps 1-2 (opening kick, drift, hash) run
 // before the first step of a call and, after that, inside the previous
-// step's gather for every system that steps again.
+// step's force pass for every system that steps again.  The reorder moves
+// the state to the other buffers and the force pass moves it back, so a
+// step starts from the same buffers every time.
 hipError_t step_body(Engine &e, hipEvent_t *ev) {
   auto mark = [&](int phase) {
     if (ev) (void)hipEventRecord(ev[phase], e.stream);
@@ -662,27 +716,29 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   mark(2);
   // Step 4
   if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], e.perm, e.cell,
-                          e.scell, e.nbr.xyzr, e.stream)) != hipSuccess)
+                          e.scell, e.nbr, e.gen[e.gc].ofs, e.stream)) != hipSuccess)
     return r;
   e.cp ^= 1;
   e.cv ^= 1;
   mark(3);
-  // Steps 5-6 into the generation that does not hold the committed history
+  // Steps 5-6; the new history table is the generation that does not hold
+  // the committed one
   if ((r = build_contacts(e, e.gc ^ 1, &e.ctl, ev ? ev[4] : nullptr)) != hipSuccess) return r;
   mark(5);
   // Steps 7-8 and the closing half kick; the new history is committed
   PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);
-  if ((r = run_forces(e, a, ev ? ev[6] : nullptr)) != hipSuccess) return r;
+  if ((r = run_forces(e, a)) != hipSuccess) return r;
   if ((r = launch_step_end(e.ctl, e.stream)) != hipSuccess) return r;
-  mark(7);
+  mark(6);
+  e.cp ^= 1;
   e.cv ^= 1;
   e.gc = e.gs;
   return hipSuccess;
 }
 
-// Capture the step body for the current position parity.  Every argument of
-// every launch is fixed by (cp, cv, gc), so the graph replays any later step
-// that starts from the same three.
+// Capture the step body for the current history generation.  Every argument
+// of every launch is fixed by (cp, cv, gc); cp and cv are the same at the
+// start of every step, so one graph per gc replays every later step.
 dem_status capture(Engine &e) {
   const int cp = e.cp, cv = e.cv, gc = e.gc, gs = e.gs;
   hipGraph_t graph = nullptr;
@@ -705,9 +761,9 @@ dem_status capture(Engine &e) {
     (void)hipGetLastError();
     return DEM_E_HIP;
   }
-  if (e.gexec[cp]) (void)hipGraphExecDestroy(e.gexec[cp]);
-  e.gexec[cp] = exec;
-  e.gexec_gc[cp] = gc;
+  if (e.gexec[gc]) (void)hipGraphExecDestroy(e.gexec[gc]);
+  e.gexec[gc] = exec;
+  e.gexec_cp[gc] = cp | (cv << 1);
   return DEM_OK;
 }
 
@@ -746,8 +802,8 @@ dem_status engine_step(Engine &e, const int64_t *steps) {
     }
     if (ev) (void)hipEventRecord(ev[1], e.stream);
     if (e.use_graph) {
-      const int par = e.cp;
-      if (!e.gexec[par] || e.gexec_gc[par] != e.gc) {
+      const int par = e.gc;
+      if (!e.gexec[par] || e.gexec_cp[par] != (e.cp | (e.cv << 1))) {
         const dem_status st = capture(e);
         if (st != DEM_OK) return e.sticky = st;
       }
@@ -758,8 +814,7 @@ dem_status engine_step(Engine &e, const int64_t *steps) {
         return e.sticky = DEM_E_HIP;
       }
       if (ev) (void)hipEventRecord(ev[DEM_NUM_PHASES], e.stream);
-      // what the replayed body does to the buffer indices (cv comes back)
-      e.cp ^= 1;
+      // what the replayed body does to the indices (cp and cv come back)
       e.gs = e.gc ^ 1;
       e.gc = e.gs;
     } else if (step_body(e, ev) != hipSuccess) {
@@ -782,7 +837,8 @@ dem_status engine_forces(Engine &e, double *F, double *T) {
   dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, 0, e.Fe, e.Te);
-  if (run_forces(e, a) != hipSuccess) {
+  if (launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream) != hipSuccess ||
+      run_forces(e, a) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;
   }
@@ -856,7 +912,8 @@ dem_status engine_diagnostics(Engine &e, double *out) {
   dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, MODE_DIAG, e.Fe, e.Te);
-  if (run_forces(e, a) != hipSuccess ||
+  if (launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream) != hipSuccess ||
+      run_forces(e, a) != hipSuccess ||
       launch_diag_reduce(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.diag, e.stream) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;
@@ -1047,6 +1104,9 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
   }
   if (e.params[0].cell_size < 2.0 * rmax) return DEM_E_INVALID;
   if (N == 0) return DEM_OK;
+  e.info[0].rmax = (float)rmax;
+  HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo), hipMemcpyHostToDevice, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
   std::vector<int32_t> id;
   if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
   std::vector<float> slot_r(N);

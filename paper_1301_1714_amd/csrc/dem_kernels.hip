@@ -4,8 +4,8 @@
 // systems of an engine at once; per-particle kernels run blocks that never
 // straddle two systems, so a block reads its system's constants once):
 //   Steps 1-2    k_kick_drift_hash: opening half kick, drift and the cell
-//                hash (CM) fused; between two steps of one call the closing
-//                pass k_gather does it instead
+//                hash (CM) fused; between two steps of one call k_force does
+//                it instead, for the next step
 //   Step 3       k_count / scan / k_scatter / k_canon: counting sort by cell,
 //                ties ordered by particle id, so SCM[j] = CM[SCCM[j]] (Eq. 11)
 //                holds with one unique order; the paper's bitonic sort is
@@ -13,21 +13,18 @@
 //                gives the same permutation)
 //   Step 4       k_reorder: gather every array into the sorted order, plus an
 //                FP32 copy of (x - lo, r) for the detection prefilter
-//   Steps 5-6    k_detect: one lane per sorted particle sweeps the forward
-//                half of the 27 cells of Eq. 12 (each pair is tested once),
-//                rejects with a conservative FP32 test and decides the rest
-//                exactly in FP64; its contacts (ascending partner slot) and
-//                walls form its list.  k_pairs / k_bwd: the lists become one
-//                compact contact array (CSR by owner slot, from a scan) and a
-//                backward index per partner (counting sort)
-//   Steps 7-8    k_pair_force: one lane per contact -- every lane of a wave
-//                evaluates a real contact, whatever the particles' contact
-//                counts -- looks up the tangential history in the owner's
-//                segment of the previous step's array and evaluates the law
-//                (Eqs. 2-10, or Eq. 1) once per pair.  k_gather: one lane per
-//                particle sums its contacts in a fixed order (lower partners,
-//                higher partners, walls; no atomics) and applies the closing
-//                half kick
+//   Steps 5-6    k_detect_direct / k_detect_tiles: each particle sweeps the
+//                27 cells of Eq. 12 (skipping cells beyond reach), rejects
+//                with a conservative FP32 test and decides the rest exactly
+//                in FP64; its contacts, in ascending slot order, and its
+//                walls form its list.  k_pairs: the keys of the contacts
+//                each particle owns (higher partners, walls) form the CSR
+//                array that will hold the new tangential history
+//   Steps 7-8    k_force: one lane per particle evaluates the law of every
+//                contact on its list (Eqs. 2-10, or Eq. 1) in the pair's
+//                canonical orientation, looks the history up in the previous
+//                array, sums in list order (no atomics) and applies the
+//                closing half kick
 // No step is a dense contraction, so nothing here uses the matrix cores.
 #include <math.h>
 
@@ -343,7 +340,7 @@ template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
-                                                    float4 *__restrict__ xyzr) {
+                                                    NbrBuf nb, const int32_t *__restrict__ old_ofs) {
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
@@ -355,13 +352,45 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   dst.z[s] = z;
   dst.r[s] = r;
   dst.id[s] = src.id[p];
-  xyzr[s] = make_xyzr(L.tab[k].g, x, y, z, r);
+  nb.xyzr[s] = make_xyzr(L.tab[k].g, x, y, z, r);
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     ((Real *)vdst.v[q])[s] = ((const Real *)vsrc.v[q])[p];
     ((Real *)vdst.w[q])[s] = ((const Real *)vsrc.w[q])[p];
   }
   scell[s] = cell[p];
+  PState<Real> ps;
+  ps.x = x;
+  ps.y = y;
+  ps.z = z;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    ps.v[q] = ((const Real *)vsrc.v[q])[p];
+    ps.w[q] = ((const Real *)vsrc.w[q])[p];
+  }
+  ps.r = r;
+  ps.pad = 0;
+  ((PState<Real> *)nb.pst)[s] = ps;
+  if (old_ofs) nb.hix[s] = make_int4(p, old_ofs[p], old_ofs[p + 1], 0);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf vel, NbrBuf nb) {
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  if (s < 0) return;
+  PState<Real> ps;
+  ps.x = pos.x[s];
+  ps.y = pos.y[s];
+  ps.z = pos.z[s];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    ps.v[q] = ((const Real *)vel.v[q])[s];
+    ps.w[q] = ((const Real *)vel.w[q])[s];
+  }
+  ps.r = pos.r[s];
+  ps.pad = 0;
+  ((PState<Real> *)nb.pst)[s] = ps;
 }
 
 __global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__restrict__ xyzr) {
@@ -372,89 +401,110 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__r
 }
 
 // --------------------------------------------------------------------------
-// Steps 5-6: contact detection over the forward half of the 27-cell stencil.
-// A pair in neighbouring cells is tested by the particle whose cell comes
-// first in (z, y, x) order; a pair in one cell by the lower slot.  Every
-// partner found this way has a higher slot, so the list comes out ascending
-// without atomics.
+// Steps 5-6: contact detection over the 27 cells of Eq. 12.
+//
+// Each particle visits the 9 rows of cells around its own (the three cells
+// of a row are one contiguous slot range after the sort).  A row, or an end
+// cell of a row, whose box lies farther than r_i + r_max from the particle is
+// skipped: a conservative bound (margin 2 eps covers the FP32 rounding of the
+// coordinates and the cell faces), so it never skips a contact.  Candidates
+// pass a conservative FP32 test; the few survivors are decided exactly in
+// FP64.  Rows are visited in (z, y) order and cells in x order, so the
+// contacts come out in ascending slot order: the partners with lower slots,
+// then those with higher slots, then the walls.  The tests are symmetric, so
+// both particles of a pair find each other.
+//
+// Two launch shapes build the same lists: the direct one (one lane per
+// particle, candidates read through the caches) and the tiled one (one
+// workgroup per run of cells along x stages the FP32 copies of the 9 rows
+// around it in LDS first).  A system's tile_cells selects the shape.
 
-constexpr int kSurv = 16;  // LDS survivor slots per lane
+constexpr int kTileThreads = 128;
+constexpr int kHaloCap = 1024;  // particles staged per tile; a fuller tile reads global memory
+constexpr int kSurv = 8;        // LDS survivor slots per lane
 
 // exact FP64 decision on one prefilter survivor (the contact test of Step 7)
 __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
                                                  float ri, double xi, double yi, double zi, int32_t t,
-                                                 int32_t &nf) {
+                                                 int32_t &nf, int32_t &nl) {
   const double ex = pos.x[t] - xi, ey = pos.y[t] - yi, ez = pos.z[t] - zi;
   const double S = (double)ri + (double)pos.r[t];
   if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
   if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = t;
   nf++;
+  nl += t < s ? 1 : 0;
 }
 
-// Prefilter one slot range; survivors wait in the lane's LDS slots so that
-// the rare exact test does not sit inside the candidate loop (where any one
-// lane taking it would hold the whole wave).  A lane whose slots fill up
-// drains them itself, in order.
-__device__ __forceinline__ void prefilter_range(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
-                                                const float4 p, float eps, double xi, double yi, double zi,
-                                                int32_t beg, int32_t end, int32_t *surv, int32_t &ns,
-                                                int32_t &nf) {
-  for (int32_t t = beg; t < end; t++) {
-    const float4 q = nb.xyzr[t];
-    const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-    const float sf = p.w + q.w + eps;
-    if (dx * dx + dy * dy + dz * dz < sf * sf) {
-      if (ns == kSurv) {
-        for (int k = 0; k < kSurv; k++) exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[k * kBlock], nf);
-        ns = 0;
-      }
-      surv[ns * kBlock] = t;
-      ns++;
-    }
-  }
+constexpr int kUnroll = 2;  // candidates loaded together
+
+// a full survivor buffer, decided in order (rare: kept out of line)
+template <int kLanes>
+__device__ __forceinline__ void drain_survivors(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s, float ri,
+                                             double xi, double yi, double zi, const int32_t *surv, int32_t &nf,
+                                             int32_t &nl) {
+  for (int j = 0; j < kSurv; j++) exact_and_record(nb, pos, N, s, ri, xi, yi, zi, surv[j * kLanes], nf, nl);
 }
 
-__global__ __launch_bounds__(kBlock) void k_detect(Layout L, StepCtl ctl, int32_t only_active, PosBuf pos,
-                                                   NbrBuf nb, const int32_t *__restrict__ scell,
-                                                   const int32_t *__restrict__ cell_start, int32_t *err) {
-  __shared__ int32_t surv_all[kSurv * kBlock];
-  int32_t k;
-  const int32_t s = block_slot(L, k);
-  if (s < 0) return;
-  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
-  const SysInfo &si = L.tab[k];
-  const int32_t n = L.n;
-  int32_t *surv = surv_all + threadIdx.x;  // slot k at surv[k * kBlock]
+// One particle's sweep.  rows(r, ca, cb, beg, end, shift) gives the slot
+// range [beg, end) of cells ca..cb of row r and where its FP32 copies are
+// (slot t at rows.src[t - shift]); false for a row outside the grid.
+// Survivors wait in the lane's LDS slots (stride kLanes) so that the rare
+// exact test does not sit inside the candidate loop, where one lane taking
+// it would hold the whole wave.
+template <int kLanes, typename Rows>
+__device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, const PosBuf &pos, int32_t N,
+                                               int32_t s, const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
+                                               int32_t *surv, int32_t *err) {
   const float4 p = nb.xyzr[s];
-  const float eps = si.eps;
   const double xi = pos.x[s], yi = pos.y[s], zi = pos.z[s];
-  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
-  const int32_t c0 = si.g.c0;
-  const int32_t cc = scell[s] - c0;
-  const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
-  const int32_t x0 = cx > 0 ? cx - 1 : 0, x1 = cx < nx - 1 ? cx + 1 : nx - 1;
-  int32_t nf = 0, ns = 0;
-  // own row: the rest of the own cell and the next cell along x
-  const int32_t row0 = c0 + (cz * ny + cy) * nx;
-  prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, s + 1, cell_start[row0 + x1 + 1], surv, ns, nf);
-  // next row along y in the same plane
-  if (cy + 1 < ny) {
-    const int32_t row = c0 + (cz * ny + cy + 1) * nx;
-    prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv, ns,
-                    nf);
+  const float eps = si.eps;
+  const int32_t nx = si.g.nc[0];
+  const float wx = (float)(1.0 / si.g.sc[0]), wy = (float)(1.0 / si.g.sc[1]), wz = (float)(1.0 / si.g.sc[2]);
+  const float cut = p.w + si.rmax + 2.0f * eps, cut2 = cut * cut;
+  // distances to the faces of the own cell (0 for a particle outside it)
+  const float dxl = fmaxf(p.x - (float)cx * wx, 0.0f), dxh = fmaxf((float)(cx + 1) * wx - p.x, 0.0f);
+  const float dyl = fmaxf(p.y - (float)cy * wy, 0.0f), dyh = fmaxf((float)(cy + 1) * wy - p.y, 0.0f);
+  const float dzl = fmaxf(p.z - (float)cz * wz, 0.0f), dzh = fmaxf((float)(cz + 1) * wz - p.z, 0.0f);
+  // the slot ranges of all 9 rows first: their loads overlap
+  int32_t beg[9], end[9], shift[9];
+  const float4 *src = rows.src;
+#pragma unroll
+  for (int r = 0; r < 9; r++) {
+    const int dyr = (r % 3) - 1, dzr = (r / 3) - 1;
+    const float dy = dyr < 0 ? dyl : (dyr > 0 ? dyh : 0.0f);
+    const float dz = dzr < 0 ? dzl : (dzr > 0 ? dzh : 0.0f);
+    const float dyz2 = dy * dy + dz * dz;
+    beg[r] = end[r] = shift[r] = 0;
+    if (!(dyz2 < cut2)) continue;
+    const int32_t ca = (cx > 0 && dxl * dxl + dyz2 < cut2) ? cx - 1 : cx;
+    const int32_t cb = (cx < nx - 1 && dxh * dxh + dyz2 < cut2) ? cx + 1 : cx;
+    if (!rows(r, ca, cb, beg[r], end[r], shift[r])) beg[r] = end[r] = 0;
   }
-  // the three rows of the next plane along z
-  if (cz + 1 < nz) {
-    for (int32_t dy = -1; dy <= 1; dy++) {
-      const int32_t yy = cy + dy;
-      if (yy < 0 || yy >= ny) continue;
-      const int32_t row = c0 + ((cz + 1) * ny + yy) * nx;
-      prefilter_range(nb, pos, n, s, p, eps, xi, yi, zi, cell_start[row + x0], cell_start[row + x1 + 1], surv,
-                      ns, nf);
+  int32_t nf = 0, nl = 0, ns = 0;
+#pragma unroll
+  for (int r = 0; r < 9; r++) {
+    const int32_t e = end[r], sh = shift[r];
+    // kUnroll candidates per round, loaded together
+    for (int32_t t = beg[r]; t < e; t += kUnroll) {
+      float4 q[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; u++) q[u] = src[(t + u < e ? t + u : t) - sh];
+#pragma unroll
+      for (int u = 0; u < kUnroll; u++) {
+        const float ex = q[u].x - p.x, ey = q[u].y - p.y, ez = q[u].z - p.z;
+        const float sf = p.w + q[u].w + eps;
+        if (t + u < e && ex * ex + ey * ey + ez * ez < sf * sf && t + u != s) {
+          if (ns == kSurv) {
+            drain_survivors<kLanes>(nb, pos, N, s, p.w, xi, yi, zi, surv, nf, nl);
+            ns = 0;
+          }
+          surv[ns * kLanes] = t + u;
+          ns++;
+        }
+      }
     }
   }
-  // exact tests of the survivors, in slot order
-  for (int32_t q = 0; q < ns; q++) exact_and_record(nb, pos, n, s, p.w, xi, yi, zi, surv[q * kBlock], nf);
+  for (int32_t j = 0; j < ns; j++) exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf, nl);
   // Step 8: walls, particles of infinite radius, after the pairs
   const uint32_t wall_mask = si.c.wall_mask;
   if (wall_mask) {
@@ -465,102 +515,170 @@ __global__ __launch_bounds__(kBlock) void k_detect(Layout L, StepCtl ctl, int32_
       const int ax = w >> 1;
       const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
       if (gap < rid) {
-        if (nf < kListCap) nb.nb[(int64_t)nf * n + s] = -1 - w;
+        if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = -1 - w;
         nf++;
       }
     }
   }
   if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
-  nb.cnt[s] = nf < kListCap ? nf : kListCap;
+  const int32_t kept = nf < kListCap ? nf : kListCap;
+  const int32_t low = nl < kept ? nl : kept;
+  nb.nlow[s] = low;
+  nb.fcnt[s] = kept - low;
 }
 
-// The lists become the compact contact array of `gen` (offsets from a scan of
-// the counts); each pair also draws its rank in the partner's backward list.
-__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int32_t n, int32_t *err) {
+struct DirectRows {
+  const float4 *src;
+  const int32_t *cell_start;
+  int32_t c0, nx, ny, nz, cy, cz;
+  __device__ __forceinline__ bool operator()(int r, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
+                                             int32_t &shift) const {
+    const int32_t yy = cy + (r % 3) - 1, zz = cz + (r / 3) - 1;
+    if (yy < 0 || yy >= ny || zz < 0 || zz >= nz) return false;
+    const int32_t row = c0 + (zz * ny + yy) * nx;
+    beg = cell_start[row + ca];
+    end = cell_start[row + cb + 1];
+    shift = 0;
+    return true;
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl, int32_t only_active, PosBuf pos,
+                                                          NbrBuf nb, const int32_t *__restrict__ scell,
+                                                          const int32_t *__restrict__ cell_start, int32_t *err) {
+  __shared__ int32_t surv_all[kSurv * kBlock];
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  if (s < 0) return;
+  const SysInfo &si = L.tab[k];
+  if (si.tile > 0) return;                        // the tiled kernel sweeps this system
+  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
+  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
+  const int32_t cc = scell[s] - si.g.c0;
+  const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
+  const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
+  sweep_particle<kBlock>(rows, nb, pos, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, err);
+}
+
+template <bool kStaged>
+struct TileRows {
+  const float4 *src;
+  const int32_t (*cs)[kMaxTile + 3];
+  int32_t xa;
+  int32_t shift[9];
+  __device__ __forceinline__ bool operator()(int r, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
+                                             int32_t &sh) const {
+    beg = cs[r][ca - xa];  // rows outside the grid hold empty ranges
+    end = cs[r][cb - xa + 1];
+    sh = kStaged ? shift[r] : 0;
+    return true;
+  }
+};
+
+__global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl ctl, int32_t only_active,
+                                                               PosBuf pos, NbrBuf nb,
+                                                               const int32_t *__restrict__ scell,
+                                                               const int32_t *__restrict__ cell_start,
+                                                               int32_t *err) {
+  __shared__ float4 halo[kHaloCap];
+  __shared__ int32_t cs[9][kMaxTile + 3];  // cell starts of cells xa .. xb + 1 of each row
+  __shared__ int32_t surv_all[kSurv * kTileThreads];
+  const int tid = threadIdx.x;
+  const int4 tile = L.tiles[blockIdx.x];
+  const int32_t k = tile.x;
+  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
+  const SysInfo &si = L.tab[k];
+  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
+  const int32_t c0 = si.g.c0;
+  const int32_t ry = tile.y % ny, rz = tile.y / ny;
+  const int32_t x0 = tile.z, x1 = tile.w;
+  const int32_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 < nx - 1 ? x1 + 1 : nx - 1;
+  const int32_t wcs = xb - xa + 2;  // cell starts per row
+  for (int32_t i = tid; i < 9 * wcs; i += kTileThreads) {
+    const int32_t r = i / wcs, j = i - r * wcs;
+    const int32_t yy = ry + (r % 3) - 1, zz = rz + (r / 3) - 1;
+    const bool in = yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+    cs[r][j] = in ? cell_start[c0 + (zz * ny + yy) * nx + xa + j] : 0;
+  }
+  __syncthreads();
+  const int32_t own_lo = cs[4][x0 - xa], own_hi = cs[4][x1 - xa + 1];
+  if (own_lo == own_hi) return;
+  TileRows<true> st;
+  st.cs = cs;
+  st.src = halo;
+  st.xa = xa;
+  int32_t total = 0;
+#pragma unroll
+  for (int r = 0; r < 9; r++) {
+    st.shift[r] = cs[r][0] - total;  // slot t of row r sits at halo[t - shift[r]]
+    total += cs[r][wcs - 1] - cs[r][0];
+  }
+  const bool staged = total <= kHaloCap;  // the same for every thread
+  if (staged) {
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+      const int32_t lo = cs[r][0], len = cs[r][wcs - 1] - lo;
+      for (int32_t i = tid; i < len; i += kTileThreads) halo[lo - st.shift[r] + i] = nb.xyzr[lo + i];
+    }
+  }
+  __syncthreads();
+  int32_t *surv = surv_all + tid;
+  if (staged) {
+    for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
+      sweep_particle<kTileThreads>(st, nb, pos, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+  } else {
+    TileRows<false> gr;
+    gr.cs = cs;
+    gr.src = nb.xyzr;
+    gr.xa = xa;
+    for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
+      sweep_particle<kTileThreads>(gr, nb, pos, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+  }
+}
+
+// history entry: delta_t in x, y, z and the key's bits in w
+__device__ __forceinline__ float key_bits(int32_t key, float) { return __int_as_float(key); }
+__device__ __forceinline__ double key_bits(int32_t key, double) { return __longlong_as_double((long long)key); }
+__device__ __forceinline__ int32_t entry_key(float w) { return __float_as_int(w); }
+__device__ __forceinline__ int32_t entry_key(double w) { return (int32_t)__double_as_longlong(w); }
+
+template <typename Real>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+  using type = float4;
+};
+template <>
+struct Vec4T<double> {
+  using type = double4;
+};
+
+template <typename Real>
+__device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Real d[3], int32_t key) {
+  using V4 = typename Vec4T<Real>::type;
+  V4 e;
+  e.x = d[0];
+  e.y = d[1];
+  e.z = d[2];
+  e.w = key_bits(key, (Real)0);
+  ((V4 *)g.ent)[q] = e;
+}
+
+// The higher-slot part of each list (and the walls) becomes the keys of the
+// CSR table (by owner: the lower slot) that will hold the new tangential
+// history; offsets come from a scan of the owned counts.
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, int64_t cap, int32_t n, int32_t *err) {
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
-  const int32_t cnt = nb.cnt[s];
+  const int32_t nl = nb.nlow[s], fc = nb.fcnt[s];
   const int64_t base = gen.ofs[s];
-  if (base + cnt > w.Pcap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
-  for (int32_t k = 0; k < cnt; k++) {
-    const int32_t t = nb.nb[(int64_t)k * n + s];
-    const int64_t q = base + k;
-    if (q >= w.Pcap) break;
-    gen.s[q] = s;
-    gen.t[q] = t;
-    gen.key[q] = t;
-    if (t >= 0) w.brank[q] = atomicAdd(&w.bcnt[t], 1);
-  }
-}
-
-__device__ __forceinline__ int32_t num_pairs(const PairGen &gen, int32_t n, int64_t cap) {
-  const int32_t P = gen.ofs[n];
-  return (int64_t)P < cap ? P : (int32_t)cap;
-}
-
-// backward index: contact q is filed under its partner at the rank its
-// count drew (arrival order; the gather sorts each short segment)
-__global__ __launch_bounds__(kBlock) void k_bwd(PairGen gen, PairWork w, int32_t n) {
-  const int32_t P = num_pairs(gen, n, w.Pcap);
-  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
-    const int32_t t = gen.t[q];
-    if (t < 0) continue;
-    w.bwd[w.bofs[t] + w.brank[q]] = q;
-  }
-}
-
-// fixed-size bitonic network on registers (indices are compile-time)
-template <int M>
-__device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
-#pragma unroll
-  for (int k = 2; k <= M; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-      for (int i = 0; i < M; i++) {
-        const int l = i ^ j;
-        if (l > i) {
-          const bool up = (i & k) == 0;
-          const int32_t u = L[i], v = L[l];
-          const bool sw = up ? (u > v) : (u < v);
-          L[i] = sw ? v : u;
-          L[l] = sw ? u : v;
-        }
-      }
-    }
-  }
-}
-
-template <int M>
-__device__ __forceinline__ void sort_small(int32_t *list, int32_t cnt) {
-  int32_t L[M];
-#pragma unroll
-  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i] : INT32_MAX;
-  bitonic_sort<M>(L);
-#pragma unroll
-  for (int i = 0; i < M; i++)
-    if (i < cnt) list[i] = L[i];
-}
-
-// ascending order of a short contiguous list (entries arrived by atomics)
-__device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
-  if (cnt <= 1) return;
-  if (cnt <= 4) {
-    sort_small<4>(list, cnt);
-  } else if (cnt <= 8) {
-    sort_small<8>(list, cnt);
-  } else if (cnt <= 16) {
-    sort_small<16>(list, cnt);
-  } else {
-    for (int32_t k = 1; k < cnt; k++) {
-      const int32_t v = list[k];
-      int32_t j = k - 1;
-      while (j >= 0 && list[j] > v) {
-        list[j + 1] = list[j];
-        j--;
-      }
-      list[j + 1] = v;
-    }
+  if (base + fc > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
+  const Real zero[3] = {0, 0, 0};
+  for (int32_t j = 0; j < fc; j++) {
+    const int64_t q = base + j;
+    if (q >= cap) break;
+    put_entry<Real>(gen, q, zero, nb.nb[(int64_t)(nl + j) * n + s]);
   }
 }
 
@@ -568,24 +686,28 @@ hipError_t launch_detect(const Layout &L, const StepCtl *ctl, const PosBuf &p, c
                          const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
   StepCtl none{nullptr, nullptr};
-  k_detect<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start, err);
+  if (L.ndirect > 0)
+    k_detect_direct<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start,
+                                                   err);
+  if (L.ntiles > 0)
+    k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell,
+                                                       cell_start, err);
   return hipGetLastError();
 }
 
-hipError_t launch_list(const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, int64_t cap,
                        const ScanScratch &sc, int32_t *err, hipStream_t st) {
   const int32_t n = L.n;
   if (n <= 0) {
     k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
-    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
     return hipGetLastError();
   }
-  hipError_t e = scan_with_total(nb.cnt, gen.ofs, n, sc, st);
+  hipError_t e = scan_with_total(nb.fcnt, gen.ofs, n, sc, st);
   if (e != hipSuccess) return e;
-  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
-  k_pairs<<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, n, err);
-  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
-  k_bwd<<<2048, kBlock, 0, st>>>(gen, w, n);
+  if (precision == DEM_PREC_FP64)
+    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, cap, n, err);
+  else
+    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, cap, n, err);
   return hipGetLastError();
 }
 
@@ -675,29 +797,17 @@ __device__ __forceinline__ double elastic_energy(const Consts &c, Real delta, Re
   return 0.5 * (double)o.kn * d * d + 0.5 * (double)o.kt * hh;
 }
 
-template <typename Real>
-struct Vec4T;
-template <>
-struct Vec4T<float> {
-  using type = float4;
-};
-template <>
-struct Vec4T<double> {
-  using type = double4;
-};
-
 // committed tangential displacement of the contact with history key `key`
-// in segment `owner` of the previous array (zero for a new contact)
+// in the entries [beg, end) of the previous table (zero for a new contact)
 template <typename Real>
-__device__ __forceinline__ void hist_lookup(const PairGen &old, int64_t cap, int32_t owner, int32_t key,
-                                            Real h[3]) {
+__device__ __forceinline__ void hist_find(const PairGen &old, int64_t cap, int32_t beg, int32_t end, int32_t key,
+                                          Real h[3]) {
   using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
-  int64_t q = old.ofs[owner];
-  const int64_t e = old.ofs[owner + 1] < cap ? old.ofs[owner + 1] : cap;
-  for (; q < e; q++) {
-    if (old.key[q] == key) {
-      const V4 d = ((const V4 *)old.dt)[q];
+  const int64_t e = end < cap ? end : cap;
+  for (int64_t q = beg; q < e; q++) {
+    const V4 d = ((const V4 *)old.ent)[q];
+    if (entry_key(d.w) == key) {
       h[0] = d.x;
       h[1] = d.y;
       h[2] = d.z;
@@ -706,88 +816,150 @@ __device__ __forceinline__ void hist_lookup(const PairGen &old, int64_t cap, int
   }
 }
 
-// One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
-// pair, seen from the owner (the lower slot), stored as the force on the
-// owner and n x F_t.  The partner receives the exact negation.  In a time
-// step, the contacts of a system that has finished its steps only carry
-// their history forward.
+// Steps 7-8 and the closing half kick: one lane per particle walks its
+// contact list in order (lower partners, higher partners, walls).  Each pair
+// is evaluated in one canonical orientation -- seen from its lower slot,
+// with the history filed under that slot -- by both of its particles, with
+// the same operands in the same order, so the two results are bit-identical
+// and the particles receive exactly opposite forces (and the same n x F_t,
+// Eq. 3) without any exchange; only the lower slot writes the new history.
+// The sums run in a fixed order and use no atomics.  In a time step the lane
+// then applies the closing half kick and, when its system steps again in
+// this call, the next step's opening kick, drift and hash, writing the
+// positions to the other buffer (partners still read the current ones).
+template <typename Real>
+__device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, const PosBuf &out, int32_t i,
+                                              const Real v[3], const Consts &c, const Grid &g, int32_t *cell,
+                                              int32_t *err) {
+#pragma clang fp contract(off)
+  const double x = x0 + c.dt * (double)v[0];
+  const double y = y0 + c.dt * (double)v[1];
+  const double z = z0 + c.dt * (double)v[2];
+  out.x[i] = x;
+  out.y[i] = y;
+  out.z[i] = z;
+  int32_t cc;
+  if (!hash_cell(g, x, y, z, &cc)) raise_err(err, ERR_DOMAIN);
+  cell[i] = cc;
+}
+
+// Committed delta_t of the contact of two particles, seen from the current
+// lower slot (own: the first particle is it).  hs, ht: previous slot and
+// committed history segment of each.  The previous step filed the contact
+// under the lower of the two previous slots, seen from there.
+template <typename Real>
+__device__ __forceinline__ void pair_history(const PairGen &old, int64_t cap, const int4 &hs, const int4 &ht,
+                                             bool own, Real h[3]) {
+  const bool s_owned = hs.x < ht.x;  // the first particle was the lower slot then
+  if (s_owned)
+    hist_find<Real>(old, cap, hs.y, hs.z, ht.x, h);
+  else
+    hist_find<Real>(old, cap, ht.y, ht.z, hs.x, h);
+  if (s_owned != own) {  // the lower slot changed: delta_t flips with the view
+    h[0] = -h[0];
+    h[1] = -h[1];
+    h[2] = -h[2];
+  }
+}
+
+// previous slot and committed history segment of slot s
+__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s) {
+  return old_perm ? a.nb.hix[s] : make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
+}
+
 template <typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
-  using V4 = typename Vec4T<Real>::type;
-  const int32_t P = num_pairs(a.cur, a.L.n, a.w.Pcap);
-  const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
-  const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
-  const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
-  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
-  const bool diag = (a.mode & MODE_DIAG) != 0;
+__global__ __launch_bounds__(kBlock) void k_force(PairArgs a) {
+  int32_t k;
+  const int32_t s = block_slot(a.L, k);
+  if (s < 0) return;
+  const SysInfo &si = a.L.tab[k];
+  const Consts &c = si.c;
+  const int32_t N = a.L.n;
+  const int64_t cap = a.cap;
   const bool stepping = (a.mode & MODE_KICK) != 0;
-  const bool one_sys = a.L.S == 1;
-  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
-    const int32_t s = a.cur.s[q], t = a.cur.t[q];
-    const int32_t k = one_sys ? 0 : a.L.psys[s];
-    const SysInfo &si = a.L.tab[k];
-    const Consts &c = si.c;
-    const int32_t ps = old_perm ? a.perm[s] : s;
-    const int32_t pt = t >= 0 ? (old_perm ? a.perm[t] : t) : t;
-    // the previous step filed this contact under its lower slot then, with
-    // delta_t seen from that particle
-    Real h[3];
-    if (LAW != DEM_LAW_SIMPLE) {
-      const bool flip = t >= 0 && ps > pt;
-      hist_lookup<Real>(a.old, a.w.Pcap, flip ? pt : ps, flip ? ps : pt, h);
-      if (flip) {
-        h[0] = -h[0];
-        h[1] = -h[1];
-        h[2] = -h[2];
+  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
+  const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
+  const bool diag = (a.mode & MODE_DIAG) != 0;
+  const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
+  const int32_t nl = a.nb.nlow[s], nc = nl + a.nb.fcnt[s];
+  const int64_t q0 = a.cur.ofs[s];  // first owned contact in the new table
+  const PState<Real> me = PS[s];
+  const int4 hs = hist_index(a, old_perm, s);
+  const double xs = me.x, ys = me.y, zs = me.z;
+  const float rsf = me.r;
+  if (stepping && !is_active(a.ctl, k)) {
+    // a finished system: state unchanged, history carried forward; the next
+    // sort sees its current cells
+    if (write_hist) {
+      for (int32_t j = nl; j < nc; j++) {
+        const int64_t q = q0 + (j - nl);
+        if (q >= cap) break;
+        const int32_t t = a.nb.nb[(int64_t)j * N + s];
+        Real h[3];
+        if (t >= 0)
+          pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), true, h);
+        else
+          hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
+        put_entry<Real>(a.cur, q, h, t);
       }
-    } else {
-      h[0] = h[1] = h[2] = 0;
     }
-    if (stepping && !is_active(a.ctl, k)) {
-      // a finished system: its state does not move, its history is kept
-      if (write_hist) {
-        V4 d;
-        d.x = h[0];
-        d.y = h[1];
-        d.z = h[2];
-        d.w = 0;
-        ((V4 *)a.cur.dt)[q] = d;
-      }
-      continue;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      ((Real *)a.vel_out.v[q])[s] = me.v[q];
+      ((Real *)a.vel_out.w[q])[s] = me.w[q];
     }
-    const double xs = a.pos.x[s], ys = a.pos.y[s], zs = a.pos.z[s];
-    const float rsf = a.pos.r[s];
-    const Real rs = (Real)rsf;
-    const Real ms = mass_of<Real>(c, rs);
-    const Real vs[3] = {VI[0][s], VI[1][s], VI[2][s]};
-    const Real ws[3] = {WI[0][s], WI[1][s], WI[2][s]};
+    a.pos_out.x[s] = xs;
+    a.pos_out.y[s] = ys;
+    a.pos_out.z[s] = zs;
+    a.pos_out.r[s] = rsf;
+    a.pos_out.id[s] = a.pos.id[s];
+    a.cell[s] = a.scell[s];
+    return;
+  }
+  const Real rs = (Real)rsf;
+  const Real ms = mass_of<Real>(c, rs);
+  const Real *vs = me.v, *ws = me.w;
+  Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  double e_el = 0.0, dmax = 0.0;
+  int32_t npair = 0, nwall = 0;
+  for (int32_t j = 0; j < nc; j++) {
+    const int32_t t = a.nb.nb[(int64_t)j * N + s];
+    const bool own = j >= nl;  // this particle is the lower slot (or faces a wall)
+    Real h[3] = {0, 0, 0};
     LawOut<Real> o;
     Real n[3], delta, R;
     if (t >= 0) {
-      const double dx = a.pos.x[t] - xs, dy = a.pos.y[t] - ys, dz = a.pos.z[t] - zs;
+      const PState<Real> pt_ = PS[t];
+      if (LAW != DEM_LAW_SIMPLE) pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), own, h);
+      // canonical orientation: body a is the lower slot
+      const double xa = own ? xs : pt_.x, ya = own ? ys : pt_.y, za = own ? zs : pt_.z;
+      const double xb = own ? pt_.x : xs, yb = own ? pt_.y : ys, zb = own ? pt_.z : zs;
+      const float raf = own ? rsf : pt_.r, rbf = own ? pt_.r : rsf;
+      const double dx = xb - xa, dy = yb - ya, dz = zb - za;
       const double d2 = dist2_exact(dx, dy, dz);
-      const double S = (double)rsf + (double)a.pos.r[t];
-      const Real rt = (Real)a.pos.r[t];
-      const Real vt_[3] = {VI[0][t], VI[1][t], VI[2][t]};
-      const Real wt_[3] = {WI[0][t], WI[1][t], WI[2][t]};
-      const Real mt = mass_of<Real>(c, rt);
+      const double S = (double)raf + (double)rbf;
+      const Real ra = (Real)raf, rb = (Real)rbf;
+      const Real ma = mass_of<Real>(c, ra), mb = mass_of<Real>(c, rb);
       const Real dd = sqrt((Real)d2);
       const Real invd = (Real)1 / dd;
       n[0] = (Real)dx * invd;
       n[1] = (Real)dy * invd;
       n[2] = (Real)dz * invd;
       delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
-      R = rs * rt / (rs + rt);
-      const Real M = ms * mt / (ms + mt);
+      R = ra * rb / (ra + rb);
+      const Real M = ma * mb / (ma + mb);
       Real v[3], spin[3];
 #pragma unroll
       for (int i = 0; i < 3; i++) {
-        v[i] = vs[i] - vt_[i];
-        spin[i] = rs * ws[i] + rt * wt_[i];
+        const Real va = own ? vs[i] : pt_.v[i], vb = own ? pt_.v[i] : vs[i];
+        const Real wa = own ? ws[i] : pt_.w[i], wb = own ? pt_.w[i] : ws[i];
+        v[i] = va - vb;
+        spin[i] = ra * wa + rb * wb;
       }
       contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
     } else {
       // Step 8: wall -1 - t, a particle of infinite radius
+      if (LAW != DEM_LAW_SIMPLE) hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
       const int w = -1 - t;
       const int ax = w >> 1;
       const double xw[3] = {xs, ys, zs};
@@ -801,93 +973,33 @@ __global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
       for (int i = 0; i < 3; i++) spin[i] = rs * ws[i];
       contact_law<Real, LAW>(c, n, delta, rs, ms, vs, spin, h, o);
     }
-    V4 f, tq;
-    f.x = o.F[0];
-    f.y = o.F[1];
-    f.z = o.F[2];
-    f.w = 0;
-    tq.x = n[1] * o.Ft[2] - n[2] * o.Ft[1];
-    tq.y = n[2] * o.Ft[0] - n[0] * o.Ft[2];
-    tq.z = n[0] * o.Ft[1] - n[1] * o.Ft[0];
-    tq.w = 0;
-    ((V4 *)a.w.pf)[2 * (int64_t)q] = f;
-    ((V4 *)a.w.pf)[2 * (int64_t)q + 1] = tq;
-    if (write_hist) {
-      V4 d;
-      d.x = o.dtn[0];
-      d.y = o.dtn[1];
-      d.z = o.dtn[2];
-      d.w = 0;
-      ((V4 *)a.cur.dt)[q] = d;
+    const Real tq[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
+                        n[0] * o.Ft[1] - n[1] * o.Ft[0]};
+    if (own) {
+      F[0] += o.F[0];
+      F[1] += o.F[1];
+      F[2] += o.F[2];
+    } else {
+      F[0] -= o.F[0];
+      F[1] -= o.F[1];
+      F[2] -= o.F[2];
     }
-    if (diag) {
-      a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
-      a.w.pd[q] = (double)delta;
-    }
-  }
-}
-
-// One lane per particle: contact sums in a fixed order (contacts with lower
-// slots, ascending; with higher slots, ascending; walls), then the closing
-// half kick of Step 1 and, when the system steps again in this call, the
-// next step's opening kick, drift and hash.
-template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
-  using V4 = typename Vec4T<Real>::type;
-  int32_t k;
-  const int32_t s = block_slot(a.L, k);
-  if (s < 0) return;
-  const SysInfo &si = a.L.tab[k];
-  const Consts &c = si.c;
-  const bool stepping = (a.mode & MODE_KICK) != 0;
-  if (stepping && !is_active(a.ctl, k)) {
-    // a finished system: carry its velocities into the other buffer; the
-    // next sort sees its current cells
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-      ((Real *)a.vel_out.v[q])[s] = ((const Real *)a.vel_in.v[q])[s];
-      ((Real *)a.vel_out.w[q])[s] = ((const Real *)a.vel_in.w[q])[s];
-    }
-    a.cell[s] = a.scell[s];
-    return;
-  }
-  const int64_t cap = a.w.Pcap;
-  const Real rs = (Real)a.pos.r[s];
-  const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
-  Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  const int32_t b0 = a.w.bofs[s], b1 = a.w.bofs[s + 1];
-  const int32_t nb = (int64_t)b1 <= cap ? b1 - b0 : 0;
-  sort_list(a.w.bwd + b0, nb);
-  for (int32_t i = 0; i < nb; i++) {
-    const int32_t q = a.w.bwd[b0 + i];
-    const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
-    F[0] -= f.x;
-    F[1] -= f.y;
-    F[2] -= f.z;
-    T[0] += rs * m.x;  // Eq. 3; the same n x F_t on both bodies
-    T[1] += rs * m.y;
-    T[2] += rs * m.z;
-  }
-  const int64_t f0 = a.cur.ofs[s];
-  const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
-  double e_el = 0.0, dmax = 0.0;
-  int32_t npair = 0, nwall = 0;
-  const bool diag = (a.mode & MODE_DIAG) != 0;
-  for (int64_t q = f0; q < f1; q++) {
-    const V4 f = pf[2 * q], m = pf[2 * q + 1];
-    F[0] += f.x;
-    F[1] += f.y;
-    F[2] += f.z;
-    T[0] += rs * m.x;
-    T[1] += rs * m.y;
-    T[2] += rs * m.z;
-    if (diag) {
-      e_el += a.w.pe[q];
-      dmax = fmax(dmax, a.w.pd[q]);
-      if (a.cur.t[q] >= 0)
-        npair++;
-      else
-        nwall++;
+    T[0] += rs * tq[0];  // Eq. 3; the same n x F_t on both bodies
+    T[1] += rs * tq[1];
+    T[2] += rs * tq[2];
+    if (own) {
+      if (write_hist) {
+        const int64_t q = q0 + (j - nl);
+        if (q < cap) put_entry<Real>(a.cur, q, o.dtn, t);
+      }
+      if (diag) {
+        e_el += elastic_energy<Real, LAW>(c, delta, R, o, h);
+        dmax = fmax(dmax, (double)delta);
+        if (t >= 0)
+          npair++;
+        else
+          nwall++;
+      }
     }
   }
   if (!(isfinite((double)F[0]) && isfinite((double)F[1]) && isfinite((double)F[2]) &&
@@ -899,20 +1011,22 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     ((Real *)a.T[q])[s] = T[q];
   }
   if (stepping) {
-    const Real *VI[3] = {(const Real *)a.vel_in.v[0], (const Real *)a.vel_in.v[1], (const Real *)a.vel_in.v[2]};
-    const Real *WI[3] = {(const Real *)a.vel_in.w[0], (const Real *)a.vel_in.w[1], (const Real *)a.vel_in.w[2]};
-    Real v[3] = {VI[0][s], VI[1][s], VI[2][s]}, w[3] = {WI[0][s], WI[1][s], WI[2][s]};
-    const Real m = mass_of<Real>(c, rs);
-    const Real I = (Real)0.4 * m * rs * rs;
-    half_kick<Real>(c, m, I, F, T, v, w);
+    Real v[3] = {vs[0], vs[1], vs[2]}, w[3] = {ws[0], ws[1], ws[2]};
+    const Real I = (Real)0.4 * ms * rs * rs;
+    half_kick<Real>(c, ms, I, F, T, v, w);
     if (*a.ctl.step + 1 < a.ctl.left[k]) {
       // the next step's Steps 1-2 with the same forces: the same operations
       // as k_kick_drift_hash, so fusing changes no bit
-      half_kick<Real>(c, m, I, F, T, v, w);
-      drift_hash(a.pos, s, v, c, si.g, a.cell, a.err);
+      half_kick<Real>(c, ms, I, F, T, v, w);
+      drift_hash_to(xs, ys, zs, a.pos_out, s, v, c, si.g, a.cell, a.err);
     } else {
-      a.cell[s] = a.scell[s];  // its last step in this call: it stops here
+      a.pos_out.x[s] = xs;  // its last step in this call: it stops here
+      a.pos_out.y[s] = ys;
+      a.pos_out.z[s] = zs;
+      a.cell[s] = a.scell[s];
     }
+    a.pos_out.r[s] = rsf;
+    a.pos_out.id[s] = a.pos.id[s];
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)a.vel_out.v[q])[s] = v[q];
@@ -1035,12 +1149,22 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
 
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          float4 *xyzr, hipStream_t st) {
+                          const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, xyzr);
+    k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, nb, old_ofs);
   else
-    k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, xyzr);
+    k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, nb, old_ofs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const NbrBuf &nb,
+                       hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
+  if (precision == DEM_PREC_FP64)
+    k_pack<double><<<L.nblocks, kBlock, 0, st>>>(L, p, v, nb);
+  else
+    k_pack<float><<<L.nblocks, kBlock, 0, st>>>(L, p, v, nb);
   return hipGetLastError();
 }
 
@@ -1049,38 +1173,30 @@ hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st) {
+hipError_t launch_force(int precision, const PairArgs &a, hipStream_t st) {
   if (a.L.n <= 0) return hipSuccess;
   const bool f64 = precision == DEM_PREC_FP64;
+  const unsigned nb = (unsigned)a.L.nblocks;
   switch (a.law) {
     case DEM_LAW_HERTZ:
       if (f64)
-        k_pair_force<double, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
+        k_force<double, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
       else
-        k_pair_force<float, DEM_LAW_HERTZ><<<2048, kBlock, 0, st>>>(a);
+        k_force<float, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
       break;
     case DEM_LAW_SIMPLE:
       if (f64)
-        k_pair_force<double, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
+        k_force<double, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
       else
-        k_pair_force<float, DEM_LAW_SIMPLE><<<2048, kBlock, 0, st>>>(a);
+        k_force<float, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
       break;
     default:
       if (f64)
-        k_pair_force<double, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
+        k_force<double, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
       else
-        k_pair_force<float, DEM_LAW_LINEAR><<<2048, kBlock, 0, st>>>(a);
+        k_force<float, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
       break;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st) {
-  if (a.L.n <= 0) return hipSuccess;
-  if (precision == DEM_PREC_FP64)
-    k_gather<double><<<a.L.nblocks, kBlock, 0, st>>>(a);
-  else
-    k_gather<float><<<a.L.nblocks, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

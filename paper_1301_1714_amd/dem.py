@@ -26,8 +26,8 @@ DEM_E_HIP = -6
 DEM_E_STATE = -7
 DEM_E_CAPACITY = -9
 
-NUM_PHASES = 7
-PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "pair_force", "gather")
+NUM_PHASES = 6
+PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "force")
 
 _LIB = None
 
@@ -50,6 +50,7 @@ class DemParams(C.Structure):
         ("simple_k", C.c_double * 3),
         ("cell_size", C.c_double),
         ("contacts_per_particle", C.c_int32), ("precision", C.c_int32),
+        ("tile_cells", C.c_int32),
     ]
 
 
@@ -118,6 +119,7 @@ def make_params(p: dict) -> DemParams:
     o.cell_size = float(p["cell_size"])
     o.contacts_per_particle = int(p.get("contacts_per_particle", 16))
     o.precision = PRECISIONS[p.get("precision", "fp64")]
+    o.tile_cells = int(p.get("tile_cells", 0))
     return o
 
 

@@ -12,9 +12,10 @@ def test_class_keys_and_representatives():
 
 
 def test_table_lookup_and_roundtrip(tmp_path):
-    t = autotune.Table({"n10_phi0": {"factor": 1.5}})
-    assert t.factor(1000, 0.21) == 1.5
-    assert t.factor(5000, 0.21) == 1.0  # unknown class: the minimum cell
+    t = autotune.Table({"n10_phi0": {"factor": 1.5, "tile": 8}})
+    assert t.factor(1000, 0.21) == 1.5 and t.tile(1000, 0.21) == 8
+    assert t.factor(5000, 0.21) == 1.0  # unknown class: the minimum cell, direct detection
+    assert t.tile(5000, 0.21) == 0
     p = str(tmp_path / "a.json")
     t.save(p)
     assert autotune.Table.load(p).entries == t.entries

@@ -258,3 +258,41 @@ def test_contact_list_overflow_is_reported(dem):
         g.step(1)
         g.sync()
     assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
+
+
+@pytest.mark.parametrize("tile,cell_scale", [(1, 1.0), (5, 1.0), (32, 1.0), (32, 4.0)])
+@pytest.mark.parametrize("name", ["fp64_partial_walls_5000", "mixed_nowalls_poly_4097", "mixed_hertz_2500"])
+def test_tiled_detection_is_bit_identical(dem, name, tile, cell_scale):
+    # tile_cells selects the detection launch shape only: the same lists, so
+    # the same forces and trajectories to the bit.  cell_scale 4 packs so many
+    # particles per cell that the tile's rows overflow LDS and are read from
+    # global memory instead.
+    c = cloud(**CASES[name])
+    p = dict(c["params"], mu=0.2, eta_t_ratio=0.5, dt=2e-6, cell_size=cell_scale * c["params"]["cell_size"])
+    a = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    b = dem.System(dict(p, tile_cells=tile), c["x"], c["v"], c["omega"], c["r"])
+    assert np.array_equal(a.contacts(), b.contacts())
+    Fa, Ta = a.forces()
+    Fb, Tb = b.forces()
+    assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb)
+    a.step(6)
+    b.step(6)
+    sa, sb = a.read_state(), b.read_state()
+    for key in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(sa[key], sb[key]), key
+    # and the tiled lists are the oracle's on the state reached
+    o = OracleSystem(p, sb["x"], sb["v"], sb["omega"], c["r"])
+    assert np.array_equal(b.contacts(), o.contacts())
+
+
+def test_profile_phases_cover_the_step(dem):
+    import torch
+    c = cloud(seed=9, n=3000, precision="mixed")
+    s = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    s.profile(True)
+    torch.cuda.synchronize()
+    s.step(10)
+    ms, n = s.profile_read()
+    assert n == 10 and len(ms) == dem.NUM_PHASES and np.all(ms >= 0) and ms.sum() > 0
+    ms2, n2 = s.profile_read()
+    assert n2 == 0 and np.all(ms2 == 0)
