@@ -92,23 +92,21 @@ def copy_probe(mib, reps):
 # launch; neighbour data reused from LDS or cache is not counted.  R is the
 # size of a Real (4 with FP32 forces, 8 in FP64).
 
-def detect_bytes(n, ncell, c_list):
+def detect_bytes(n, ncell, c_own):
     """k_detect: per particle its FP32 copy (x, y, z, r: 16 B), its FP64
-    position (24 B) and cell (4 B) read, its two counts (8 B) and c_list
-    list entries (4 B each: every partner, both ways, and the walls)
-    written; the cell starts read once."""
-    return n * (52 + 4 * c_list) + 4 * (ncell + 1)
+    position (24 B) and cell (4 B) read, its count (4 B) and c_own list
+    entries (4 B each: partners with higher slots, walls) written; the cell
+    starts read once."""
+    return n * (48 + 4 * c_own) + 4 * (ncell + 1)
 
 
-def force_bytes(n, c_list, c_own, R):
-    """k_force: per particle its state read (x 24 B, r 4, id 4, v and w 6R),
-    its old slot and history offset (8 B), its two counts (8 B) and its list
-    (4 B per entry); written: force and torque (6R), v and w (6R), the
-    position for the next step (x, r, id: 32 B) and its cell (4 B); per
-    owned contact the committed history read (key 4 B, delta_t 3R) and the
-    new delta_t written (3R).  Partner state is reuse (cache)."""
-    per = (32 + 6 * R) + 8 + 8 + 6 * R + 6 * R + 32 + 4
-    return n * (per + 4 * c_list) + n * c_own * (4 + 6 * R)
+def pair_force_bytes(n, P, R):
+    """k_pair_force: per contact its two slots (8 B), the committed history
+    read (key 4 B, delta_t 3R), the new entry written (key 4 B, delta_t 3R)
+    and the force and torque term written (6R); per particle its packed
+    state (x 24 B, r 4 B, v and w 6R) and its history index (12 B) read
+    once.  Partner reads are reuse."""
+    return P * (16 + 12 * R) + n * (40 + 6 * R)
 
 
 def step_algorithmic_bytes(n, z, R):
@@ -193,10 +191,9 @@ def bench_dense(args):
     P = pairs + walls
     Z = 2.0 * pairs / n
     R = 4 if p["precision"] == "mixed" else 8
-    c_list = (2.0 * pairs + walls) / n
     kernels = {
-        "k_detect": ("detect", detect_bytes(n, ncell, c_list)),
-        "k_force": ("force", force_bytes(n, c_list, P / n, R)),
+        "k_detect": ("detect", detect_bytes(n, ncell, P / n)),
+        "k_pair_force": ("pair_force", pair_force_bytes(n, P, R)),
     }
     name = max(kernels, key=lambda k: phase_ms[kernels[k][0]])
     ph, nbytes = kernels[name]

@@ -167,15 +167,15 @@ dem_status dem_set_radii(dem_system *s, const double *r);
  * the stream, returns the milliseconds spent in each phase summed over the
  * steps timed since the previous read (and their number), then clears them.
  * Phases: 0 kick-drift-hash of a call's first step (Steps 1-2; later steps
- * do it inside phase 5), 1 sort and cell starts (Step 3), 2 reorder
+ * do it inside phase 6), 1 sort and cell starts (Step 3), 2 reorder
  * (Step 4), 3 contact detection over the neighbouring cells (Steps 5-6),
- * 4 keys of the new tangential-history table, 5 contact forces, sums,
- * closing kick and the next step's kick-drift-hash (Steps 7-8, 1-2).
- * Phases 3 and 5 are one kernel each (detection: one per launch shape in
- * use).  With graph replay the whole step after phase 0 is counted in
- * phase 5.  At most DEM_PROFILE_CAPACITY steps are timed between two
- * reads. */
-#define DEM_NUM_PHASES 6
+ * 4 compact contact array and its backward index, 5 contact law once per
+ * contact (Steps 7-8), 6 per-particle sums, closing kick and the next
+ * step's kick-drift-hash.  Phases 3 and 5 are one kernel each (detection:
+ * one per launch shape in use).  With graph replay the whole step after
+ * phase 0 is counted in phase 6.  At most DEM_PROFILE_CAPACITY steps are
+ * timed between two reads. */
+#define DEM_NUM_PHASES 7
 #define DEM_PROFILE_CAPACITY 4096
 dem_status dem_profile(dem_system *s, int enable);
 dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps);

@@ -57,6 +57,7 @@ struct Engine {
   ScanScratch scan{};
   NbrBuf nbr{};
   PairGen gen[2];
+  PairWork work{};
   DiagBuf diag{};
   int32_t *err = nullptr;
   hipStream_t stream = nullptr;
@@ -260,15 +261,23 @@ size_t carve(Engine &e, char *base) {
     e.scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
   }
   e.nbr.xyzr = cv.take<float4>(N);
-  e.nbr.nlow = cv.take<int32_t>(N);
   e.nbr.fcnt = cv.take<int32_t>(N);
   e.nbr.pst = cv.take_bytes((e.prec == DEM_PREC_FP64 ? sizeof(PState<double>) : sizeof(PState<float>)) * N);
   e.nbr.hix = cv.take<int4>(N);
   e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
   for (int b = 0; b < 2; b++) {
     e.gen[b].ofs = cv.take<int32_t>(N + 1);
+    e.gen[b].s = cv.take<int32_t>(P);
+    e.gen[b].t = cv.take<int32_t>(P);
     e.gen[b].ent = cv.take_bytes(4 * R * P);
   }
+  e.work.pf = cv.take_bytes(8 * R * P);
+  e.work.brank = cv.take<int32_t>(P);
+  e.work.pe = cv.take<double>(P);
+  e.work.pd = cv.take<double>(P);
+  e.work.bcnt = cv.take<int32_t>(N);
+  e.work.bofs = cv.take<int32_t>(N + 1);
+  e.work.bwd = cv.take<int32_t>(P);
   e.diag.e_el = cv.take<double>(N);
   e.diag.npair = cv.take<int32_t>(N);
   e.diag.nwall = cv.take<int32_t>(N);
@@ -365,14 +374,20 @@ void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, s
 hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after_detect = nullptr) {
   e.gs = g;
   const Layout L = e.layout();
-  hipError_t r = launch_detect(L, ctl, e.pos[e.cp], e.nbr, e.scell, e.cell_start, e.err, e.stream);
+  hipError_t r = launch_detect(e.prec, L, ctl, e.nbr, e.scell, e.cell_start, e.err, e.stream);
   if (r != hipSuccess) return r;
   if (after_detect) (void)hipEventRecord(after_detect, e.stream);
-  return launch_list(e.prec, L, e.nbr, e.gen[g], e.Pcap, e.scan, e.err, e.stream);
+  return launch_list(e.prec, L, e.nbr, e.gen[g], e.work, e.Pcap, e.scan, e.err, e.stream);
 }
 
-// Steps 7-8, the per-particle sums and (in a time step) the kicks
-hipError_t run_forces(Engine &e, const PairArgs &a) { return launch_force(e.prec, a, e.stream); }
+// Steps 7-8 once per contact, then the per-particle sums (and, in a time
+// step, the kicks)
+hipError_t run_forces(Engine &e, const PairArgs &a, hipEvent_t after_law = nullptr) {
+  hipError_t r = launch_pair_force(e.prec, a, e.stream);
+  if (r != hipSuccess) return r;
+  if (after_law) (void)hipEventRecord(after_law, e.stream);
+  return launch_gather(e.prec, a, e.stream);
+}
 
 // Steps 7-8 on the contact list of generation gs, with the committed history
 // of generation gc
@@ -388,6 +403,7 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.nb = e.nbr;
   a.cur = e.gen[e.gs];
   a.old = e.gen[e.gc];
+  a.w = e.work;
   a.cap = e.Pcap;
   a.perm = e.perm;
   for (int k = 0; k < 3; k++) {
@@ -642,7 +658,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   HIP_TRY(launch_hash(L, e.pos[0], e.cell, e.err, e.stream));
   HIP_TRY(launch_sort(e.cell, e.pos[0].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
                       e.stream));
-  HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], e.perm, e.cell, e.scell, e.nbr,
+  HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], true, e.perm, e.cell, e.scell, e.nbr,
                          nullptr, e.stream));
   e.cp = 1;
   e.cv = 1;
@@ -715,8 +731,9 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
     return r;
   mark(2);
   // Step 4
-  if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], e.perm, e.cell,
-                          e.scell, e.nbr, e.gen[e.gc].ofs, e.stream)) != hipSuccess)
+  // (the state goes into the packed records only; the gather writes it back)
+  if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], false, e.perm,
+                          e.cell, e.scell, e.nbr, e.gen[e.gc].ofs, e.stream)) != hipSuccess)
     return r;
   e.cp ^= 1;
   e.cv ^= 1;
@@ -727,9 +744,9 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   mark(5);
   // Steps 7-8 and the closing half kick; the new history is committed
   PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);
-  if ((r = run_forces(e, a)) != hipSuccess) return r;
+  if ((r = run_forces(e, a, ev ? ev[6] : nullptr)) != hipSuccess) return r;
   if ((r = launch_step_end(e.ctl, e.stream)) != hipSuccess) return r;
-  mark(6);
+  mark(7);
   e.cp ^= 1;
   e.cv ^= 1;
   e.gc = e.gs;
@@ -1113,6 +1130,7 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
   for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
   if ((st = h2d(e, e.pos[e.cp].r, slot_r)) != DEM_OK) return st;
   HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr.xyzr, e.stream));
+  HIP_TRY(launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream));
   // the contact list of the new radii, beside the committed history
   HIP_TRY(build_contacts(e, e.gc ^ 1, nullptr));
   return sync_and_check(e);

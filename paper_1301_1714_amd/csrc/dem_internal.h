@@ -15,19 +15,20 @@
 //   psys     system of each slot; bsys/bfirst: system and first slot of each
 //            kernel block (blocks never straddle two systems)
 //   nbr      detection output: xyzr (FP32 copy of x - lo and r, the
-//            prefilter's input) and, per particle, its contacts in ascending
-//            slot order -- nlow with lower slots, then those with higher
-//            slots -- followed by its walls (-1 - w); fcnt counts the last two
+//            prefilter's input) and, per particle, its contacts with higher
+//            slots in ascending order followed by its walls (-1 - w)
 //   pst      the law's inputs per particle, packed (PState<Real>); hix the
 //            previous slot and committed history segment of each slot
 //   tiles    detection work items: (system, row, first cell, last cell)
-//   gen[2]   two generations of the tangential-history table, CSR by owner
-//            slot (the lower slot of a pair; the particle for a wall):
-//            ofs[N + 1], per contact one Real4 entry: delta_t as seen from
-//            the owner in x, y, z and the key (partner slot or -1 - w, its
-//            bits) in w, so that one load brings both.  One generation holds
-//            the committed history, the other is written for the new
-//            positions.
+//   gen[2]   two generations of the compact contact array, CSR by owner slot
+//            (the lower slot of a pair; the particle for a wall): ofs[N + 1],
+//            per contact the owner s and partner t (slot or -1 - w), and one
+//            Real4 entry of the tangential-history table: delta_t as seen
+//            from the owner in x, y, z and the key (t, its bits) in w, so
+//            that one load brings both.  One generation holds the committed
+//            history, the other is built for the new positions.
+//   work     per-contact force on the owner and n x F_t (2 x Real4), and the
+//            backward CSR (contacts of each particle as the partner)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -49,7 +50,7 @@ enum ModeBits : int32_t {
 };
 
 constexpr int32_t kBlock = 256;
-constexpr int32_t kListCap = 64;  // detection: contacts per particle (both directions + walls)
+constexpr int32_t kListCap = 64;  // detection: contacts per particle (higher partners + walls)
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 
 struct Grid {
@@ -106,13 +107,12 @@ struct alignas(16) PState {
   double x, y, z;
   Real v[3], w[3];
   float r;
-  int32_t pad;
+  int32_t id;
 };
 
 struct NbrBuf {
   float4 *xyzr;   // [N] (x - lo, y - lo, z - lo, r), FP32
-  int32_t *nlow;  // [N] entries of nb with lower slots
-  int32_t *fcnt;  // [N] entries after those (higher slots, walls); nlow + fcnt <= kListCap
+  int32_t *fcnt;  // [N] entries of nb (clamped to kListCap)
   int32_t *nb;    // [kListCap][N]
   void *pst;      // [N] PState<Real> of the current slots
   int4 *hix;      // [N] time steps: (previous slot, its committed history segment begin, end, 0)
@@ -120,7 +120,19 @@ struct NbrBuf {
 
 struct PairGen {
   int32_t *ofs;  // [N + 1]
+  int32_t *s;    // [Pcap] owner slot
+  int32_t *t;    // [Pcap] partner slot or -1 - w
   void *ent;     // [Pcap] Real4: delta_t (x, y, z), key bits (w)
+};
+
+struct PairWork {
+  void *pf;        // [2 Pcap] Real4: force on the owner, then n x F_t
+  int32_t *brank;  // [Pcap] rank of the contact in its partner's backward list
+  double *pe;      // [Pcap] elastic energy (diagnostics)
+  double *pd;      // [Pcap] overlap (diagnostics)
+  int32_t *bcnt;   // [N] backward counts
+  int32_t *bofs;   // [N + 1]
+  int32_t *bwd;    // [Pcap] contact indices grouped by partner
 };
 
 struct DiagBuf {
@@ -152,8 +164,9 @@ struct PairArgs {
   PosBuf pos;            // current positions
   PosBuf pos_out;        // time steps: positions after the step (drifted for the next one)
   VelBuf vel_in, vel_out;
-  NbrBuf nb;             // contact lists of the current positions
-  PairGen cur, old;      // cur: history table being written; old: committed history
+  NbrBuf nb;             // packed state and history index of the current slots
+  PairGen cur, old;      // cur: contacts of the current positions; old: committed history
+  PairWork w;
   int64_t cap;           // contacts a table holds
   const int32_t *perm;   // with MODE_OLD_PERM: current slot -> slot of `old`
   void *F[3], *T[3];
@@ -178,23 +191,28 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
                                   int32_t *cell, int32_t *err, hipStream_t st);
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
-// (also packs nb.pst; old_ofs: offsets of the committed history, whose
-// segments are recorded per new slot in nb.hix; nullptr: none)
+// Step 4 into the packed records nb.pst (and, with soa, into dst / vdst as
+// well; a time step leaves that to its gather); old_ofs: offsets of the
+// committed history, whose segments are recorded per new slot in nb.hix
+// (nullptr: none)
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
-                          const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
+                          const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st);
 hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st);
 // nb.pst from the current buffers (before a force evaluation outside a step)
 hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const NbrBuf &nb,
                        hipStream_t st);
 // Steps 5-6: detection (all systems, or with ctl only the active ones; the
-// others keep their lists), then the compact contact list of `gen`
-hipError_t launch_detect(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+// others keep their lists), then the compact contact array of `gen` and its
+// backward index
+hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
                          const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st);
-hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, int64_t cap,
-                       const ScanScratch &sc, int32_t *err, hipStream_t st);
-// Steps 7-8: contact forces, per-particle sums and (in a time step) the kicks
-hipError_t launch_force(int precision, const PairArgs &a, hipStream_t st);
+hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                       int64_t cap, const ScanScratch &sc, int32_t *err, hipStream_t st);
+// Steps 7-8: the law once per contact, then per-particle sums and (in a time
+// step) the kicks
+hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st);
+hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st);
 hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,
                               hipStream_t st);

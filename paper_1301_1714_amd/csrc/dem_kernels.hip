@@ -338,40 +338,40 @@ __device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, d
 
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
-                                                    const int32_t *__restrict__ perm,
+                                                    int32_t soa, const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
                                                     NbrBuf nb, const int32_t *__restrict__ old_ofs) {
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
   const int32_t p = perm[s];
-  const double x = src.x[p], y = src.y[p], z = src.z[p];
-  const float r = src.r[p];
-  dst.x[s] = x;
-  dst.y[s] = y;
-  dst.z[s] = z;
-  dst.r[s] = r;
-  dst.id[s] = src.id[p];
-  nb.xyzr[s] = make_xyzr(L.tab[k].g, x, y, z, r);
-#pragma unroll
-  for (int q = 0; q < 3; q++) {
-    ((Real *)vdst.v[q])[s] = ((const Real *)vsrc.v[q])[p];
-    ((Real *)vdst.w[q])[s] = ((const Real *)vsrc.w[q])[p];
-  }
-  scell[s] = cell[p];
   PState<Real> ps;
-  ps.x = x;
-  ps.y = y;
-  ps.z = z;
+  ps.x = src.x[p];
+  ps.y = src.y[p];
+  ps.z = src.z[p];
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     ps.v[q] = ((const Real *)vsrc.v[q])[p];
     ps.w[q] = ((const Real *)vsrc.w[q])[p];
   }
-  ps.r = r;
-  ps.pad = 0;
+  ps.r = src.r[p];
+  ps.id = src.id[p];
   ((PState<Real> *)nb.pst)[s] = ps;
+  nb.xyzr[s] = make_xyzr(L.tab[k].g, ps.x, ps.y, ps.z, ps.r);
+  scell[s] = cell[p];
   if (old_ofs) nb.hix[s] = make_int4(p, old_ofs[p], old_ofs[p + 1], 0);
+  if (soa) {
+    dst.x[s] = ps.x;
+    dst.y[s] = ps.y;
+    dst.z[s] = ps.z;
+    dst.r[s] = ps.r;
+    dst.id[s] = ps.id;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      ((Real *)vdst.v[q])[s] = ps.v[q];
+      ((Real *)vdst.w[q])[s] = ps.w[q];
+    }
+  }
 }
 
 template <typename Real>
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
     ps.w[q] = ((const Real *)vel.w[q])[s];
   }
   ps.r = pos.r[s];
-  ps.pad = 0;
+  ps.id = pos.id[s];
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
@@ -403,108 +403,143 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__r
 // --------------------------------------------------------------------------
 // Steps 5-6: contact detection over the 27 cells of Eq. 12.
 //
-// Each particle visits the 9 rows of cells around its own (the three cells
-// of a row are one contiguous slot range after the sort).  A row, or an end
-// cell of a row, whose box lies farther than r_i + r_max from the particle is
-// skipped: a conservative bound (margin 2 eps covers the FP32 rounding of the
-// coordinates and the cell faces), so it never skips a contact.  Candidates
-// pass a conservative FP32 test; the few survivors are decided exactly in
-// FP64.  Rows are visited in (z, y) order and cells in x order, so the
-// contacts come out in ascending slot order: the partners with lower slots,
-// then those with higher slots, then the walls.  The tests are symmetric, so
-// both particles of a pair find each other.
+// Each pair is tested once, by its lower slot: a particle visits the
+// forward half of its 27 cells -- the rest of its own row of cells after
+// itself, the next row along y, the three rows of the next plane along z
+// (after the sort each row's three cells are one contiguous slot range).  A
+// row, or an end cell of a row, whose box lies farther than r_i + r_max from
+// the particle is skipped: a conservative bound (margin 2 eps covers the
+// FP32 rounding of the coordinates and the cell faces), so it never skips a
+// contact.  Candidates pass a conservative FP32 test; the few survivors are
+// decided exactly in FP64.  Rows are visited in (z, y) order and cells in x
+// order, so the contacts come out in ascending slot order, then the walls.
 //
 // Two launch shapes build the same lists: the direct one (one lane per
 // particle, candidates read through the caches) and the tiled one (one
-// workgroup per run of cells along x stages the FP32 copies of the 9 rows
-// around it in LDS first).  A system's tile_cells selects the shape.
+// workgroup per run of cells along x stages the FP32 copies of the rows it
+// needs in LDS first).  A system's tile_cells selects the shape.
 
 constexpr int kTileThreads = 128;
 constexpr int kHaloCap = 1024;  // particles staged per tile; a fuller tile reads global memory
 constexpr int kSurv = 8;        // LDS survivor slots per lane
+constexpr int kUnroll = 2;      // candidates per pipeline stage
+
+// FP64 position and FP32 radius of slot t, from its packed record (the
+// same layout for both Real types up to the radius' offset)
+struct XR {
+  double x, y, z;
+  float r;
+};
+__device__ __forceinline__ XR state_xr(const NbrBuf &nb, bool f64, int32_t t) {
+  XR o;
+  if (f64) {
+    const PState<double> &q = ((const PState<double> *)nb.pst)[t];
+    o.x = q.x;
+    o.y = q.y;
+    o.z = q.z;
+    o.r = q.r;
+  } else {
+    const PState<float> &q = ((const PState<float> *)nb.pst)[t];
+    o.x = q.x;
+    o.y = q.y;
+    o.z = q.z;
+    o.r = q.r;
+  }
+  return o;
+}
 
 // exact FP64 decision on one prefilter survivor (the contact test of Step 7)
-__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s,
-                                                 float ri, double xi, double yi, double zi, int32_t t,
-                                                 int32_t &nf, int32_t &nl) {
-  const double ex = pos.x[t] - xi, ey = pos.y[t] - yi, ez = pos.z[t] - zi;
-  const double S = (double)ri + (double)pos.r[t];
+__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int32_t N, int32_t s, float ri,
+                                                 double xi, double yi, double zi, int32_t t, int32_t &nf) {
+  const XR q = state_xr(nb, f64, t);
+  const double ex = q.x - xi, ey = q.y - yi, ez = q.z - zi;
+  const double S = (double)ri + (double)q.r;
   if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
   if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = t;
   nf++;
-  nl += t < s ? 1 : 0;
-}
-
-constexpr int kUnroll = 2;  // candidates loaded together
-
-// a full survivor buffer, decided in order (rare: kept out of line)
-template <int kLanes>
-__device__ __forceinline__ void drain_survivors(const NbrBuf &nb, const PosBuf &pos, int32_t N, int32_t s, float ri,
-                                             double xi, double yi, double zi, const int32_t *surv, int32_t &nf,
-                                             int32_t &nl) {
-  for (int j = 0; j < kSurv; j++) exact_and_record(nb, pos, N, s, ri, xi, yi, zi, surv[j * kLanes], nf, nl);
 }
 
 // One particle's sweep.  rows(r, ca, cb, beg, end, shift) gives the slot
-// range [beg, end) of cells ca..cb of row r and where its FP32 copies are
-// (slot t at rows.src[t - shift]); false for a row outside the grid.
-// Survivors wait in the lane's LDS slots (stride kLanes) so that the rare
-// exact test does not sit inside the candidate loop, where one lane taking
-// it would hold the whole wave.
+// range [beg, end) of cells ca..cb of row r (r = 3 (dz + 1) + dy + 1) and
+// where their FP32 copies are (slot t at rows.src[t - shift]); false for a
+// row outside the grid.  Survivors wait in the lane's LDS slots (stride
+// kLanes) so that the rare exact test does not sit inside the candidate
+// loop, where one lane taking it would hold the whole wave.
 template <int kLanes, typename Rows>
-__device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, const PosBuf &pos, int32_t N,
-                                               int32_t s, const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
+__device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N, int32_t s,
+                                               const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
                                                int32_t *surv, int32_t *err) {
   const float4 p = nb.xyzr[s];
-  const double xi = pos.x[s], yi = pos.y[s], zi = pos.z[s];
+  const XR me = state_xr(nb, f64, s);
+  const double xi = me.x, yi = me.y, zi = me.z;
   const float eps = si.eps;
   const int32_t nx = si.g.nc[0];
   const float wx = (float)(1.0 / si.g.sc[0]), wy = (float)(1.0 / si.g.sc[1]), wz = (float)(1.0 / si.g.sc[2]);
   const float cut = p.w + si.rmax + 2.0f * eps, cut2 = cut * cut;
   // distances to the faces of the own cell (0 for a particle outside it)
-  const float dxl = fmaxf(p.x - (float)cx * wx, 0.0f), dxh = fmaxf((float)(cx + 1) * wx - p.x, 0.0f);
+  const float dxh = fmaxf((float)(cx + 1) * wx - p.x, 0.0f);
   const float dyl = fmaxf(p.y - (float)cy * wy, 0.0f), dyh = fmaxf((float)(cy + 1) * wy - p.y, 0.0f);
-  const float dzl = fmaxf(p.z - (float)cz * wz, 0.0f), dzh = fmaxf((float)(cz + 1) * wz - p.z, 0.0f);
-  // the slot ranges of all 9 rows first: their loads overlap
-  int32_t beg[9], end[9], shift[9];
+  const float dzh = fmaxf((float)(cz + 1) * wz - p.z, 0.0f);
+  const float dxl = fmaxf(p.x - (float)cx * wx, 0.0f);
+  // the slot ranges of the 5 forward rows first, so that their loads overlap
+  int32_t beg[5], end[5], shift[5];
   const float4 *src = rows.src;
 #pragma unroll
-  for (int r = 0; r < 9; r++) {
+  for (int h = 0; h < 5; h++) {
+    const int r = 4 + h;
     const int dyr = (r % 3) - 1, dzr = (r / 3) - 1;
     const float dy = dyr < 0 ? dyl : (dyr > 0 ? dyh : 0.0f);
-    const float dz = dzr < 0 ? dzl : (dzr > 0 ? dzh : 0.0f);
+    const float dz = dzr > 0 ? dzh : 0.0f;
     const float dyz2 = dy * dy + dz * dz;
-    beg[r] = end[r] = shift[r] = 0;
+    beg[h] = end[h] = shift[h] = 0;
     if (!(dyz2 < cut2)) continue;
-    const int32_t ca = (cx > 0 && dxl * dxl + dyz2 < cut2) ? cx - 1 : cx;
+    const int32_t ca = (h > 0 && cx > 0 && dxl * dxl + dyz2 < cut2) ? cx - 1 : cx;
     const int32_t cb = (cx < nx - 1 && dxh * dxh + dyz2 < cut2) ? cx + 1 : cx;
-    if (!rows(r, ca, cb, beg[r], end[r], shift[r])) beg[r] = end[r] = 0;
+    if (!rows(r, ca, cb, beg[h], end[h], shift[h])) beg[h] = end[h] = 0;
   }
-  int32_t nf = 0, nl = 0, ns = 0;
+  beg[0] = s + 1;  // own row: the slots after the particle
+  const float pe = p.w + eps;
+  int32_t nf = 0, ns = 0;
 #pragma unroll
-  for (int r = 0; r < 9; r++) {
-    const int32_t e = end[r], sh = shift[r];
-    // kUnroll candidates per round, loaded together
-    for (int32_t t = beg[r]; t < e; t += kUnroll) {
+  for (int h = 0; h < 5; h++) {
+    const int32_t e = end[h], sh = shift[h];
+    int32_t t = beg[h];
+    while (t < e) {
+      // software pipeline: the next kUnroll candidates are in flight while
+      // the current ones are tested; the exact tests (global loads) stay
+      // outside this loop
       float4 q[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; u++) q[u] = src[(t + u < e ? t + u : t) - sh];
+      for (int u = 0; u < kUnroll; u++) q[u] = src[(uint32_t)(min(t + u, e - 1) - sh)];
+      for (;;) {
+        const int32_t tn = t + kUnroll;
+        float4 n[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; u++) {
-        const float ex = q[u].x - p.x, ey = q[u].y - p.y, ez = q[u].z - p.z;
-        const float sf = p.w + q[u].w + eps;
-        if (t + u < e && ex * ex + ey * ey + ez * ez < sf * sf && t + u != s) {
-          if (ns == kSurv) {
-            drain_survivors<kLanes>(nb, pos, N, s, p.w, xi, yi, zi, surv, nf, nl);
-            ns = 0;
-          }
-          surv[ns * kLanes] = t + u;
-          ns++;
+        for (int u = 0; u < kUnroll; u++) n[u] = q[u];
+        if (tn < e) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; u++) n[u] = src[(uint32_t)(min(tn + u, e - 1) - sh)];
         }
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+          const float dx = q[u].x - p.x, dy = q[u].y - p.y, dz = q[u].z - p.z, sf = pe + q[u].w;
+          if (t + u < e && dx * dx + dy * dy + dz * dz < sf * sf) {
+            surv[ns * kLanes] = t + u;
+            ns++;
+          }
+        }
+        t = tn;
+        if (t >= e || ns > kSurv - kUnroll) break;
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) q[u] = n[u];
+      }
+      if (ns > kSurv - kUnroll) {
+        for (int32_t j = 0; j < ns; j++) exact_and_record(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf);
+        ns = 0;
       }
     }
   }
-  for (int32_t j = 0; j < ns; j++) exact_and_record(nb, pos, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf, nl);
+  for (int32_t j = 0; j < ns; j++) exact_and_record(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf);
   // Step 8: walls, particles of infinite radius, after the pairs
   const uint32_t wall_mask = si.c.wall_mask;
   if (wall_mask) {
@@ -521,10 +556,7 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
     }
   }
   if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
-  const int32_t kept = nf < kListCap ? nf : kListCap;
-  const int32_t low = nl < kept ? nl : kept;
-  nb.nlow[s] = low;
-  nb.fcnt[s] = kept - low;
+  nb.fcnt[s] = nf < kListCap ? nf : kListCap;
 }
 
 struct DirectRows {
@@ -543,7 +575,7 @@ struct DirectRows {
   }
 };
 
-__global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl, int32_t only_active, PosBuf pos,
+__global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl, int32_t only_active, bool f64,
                                                           NbrBuf nb, const int32_t *__restrict__ scell,
                                                           const int32_t *__restrict__ cell_start, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
@@ -557,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
   const int32_t cc = scell[s] - si.g.c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
-  sweep_particle<kBlock>(rows, nb, pos, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, err);
+  sweep_particle<kBlock>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, err);
 }
 
 template <bool kStaged>
@@ -576,7 +608,7 @@ struct TileRows {
 };
 
 __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl ctl, int32_t only_active,
-                                                               PosBuf pos, NbrBuf nb,
+                                                               bool f64, NbrBuf nb,
                                                                const int32_t *__restrict__ scell,
                                                                const int32_t *__restrict__ cell_start,
                                                                int32_t *err) {
@@ -594,18 +626,19 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
   const int32_t x0 = tile.z, x1 = tile.w;
   const int32_t xa = x0 > 0 ? x0 - 1 : 0, xb = x1 < nx - 1 ? x1 + 1 : nx - 1;
   const int32_t wcs = xb - xa + 2;  // cell starts per row
+  // the own row and the 4 forward rows (rows 0-3 are not needed: empty)
   for (int32_t i = tid; i < 9 * wcs; i += kTileThreads) {
     const int32_t r = i / wcs, j = i - r * wcs;
     const int32_t yy = ry + (r % 3) - 1, zz = rz + (r / 3) - 1;
-    const bool in = yy >= 0 && yy < ny && zz >= 0 && zz < nz;
+    const bool in = r >= 4 && yy >= 0 && yy < ny && zz >= 0 && zz < nz;
     cs[r][j] = in ? cell_start[c0 + (zz * ny + yy) * nx + xa + j] : 0;
   }
   __syncthreads();
   const int32_t own_lo = cs[4][x0 - xa], own_hi = cs[4][x1 - xa + 1];
   if (own_lo == own_hi) return;
   TileRows<true> st;
-  st.cs = cs;
   st.src = halo;
+  st.cs = cs;
   st.xa = xa;
   int32_t total = 0;
 #pragma unroll
@@ -616,7 +649,7 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
   const bool staged = total <= kHaloCap;  // the same for every thread
   if (staged) {
 #pragma unroll
-    for (int r = 0; r < 9; r++) {
+    for (int r = 4; r < 9; r++) {
       const int32_t lo = cs[r][0], len = cs[r][wcs - 1] - lo;
       for (int32_t i = tid; i < len; i += kTileThreads) halo[lo - st.shift[r] + i] = nb.xyzr[lo + i];
     }
@@ -625,14 +658,14 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
   int32_t *surv = surv_all + tid;
   if (staged) {
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(st, nb, pos, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+      sweep_particle<kTileThreads>(st, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
   } else {
     TileRows<false> gr;
-    gr.cs = cs;
     gr.src = nb.xyzr;
+    gr.cs = cs;
     gr.xa = xa;
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(gr, nb, pos, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+      sweep_particle<kTileThreads>(gr, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
   }
 }
 
@@ -664,50 +697,131 @@ __device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Rea
   ((V4 *)g.ent)[q] = e;
 }
 
-// The higher-slot part of each list (and the walls) becomes the keys of the
-// CSR table (by owner: the lower slot) that will hold the new tangential
-// history; offsets come from a scan of the owned counts.
+// The lists become the compact contact array of `gen` (offsets from a scan
+// of the counts, the history keys in the table entries); each pair draws its
+// rank in the partner's backward list.
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, int64_t cap, int32_t n, int32_t *err) {
+__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int64_t cap, int32_t n,
+                                                  int32_t *err) {
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
-  const int32_t nl = nb.nlow[s], fc = nb.fcnt[s];
+  const int32_t cnt = nb.fcnt[s];
   const int64_t base = gen.ofs[s];
-  if (base + fc > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
+  if (base + cnt > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
   const Real zero[3] = {0, 0, 0};
-  for (int32_t j = 0; j < fc; j++) {
+  for (int32_t j = 0; j < cnt; j++) {
     const int64_t q = base + j;
     if (q >= cap) break;
-    put_entry<Real>(gen, q, zero, nb.nb[(int64_t)(nl + j) * n + s]);
+    const int32_t t = nb.nb[(int64_t)j * n + s];
+    gen.s[q] = s;
+    gen.t[q] = t;
+    put_entry<Real>(gen, q, zero, t);
+    if (t >= 0) w.brank[q] = atomicAdd(&w.bcnt[t], 1);
   }
 }
 
-hipError_t launch_detect(const Layout &L, const StepCtl *ctl, const PosBuf &p, const NbrBuf &nb,
+__device__ __forceinline__ int32_t num_pairs(const PairGen &gen, int32_t n, int64_t cap) {
+  const int32_t P = gen.ofs[n];
+  return (int64_t)P < cap ? P : (int32_t)cap;
+}
+
+// backward index: contact q is filed under its partner at the rank its
+// count drew (arrival order; the gather sorts each short segment)
+__global__ __launch_bounds__(kBlock) void k_bwd(PairGen gen, PairWork w, int64_t cap, int32_t n) {
+  const int32_t P = num_pairs(gen, n, cap);
+  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
+    const int32_t t = gen.t[q];
+    if (t < 0) continue;
+    w.bwd[w.bofs[t] + w.brank[q]] = q;
+  }
+}
+
+// fixed-size bitonic network on registers (indices are compile-time)
+template <int M>
+__device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
+#pragma unroll
+  for (int k = 2; k <= M; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < M; i++) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const int32_t u = L[i], v = L[l];
+          const bool sw = up ? (u > v) : (u < v);
+          L[i] = sw ? v : u;
+          L[l] = sw ? u : v;
+        }
+      }
+    }
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void sort_small(int32_t *list, int32_t cnt) {
+  int32_t L[M];
+#pragma unroll
+  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i] : INT32_MAX;
+  bitonic_sort<M>(L);
+#pragma unroll
+  for (int i = 0; i < M; i++)
+    if (i < cnt) list[i] = L[i];
+}
+
+// ascending order of a short contiguous list (entries arrived by atomics)
+__device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
+  if (cnt <= 1) return;
+  if (cnt <= 4) {
+    sort_small<4>(list, cnt);
+  } else if (cnt <= 8) {
+    sort_small<8>(list, cnt);
+  } else if (cnt <= 16) {
+    sort_small<16>(list, cnt);
+  } else {
+    for (int32_t k = 1; k < cnt; k++) {
+      const int32_t v = list[k];
+      int32_t j = k - 1;
+      while (j >= 0 && list[j] > v) {
+        list[j + 1] = list[j];
+        j--;
+      }
+      list[j + 1] = v;
+    }
+  }
+}
+
+hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
                          const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
   StepCtl none{nullptr, nullptr};
+  const bool f64 = precision == DEM_PREC_FP64;
   if (L.ndirect > 0)
-    k_detect_direct<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell, cell_start,
+    k_detect_direct<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
                                                    err);
   if (L.ntiles > 0)
-    k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, p, nb, scell,
+    k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell,
                                                        cell_start, err);
   return hipGetLastError();
 }
 
-hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, int64_t cap,
-                       const ScanScratch &sc, int32_t *err, hipStream_t st) {
+hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
+                       int64_t cap, const ScanScratch &sc, int32_t *err, hipStream_t st) {
   const int32_t n = L.n;
   if (n <= 0) {
     k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
+    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
     return hipGetLastError();
   }
   hipError_t e = scan_with_total(nb.fcnt, gen.ofs, n, sc, st);
   if (e != hipSuccess) return e;
+  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
   if (precision == DEM_PREC_FP64)
-    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, cap, n, err);
+    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, err);
   else
-    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, cap, n, err);
+    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, err);
+  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
+  k_bwd<<<2048, kBlock, 0, st>>>(gen, w, cap, n);
   return hipGetLastError();
 }
 
@@ -816,17 +930,132 @@ __device__ __forceinline__ void hist_find(const PairGen &old, int64_t cap, int32
   }
 }
 
-// Steps 7-8 and the closing half kick: one lane per particle walks its
-// contact list in order (lower partners, higher partners, walls).  Each pair
-// is evaluated in one canonical orientation -- seen from its lower slot,
-// with the history filed under that slot -- by both of its particles, with
-// the same operands in the same order, so the two results are bit-identical
-// and the particles receive exactly opposite forces (and the same n x F_t,
-// Eq. 3) without any exchange; only the lower slot writes the new history.
-// The sums run in a fixed order and use no atomics.  In a time step the lane
-// then applies the closing half kick and, when its system steps again in
-// this call, the next step's opening kick, drift and hash, writing the
-// positions to the other buffer (partners still read the current ones).
+// Committed delta_t of a contact, seen from its current owner (lower slot).
+// ho, hp: previous slot and committed history segment of the owner and of
+// the partner.  The previous step filed the contact under the lower of the
+// two previous slots, seen from there.
+template <typename Real>
+__device__ __forceinline__ void pair_history(const PairGen &old, int64_t cap, const int4 &ho, const int4 &hp,
+                                             Real h[3]) {
+  const bool kept = ho.x < hp.x;  // the owner was the lower slot then too
+  if (kept) {
+    hist_find<Real>(old, cap, ho.y, ho.z, hp.x, h);
+  } else {
+    hist_find<Real>(old, cap, hp.y, hp.z, ho.x, h);
+    h[0] = -h[0];
+    h[1] = -h[1];
+    h[2] = -h[2];
+  }
+}
+
+// previous slot and committed history segment of slot s
+__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s) {
+  return old_perm ? a.nb.hix[s] : make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
+}
+
+// One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
+// pair, seen from the owner (the lower slot), stored as the force on the
+// owner and n x F_t.  The partner receives the exact negation.  Both
+// particles' inputs come from their packed state records.  In a time step,
+// the contacts of a system that has finished its steps only carry their
+// history forward.
+template <typename Real, int LAW>
+__device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
+  using V4 = typename Vec4T<Real>::type;
+  const int64_t cap = a.cap;
+  const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
+  const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
+  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
+  const bool diag = (a.mode & MODE_DIAG) != 0;
+  const bool stepping = (a.mode & MODE_KICK) != 0;
+  const bool one_sys = a.L.S == 1;
+  const int32_t s = a.cur.s[q], t = a.cur.t[q];
+  const int32_t k = one_sys ? 0 : a.L.psys[s];
+  const SysInfo &si = a.L.tab[k];
+  const Consts &c = si.c;
+  const PState<Real> me = PS[s];
+  const int4 hs = hist_index(a, old_perm, s);
+  Real h[3] = {0, 0, 0};
+  if (LAW != DEM_LAW_SIMPLE) {
+    if (t >= 0)
+      pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), h);
+    else
+      hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
+  }
+  if (stepping && !is_active(a.ctl, k)) {
+    // a finished system: its state does not move, its history is kept
+    if (write_hist) put_entry<Real>(a.cur, q, h, t);
+    return;
+  }
+  const float rsf = me.r;
+  const Real rs = (Real)rsf;
+  const Real ms = mass_of<Real>(c, rs);
+  LawOut<Real> o;
+  Real n[3], delta, R;
+  if (t >= 0) {
+    const PState<Real> pt = PS[t];
+    const double dx = pt.x - me.x, dy = pt.y - me.y, dz = pt.z - me.z;
+    const double d2 = dist2_exact(dx, dy, dz);
+    const double S = (double)rsf + (double)pt.r;
+    const Real rt = (Real)pt.r;
+    const Real mt = mass_of<Real>(c, rt);
+    const Real dd = sqrt((Real)d2);
+    const Real invd = (Real)1 / dd;
+    n[0] = (Real)dx * invd;
+    n[1] = (Real)dy * invd;
+    n[2] = (Real)dz * invd;
+    delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
+    R = rs * rt / (rs + rt);
+    const Real M = ms * mt / (ms + mt);
+    Real v[3], spin[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      v[i] = me.v[i] - pt.v[i];
+      spin[i] = rs * me.w[i] + rt * pt.w[i];
+    }
+    contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
+  } else {
+    // Step 8: wall -1 - t, a particle of infinite radius
+    const int w = -1 - t;
+    const int ax = w >> 1;
+    const double xw[3] = {me.x, me.y, me.z};
+    const double gap = (w & 1) ? (si.g.hi[ax] - xw[ax]) : (xw[ax] - si.g.lo[ax]);
+    n[0] = n[1] = n[2] = 0;
+    n[ax] = (w & 1) ? (Real)1 : (Real)-1;
+    delta = (Real)((double)rsf - gap);
+    R = rs;
+    Real spin[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) spin[i] = rs * me.w[i];
+    contact_law<Real, LAW>(c, n, delta, rs, ms, me.v, spin, h, o);
+  }
+  V4 f, tq;
+  f.x = o.F[0];
+  f.y = o.F[1];
+  f.z = o.F[2];
+  f.w = 0;
+  tq.x = n[1] * o.Ft[2] - n[2] * o.Ft[1];
+  tq.y = n[2] * o.Ft[0] - n[0] * o.Ft[2];
+  tq.z = n[0] * o.Ft[1] - n[1] * o.Ft[0];
+  tq.w = 0;
+  ((V4 *)a.w.pf)[2 * (int64_t)q] = f;
+  ((V4 *)a.w.pf)[2 * (int64_t)q + 1] = tq;
+  if (write_hist) put_entry<Real>(a.cur, q, o.dtn, t);
+  if (diag) {
+    a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
+    a.w.pd[q] = (double)delta;
+  }
+}
+
+template <typename Real, int LAW>
+__global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
+  const int32_t P = num_pairs(a.cur, a.L.n, a.cap);
+  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock)
+    pair_force_one<Real, LAW>(a, q);
+}
+
+// Step 1 drift x += dt v and Step 2 hash of the new position, written to
+// the other position buffer
 template <typename Real>
 __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, const PosBuf &out, int32_t i,
                                               const Real v[3], const Consts &c, const Grid &g, int32_t *cell,
@@ -843,163 +1072,73 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
   cell[i] = cc;
 }
 
-// Committed delta_t of the contact of two particles, seen from the current
-// lower slot (own: the first particle is it).  hs, ht: previous slot and
-// committed history segment of each.  The previous step filed the contact
-// under the lower of the two previous slots, seen from there.
+// One lane per particle: contact sums in a fixed order (contacts with lower
+// slots, ascending; with higher slots, ascending; walls), then in a time
+// step the closing half kick and, when the system steps again in this call,
+// the next step's opening kick, drift and hash.  The state goes to the other
+// buffers.
 template <typename Real>
-__device__ __forceinline__ void pair_history(const PairGen &old, int64_t cap, const int4 &hs, const int4 &ht,
-                                             bool own, Real h[3]) {
-  const bool s_owned = hs.x < ht.x;  // the first particle was the lower slot then
-  if (s_owned)
-    hist_find<Real>(old, cap, hs.y, hs.z, ht.x, h);
-  else
-    hist_find<Real>(old, cap, ht.y, ht.z, hs.x, h);
-  if (s_owned != own) {  // the lower slot changed: delta_t flips with the view
-    h[0] = -h[0];
-    h[1] = -h[1];
-    h[2] = -h[2];
-  }
-}
-
-// previous slot and committed history segment of slot s
-__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s) {
-  return old_perm ? a.nb.hix[s] : make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
-}
-
-template <typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_force(PairArgs a) {
+__global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
+  using V4 = typename Vec4T<Real>::type;
   int32_t k;
   const int32_t s = block_slot(a.L, k);
   if (s < 0) return;
   const SysInfo &si = a.L.tab[k];
   const Consts &c = si.c;
-  const int32_t N = a.L.n;
-  const int64_t cap = a.cap;
   const bool stepping = (a.mode & MODE_KICK) != 0;
-  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
-  const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
-  const bool diag = (a.mode & MODE_DIAG) != 0;
-  const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
-  const int32_t nl = a.nb.nlow[s], nc = nl + a.nb.fcnt[s];
-  const int64_t q0 = a.cur.ofs[s];  // first owned contact in the new table
-  const PState<Real> me = PS[s];
-  const int4 hs = hist_index(a, old_perm, s);
-  const double xs = me.x, ys = me.y, zs = me.z;
-  const float rsf = me.r;
+  const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
   if (stepping && !is_active(a.ctl, k)) {
-    // a finished system: state unchanged, history carried forward; the next
-    // sort sees its current cells
-    if (write_hist) {
-      for (int32_t j = nl; j < nc; j++) {
-        const int64_t q = q0 + (j - nl);
-        if (q >= cap) break;
-        const int32_t t = a.nb.nb[(int64_t)j * N + s];
-        Real h[3];
-        if (t >= 0)
-          pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), true, h);
-        else
-          hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
-        put_entry<Real>(a.cur, q, h, t);
-      }
-    }
+    // a finished system: state unchanged; the next sort sees its current cells
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)a.vel_out.v[q])[s] = me.v[q];
       ((Real *)a.vel_out.w[q])[s] = me.w[q];
     }
-    a.pos_out.x[s] = xs;
-    a.pos_out.y[s] = ys;
-    a.pos_out.z[s] = zs;
-    a.pos_out.r[s] = rsf;
-    a.pos_out.id[s] = a.pos.id[s];
+    a.pos_out.x[s] = me.x;
+    a.pos_out.y[s] = me.y;
+    a.pos_out.z[s] = me.z;
+    a.pos_out.r[s] = me.r;
+    a.pos_out.id[s] = me.id;
     a.cell[s] = a.scell[s];
     return;
   }
-  const Real rs = (Real)rsf;
-  const Real ms = mass_of<Real>(c, rs);
-  const Real *vs = me.v, *ws = me.w;
+  const int64_t cap = a.cap;
+  const Real rs = (Real)me.r;
+  const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  const int32_t b0 = a.w.bofs[s], b1 = a.w.bofs[s + 1];
+  const int32_t nb = (int64_t)b1 <= cap ? b1 - b0 : 0;
+  sort_list(a.w.bwd + b0, nb);
+  for (int32_t i = 0; i < nb; i++) {
+    const int32_t q = a.w.bwd[b0 + i];
+    const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
+    F[0] -= f.x;
+    F[1] -= f.y;
+    F[2] -= f.z;
+    T[0] += rs * m.x;  // Eq. 3; the same n x F_t on both bodies
+    T[1] += rs * m.y;
+    T[2] += rs * m.z;
+  }
+  const int64_t f0 = a.cur.ofs[s];
+  const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
-  for (int32_t j = 0; j < nc; j++) {
-    const int32_t t = a.nb.nb[(int64_t)j * N + s];
-    const bool own = j >= nl;  // this particle is the lower slot (or faces a wall)
-    Real h[3] = {0, 0, 0};
-    LawOut<Real> o;
-    Real n[3], delta, R;
-    if (t >= 0) {
-      const PState<Real> pt_ = PS[t];
-      if (LAW != DEM_LAW_SIMPLE) pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), own, h);
-      // canonical orientation: body a is the lower slot
-      const double xa = own ? xs : pt_.x, ya = own ? ys : pt_.y, za = own ? zs : pt_.z;
-      const double xb = own ? pt_.x : xs, yb = own ? pt_.y : ys, zb = own ? pt_.z : zs;
-      const float raf = own ? rsf : pt_.r, rbf = own ? pt_.r : rsf;
-      const double dx = xb - xa, dy = yb - ya, dz = zb - za;
-      const double d2 = dist2_exact(dx, dy, dz);
-      const double S = (double)raf + (double)rbf;
-      const Real ra = (Real)raf, rb = (Real)rbf;
-      const Real ma = mass_of<Real>(c, ra), mb = mass_of<Real>(c, rb);
-      const Real dd = sqrt((Real)d2);
-      const Real invd = (Real)1 / dd;
-      n[0] = (Real)dx * invd;
-      n[1] = (Real)dy * invd;
-      n[2] = (Real)dz * invd;
-      delta = (Real)(sq_exact(S) - d2) / ((Real)S + dd);
-      R = ra * rb / (ra + rb);
-      const Real M = ma * mb / (ma + mb);
-      Real v[3], spin[3];
-#pragma unroll
-      for (int i = 0; i < 3; i++) {
-        const Real va = own ? vs[i] : pt_.v[i], vb = own ? pt_.v[i] : vs[i];
-        const Real wa = own ? ws[i] : pt_.w[i], wb = own ? pt_.w[i] : ws[i];
-        v[i] = va - vb;
-        spin[i] = ra * wa + rb * wb;
-      }
-      contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
-    } else {
-      // Step 8: wall -1 - t, a particle of infinite radius
-      if (LAW != DEM_LAW_SIMPLE) hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
-      const int w = -1 - t;
-      const int ax = w >> 1;
-      const double xw[3] = {xs, ys, zs};
-      const double gap = (w & 1) ? (si.g.hi[ax] - xw[ax]) : (xw[ax] - si.g.lo[ax]);
-      n[0] = n[1] = n[2] = 0;
-      n[ax] = (w & 1) ? (Real)1 : (Real)-1;
-      delta = (Real)((double)rsf - gap);
-      R = rs;
-      Real spin[3];
-#pragma unroll
-      for (int i = 0; i < 3; i++) spin[i] = rs * ws[i];
-      contact_law<Real, LAW>(c, n, delta, rs, ms, vs, spin, h, o);
-    }
-    const Real tq[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
-                        n[0] * o.Ft[1] - n[1] * o.Ft[0]};
-    if (own) {
-      F[0] += o.F[0];
-      F[1] += o.F[1];
-      F[2] += o.F[2];
-    } else {
-      F[0] -= o.F[0];
-      F[1] -= o.F[1];
-      F[2] -= o.F[2];
-    }
-    T[0] += rs * tq[0];  // Eq. 3; the same n x F_t on both bodies
-    T[1] += rs * tq[1];
-    T[2] += rs * tq[2];
-    if (own) {
-      if (write_hist) {
-        const int64_t q = q0 + (j - nl);
-        if (q < cap) put_entry<Real>(a.cur, q, o.dtn, t);
-      }
-      if (diag) {
-        e_el += elastic_energy<Real, LAW>(c, delta, R, o, h);
-        dmax = fmax(dmax, (double)delta);
-        if (t >= 0)
-          npair++;
-        else
-          nwall++;
-      }
+  const bool diag = (a.mode & MODE_DIAG) != 0;
+  for (int64_t q = f0; q < f1; q++) {
+    const V4 f = pf[2 * q], m = pf[2 * q + 1];
+    F[0] += f.x;
+    F[1] += f.y;
+    F[2] += f.z;
+    T[0] += rs * m.x;
+    T[1] += rs * m.y;
+    T[2] += rs * m.z;
+    if (diag) {
+      e_el += a.w.pe[q];
+      dmax = fmax(dmax, a.w.pd[q]);
+      if (a.cur.t[q] >= 0)
+        npair++;
+      else
+        nwall++;
     }
   }
   if (!(isfinite((double)F[0]) && isfinite((double)F[1]) && isfinite((double)F[2]) &&
@@ -1011,22 +1150,23 @@ __global__ __launch_bounds__(kBlock) void k_force(PairArgs a) {
     ((Real *)a.T[q])[s] = T[q];
   }
   if (stepping) {
-    Real v[3] = {vs[0], vs[1], vs[2]}, w[3] = {ws[0], ws[1], ws[2]};
-    const Real I = (Real)0.4 * ms * rs * rs;
-    half_kick<Real>(c, ms, I, F, T, v, w);
+    Real v[3] = {me.v[0], me.v[1], me.v[2]}, w[3] = {me.w[0], me.w[1], me.w[2]};
+    const Real m = mass_of<Real>(c, rs);
+    const Real I = (Real)0.4 * m * rs * rs;
+    half_kick<Real>(c, m, I, F, T, v, w);
     if (*a.ctl.step + 1 < a.ctl.left[k]) {
       // the next step's Steps 1-2 with the same forces: the same operations
       // as k_kick_drift_hash, so fusing changes no bit
-      half_kick<Real>(c, ms, I, F, T, v, w);
-      drift_hash_to(xs, ys, zs, a.pos_out, s, v, c, si.g, a.cell, a.err);
+      half_kick<Real>(c, m, I, F, T, v, w);
+      drift_hash_to(me.x, me.y, me.z, a.pos_out, s, v, c, si.g, a.cell, a.err);
     } else {
-      a.pos_out.x[s] = xs;  // its last step in this call: it stops here
-      a.pos_out.y[s] = ys;
-      a.pos_out.z[s] = zs;
+      a.pos_out.x[s] = me.x;  // its last step in this call: it stops here
+      a.pos_out.y[s] = me.y;
+      a.pos_out.z[s] = me.z;
       a.cell[s] = a.scell[s];
     }
-    a.pos_out.r[s] = rsf;
-    a.pos_out.id[s] = a.pos.id[s];
+    a.pos_out.r[s] = me.r;
+    a.pos_out.id[s] = me.id;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)a.vel_out.v[q])[s] = v[q];
@@ -1148,13 +1288,15 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
 }
 
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
-                          const VelBuf &vdst, const int32_t *perm, const int32_t *cell, int32_t *scell,
+                          const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, nb, old_ofs);
+    k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, soa ? 1 : 0, perm, cell, scell, nb,
+                                                     old_ofs);
   else
-    k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, perm, cell, scell, nb, old_ofs);
+    k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, soa ? 1 : 0, perm, cell, scell, nb,
+                                                    old_ofs);
   return hipGetLastError();
 }
 
@@ -1173,30 +1315,39 @@ hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_force(int precision, const PairArgs &a, hipStream_t st) {
-  if (a.L.n <= 0) return hipSuccess;
+hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st) {
+  if (a.L.n <= 0 || a.cap <= 0) return hipSuccess;
   const bool f64 = precision == DEM_PREC_FP64;
-  const unsigned nb = (unsigned)a.L.nblocks;
+  const unsigned nb = 2048;  // grid-stride over the contacts: the count is on the device
   switch (a.law) {
     case DEM_LAW_HERTZ:
       if (f64)
-        k_force<double, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<double, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
       else
-        k_force<float, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<float, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
       break;
     case DEM_LAW_SIMPLE:
       if (f64)
-        k_force<double, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<double, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
       else
-        k_force<float, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<float, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
       break;
     default:
       if (f64)
-        k_force<double, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<double, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
       else
-        k_force<float, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
+        k_pair_force<float, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st) {
+  if (a.L.n <= 0) return hipSuccess;
+  if (precision == DEM_PREC_FP64)
+    k_gather<double><<<a.L.nblocks, kBlock, 0, st>>>(a);
+  else
+    k_gather<float><<<a.L.nblocks, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -26,8 +26,8 @@ DEM_E_HIP = -6
 DEM_E_STATE = -7
 DEM_E_CAPACITY = -9
 
-NUM_PHASES = 6
-PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "force")
+NUM_PHASES = 7
+PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "pair_force", "gather")
 
 _LIB = None
 
