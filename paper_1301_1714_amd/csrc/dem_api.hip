@@ -272,12 +272,10 @@ size_t carve(Engine &e, char *base) {
     e.gen[b].ent = cv.take_bytes(4 * R * P);
   }
   e.work.pf = cv.take_bytes(8 * R * P);
-  e.work.brank = cv.take<int32_t>(P);
   e.work.pe = cv.take<double>(P);
   e.work.pd = cv.take<double>(P);
   e.work.bcnt = cv.take<int32_t>(N);
-  e.work.bofs = cv.take<int32_t>(N + 1);
-  e.work.bwd = cv.take<int32_t>(P);
+  e.work.bwd = cv.take<int32_t>((size_t)kBwdCap * N);
   e.diag.e_el = cv.take<double>(N);
   e.diag.npair = cv.take<int32_t>(N);
   e.diag.nwall = cv.take<int32_t>(N);
@@ -371,13 +369,14 @@ void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, s
 
 // Steps 5-6 on the current positions into generation g (with ctl only the
 // systems still stepping detect again; the others keep their lists)
-hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after_detect = nullptr) {
+hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after_detect = nullptr,
+                          bool write_keys = true) {
   e.gs = g;
   const Layout L = e.layout();
   hipError_t r = launch_detect(e.prec, L, ctl, e.nbr, e.scell, e.cell_start, e.err, e.stream);
   if (r != hipSuccess) return r;
   if (after_detect) (void)hipEventRecord(after_detect, e.stream);
-  return launch_list(e.prec, L, e.nbr, e.gen[g], e.work, e.Pcap, e.scan, e.err, e.stream);
+  return launch_list(e.prec, L, e.nbr, e.gen[g], e.work, e.Pcap, write_keys, e.scan, e.err, e.stream);
 }
 
 // Steps 7-8 once per contact, then the per-particle sums (and, in a time
@@ -740,7 +739,10 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   mark(3);
   // Steps 5-6; the new history table is the generation that does not hold
   // the committed one
-  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl, ev ? ev[4] : nullptr)) != hipSuccess) return r;
+  // (with a law that keeps history, the law pass writes every entry, key
+  // included, so the list pass leaves the keys out)
+  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl, ev ? ev[4] : nullptr, e.law == DEM_LAW_SIMPLE)) != hipSuccess)
+    return r;
   mark(5);
   // Steps 7-8 and the closing half kick; the new history is committed
   PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);

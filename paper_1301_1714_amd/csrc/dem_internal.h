@@ -28,7 +28,7 @@
 //            that one load brings both.  One generation holds the committed
 //            history, the other is built for the new positions.
 //   work     per-contact force on the owner and n x F_t (2 x Real4), and the
-//            backward CSR (contacts of each particle as the partner)
+//            backward lists (contacts of each particle as the partner)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -51,6 +51,7 @@ enum ModeBits : int32_t {
 
 constexpr int32_t kBlock = 256;
 constexpr int32_t kListCap = 64;  // detection: contacts per particle (higher partners + walls)
+constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 
 struct Grid {
@@ -127,12 +128,10 @@ struct PairGen {
 
 struct PairWork {
   void *pf;        // [2 Pcap] Real4: force on the owner, then n x F_t
-  int32_t *brank;  // [Pcap] rank of the contact in its partner's backward list
   double *pe;      // [Pcap] elastic energy (diagnostics)
   double *pd;      // [Pcap] overlap (diagnostics)
-  int32_t *bcnt;   // [N] backward counts
-  int32_t *bofs;   // [N + 1]
-  int32_t *bwd;    // [Pcap] contact indices grouped by partner
+  int32_t *bcnt;   // [N] contacts of each particle as the partner
+  int32_t *bwd;    // [kBwdCap][N] their indices, in arrival order
 };
 
 struct DiagBuf {
@@ -207,8 +206,10 @@ hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const Ve
 // backward index
 hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
                          const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st);
+// (write_keys: also write the history keys into the entries; a time step
+// whose law keeps history leaves that to the law pass)
 hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                       int64_t cap, const ScanScratch &sc, int32_t *err, hipStream_t st);
+                       int64_t cap, bool write_keys, const ScanScratch &sc, int32_t *err, hipStream_t st);
 // Steps 7-8: the law once per contact, then per-particle sums and (in a time
 // step) the kicks
 hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st);

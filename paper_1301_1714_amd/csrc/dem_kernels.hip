@@ -698,11 +698,12 @@ __device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Rea
 }
 
 // The lists become the compact contact array of `gen` (offsets from a scan
-// of the counts, the history keys in the table entries); each pair draws its
-// rank in the partner's backward list.
+// of the counts); each pair is also filed in its partner's backward list,
+// at the position its atomic count drew (arrival order; the gather sorts
+// each short list).  With write_keys the history keys go into the entries.
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int64_t cap, int32_t n,
-                                                  int32_t *err) {
+                                                  int32_t write_keys, int32_t *err) {
   const int32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= n) return;
   const int32_t cnt = nb.fcnt[s];
@@ -715,25 +716,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWo
     const int32_t t = nb.nb[(int64_t)j * n + s];
     gen.s[q] = s;
     gen.t[q] = t;
-    put_entry<Real>(gen, q, zero, t);
-    if (t >= 0) w.brank[q] = atomicAdd(&w.bcnt[t], 1);
+    if (write_keys) put_entry<Real>(gen, q, zero, t);
+    if (t >= 0) {
+      const int32_t k = atomicAdd(&w.bcnt[t], 1);
+      if (k < kBwdCap)
+        w.bwd[(int64_t)k * n + t] = (int32_t)q;
+      else
+        raise_err(err, ERR_OVERFLOW);
+    }
   }
 }
 
 __device__ __forceinline__ int32_t num_pairs(const PairGen &gen, int32_t n, int64_t cap) {
   const int32_t P = gen.ofs[n];
   return (int64_t)P < cap ? P : (int32_t)cap;
-}
-
-// backward index: contact q is filed under its partner at the rank its
-// count drew (arrival order; the gather sorts each short segment)
-__global__ __launch_bounds__(kBlock) void k_bwd(PairGen gen, PairWork w, int64_t cap, int32_t n) {
-  const int32_t P = num_pairs(gen, n, cap);
-  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock) {
-    const int32_t t = gen.t[q];
-    if (t < 0) continue;
-    w.bwd[w.bofs[t] + w.brank[q]] = q;
-  }
 }
 
 // fixed-size bitonic network on registers (indices are compile-time)
@@ -758,37 +754,17 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
   }
 }
 
-template <int M>
-__device__ __forceinline__ void sort_small(int32_t *list, int32_t cnt) {
+// the backward list of slot s (M >= cnt entries, k-major), sorted ascending
+// in registers, then fn(q) for each entry in that order
+template <int M, typename Fn>
+__device__ __forceinline__ void for_sorted(const int32_t *bwd, int32_t n, int32_t s, int32_t cnt, Fn &&fn) {
   int32_t L[M];
 #pragma unroll
-  for (int i = 0; i < M; i++) L[i] = i < cnt ? list[i] : INT32_MAX;
+  for (int i = 0; i < M; i++) L[i] = i < cnt ? bwd[(int64_t)i * n + s] : INT32_MAX;
   bitonic_sort<M>(L);
 #pragma unroll
   for (int i = 0; i < M; i++)
-    if (i < cnt) list[i] = L[i];
-}
-
-// ascending order of a short contiguous list (entries arrived by atomics)
-__device__ __forceinline__ void sort_list(int32_t *list, int32_t cnt) {
-  if (cnt <= 1) return;
-  if (cnt <= 4) {
-    sort_small<4>(list, cnt);
-  } else if (cnt <= 8) {
-    sort_small<8>(list, cnt);
-  } else if (cnt <= 16) {
-    sort_small<16>(list, cnt);
-  } else {
-    for (int32_t k = 1; k < cnt; k++) {
-      const int32_t v = list[k];
-      int32_t j = k - 1;
-      while (j >= 0 && list[j] > v) {
-        list[j + 1] = list[j];
-        j--;
-      }
-      list[j + 1] = v;
-    }
-  }
+    if (i < cnt) fn(L[i]);
 }
 
 hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
@@ -806,22 +782,20 @@ hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, con
 }
 
 hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                       int64_t cap, const ScanScratch &sc, int32_t *err, hipStream_t st) {
+                       int64_t cap, bool write_keys, const ScanScratch &sc, int32_t *err, hipStream_t st) {
   const int32_t n = L.n;
   if (n <= 0) {
     k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
-    k_fill<<<1, kBlock, 0, st>>>(w.bofs, 1, 0);
     return hipGetLastError();
   }
   hipError_t e = scan_with_total(nb.fcnt, gen.ofs, n, sc, st);
   if (e != hipSuccess) return e;
   k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
+  const int32_t wk = write_keys ? 1 : 0;
   if (precision == DEM_PREC_FP64)
-    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, err);
+    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, wk, err);
   else
-    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, err);
-  if ((e = scan_with_total(w.bcnt, w.bofs, n, sc, st)) != hipSuccess) return e;
-  k_bwd<<<2048, kBlock, 0, st>>>(gen, w, cap, n);
+    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, wk, err);
   return hipGetLastError();
 }
 
@@ -1106,11 +1080,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   const Real rs = (Real)me.r;
   const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  const int32_t b0 = a.w.bofs[s], b1 = a.w.bofs[s + 1];
-  const int32_t nb = (int64_t)b1 <= cap ? b1 - b0 : 0;
-  sort_list(a.w.bwd + b0, nb);
-  for (int32_t i = 0; i < nb; i++) {
-    const int32_t q = a.w.bwd[b0 + i];
+  // contacts with lower partners, ascending by contact (= by owner slot)
+  auto back = [&](int32_t q) {
     const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
     F[0] -= f.x;
     F[1] -= f.y;
@@ -1118,7 +1089,17 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     T[0] += rs * m.x;  // Eq. 3; the same n x F_t on both bodies
     T[1] += rs * m.y;
     T[2] += rs * m.z;
-  }
+  };
+  const int32_t nbk = min(a.w.bcnt[s], kBwdCap);
+  const int32_t N = a.L.n;
+  if (nbk <= 4)
+    for_sorted<4>(a.w.bwd, N, s, nbk, back);
+  else if (nbk <= 8)
+    for_sorted<8>(a.w.bwd, N, s, nbk, back);
+  else if (nbk <= 16)
+    for_sorted<16>(a.w.bwd, N, s, nbk, back);
+  else
+    for_sorted<32>(a.w.bwd, N, s, nbk, back);
   const int64_t f0 = a.cur.ofs[s];
   const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
   double e_el = 0.0, dmax = 0.0;
