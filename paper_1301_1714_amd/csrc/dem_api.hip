@@ -271,7 +271,7 @@ size_t carve(Engine &e, char *base) {
     e.gen[b].t = cv.take<int32_t>(P);
     e.gen[b].ent = cv.take_bytes(4 * R * P);
   }
-  e.work.pf = cv.take_bytes(8 * R * P);
+  e.work.pf = cv.take_bytes(6 * R * P);
   e.work.pe = cv.take<double>(P);
   e.work.pd = cv.take<double>(P);
   e.work.bcnt = cv.take<int32_t>(N);

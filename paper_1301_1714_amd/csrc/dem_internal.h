@@ -27,7 +27,7 @@
 //            from the owner in x, y, z and the key (t, its bits) in w, so
 //            that one load brings both.  One generation holds the committed
 //            history, the other is built for the new positions.
-//   work     per-contact force on the owner and n x F_t (2 x Real4), and the
+//   work     per-contact force on the owner and n x F_t (6 Real), and the
 //            backward lists (contacts of each particle as the partner)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
@@ -127,7 +127,7 @@ struct PairGen {
 };
 
 struct PairWork {
-  void *pf;        // [2 Pcap] Real4: force on the owner, then n x F_t
+  void *pf;        // [6 Pcap] Real: force on the owner, then n x F_t
   double *pe;      // [Pcap] elastic energy (diagnostics)
   double *pd;      // [Pcap] overlap (diagnostics)
   int32_t *bcnt;   // [N] contacts of each particle as the partner

@@ -687,6 +687,48 @@ struct Vec4T<double> {
 };
 
 template <typename Real>
+struct Vec2T;
+template <>
+struct Vec2T<float> {
+  using type = float2;
+};
+template <>
+struct Vec2T<double> {
+  using type = double2;
+};
+
+// per-contact record of the law: force on the owner and n x F_t, six Reals
+// in three pairs
+template <typename Real>
+__device__ __forceinline__ void put_record(void *pf, int64_t q, const Real f[3], const Real m[3]) {
+  using V2 = typename Vec2T<Real>::type;
+  V2 *p = (V2 *)pf + 3 * q;
+  V2 a, b, c;
+  a.x = f[0];
+  a.y = f[1];
+  b.x = f[2];
+  b.y = m[0];
+  c.x = m[1];
+  c.y = m[2];
+  p[0] = a;
+  p[1] = b;
+  p[2] = c;
+}
+
+template <typename Real>
+__device__ __forceinline__ void get_record(const void *pf, int64_t q, Real f[3], Real m[3]) {
+  using V2 = typename Vec2T<Real>::type;
+  const V2 *p = (const V2 *)pf + 3 * q;
+  const V2 a = p[0], b = p[1], c = p[2];
+  f[0] = a.x;
+  f[1] = a.y;
+  f[2] = b.x;
+  m[0] = b.y;
+  m[1] = c.x;
+  m[2] = c.y;
+}
+
+template <typename Real>
 __device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Real d[3], int32_t key) {
   using V4 = typename Vec4T<Real>::type;
   V4 e;
@@ -935,7 +977,6 @@ __device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int
 // history forward.
 template <typename Real, int LAW>
 __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
-  using V4 = typename Vec4T<Real>::type;
   const int64_t cap = a.cap;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
@@ -1003,17 +1044,9 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
     for (int i = 0; i < 3; i++) spin[i] = rs * me.w[i];
     contact_law<Real, LAW>(c, n, delta, rs, ms, me.v, spin, h, o);
   }
-  V4 f, tq;
-  f.x = o.F[0];
-  f.y = o.F[1];
-  f.z = o.F[2];
-  f.w = 0;
-  tq.x = n[1] * o.Ft[2] - n[2] * o.Ft[1];
-  tq.y = n[2] * o.Ft[0] - n[0] * o.Ft[2];
-  tq.z = n[0] * o.Ft[1] - n[1] * o.Ft[0];
-  tq.w = 0;
-  ((V4 *)a.w.pf)[2 * (int64_t)q] = f;
-  ((V4 *)a.w.pf)[2 * (int64_t)q + 1] = tq;
+  const Real tq[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
+                      n[0] * o.Ft[1] - n[1] * o.Ft[0]};
+  put_record<Real>(a.w.pf, q, o.F, tq);
   if (write_hist) put_entry<Real>(a.cur, q, o.dtn, t);
   if (diag) {
     a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
@@ -1053,7 +1086,6 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
 // buffers.
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
-  using V4 = typename Vec4T<Real>::type;
   int32_t k;
   const int32_t s = block_slot(a.L, k);
   if (s < 0) return;
@@ -1078,17 +1110,17 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   }
   const int64_t cap = a.cap;
   const Real rs = (Real)me.r;
-  const V4 *pf = (const V4 *)a.w.pf;  // contact q: force at 2q, n x F_t at 2q + 1
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   // contacts with lower partners, ascending by contact (= by owner slot)
   auto back = [&](int32_t q) {
-    const V4 f = pf[2 * (int64_t)q], m = pf[2 * (int64_t)q + 1];
-    F[0] -= f.x;
-    F[1] -= f.y;
-    F[2] -= f.z;
-    T[0] += rs * m.x;  // Eq. 3; the same n x F_t on both bodies
-    T[1] += rs * m.y;
-    T[2] += rs * m.z;
+    Real f[3], m[3];
+    get_record<Real>(a.w.pf, q, f, m);
+    F[0] -= f[0];
+    F[1] -= f[1];
+    F[2] -= f[2];
+    T[0] += rs * m[0];  // Eq. 3; the same n x F_t on both bodies
+    T[1] += rs * m[1];
+    T[2] += rs * m[2];
   };
   const int32_t nbk = min(a.w.bcnt[s], kBwdCap);
   const int32_t N = a.L.n;
@@ -1106,13 +1138,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   for (int64_t q = f0; q < f1; q++) {
-    const V4 f = pf[2 * q], m = pf[2 * q + 1];
-    F[0] += f.x;
-    F[1] += f.y;
-    F[2] += f.z;
-    T[0] += rs * m.x;
-    T[1] += rs * m.y;
-    T[2] += rs * m.z;
+    Real f[3], m[3];
+    get_record<Real>(a.w.pf, q, f, m);
+    F[0] += f[0];
+    F[1] += f[1];
+    F[2] += f[2];
+    T[0] += rs * m[0];
+    T[1] += rs * m[1];
+    T[2] += rs * m[2];
     if (diag) {
       e_el += a.w.pe[q];
       dmax = fmax(dmax, a.w.pd[q]);
