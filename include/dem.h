@@ -44,7 +44,7 @@ typedef enum {
     DEM_OK = 0,
     DEM_E_INVALID = -1,          /* bad argument or parameter */
     DEM_E_WORKSPACE = -2,        /* workspace missing or too small */
-    DEM_E_CONTACT_OVERFLOW = -3, /* more contacts than the contact list can hold */
+    DEM_E_CONTACT_OVERFLOW = -3, /* more contacts than the contact list can hold (see dem_params) */
     DEM_E_OUT_OF_DOMAIN = -4,    /* a particle went more than one cell outside the box */
     DEM_E_NONFINITE = -5,        /* non-finite state or force */
     DEM_E_HIP = -6,              /* a HIP runtime call failed */
@@ -79,8 +79,9 @@ typedef struct {
     double simple_k[3];          /* k_sp, k_da, k_sh of Eq. 1 (DEM_LAW_SIMPLE only) */
     double cell_size;            /* requested cell width (Sec. 4.1), >= 2 max radius */
     int32_t contacts_per_particle; /* contact-list capacity: n * this many contacts (each pair
-                                      once, plus wall contacts) may be held; 1..64.  One
-                                      particle may touch at most 64 partners and walls */
+                                      once, plus wall contacts) may be held; 1..64.  In the
+                                      sorted order a particle may touch at most 64 partners
+                                      after it (walls included) and 32 before it */
     int32_t precision;           /* dem_precision */
     int32_t tile_cells;          /* detection launch shape: 0 = one lane per particle reading
                                     neighbours through the caches; 1..32 = workgroups over

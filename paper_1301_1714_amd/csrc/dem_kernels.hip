@@ -1158,17 +1158,23 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   if (!(isfinite((double)F[0]) && isfinite((double)F[1]) && isfinite((double)F[2]) &&
         isfinite((double)T[0]) && isfinite((double)T[1]) && isfinite((double)T[2])))
     raise_err(a.err, ERR_NONFINITE);
+  // the system steps again in this call: the forces stay in registers for
+  // the fused kick; otherwise they are kept for the read-back and the next
+  // call's opening kick
+  const bool again = stepping && *a.ctl.step + 1 < a.ctl.left[k];
+  if (!again) {
 #pragma unroll
-  for (int q = 0; q < 3; q++) {
-    ((Real *)a.F[q])[s] = F[q];
-    ((Real *)a.T[q])[s] = T[q];
+    for (int q = 0; q < 3; q++) {
+      ((Real *)a.F[q])[s] = F[q];
+      ((Real *)a.T[q])[s] = T[q];
+    }
   }
   if (stepping) {
     Real v[3] = {me.v[0], me.v[1], me.v[2]}, w[3] = {me.w[0], me.w[1], me.w[2]};
     const Real m = mass_of<Real>(c, rs);
     const Real I = (Real)0.4 * m * rs * rs;
     half_kick<Real>(c, m, I, F, T, v, w);
-    if (*a.ctl.step + 1 < a.ctl.left[k]) {
+    if (again) {
       // the next step's Steps 1-2 with the same forces: the same operations
       // as k_kick_drift_hash, so fusing changes no bit
       half_kick<Real>(c, m, I, F, T, v, w);

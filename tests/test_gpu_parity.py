@@ -296,3 +296,26 @@ def test_profile_phases_cover_the_step(dem):
     assert n == 10 and len(ms) == dem.NUM_PHASES and np.all(ms >= 0) and ms.sum() > 0
     ms2, n2 = s.profile_read()
     assert n2 == 0 and np.all(ms2 == 0)
+
+
+def test_backward_list_capacity_is_reported(dem):
+    # one large sphere touched by 60 small ones that mostly precede it in the
+    # sorted order (it has the highest id): more than the 32 lower partners a
+    # particle may have, which must be reported, not silently dropped
+    n_small = 60
+    R, r = 0.05, 0.01
+    c = np.array([0.1, 0.1, 0.1])
+    k = np.arange(n_small) + 0.5
+    phi = np.arccos(1 - 2 * k / n_small)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    x = np.concatenate([c + (R + 0.9 * r) * d, c[None]])
+    rad = W.fp32_radii(np.concatenate([np.full(n_small, r), [R]]))
+    z = np.zeros_like(x)
+    # one cell: every small sphere precedes the large one (ids order a cell)
+    p = W.base_params(box_hi=(0.2, 0.2, 0.2), cell_size=0.15, wall_mask=0, gravity=(0, 0, 0), dt=1e-6)
+    o = OracleSystem(p, x, z, z, rad)
+    assert len(o.contacts()) == n_small  # the oracle has no such limit
+    with pytest.raises(dem.DemError) as e:
+        dem.System(p, x, z, z, rad)
+    assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
