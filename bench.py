@@ -104,9 +104,9 @@ def pair_force_bytes(n, P, R):
     """k_pair_force: per contact its two slots (8 B), the committed history
     read (key 4 B, delta_t 3R), the new entry written (key 4 B, delta_t 3R)
     and the force and torque term written (6R); per particle its packed
-    state (x 24 B, r 4 B, v and w 6R) and its history index (12 B) read
-    once.  Partner reads are reuse."""
-    return P * (16 + 12 * R) + n * (40 + 6 * R)
+    state (x 24 B, r 4 B, v and w 6R, with the previous slot, history count
+    and history offset in 8 B) read once.  Partner reads are reuse."""
+    return P * (16 + 12 * R) + n * (36 + 6 * R)
 
 
 def step_algorithmic_bytes(n, z, R):

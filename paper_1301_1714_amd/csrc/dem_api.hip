@@ -23,8 +23,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// contact-list offsets are int32: n * kListCap must stay below 2^31
-constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 
 struct Engine {
   int32_t S = 0;
@@ -263,7 +261,6 @@ size_t carve(Engine &e, char *base) {
   e.nbr.xyzr = cv.take<float4>(N);
   e.nbr.fcnt = cv.take<int32_t>(N);
   e.nbr.pst = cv.take_bytes((e.prec == DEM_PREC_FP64 ? sizeof(PState<double>) : sizeof(PState<float>)) * N);
-  e.nbr.hix = cv.take<int4>(N);
   e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
   for (int b = 0; b < 2; b++) {
     e.gen[b].ofs = cv.take<int32_t>(N + 1);

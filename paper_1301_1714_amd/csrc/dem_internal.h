@@ -17,7 +17,7 @@
 //   nbr      detection output: xyzr (FP32 copy of x - lo and r, the
 //            prefilter's input) and, per particle, its contacts with higher
 //            slots in ascending order followed by its walls (-1 - w)
-//   pst      the law's inputs per particle, packed (PState<Real>); hix the
+//   pst      the law's inputs per particle, packed (PState<Real>), with the
 //            previous slot and committed history segment of each slot
 //   tiles    detection work items: (system, row, first cell, last cell)
 //   gen[2]   two generations of the compact contact array, CSR by owner slot
@@ -51,6 +51,8 @@ enum ModeBits : int32_t {
 
 constexpr int32_t kBlock = 256;
 constexpr int32_t kListCap = 64;  // detection: contacts per particle (higher partners + walls)
+// contact-list offsets are int32: n * kListCap must stay below 2^31
+constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 
@@ -102,13 +104,21 @@ struct VelBuf {
 };
 
 // The state the contact law reads, packed per particle so that a partner
-// costs one or two cache lines instead of one per array.
+// costs one or two cache lines instead of one per array.  In a time step it
+// also carries where the particle's committed tangential history is: its
+// previous slot (low kPrevBits bits of hp) and the count (high bits) and
+// first index (hb) of the contacts it owned there.
+constexpr int kPrevBits = 25;
+static_assert(kMaxParticles <= (1 << kPrevBits), "previous slot must fit in kPrevBits bits");
+static_assert(kListCap < (1 << (32 - kPrevBits)), "history count must fit above the previous slot");
 template <typename Real>
 struct alignas(16) PState {
   double x, y, z;
   Real v[3], w[3];
   float r;
   int32_t id;
+  uint32_t hp;  // previous slot | owned history count << kPrevBits
+  int32_t hb;   // first committed history entry of the previous slot
 };
 
 struct NbrBuf {
@@ -116,7 +126,6 @@ struct NbrBuf {
   int32_t *fcnt;  // [N] entries of nb (clamped to kListCap)
   int32_t *nb;    // [kListCap][N]
   void *pst;      // [N] PState<Real> of the current slots
-  int4 *hix;      // [N] time steps: (previous slot, its committed history segment begin, end, 0)
 };
 
 struct PairGen {
@@ -192,8 +201,8 @@ hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, in
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
 // Step 4 into the packed records nb.pst (and, with soa, into dst / vdst as
 // well; a time step leaves that to its gather); old_ofs: offsets of the
-// committed history, whose segments are recorded per new slot in nb.hix
-// (nullptr: none)
+// committed history, whose segments are recorded in the records (nullptr:
+// none)
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st);

@@ -4,27 +4,28 @@
 // systems of an engine at once; per-particle kernels run blocks that never
 // straddle two systems, so a block reads its system's constants once):
 //   Steps 1-2    k_kick_drift_hash: opening half kick, drift and the cell
-//                hash (CM) fused; between two steps of one call k_force does
-//                it instead, for the next step
+//                hash (CM) fused; between two steps of one call k_gather
+//                does it instead, for the next step
 //   Step 3       k_count / scan / k_scatter / k_canon: counting sort by cell,
 //                ties ordered by particle id, so SCM[j] = CM[SCCM[j]] (Eq. 11)
 //                holds with one unique order; the paper's bitonic sort is
 //                replaced by this O(N) sort (any correct sort of unique keys
 //                gives the same permutation)
-//   Step 4       k_reorder: gather every array into the sorted order, plus an
-//                FP32 copy of (x - lo, r) for the detection prefilter
+//   Step 4       k_reorder: gather the state into the sorted order as one
+//                packed record per particle, plus an FP32 copy of (x - lo, r)
+//                for the detection prefilter
 //   Steps 5-6    k_detect_direct / k_detect_tiles: each particle sweeps the
-//                27 cells of Eq. 12 (skipping cells beyond reach), rejects
-//                with a conservative FP32 test and decides the rest exactly
-//                in FP64; its contacts, in ascending slot order, and its
-//                walls form its list.  k_pairs: the keys of the contacts
-//                each particle owns (higher partners, walls) form the CSR
-//                array that will hold the new tangential history
-//   Steps 7-8    k_force: one lane per particle evaluates the law of every
-//                contact on its list (Eqs. 2-10, or Eq. 1) in the pair's
-//                canonical orientation, looks the history up in the previous
-//                array, sums in list order (no atomics) and applies the
-//                closing half kick
+//                forward half of the 27 cells of Eq. 12 (skipping cells
+//                beyond reach), rejects with a conservative FP32 test and
+//                decides the rest exactly in FP64; its contacts, in ascending
+//                slot order, and its walls form its list.  k_pairs: the lists
+//                become the compact contact array (CSR by owner slot), and
+//                each contact joins its partner's backward list
+//   Steps 7-8    k_pair_force: one lane per contact evaluates the law
+//                (Eqs. 2-10, or Eq. 1) once, seen from the owner, with the
+//                history looked up in the previous array.  k_gather: one lane
+//                per particle sums its contacts in a fixed order (no float
+//                atomics) and applies the closing half kick
 // No step is a dense contraction, so nothing here uses the matrix cores.
 #include <math.h>
 
@@ -356,10 +357,16 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   }
   ps.r = src.r[p];
   ps.id = src.id[p];
+  ps.hp = 0;
+  ps.hb = 0;
+  if (old_ofs) {
+    const int32_t b = old_ofs[p], c = min(old_ofs[p + 1] - b, kListCap);
+    ps.hp = (uint32_t)p | ((uint32_t)c << kPrevBits);
+    ps.hb = b;
+  }
   ((PState<Real> *)nb.pst)[s] = ps;
   nb.xyzr[s] = make_xyzr(L.tab[k].g, ps.x, ps.y, ps.z, ps.r);
   scell[s] = cell[p];
-  if (old_ofs) nb.hix[s] = make_int4(p, old_ofs[p], old_ofs[p + 1], 0);
   if (soa) {
     dst.x[s] = ps.x;
     dst.y[s] = ps.y;
@@ -390,6 +397,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
   }
   ps.r = pos.r[s];
   ps.id = pos.id[s];
+  ps.hp = 0;
+  ps.hb = 0;
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
@@ -964,9 +973,16 @@ __device__ __forceinline__ void pair_history(const PairGen &old, int64_t cap, co
   }
 }
 
-// previous slot and committed history segment of slot s
-__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s) {
-  return old_perm ? a.nb.hix[s] : make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
+// previous slot and committed history segment [begin, end) of slot s, whose
+// packed record is ps: recorded there in a time step, the slot's own
+// otherwise
+template <typename Real>
+__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
+  if (old_perm) {
+    const int32_t p = (int32_t)(ps.hp & ((1u << kPrevBits) - 1)), c = (int32_t)(ps.hp >> kPrevBits);
+    return make_int4(p, ps.hb, ps.hb + c, 0);
+  }
+  return make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
 }
 
 // One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
@@ -989,11 +1005,12 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
   const SysInfo &si = a.L.tab[k];
   const Consts &c = si.c;
   const PState<Real> me = PS[s];
-  const int4 hs = hist_index(a, old_perm, s);
+  const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
+  const int4 hs = hist_index(a, old_perm, s, me);
   Real h[3] = {0, 0, 0};
   if (LAW != DEM_LAW_SIMPLE) {
     if (t >= 0)
-      pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t), h);
+      pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t, pt), h);
     else
       hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
   }
@@ -1008,7 +1025,6 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
   LawOut<Real> o;
   Real n[3], delta, R;
   if (t >= 0) {
-    const PState<Real> pt = PS[t];
     const double dx = pt.x - me.x, dy = pt.y - me.y, dz = pt.z - me.z;
     const double d2 = dist2_exact(dx, dy, dz);
     const double S = (double)rsf + (double)pt.r;
