@@ -84,9 +84,13 @@ typedef struct {
                                       after it (walls included) and 32 before it */
     int32_t precision;           /* dem_precision */
     int32_t tile_cells;          /* detection launch shape: 0 = one lane per particle reading
-                                    neighbours through the caches; 1..32 = workgroups over
-                                    runs of this many cells along x, neighbours staged in
-                                    LDS.  Changes only speed, never the contacts found */
+                                    neighbours through the caches; -1 = one wave64 per run
+                                    of 8 cells along x, the candidates of a cell in the
+                                    lanes and its particles in turn, prefilter survivors
+                                    compacted by ballot and decided 64 at a time; 1..32 =
+                                    workgroups over runs of this many cells along x,
+                                    neighbours staged in LDS.  Changes only speed, never
+                                    the contacts found */
 } dem_params;
 
 typedef struct dem_system dem_system; /* opaque host-side handle */

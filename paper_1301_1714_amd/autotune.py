@@ -7,8 +7,10 @@ Two knobs, neither of which changes the contacts found:
               count and scan in a dilute system, more candidates to reject
               in a dense one;
   tile        the detection launch shape: one lane per particle reading its
-              neighbours through the caches (0), or workgroups over runs of
-              that many cells staging the neighbouring rows in LDS.
+              neighbours through the caches (0), one wave per run of cells
+              with the candidates in the lanes and survivors compacted by
+              ballot (-1), or workgroups over runs of that many cells staging
+              the neighbouring rows in LDS (8, 16).
 The tuner times short runs of a representative system of each class (size
 octave x packing-fraction band) for every candidate pair and keeps the
 fastest.  The choice for a system is then a pure function of its class and
@@ -22,7 +24,7 @@ import os
 import time
 
 CANDIDATES = (1.0, 1.25, 1.5, 2.0)  # cell width / largest diameter
-TILES = (0, 8, 16)                   # detection launch shape (tile_cells)
+TILES = (0, -1, 8, 16)               # detection launch shape (tile_cells)
 PHI_BANDS = (0.3, 0.42)              # band edges of the packing fraction
 DEFAULT_PATH = os.path.join(os.path.expanduser("~"), ".cache", "paper_1301_1714_amd", "autotune.json")
 

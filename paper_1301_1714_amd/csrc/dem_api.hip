@@ -34,12 +34,14 @@ struct Engine {
   std::vector<SysInfo> info;  // host copy of the system table
   std::vector<int32_t> bsys_h, bfirst_h;
   std::vector<int4> tiles_h;  // detection work items
+  std::vector<int4> runs_h;   // wave detection work items
   int64_t ncell = 0;  // cells of all systems
   int64_t Pcap = 0;
   // device
   SysInfo *tab = nullptr;
   int32_t *psys = nullptr, *bsys = nullptr, *bfirst = nullptr;
   int4 *tiles = nullptr;
+  int4 *runs = nullptr;
   StepCtl ctl{};
   std::vector<int32_t> left_h;  // source of the ctl.left upload
   hipEvent_t left_ev = nullptr;  // that upload has been read
@@ -77,8 +79,10 @@ struct Engine {
     L.bsys = bsys;
     L.bfirst = bfirst;
     L.tiles = tiles;
+    L.runs = runs;
     L.nblocks = (int32_t)bsys_h.size();
     L.ntiles = (int32_t)tiles_h.size();
+    L.nruns = (int32_t)runs_h.size();
     L.ndirect = ndirect;
     L.n = n;
     L.S = S;
@@ -108,7 +112,7 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   if (p->contacts_per_particle < 1 || p->contacts_per_particle > kListCap) return DEM_E_INVALID;
   if (p->wall_mask > 0x3F) return DEM_E_INVALID;
   if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
-  if (p->tile_cells < 0 || p->tile_cells > kMaxTile) return DEM_E_INVALID;
+  if (p->tile_cells < -1 || p->tile_cells > kMaxTile) return DEM_E_INVALID;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
     const double L = p->box_hi[a] - p->box_lo[a];
@@ -174,6 +178,7 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   e.bsys_h.clear();
   e.bfirst_h.clear();
   e.tiles_h.clear();
+  e.runs_h.clear();
   e.ndirect = 0;
   for (int32_t k = 0; k < S; k++) {
     SysInfo &si = e.info[k];
@@ -196,6 +201,13 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     const int32_t nx = si.g.nc[0], rows = si.g.nc[1] * si.g.nc[2];
     si.tile = T;
     if (n[k] > 0 && T == 0) e.ndirect++;
+    if (n[k] > 0 && T < 0) {
+      if ((int64_t)e.runs_h.size() + (int64_t)rows * ((nx + kRunCells - 1) / kRunCells) >= (int64_t)INT32_MAX)
+        return DEM_E_INVALID;
+      for (int32_t row = 0; row < rows; row++)
+        for (int32_t x0 = 0; x0 < nx; x0 += kRunCells)
+          e.runs_h.push_back(make_int4(k, row, x0, std::min(x0 + kRunCells, nx) - 1));
+    }
     if (n[k] > 0 && T > 0) {
       if ((int64_t)e.tiles_h.size() + (int64_t)rows * ((nx + T - 1) / T) >= (int64_t)INT32_MAX)
         return DEM_E_INVALID;
@@ -229,6 +241,7 @@ size_t carve(Engine &e, char *base) {
   e.bsys = cv.take<int32_t>(B);
   e.bfirst = cv.take<int32_t>(B);
   e.tiles = cv.take<int4>(std::max<size_t>(e.tiles_h.size(), 1));
+  e.runs = cv.take<int4>(std::max<size_t>(e.runs_h.size(), 1));
   e.ctl.step = cv.take<int32_t>(64);
   e.ctl.left = cv.take<int32_t>(S);
   for (int b = 0; b < 2; b++) {
@@ -631,7 +644,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo) * e.info.size(), hipMemcpyHostToDevice, e.stream));
   HIP_TRY(hipStreamSynchronize(e.stream));
   if ((st = h2d(e, e.psys, psys)) != DEM_OK || (st = h2d(e, e.bsys, e.bsys_h)) != DEM_OK ||
-      (st = h2d(e, e.tiles, e.tiles_h)) != DEM_OK ||
+      (st = h2d(e, e.tiles, e.tiles_h)) != DEM_OK || (st = h2d(e, e.runs, e.runs_h)) != DEM_OK ||
       (st = h2d(e, e.bfirst, e.bfirst_h)) != DEM_OK || (st = h2d(e, e.err, zeros)) != DEM_OK ||
       (st = h2d(e, e.ctl.step, zeros)) != DEM_OK)
     return st;

@@ -55,6 +55,7 @@ constexpr int32_t kListCap = 64;  // detection: contacts per particle (higher pa
 constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
+constexpr int32_t kRunCells = 8;  // cells along x per wave of the wave-per-cell-run detection
 
 struct Grid {
   double lo[3], hi[3];
@@ -159,8 +160,10 @@ struct Layout {
   const int32_t *bsys;    // [nblocks]
   const int32_t *bfirst;  // [nblocks]
   const int4 *tiles;      // [ntiles] (system, y + ny z, first cell x, last cell x)
+  const int4 *runs;       // [nruns] the same for the wave-per-cell-run detection
   int32_t nblocks;
   int32_t ntiles;
+  int32_t nruns;
   int32_t ndirect;  // systems swept by the direct detection kernel
   int32_t n;
   int32_t S;

@@ -14,13 +14,13 @@
 //   Step 4       k_reorder: gather the state into the sorted order as one
 //                packed record per particle, plus an FP32 copy of (x - lo, r)
 //                for the detection prefilter
-//   Steps 5-6    k_detect_direct / k_detect_tiles: each particle sweeps the
-//                forward half of the 27 cells of Eq. 12 (skipping cells
-//                beyond reach), rejects with a conservative FP32 test and
-//                decides the rest exactly in FP64; its contacts, in ascending
-//                slot order, and its walls form its list.  k_pairs: the lists
-//                become the compact contact array (CSR by owner slot), and
-//                each contact joins its partner's backward list
+//   Steps 5-6    k_detect_direct / k_detect_cells / k_detect_tiles: each
+//                particle sweeps the forward half of the 27 cells of Eq. 12,
+//                rejects with a conservative FP32 test and decides the rest
+//                exactly in FP64; its contacts, in ascending slot order, and
+//                its walls form its list.  k_pairs: the lists become the
+//                compact contact array (CSR by owner slot), and each contact
+//                joins its partner's backward list
 //   Steps 7-8    k_pair_force: one lane per contact evaluates the law
 //                (Eqs. 2-10, or Eq. 1) once, seen from the owner, with the
 //                history looked up in the previous array.  k_gather: one lane
@@ -423,10 +423,12 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__r
 // decided exactly in FP64.  Rows are visited in (z, y) order and cells in x
 // order, so the contacts come out in ascending slot order, then the walls.
 //
-// Two launch shapes build the same lists: the direct one (one lane per
-// particle, candidates read through the caches) and the tiled one (one
-// workgroup per run of cells along x stages the FP32 copies of the rows it
-// needs in LDS first).  A system's tile_cells selects the shape.
+// Three launch shapes build the same lists: the direct one (one lane per
+// particle, candidates read through the caches), the wave one (k_detect_cells
+// below: one wave per run of cells, candidates in the lanes, particles in
+// turn) and the tiled one (one workgroup per run of cells along x stages the
+// FP32 copies of the rows it needs in LDS first).  A system's tile_cells
+// selects the shape.
 
 constexpr int kTileThreads = 128;
 constexpr int kHaloCap = 1024;  // particles staged per tile; a fuller tile reads global memory
@@ -592,13 +594,230 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
   const SysInfo &si = L.tab[k];
-  if (si.tile > 0) return;                        // the tiled kernel sweeps this system
+  if (si.tile != 0) return;                       // another launch shape sweeps this system
   if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
   const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
   const int32_t cc = scell[s] - si.g.c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
   sweep_particle<kBlock>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, err);
+}
+
+// --------------------------------------------------------------------------
+// Wave-per-cell-run detection (wave64 ballot and compaction).  One wave walks
+// a run of kRunCells consecutive cells of one row, taking their particles 64
+// consecutive slots at a time.  For each particle, uniform across the wave,
+// the lanes hold the candidates of its cell's forward half stencil -- its
+// own cell and the next one along x, cells x-1..x+1 of the next row and of
+// the three rows of the next plane -- as one concatenated slot range, 64 per
+// chunk, loaded coalesced once per cell and kept in registers.  The FP32
+// prefilter runs with every lane on that one particle; survivors are appended
+// in order (ballot + mbcnt) to the wave's queue in LDS and decided exactly in
+// FP64 64 at a time, so the contact branch costs one pass per 64 survivors
+// rather than holding a wave per survivor.  A particle's survivors enter the
+// queue together and in ascending slot order, so its list is exactly the
+// one the per-particle sweep makes.
+
+constexpr int kQueue = 128;    // survivor queue entries per wave
+constexpr int kCellWaves = 4;  // waves per workgroup
+
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// The forward half stencil of cell (cx, cy, cz) as five slot ranges in
+// ascending order: rb[h] their first slots, pc[h] the running total of their
+// lengths (pc[5] = all candidates).  Rows outside the grid are empty.
+struct CellRanges {
+  int32_t rb[5], pc[6];
+};
+
+__device__ __forceinline__ void cell_ranges(const SysInfo &si, const int32_t *cs, int32_t cx, int32_t cy,
+                                                 int32_t cz, CellRanges &R) {
+  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2], c0 = si.g.c0;
+  const int32_t xa = cx > 0 ? cx - 1 : 0, xb = cx < nx - 1 ? cx + 1 : nx - 1;
+  const int dys[5] = {0, 1, -1, 0, 1}, dzs[5] = {0, 0, 1, 1, 1};
+  R.pc[0] = 0;
+#pragma unroll
+  for (int h = 0; h < 5; h++) {
+    const int32_t yy = cy + dys[h], zz = cz + dzs[h];
+    int32_t b = 0, e = 0;
+    if (yy >= 0 && yy < ny && zz < nz) {
+      const int32_t row = c0 + (zz * ny + yy) * nx;
+      b = cs[row + (h == 0 ? cx : xa)];
+      e = cs[row + xb + 1];
+    }
+    R.rb[h] = b;
+    R.pc[h + 1] = R.pc[h] + (e - b);
+  }
+}
+
+// slot of candidate c (0 <= c < pc[5]) of the concatenated ranges
+__device__ __forceinline__ int32_t cand_slot(const CellRanges &R, int32_t c) {
+  int32_t t = R.rb[0] + c;
+#pragma unroll
+  for (int h = 1; h < 5; h++) t = c >= R.pc[h] ? R.rb[h] + (c - R.pc[h]) : t;
+  return t;
+}
+
+__global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, StepCtl ctl, int32_t only_active,
+                                                                  bool f64, NbrBuf nb,
+                                                                  const int32_t *__restrict__ scell,
+                                                                  const int32_t *__restrict__ cell_start,
+                                                                  int32_t *err) {
+  __shared__ int2 queue_all[kCellWaves][kQueue];  // (particle in group, candidate slot)
+  __shared__ int32_t cnt_all[kCellWaves][64];     // contacts so far of each particle of the group
+  const int32_t wave = uni((int32_t)(threadIdx.x >> 6)), lane = (int32_t)(threadIdx.x & 63);
+  const int32_t run = (int32_t)blockIdx.x * kCellWaves + wave;
+  if (run >= L.nruns) return;
+  const int4 rr = L.runs[run];
+  const int32_t k = uni(rr.x);
+  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
+  const SysInfo &si = L.tab[k];
+  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], c0 = si.g.c0;
+  const int32_t row = uni(rr.y), cy = row % ny, cz = row / ny;
+  const int32_t s_lo = uni(cell_start[c0 + row * nx + uni(rr.z)]);
+  const int32_t s_hi = uni(cell_start[c0 + row * nx + uni(rr.w) + 1]);
+  int2 *queue = queue_all[wave];
+  int32_t *cnt = cnt_all[wave];
+  const int32_t N = L.n;
+  const float eps = si.eps;
+  const float4 *xyzr = nb.xyzr;
+  const uint64_t lt = (1ull << lane) - 1;  // lanes below this one
+
+  for (int32_t g0 = s_lo; g0 < s_hi; g0 += 64) {
+    const int32_t gn = min(64, s_hi - g0);
+    cnt[lane] = 0;
+    int32_t qh = 0, qt = 0;  // queue head and tail (wave-uniform)
+
+    // decide the queue entries [qh, qh + m) exactly and file the contacts
+    auto flush = [&](int32_t m) {
+      __builtin_amdgcn_wave_barrier();
+      const bool act = lane < m;
+      const int2 e = queue[(qh + lane) & (kQueue - 1)];
+      const int32_t il = act ? e.x : -1, t = e.y;
+      bool ok = false;
+      if (act) {
+        const XR a = state_xr(nb, f64, g0 + il), b = state_xr(nb, f64, t);
+        const double S = (double)a.r + (double)b.r;
+        ok = dist2_exact(b.x - a.x, b.y - a.y, b.z - a.z) < sq_exact(S);
+      }
+      const uint64_t mok = __ballot(ok);
+      // a particle's entries are one run of lanes; rs: its first lane
+      const int32_t prev = __shfl_up(il, 1), next = __shfl_down(il, 1);
+      const uint64_t starts = __ballot(act && (lane == 0 || prev != il));
+      const uint64_t mine = starts & (lt | (1ull << lane));
+      const int32_t rs = mine ? 63 - __clzll(mine) : 0;
+      const int32_t before = __popcll(mok & lt & ~((1ull << rs) - 1));
+      if (ok) {
+        const int32_t pos = cnt[il] + before;
+        if (pos < kListCap) nb.nb[(int64_t)pos * N + g0 + il] = t;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (act && (lane == m - 1 || next != il)) cnt[il] += before + (ok ? 1 : 0);
+      __builtin_amdgcn_wave_barrier();
+      qh += m;
+    };
+
+    // each lane loads its particle's prefilter copy, cell and candidate
+    // ranges once; the loops below read them with readlane
+    const int32_t me = g0 + (lane < gn ? lane : 0);
+    const float4 pv = xyzr[me];
+    const int32_t mcell = scell[me];
+    CellRanges Rl;
+    {
+      const int32_t cc = mcell - c0;
+      cell_ranges(si, cell_start, cc % nx, cy, cz, Rl);
+    }
+    const uint64_t starts = __ballot(lane < gn && (lane == 0 || __shfl_up(mcell, 1) != mcell));
+    auto ranges_of = [&](int32_t l, CellRanges &R) {
+#pragma unroll
+      for (int h = 0; h < 5; h++) R.rb[h] = __builtin_amdgcn_readlane(Rl.rb[h], l);
+#pragma unroll
+      for (int h = 0; h < 6; h++) R.pc[h] = __builtin_amdgcn_readlane(Rl.pc[h], l);
+    };
+    auto load_chunks = [&](const CellRanges &R, float4 &qa, int32_t &ta, float4 &qb, int32_t &tb) {
+      const int32_t C = R.pc[5];
+      ta = lane < C ? cand_slot(R, lane) : -1;
+      tb = 64 + lane < C ? cand_slot(R, 64 + lane) : -1;
+      qa = xyzr[ta >= 0 ? ta : me];
+      qb = xyzr[tb >= 0 ? tb : me];
+    };
+    CellRanges R;
+    ranges_of(0, R);
+    float4 q0, q1;
+    int32_t t0, t1;
+    load_chunks(R, q0, t0, q1, t1);
+    int32_t a = 0;  // first lane of the current cell
+    while (a < gn) {
+      // the next cell's first lane and its chunks, in flight while this
+      // cell is tested
+      const uint64_t later = starts & ~((2ull << a) - 1);
+      const int32_t b = later ? __ffsll((long long)later) - 1 : gn;
+      CellRanges Rn = R;
+      float4 n0 = q0, n1 = q1;
+      int32_t u0 = t0, u1 = t1;
+      if (b < gn) {
+        ranges_of(b, Rn);
+        load_chunks(Rn, n0, u0, n1, u1);
+      }
+      const int32_t C = R.pc[5];
+      for (int32_t l = a; l < b; l++) {
+        const int32_t i = g0 + l;
+        const float px = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), l));
+        const float py = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), l));
+        const float pz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), l));
+        const float pe = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), l)) + eps;
+        auto test = [&](const float4 &q, int32_t t) {
+          const float dx = q.x - px, dy = q.y - py, dz = q.z - pz, sf = pe + q.w;
+          const bool pass = t > i && dx * dx + dy * dy + dz * dz < sf * sf;
+          const uint64_t m = __ballot(pass);
+          if (m) {
+            if (pass) queue[(qt + __popcll(m & lt)) & (kQueue - 1)] = make_int2(l, t);
+            qt += __popcll(m);
+            if (qt - qh >= 64) flush(64);
+          }
+        };
+        test(q0, t0);
+        if (C > 64) test(q1, t1);
+        for (int32_t cb = 128; cb < C; cb += 64) {  // a crowded stencil: further chunks from the caches
+          const int32_t t = cb + lane < C ? cand_slot(R, cb + lane) : -1;
+          test(xyzr[t >= 0 ? t : me], t);
+        }
+      }
+      R = Rn;
+      q0 = n0;
+      q1 = n1;
+      t0 = u0;
+      t1 = u1;
+      a = b;
+    }
+    if (qt > qh) flush(qt - qh);
+    // Step 8: walls, particles of infinite radius, after the pairs
+    if (lane < gn) {
+      const int32_t s = g0 + lane;
+      int32_t nf = cnt[lane];
+      const uint32_t wall_mask = si.c.wall_mask;
+      if (wall_mask) {
+        const XR a = state_xr(nb, f64, s);
+        const double xs[3] = {a.x, a.y, a.z};
+        const double rid = (double)a.r;
+        for (int w = 0; w < 6; w++) {
+          if (!((wall_mask >> w) & 1)) continue;
+          const int ax = w >> 1;
+          const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
+          if (gap < rid) {
+            if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = -1 - w;
+            nf++;
+          }
+        }
+      }
+      if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
+      nb.fcnt[s] = nf < kListCap ? nf : kListCap;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 template <bool kStaged>
@@ -826,6 +1045,9 @@ hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, con
   if (L.ndirect > 0)
     k_detect_direct<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
                                                    err);
+  if (L.nruns > 0)
+    k_detect_cells<<<(L.nruns + kCellWaves - 1) / kCellWaves, kCellWaves * 64, 0, st>>>(
+        L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start, err);
   if (L.ntiles > 0)
     k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell,
                                                        cell_start, err);

@@ -22,7 +22,9 @@ Parameter dictionary keys (each side marshals them into its own structure):
   mu                 Coulomb friction coefficient (Eq. 5)
   cell_size          requested cell width of the collision-detection grid
   contacts_per_particle  contact-list capacity per particle, on average (GPU only)
-  tile_cells         cells along x per detection workgroup (GPU only; speed only)
+  tile_cells         detection launch shape: 0 one lane per particle, -1 one wave
+                     per run of cells, 1..32 cells per LDS-staged workgroup
+                     (GPU only; speed only)
   precision          "fp64" or "mixed" (FP32 forces, FP64 positions; GPU only)
 """
 import math

@@ -68,6 +68,11 @@ def test_workspace_bytes_and_validation_on_host(L):
         dem.dem_workspace_bytes(dict(p, restitution=1.5), 10)
     with pytest.raises(dem.DemError):
         dem.dem_workspace_bytes(p, -1)
+    for tile in (-1, 0, 8, 32):  # detection launch shapes
+        assert dem.dem_workspace_bytes(dict(p, tile_cells=tile), 4096) > 0
+    for tile in (-2, 33):
+        with pytest.raises(dem.DemError):
+            dem.dem_workspace_bytes(dict(p, tile_cells=tile), 4096)
     assert L.dem_status_string(-3) == b"contact list overflow"
 
 

@@ -260,13 +260,14 @@ def test_contact_list_overflow_is_reported(dem):
     assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
 
 
-@pytest.mark.parametrize("tile,cell_scale", [(1, 1.0), (5, 1.0), (32, 1.0), (32, 4.0)])
+@pytest.mark.parametrize("tile,cell_scale", [(1, 1.0), (5, 1.0), (32, 1.0), (32, 4.0), (-1, 1.0), (-1, 4.0)])
 @pytest.mark.parametrize("name", ["fp64_partial_walls_5000", "mixed_nowalls_poly_4097", "mixed_hertz_2500"])
 def test_tiled_detection_is_bit_identical(dem, name, tile, cell_scale):
     # tile_cells selects the detection launch shape only: the same lists, so
     # the same forces and trajectories to the bit.  cell_scale 4 packs so many
     # particles per cell that the tile's rows overflow LDS and are read from
-    # global memory instead.
+    # global memory instead, and that the wave shape (-1) sees cells of more
+    # than 64 particles and stencils of more than two chunks.
     c = cloud(**CASES[name])
     p = dict(c["params"], mu=0.2, eta_t_ratio=0.5, dt=2e-6, cell_size=cell_scale * c["params"]["cell_size"])
     a = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
