@@ -16,6 +16,7 @@ import pytest
 
 from oracle.oracle import OracleSystem
 from paper_1301_1714_amd import workloads as W
+from parity_util import assert_forces_close
 
 pytestmark = pytest.mark.gpu
 
@@ -53,23 +54,6 @@ def make(dem, c, **kw):
     g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"], **kw)
     o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"], **kw)
     return g, o
-
-
-def assert_forces_close(Fg, Tg, F, T, Fa, Ta, tol):
-    dF = np.linalg.norm(Fg - F, axis=1)
-    dT = np.linalg.norm(Tg - T, axis=1)
-    free = Fa == 0
-    assert np.all(Fg[free] == 0.0) and np.all(Tg[Ta == 0] == 0.0)
-    floor = 1e-2 * tol  # only matters in FP64 (see the module docstring)
-    if np.any(~free):
-        bound = tol * Fa[~free] + floor * Fa.max()
-        worst = np.max(dF[~free] / bound)
-        assert worst <= 1.0, f"force error {worst:.3f} x the bound (tol {tol:.1e})"
-    has_t = Ta > 0
-    if np.any(has_t):
-        bound = tol * Ta[has_t] + floor * Ta.max()
-        wt = np.max(dT[has_t] / bound)
-        assert wt <= 1.0, f"torque error {wt:.3f} x the bound (tol {tol:.1e})"
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
