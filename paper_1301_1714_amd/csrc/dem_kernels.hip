@@ -737,12 +737,26 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
 #pragma unroll
       for (int h = 0; h < 6; h++) R.pc[h] = __builtin_amdgcn_readlane(Rl.pc[h], l);
     };
+    // A cell with 65..96 candidates tests its second chunk for two
+    // particles at once, 32 lanes each: both halves hold candidates 64..95.
+    auto halves = [](int32_t C) { return C > 64 && C <= 96; };
     auto load_chunks = [&](const CellRanges &R, float4 &qa, int32_t &ta, float4 &qb, int32_t &tb) {
       const int32_t C = R.pc[5];
+      const int32_t cb = 64 + (halves(C) ? (lane & 31) : lane);
       ta = lane < C ? cand_slot(R, lane) : -1;
-      tb = 64 + lane < C ? cand_slot(R, 64 + lane) : -1;
+      tb = cb < C ? cand_slot(R, cb) : -1;
       qa = xyzr[ta >= 0 ? ta : me];
       qb = xyzr[tb >= 0 ? tb : me];
+    };
+    // queue the lanes of m (this lane if mine) as contacts of particle l
+    auto append = [&](uint64_t m, bool mine, int32_t l, int32_t t) {
+      if (!m) return;
+      if (mine) {
+        const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qt));
+        queue[pos & (kQueue - 1)] = make_int2(l, t);
+      }
+      qt += __popcll(m);
+      if (qt - qh >= 64) flush(64);
     };
     CellRanges R;
     ranges_of(0, R);
@@ -763,28 +777,49 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
         load_chunks(Rn, n0, u0, n1, u1);
       }
       const int32_t C = R.pc[5];
-      for (int32_t l = a; l < b; l++) {
+      const bool split = halves(C);
+      for (int32_t l = a; l < b;) {
         const int32_t i = g0 + l;
         const float px = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), l));
         const float py = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), l));
         const float pz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), l));
         const float pe = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), l)) + eps;
-        auto test = [&](const float4 &q, int32_t t) {
-          const float dx = q.x - px, dy = q.y - py, dz = q.z - pz, sf = pe + q.w;
-          const bool pass = t > i && dx * dx + dy * dy + dz * dz < sf * sf;
-          const uint64_t m = __ballot(pass);
-          if (m) {
-            if (pass) queue[(qt + __popcll(m & lt)) & (kQueue - 1)] = make_int2(l, t);
-            qt += __popcll(m);
-            if (qt - qh >= 64) flush(64);
-          }
+        auto passes = [&](const float4 &q, int32_t t, float x, float y, float z, float e, int32_t ii) {
+          const float dx = q.x - x, dy = q.y - y, dz = q.z - z, sf = e + q.w;
+          return (t > ii) & (dx * dx + dy * dy + dz * dz < sf * sf);
         };
-        test(q0, t0);
-        if (C > 64) test(q1, t1);
+        // chunk 0 of particle l
+        {
+          const bool ps = passes(q0, t0, px, py, pz, pe, i);
+          append(__builtin_amdgcn_ballot_w64(ps), ps, l, t0);
+        }
+        if (split && l + 1 < b) {
+          // chunk 1 of particles l (lanes 0-31) and l + 1 (lanes 32-63);
+          // l + 1 files its chunk-1 survivors after its chunk-0 ones
+          const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), l + 1));
+          const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), l + 1));
+          const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), l + 1));
+          const float qe = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), l + 1)) + eps;
+          const bool lo = lane < 32;
+          const bool p1 = passes(q1, t1, lo ? px : qx, lo ? py : qy, lo ? pz : qz, lo ? pe : qe, lo ? i : i + 1);
+          const uint64_t m1 = __builtin_amdgcn_ballot_w64(p1);
+          append(m1 & 0xFFFFFFFFull, p1 && lo, l, t1);
+          const bool p0 = passes(q0, t0, qx, qy, qz, qe, i + 1);
+          append(__builtin_amdgcn_ballot_w64(p0), p0, l + 1, t0);
+          append(m1 & ~0xFFFFFFFFull, p1 && !lo, l + 1, t1);
+          l += 2;
+          continue;
+        }
+        if (C > 64) {
+          const bool ps = (!split || lane < 32) && passes(q1, t1, px, py, pz, pe, i);
+          append(__builtin_amdgcn_ballot_w64(ps), ps, l, t1);
+        }
         for (int32_t cb = 128; cb < C; cb += 64) {  // a crowded stencil: further chunks from the caches
           const int32_t t = cb + lane < C ? cand_slot(R, cb + lane) : -1;
-          test(xyzr[t >= 0 ? t : me], t);
+          const bool ps = passes(xyzr[t >= 0 ? t : me], t, px, py, pz, pe, i);
+          append(__builtin_amdgcn_ballot_w64(ps), ps, l, t);
         }
+        l += 1;
       }
       R = Rn;
       q0 = n0;
