@@ -292,13 +292,19 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t *__restrict__ 
   perm[cell_start[cell[i]] + rank[i]] = i;
 }
 
-// insertion sort of each cell's slots by particle id (cells hold a handful)
+// Each cell's slots ordered by particle id.  Cells of up to kCanonSerial
+// particles (the usual handful): one thread's insertion sort.
+constexpr int32_t kCanonSerial = 32;
+constexpr int32_t kCanonChunk = 4096;  // cells scanned per workgroup by k_canon_big
+constexpr int32_t kCanonIds = 1024;    // ids staged in LDS per round of k_canon_big
+
 __global__ __launch_bounds__(kBlock) void k_canon(const int32_t *__restrict__ cell_start,
                                                   const int32_t *__restrict__ id_old, int32_t *perm,
                                                   int64_t ncell) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= ncell) return;
   const int32_t beg = cell_start[c], end = cell_start[c + 1];
+  if (end - beg > kCanonSerial) return;  // a crowded cell: k_canon_big
   for (int32_t k = beg + 1; k < end; k++) {
     const int32_t pk = perm[k];
     const int32_t key = id_old[pk];
@@ -308,6 +314,46 @@ __global__ __launch_bounds__(kBlock) void k_canon(const int32_t *__restrict__ ce
       j--;
     }
     perm[j + 1] = pk;
+  }
+}
+
+// Crowded cells (more than kCanonSerial particles: a degenerate grid or a
+// pile-up), each ordered by one workgroup instead of one thread: a
+// particle's place in its cell is the number of the cell's ids below its
+// own (ids are unique), counted against the ids staged kCanonIds at a time
+// in LDS; the permutation goes through tmp and back.
+__global__ __launch_bounds__(kBlock) void k_canon_big(const int32_t *__restrict__ cell_start,
+                                                      const int32_t *__restrict__ id_old, int32_t *perm,
+                                                      int32_t *tmp, int64_t ncell) {
+  __shared__ int32_t big[kCanonChunk];
+  __shared__ int32_t ids[kCanonIds];
+  __shared__ int32_t nbig;
+  const int64_t c_lo = (int64_t)blockIdx.x * kCanonChunk;
+  if (threadIdx.x == 0) nbig = 0;
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < kCanonChunk && c_lo + i < ncell; i += kBlock)
+    if (cell_start[c_lo + i + 1] - cell_start[c_lo + i] > kCanonSerial) big[atomicAdd(&nbig, 1)] = i;
+  __syncthreads();
+  const int32_t nb = nbig;
+  for (int32_t b = 0; b < nb; b++) {
+    const int64_t c = c_lo + big[b];
+    const int32_t beg = cell_start[c], n = cell_start[c + 1] - beg;
+    for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
+      const int32_t e = e0 + (int32_t)threadIdx.x;
+      const int32_t key = e < n ? id_old[perm[beg + e]] : 0;
+      int32_t r = 0;
+      for (int32_t f0 = 0; f0 < n; f0 += kCanonIds) {
+        const int32_t m = min(kCanonIds, n - f0);
+        __syncthreads();
+        for (int32_t f = threadIdx.x; f < m; f += kBlock) ids[f] = id_old[perm[beg + f0 + f]];
+        __syncthreads();
+        for (int32_t f = 0; f < m; f++) r += ids[f] < key ? 1 : 0;
+      }
+      if (e < n) tmp[beg + r] = perm[beg + e];
+    }
+    __syncthreads();
+    for (int32_t e = threadIdx.x; e < n; e += kBlock) perm[beg + e] = tmp[beg + e];
+    __syncthreads();
   }
 }
 
@@ -321,6 +367,9 @@ hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, in
   if (n > 0) {
     k_scatter<<<blocks_for(n), kBlock, 0, st>>>(cell, rank, cell_start, perm, n);
     k_canon<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, id_old, perm, ncell);
+    // rank is free once scattered: the crowded cells' permutation passes through it
+    k_canon_big<<<(unsigned)((ncell + kCanonChunk - 1) / kCanonChunk), kBlock, 0, st>>>(cell_start, id_old, perm,
+                                                                                      rank, ncell);
   }
   return hipGetLastError();
 }

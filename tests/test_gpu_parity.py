@@ -216,6 +216,29 @@ def test_one_cell_grid(dem):
     assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["fp64"])
 
 
+def test_crowded_cells_keep_the_canonical_order(dem):
+    # 2,600 small spheres piled into one cell and 700 spread over the box:
+    # cells far above the handful the per-thread insertion sort handles,
+    # several workgroup rounds and several LDS rounds of ids per cell
+    rng = np.random.default_rng(21)
+    spread = rng.uniform(0.05, 0.95, (700, 3))
+    pile = rng.uniform(0.21, 0.29, (2600, 3))
+    x = np.concatenate([spread, pile])
+    r = W.fp32_radii(np.concatenate([rng.uniform(0.01, 0.03, 700), np.full(2600, 0.0012)]))
+    p = W.base_params(cell_size=0.1, gravity=(0, 0, 0), contacts_per_particle=16)
+    v = rng.normal(0, 0.1, x.shape)
+    w = rng.normal(0, 1.0, x.shape)
+    g = dem.System(p, x, v, w, r)
+    o = OracleSystem(p, x, v, w, r)
+    for a, b in zip(g.read_grid(), o.read_grid()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(g.contacts(), o.contacts())
+    g.step(3)
+    o.step(3)
+    for a, b in zip(g.read_grid(), o.read_grid()):
+        assert np.array_equal(a, b)
+
+
 def test_out_of_domain_is_reported(dem):
     p = W.base_params(cell_size=0.1, wall_mask=0, gravity=(0, 0, 0))
     x = np.array([[0.5, 0.5, 0.5], [1.2, 0.5, 0.5]])
