@@ -1121,6 +1121,23 @@ __device__ __forceinline__ void for_sorted(const int32_t *bwd, int32_t n, int32_
     if (i < cnt) fn(L[i]);
 }
 
+// the same for a long list (rare), without a register array: each next
+// entry is the smallest one above the previous (the entries are distinct
+// contact indices)
+template <typename Fn>
+__device__ __forceinline__ void for_selected(const int32_t *bwd, int32_t n, int32_t s, int32_t cnt, Fn &&fn) {
+  int32_t prev = -1;
+  for (int32_t i = 0; i < cnt; i++) {
+    int32_t cur = INT32_MAX;
+    for (int32_t k = 0; k < cnt; k++) {
+      const int32_t q = bwd[(int64_t)k * n + s];
+      cur = q > prev && q < cur ? q : cur;
+    }
+    fn(cur);
+    prev = cur;
+  }
+}
+
 hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
                          const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
@@ -1450,10 +1467,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     for_sorted<4>(a.w.bwd, N, s, nbk, back);
   else if (nbk <= 8)
     for_sorted<8>(a.w.bwd, N, s, nbk, back);
-  else if (nbk <= 16)
-    for_sorted<16>(a.w.bwd, N, s, nbk, back);
   else
-    for_sorted<32>(a.w.bwd, N, s, nbk, back);
+    for_selected(a.w.bwd, N, s, nbk, back);  // a register network this long would cost every wave occupancy
   const int64_t f0 = a.cur.ofs[s];
   const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
   double e_el = 0.0, dmax = 0.0;

@@ -306,11 +306,10 @@ def test_profile_phases_cover_the_step(dem):
     assert n2 == 0 and np.all(ms2 == 0)
 
 
-def test_backward_list_capacity_is_reported(dem):
-    # one large sphere touched by 60 small ones that mostly precede it in the
-    # sorted order (it has the highest id): more than the 32 lower partners a
-    # particle may have, which must be reported, not silently dropped
-    n_small = 60
+def crowned_sphere(n_small, seed=0):
+    """One large sphere touched by n_small small ones spread over its
+    surface, all in one cell, the large one last in id (so every contact is
+    one of its backward contacts), with seeded velocities and spins."""
     R, r = 0.05, 0.01
     c = np.array([0.1, 0.1, 0.1])
     k = np.arange(n_small) + 0.5
@@ -319,9 +318,40 @@ def test_backward_list_capacity_is_reported(dem):
     d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
     x = np.concatenate([c + (R + 0.9 * r) * d, c[None]])
     rad = W.fp32_radii(np.concatenate([np.full(n_small, r), [R]]))
-    z = np.zeros_like(x)
-    # one cell: every small sphere precedes the large one (ids order a cell)
+    rng = np.random.default_rng(seed)
+    v, w = rng.normal(0, 0.05, x.shape), rng.normal(0, 2.0, x.shape)
     p = W.base_params(box_hi=(0.2, 0.2, 0.2), cell_size=0.15, wall_mask=0, gravity=(0, 0, 0), dt=1e-6)
+    return p, x, v, w, rad
+
+
+@pytest.mark.parametrize("n_small,precision", [(6, "fp64"), (20, "fp64"), (20, "mixed"), (32, "mixed")])
+def test_long_backward_lists_sum_in_order(dem, n_small, precision):
+    # a particle with many lower partners: short lists are sorted in
+    # registers, long ones by repeated selection; the sums follow the same
+    # fixed order either way and match the oracle
+    p, x, v, w, rad = crowned_sphere(n_small, seed=n_small)
+    p = dict(p, precision=precision, mu=0.3, eta_t_ratio=0.5)
+    g = dem.System(p, x, v, w, rad)
+    o = OracleSystem(p, x, v, w, rad)
+    assert len(o.contacts()) == n_small
+    assert np.array_equal(g.contacts(), o.contacts())
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL[precision])
+    g.step(5)
+    o.step(5)
+    sg, so = g.read_state(), o.read_state()
+    scale = np.abs(so["x"]).max()
+    assert np.abs(sg["x"] - so["x"]).max() <= (1e-12 if precision == "fp64" else 1e-6) * scale
+
+
+def test_backward_list_capacity_is_reported(dem):
+    # one large sphere touched by 60 small ones that all precede it in the
+    # sorted order (it has the highest id): more than the 32 lower partners a
+    # particle may have, which must be reported, not silently dropped
+    n_small = 60
+    p, x, _, _, rad = crowned_sphere(n_small)
+    z = np.zeros_like(x)
     o = OracleSystem(p, x, z, z, rad)
     assert len(o.contacts()) == n_small  # the oracle has no such limit
     with pytest.raises(dem.DemError) as e:
