@@ -1315,7 +1315,7 @@ __device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int
 // the contacts of a system that has finished its steps only carry their
 // history forward.
 template <typename Real, int LAW>
-__device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
+__device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q, int32_t s, int32_t t) {
   const int64_t cap = a.cap;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
@@ -1323,7 +1323,6 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const bool stepping = (a.mode & MODE_KICK) != 0;
   const bool one_sys = a.L.S == 1;
-  const int32_t s = a.cur.s[q], t = a.cur.t[q];
   const int32_t k = one_sys ? 0 : a.L.psys[s];
   const SysInfo &si = a.L.tab[k];
   const Consts &c = si.c;
@@ -1396,8 +1395,17 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q) {
 template <typename Real, int LAW>
 __global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
   const int32_t P = num_pairs(a.cur, a.L.n, a.cap);
-  for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < P; q += gridDim.x * kBlock)
-    pair_force_one<Real, LAW>(a, q);
+  const int32_t stride = gridDim.x * kBlock;
+  int32_t q = blockIdx.x * kBlock + threadIdx.x;
+  int32_t s = q < P ? a.cur.s[q] : 0, t = q < P ? a.cur.t[q] : 0;
+  for (; q < P; q += stride) {
+    // the next contact's slots are in flight while this one is evaluated
+    const int32_t qn = q + stride;
+    const int32_t sn = qn < P ? a.cur.s[qn] : 0, tn = qn < P ? a.cur.t[qn] : 0;
+    pair_force_one<Real, LAW>(a, q, s, t);
+    s = sn;
+    t = tn;
+  }
 }
 
 // Step 1 drift x += dt v and Step 2 hash of the new position, written to
