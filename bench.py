@@ -10,6 +10,11 @@ see paper_1301_1714_amd/prepare.py); the timed steps run with kn = 1e5,
 e = 0.9, kt = 2/7 kn, mu = 0.3.
 
 Also measured (unless skipped):
+  configs  the other single-system workloads, each as specified: 4,096 equal
+           spheres in FP64 (1,000 steps) and the 2^20-sphere settling gas
+           under the practical (linear) law and under the simple law of Eq. 1
+           (10,000 steps each), with graph replay; the practical/simple time
+           ratio is reported next to the paper's (about 7 on its GPU).
   batched  256 independent systems (sizes log-uniform in [1k, 256k], materials
            and packing fractions drawn per system), cells from the autotuner,
            all stepped together with graph replay, 1,000 steps each; against
@@ -139,12 +144,25 @@ def cpu_baseline(target_seconds):
     t0 = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t0
-    return {"value": n * k / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} spheres of the dense-bed recipe (lattice at {lam:.3f} of full radii), "
-                      f"{k} steps, {dt:.1f} s, FP64, single thread"}
+    out = {"value": n * k / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n} spheres of the dense-bed recipe (lattice at {lam:.3f} of full radii), "
+                     f"{k} steps, {dt:.1f} s, FP64, single thread"}
+    # the 4,096-sphere FP64 configuration in full (1,000 steps), for the
+    # GPU/CPU ratio of the paper's kind
+    wp = W.plain_fp64(seed=1000)
+    o = OracleSystem(wp["params"], wp["x"], wp["v"], wp["omega"], wp["r"])
+    t0 = time.perf_counter()
+    o.step(1000)
+    dt = time.perf_counter() - t0
+    out["plain_fp64_4096"] = {"value": 4096 * 1000 / dt, "unit": "particle-steps/s", "cores": 1,
+                              "sample": f"4096 spheres, 1000 steps, {dt:.1f} s"}
+    return out
 
 
 # ------------------------------------------------------------ dense bed
+
+_DENSE = {}  # the prepared bed, for the law comparison of bench_configs
+
 
 def bench_dense(args):
     import torch
@@ -165,6 +183,7 @@ def bench_dense(args):
         if args.cache:
             np.savez(args.cache, x=x, v=v, omega=om, info=json.dumps(prep))
     p = w["params"]
+    _DENSE.update(w=w, x=x, v=v, omega=om)
     s = dem.System(p, x, v, om, w["r"])
     dims = s.grid_dims()
     ncell = dims[0] * dims[1] * dims[2]
@@ -217,6 +236,67 @@ def bench_dense(args):
         "step_hbm": {"algorithmic_bytes_per_step": sb, "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9,
                      "frac": sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    return out
+
+
+# ------------------------------------------------------------ other configs
+
+PAPER_SIMPLE_RATIO = 21266.0 / 2960.0  # Table 3: simple vs practical model, OpenCL on its GPU
+PAPER_GPU_VS_CPU = 2960.0 / 474.0       # Table 3: practical model, its GPU vs one core of its CPU
+
+
+def time_system(w, steps, warmup):
+    """Particle-steps/s of one system stepped alone with graph replay."""
+    import torch
+
+    from paper_1301_1714_amd import dem
+
+    st = torch.cuda.Stream()
+    s = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"], stream=st)
+    try:
+        s.use_graph(True)
+        s.step(warmup)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        el = time.perf_counter() - t0
+        d = s.diagnostics()
+    finally:
+        s.close()
+    n = len(w["r"])
+    return {"value": n * steps / el, "unit": "particle-steps/s", "ms_per_step": 1e3 * el / steps, "n": n,
+            "steps": steps, "Z": 2.0 * float(d[7]) / max(n, 1)}
+
+
+def bench_configs(args):
+    from paper_1301_1714_amd import workloads as W
+
+    out = {"plain_fp64_4096": time_system(W.plain_fp64(seed=1000), 1000, 20)}
+    log(f"[bench] plain FP64 4096: {out['plain_fp64_4096']['value']:.4g} particle-steps/s")
+    # both laws from the same seeded gas, over the configuration's 10,000 steps
+    for law in ("linear", "simple"):
+        w = W.gas_mixed(seed=2000, law=law)
+        out[f"gas_2^20_{law}"] = time_system(w, args.gas_steps, 20)
+        log(f"[bench] gas 2^20 {law}: {out[f'gas_2^20_{law}']['value']:.4g} particle-steps/s")
+    lin, sim = out["gas_2^20_linear"], out["gas_2^20_simple"]
+    out["practical_vs_simple_time_ratio"] = lin["ms_per_step"] / sim["ms_per_step"]
+    out["paper_practical_vs_simple_time_ratio"] = PAPER_SIMPLE_RATIO
+    # the same comparison where contacts abound: the prepared 2^24 bed under
+    # both laws (simple-law coefficients for its median radius)
+    if _DENSE:
+        w = _DENSE["w"]
+        base = dict(w, x=_DENSE["x"], v=_DENSE["v"], omega=_DENSE["omega"])
+        r_med = float(np.median(w["r"]))
+        runs = {}
+        for law in ("linear", "simple"):
+            p = dict(w["params"], law=law)
+            if law == "simple":
+                p["simple_k"] = W.simple_coefficients(r_med)
+            runs[law] = time_system(dict(base, params=p), args.dense_law_steps, 10)
+            log(f"[bench] dense 2^24 {law} (graph replay): {runs[law]['ms_per_step']:.3f} ms/step")
+        out["dense_2^24_linear"], out["dense_2^24_simple"] = runs["linear"], runs["simple"]
+        out["dense_practical_vs_simple_time_ratio"] = runs["linear"]["ms_per_step"] / runs["simple"]["ms_per_step"]
     return out
 
 
@@ -350,6 +430,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the FP64 4,096 and the 2^20 gas runs")
+    ap.add_argument("--gas-steps", type=int, default=10000)
+    ap.add_argument("--dense-law-steps", type=int, default=100)
     ap.add_argument("--batch-systems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-seed", type=int, default=4000)
@@ -363,7 +446,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--serve-hbm-frac", type=float, default=0.8)
-    ap.add_argument("--only-dense", action="store_true", help="skip batched, serving and the CPU baseline")
+    ap.add_argument("--only-dense", action="store_true", help="skip the other configs, batched, serving and the CPU baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (profiler counter calibration)")
     args = ap.parse_args()
@@ -383,6 +466,8 @@ def main():
     dem.lib()
     out = bench_dense(args)
     log(f"[bench] dense bed: {out['value']:.4g} particle-steps/s, {out['ms_per_step']:.3f} ms/step")
+    if not (args.no_configs or args.only_dense):
+        out["configs"] = bench_configs(args)
     if not (args.no_batched or args.only_dense):
         out["batched"] = bench_batched(args)
         log(f"[bench] batched: {out['batched']['value']:.4g} particle-steps/s "
@@ -395,6 +480,10 @@ def main():
     if not (args.no_cpu_baseline or args.only_dense):
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        if "configs" in out:
+            g, c = out["configs"]["plain_fp64_4096"], out["cpu_baseline"]["plain_fp64_4096"]
+            g["vs_oracle_1core"] = g["value"] / c["value"]
+            g["paper_gpu_vs_cpu"] = PAPER_GPU_VS_CPU
     print(json.dumps(out), flush=True)
 
 
