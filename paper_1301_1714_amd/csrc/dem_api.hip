@@ -414,7 +414,6 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.old = e.gen[e.gc];
   a.w = e.work;
   a.cap = e.Pcap;
-  a.perm = e.perm;
   for (int k = 0; k < 3; k++) {
     a.F[k] = F[k];
     a.T[k] = T[k];

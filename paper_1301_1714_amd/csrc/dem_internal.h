@@ -19,7 +19,8 @@
 //            slots in ascending order followed by its walls (-1 - w)
 //   pst      the law's inputs per particle, packed (PState<Real>), with the
 //            previous slot and committed history segment of each slot
-//   tiles    detection work items: (system, row, first cell, last cell)
+//   tiles    detection work items: (system, row, first cell, last cell) of
+//            the LDS-tiled shape; runs: the same for the wave shape
 //   gen[2]   two generations of the compact contact array, CSR by owner slot
 //            (the lower slot of a pair; the particle for a wall): ofs[N + 1],
 //            per contact the owner s and partner t (slot or -1 - w), and one
@@ -46,7 +47,7 @@ enum ModeBits : int32_t {
   MODE_WRITE_HIST = 1,  // write the new tangential displacements
   MODE_KICK = 2,        // a time step: closing half kick (active systems only)
   MODE_DIAG = 4,        // per-particle elastic energy / contact counts / max overlap
-  MODE_OLD_PERM = 8     // committed history is in the pre-sort slot order (use perm)
+  MODE_OLD_PERM = 8     // committed history is in the pre-sort slot order (the records say where)
 };
 
 constexpr int32_t kBlock = 256;
@@ -179,7 +180,6 @@ struct PairArgs {
   PairGen cur, old;      // cur: contacts of the current positions; old: committed history
   PairWork w;
   int64_t cap;           // contacts a table holds
-  const int32_t *perm;   // with MODE_OLD_PERM: current slot -> slot of `old`
   void *F[3], *T[3];
   DiagBuf diag;
   int32_t *cell;         // cells for the next sort (drifted positions, or unchanged ones)
