@@ -508,15 +508,32 @@ __device__ __forceinline__ XR state_xr(const NbrBuf &nb, bool f64, int32_t t) {
   return o;
 }
 
+constexpr int kListStage = 8;  // list entries a lane keeps in LDS until its sweep ends
+
+// entry nf of slot s's list: one of the first kListStage goes to the lane's
+// LDS slots (stride kLanes) and is stored with the rest of the list at the
+// end of the sweep, so that a wave writes each list column in one store
+// rather than one scattered store per contact as it is found
+template <int kLanes>
+__device__ __forceinline__ void record(const NbrBuf &nb, int32_t N, int32_t s, int32_t *lst, int32_t t,
+                                       int32_t &nf) {
+  if (nf < kListStage)
+    lst[nf * kLanes] = t;
+  else if (nf < kListCap)
+    nb.nb[(int64_t)nf * N + s] = t;
+  nf++;
+}
+
 // exact FP64 decision on one prefilter survivor (the contact test of Step 7)
+template <int kLanes>
 __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int32_t N, int32_t s, float ri,
-                                                 double xi, double yi, double zi, int32_t t, int32_t &nf) {
+                                                 double xi, double yi, double zi, int32_t t, int32_t *lst,
+                                                 int32_t &nf) {
   const XR q = state_xr(nb, f64, t);
   const double ex = q.x - xi, ey = q.y - yi, ez = q.z - zi;
   const double S = (double)ri + (double)q.r;
   if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
-  if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = t;
-  nf++;
+  record<kLanes>(nb, N, s, lst, t, nf);
 }
 
 // One particle's sweep.  rows(r, ca, cb, beg, end, shift) gives the slot
@@ -528,7 +545,7 @@ __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int
 template <int kLanes, typename Rows>
 __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N, int32_t s,
                                                const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
-                                               int32_t *surv, int32_t *err) {
+                                               int32_t *surv, int32_t *lst, int32_t *err) {
   const float4 p = nb.xyzr[s];
   const XR me = state_xr(nb, f64, s);
   const double xi = me.x, yi = me.y, zi = me.z;
@@ -594,12 +611,14 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
         for (int u = 0; u < kUnroll; u++) q[u] = n[u];
       }
       if (ns > kSurv - kUnroll) {
-        for (int32_t j = 0; j < ns; j++) exact_and_record(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf);
+        for (int32_t j = 0; j < ns; j++)
+          exact_and_record<kLanes>(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
         ns = 0;
       }
     }
   }
-  for (int32_t j = 0; j < ns; j++) exact_and_record(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], nf);
+  for (int32_t j = 0; j < ns; j++)
+    exact_and_record<kLanes>(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
   // Step 8: walls, particles of infinite radius, after the pairs
   const uint32_t wall_mask = si.c.wall_mask;
   if (wall_mask) {
@@ -609,12 +628,10 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
       if (!((wall_mask >> w) & 1)) continue;
       const int ax = w >> 1;
       const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
-      if (gap < rid) {
-        if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = -1 - w;
-        nf++;
-      }
+      if (gap < rid) record<kLanes>(nb, N, s, lst, -1 - w, nf);
     }
   }
+  for (int32_t j = 0; j < nf && j < kListStage; j++) nb.nb[(int64_t)j * N + s] = lst[j * kLanes];
   if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
   nb.fcnt[s] = nf < kListCap ? nf : kListCap;
 }
@@ -639,6 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
                                                           NbrBuf nb, const int32_t *__restrict__ scell,
                                                           const int32_t *__restrict__ cell_start, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
+  __shared__ int32_t lst_all[kListStage * kBlock];
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
@@ -649,7 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
   const int32_t cc = scell[s] - si.g.c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
-  sweep_particle<kBlock>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, err);
+  sweep_particle<kBlock>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, lst_all + threadIdx.x,
+                         err);
 }
 
 // --------------------------------------------------------------------------
@@ -927,6 +946,7 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
   __shared__ float4 halo[kHaloCap];
   __shared__ int32_t cs[9][kMaxTile + 3];  // cell starts of cells xa .. xb + 1 of each row
   __shared__ int32_t surv_all[kSurv * kTileThreads];
+  __shared__ int32_t lst_all[kListStage * kTileThreads];
   const int tid = threadIdx.x;
   const int4 tile = L.tiles[blockIdx.x];
   const int32_t k = tile.x;
@@ -967,17 +987,17 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
     }
   }
   __syncthreads();
-  int32_t *surv = surv_all + tid;
+  int32_t *surv = surv_all + tid, *lst = lst_all + tid;
   if (staged) {
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(st, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+      sweep_particle<kTileThreads>(st, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
   } else {
     TileRows<false> gr;
     gr.src = nb.xyzr;
     gr.cs = cs;
     gr.xa = xa;
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(gr, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, err);
+      sweep_particle<kTileThreads>(gr, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
   }
 }
 
