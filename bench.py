@@ -317,8 +317,10 @@ def bench_batched(args):
     t_tune = time.time() - t0
     factors = autotune.factors_for(draws, table)
     tiles = autotune.tiles_for(draws, table)
+    divisors = autotune.divisors_for(draws, table)
     t0 = time.time()
-    systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors, tiles=tiles)
+    systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors, tiles=tiles,
+                                divisors=divisors)
     ns = np.array([len(s["r"]) for s in systems])
     log(f"[bench] batched: {len(systems)} systems, {ns.sum()} spheres, generated in {time.time() - t0:.1f}s, "
         f"tuned in {t_tune:.1f}s")
@@ -361,6 +363,7 @@ def bench_batched(args):
         "speedup_vs_plain": batched_rate / plain_rate,
         "cell_factors": {str(f): int(c) for f, c in zip(fac, cnt)},
         "detect_tiles": {str(t): int(c) for t, c in zip(til, tcnt)},
+        "cell_divisors": {str(int(d)): int(c) for d, c in zip(*np.unique(divisors, return_counts=True))},
         "Z_mean": float(2.0 * diag[:, 7].sum() / ns.sum()),
         "tune_seconds": t_tune,
     }

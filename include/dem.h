@@ -91,6 +91,13 @@ typedef struct {
                                     workgroups over runs of this many cells along x,
                                     neighbours staged in LDS.  Changes only speed, never
                                     the contacts found */
+    int32_t cell_divisor;        /* k in 1..2: the grid's cells are cell_size / k wide and a
+                                    particle sweeps the (2k + 1)^3 cells around its own
+                                    (k = 1: the 27 cells of Eq. 12).  Finer cells cover the
+                                    same contact distance with fewer candidates.  The
+                                    contacts found never change; the sorted order, and so
+                                    the rounding of the sums, does.  k > 1 needs
+                                    tile_cells = 0 */
 } dem_params;
 
 typedef struct dem_system dem_system; /* opaque host-side handle */

@@ -70,7 +70,8 @@ struct Engine {
   bool use_graph = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gexec_cp[2] = {-1, -1};  // the position buffer each graph was captured with
-  int32_t ndirect = 0;         // systems swept by the direct detection kernel
+  int32_t ndirect = 0;         // systems swept by the direct detection kernel (reach 1)
+  int32_t ndirect2 = 0;        // the same with reach 2
 
   Layout layout() const {
     Layout L;
@@ -84,6 +85,7 @@ struct Engine {
     L.ntiles = (int32_t)tiles_h.size();
     L.nruns = (int32_t)runs_h.size();
     L.ndirect = ndirect;
+    L.ndirect2 = ndirect2;
     L.n = n;
     L.S = S;
     return L;
@@ -113,11 +115,14 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   if (p->wall_mask > 0x3F) return DEM_E_INVALID;
   if (!isfinite(p->kn) || !isfinite(p->kt) || !isfinite(p->eta_t_ratio)) return DEM_E_INVALID;
   if (p->tile_cells < -1 || p->tile_cells > kMaxTile) return DEM_E_INVALID;
+  if (p->cell_divisor < 1 || p->cell_divisor > kMaxReach) return DEM_E_INVALID;
+  if (p->cell_divisor > 1 && p->tile_cells != 0) return DEM_E_INVALID;  // the other shapes sweep 27 cells
+  const double width = p->cell_size / p->cell_divisor;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
     const double L = p->box_hi[a] - p->box_lo[a];
     if (!(L > 0.0) || !isfinite(L)) return DEM_E_INVALID;
-    const double nf = floor(L / p->cell_size);
+    const double nf = floor(L / width);
     if (nf < 1.0 || nf > 1.0e6) return DEM_E_INVALID;
     g->nc[a] = (int32_t)nf;
     g->sc[a] = (double)g->nc[a] / L;
@@ -180,6 +185,7 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   e.tiles_h.clear();
   e.runs_h.clear();
   e.ndirect = 0;
+  e.ndirect2 = 0;
   for (int32_t k = 0; k < S; k++) {
     SysInfo &si = e.info[k];
     memset(&si, 0, sizeof(si));
@@ -188,6 +194,7 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     if (p[k].precision != e.prec || p[k].law != e.law) return DEM_E_INVALID;
     fill_consts(p[k], si.c);
     si.eps = prefilter_eps(si.g, p[k].cell_size);
+    si.reach = p[k].cell_divisor;
     si.p0 = (int32_t)ntot;
     si.n = (int32_t)n[k];
     si.g.c0 = (int32_t)ctot;
@@ -200,7 +207,7 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     const int32_t T = p[k].tile_cells;
     const int32_t nx = si.g.nc[0], rows = si.g.nc[1] * si.g.nc[2];
     si.tile = T;
-    if (n[k] > 0 && T == 0) e.ndirect++;
+    if (n[k] > 0 && T == 0) (si.reach == 1 ? e.ndirect : e.ndirect2)++;
     if (n[k] > 0 && T < 0) {
       if ((int64_t)e.runs_h.size() + (int64_t)rows * ((nx + kRunCells - 1) / kRunCells) >= (int64_t)INT32_MAX)
         return DEM_E_INVALID;

@@ -57,6 +57,7 @@ constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 constexpr int32_t kRunCells = 8;  // cells along x per wave of the wave-per-cell-run detection
+constexpr int32_t kMaxReach = 2;  // largest cell divisor
 
 struct Grid {
   double lo[3], hi[3];
@@ -83,8 +84,8 @@ struct SysInfo {
   int32_t p0, n;  // slot range
   float eps;      // detection prefilter margin
   float rmax;     // largest radius (FP32), bounds the contact distance
-  int32_t tile;   // detection: cells per tile (0: direct sweep)
-  int32_t pad;
+  int32_t tile;   // detection: cells per tile (0: direct sweep, -1: wave per cell run)
+  int32_t reach;  // cells swept on each side of a particle's own (the cell divisor)
 };
 
 // Step control on the device, so that one captured step can be replayed:
@@ -165,7 +166,8 @@ struct Layout {
   int32_t nblocks;
   int32_t ntiles;
   int32_t nruns;
-  int32_t ndirect;  // systems swept by the direct detection kernel
+  int32_t ndirect;  // systems swept by the direct detection kernel with reach 1
+  int32_t ndirect2; // and with reach 2
   int32_t n;
   int32_t S;
 };

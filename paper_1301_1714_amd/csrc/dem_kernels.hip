@@ -536,13 +536,16 @@ __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int
   record<kLanes>(nb, N, s, lst, t, nf);
 }
 
-// One particle's sweep.  rows(r, ca, cb, beg, end, shift) gives the slot
-// range [beg, end) of cells ca..cb of row r (r = 3 (dz + 1) + dy + 1) and
-// where their FP32 copies are (slot t at rows.src[t - shift]); false for a
-// row outside the grid.  Survivors wait in the lane's LDS slots (stride
-// kLanes) so that the rare exact test does not sit inside the candidate
-// loop, where one lane taking it would hold the whole wave.
-template <int kLanes, typename Rows>
+// One particle's sweep over the forward half of the (2K + 1)^3 cells around
+// its own (K = 1: the 27 cells of Eq. 12).  rows(dy, dz, ca, cb, beg, end,
+// shift) gives the slot range [beg, end) of cells ca..cb of the row at
+// offset (dy, dz) and where their FP32 copies are (slot t at rows.src[t -
+// shift]); false for a row outside the grid.  The rows are visited in
+// ascending slot order: the own row, rows dy = 1..K of the own plane, then
+// rows dy = -K..K of planes dz = 1..K.  Survivors wait in the lane's LDS
+// slots (stride kLanes) so that the rare exact test does not sit inside the
+// candidate loop, where one lane taking it would hold the whole wave.
+template <int kLanes, int K, typename Rows>
 __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N, int32_t s,
                                                const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
                                                int32_t *surv, int32_t *lst, int32_t *err) {
@@ -558,27 +561,36 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
   const float dyl = fmaxf(p.y - (float)cy * wy, 0.0f), dyh = fmaxf((float)(cy + 1) * wy - p.y, 0.0f);
   const float dzh = fmaxf((float)(cz + 1) * wz - p.z, 0.0f);
   const float dxl = fmaxf(p.x - (float)cx * wx, 0.0f);
-  // the slot ranges of the 5 forward rows first, so that their loads overlap
-  int32_t beg[5], end[5], shift[5];
+  // the slot ranges of the forward rows first, so that their loads overlap;
+  // a row, or a cell at either end of a row, whose box lies beyond cut is
+  // skipped (the distance to the row or cell i steps away is the distance to
+  // the own cell's face plus i - 1 cell widths)
+  constexpr int R = 1 + 2 * K + 2 * K * K;
+  int32_t beg[R], end[R], shift[R];
   const float4 *src = rows.src;
 #pragma unroll
-  for (int h = 0; h < 5; h++) {
-    const int r = 4 + h;
-    const int dyr = (r % 3) - 1, dzr = (r / 3) - 1;
-    const float dy = dyr < 0 ? dyl : (dyr > 0 ? dyh : 0.0f);
-    const float dz = dzr > 0 ? dzh : 0.0f;
+  for (int h = 0; h < R; h++) {
+    const int dyr = h <= K ? h : (h - K - 1) % (2 * K + 1) - K;
+    const int dzr = h <= K ? 0 : 1 + (h - K - 1) / (2 * K + 1);
+    const float dy = dyr < 0 ? dyl + (float)(-dyr - 1) * wy : (dyr > 0 ? dyh + (float)(dyr - 1) * wy : 0.0f);
+    const float dz = dzr > 0 ? dzh + (float)(dzr - 1) * wz : 0.0f;
     const float dyz2 = dy * dy + dz * dz;
     beg[h] = end[h] = shift[h] = 0;
     if (!(dyz2 < cut2)) continue;
-    const int32_t ca = (h > 0 && cx > 0 && dxl * dxl + dyz2 < cut2) ? cx - 1 : cx;
-    const int32_t cb = (cx < nx - 1 && dxh * dxh + dyz2 < cut2) ? cx + 1 : cx;
-    if (!rows(r, ca, cb, beg[h], end[h], shift[h])) beg[h] = end[h] = 0;
+    int32_t ca = cx, cb = cx;
+#pragma unroll
+    for (int i = 1; i <= K; i++) {
+      const float dl = dxl + (float)(i - 1) * wx, dh = dxh + (float)(i - 1) * wx;
+      ca = (h > 0 && cx - i >= 0 && dl * dl + dyz2 < cut2) ? cx - i : ca;
+      cb = (cx + i < nx && dh * dh + dyz2 < cut2) ? cx + i : cb;
+    }
+    if (!rows(dyr, dzr, ca, cb, beg[h], end[h], shift[h])) beg[h] = end[h] = 0;
   }
   beg[0] = s + 1;  // own row: the slots after the particle
   const float pe = p.w + eps;
   int32_t nf = 0, ns = 0;
 #pragma unroll
-  for (int h = 0; h < 5; h++) {
+  for (int h = 0; h < R; h++) {
     const int32_t e = end[h], sh = shift[h];
     int32_t t = beg[h];
     while (t < e) {
@@ -640,9 +652,9 @@ struct DirectRows {
   const float4 *src;
   const int32_t *cell_start;
   int32_t c0, nx, ny, nz, cy, cz;
-  __device__ __forceinline__ bool operator()(int r, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
+  __device__ __forceinline__ bool operator()(int dy, int dz, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
                                              int32_t &shift) const {
-    const int32_t yy = cy + (r % 3) - 1, zz = cz + (r / 3) - 1;
+    const int32_t yy = cy + dy, zz = cz + dz;
     if (yy < 0 || yy >= ny || zz < 0 || zz >= nz) return false;
     const int32_t row = c0 + (zz * ny + yy) * nx;
     beg = cell_start[row + ca];
@@ -652,6 +664,7 @@ struct DirectRows {
   }
 };
 
+template <int K>
 __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl, int32_t only_active, bool f64,
                                                           NbrBuf nb, const int32_t *__restrict__ scell,
                                                           const int32_t *__restrict__ cell_start, int32_t *err) {
@@ -661,14 +674,14 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
   const SysInfo &si = L.tab[k];
-  if (si.tile != 0) return;                       // another launch shape sweeps this system
+  if (si.tile != 0 || si.reach != K) return;      // another launch sweeps this system
   if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
   const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
   const int32_t cc = scell[s] - si.g.c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
   const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
-  sweep_particle<kBlock>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, lst_all + threadIdx.x,
-                         err);
+  sweep_particle<kBlock, K>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, lst_all + threadIdx.x,
+                            err);
 }
 
 // --------------------------------------------------------------------------
@@ -929,8 +942,9 @@ struct TileRows {
   const int32_t (*cs)[kMaxTile + 3];
   int32_t xa;
   int32_t shift[9];
-  __device__ __forceinline__ bool operator()(int r, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
+  __device__ __forceinline__ bool operator()(int dy, int dz, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
                                              int32_t &sh) const {
+    const int r = 3 * (dz + 1) + dy + 1;
     beg = cs[r][ca - xa];  // rows outside the grid hold empty ranges
     end = cs[r][cb - xa + 1];
     sh = kStaged ? shift[r] : 0;
@@ -990,14 +1004,14 @@ __global__ __launch_bounds__(kTileThreads) void k_detect_tiles(Layout L, StepCtl
   int32_t *surv = surv_all + tid, *lst = lst_all + tid;
   if (staged) {
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(st, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
+      sweep_particle<kTileThreads, 1>(st, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
   } else {
     TileRows<false> gr;
     gr.src = nb.xyzr;
     gr.cs = cs;
     gr.xa = xa;
     for (int32_t s = own_lo + tid; s < own_hi; s += kTileThreads)
-      sweep_particle<kTileThreads>(gr, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
+      sweep_particle<kTileThreads, 1>(gr, nb, f64, L.n, s, si, (scell[s] - c0) % nx, ry, rz, surv, lst, err);
   }
 }
 
@@ -1164,8 +1178,11 @@ hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, con
   StepCtl none{nullptr, nullptr};
   const bool f64 = precision == DEM_PREC_FP64;
   if (L.ndirect > 0)
-    k_detect_direct<<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
-                                                   err);
+    k_detect_direct<1><<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
+                                                      err);
+  if (L.ndirect2 > 0)
+    k_detect_direct<2><<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
+                                                      err);
   if (L.nruns > 0)
     k_detect_cells<<<(L.nruns + kCellWaves - 1) / kCellWaves, kCellWaves * 64, 0, st>>>(
         L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start, err);

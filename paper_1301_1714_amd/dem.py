@@ -50,7 +50,7 @@ class DemParams(C.Structure):
         ("simple_k", C.c_double * 3),
         ("cell_size", C.c_double),
         ("contacts_per_particle", C.c_int32), ("precision", C.c_int32),
-        ("tile_cells", C.c_int32),
+        ("tile_cells", C.c_int32), ("cell_divisor", C.c_int32),
     ]
 
 
@@ -120,6 +120,7 @@ def make_params(p: dict) -> DemParams:
     o.contacts_per_particle = int(p.get("contacts_per_particle", 16))
     o.precision = PRECISIONS[p.get("precision", "fp64")]
     o.tile_cells = int(p.get("tile_cells", 0))
+    o.cell_divisor = int(p.get("cell_divisor", 1))
     return o
 
 

@@ -25,6 +25,8 @@ Parameter dictionary keys (each side marshals them into its own structure):
   tile_cells         detection launch shape: 0 one lane per particle, -1 one wave
                      per run of cells, 1..32 cells per LDS-staged workgroup
                      (GPU only; speed only)
+  cell_divisor       k: grid cells of cell_size / k swept over (2k + 1)^3 cells
+                     (GPU only; 1 or 2; speed and summation order only)
   precision          "fp64" or "mixed" (FP32 forces, FP64 positions; GPU only)
 """
 import math
@@ -296,7 +298,7 @@ def system_draw(rng, n_lo, n_hi):
 
 
 def unit_box_system(seed, n, kn, restitution, mu, phi, precision="mixed", law="linear", cell_factor=1.0,
-                    contacts_per_particle=8, tile_cells=0):
+                    contacts_per_particle=8, tile_cells=0, cell_divisor=1):
     """One system of the batched and serving workloads: n spheres with radii
     U[0.8, 1.2] r_s in a walled unit box, r_s set so that the spheres fill the
     packing fraction phi, on a jittered FCC lattice, v ~ N(0, 0.1^2) per axis,
@@ -317,7 +319,8 @@ def unit_box_system(seed, n, kn, restitution, mu, phi, precision="mixed", law="l
     dmax = 2.0 * (float(r.max()) if n else r_s)
     p = base_params(kn=kn, kt=2.0 / 7.0 * kn, restitution=restitution, mu=mu, law=law, precision=precision,
                     dt=stable_dt(kn, restitution, r_min), cell_size=min(1.0, cell_factor * dmax),
-                    contacts_per_particle=contacts_per_particle, tile_cells=tile_cells)
+                    contacts_per_particle=contacts_per_particle, tile_cells=tile_cells,
+                    cell_divisor=cell_divisor)
     phi_start = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
     return dict(name=f"system_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r, phi=phi, phi_start=phi_start)
 
@@ -329,17 +332,19 @@ def batched_draws(seed=4000, count=256, n_lo=1024, n_hi=262144):
 
 
 def batched_systems(seed=4000, count=256, n_lo=1024, n_hi=262144, precision="mixed", law="linear",
-                    cell_factors=None, tiles=None):
+                    cell_factors=None, tiles=None, divisors=None):
     """The batched workload: `count` independent systems, each drawn by
     ``system_draw`` and built by ``unit_box_system`` with seed seed + 1 + k.
-    cell_factors and tiles (one per system) come from the autotuner;
-    default 1 and 0."""
+    cell_factors, tiles and divisors (one per system) come from the
+    autotuner; default 1, 0 and 1."""
     out = []
     for k, d in enumerate(batched_draws(seed, count, n_lo, n_hi)):
         cf = 1.0 if cell_factors is None else float(cell_factors[k])
         tc = 0 if tiles is None else int(tiles[k])
+        cd = 1 if divisors is None else int(divisors[k])
         out.append(unit_box_system(seed + 1 + k, d["n"], d["kn"], d["restitution"], d["mu"], d["phi"],
-                                   precision=precision, law=law, cell_factor=cf, tile_cells=tc))
+                                   precision=precision, law=law, cell_factor=cf, tile_cells=tc,
+                                   cell_divisor=cd))
     return out
 
 

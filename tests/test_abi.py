@@ -73,6 +73,11 @@ def test_workspace_bytes_and_validation_on_host(L):
     for tile in (-2, 33):
         with pytest.raises(dem.DemError):
             dem.dem_workspace_bytes(dict(p, tile_cells=tile), 4096)
+    # the cell divisor: 1 or 2, finer cells (more of them) only with the direct sweep
+    assert dem.dem_workspace_bytes(dict(p, cell_divisor=2), 4096) > dem.dem_workspace_bytes(p, 4096)
+    for bad in (dict(p, cell_divisor=0), dict(p, cell_divisor=3), dict(p, cell_divisor=2, tile_cells=8)):
+        with pytest.raises(dem.DemError):
+            dem.dem_workspace_bytes(bad, 4096)
     assert L.dem_status_string(-3) == b"contact list overflow"
 
 

@@ -12,10 +12,12 @@ def test_class_keys_and_representatives():
 
 
 def test_table_lookup_and_roundtrip(tmp_path):
-    t = autotune.Table({"n10_phi0": {"factor": 1.5, "tile": 8}})
+    t = autotune.Table({"n10_phi0": {"factor": 1.5, "tile": 8}, "n12_phi2": {"factor": 1.0, "tile": 0, "divisor": 2}})
     assert t.factor(1000, 0.21) == 1.5 and t.tile(1000, 0.21) == 8
+    assert t.divisor(1000, 0.21) == 1  # an entry without a divisor: the paper's 27 cells
+    assert t.divisor(4000, 0.5) == 2
     assert t.factor(5000, 0.21) == 1.0  # unknown class: the minimum cell, direct detection
-    assert t.tile(5000, 0.21) == 0
+    assert t.tile(5000, 0.21) == 0 and t.divisor(5000, 0.21) == 1
     p = str(tmp_path / "a.json")
     t.save(p)
     assert autotune.Table.load(p).entries == t.entries

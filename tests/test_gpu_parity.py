@@ -293,6 +293,31 @@ def test_tiled_detection_is_bit_identical(dem, name, tile, cell_scale):
     assert np.array_equal(b.contacts(), o.contacts())
 
 
+@pytest.mark.parametrize("name", ["fp64_linear_3001", "mixed_nowalls_poly_4097", "fp64_partial_walls_5000",
+                                  "mixed_hertz_2500"])
+def test_cell_divisor_two_finds_the_same_contacts(dem, name):
+    # cells of half the width swept over 5^3 cells cover the same contact
+    # distance as the 27-cell sweep: the same contacts, forces within the
+    # tolerance (the slot order, and so the summation order, differs), and
+    # trajectories that track the oracle's
+    c = cloud(**CASES[name])
+    p = dict(c["params"], mu=0.2, eta_t_ratio=0.5, dt=2e-6)
+    g = dem.System(dict(p, cell_divisor=2), c["x"], c["v"], c["omega"], c["r"])
+    o = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    assert all(a >= 2 * b for a, b in zip(g.grid_dims(), o.grid_dims()))
+    assert np.array_equal(g.contacts(), o.contacts())
+    tol = TOL[p["precision"]]
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, tol)
+    g.step(6)
+    o.step(6)
+    assert np.array_equal(g.contacts(), o.contacts())
+    sg, so = g.read_state(), o.read_state()
+    scale = np.abs(so["x"]).max()
+    assert np.abs(sg["x"] - so["x"]).max() <= (1e-12 if tol < 1e-9 else 1e-6) * scale
+
+
 def test_profile_phases_cover_the_step(dem):
     import torch
     c = cloud(seed=9, n=3000, precision="mixed")

@@ -75,15 +75,18 @@ def test_autotuned_batch_is_deterministic(ex, tmp_path):
     from paper_1301_1714_amd import dem
     draws = W.batched_draws(seed=41, count=6, n_lo=500, n_hi=3000)
     keys = [autotune.system_class(d["n"], d["phi"]) for d in draws]
-    table = autotune.tune(keys, steps=5, factors=(1.0, 1.5), tiles=(0, 4))
+    table = autotune.tune(keys, steps=5, factors=(1.0, 1.5), tiles=(0, 4), divisors=(1, 2))
     path = str(tmp_path / "t.json")
     table.save(path)
     t2 = autotune.Table.load(path)
     f1 = autotune.factors_for(draws, table)
     tl = autotune.tiles_for(draws, table)
+    dv = autotune.divisors_for(draws, table)
     assert f1 == autotune.factors_for(draws, t2) and tl == autotune.tiles_for(draws, t2)
+    assert dv == autotune.divisors_for(draws, t2)
     assert all(f in (1.0, 1.5) for f in f1) and all(t in (0, 4) for t in tl)
-    systems = W.batched_systems(seed=41, count=6, n_lo=500, n_hi=3000, cell_factors=f1, tiles=tl)
+    assert all(d == 1 or t == 0 for d, t in zip(dv, tl))
+    systems = W.batched_systems(seed=41, count=6, n_lo=500, n_hi=3000, cell_factors=f1, tiles=tl, divisors=dv)
     b = dem.Batch(systems)
     b.use_graph(True)
     b.step([9, 3, 0, 7, 9, 1])
