@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s (practical model) at 16M"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FILL_HEIGHT = 0.93     # the prepared bed fills the lower 93% of the box
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_dense_bed_16M.json")
 
 
 def log(msg):
@@ -65,7 +66,7 @@ def measured_traffic(kernel):
     summary (FETCH_SIZE and WRITE_SIZE scaled by what the same counters read
     for a plain copy of known size), or None when there is none for the
     current kernel source."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_dense_bed_16M.json")
+    path = TRAFFIC_JSON
     if not os.path.exists(path):
         return None
     with open(path) as f:

@@ -1,0 +1,45 @@
+"""Host-side pieces of bench.py (no GPU): the multi-GPU refusal, the byte
+models behind the roofline, and the traffic figures' source check."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_byte_models():
+    # detection: per sphere 16 + 24 + 4 + 4 bytes plus 4 per owned entry, cell starts once
+    assert bench.detect_bytes(10, 7, 2.0) == 10 * (48 + 8) + 4 * 8
+    # law: per contact slots, history read and written, force record; per sphere its record
+    assert bench.pair_force_bytes(10, 20, 4) == 20 * (16 + 48) + 10 * (36 + 24)
+    assert bench.pair_force_bytes(10, 20, 8) == 20 * (16 + 96) + 10 * (36 + 48)
+    # whole step: B = 2 state + 16 + 3 + Z (4 + 3R); 131 + 16 Z bytes in mixed precision
+    assert bench.step_algorithmic_bytes(1, 0.0, 4) == 131
+    assert bench.step_algorithmic_bytes(1, 6.0, 4) == pytest.approx(131 + 16 * 6)
+
+
+def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch):
+    rec = {"kernel_source_sha256": bench.kernel_source_hash(),
+           "kernels": {"k_detect": {"bytes_per_launch": 1.5e9}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(p))
+    assert bench.measured_traffic("k_detect") == 1.5e9
+    assert bench.measured_traffic("k_gather") is None  # not measured
+    p.write_text(json.dumps(dict(rec, kernel_source_sha256="0" * 64)))  # counters of other kernels
+    assert bench.measured_traffic("k_detect") is None
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "missing.json"))
+    assert bench.measured_traffic("k_detect") is None
