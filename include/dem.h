@@ -195,7 +195,7 @@ dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *s
 /* Capture one time step (Steps 2-8 and the closing kick) into two HIP
  * graphs, one per buffer parity, and replay them in dem_step from then on.
  * The stream given to dem_create must not be the NULL stream (graph capture
- * needs a created stream).  Phase timing then covers whole steps (phase 4).
+ * needs a created stream).  Phase timing then counts whole steps in phase 6.
  * Results are identical with and without graphs.  enable = 0 goes back to
  * plain launches. */
 dem_status dem_use_graph(dem_system *s, int enable);
@@ -236,12 +236,18 @@ dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n
  * (state and history) while the others go on.  Asynchronous. */
 dem_status dem_batch_step(dem_batch *b, const int64_t *steps);
 
+/* State of system k (0 <= k < n_sys) as dem_read_state: its n[k] particles
+ * in its own original order.  Synchronous.  Errors: DEM_E_INVALID for k out
+ * of range, else the sticky error. */
 dem_status dem_batch_read_state(dem_batch *b, int32_t k, double *x, double *v, double *omega, double *F,
                                 double *T);
+/* Committed history of system k as dem_read_contacts (keys local to it). */
 dem_status dem_batch_read_contacts(dem_batch *b, int32_t k, int64_t cap, int64_t *n_out, int64_t *pairs,
                                    double *delta_t);
 /* Diagnostics of every system: out[10 * k + j] as dem_diagnostics. */
 dem_status dem_batch_diagnostics(dem_batch *b, double *out);
+/* As dem_use_graph, dem_profile, dem_profile_read, dem_sync and dem_destroy,
+ * for the whole batch (phases summed over all its systems). */
 dem_status dem_batch_use_graph(dem_batch *b, int enable);
 dem_status dem_batch_profile(dem_batch *b, int enable);
 dem_status dem_batch_profile_read(dem_batch *b, double ms[DEM_NUM_PHASES], int64_t *steps);
