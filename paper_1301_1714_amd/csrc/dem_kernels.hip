@@ -1089,18 +1089,30 @@ __device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Rea
 // of the counts); each pair is also filed in its partner's backward list,
 // at the position its atomic count drew (arrival order; the gather sorts
 // each short list).  With write_keys the history keys go into the entries.
+// One lane per contact: a block takes the contacts of its kBlock owners, a
+// lane finds its owner by bisecting their offsets in LDS, so that every
+// lane of a wave writes (and files) a real contact, at consecutive indices.
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int64_t cap, int32_t n,
                                                   int32_t write_keys, int32_t *err) {
-  const int32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= n) return;
-  const int32_t cnt = nb.fcnt[s];
-  const int64_t base = gen.ofs[s];
-  if (base + cnt > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
+  __shared__ int32_t so[kBlock + 1];
+  const int32_t s0 = blockIdx.x * kBlock, m = min(kBlock, n - s0);
+  for (int32_t i = threadIdx.x; i <= m; i += kBlock) so[i] = gen.ofs[s0 + i];
+  __syncthreads();
+  const int32_t q0 = so[0], q1 = so[m];
+  if (threadIdx.x == 0 && q1 > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
+  const int32_t qe = (int64_t)q1 < cap ? q1 : (int32_t)cap;
   const Real zero[3] = {0, 0, 0};
-  for (int32_t j = 0; j < cnt; j++) {
-    const int64_t q = base + j;
-    if (q >= cap) break;
+  for (int32_t q = q0 + (int32_t)threadIdx.x; q < qe; q += kBlock) {
+    int32_t lo = 0, hi = m;  // so[lo] <= q < so[hi]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (so[mid] <= q)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int32_t s = s0 + lo, j = q - so[lo];
     const int32_t t = nb.nb[(int64_t)j * n + s];
     gen.s[q] = s;
     gen.t[q] = t;
@@ -1108,7 +1120,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWo
     if (t >= 0) {
       const int32_t k = atomicAdd(&w.bcnt[t], 1);
       if (k < kBwdCap)
-        w.bwd[(int64_t)k * n + t] = (int32_t)q;
+        w.bwd[(int64_t)k * n + t] = q;
       else
         raise_err(err, ERR_OVERFLOW);
     }
