@@ -1480,16 +1480,49 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
 // step the closing half kick and, when the system steps again in this call,
 // the next step's opening kick, drift and hash.  The state goes to the other
 // buffers.
+// exclusive prefix sum of c over the block (and its total); every thread
+// of the block must call it
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum, int32_t &total) {
+  const int32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t x = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; w++) {
+    const int32_t v = wsum[w];
+    base += w < wv ? v : 0;
+    tot += v;
+  }
+  total = tot;
+  return base + x - c;
+}
+
+// backward records a gather workgroup stages in LDS (more: it reads them
+// from global memory lane by lane)
+constexpr int32_t kGatherStage = 512;
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
+  using V2 = typename Vec2T<Real>::type;
+  __shared__ int32_t bo[kBlock + 1];       // the block's backward segments
+  __shared__ int32_t bq[kGatherStage];     // their contact indices, in arrival order
+  __shared__ V2 brec[3 * kGatherStage];    // and their records
+  __shared__ int32_t wsum[kBlock / 64];
   int32_t k;
-  const int32_t s = block_slot(a.L, k);
-  if (s < 0) return;
+  const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + m), one system
   const SysInfo &si = a.L.tab[k];
   const Consts &c = si.c;
   const bool stepping = (a.mode & MODE_KICK) != 0;
-  const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
+  const int32_t N = a.L.n;
   if (stepping && !is_active(a.ctl, k)) {
+    if (s < 0) return;
+    const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
     // a finished system: state unchanged; the next sort sees its current cells
 #pragma unroll
     for (int q = 0; q < 3; q++) {
@@ -1504,6 +1537,40 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     a.cell[s] = a.scell[s];
     return;
   }
+  // The backward records -- random reads -- are fetched first with every
+  // lane on one (lane e takes entry e of the block's segments, its particle
+  // found by bisection), into LDS; each particle then sums its own from
+  // there.  A block with more than kGatherStage of them reads them lane by
+  // lane from global memory instead.
+  const int32_t s0 = a.L.bfirst[blockIdx.x];
+  const int32_t nbk = s >= 0 ? min(a.w.bcnt[s], kBwdCap) : 0;
+  int32_t B;
+  const int32_t off = block_exclusive_scan(nbk, wsum, B);
+  bo[threadIdx.x] = off;
+  if (threadIdx.x == kBlock - 1) bo[kBlock] = B;
+  __syncthreads();
+  const bool staged = B <= kGatherStage;
+  if (staged) {
+    for (int32_t e = threadIdx.x; e < B; e += kBlock) {
+      int32_t lo = 0, hi = kBlock;  // bo[lo] <= e < bo[hi]
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (bo[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const int32_t q = a.w.bwd[(int64_t)(e - bo[lo]) * N + s0 + lo];
+      bq[e] = q;
+      const V2 *p = (const V2 *)a.w.pf + 3 * (int64_t)q;
+      brec[3 * e] = p[0];
+      brec[3 * e + 1] = p[1];
+      brec[3 * e + 2] = p[2];
+    }
+  }
+  __syncthreads();
+  if (s < 0) return;
+  const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
   const int64_t cap = a.cap;
   const Real rs = (Real)me.r;
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
@@ -1518,14 +1585,36 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     T[1] += rs * m[1];
     T[2] += rs * m[2];
   };
-  const int32_t nbk = min(a.w.bcnt[s], kBwdCap);
-  const int32_t N = a.L.n;
-  if (nbk <= 4)
+  if (staged) {
+    // ascending by contact index: each next entry is the smallest above the
+    // previous one (the indices are distinct)
+    const int32_t b0 = bo[threadIdx.x];
+    int32_t prev = -1;
+    for (int32_t i = 0; i < nbk; i++) {
+      int32_t cur = INT32_MAX, at = b0;
+      for (int32_t j = b0; j < b0 + nbk; j++) {
+        const int32_t q = bq[j];
+        if (q > prev && q < cur) {
+          cur = q;
+          at = j;
+        }
+      }
+      prev = cur;
+      const V2 r0 = brec[3 * at], r1 = brec[3 * at + 1], r2 = brec[3 * at + 2];
+      F[0] -= r0.x;
+      F[1] -= r0.y;
+      F[2] -= r1.x;
+      T[0] += rs * r1.y;  // Eq. 3; the same n x F_t on both bodies
+      T[1] += rs * r2.x;
+      T[2] += rs * r2.y;
+    }
+  } else if (nbk <= 4) {
     for_sorted<4>(a.w.bwd, N, s, nbk, back);
-  else if (nbk <= 8)
+  } else if (nbk <= 8) {
     for_sorted<8>(a.w.bwd, N, s, nbk, back);
-  else
+  } else {
     for_selected(a.w.bwd, N, s, nbk, back);  // a register network this long would cost every wave occupancy
+  }
   const int64_t f0 = a.cur.ofs[s];
   const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
   double e_el = 0.0, dmax = 0.0;
