@@ -99,11 +99,11 @@ def copy_probe(mib, reps):
 # size of a Real (4 with FP32 forces, 8 in FP64).
 
 def detect_bytes(n, ncell, c_own):
-    """k_detect: per particle its FP32 copy (x, y, z, r: 16 B), its FP64
-    position (24 B) and cell (4 B) read, its count (4 B) and c_own list
+    """k_detect: per particle its 8-byte fixed-point candidate record, its
+    FP64 position (24 B) and cell (4 B) read, its count (4 B) and c_own list
     entries (4 B each: partners with higher slots, walls) written; the cell
     starts read once."""
-    return n * (48 + 4 * c_own) + 4 * (ncell + 1)
+    return n * (40 + 4 * c_own) + 4 * (ncell + 1)
 
 
 def pair_force_bytes(n, P, R):

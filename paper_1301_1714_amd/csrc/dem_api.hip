@@ -279,6 +279,7 @@ size_t carve(Engine &e, char *base) {
     e.scan.level[l] = l < nl ? cv.take<int32_t>((size_t)lens[l] + 1) : nullptr;
   }
   e.nbr.xyzr = cv.take<float4>(N);
+  e.nbr.xq = cv.take<uint2>(N + 1);  // one pad record: detection loads records in pairs
   e.nbr.fcnt = cv.take<int32_t>(N);
   e.nbr.pst = cv.take_bytes((e.prec == DEM_PREC_FP64 ? sizeof(PState<double>) : sizeof(PState<float>)) * N);
   e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
@@ -1147,7 +1148,7 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
   std::vector<float> slot_r(N);
   for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
   if ((st = h2d(e, e.pos[e.cp].r, slot_r)) != DEM_OK) return st;
-  HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr.xyzr, e.stream));
+  HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr, e.stream));
   HIP_TRY(launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream));
   // the contact list of the new radii, beside the committed history
   HIP_TRY(build_contacts(e, e.gc ^ 1, nullptr));

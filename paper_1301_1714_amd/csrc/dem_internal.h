@@ -14,9 +14,10 @@
 //   scell    global cell of each sorted slot; cell_start[ncell_total + 1]
 //   psys     system of each slot; bsys/bfirst: system and first slot of each
 //            kernel block (blocks never straddle two systems)
-//   nbr      detection output: xyzr (FP32 copy of x - lo and r, the
-//            prefilter's input) and, per particle, its contacts with higher
-//            slots in ascending order followed by its walls (-1 - w)
+//   nbr      detection input and output: xyzr (FP32 copy of x - lo and r)
+//            and xq (8-byte fixed-point copy, the direct sweep's candidate
+//            records), and, per particle, its contacts with higher slots in
+//            ascending order followed by its walls (-1 - w)
 //   pst      the law's inputs per particle, packed (PState<Real>), with the
 //            previous slot and committed history segment of each slot
 //   tiles    detection work items: (system, row, first cell, last cell) of
@@ -126,6 +127,7 @@ struct alignas(16) PState {
 
 struct NbrBuf {
   float4 *xyzr;   // [N] (x - lo, y - lo, z - lo, r), FP32
+  uint2 *xq;      // [N] x, y, z in cell units modulo 8 cells (1/8192 cell, 16 bits each), r in rmax/65535 rounded up
   int32_t *fcnt;  // [N] entries of nb (clamped to kListCap)
   int32_t *nb;    // [kListCap][N]
   void *pst;      // [N] PState<Real> of the current slots
@@ -211,7 +213,7 @@ hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, in
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
                           const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st);
-hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st);
+hipError_t launch_xyzr(const Layout &L, const PosBuf &p, const NbrBuf &nb, hipStream_t st);
 // nb.pst from the current buffers (before a force evaluation outside a step)
 hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const NbrBuf &nb,
                        hipStream_t st);

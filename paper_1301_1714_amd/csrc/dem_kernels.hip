@@ -386,6 +386,30 @@ __device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, d
   return make_float4((float)(x - g.lo[0]), (float)(y - g.lo[1]), (float)(z - g.lo[2]), r);
 }
 
+// The direct sweep's candidate record, 8 bytes instead of the 16 of the FP32
+// copy (the sweep is bound by the bytes its candidate loads move through the
+// address unit).  Each coordinate is the cell-space position u = (x - lo) sc,
+// rounded to 1/8192 cell and kept modulo 8 cells in 16 bits; the radius is
+// r / rmax in units of 1/65535, rounded up.  The difference of two such
+// coordinates, read as a signed 16-bit number, is the rounded difference
+// reduced to [-4, 4) cells: never larger in magnitude than the true one, and
+// off by at most 1/8192 cell where the true one lies inside that range.  A
+// prefilter on these records with its cut-off widened by the rounding bound
+// therefore passes every pair the FP32 prefilter passes.
+constexpr double kFixCell = 8192.0;
+constexpr double kFixRad = 65535.0;
+__device__ __forceinline__ uint32_t fix_cell(double u) {
+  return (uint32_t)(int64_t)floor(u * kFixCell + 0.5) & 0xffffu;
+}
+__device__ __forceinline__ uint2 make_xq(const SysInfo &si, double x, double y, double z, float r) {
+  const Grid &g = si.g;
+  const uint32_t qx = fix_cell((x - g.lo[0]) * g.sc[0]), qy = fix_cell((y - g.lo[1]) * g.sc[1]),
+                 qz = fix_cell((z - g.lo[2]) * g.sc[2]);
+  const double rr = si.rmax > 0.0f ? ceil((double)r / (double)si.rmax * kFixRad) : 0.0;
+  const uint32_t qr = rr <= 0.0 ? 0u : (rr >= kFixRad ? 0xffffu : (uint32_t)rr);
+  return make_uint2(qx | (qy << 16), qz | (qr << 16));
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     int32_t soa, const int32_t *__restrict__ perm,
@@ -414,7 +438,9 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
     ps.hb = b;
   }
   ((PState<Real> *)nb.pst)[s] = ps;
-  nb.xyzr[s] = make_xyzr(L.tab[k].g, ps.x, ps.y, ps.z, ps.r);
+  // the FP32 copies are candidates only of the tiled and wave detection shapes
+  if (L.ntiles > 0 || L.nruns > 0) nb.xyzr[s] = make_xyzr(L.tab[k].g, ps.x, ps.y, ps.z, ps.r);
+  nb.xq[s] = make_xq(L.tab[k], ps.x, ps.y, ps.z, ps.r);
   scell[s] = cell[p];
   if (soa) {
     dst.x[s] = ps.x;
@@ -451,11 +477,12 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
-__global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__restrict__ xyzr) {
+__global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, NbrBuf nb) {
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
-  xyzr[s] = make_xyzr(L.tab[k].g, p.x[s], p.y[s], p.z[s], p.r[s]);
+  nb.xyzr[s] = make_xyzr(L.tab[k].g, p.x[s], p.y[s], p.z[s], p.r[s]);
+  nb.xq[s] = make_xq(L.tab[k], p.x[s], p.y[s], p.z[s], p.r[s]);
 }
 
 // --------------------------------------------------------------------------
@@ -482,7 +509,6 @@ __global__ __launch_bounds__(kBlock) void k_xyzr(Layout L, PosBuf p, float4 *__r
 constexpr int kTileThreads = 128;
 constexpr int kHaloCap = 1024;  // particles staged per tile; a fuller tile reads global memory
 constexpr int kSurv = 8;        // LDS survivor slots per lane
-constexpr int kUnroll = 2;      // candidates per pipeline stage
 
 // FP64 position and FP32 radius of slot t, from its packed record (the
 // same layout for both Real types up to the radius' offset)
@@ -536,11 +562,43 @@ __device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int
   record<kLanes>(nb, N, s, lst, t, nf);
 }
 
+// The prefilter on FP32 copies (x - lo, y - lo, z - lo, r): a pair passes
+// when its FP32 distance is below the sum of the radii plus the margin eps,
+// which covers the rounding of the copies and of the test.
+struct NearF32 {
+  float px, py, pz, pe;  // pe: own radius + eps
+  __device__ __forceinline__ bool operator()(const float4 &q) const {
+    const float dx = q.x - px, dy = q.y - py, dz = q.z - pz, sf = pe + q.w;
+    return dx * dx + dy * dy + dz * dz < sf * sf;
+  }
+};
+
+// The same test on the fixed-point records (make_xq): differences of the
+// rounded cell-space coordinates in cell widths / 8192, the partner's radius
+// rounded up, and the cut-off widened by h, the bound on the distance error
+// of the rounding (one unit per axis).  A pair in contact is at most reach
+// (<= 2) cells apart on each axis, inside the [-4, 4) cells the 16-bit
+// differences resolve; beyond that range the wrapped difference is smaller
+// than the true one, so the test can only pass more pairs, never fewer.
+struct NearFix {
+  uint32_t qxy, qz;       // own record
+  float hx, hy, hz, rs;   // cell widths / 8192, rmax / 65535
+  float pe;               // own radius + eps + h
+  __device__ __forceinline__ bool operator()(const uint2 &q) const {
+    const float dx = (float)(int16_t)(q.x - qxy) * hx;
+    const float dy = (float)(int16_t)((q.x >> 16) - (qxy >> 16)) * hy;
+    const float dz = (float)(int16_t)(q.y - qz) * hz;
+    const float sf = pe + (float)(q.y >> 16) * rs;
+    return dx * dx + dy * dy + dz * dz < sf * sf;
+  }
+};
+
 // One particle's sweep over the forward half of the (2K + 1)^3 cells around
 // its own (K = 1: the 27 cells of Eq. 12).  rows(dy, dz, ca, cb, beg, end,
 // shift) gives the slot range [beg, end) of cells ca..cb of the row at
-// offset (dy, dz) and where their FP32 copies are (slot t at rows.src[t -
-// shift]); false for a row outside the grid.  The rows are visited in
+// offset (dy, dz) and where their candidate records are (slot t at rows.src[t -
+// shift]); false for a row outside the grid; rows.filter gives the
+// prefilter on those records.  The rows are visited in
 // ascending slot order: the own row, rows dy = 1..K of the own plane, then
 // rows dy = -K..K of planes dz = 1..K.  Survivors wait in the lane's LDS
 // slots (stride kLanes) so that the rare exact test does not sit inside the
@@ -549,8 +607,8 @@ template <int kLanes, int K, typename Rows>
 __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N, int32_t s,
                                                const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
                                                int32_t *surv, int32_t *lst, int32_t *err) {
-  const float4 p = nb.xyzr[s];
   const XR me = state_xr(nb, f64, s);
+  const float4 p = make_xyzr(si.g, me.x, me.y, me.z, me.r);
   const double xi = me.x, yi = me.y, zi = me.z;
   const float eps = si.eps;
   const int32_t nx = si.g.nc[0];
@@ -561,13 +619,15 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
   const float dyl = fmaxf(p.y - (float)cy * wy, 0.0f), dyh = fmaxf((float)(cy + 1) * wy - p.y, 0.0f);
   const float dzh = fmaxf((float)(cz + 1) * wz - p.z, 0.0f);
   const float dxl = fmaxf(p.x - (float)cx * wx, 0.0f);
+  const auto near = rows.filter(nb, s, si, p, p.w + eps);
   // the slot ranges of the forward rows first, so that their loads overlap;
   // a row, or a cell at either end of a row, whose box lies beyond cut is
   // skipped (the distance to the row or cell i steps away is the distance to
   // the own cell's face plus i - 1 cell widths)
   constexpr int R = 1 + 2 * K + 2 * K * K;
   int32_t beg[R], end[R], shift[R];
-  const float4 *src = rows.src;
+  using Rec = typename Rows::Rec;
+  constexpr int kU = Rows::kUnroll;
 #pragma unroll
   for (int h = 0; h < R; h++) {
     const int dyr = h <= K ? h : (h - K - 1) % (2 * K + 1) - K;
@@ -587,42 +647,36 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
     if (!rows(dyr, dzr, ca, cb, beg[h], end[h], shift[h])) beg[h] = end[h] = 0;
   }
   beg[0] = s + 1;  // own row: the slots after the particle
-  const float pe = p.w + eps;
   int32_t nf = 0, ns = 0;
 #pragma unroll
   for (int h = 0; h < R; h++) {
     const int32_t e = end[h], sh = shift[h];
     int32_t t = beg[h];
     while (t < e) {
-      // software pipeline: the next kUnroll candidates are in flight while
-      // the current ones are tested; the exact tests (global loads) stay
-      // outside this loop
-      float4 q[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; u++) q[u] = src[(uint32_t)(min(t + u, e - 1) - sh)];
+      // software pipeline: the next kU candidates are in flight while the
+      // current ones are tested; the exact tests (global loads) stay outside
+      // this loop
+      Rec q[kU];
+      rows.fetch(q, t, e, sh);
       for (;;) {
-        const int32_t tn = t + kUnroll;
-        float4 n[kUnroll];
+        const int32_t tn = t + kU;
+        Rec n[kU];
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) n[u] = q[u];
-        if (tn < e) {
+        for (int u = 0; u < kU; u++) n[u] = q[u];
+        if (tn < e) rows.fetch(n, tn, e, sh);
 #pragma unroll
-          for (int u = 0; u < kUnroll; u++) n[u] = src[(uint32_t)(min(tn + u, e - 1) - sh)];
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-          const float dx = q[u].x - p.x, dy = q[u].y - p.y, dz = q[u].z - p.z, sf = pe + q[u].w;
-          if (t + u < e && dx * dx + dy * dy + dz * dz < sf * sf) {
+        for (int u = 0; u < kU; u++) {
+          if (t + u < e && near(q[u])) {
             surv[ns * kLanes] = t + u;
             ns++;
           }
         }
         t = tn;
-        if (t >= e || ns > kSurv - kUnroll) break;
+        if (t >= e || ns > kSurv - kU) break;
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) q[u] = n[u];
+        for (int u = 0; u < kU; u++) q[u] = n[u];
       }
-      if (ns > kSurv - kUnroll) {
+      if (ns > kSurv - kU) {
         for (int32_t j = 0; j < ns; j++)
           exact_and_record<kLanes>(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
         ns = 0;
@@ -648,10 +702,43 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
   nb.fcnt[s] = nf < kListCap ? nf : kListCap;
 }
 
+// two consecutive 8-byte records in one 16-byte load (the records are
+// 8-byte aligned; the address unit's cost is per lane and instruction, not
+// per byte)
+__device__ __forceinline__ uint4 load_two(const uint2 *p) {
+  typedef uint4 uint4_a8 __attribute__((aligned(8)));
+  return *(const uint4_a8 *)p;
+}
+
 struct DirectRows {
-  const float4 *src;
+  using Rec = uint2;
+  static constexpr int kUnroll = 2;  // candidates per pipeline stage (even)
+  const uint2 *src;                  // [N + 1]: the last record pads the pair loads
   const int32_t *cell_start;
   int32_t c0, nx, ny, nz, cy, cz;
+  __device__ __forceinline__ NearFix filter(const NbrBuf &nb, int32_t s, const SysInfo &si, const float4 &,
+                                            float pe) const {
+    const uint2 me = src[s];
+    NearFix f;
+    f.qxy = me.x;
+    f.qz = me.y;
+    f.hx = (float)(1.0 / (si.g.sc[0] * kFixCell));
+    f.hy = (float)(1.0 / (si.g.sc[1] * kFixCell));
+    f.hz = (float)(1.0 / (si.g.sc[2] * kFixCell));
+    f.rs = (float)((double)si.rmax / kFixRad);
+    f.pe = pe + sqrtf(f.hx * f.hx + f.hy * f.hy + f.hz * f.hz);
+    return f;
+  }
+  // records t .. t + kUnroll - 1 of a range ending at e (past e: copies of
+  // slot e - 1 or the pad, which the caller masks)
+  __device__ __forceinline__ void fetch(uint2 (&q)[kUnroll], int32_t t, int32_t e, int32_t) const {
+#pragma unroll
+    for (int u = 0; u < kUnroll; u += 2) {
+      const uint4 w = load_two(src + min(t + u, e - 1));
+      q[u] = make_uint2(w.x, w.y);
+      q[u + 1] = make_uint2(w.z, w.w);
+    }
+  }
   __device__ __forceinline__ bool operator()(int dy, int dz, int32_t ca, int32_t cb, int32_t &beg, int32_t &end,
                                              int32_t &shift) const {
     const int32_t yy = cy + dy, zz = cz + dz;
@@ -679,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl,
   const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
   const int32_t cc = scell[s] - si.g.c0;
   const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
-  const DirectRows rows{nb.xyzr, cell_start, si.g.c0, nx, ny, nz, cy, cz};
+  const DirectRows rows{nb.xq, cell_start, si.g.c0, nx, ny, nz, cy, cz};
   sweep_particle<kBlock, K>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, lst_all + threadIdx.x,
                             err);
 }
@@ -938,6 +1025,8 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
 
 template <bool kStaged>
 struct TileRows {
+  using Rec = float4;
+  static constexpr int kUnroll = 2;  // candidates per pipeline stage
   const float4 *src;
   const int32_t (*cs)[kMaxTile + 3];
   int32_t xa;
@@ -949,6 +1038,14 @@ struct TileRows {
     end = cs[r][cb - xa + 1];
     sh = kStaged ? shift[r] : 0;
     return true;
+  }
+  __device__ __forceinline__ NearF32 filter(const NbrBuf &, int32_t, const SysInfo &, const float4 &p,
+                                            float pe) const {
+    return NearF32{p.x, p.y, p.z, pe};
+  }
+  __device__ __forceinline__ void fetch(float4 (&q)[kUnroll], int32_t t, int32_t e, int32_t sh) const {
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) q[u] = src[(uint32_t)(min(t + u, e - 1) - sh)];
   }
 };
 
@@ -1813,8 +1910,8 @@ hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const Ve
   return hipGetLastError();
 }
 
-hipError_t launch_xyzr(const Layout &L, const PosBuf &p, float4 *xyzr, hipStream_t st) {
-  if (L.n > 0) k_xyzr<<<L.nblocks, kBlock, 0, st>>>(L, p, xyzr);
+hipError_t launch_xyzr(const Layout &L, const PosBuf &p, const NbrBuf &nb, hipStream_t st) {
+  if (L.n > 0) k_xyzr<<<L.nblocks, kBlock, 0, st>>>(L, p, nb);
   return hipGetLastError();
 }
 

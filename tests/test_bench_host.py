@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_byte_models():
     # detection: per sphere 16 + 24 + 4 + 4 bytes plus 4 per owned entry, cell starts once
-    assert bench.detect_bytes(10, 7, 2.0) == 10 * (48 + 8) + 4 * 8
+    assert bench.detect_bytes(10, 7, 2.0) == 10 * (40 + 8) + 4 * 8
     # law: per contact slots, history read and written, force record; per sphere its record
     assert bench.pair_force_bytes(10, 20, 4) == 20 * (16 + 48) + 10 * (36 + 24)
     assert bench.pair_force_bytes(10, 20, 8) == 20 * (16 + 96) + 10 * (36 + 48)

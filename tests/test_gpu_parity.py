@@ -318,6 +318,50 @@ def test_cell_divisor_two_finds_the_same_contacts(dem, name):
     assert np.abs(sg["x"] - so["x"]).max() <= (1e-12 if tol < 1e-9 else 1e-6) * scale
 
 
+def edge_pairs(seed, k, divisor, precision):
+    """k^3 isolated pairs on a lattice, each at a distance a relative 1e-9 to
+    1e-3 below or above the sum of its radii (or well inside it), in random
+    directions, with seeded FP32 radii between 0.3 and 1 r_max.  With a cell
+    of 3 r_max and one grid cell per cell the first spheres reach 0.3 cells
+    beyond the box on every side (their partners up to 0.97 cells), where
+    the cell ids are clamped; with cells halved every sphere stays inside."""
+    rng = np.random.default_rng(seed)
+    rmax = 0.01
+    cell = 3.0 * rmax
+    L = 6.0 * rmax * (k - 1)
+    out = 0.3 * cell if divisor == 1 else -2.2 * rmax
+    a = np.linspace(-out, L + out, k)
+    A = np.stack(np.meshgrid(a, a, a, indexing="ij"), axis=-1).reshape(-1, 3)
+    m = len(A)
+    r = W.fp32_radii(rng.uniform(0.3, 1.0, 2 * m) * rmax)
+    r[0] = rmax  # the largest radius, so that rmax is what the cell was sized for
+    rA, rB = r[:m], r[m:]
+    f = rng.choice([1 - 1e-9, 1 - 1e-7, 1 - 1e-5, 1 - 1e-3, 1 + 1e-9, 1 + 1e-7, 1 + 1e-5, 1 + 1e-3, 0.7], m)
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    B = A + d * ((rA + rB) * f)[:, None]
+    x = np.empty((2 * m, 3))
+    x[0::2], x[1::2] = A, B
+    rr = np.empty(2 * m)
+    rr[0::2], rr[1::2] = rA, rB
+    p = W.base_params(box_hi=(L, L, L), cell_size=cell, wall_mask=0, precision=precision)
+    zero = np.zeros_like(x)
+    return p, x, zero, zero, rr, int(np.sum(f < 1))
+
+
+@pytest.mark.parametrize("divisor,precision", [(1, "mixed"), (1, "fp64"), (2, "mixed")])
+def test_pairs_at_the_prefilter_edge(dem, divisor, precision):
+    # pairs a relative 1e-9 inside or outside contact, in every direction and
+    # across the clamped cells beyond the box: the prefilter passes every true
+    # contact, and the exact test decides as the oracle does
+    p, x, v, w, r, n_in = edge_pairs(11 + divisor, 12, divisor, precision)
+    g = dem.System(dict(p, cell_divisor=divisor), x, v, w, r)
+    o = OracleSystem(p, x, v, w, r)
+    co = o.contacts()
+    assert len(co) == n_in
+    assert np.array_equal(g.contacts(), co)
+
+
 def test_profile_phases_cover_the_step(dem):
     import torch
     c = cloud(seed=9, n=3000, precision="mixed")
