@@ -437,11 +437,18 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
     ps.hp = (uint32_t)p | ((uint32_t)c << kPrevBits);
     ps.hb = b;
   }
+  // the candidate records are formed ahead of every store, so that the
+  // system's grid is read with scalar loads (a store may alias it as far as
+  // the compiler knows); the FP32 copies are candidates only of the tiled and
+  // wave detection shapes
+  const SysInfo &si = L.tab[k];
+  const uint2 xq = make_xq(si, ps.x, ps.y, ps.z, ps.r);
+  const float4 xyzr = make_xyzr(si.g, ps.x, ps.y, ps.z, ps.r);
+  const int32_t cp = cell[p];
   ((PState<Real> *)nb.pst)[s] = ps;
-  // the FP32 copies are candidates only of the tiled and wave detection shapes
-  if (L.ntiles > 0 || L.nruns > 0) nb.xyzr[s] = make_xyzr(L.tab[k].g, ps.x, ps.y, ps.z, ps.r);
-  nb.xq[s] = make_xq(L.tab[k], ps.x, ps.y, ps.z, ps.r);
-  scell[s] = cell[p];
+  if (L.ntiles > 0 || L.nruns > 0) nb.xyzr[s] = xyzr;
+  nb.xq[s] = xq;
+  scell[s] = cp;
   if (soa) {
     dst.x[s] = ps.x;
     dst.y[s] = ps.y;
@@ -1614,10 +1621,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   int32_t k;
   const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + m), one system
   const SysInfo &si = a.L.tab[k];
-  const Consts &c = si.c;
+  // the system's constants, grid and step control are read here, ahead of
+  // every store, so that they are scalar loads (a store may alias them as
+  // far as the compiler knows)
+  const Consts c = si.c;
+  const Grid g = si.g;
   const bool stepping = (a.mode & MODE_KICK) != 0;
+  const int32_t step_now = stepping ? *a.ctl.step : 0, left_k = stepping ? a.ctl.left[k] : 0;
   const int32_t N = a.L.n;
-  if (stepping && !is_active(a.ctl, k)) {
+  if (stepping && !(step_now < left_k)) {
     if (s < 0) return;
     const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
     // a finished system: state unchanged; the next sort sees its current cells
@@ -1741,7 +1753,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   // the system steps again in this call: the forces stay in registers for
   // the fused kick; otherwise they are kept for the read-back and the next
   // call's opening kick
-  const bool again = stepping && *a.ctl.step + 1 < a.ctl.left[k];
+  const bool again = stepping && step_now + 1 < left_k;
   if (!again) {
 #pragma unroll
     for (int q = 0; q < 3; q++) {
@@ -1758,7 +1770,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
       // the next step's Steps 1-2 with the same forces: the same operations
       // as k_kick_drift_hash, so fusing changes no bit
       half_kick<Real>(c, m, I, F, T, v, w);
-      drift_hash_to(me.x, me.y, me.z, a.pos_out, s, v, c, si.g, a.cell, a.err);
+      drift_hash_to(me.x, me.y, me.z, a.pos_out, s, v, c, g, a.cell, a.err);
     } else {
       a.pos_out.x[s] = me.x;  // its last step in this call: it stops here
       a.pos_out.y[s] = me.y;
