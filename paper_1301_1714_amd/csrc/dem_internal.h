@@ -126,7 +126,7 @@ struct alignas(16) PState {
 };
 
 struct NbrBuf {
-  float4 *xyzr;   // [N] (x - lo, y - lo, z - lo, r), FP32
+  float4 *xyzr;   // [N] (x - lo, y - lo, z - lo, r), FP32; written only while a system uses tiles or waves
   uint2 *xq;      // [N] x, y, z in cell units modulo 8 cells (1/8192 cell, 16 bits each), r in rmax/65535 rounded up
   int32_t *fcnt;  // [N] entries of nb (clamped to kListCap)
   int32_t *nb;    // [kListCap][N]
