@@ -342,8 +342,9 @@ def bench_batched(args):
     work = float(ns.sum()) * args.batch_steps
     batched_rate = work / elapsed
     # the same systems one at a time through the plain single-system path
+    # (skipped with --plain-steps 0, e.g. for a profile of the batch alone)
     t_plain = 0.0
-    for s in systems:
+    for s in systems if args.plain_steps > 0 else []:
         one = dem.System(s["params"], s["x"], s["v"], s["omega"], s["r"])
         one.step(2)
         one.sync()
@@ -352,7 +353,7 @@ def bench_batched(args):
         one.sync()
         t_plain += time.perf_counter() - t0
         one.close()
-    plain_rate = float(ns.sum()) * args.plain_steps / t_plain
+    plain_rate = float(ns.sum()) * args.plain_steps / t_plain if t_plain > 0 else None
     fac, cnt = np.unique(factors, return_counts=True)
     til, tcnt = np.unique(tiles, return_counts=True)
     return {
@@ -361,7 +362,7 @@ def bench_batched(args):
         "value": batched_rate, "unit": "particle-steps/s", "ms_per_step": elapsed * 1e3 / args.batch_steps,
         "graph": True, "plain_one_at_a_time": {"value": plain_rate, "unit": "particle-steps/s",
                                               "steps_per_system": args.plain_steps},
-        "speedup_vs_plain": batched_rate / plain_rate,
+        "speedup_vs_plain": batched_rate / plain_rate if plain_rate else None,
         "cell_factors": {str(f): int(c) for f, c in zip(fac, cnt)},
         "detect_tiles": {str(t): int(c) for t, c in zip(til, tcnt)},
         "cell_divisors": {str(int(d)): int(c) for d, c in zip(*np.unique(divisors, return_counts=True))},
@@ -451,6 +452,8 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=100)
     ap.add_argument("--serve-hbm-frac", type=float, default=0.8)
     ap.add_argument("--only-dense", action="store_true", help="skip the other configs, batched, serving and the CPU baseline")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched workload and print its record (a profile of the batch)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (profiler counter calibration)")
     args = ap.parse_args()
@@ -468,6 +471,9 @@ def main():
         return
     from paper_1301_1714_amd import dem
     dem.lib()
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(args)}), flush=True)
+        return
     out = bench_dense(args)
     log(f"[bench] dense bed: {out['value']:.4g} particle-steps/s, {out['ms_per_step']:.3f} ms/step")
     if not (args.no_configs or args.only_dense):
@@ -475,7 +481,7 @@ def main():
     if not (args.no_batched or args.only_dense):
         out["batched"] = bench_batched(args)
         log(f"[bench] batched: {out['batched']['value']:.4g} particle-steps/s "
-            f"({out['batched']['speedup_vs_plain']:.2f}x plain)")
+            f"({out['batched']['speedup_vs_plain'] or 0:.2f}x plain)")
     if not (args.no_serve or args.only_dense):
         out["serving"] = bench_serving(args)
         sv = out["serving"]
