@@ -1,0 +1,110 @@
+"""The oracle pins catch plausible mistakes: each case below plants one mistake
+in a copy of the oracle's C source (never in the oracle itself), builds it,
+and runs the pins against that build, which must fail.  CPU only.
+
+The mistakes are of the kinds a reading of Sec. 3 could make: a wrong sign,
+a dropped term, a wrong factor, a wrong stencil or comparison, the history
+seen from the wrong side.  A control build of the unchanged source passes.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dem_oracle.c")
+
+# name: (what it breaks, text in the oracle, the planted replacement)
+MUTATIONS = {
+    "spin_sign": ("Eq. 4: relative surface velocity uses r_i w_i + r_j w_j",
+                  "G->spin[k] = s->r[a] * s->w[3 * a + k] + s->r[b] * s->w[3 * b + k];",
+                  "G->spin[k] = s->r[a] * s->w[3 * a + k] - s->r[b] * s->w[3 * b + k];"),
+    "no_projection": ("Eq. 7: delta_t projected onto the tangent plane",
+                      "dt_new[k] = h[k] - hn * G->n[k] + vt[k] * p->dt;",
+                      "dt_new[k] = h[k] + vt[k] * p->dt;"),
+    "torque_b_sign": ("Eq. 3: torque on the partner",
+                      "T[3 * b + q] += s->r[b] * nxft[q];",
+                      "T[3 * b + q] -= s->r[b] * nxft[q];"),
+    "torque_scale": ("Eq. 3: torque lever arm r_i",
+                     "T[3 * a + q] += s->r[a] * nxft[q]; /* Eq. 3 */",
+                     "T[3 * a + q] += s->r[a] * nxft[q] * 1.0001; /* Eq. 3 */"),
+    "eta_mass": ("Eq. 10: eta = alpha sqrt(k M)",
+                 "double eta = s->alpha * sqrt(kn * G->M);",
+                 "double eta = s->alpha * sqrt(kn * G->M * 2.0);"),
+    "alpha_factor": ("Eq. 10: alpha from the restitution coefficient",
+                     "-2.0 * log(p->e) / sqrt",
+                     "-1.0 * log(p->e) / sqrt"),
+    "no_cap_rescale": ("Eq. 5: delta_t rescaled when the Coulomb cap holds",
+                       "for (int k = 0; k < 3; k++) dt_new[k] = -(Ft[k] + eta_t * vt[k]) / kt;",
+                       ";"),
+    "vt_drop_spin": ("Eq. 4: tangential velocity includes the spin term",
+                     "vt[k] = G->v[k] - vn[k] + sxn[k];",
+                     "vt[k] = G->v[k] - vn[k];"),
+    "hertz_radius": ("Eqs. 8-9: Hertz stiffness from the effective radius",
+                     "double q = sqrt(G->delta * G->R);",
+                     "double q = sqrt(G->delta * G->R * 2.0);"),
+    "inertia": ("solid-sphere moment of inertia 2/5 m r^2",
+                "s->I[i] = 0.4 * s->m[i] * ri * ri;",
+                "s->I[i] = 0.5 * s->m[i] * ri * ri;"),
+    "wall_mass": ("Sec. 4.2 Step 8: a wall is a particle of infinite mass",
+                  "G->M = s->m[a];\n}",
+                  "G->M = 0.5 * s->m[a];\n}"),
+    "contact_le": ("contact means d < r_i + r_j",
+                   "return d2 < S * S;",
+                   "return d2 <= S * S * 1.000001;"),
+    "stencil_2d": ("Eq. 12: 27 cells, not 9",
+                   "for (int dz = -1; dz <= 1; dz++)",
+                   "for (int dz = 0; dz <= 0; dz++)"),
+    "kick_gravity": ("KDK kick with the external field",
+                     "s->v[3 * i + k] += h * (s->F[3 * i + k] / s->m[i] + s->p.g[k]);",
+                     "s->v[3 * i + k] += h * (s->F[3 * i + k] / s->m[i] + 2*s->p.g[k]);"),
+    "simple_sign": ("Eq. 1: damping opposes the relative velocity",
+                    "F[k] = -p->k_sp * G->delta * G->n[k] - p->k_da * G->v[k] - p->k_sh * vt[k];",
+                    "F[k] = -p->k_sp * G->delta * G->n[k] + p->k_da * G->v[k] - p->k_sh * vt[k];"),
+    "history_side": ("Eq. 6: the history seen from the other particle is negated",
+                     "const double *h = he ? he->d : zero;",
+                     "double hneg[3]; if (he) { hneg[0]=-he->d[0]; hneg[1]=-he->d[1]; hneg[2]=-he->d[2]; } "
+                     "const double *h = he ? (b >= 0 && (a ^ b) & 1 ? hneg : he->d) : zero;"),
+}
+
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+SLOW = "tests/test_oracle_pins.py::test_energy_drift_plain_fp64_workload"
+
+
+def _build(src_text, out_dir, name):
+    c = os.path.join(out_dir, f"{name}.c")
+    lib = os.path.join(out_dir, f"lib_{name}.so")
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", c,
+                    "-o", lib, "-lm"], check=True, capture_output=True)
+    return lib
+
+
+def _pins_against(lib):
+    env = dict(os.environ, DEM_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", PINS, "-q", "-x", "-p", "no:cacheprovider",
+                        "--deselect", SLOW], env=env, capture_output=True, text=True, cwd=ROOT, timeout=300)
+    tail = (r.stdout.strip().splitlines() or [""])[-1]
+    return r.returncode, tail
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    src = open(SRC).read()
+    for name, (_, old, _new) in MUTATIONS.items():
+        assert src.count(old) >= 1, f"mutation {name}: its text is no longer in the oracle source"
+
+    def run(item):
+        name, (_, old, new) = item
+        lib = _build(src.replace(old, new, 1), str(tmp_path), name)
+        return name, _pins_against(lib)
+
+    control = _pins_against(_build(src, str(tmp_path), "control"))
+    assert control[0] == 0, f"the unchanged source fails its pins: {control[1]}"
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        results = dict(ex.map(run, MUTATIONS.items()))
+    # exit status 1: tests ran and at least one failed (not a crash or a usage error)
+    missed = {n: t for n, (rc, t) in results.items() if rc != 1}
+    assert not missed, f"mistakes no pin caught (or that crashed the run): {missed}"
