@@ -32,7 +32,10 @@
  *    point and Eq. 4 is repulsive and dissipative.
  *  - Eq. 1 is applied as F_i = -k_sp d n - k_da v - k_sh v_t; gravity is
  *    added once per particle in the kick, not per pair.  The simple model
- *    produces no torque and keeps no history.
+ *    produces no torque and keeps no history, and its v_t is the tangential
+ *    component v - (v.n) n of the relative velocity (the suffix t as Sec. 3
+ *    defines it), without Eq. 6's spin term, which belongs to the practical
+ *    model.
  *  - Eq. 4's tangential damping is eta_t = eta_t_ratio * eta (ratio 1 is the
  *    literal reading of Eq. 4).
  *  - Eq. 5 (sliding): the stored tangential displacement is rescaled to the
@@ -241,7 +244,7 @@ static int detect(const orc_sys *s, const orc_grid *g, orc_clist *L)
     L->n = L->cap = 0;
     for (int64_t slot = 0; slot < s->n; slot++) {
         int64_t a = g->sccm[slot];
-        int32_t ijk[3];
+        int32_t ijk[3] = {0, 0, 0};
         cell_of(s, s->x + 3 * a, ijk); /* in domain: grid_build succeeded */
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
@@ -326,8 +329,13 @@ static void contact_law(const orc_sys *s, const orc_geom *G, const double h[3], 
         vt[k] = G->v[k] - vn[k] + sxn[k]; /* Eq. 6 */
     }
     if (p->law == ORC_SIMPLE) { /* Eq. 1, gravity excluded */
+        /* Sec. 3 defines the suffix t of Eq. 1 as the tangential component of
+         * the relative velocity v; the simple model carries no rotation, so
+         * Eq. 6's spin term does not enter it */
+        double vts[3];
+        for (int k = 0; k < 3; k++) vts[k] = G->v[k] - vn[k];
         for (int k = 0; k < 3; k++) {
-            F[k] = -p->k_sp * G->delta * G->n[k] - p->k_da * G->v[k] - p->k_sh * vt[k];
+            F[k] = -p->k_sp * G->delta * G->n[k] - p->k_da * G->v[k] - p->k_sh * vts[k];
             Ft[k] = 0.0;
             dt_new[k] = 0.0;
         }

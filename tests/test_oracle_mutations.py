@@ -61,8 +61,26 @@ MUTATIONS = {
                      "s->v[3 * i + k] += h * (s->F[3 * i + k] / s->m[i] + s->p.g[k]);",
                      "s->v[3 * i + k] += h * (s->F[3 * i + k] / s->m[i] + 2*s->p.g[k]);"),
     "simple_sign": ("Eq. 1: damping opposes the relative velocity",
-                    "F[k] = -p->k_sp * G->delta * G->n[k] - p->k_da * G->v[k] - p->k_sh * vt[k];",
-                    "F[k] = -p->k_sp * G->delta * G->n[k] + p->k_da * G->v[k] - p->k_sh * vt[k];"),
+                    "F[k] = -p->k_sp * G->delta * G->n[k] - p->k_da * G->v[k] - p->k_sh * vts[k];",
+                    "F[k] = -p->k_sp * G->delta * G->n[k] + p->k_da * G->v[k] - p->k_sh * vts[k];"),
+    "simple_shear_sign": ("Eq. 1: the shear term opposes the tangential velocity",
+                          "- p->k_sh * vts[k];",
+                          "+ p->k_sh * vts[k];"),
+    "simple_shear_dropped": ("Eq. 1: the shear term k_sh v_t is part of the force",
+                             "- p->k_sh * vts[k];",
+                             ";"),
+    "simple_shear_spin": ("Eq. 1: v_t is the tangential part of v, with no spin term",
+                          "vts[k] = G->v[k] - vn[k];",
+                          "vts[k] = G->v[k] - vn[k] + sxn[k];"),
+    "rotational_ke_mass": ("rotational kinetic energy I |w|^2 / 2",
+                           "term[4] = 0.5 * s->I[i] * dot3(w, w);",
+                           "term[4] = 0.5 * s->m[i] * dot3(w, w);"),
+    "hertz_energy_factor": ("Eqs. 8-9: Hertz elastic energy (2/5) K delta^(5/2)",
+                            "en = 0.4 * s->p.kn * sqrt(G.R) * pow(G.delta, 2.5)",
+                            "en = 0.5 * s->p.kn * sqrt(G.R) * pow(G.delta, 2.5)"),
+    "tangential_energy_dropped": ("Eq. 4: tangential spring energy k_t |delta_t|^2 / 2",
+                                  "en = 0.5 * kn * G.delta * G.delta + 0.5 * kt * dot3(h, h);",
+                                  "en = 0.5 * kn * G.delta * G.delta;"),
     "history_side": ("Eq. 6: the history seen from the other particle is negated",
                      "const double *h = he ? he->d : zero;",
                      "double hneg[3]; if (he) { hneg[0]=-he->d[0]; hneg[1]=-he->d[1]; hneg[2]=-he->d[2]; } "
@@ -78,7 +96,7 @@ def _build(src_text, out_dir, name):
     lib = os.path.join(out_dir, f"lib_{name}.so")
     with open(c, "w") as f:
         f.write(src_text)
-    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", c,
+    subprocess.run(["gcc", "-O3", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", c,
                     "-o", lib, "-lm"], check=True, capture_output=True)
     return lib
 

@@ -365,6 +365,123 @@ def test_simple_model_head_on():
     assert np.all(states[-1]["omega"] == 0.0)
 
 
+def test_simple_model_shear_decay():
+    """Eq. 1 with a tangential relative velocity: a sphere resting on the
+    floor at its static overlap m g / k_sp, launched along x with no spin.
+    Its normal velocity stays zero, so both the damping k_da v and the shear
+    term k_sh v_t act along x alone and v_x = u exp(-(k_da + k_sh) t / m)."""
+    r, ksp, kda, ksh = 1.0 / 64.0, 1.0e5, 1.5, 0.5
+    m = sphere_mass(r)
+    lam = (kda + ksh) / m
+    dt = 1e-3 / lam
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), dt=dt, law="simple", simple_k=(ksp, kda, ksh))
+    rr = float(np.float32(r))
+    z0 = rr - m * 9.81 / ksp
+    u = 0.05
+    s = OracleSystem(p, [[0.02, 0.1, z0]], [[u, 0, 0]], [[0, 0, 0]], [r])
+    ts, lv = [], []
+    for k in range(20):
+        st = s.read_state()
+        ts.append(k * 100 * dt)
+        lv.append(math.log(st["v"][0, 0]))
+        assert abs(st["x"][0, 2] - z0) < 1e-12  # the normal balance holds throughout
+        s.step(100)
+    slope = np.polyfit(ts, lv, 1)[0]
+    assert abs(-slope - lam) / lam < 1e-3
+
+
+def test_simple_model_ignores_spin():
+    """Eq. 1 has no rotation: its v_t is the tangential part of the relative
+    velocity (the suffix t of Sec. 3), so a sphere at rest on the floor that
+    spins produces no shear force, and its spin never changes (no torque)."""
+    r, ksp = 1.0 / 64.0, 1.0e5
+    m = sphere_mass(r)
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), dt=1e-5, law="simple", simple_k=(ksp, 1.5, 0.5))
+    rr = float(np.float32(r))
+    z0 = rr - m * 9.81 / ksp
+    w0 = [3.0, -20.0, 7.0]
+    s = OracleSystem(p, [[0.1, 0.1, z0]], [[0, 0, 0]], [w0], [r])
+    s.step(500)
+    st = s.read_state()
+    assert np.all(st["v"][0, :2] == 0.0) and np.all(st["x"][0, :2] == [0.1, 0.1])
+    assert np.array_equal(st["omega"][0], w0)
+
+
+# ---------------------------------------------------------------- diagnostics
+
+
+def test_kinetic_energy_diagnostics_of_a_free_sphere():
+    """out[3] = m |v|^2 / 2 and out[4] = I |w|^2 / 2 with I = 2/5 m r^2 (a
+    solid sphere), i.e. m r^2 |w|^2 / 5; out[0..2] = m v; out[5] = m g h."""
+    r = 0.01
+    m = sphere_mass(r)
+    rr = float(np.float32(r))
+    p = W.base_params(cell_size=0.1, wall_mask=0, dt=1e-5)
+    v0, w0 = np.array([0.3, -0.4, 1.2]), np.array([5.0, -2.0, 11.0])
+    s = OracleSystem(p, [[0.3, 0.4, 0.6]], [v0], [w0], [r])
+    d = s.diagnostics()
+    assert np.allclose(d[:3], m * v0, rtol=1e-14, atol=0)
+    assert abs(d[3] - 0.5 * m * v0 @ v0) <= 1e-14 * d[3]
+    assert abs(d[4] - m * rr * rr * (w0 @ w0) / 5.0) <= 1e-14 * d[4]
+    assert abs(d[5] - m * 9.81 * 0.6) <= 1e-14 * d[5]
+    assert d[6] == 0.0 and d[7] == 0 and d[8] == 0
+
+
+def test_hertz_elastic_energy_conserves_total():
+    """Undamped Hertz head-on collision: the elastic energy of Eqs. 8-9,
+    (2/5) K delta^(5/2) with K = C_kn sqrt(R) (the integral of K sqrt(delta)
+    delta), plus the kinetic energy stays at its initial value through the
+    contact; the elastic part peaks at nearly all of it."""
+    r, C = 1.0 / 64.0, 1.0e7
+    rr = float(np.float32(r))
+    M = sphere_mass(r) / 2
+    K = C * math.sqrt(rr / 2)
+    u = 0.1
+    dmax = (5 * M * (2 * u) ** 2 / (4 * K)) ** 0.4
+    tc = 0.8 * beta_fn(0.4, 0.5) * dmax / (2 * u)
+    dt = tc / 10000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=1.0,
+                      law="hertz", kn=C, kt=0.0)
+    s = two_spheres(p, r, u, gap=1e-9)
+    E0 = s.diagnostics()[3]
+    peak = 0.0
+    for _ in range(120):
+        d = s.diagnostics()
+        assert abs(d[3] + d[6] - E0) <= 1e-6 * E0
+        peak = max(peak, d[6])
+        s.step(100)
+    assert peak > 0.99 * E0
+
+
+def test_tangential_spring_energy_conserves_total():
+    """Stick oscillation without damping (e = 1, eta_t = 0, no sliding): the
+    energy of the tangential spring, k_t |delta_t|^2 / 2 (Eq. 4 with the
+    displacement of Eq. 7), exchanges with the translational and rotational
+    kinetic energy, and the total of the four diagnostics stays constant."""
+    r, kn = 1.0 / 64.0, 1.0e5
+    kt = 2.0 / 7.0 * kn
+    m = sphere_mass(r)
+    period = 2 * math.pi / math.sqrt(kn / m)
+    dt = period / 4000
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=1.0, mu=10.0, kt=kt, dt=dt,
+                      eta_t_ratio=0.0)
+    rr = float(np.float32(r))
+    z0 = rr - m * 9.81 / kn
+    s = OracleSystem(p, [[0.1, 0.1, z0]], [[2e-3, 0, 0]], [[0, 0, 0]], [r])
+    tot, tang = [], []
+    for _ in range(80):
+        d = s.diagnostics()
+        st = s.read_state()
+        pairs, dts = s.read_contacts()
+        tot.append(d[3] + d[4] + d[5] + d[6])
+        tang.append(0.5 * kt * float(np.sum(dts ** 2)))
+        s.step(50)
+    tot = np.array(tot)
+    swing = 0.5 * m * 2e-3 ** 2  # the kinetic energy the spring takes up and gives back
+    assert max(tang) > 0.1 * swing
+    assert np.max(np.abs(tot - tot[0])) <= 1e-5 * swing
+
+
 # ---------------------------------------------------------------- invariants
 
 
