@@ -98,21 +98,25 @@ def copy_probe(mib, reps):
 # launch; neighbour data reused from LDS or cache is not counted.  R is the
 # size of a Real (4 with FP32 forces, 8 in FP64).
 
-def detect_bytes(n, ncell, c_own):
-    """k_detect: per particle its 8-byte fixed-point candidate record, its
-    FP64 position (24 B) and cell (4 B) read, its count (4 B) and c_own list
-    entries (4 B each: partners with higher slots, walls) written; the cell
-    starts read once."""
-    return n * (40 + 4 * c_own) + 4 * (ncell + 1)
+def contacts_bytes(n, ncell, P, R):
+    """k_contacts_direct (detection and the contact law in one pass): per
+    particle its 8-byte fixed-point candidate record, its packed state (x
+    24 B, v and w 6R, r, id, previous slot and history count 16 B) and cell
+    (4 B) read, its contact count and history count (4 B each) written; per
+    owned contact (P of them, pairs once plus walls) the list entry (4 B),
+    the committed history entry read (key 4 B, delta_t 3R), the new one
+    written (4 + 3R), the force record written (6R) and the backward-list
+    entry with its count (8 B); the cell starts read once.  Partner records
+    and neighbouring candidate records are reuse."""
+    return n * (60 + 6 * R) + P * (20 + 12 * R) + 4 * (ncell + 1)
 
 
-def pair_force_bytes(n, P, R):
-    """k_pair_force: per contact its two slots (8 B), the committed history
-    read (key 4 B, delta_t 3R), the new entry written (key 4 B, delta_t 3R)
-    and the force and torque term written (6R); per particle its packed
-    state (x 24 B, r 4 B, v and w 6R, with the previous slot, history count
-    and history offset in 8 B) read once.  Partner reads are reuse."""
-    return P * (16 + 12 * R) + n * (36 + 6 * R)
+def gather_bytes(n, P, R):
+    """k_gather: per particle its packed state (40 + 6R), backward count read
+    and cleared (8 B) and contact count (4 B), the state written back (x
+    24 B, r 4, id 4, v and w 6R, cell 4); per contact the force record read
+    by the owner and by the partner (2 x 6R) and the backward entry (4 B)."""
+    return n * (88 + 12 * R) + P * (4 + 12 * R)
 
 
 def step_algorithmic_bytes(n, z, R):
@@ -127,29 +131,80 @@ def step_algorithmic_bytes(n, z, R):
 
 # ------------------------------------------------------------ CPU oracle
 
-def cpu_baseline(target_seconds):
-    """The FP64 oracle, single-threaded, on 2^15 spheres of the same recipe
-    (same radius distribution, number density, box aspect and cell width) on
-    the FCC lattice at 1.05x the largest non-overlapping radius scale."""
+CPU_SAMPLE_N = 1 << 15
+
+
+def oracle_sample(seed, seconds):
+    """The FP64 oracle, single-threaded, on 2^15 spheres of the dense-bed
+    recipe (same radius distribution, number density, box aspect and cell
+    width) on its FCC lattice at 1.05x the largest non-overlapping radius
+    scale, stepped for about `seconds`; returns (particle-steps, elapsed s,
+    steps, lattice scale)."""
     from oracle.oracle import OracleSystem
     from paper_1301_1714_amd import workloads as W
 
-    n = 1 << 15
-    w = W.dense_bed_lattice(seed=3000, n=n)
+    w = W.dense_bed_lattice(seed=seed, n=CPU_SAMPLE_N)
     lam = 1.05 * W.lattice_scale(w["r"], w["d_nn"])
     o = OracleSystem(w["params"], w["x"], w["v"], w["omega"], w["r"] * lam)
     t0 = time.perf_counter()
     o.step(2)
     per = (time.perf_counter() - t0) / 2
-    k = max(2, int(target_seconds / max(per, 1e-6)))
+    k = max(2, int(seconds / max(per, 1e-6)))
     t0 = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t0
-    out = {"value": n * k / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-           "sample": f"{n} spheres of the dense-bed recipe (lattice at {lam:.3f} of full radii), "
-                     f"{k} steps, {dt:.1f} s, FP64, single thread"}
+    return CPU_SAMPLE_N * k, dt, k, lam
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": share}
+
+
+def cpu_baseline(target_seconds):
+    """The FP64 oracle on the host: one thread on a bounded sample of the
+    dense-bed recipe (the paper's CPU baseline is one core), and the same on
+    every usable core at once -- independent oracle processes, each on its own
+    seeded sample, their particle-steps summed (the oracle's arithmetic and
+    order are untouched; the host's cores are used the way independent runs
+    would use them).  At most 16 processes (the host share of one GPU)."""
+    from oracle import build as oracle_build
+    from oracle.oracle import OracleSystem
+    from paper_1301_1714_amd import workloads as W
+
+    oracle_build.build()  # -O3, as the tests use it
+    info = cpu_info()
+    work, dt, k, lam = oracle_sample(3000, 0.5 * target_seconds)
+    single = {"value": work / dt, "unit": "particle-steps/s", "cores": 1,
+              "sample": f"{CPU_SAMPLE_N} spheres of the dense-bed recipe (lattice at {lam:.3f} of full radii), "
+                        f"{k} steps, {dt:.1f} s, FP64, one thread"}
+    procs = max(1, min(16, int(info["usable"] or 1)))
+    import subprocess
+
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker"]
+    kids = [subprocess.Popen(cmd + [str(3000 + 17 * j), str(0.5 * target_seconds)], stdout=subprocess.PIPE,
+                             text=True) for j in range(procs)]
+    t0 = time.perf_counter()
+    outs = [json.loads(kid.communicate()[0].strip().splitlines()[-1]) for kid in kids]
+    wall = time.perf_counter() - t0
+    total = sum(o["work"] for o in outs)
+    span = max(o["seconds"] for o in outs)
+    out = {"value": total / span, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+           "sample": f"{procs} independent single-thread oracle processes, each {CPU_SAMPLE_N} spheres of the "
+                     f"dense-bed recipe on its own seeded lattice, about {0.5 * target_seconds:.0f} s each "
+                     f"({wall:.1f} s wall); FP64, built -O3",
+           "cpu": info, "single_core": single}
     # the 4,096-sphere FP64 configuration in full (1,000 steps), for the
-    # GPU/CPU ratio of the paper's kind
+    # GPU/CPU ratio of the paper's kind (one core)
     wp = W.plain_fp64(seed=1000)
     o = OracleSystem(wp["params"], wp["x"], wp["v"], wp["omega"], wp["r"])
     t0 = time.perf_counter()
@@ -212,8 +267,8 @@ def bench_dense(args):
     Z = 2.0 * pairs / n
     R = 4 if p["precision"] == "mixed" else 8
     kernels = {
-        "k_detect": ("detect", detect_bytes(n, ncell, P / n)),
-        "k_pair_force": ("pair_force", pair_force_bytes(n, P, R)),
+        "k_contacts_direct": ("contacts", contacts_bytes(n, ncell, P, R)),
+        "k_gather": ("gather", gather_bytes(n, P, R)),
     }
     name = max(kernels, key=lambda k: phase_ms[kernels[k][0]])
     ph, nbytes = kernels[name]
@@ -237,6 +292,117 @@ def bench_dense(args):
         "step_hbm": {"algorithmic_bytes_per_step": sb, "achieved_GBs": sb / (ms_per_step * 1e-3) / 1e9,
                      "frac": sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    return out
+
+
+# ------------------------------------------------------------ precision
+
+def _force_errors(F, T, Fo, To, Fa, Ta, mask):
+    """Per-particle force and torque errors against the oracle, relative to
+    each particle's contact-force scale (the sum of the magnitudes of its
+    contact forces / torques); particles with contacts in `mask`."""
+    m = mask & (Fa > 0)
+    ef = np.linalg.norm(F - Fo, axis=1)[m] / Fa[m]
+    mt = mask & (Ta > 0)
+    et = np.linalg.norm(T - To, axis=1)[mt] / Ta[mt]
+    q = lambda a, p: float(np.percentile(a, p)) if a.size else None
+    return {"particles": int(m.sum()), "force_max": q(ef, 100), "force_p50": q(ef, 50), "force_p99": q(ef, 99),
+            "torque_max": q(et, 100), "torque_p50": q(et, 50)}
+
+
+def precision_errors(name, w, x, v, om, checkpoints, window=None):
+    """The error of mixed precision (FP32 v, w, forces and history, FP64
+    positions and reductions) stated per result for one workload:
+      trajectory  the same initial state stepped in mixed precision and in FP64
+                  (both on the GPU; the FP64 path tracks the FP64 oracle to
+                  1e-9 in the tests) -- largest position difference, relative
+                  to the largest radius, at each checkpoint
+      diagnostics the FP64 reductions (momentum, kinetic, rotational,
+                  potential and elastic energy) of both runs, their relative
+                  difference at each checkpoint
+      forces      at the last checkpoint, the mixed-precision forces on the
+                  mixed run's own state (positions, velocities, spins and
+                  committed history) against the FP64 oracle's on that same
+                  state, per particle relative to its contact-force scale;
+                  window=(axis, lo, hi, margin): only the particles with
+                  lo <= x_axis < hi go to the oracle, and those at least
+                  `margin` inside the window are compared (all their contacts
+                  lie in it)."""
+    from oracle.oracle import OracleSystem
+    from paper_1301_1714_amd import dem
+
+    r = np.asarray(w["r"])
+    rmax = float(r.max())
+    pm = dict(w["params"], precision="mixed")
+    pf = dict(w["params"], precision="fp64")
+    t0 = time.time()
+    sm = dem.System(pm, x, v, om, r)
+    sf = dem.System(pf, x, v, om, r)
+    traj, diag = [], []
+    done = 0
+    keys = ("momentum", "kinetic", "rotational", "potential", "elastic")
+    for c in checkpoints:
+        sm.step(c - done)
+        sf.step(c - done)
+        done = c
+        a, b = sm.read_state(), sf.read_state()
+        dm, df = sm.diagnostics(), sf.diagnostics()
+        traj.append({"step": c, "x_max_diff_over_rmax": float(np.abs(a["x"] - b["x"]).max() / rmax),
+                     "v_max_diff": float(np.abs(a["v"] - b["v"]).max()), "v_max": float(np.abs(b["v"]).max())})
+        mom = float(np.linalg.norm(dm[:3] - df[:3]) / max(np.linalg.norm(df[:3]), 1e-300))
+        rel = lambda i: float(abs(dm[i] - df[i]) / max(abs(df[i]), 1e-300))
+        diag.append({"step": c, **dict(zip(keys, [mom] + [rel(i) for i in (3, 4, 5, 6)])),
+                     "pairs_mixed": int(dm[7]), "pairs_fp64": int(df[7])})
+    sf.close()
+    del sf
+    st = sm.read_state()
+    pairs, dts = sm.read_contacts()
+    F, T = sm.forces()
+    sm.close()
+    del sm
+    if window is None:
+        sel = np.arange(len(r))
+        inner = np.ones(len(r), bool)
+    else:
+        ax, lo, hi, margin = window
+        sel = np.nonzero((st["x"][:, ax] >= lo) & (st["x"][:, ax] < hi))[0]
+        xa = st["x"][sel, ax]
+        inner = (xa >= lo + margin) & (xa < hi - margin)
+    local = -np.ones(len(r), np.int64)
+    local[sel] = np.arange(len(sel))
+    keep = (local[pairs[:, 0]] >= 0) & ((pairs[:, 1] < 0) | (local[np.maximum(pairs[:, 1], 0)] >= 0))
+    hp = pairs[keep].copy()
+    hp[:, 0] = local[hp[:, 0]]
+    hp[:, 1] = np.where(hp[:, 1] >= 0, local[np.maximum(hp[:, 1], 0)], hp[:, 1])
+    o = OracleSystem(pf, st["x"][sel], st["v"][sel], st["omega"][sel], r[sel], F0=np.zeros((len(sel), 3)),
+                     T0=np.zeros((len(sel), 3)), hist_pairs=hp, hist_dt=dts[keep])
+    Fo, To, Fa, Ta = o.forces_scale()
+    del o
+    out = {"workload": name, "trajectory": traj, "diagnostics": diag,
+           "forces": {"step": done, **_force_errors(F[sel], T[sel], Fo, To, Fa, Ta, inner),
+                      "compared": "all particles" if window is None else
+                      f"{int(inner.sum())} particles at least {window[3]:.4g} m inside a window of {len(sel)}"},
+           "seconds": time.time() - t0}
+    log(f"[bench] precision {name}: forces max {out['forces']['force_max']:.2e}, x diff "
+        f"{traj[-1]['x_max_diff_over_rmax']:.2e} r_max after {done} steps ({out['seconds']:.0f}s)")
+    return out
+
+
+def bench_precision(args):
+    """Mixed precision's error on the 2^20 settling gas (from its seeded start,
+    over 3,000 steps; the oracle takes the whole system) and on the prepared
+    2^24 bed (100 steps; the oracle takes a window of the bed)."""
+    from paper_1301_1714_amd import workloads as W
+
+    out = {}
+    g = W.gas_mixed(seed=2000)
+    out["gas_2^20"] = precision_errors("gas_2^20", g, g["x"], g["v"], g["omega"], (10, 100, 1000, 3000))
+    if _DENSE:
+        w = _DENSE["w"]
+        cell = float(w["params"]["cell_size"])
+        mid = 0.5 * float(w["params"]["box_hi"][0])
+        out["dense_2^24"] = precision_errors("dense_2^24", w, _DENSE["x"], _DENSE["v"], _DENSE["omega"], (10, 100),
+                                             window=(0, mid - 0.03, mid + 0.03, 1.5 * cell))
     return out
 
 
@@ -436,6 +602,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the FP64 4,096 and the 2^20 gas runs")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the mixed-precision error statement (gas and bed against FP64 and the oracle)")
     ap.add_argument("--gas-steps", type=int, default=10000)
     ap.add_argument("--dense-law-steps", type=int, default=100)
     ap.add_argument("--batch-systems", type=int, default=256)
@@ -456,6 +624,10 @@ def main():
                     help="run only the batched workload and print its record (a profile of the batch)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (profiler counter calibration)")
+    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-worker":
+        work, dt, k, _ = oracle_sample(int(sys.argv[2]), float(sys.argv[3]))
+        print(json.dumps({"work": work, "seconds": dt, "steps": k}), flush=True)
+        return
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -478,6 +650,8 @@ def main():
     log(f"[bench] dense bed: {out['value']:.4g} particle-steps/s, {out['ms_per_step']:.3f} ms/step")
     if not (args.no_configs or args.only_dense):
         out["configs"] = bench_configs(args)
+    if not (args.no_precision or args.only_dense):
+        out["precision_errors"] = bench_precision(args)
     if not (args.no_batched or args.only_dense):
         out["batched"] = bench_batched(args)
         log(f"[bench] batched: {out['batched']['value']:.4g} particle-steps/s "

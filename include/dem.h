@@ -55,7 +55,8 @@ typedef enum {
 typedef enum {
     DEM_LAW_LINEAR = 0, /* Eqs. 2-7, 10 with constant kn, kt */
     DEM_LAW_HERTZ = 1,  /* Eqs. 2-10: kn, kt are C_kn, C_kt of Eqs. 8-9 */
-    DEM_LAW_SIMPLE = 2  /* Eq. 1: F = -k_sp d n - k_da v - k_sh v_t, no torque, no history */
+    DEM_LAW_SIMPLE = 2  /* Eq. 1: F = -k_sp d n - k_da v - k_sh v_t with v_t = v - (v.n) n (the
+                           tangential part of v, Sec. 3), no torque, no history */
 } dem_law;
 
 typedef enum {
@@ -78,10 +79,12 @@ typedef struct {
     double mu;                   /* Coulomb coefficient (Eq. 5), >= 0 */
     double simple_k[3];          /* k_sp, k_da, k_sh of Eq. 1 (DEM_LAW_SIMPLE only) */
     double cell_size;            /* requested cell width (Sec. 4.1), >= 2 max radius */
-    int32_t contacts_per_particle; /* contact-list capacity: n * this many contacts (each pair
-                                      once, plus wall contacts) may be held; 1..64.  In the
-                                      sorted order a particle may touch at most 64 partners
-                                      after it (walls included) and 32 before it */
+    int32_t contacts_per_particle; /* capacity of the contact lists, 1..64: the most contacts one
+                                      particle may own -- partners after it in the sorted order
+                                      (each pair is owned by its lower slot) plus its walls.  In
+                                      the sorted order a particle may also touch at most 32
+                                      partners before it.  Device memory grows with it (about
+                                      this many x 84 bytes per particle in mixed precision) */
     int32_t precision;           /* dem_precision */
     int32_t tile_cells;          /* detection launch shape: 0 = one lane per particle reading
                                     neighbours through the caches; -1 = one wave64 per run
@@ -179,15 +182,15 @@ dem_status dem_set_radii(dem_system *s, const double *r);
  * the stream, returns the milliseconds spent in each phase summed over the
  * steps timed since the previous read (and their number), then clears them.
  * Phases: 0 kick-drift-hash of a call's first step (Steps 1-2; later steps
- * do it inside phase 6), 1 sort and cell starts (Step 3), 2 reorder
- * (Step 4), 3 contact detection over the neighbouring cells (Steps 5-6),
- * 4 compact contact array and its backward index, 5 contact law once per
- * contact (Steps 7-8), 6 per-particle sums, closing kick and the next
- * step's kick-drift-hash.  Phases 3 and 5 are one kernel each (detection:
- * one per launch shape in use).  With graph replay the whole step after
- * phase 0 is counted in phase 6.  At most DEM_PROFILE_CAPACITY steps are
- * timed between two reads. */
-#define DEM_NUM_PHASES 7
+ * do it inside phase 5), 1 sort and cell starts (Step 3), 2 reorder
+ * (Step 4), 3 contact detection over the neighbouring cells (Steps 5-6 and
+ * 8) with, for the direct launch shape, the contact law of each owned
+ * contact in the same kernel (Step 7), 4 the contact-law pass of the systems
+ * swept by the other launch shapes (empty otherwise), 5 per-particle sums,
+ * closing kick and the next step's kick-drift-hash.  With graph replay the
+ * whole step after phase 0 is counted in phase 5.  At most
+ * DEM_PROFILE_CAPACITY steps are timed between two reads. */
+#define DEM_NUM_PHASES 6
 #define DEM_PROFILE_CAPACITY 4096
 dem_status dem_profile(dem_system *s, int enable);
 dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *steps);
@@ -224,12 +227,22 @@ typedef struct dem_batch dem_batch;
 /* Device bytes for systems k = 0..n_sys-1 of n[k] particles, parameters p[k]. */
 dem_status dem_batch_workspace_bytes(int32_t n_sys, const dem_params *p, const int64_t *n, size_t *bytes);
 
-/* Create a batch (no initial history; forces evaluated on the given state).
- * Synchronous.  Errors as dem_create, plus DEM_E_INVALID when the systems'
- * laws or precisions differ. */
+/* Create a batch from the systems' host arrays, concatenated in system order
+ * (each as dem_create would take it).  F0, T0 (sum(n) x 3, or both NULL) and
+ * the tangential history restart the systems exactly: n_hist[k] keys of
+ * system k (ids local to it) follow those of system k - 1 in hist_pairs
+ * (2 each) and hist_dt (3 each); n_hist NULL for none.  Synchronous.  Errors
+ * as dem_create, plus DEM_E_INVALID when the systems' laws or precisions
+ * differ. */
 dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n, const double *x,
-                            const double *v, const double *omega, const double *r, void *workspace,
-                            size_t ws_bytes, void *hip_stream, dem_batch **out);
+                            const double *v, const double *omega, const double *r, const double *F0,
+                            const double *T0, const int64_t *n_hist, const int64_t *hist_pairs,
+                            const double *hist_dt, void *workspace, size_t ws_bytes, void *hip_stream,
+                            dem_batch **out);
+
+/* dem_set_radii for every system of the batch: r holds sum(n) radii,
+ * concatenated in system order.  Synchronous. */
+dem_status dem_batch_set_radii(dem_batch *b, const double *r);
 
 /* Advance system k by steps[k] >= 0 steps (0: it does not move).  The batch
  * runs max(steps) steps; a system that has done its steps stays unchanged

@@ -7,6 +7,7 @@
 // synchronous read-back calls, which return everything in the caller's
 // original particle order.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -33,10 +34,11 @@ struct Engine {
   std::vector<dem_params> params;
   std::vector<SysInfo> info;  // host copy of the system table
   std::vector<int32_t> bsys_h, bfirst_h;
+  std::vector<int32_t> psys_h;  // system of each slot
   std::vector<int4> tiles_h;  // detection work items
   std::vector<int4> runs_h;   // wave detection work items
   int64_t ncell = 0;  // cells of all systems
-  int64_t Pcap = 0;
+  int32_t K = 1;      // owned contacts per particle at most (largest contacts_per_particle)
   // device
   SysInfo *tab = nullptr;
   int32_t *psys = nullptr, *bsys = nullptr, *bfirst = nullptr;
@@ -50,13 +52,12 @@ struct Engine {
   VelBuf vel[2];
   int cp = 0, cv = 0;  // current position / velocity buffers
   int gc = 0;          // generation holding the committed tangential history
-  int gs = 0;          // generation holding the contact list of the current positions
   void *F[3], *T[3], *Fe[3], *Te[3];
   int32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *scell = nullptr, *counts = nullptr,
           *cell_start = nullptr;
   ScanScratch scan{};
   NbrBuf nbr{};
-  PairGen gen[2];
+  HistGen hist[2];
   PairWork work{};
   DiagBuf diag{};
   int32_t *err = nullptr;
@@ -179,7 +180,8 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   e.info.assign(S, SysInfo{});
   e.prec = p[0].precision;
   e.law = p[0].law;
-  int64_t ntot = 0, ctot = 0, pcap = 0;
+  int64_t ntot = 0, ctot = 0;
+  e.K = 1;
   e.bsys_h.clear();
   e.bfirst_h.clear();
   e.tiles_h.clear();
@@ -195,6 +197,8 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     fill_consts(p[k], si.c);
     si.eps = prefilter_eps(si.g, p[k].cell_size);
     si.reach = p[k].cell_divisor;
+    si.kcap = p[k].contacts_per_particle;
+    e.K = std::max(e.K, si.kcap);
     si.p0 = (int32_t)ntot;
     si.n = (int32_t)n[k];
     si.g.c0 = (int32_t)ctot;
@@ -223,13 +227,10 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     }
     ntot += n[k];
     ctot += si.g.ncell;
-    pcap += (int64_t)p[k].contacts_per_particle * n[k];
-    if (ntot > kMaxParticles || ctot >= (int64_t)INT32_MAX - 1 || pcap >= (int64_t)INT32_MAX)
-      return DEM_E_INVALID;
+    if (ntot > kMaxParticles || ctot >= (int64_t)INT32_MAX - 1) return DEM_E_INVALID;
   }
   e.n = (int32_t)ntot;
   e.ncell = ctot;
-  e.Pcap = std::max<int64_t>(pcap, 256);
   e.rsz = e.prec == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
   e.left_h.assign(S, 0);
   return DEM_OK;
@@ -240,7 +241,7 @@ size_t carve(Engine &e, char *base) {
   Carver cv{base};
   const size_t N = (size_t)(e.n > 0 ? e.n : 1);
   const size_t R = e.rsz;
-  const size_t P = (size_t)e.Pcap;
+  const size_t P = (size_t)e.K * N;  // owned-contact entries [K][N]
   const size_t S = (size_t)e.S;
   const size_t B = std::max<size_t>(e.bsys_h.size(), 1);
   e.tab = cv.take<SysInfo>(S);
@@ -272,7 +273,7 @@ size_t carve(Engine &e, char *base) {
   e.cell_start = cv.take<int32_t>((size_t)e.ncell + 1);
   int64_t lens[4] = {0, 0, 0, 0};
   int nl = 0;
-  scan_scratch_len(std::max<int64_t>(e.ncell, (int64_t)N), lens, &nl);
+  scan_scratch_len(e.ncell, lens, &nl);
   e.scan.nlevels = nl;
   for (int l = 0; l < 4; l++) {
     e.scan.len[l] = lens[l];
@@ -282,12 +283,11 @@ size_t carve(Engine &e, char *base) {
   e.nbr.xq = cv.take<uint2>(N + 1);  // one pad record: detection loads records in pairs
   e.nbr.fcnt = cv.take<int32_t>(N);
   e.nbr.pst = cv.take_bytes((e.prec == DEM_PREC_FP64 ? sizeof(PState<double>) : sizeof(PState<float>)) * N);
-  e.nbr.nb = cv.take<int32_t>((size_t)kListCap * N);
+  e.nbr.nb = cv.take<int32_t>(P);
+  e.nbr.K = e.K;
   for (int b = 0; b < 2; b++) {
-    e.gen[b].ofs = cv.take<int32_t>(N + 1);
-    e.gen[b].s = cv.take<int32_t>(P);
-    e.gen[b].t = cv.take<int32_t>(P);
-    e.gen[b].ent = cv.take_bytes(4 * R * P);
+    e.hist[b].cnt = cv.take<int32_t>(N);
+    e.hist[b].ent = cv.take_bytes(4 * R * P);
   }
   e.work.pf = cv.take_bytes(6 * R * P);
   e.work.pe = cv.take<double>(P);
@@ -311,12 +311,21 @@ dem_status map_err(int32_t bits) {
   return DEM_OK;
 }
 
-#define HIP_TRY(expr)           \
-  do {                          \
-    if ((expr) != hipSuccess) { \
-      (void)hipGetLastError();  \
-      return DEM_E_HIP;         \
-    }                           \
+// With DEM_DEBUG set in the environment, a failed HIP call is named on
+// stderr (the status code alone does not say which call failed).
+void report_hip(hipError_t r, const char *expr, int line) {
+  static const bool on = getenv("DEM_DEBUG") != nullptr;
+  if (on) fprintf(stderr, "libdem: %s (line %d) failed: %s\n", expr, line, hipGetErrorString(r));
+}
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    const hipError_t hip_r_ = (expr);      \
+    if (hip_r_ != hipSuccess) {            \
+      report_hip(hip_r_, #expr, __LINE__); \
+      (void)hipGetLastError();             \
+      return DEM_E_HIP;                    \
+    }                                      \
   } while (0)
 
 // Wait for the stream and fold the device error flags into the sticky status.
@@ -385,29 +394,25 @@ void gather3(const double *src, const std::vector<int32_t> &id_at_slot, int k, s
   for (size_t s = 0; s < id_at_slot.size(); s++) out[s] = src[3 * (size_t)id_at_slot[s] + k];
 }
 
-// Steps 5-6 on the current positions into generation g (with ctl only the
-// systems still stepping detect again; the others keep their lists)
-hipError_t build_contacts(Engine &e, int g, const StepCtl *ctl, hipEvent_t after_detect = nullptr,
-                          bool write_keys = true) {
-  e.gs = g;
-  const Layout L = e.layout();
-  hipError_t r = launch_detect(e.prec, L, ctl, e.nbr, e.scell, e.cell_start, e.err, e.stream);
-  if (r != hipSuccess) return r;
-  if (after_detect) (void)hipEventRecord(after_detect, e.stream);
-  return launch_list(e.prec, L, e.nbr, e.gen[g], e.work, e.Pcap, write_keys, e.scan, e.err, e.stream);
+// Steps 5-8 detection on the current positions: the owned-contact lists
+// (with ctl only the systems still stepping detect again; the others keep
+// their lists)
+hipError_t build_contacts(Engine &e, const StepCtl *ctl) {
+  return launch_contacts(e.prec, e.layout(), ctl, e.nbr, e.scell, e.cell_start, nullptr, e.err, e.stream, nullptr);
 }
 
-// Steps 7-8 once per contact, then the per-particle sums (and, in a time
-// step, the kicks)
-hipError_t run_forces(Engine &e, const PairArgs &a, hipEvent_t after_law = nullptr) {
-  hipError_t r = launch_pair_force(e.prec, a, e.stream);
+// Steps 5-8 with the contact law (in the detection pass for the direct
+// shape), then the per-particle sums (and, in a time step, the kicks)
+hipError_t run_forces(Engine &e, const PairArgs &a, const StepCtl *ctl, hipEvent_t after_detect = nullptr,
+                      hipEvent_t after_law = nullptr) {
+  hipError_t r = launch_contacts(e.prec, a.L, ctl, e.nbr, e.scell, e.cell_start, &a, e.err, e.stream, after_detect);
   if (r != hipSuccess) return r;
   if (after_law) (void)hipEventRecord(after_law, e.stream);
   return launch_gather(e.prec, a, e.stream);
 }
 
-// Steps 7-8 on the contact list of generation gs, with the committed history
-// of generation gc
+// Steps 7-8 on the current positions with the committed history of
+// generation gc; a time step writes the new history into the other one
 PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   PairArgs a;
   memset(&a, 0, sizeof(a));
@@ -418,10 +423,9 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.vel_in = e.vel[e.cv];
   a.vel_out = e.vel[e.cv ^ 1];
   a.nb = e.nbr;
-  a.cur = e.gen[e.gs];
-  a.old = e.gen[e.gc];
+  a.cur = e.hist[e.gc ^ 1];
+  a.old = e.hist[e.gc];
   a.w = e.work;
-  a.cap = e.Pcap;
   for (int k = 0; k < 3; k++) {
     a.F[k] = F[k];
     a.T[k] = T[k];
@@ -440,19 +444,17 @@ struct Entry {
   double d[3];
 };
 
-// The contacts of system k in a generation as sorted (a, b) keys with ids
-// local to the system: (lower id, higher id) for a pair, (id, -1 - w) for a
-// wall; with_d also reads delta_t, turned to the view of the lower id.
-// entries [q0, q1) of a history table: keys and delta_t
-dem_status read_entries(Engine &e, const PairGen &g, size_t q0, size_t q1, std::vector<int32_t> &key,
-                        std::vector<double> &d) {
-  const size_t m = q1 - q0;
-  key.assign(m, 0);
+// Rows [0, kmax) of a [K][N] history table: delta_t (3 per entry, as
+// doubles) and the keys (the bits of each entry's w)
+dem_status read_hist_rows(Engine &e, const void *src, int32_t kmax, std::vector<double> &d,
+                          std::vector<int32_t> &key) {
+  const size_t N = (size_t)e.n, m = (size_t)kmax * N;
   d.assign(3 * m, 0.0);
+  key.assign(m, 0);
   if (m == 0) return DEM_OK;
   if (e.prec == DEM_PREC_FP64) {
     std::vector<double> raw(4 * m);
-    HIP_TRY(hipMemcpyAsync(raw.data(), (const double *)g.ent + 4 * q0, 32 * m, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipMemcpyAsync(raw.data(), src, 32 * m, hipMemcpyDeviceToHost, e.stream));
     HIP_TRY(hipStreamSynchronize(e.stream));
     for (size_t q = 0; q < m; q++) {
       int64_t bits;
@@ -462,7 +464,7 @@ dem_status read_entries(Engine &e, const PairGen &g, size_t q0, size_t q1, std::
     }
   } else {
     std::vector<float> raw(4 * m);
-    HIP_TRY(hipMemcpyAsync(raw.data(), (const float *)g.ent + 4 * q0, 16 * m, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipMemcpyAsync(raw.data(), src, 16 * m, hipMemcpyDeviceToHost, e.stream));
     HIP_TRY(hipStreamSynchronize(e.stream));
     for (size_t q = 0; q < m; q++) {
       memcpy(&key[q], &raw[4 * q + 3], 4);
@@ -472,37 +474,42 @@ dem_status read_entries(Engine &e, const PairGen &g, size_t q0, size_t q1, std::
   return DEM_OK;
 }
 
-// The contacts of system k in a table as sorted (a, b) keys with ids local
-// to the system: (lower id, higher id) for a pair, (id, -1 - w) for a wall;
-// with_d also returns delta_t, turned to the view of the lower id.
-dem_status read_gen(Engine &e, const PairGen &g, int32_t k, bool with_d, std::vector<Entry> &out) {
+// The contacts of system k as sorted (a, b) keys with ids local to the
+// system: (lower id, higher id) for a pair, (id, -1 - w) for a wall.
+// committed: the tangential history (with delta_t, turned to the view of the
+// lower id); otherwise the owned-contact lists of the current positions.
+dem_status read_gen(Engine &e, int32_t k, bool committed, std::vector<Entry> &out) {
   out.clear();
   const SysInfo &si = e.info[k];
   if (si.n == 0) return DEM_OK;
   const size_t N = (size_t)e.n;
-  std::vector<int32_t> ofs, key, id;
-  std::vector<double> d;
+  std::vector<int32_t> cnt, id, nb;
   dem_status st;
-  if ((st = d2h(e, (const int32_t *)g.ofs, ofs, N + 1)) != DEM_OK) return st;
-  const size_t P = (size_t)std::min<int64_t>(ofs[N], e.Pcap);
-  // a system's contacts are owned by its own slots: one contiguous range
-  const size_t q0 = std::min<size_t>((size_t)ofs[si.p0], P);
-  const size_t q1 = std::min<size_t>((size_t)ofs[si.p0 + si.n], P);
-  if ((st = read_entries(e, g, q0, q1, key, d)) != DEM_OK) return st;
+  if ((st = d2h(e, committed ? e.hist[e.gc].cnt : e.nbr.fcnt, cnt, N)) != DEM_OK) return st;
+  int32_t kmax = 0;
+  for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++)
+    kmax = std::max(kmax, std::min(std::max(cnt[slot], 0), e.K));
+  std::vector<double> rows;
+  std::vector<int32_t> keys;
+  if (committed) {
+    if ((st = read_hist_rows(e, e.hist[e.gc].ent, kmax, rows, keys)) != DEM_OK) return st;
+  } else if ((st = d2h(e, (const int32_t *)e.nbr.nb, nb, (size_t)kmax * N)) != DEM_OK) {
+    return st;
+  }
   if ((st = d2h(e, (const int32_t *)e.pos[e.cp].id, id, N)) != DEM_OK) return st;
-  out.reserve(q1 - q0);
   for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++) {
-    const size_t e0 = std::min<size_t>((size_t)ofs[slot], P), e1 = std::min<size_t>((size_t)ofs[slot + 1], P);
-    for (size_t q = e0; q < e1; q++) {
+    const int32_t c = std::min(std::max(cnt[slot], 0), e.K);
+    for (int32_t j = 0; j < c; j++) {
+      const size_t q = (size_t)j * N + slot;
       Entry en;
       const int64_t me = id[slot] - si.p0;
-      const int32_t other = key[q - q0];
+      const int32_t other = committed ? keys[q] : nb[q];
       const bool pair = other >= 0;
       const int64_t them = pair ? id[other] - si.p0 : other;
       en.a = pair ? std::min(me, them) : me;
       en.b = pair ? std::max(me, them) : them;
       const double sg = (pair && me > them) ? -1.0 : 1.0;  // stored as seen from the owner slot
-      for (int c = 0; c < 3; c++) en.d[c] = with_d ? sg * d[3 * (q - q0) + c] : 0.0;
+      for (int c3 = 0; c3 < 3; c3++) en.d[c3] = committed ? sg * rows[3 * q + c3] : 0.0;
       out.push_back(en);
     }
   }
@@ -578,7 +585,9 @@ dem_status validate_inputs(Engine &e, const double *x, const double *v, const do
 }
 
 // The given history becomes generation 0: each contact filed under the lower
-// slot of its pair (the particle for a wall) with delta_t seen from it.
+// slot of its pair (the particle for a wall) with delta_t seen from it, at
+// [k * N + owner] for its k-th entry (keys ascending), with the owners'
+// counts.  More entries for one particle than its capacity is an overflow.
 dem_status upload_history(Engine &e, const HistIn &hist, const std::vector<int32_t> &id_at_slot) {
   const size_t N = (size_t)e.n;
   struct Rec {
@@ -612,28 +621,36 @@ dem_status upload_history(Engine &e, const HistIn &hist, const std::vector<int32
     for (size_t k = 1; k < recs.size(); k++)
       if (recs[k].owner == recs[k - 1].owner && recs[k].key == recs[k - 1].key) return DEM_E_INVALID;
   }
-  if ((int64_t)recs.size() > e.Pcap) return DEM_E_CONTACT_OVERFLOW;
-  std::vector<int32_t> ofs(N + 1, 0);
-  for (const Rec &rc : recs) ofs[rc.owner + 1]++;
-  for (size_t k = 0; k < N; k++) ofs[k + 1] += ofs[k];
-  const PairGen &g0 = e.gen[0];
+  std::vector<int32_t> cnt(N, 0);
+  for (const Rec &rc : recs) cnt[rc.owner]++;
+  int32_t kmax = 0;
+  for (size_t sl = 0; sl < N; sl++) {
+    const int32_t k = e.psys_h[sl];
+    if (cnt[sl] > e.info[k].kcap) return DEM_E_CONTACT_OVERFLOW;
+    kmax = std::max(kmax, cnt[sl]);
+  }
+  const HistGen &g0 = e.hist[0];
   dem_status st;
-  if ((st = h2d(e, g0.ofs, ofs)) != DEM_OK) return st;
+  if ((st = h2d(e, g0.cnt, cnt)) != DEM_OK) return st;
   if (recs.empty()) return DEM_OK;
-  // entries: delta_t in x, y, z, the key's bits in w
+  // entries: delta_t in x, y, z, the key's bits in w; rows 0 .. kmax - 1
+  const size_t m = (size_t)kmax * N;
+  std::vector<int32_t> pos(N, 0);
   if (e.prec == DEM_PREC_FP64) {
-    std::vector<double> raw(4 * recs.size());
-    for (size_t k = 0; k < recs.size(); k++) {
-      for (int c = 0; c < 3; c++) raw[4 * k + c] = recs[k].d[c];
-      const int64_t bits = (int64_t)recs[k].key;
-      memcpy(&raw[4 * k + 3], &bits, 8);
+    std::vector<double> raw(4 * m, 0.0);
+    for (const Rec &rc : recs) {
+      const size_t q = (size_t)pos[rc.owner]++ * N + (size_t)rc.owner;
+      for (int c = 0; c < 3; c++) raw[4 * q + c] = rc.d[c];
+      const int64_t bits = (int64_t)rc.key;
+      memcpy(&raw[4 * q + 3], &bits, 8);
     }
     return h2d(e, (double *)g0.ent, raw);
   }
-  std::vector<float> raw(4 * recs.size());
-  for (size_t k = 0; k < recs.size(); k++) {
-    for (int c = 0; c < 3; c++) raw[4 * k + c] = (float)recs[k].d[c];
-    memcpy(&raw[4 * k + 3], &recs[k].key, 4);
+  std::vector<float> raw(4 * m, 0.0f);
+  for (const Rec &rc : recs) {
+    const size_t q = (size_t)pos[rc.owner]++ * N + (size_t)rc.owner;
+    for (int c = 0; c < 3; c++) raw[4 * q + c] = (float)rc.d[c];
+    memcpy(&raw[4 * q + 3], &rc.key, 4);
   }
   return h2d(e, (float *)g0.ent, raw);
 }
@@ -648,6 +665,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   std::vector<int32_t> psys(N);
   for (int32_t k = 0; k < e.S; k++)
     for (int32_t i = 0; i < e.info[k].n; i++) psys[(size_t)e.info[k].p0 + i] = k;
+  e.psys_h = psys;
   HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo) * e.info.size(), hipMemcpyHostToDevice, e.stream));
   HIP_TRY(hipStreamSynchronize(e.stream));
   if ((st = h2d(e, e.psys, psys)) != DEM_OK || (st = h2d(e, e.bsys, e.bsys_h)) != DEM_OK ||
@@ -679,8 +697,10 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   e.cp = 1;
   e.cv = 1;
   e.gc = 0;
-  // Steps 5-6: the contacts of the initial positions go to generation 1
-  HIP_TRY(build_contacts(e, 1, nullptr));
+  // no backward entries are filed yet (each gather clears what it read)
+  HIP_TRY(launch_fill(e.work.bcnt, e.n, 0, e.stream));
+  // Steps 5-6: the contacts of the initial positions
+  HIP_TRY(build_contacts(e, nullptr));
   if ((st = sync_and_check(e)) != DEM_OK) return st;
   std::vector<int32_t> id_at_slot;
   if ((st = d2h(e, e.pos[1].id, id_at_slot, N)) != DEM_OK) return st;
@@ -695,7 +715,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
     }
   } else {
     PairArgs a = pair_args(e, 0, e.F, e.T);
-    HIP_TRY(run_forces(e, a));
+    HIP_TRY(run_forces(e, a, nullptr));
   }
   return sync_and_check(e);
 }
@@ -718,6 +738,9 @@ dem_status engine_create(int32_t S, const dem_params *p, const int64_t *n, const
     return st;
   }
   e->stream = (hipStream_t)hip_stream;
+  // an error another library left on this thread is not ours: the launches
+  // below check hipGetLastError after each kernel
+  (void)hipGetLastError();
   carve(*e, (char *)workspace);
   st = engine_init(*e, x, v, omega, rf, F0, T0, hist);
   if (st != DEM_OK) {
@@ -732,9 +755,9 @@ dem_status engine_create(int32_t S, const dem_params *p, const int64_t *n, const
 
 // Steps 3-8 of one time step.  Steps 1-2 (opening kick, drift, hash) run
 // before the first step of a call and, after that, inside the previous
-// step's force pass for every system that steps again.  The reorder moves
-// the state to the other buffers and the force pass moves it back, so a
-// step starts from the same buffers every time.
+// step's gather for every system that steps again.  The reorder moves the
+// state to the other buffers and the gather moves it back, so a step starts
+// from the same buffers every time.
 hipError_t step_body(Engine &e, hipEvent_t *ev) {
   auto mark = [&](int phase) {
     if (ev) (void)hipEventRecord(ev[phase], e.stream);
@@ -749,26 +772,20 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   // Step 4
   // (the state goes into the packed records only; the gather writes it back)
   if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], false, e.perm,
-                          e.cell, e.scell, e.nbr, e.gen[e.gc].ofs, e.stream)) != hipSuccess)
+                          e.cell, e.scell, e.nbr, e.hist[e.gc].cnt, e.stream)) != hipSuccess)
     return r;
   e.cp ^= 1;
   e.cv ^= 1;
   mark(3);
-  // Steps 5-6; the new history table is the generation that does not hold
-  // the committed one
-  // (with a law that keeps history, the law pass writes every entry, key
-  // included, so the list pass leaves the keys out)
-  if ((r = build_contacts(e, e.gc ^ 1, &e.ctl, ev ? ev[4] : nullptr, e.law == DEM_LAW_SIMPLE)) != hipSuccess)
-    return r;
-  mark(5);
-  // Steps 7-8 and the closing half kick; the new history is committed
+  // Steps 5-8 and the closing half kick; the new history goes into the
+  // generation that does not hold the committed one, and is committed
   PairArgs a = pair_args(e, MODE_WRITE_HIST | MODE_KICK | MODE_OLD_PERM, e.F, e.T);
-  if ((r = run_forces(e, a, ev ? ev[6] : nullptr)) != hipSuccess) return r;
+  if ((r = run_forces(e, a, &e.ctl, ev ? ev[4] : nullptr, ev ? ev[5] : nullptr)) != hipSuccess) return r;
   if ((r = launch_step_end(e.ctl, e.stream)) != hipSuccess) return r;
-  mark(7);
+  mark(6);
   e.cp ^= 1;
   e.cv ^= 1;
-  e.gc = e.gs;
+  e.gc ^= 1;
   return hipSuccess;
 }
 
@@ -776,7 +793,7 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
 // of every launch is fixed by (cp, cv, gc); cp and cv are the same at the
 // start of every step, so one graph per gc replays every later step.
 dem_status capture(Engine &e) {
-  const int cp = e.cp, cv = e.cv, gc = e.gc, gs = e.gs;
+  const int cp = e.cp, cv = e.cv, gc = e.gc;
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
   const hipError_t r = step_body(e, nullptr);
@@ -784,7 +801,6 @@ dem_status capture(Engine &e) {
   e.cp = cp;
   e.cv = cv;
   e.gc = gc;
-  e.gs = gs;
   if (r != hipSuccess || r2 != hipSuccess || !graph) {
     (void)hipGetLastError();
     if (graph) (void)hipGraphDestroy(graph);
@@ -811,6 +827,7 @@ dem_status engine_step(Engine &e, const int64_t *steps) {
     maxs = std::max(maxs, steps[k]);
   }
   if (maxs == 0) return DEM_OK;
+  (void)hipGetLastError();  // not ours (see engine_create)
   // the previous call's upload of left[] must have been read before the
   // host array is overwritten
   if (e.left_pending && hipEventSynchronize(e.left_ev) != hipSuccess) return e.sticky = DEM_E_HIP;
@@ -851,8 +868,7 @@ dem_status engine_step(Engine &e, const int64_t *steps) {
       }
       if (ev) (void)hipEventRecord(ev[DEM_NUM_PHASES], e.stream);
       // what the replayed body does to the indices (cp and cv come back)
-      e.gs = e.gc ^ 1;
-      e.gc = e.gs;
+      e.gc ^= 1;
     } else if (step_body(e, ev) != hipSuccess) {
       (void)hipGetLastError();
       return e.sticky = DEM_E_HIP;
@@ -874,7 +890,7 @@ dem_status engine_forces(Engine &e, double *F, double *T) {
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, 0, e.Fe, e.Te);
   if (launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream) != hipSuccess ||
-      run_forces(e, a) != hipSuccess) {
+      run_forces(e, a, nullptr) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;
   }
@@ -928,9 +944,7 @@ dem_status engine_read_contacts(Engine &e, int32_t k, bool committed, int64_t ca
   dem_status st = sync_and_check(e);
   if (st != DEM_OK) return st;
   std::vector<Entry> ent;
-  if (!(committed && e.law == DEM_LAW_SIMPLE) &&
-      (st = read_gen(e, e.gen[committed ? e.gc : e.gs], k, committed, ent)) != DEM_OK)
-    return st;
+  if (!(committed && e.law == DEM_LAW_SIMPLE) && (st = read_gen(e, k, committed, ent)) != DEM_OK) return st;
   *n_out = (int64_t)ent.size();
   if ((int64_t)ent.size() > cap) return DEM_E_CAPACITY;
   for (size_t q = 0; q < ent.size(); q++) {
@@ -949,7 +963,7 @@ dem_status engine_diagnostics(Engine &e, double *out) {
   if (st != DEM_OK) return st;
   PairArgs a = pair_args(e, MODE_DIAG, e.Fe, e.Te);
   if (launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream) != hipSuccess ||
-      run_forces(e, a) != hipSuccess ||
+      run_forces(e, a, nullptr) != hipSuccess ||
       launch_diag_reduce(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.diag, e.stream) != hipSuccess) {
     (void)hipGetLastError();
     return e.sticky = DEM_E_HIP;
@@ -959,6 +973,42 @@ dem_status engine_diagnostics(Engine &e, double *out) {
   if ((st = d2h(e, (const double *)e.diag.out, o, 10 * (size_t)e.S)) != DEM_OK) return st;
   memcpy(out, o.data(), o.size() * sizeof(double));
   return DEM_OK;
+}
+
+// Replace the radii of every system (the engine's original order: systems
+// concatenated), then rebuild the contact list beside the committed history.
+dem_status engine_set_radii(Engine &e, const double *r) {
+  if (e.n > 0 && !r) return DEM_E_INVALID;
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  const size_t N = (size_t)e.n;
+  std::vector<float> rf(N);
+  std::vector<SysInfo> info = e.info;
+  for (int32_t k = 0; k < e.S; k++) {
+    double rmax = 0.0;
+    for (int64_t i = info[k].p0; i < (int64_t)info[k].p0 + info[k].n; i++) {
+      const float q = (float)r[i];
+      if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
+      rf[i] = q;
+      rmax = std::max(rmax, (double)q);
+    }
+    if (e.params[k].cell_size < 2.0 * rmax) return DEM_E_INVALID;
+    info[k].rmax = (float)rmax;
+  }
+  if (N == 0) return DEM_OK;
+  e.info = info;
+  HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo) * e.info.size(), hipMemcpyHostToDevice, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  std::vector<int32_t> id;
+  if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
+  std::vector<float> slot_r(N);
+  for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
+  if ((st = h2d(e, e.pos[e.cp].r, slot_r)) != DEM_OK) return st;
+  HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr, e.stream));
+  HIP_TRY(launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream));
+  // the contact list of the new radii, beside the committed history
+  HIP_TRY(build_contacts(e, nullptr));
+  return sync_and_check(e);
 }
 
 dem_status engine_profile(Engine &e, int enable) {
@@ -1125,34 +1175,7 @@ dem_status dem_diagnostics(dem_system *s, double out[10]) {
 
 dem_status dem_set_radii(dem_system *s, const double *r) {
   if (!s) return DEM_E_STATE;
-  Engine &e = *s->e;
-  if (e.n > 0 && !r) return DEM_E_INVALID;
-  dem_status st = sync_and_check(e);
-  if (st != DEM_OK) return st;
-  const size_t N = (size_t)e.n;
-  std::vector<float> rf(N);
-  double rmax = 0.0;
-  for (size_t i = 0; i < N; i++) {
-    const float q = (float)r[i];
-    if (!(q > 0.0f) || !isfinite(q)) return DEM_E_INVALID;
-    rf[i] = q;
-    rmax = std::max(rmax, (double)q);
-  }
-  if (e.params[0].cell_size < 2.0 * rmax) return DEM_E_INVALID;
-  if (N == 0) return DEM_OK;
-  e.info[0].rmax = (float)rmax;
-  HIP_TRY(hipMemcpyAsync(e.tab, e.info.data(), sizeof(SysInfo), hipMemcpyHostToDevice, e.stream));
-  HIP_TRY(hipStreamSynchronize(e.stream));
-  std::vector<int32_t> id;
-  if ((st = d2h(e, e.pos[e.cp].id, id, N)) != DEM_OK) return st;
-  std::vector<float> slot_r(N);
-  for (size_t k = 0; k < N; k++) slot_r[k] = rf[id[k]];
-  if ((st = h2d(e, e.pos[e.cp].r, slot_r)) != DEM_OK) return st;
-  HIP_TRY(launch_xyzr(e.layout(), e.pos[e.cp], e.nbr, e.stream));
-  HIP_TRY(launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream));
-  // the contact list of the new radii, beside the committed history
-  HIP_TRY(build_contacts(e, e.gc ^ 1, nullptr));
-  return sync_and_check(e);
+  return engine_set_radii(*s->e, r);
 }
 
 dem_status dem_profile(dem_system *s, int enable) {
@@ -1185,13 +1208,41 @@ dem_status dem_batch_workspace_bytes(int32_t n_sys, const dem_params *p, const i
 }
 
 dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n, const double *x,
-                            const double *v, const double *omega, const double *r, void *workspace,
-                            size_t ws_bytes, void *hip_stream, dem_batch **out) {
+                            const double *v, const double *omega, const double *r, const double *F0,
+                            const double *T0, const int64_t *n_hist, const int64_t *hist_pairs,
+                            const double *hist_dt, void *workspace, size_t ws_bytes, void *hip_stream,
+                            dem_batch **out) {
   if (!out) return DEM_E_INVALID;
   *out = nullptr;
+  if ((F0 == nullptr) != (T0 == nullptr) || n_sys < 1 || !n) return DEM_E_INVALID;
+  // the systems' history keys (local ids) become keys over the whole batch
+  std::vector<int64_t> gpairs;
+  HistIn h;
+  if (n_hist) {
+    int64_t tot = 0, base = 0;
+    for (int32_t k = 0; k < n_sys; k++) {
+      if (n_hist[k] < 0 || n[k] < 0) return DEM_E_INVALID;
+      tot += n_hist[k];
+    }
+    if (tot > 0 && (!hist_pairs || !hist_dt)) return DEM_E_INVALID;
+    gpairs.resize((size_t)(2 * tot));
+    int64_t q = 0;
+    for (int32_t k = 0; k < n_sys; k++) {
+      for (int64_t j = 0; j < n_hist[k]; j++, q++) {
+        const int64_t a = hist_pairs[2 * q], b = hist_pairs[2 * q + 1];
+        const bool ok = a >= 0 && a < n[k] && ((b > a && b < n[k]) || (b < 0 && b >= -6));
+        if (!ok) return DEM_E_INVALID;
+        gpairs[2 * q] = a + base;
+        gpairs[2 * q + 1] = b >= 0 ? b + base : b;
+      }
+      base += n[k];
+    }
+    h.n = tot;
+    h.pairs = gpairs.data();
+    h.dt = hist_dt;
+  }
   Engine *e = nullptr;
-  const dem_status st = engine_create(n_sys, p, n, x, v, omega, r, nullptr, nullptr, HistIn{}, workspace,
-                                      ws_bytes, hip_stream, &e);
+  const dem_status st = engine_create(n_sys, p, n, x, v, omega, r, F0, T0, h, workspace, ws_bytes, hip_stream, &e);
   if (st != DEM_OK) return st;
   dem_batch *b = new (std::nothrow) dem_batch;
   if (!b) {
@@ -1207,6 +1258,11 @@ dem_status dem_batch_step(dem_batch *b, const int64_t *steps) {
   if (!b) return DEM_E_STATE;
   if (!steps) return DEM_E_INVALID;
   return engine_step(*b->e, steps);
+}
+
+dem_status dem_batch_set_radii(dem_batch *b, const double *r) {
+  if (!b) return DEM_E_STATE;
+  return engine_set_radii(*b->e, r);
 }
 
 dem_status dem_batch_read_state(dem_batch *b, int32_t k, double *x, double *v, double *omega, double *F,

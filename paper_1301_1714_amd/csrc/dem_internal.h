@@ -16,21 +16,23 @@
 //            kernel block (blocks never straddle two systems)
 //   nbr      detection input and output: xyzr (FP32 copy of x - lo and r)
 //            and xq (8-byte fixed-point copy, the direct sweep's candidate
-//            records), and, per particle, its contacts with higher slots in
-//            ascending order followed by its walls (-1 - w)
+//            records); per particle the contacts it owns (partners with
+//            higher slots in ascending order, then its walls as -1 - w),
+//            K of them at most (the system's contacts_per_particle), stored
+//            k-major: entry k of slot s at [k * N + s]
 //   pst      the law's inputs per particle, packed (PState<Real>), with the
-//            previous slot and committed history segment of each slot
+//            previous slot and committed history count of each slot
 //   tiles    detection work items: (system, row, first cell, last cell) of
 //            the LDS-tiled shape; runs: the same for the wave shape
-//   gen[2]   two generations of the compact contact array, CSR by owner slot
-//            (the lower slot of a pair; the particle for a wall): ofs[N + 1],
-//            per contact the owner s and partner t (slot or -1 - w), and one
-//            Real4 entry of the tangential-history table: delta_t as seen
-//            from the owner in x, y, z and the key (t, its bits) in w, so
+//   hist[2]  two generations of the tangential-history table, laid out like
+//            the owned contacts: per slot its count and, at [k * N + s], one
+//            Real4 entry per owned contact: delta_t as seen from the owner in
+//            x, y, z and the key (partner slot or -1 - w, its bits) in w, so
 //            that one load brings both.  One generation holds the committed
-//            history, the other is built for the new positions.
-//   work     per-contact force on the owner and n x F_t (6 Real), and the
-//            backward lists (contacts of each particle as the partner)
+//            history, the other is written for the new positions.
+//   work     per owned contact [k * N + s]: force on the owner and n x F_t
+//            (6 Real), and the backward lists (contacts of each particle as
+//            the partner, each as owner slot << 6 | k)
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -52,10 +54,13 @@ enum ModeBits : int32_t {
 };
 
 constexpr int32_t kBlock = 256;
-constexpr int32_t kListCap = 64;  // detection: contacts per particle (higher partners + walls)
-// contact-list offsets are int32: n * kListCap must stay below 2^31
+constexpr int32_t kListCap = 64;  // largest per-particle capacity of owned contacts (higher partners + walls)
+// contact indices k * N + s are int32: n * kListCap must stay below 2^31
 constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
+constexpr int kOwnerShift = 6;    // a backward entry is owner slot << kOwnerShift | k
+static_assert(kListCap <= (1 << kOwnerShift), "k must fit below the owner slot");
+static_assert(kMaxParticles <= (INT32_MAX >> kOwnerShift) + 1, "owner slot << kOwnerShift must fit in int32");
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 constexpr int32_t kRunCells = 8;  // cells along x per wave of the wave-per-cell-run detection
 constexpr int32_t kMaxReach = 2;  // largest cell divisor
@@ -87,6 +92,7 @@ struct SysInfo {
   float rmax;     // largest radius (FP32), bounds the contact distance
   int32_t tile;   // detection: cells per tile (0: direct sweep, -1: wave per cell run)
   int32_t reach;  // cells swept on each side of a particle's own (the cell divisor)
+  int32_t kcap;   // owned contacts per particle at most (contacts_per_particle)
 };
 
 // Step control on the device, so that one captured step can be replayed:
@@ -110,8 +116,8 @@ struct VelBuf {
 // The state the contact law reads, packed per particle so that a partner
 // costs one or two cache lines instead of one per array.  In a time step it
 // also carries where the particle's committed tangential history is: its
-// previous slot (low kPrevBits bits of hp) and the count (high bits) and
-// first index (hb) of the contacts it owned there.
+// previous slot (low kPrevBits bits of hp) and the number of contacts it
+// owned there (high bits); the entries are at [k * N + previous slot].
 constexpr int kPrevBits = 25;
 static_assert(kMaxParticles <= (1 << kPrevBits), "previous slot must fit in kPrevBits bits");
 static_assert(kListCap < (1 << (32 - kPrevBits)), "history count must fit above the previous slot");
@@ -122,30 +128,30 @@ struct alignas(16) PState {
   float r;
   int32_t id;
   uint32_t hp;  // previous slot | owned history count << kPrevBits
-  int32_t hb;   // first committed history entry of the previous slot
+  int32_t pad;
 };
 
 struct NbrBuf {
   float4 *xyzr;   // [N] (x - lo, y - lo, z - lo, r), FP32; written only while a system uses tiles or waves
   uint2 *xq;      // [N] x, y, z in cell units modulo 8 cells (1/8192 cell, 16 bits each), r in rmax/65535 rounded up
-  int32_t *fcnt;  // [N] entries of nb (clamped to kListCap)
-  int32_t *nb;    // [kListCap][N]
+  int32_t *fcnt;  // [N] owned contacts (clamped to the capacity K)
+  int32_t *nb;    // [K][N] their partners
   void *pst;      // [N] PState<Real> of the current slots
+  int32_t K;      // owned contacts per particle at most (largest contacts_per_particle of the engine)
 };
 
-struct PairGen {
-  int32_t *ofs;  // [N + 1]
-  int32_t *s;    // [Pcap] owner slot
-  int32_t *t;    // [Pcap] partner slot or -1 - w
-  void *ent;     // [Pcap] Real4: delta_t (x, y, z), key bits (w)
+// one generation of the tangential-history table
+struct HistGen {
+  int32_t *cnt;  // [N] entries of each slot
+  void *ent;     // [K][N] Real4: delta_t (x, y, z), key bits (w)
 };
 
 struct PairWork {
-  void *pf;        // [6 Pcap] Real: force on the owner, then n x F_t
-  double *pe;      // [Pcap] elastic energy (diagnostics)
-  double *pd;      // [Pcap] overlap (diagnostics)
-  int32_t *bcnt;   // [N] contacts of each particle as the partner
-  int32_t *bwd;    // [kBwdCap][N] their indices, in arrival order
+  void *pf;        // [K][N] 3 x Real2: force on the owner, then n x F_t
+  double *pe;      // [K][N] elastic energy (diagnostics)
+  double *pd;      // [K][N] overlap (diagnostics)
+  int32_t *bcnt;   // [N] contacts of each particle as the partner (zero between evaluations)
+  int32_t *bwd;    // [kBwdCap][N] their owner slot << kOwnerShift | k, in arrival order
 };
 
 struct DiagBuf {
@@ -180,10 +186,9 @@ struct PairArgs {
   PosBuf pos;            // current positions
   PosBuf pos_out;        // time steps: positions after the step (drifted for the next one)
   VelBuf vel_in, vel_out;
-  NbrBuf nb;             // packed state and history index of the current slots
-  PairGen cur, old;      // cur: contacts of the current positions; old: committed history
+  NbrBuf nb;             // packed state and history index of the current slots; owned contacts
+  HistGen cur, old;      // cur: history written for the current positions; old: committed history
   PairWork w;
-  int64_t cap;           // contacts a table holds
   void *F[3], *T[3];
   DiagBuf diag;
   int32_t *cell;         // cells for the next sort (drifted positions, or unchanged ones)
@@ -207,28 +212,25 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
 // Step 4 into the packed records nb.pst (and, with soa, into dst / vdst as
-// well; a time step leaves that to its gather); old_ofs: offsets of the
-// committed history, whose segments are recorded in the records (nullptr:
-// none)
+// well; a time step leaves that to its gather); old_cnt: counts of the
+// committed history, recorded in the records with the previous slots
+// (nullptr: none)
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st);
+                          const NbrBuf &nb, const int32_t *old_cnt, hipStream_t st);
 hipError_t launch_xyzr(const Layout &L, const PosBuf &p, const NbrBuf &nb, hipStream_t st);
 // nb.pst from the current buffers (before a force evaluation outside a step)
 hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const NbrBuf &nb,
                        hipStream_t st);
-// Steps 5-6: detection (all systems, or with ctl only the active ones; the
-// others keep their lists), then the compact contact array of `gen` and its
-// backward index
-hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
-                         const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st);
-// (write_keys: also write the history keys into the entries; a time step
-// whose law keeps history leaves that to the law pass)
-hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                       int64_t cap, bool write_keys, const ScanScratch &sc, int32_t *err, hipStream_t st);
-// Steps 7-8: the law once per contact, then per-particle sums and (in a time
-// step) the kicks
-hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st);
+// Steps 5-8: detection of the owned contacts (all systems, or with ctl only
+// the active ones; the others keep their lists).  With `a` the contact law
+// follows in the same pass (one lane per contact, compacted per wave) for the
+// systems swept by the direct shape, and in a second pass for the others;
+// without it only the lists are built.
+hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
+                           const int32_t *scell, const int32_t *cell_start, const PairArgs *a, int32_t *err,
+                           hipStream_t st, hipEvent_t after_detect);
+// per-particle sums and (in a time step) the kicks
 hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st);
 hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,

@@ -14,20 +14,24 @@
 //   Step 4       k_reorder: gather the state into the sorted order as one
 //                packed record per particle, plus an FP32 copy of (x - lo, r)
 //                for the detection prefilter
-//   Steps 5-6    k_detect_direct / k_detect_cells / k_detect_tiles: each
-//                particle sweeps the forward half of the 27 cells of Eq. 12,
-//                rejects with a conservative FP32 test and decides the rest
-//                exactly in FP64; its contacts, in ascending slot order, and
-//                its walls form its list.  k_pairs: the lists become the
-//                compact contact array (CSR by owner slot), and each contact
-//                joins its partner's backward list
-//   Steps 7-8    k_pair_force: one lane per contact evaluates the law
-//                (Eqs. 2-10, or Eq. 1) once, seen from the owner, with the
-//                history looked up in the previous array.  k_gather: one lane
-//                per particle sums its contacts in a fixed order (no float
-//                atomics) and applies the closing half kick
+//   Steps 5-8    k_contacts_direct: each particle sweeps the forward half of
+//                the 27 cells of Eq. 12, rejects with a conservative
+//                fixed-point test and decides the rest exactly in FP64; its
+//                contacts (ascending slot order, then its walls) form the
+//                list of contacts it owns.  In the same pass each wave then
+//                evaluates its particles' contacts one lane per contact
+//                (compacted by a prefix sum over the wave, so every lane has a
+//                real contact): the law (Eqs. 2-10, or Eq. 1) once per pair,
+//                seen from the owner, with the history looked up in the
+//                committed table; the result is stored per contact and filed
+//                in the partner's backward list.  k_detect_cells /
+//                k_detect_tiles build the same lists with other launch
+//                shapes; k_contact_law then runs the law pass for them.
+//   Steps 7-8    k_gather: one lane per particle sums its contacts in a fixed
+//                order (no float atomics) and applies the closing half kick
 // No step is a dense contraction, so nothing here uses the matrix cores.
 #include <math.h>
+#include <string.h>
 
 #include "dem_internal.h"
 
@@ -62,9 +66,13 @@ __device__ __forceinline__ bool hash_cell(const Grid &g, double x, double y, dou
   for (int a = 0; a < 3; a++) {
     double u = (p[a] - g.lo[a]) * g.sc[a];
     ok = ok && (u >= -1.0 && u < (double)g.nc[a] + 1.0);
+    // clamped in floating point before the conversion, so that a position
+    // out of range or not a number (an error already flagged) still gives a
+    // cell of the grid
     double f = floor(u);
-    int32_t i = f < 0.0 ? 0 : (f > (double)(g.nc[a] - 1) ? g.nc[a] - 1 : (int32_t)f);
-    ijk[a] = i;
+    f = f >= 0.0 ? f : 0.0;
+    f = f <= (double)(g.nc[a] - 1) ? f : (double)(g.nc[a] - 1);
+    ijk[a] = (int32_t)f;
   }
   *cell = g.c0 + ijk[0] + g.nc[0] * (ijk[1] + g.nc[1] * ijk[2]);
   return ok;
@@ -399,7 +407,12 @@ __device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, d
 constexpr double kFixCell = 8192.0;
 constexpr double kFixRad = 65535.0;
 __device__ __forceinline__ uint32_t fix_cell(double u) {
-  return (uint32_t)(int64_t)floor(u * kFixCell + 0.5) & 0xffffu;
+  double f = floor(u * kFixCell + 0.5);
+  // a position far outside the grid or not a number (a step that has failed
+  // with the domain error) gets a defined record instead of an out-of-range
+  // conversion
+  f = fabs(f) < 4.0e15 ? f : 0.0;
+  return (uint32_t)(int64_t)f & 0xffffu;
 }
 __device__ __forceinline__ uint2 make_xq(const SysInfo &si, double x, double y, double z, float r) {
   const Grid &g = si.g;
@@ -414,7 +427,7 @@ template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     int32_t soa, const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
-                                                    NbrBuf nb, const int32_t *__restrict__ old_ofs) {
+                                                    NbrBuf nb, const int32_t *__restrict__ old_cnt) {
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
@@ -431,11 +444,10 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   ps.r = src.r[p];
   ps.id = src.id[p];
   ps.hp = 0;
-  ps.hb = 0;
-  if (old_ofs) {
-    const int32_t b = old_ofs[p], c = min(old_ofs[p + 1] - b, kListCap);
+  ps.pad = 0;
+  if (old_cnt) {
+    const int32_t c = min(max(old_cnt[p], 0), nb.K);  // the table holds K rows
     ps.hp = (uint32_t)p | ((uint32_t)c << kPrevBits);
-    ps.hb = b;
   }
   // the candidate records are formed ahead of every store, so that the
   // system's grid is read with scalar loads (a store may alias it as far as
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
   ps.r = pos.r[s];
   ps.id = pos.id[s];
   ps.hp = 0;
-  ps.hb = 0;
+  ps.pad = 0;
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
@@ -548,25 +560,25 @@ constexpr int kListStage = 8;  // list entries a lane keeps in LDS until its swe
 // end of the sweep, so that a wave writes each list column in one store
 // rather than one scattered store per contact as it is found
 template <int kLanes>
-__device__ __forceinline__ void record(const NbrBuf &nb, int32_t N, int32_t s, int32_t *lst, int32_t t,
-                                       int32_t &nf) {
+__device__ __forceinline__ void record(const NbrBuf &nb, int32_t N, int32_t kcap, int32_t s, int32_t *lst,
+                                       int32_t t, int32_t &nf) {
   if (nf < kListStage)
     lst[nf * kLanes] = t;
-  else if (nf < kListCap)
+  else if (nf < kcap)
     nb.nb[(int64_t)nf * N + s] = t;
   nf++;
 }
 
 // exact FP64 decision on one prefilter survivor (the contact test of Step 7)
 template <int kLanes>
-__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int32_t N, int32_t s, float ri,
-                                                 double xi, double yi, double zi, int32_t t, int32_t *lst,
-                                                 int32_t &nf) {
+__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int32_t N, int32_t kcap, int32_t s,
+                                                 float ri, double xi, double yi, double zi, int32_t t,
+                                                 int32_t *lst, int32_t &nf) {
   const XR q = state_xr(nb, f64, t);
   const double ex = q.x - xi, ey = q.y - yi, ez = q.z - zi;
   const double S = (double)ri + (double)q.r;
   if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
-  record<kLanes>(nb, N, s, lst, t, nf);
+  record<kLanes>(nb, N, kcap, s, lst, t, nf);
 }
 
 // The prefilter on FP32 copies (x - lo, y - lo, z - lo, r): a pair passes
@@ -609,11 +621,14 @@ struct NearFix {
 // ascending slot order: the own row, rows dy = 1..K of the own plane, then
 // rows dy = -K..K of planes dz = 1..K.  Survivors wait in the lane's LDS
 // slots (stride kLanes) so that the rare exact test does not sit inside the
-// candidate loop, where one lane taking it would hold the whole wave.
+// candidate loop, where one lane taking it would hold the whole wave.  The
+// first kListStage contacts stay in the lane's LDS slots lst (stride kLanes)
+// and are also stored to the list; returns the number of contacts kept.
 template <int kLanes, int K, typename Rows>
-__device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N, int32_t s,
-                                               const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
-                                               int32_t *surv, int32_t *lst, int32_t *err) {
+__device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf &nb, bool f64, int32_t N,
+                                                  int32_t s, const SysInfo &si, int32_t cx, int32_t cy, int32_t cz,
+                                                  int32_t *surv, int32_t *lst, int32_t *err) {
+  const int32_t kcap = si.kcap;
   const XR me = state_xr(nb, f64, s);
   const float4 p = make_xyzr(si.g, me.x, me.y, me.z, me.r);
   const double xi = me.x, yi = me.y, zi = me.z;
@@ -685,13 +700,13 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
       }
       if (ns > kSurv - kU) {
         for (int32_t j = 0; j < ns; j++)
-          exact_and_record<kLanes>(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
+          exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
         ns = 0;
       }
     }
   }
   for (int32_t j = 0; j < ns; j++)
-    exact_and_record<kLanes>(nb, f64, N, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
+    exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
   // Step 8: walls, particles of infinite radius, after the pairs
   const uint32_t wall_mask = si.c.wall_mask;
   if (wall_mask) {
@@ -701,12 +716,14 @@ __device__ __forceinline__ void sweep_particle(const Rows &rows, const NbrBuf &n
       if (!((wall_mask >> w) & 1)) continue;
       const int ax = w >> 1;
       const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
-      if (gap < rid) record<kLanes>(nb, N, s, lst, -1 - w, nf);
+      if (gap < rid) record<kLanes>(nb, N, kcap, s, lst, -1 - w, nf);
     }
   }
-  for (int32_t j = 0; j < nf && j < kListStage; j++) nb.nb[(int64_t)j * N + s] = lst[j * kLanes];
-  if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
-  nb.fcnt[s] = nf < kListCap ? nf : kListCap;
+  const int32_t nc = nf < kcap ? nf : kcap;
+  for (int32_t j = 0; j < nc && j < kListStage; j++) nb.nb[(int64_t)j * N + s] = lst[j * kLanes];
+  if (nf > kcap) raise_err(err, ERR_OVERFLOW);
+  nb.fcnt[s] = nc;
+  return nc;
 }
 
 // two consecutive 8-byte records in one 16-byte load (the records are
@@ -757,26 +774,6 @@ struct DirectRows {
     return true;
   }
 };
-
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_detect_direct(Layout L, StepCtl ctl, int32_t only_active, bool f64,
-                                                          NbrBuf nb, const int32_t *__restrict__ scell,
-                                                          const int32_t *__restrict__ cell_start, int32_t *err) {
-  __shared__ int32_t surv_all[kSurv * kBlock];
-  __shared__ int32_t lst_all[kListStage * kBlock];
-  int32_t k;
-  const int32_t s = block_slot(L, k);
-  if (s < 0) return;
-  const SysInfo &si = L.tab[k];
-  if (si.tile != 0 || si.reach != K) return;      // another launch sweeps this system
-  if (only_active && !is_active(ctl, k)) return;  // a finished system keeps its lists
-  const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
-  const int32_t cc = scell[s] - si.g.c0;
-  const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
-  const DirectRows rows{nb.xq, cell_start, si.g.c0, nx, ny, nz, cy, cz};
-  sweep_particle<kBlock, K>(rows, nb, f64, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x, lst_all + threadIdx.x,
-                            err);
-}
 
 // --------------------------------------------------------------------------
 // Wave-per-cell-run detection (wave64 ballot and compaction).  One wave walks
@@ -887,7 +884,7 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
       const int32_t before = __popcll(mok & lt & ~((1ull << rs) - 1));
       if (ok) {
         const int32_t pos = cnt[il] + before;
-        if (pos < kListCap) nb.nb[(int64_t)pos * N + g0 + il] = t;
+        if (pos < si.kcap) nb.nb[(int64_t)pos * N + g0 + il] = t;
       }
       __builtin_amdgcn_wave_barrier();
       if (act && (lane == m - 1 || next != il)) cnt[il] += before + (ok ? 1 : 0);
@@ -1018,13 +1015,13 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
           const int ax = w >> 1;
           const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
           if (gap < rid) {
-            if (nf < kListCap) nb.nb[(int64_t)nf * N + s] = -1 - w;
+            if (nf < si.kcap) nb.nb[(int64_t)nf * N + s] = -1 - w;
             nf++;
           }
         }
       }
-      if (nf > kListCap) raise_err(err, ERR_OVERFLOW);
-      nb.fcnt[s] = nf < kListCap ? nf : kListCap;
+      if (nf > si.kcap) raise_err(err, ERR_OVERFLOW);
+      nb.fcnt[s] = nf < si.kcap ? nf : si.kcap;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1179,7 +1176,7 @@ __device__ __forceinline__ void get_record(const void *pf, int64_t q, Real f[3],
 }
 
 template <typename Real>
-__device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Real d[3], int32_t key) {
+__device__ __forceinline__ void put_entry(const HistGen &g, int64_t q, const Real d[3], int32_t key) {
   using V4 = typename Vec4T<Real>::type;
   V4 e;
   e.x = d[0];
@@ -1187,53 +1184,6 @@ __device__ __forceinline__ void put_entry(const PairGen &g, int64_t q, const Rea
   e.z = d[2];
   e.w = key_bits(key, (Real)0);
   ((V4 *)g.ent)[q] = e;
-}
-
-// The lists become the compact contact array of `gen` (offsets from a scan
-// of the counts); each pair is also filed in its partner's backward list,
-// at the position its atomic count drew (arrival order; the gather sorts
-// each short list).  With write_keys the history keys go into the entries.
-// One lane per contact: a block takes the contacts of its kBlock owners, a
-// lane finds its owner by bisecting their offsets in LDS, so that every
-// lane of a wave writes (and files) a real contact, at consecutive indices.
-template <typename Real>
-__global__ __launch_bounds__(kBlock) void k_pairs(NbrBuf nb, PairGen gen, PairWork w, int64_t cap, int32_t n,
-                                                  int32_t write_keys, int32_t *err) {
-  __shared__ int32_t so[kBlock + 1];
-  const int32_t s0 = blockIdx.x * kBlock, m = min(kBlock, n - s0);
-  for (int32_t i = threadIdx.x; i <= m; i += kBlock) so[i] = gen.ofs[s0 + i];
-  __syncthreads();
-  const int32_t q0 = so[0], q1 = so[m];
-  if (threadIdx.x == 0 && q1 > cap) raise_err(err, ERR_OVERFLOW);  // contacts past the capacity are dropped
-  const int32_t qe = (int64_t)q1 < cap ? q1 : (int32_t)cap;
-  const Real zero[3] = {0, 0, 0};
-  for (int32_t q = q0 + (int32_t)threadIdx.x; q < qe; q += kBlock) {
-    int32_t lo = 0, hi = m;  // so[lo] <= q < so[hi]
-    while (hi - lo > 1) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (so[mid] <= q)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    const int32_t s = s0 + lo, j = q - so[lo];
-    const int32_t t = nb.nb[(int64_t)j * n + s];
-    gen.s[q] = s;
-    gen.t[q] = t;
-    if (write_keys) put_entry<Real>(gen, q, zero, t);
-    if (t >= 0) {
-      const int32_t k = atomicAdd(&w.bcnt[t], 1);
-      if (k < kBwdCap)
-        w.bwd[(int64_t)k * n + t] = q;
-      else
-        raise_err(err, ERR_OVERFLOW);
-    }
-  }
-}
-
-__device__ __forceinline__ int32_t num_pairs(const PairGen &gen, int32_t n, int64_t cap) {
-  const int32_t P = gen.ofs[n];
-  return (int64_t)P < cap ? P : (int32_t)cap;
 }
 
 // fixed-size bitonic network on registers (indices are compile-time)
@@ -1288,44 +1238,6 @@ __device__ __forceinline__ void for_selected(const int32_t *bwd, int32_t n, int3
   }
 }
 
-hipError_t launch_detect(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
-                         const int32_t *scell, const int32_t *cell_start, int32_t *err, hipStream_t st) {
-  if (L.n <= 0) return hipSuccess;
-  StepCtl none{nullptr, nullptr};
-  const bool f64 = precision == DEM_PREC_FP64;
-  if (L.ndirect > 0)
-    k_detect_direct<1><<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
-                                                      err);
-  if (L.ndirect2 > 0)
-    k_detect_direct<2><<<L.nblocks, kBlock, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start,
-                                                      err);
-  if (L.nruns > 0)
-    k_detect_cells<<<(L.nruns + kCellWaves - 1) / kCellWaves, kCellWaves * 64, 0, st>>>(
-        L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell, cell_start, err);
-  if (L.ntiles > 0)
-    k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, ctl ? *ctl : none, ctl ? 1 : 0, f64, nb, scell,
-                                                       cell_start, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_list(int precision, const Layout &L, const NbrBuf &nb, const PairGen &gen, const PairWork &w,
-                       int64_t cap, bool write_keys, const ScanScratch &sc, int32_t *err, hipStream_t st) {
-  const int32_t n = L.n;
-  if (n <= 0) {
-    k_fill<<<1, kBlock, 0, st>>>(gen.ofs, 1, 0);
-    return hipGetLastError();
-  }
-  hipError_t e = scan_with_total(nb.fcnt, gen.ofs, n, sc, st);
-  if (e != hipSuccess) return e;
-  k_fill<<<blocks_for(n), kBlock, 0, st>>>(w.bcnt, n, 0);
-  const int32_t wk = write_keys ? 1 : 0;
-  if (precision == DEM_PREC_FP64)
-    k_pairs<double><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, wk, err);
-  else
-    k_pairs<float><<<blocks_for(n), kBlock, 0, st>>>(nb, gen, w, cap, n, wk, err);
-  return hipGetLastError();
-}
-
 // --------------------------------------------------------------------------
 // Steps 7-8: contact law
 
@@ -1354,9 +1266,11 @@ __device__ __forceinline__ void contact_law(const Consts &c, const Real n[3], Re
     vt[k] = v[k] - vn[k] + sxn[k];  // Eq. 6
   }
   if (LAW == DEM_LAW_SIMPLE) {  // Eq. 1 without gravity
+    // the t of Eq. 1 is the tangential component of v (Sec. 3); the simple
+    // model has no rotation, so Eq. 6's spin term is not part of it
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      o.F[k] = -(Real)c.k_sp * delta * n[k] - (Real)c.k_da * v[k] - (Real)c.k_sh * vt[k];
+      o.F[k] = -(Real)c.k_sp * delta * n[k] - (Real)c.k_da * v[k] - (Real)c.k_sh * (v[k] - vn[k]);
       o.Ft[k] = 0;
       o.dtn[k] = 0;
     }
@@ -1413,15 +1327,15 @@ __device__ __forceinline__ double elastic_energy(const Consts &c, Real delta, Re
 }
 
 // committed tangential displacement of the contact with history key `key`
-// in the entries [beg, end) of the previous table (zero for a new contact)
+// among the c entries of previous slot p in the committed table (zero for a
+// new contact)
 template <typename Real>
-__device__ __forceinline__ void hist_find(const PairGen &old, int64_t cap, int32_t beg, int32_t end, int32_t key,
+__device__ __forceinline__ void hist_find(const HistGen &old, int32_t N, int32_t p, int32_t c, int32_t key,
                                           Real h[3]) {
   using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
-  const int64_t e = end < cap ? end : cap;
-  for (int64_t q = beg; q < e; q++) {
-    const V4 d = ((const V4 *)old.ent)[q];
+  for (int32_t k = 0; k < c; k++) {
+    const V4 d = ((const V4 *)old.ent)[(int64_t)k * N + p];
     if (entry_key(d.w) == key) {
       h[0] = d.x;
       h[1] = d.y;
@@ -1432,67 +1346,55 @@ __device__ __forceinline__ void hist_find(const PairGen &old, int64_t cap, int32
 }
 
 // Committed delta_t of a contact, seen from its current owner (lower slot).
-// ho, hp: previous slot and committed history segment of the owner and of
-// the partner.  The previous step filed the contact under the lower of the
-// two previous slots, seen from there.
+// ho, hp: previous slot and committed entry count of the owner and of the
+// partner.  The previous step filed the contact under the lower of the two
+// previous slots, seen from there.
 template <typename Real>
-__device__ __forceinline__ void pair_history(const PairGen &old, int64_t cap, const int4 &ho, const int4 &hp,
+__device__ __forceinline__ void pair_history(const HistGen &old, int32_t N, const int2 &ho, const int2 &hp,
                                              Real h[3]) {
   const bool kept = ho.x < hp.x;  // the owner was the lower slot then too
   if (kept) {
-    hist_find<Real>(old, cap, ho.y, ho.z, hp.x, h);
+    hist_find<Real>(old, N, ho.x, ho.y, hp.x, h);
   } else {
-    hist_find<Real>(old, cap, hp.y, hp.z, ho.x, h);
+    hist_find<Real>(old, N, hp.x, hp.y, ho.x, h);
     h[0] = -h[0];
     h[1] = -h[1];
     h[2] = -h[2];
   }
 }
 
-// previous slot and committed history segment [begin, end) of slot s, whose
-// packed record is ps: recorded there in a time step, the slot's own
-// otherwise
+// previous slot and committed entry count of slot s, whose packed record is
+// ps: recorded there in a time step, the slot's own otherwise
 template <typename Real>
-__device__ __forceinline__ int4 hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
-  if (old_perm) {
-    const int32_t p = (int32_t)(ps.hp & ((1u << kPrevBits) - 1)), c = (int32_t)(ps.hp >> kPrevBits);
-    return make_int4(p, ps.hb, ps.hb + c, 0);
-  }
-  return make_int4(s, a.old.ofs[s], a.old.ofs[s + 1], 0);
+__device__ __forceinline__ int2 hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
+  if (old_perm) return make_int2((int32_t)(ps.hp & ((1u << kPrevBits) - 1)), (int32_t)(ps.hp >> kPrevBits));
+  return make_int2(s, min(max(a.old.cnt[s], 0), a.nb.K));
 }
 
-// One lane per contact: the law of Eqs. 2-10 (or Eq. 1) evaluated once per
-// pair, seen from the owner (the lower slot), stored as the force on the
-// owner and n x F_t.  The partner receives the exact negation.  Both
-// particles' inputs come from their packed state records.  In a time step,
-// the contacts of a system that has finished its steps only carry their
-// history forward.
+// Owned contact k of slot s (partner t, a slot or -1 - w): the law of
+// Eqs. 2-10 (or Eq. 1) evaluated once per pair, seen from the owner (the
+// lower slot), stored at [k * N + s] as the force on the owner and n x F_t;
+// the partner receives the exact negation through its backward list, where
+// the contact is filed here.  Both particles' inputs come from their packed
+// state records.
 template <typename Real, int LAW>
-__device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q, int32_t s, int32_t t) {
-  const int64_t cap = a.cap;
+__device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t k) {
+  const int32_t N = a.L.n;
+  const int64_t q = (int64_t)k * N + s;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
-  const bool stepping = (a.mode & MODE_KICK) != 0;
-  const bool one_sys = a.L.S == 1;
-  const int32_t k = one_sys ? 0 : a.L.psys[s];
-  const SysInfo &si = a.L.tab[k];
   const Consts &c = si.c;
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
-  const int4 hs = hist_index(a, old_perm, s, me);
   Real h[3] = {0, 0, 0};
   if (LAW != DEM_LAW_SIMPLE) {
+    const int2 hs = hist_index(a, old_perm, s, me);
     if (t >= 0)
-      pair_history<Real>(a.old, cap, hs, hist_index(a, old_perm, t, pt), h);
+      pair_history<Real>(a.old, N, hs, hist_index(a, old_perm, t, pt), h);
     else
-      hist_find<Real>(a.old, cap, hs.y, hs.z, t, h);
-  }
-  if (stepping && !is_active(a.ctl, k)) {
-    // a finished system: its state does not move, its history is kept
-    if (write_hist) put_entry<Real>(a.cur, q, h, t);
-    return;
+      hist_find<Real>(a.old, N, hs.x, hs.y, t, h);
   }
   const float rsf = me.r;
   const Real rs = (Real)rsf;
@@ -1543,22 +1445,129 @@ __device__ __forceinline__ void pair_force_one(const PairArgs &a, int32_t q, int
     a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
     a.w.pd[q] = (double)delta;
   }
+  if (t >= 0) {
+    const int32_t r = atomicAdd(&a.w.bcnt[t], 1);
+    if (r < kBwdCap)
+      a.w.bwd[(int64_t)r * N + t] = (s << kOwnerShift) | k;
+    else
+      raise_err(a.err, ERR_OVERFLOW);
+  }
 }
 
+// The owned contacts of one wave's particles (lane l: slot first + l, cnt
+// contacts), one lane per contact in owner order, 64 at a time, so that
+// every lane of the wave evaluates a real contact however unevenly the
+// contacts fall on the particles (the contact-branch divergence of a lane per
+// particle).  Contact k of lane l is read from lst[k * stride + l] for k <
+// kListStage when lst is given (the detection's LDS copy), else from the
+// list in global memory.  woff: 65 ints of LDS for the wave.  Every lane of
+// the wave must call it.
 template <typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_pair_force(PairArgs a) {
-  const int32_t P = num_pairs(a.cur, a.L.n, a.cap);
-  const int32_t stride = gridDim.x * kBlock;
-  int32_t q = blockIdx.x * kBlock + threadIdx.x;
-  int32_t s = q < P ? a.cur.s[q] : 0, t = q < P ? a.cur.t[q] : 0;
-  for (; q < P; q += stride) {
-    // the next contact's slots are in flight while this one is evaluated
-    const int32_t qn = q + stride;
-    const int32_t sn = qn < P ? a.cur.s[qn] : 0, tn = qn < P ? a.cur.t[qn] : 0;
-    pair_force_one<Real, LAW>(a, q, s, t);
-    s = sn;
-    t = tn;
+__device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, int32_t first, int32_t cnt,
+                                         const int32_t *lst, int32_t stride, int32_t *woff) {
+  const int32_t lane = (int32_t)(threadIdx.x & 63);
+  int32_t x = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
   }
+  const int32_t total = __shfl(x, 63);
+  woff[lane] = x - cnt;
+  if (lane == 63) woff[64] = total;
+  __builtin_amdgcn_wave_barrier();
+  for (int32_t e0 = 0; e0 < total; e0 += 64) {
+    const int32_t e = e0 + lane;
+    if (e < total) {
+      int32_t lo = 0, hi = 64;  // woff[lo] <= e < woff[hi]
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (woff[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const int32_t k = e - woff[lo], s = first + lo;
+      const int32_t t = (lst && k < kListStage) ? lst[k * stride + lo] : a.nb.nb[(int64_t)k * a.L.n + s];
+      contact_one<Real, LAW>(a, si, s, t, k);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// A system that has finished its steps in this call: its state does not
+// move (so its slots do not change) and its committed history is carried
+// into the generation being written.
+template <typename Real>
+__device__ __forceinline__ void carry_history(const PairArgs &a, int32_t s) {
+  using V4 = typename Vec4T<Real>::type;
+  if (s < 0 || (a.mode & MODE_WRITE_HIST) == 0) return;
+  const int32_t N = a.L.n;
+  const int32_t c = min(max(a.old.cnt[s], 0), a.nb.K);
+  a.cur.cnt[s] = c;
+  for (int32_t k = 0; k < c; k++)
+    ((V4 *)a.cur.ent)[(int64_t)k * N + s] = ((const V4 *)a.old.ent)[(int64_t)k * N + s];
+}
+
+// count of the history generation being written: the owned contacts (none
+// for the simple law, which keeps no history)
+template <int LAW>
+__device__ __forceinline__ void set_hist_count(const PairArgs &a, int32_t s, int32_t cnt) {
+  if (s >= 0 && (a.mode & MODE_WRITE_HIST) != 0) a.cur.cnt[s] = LAW == DEM_LAW_SIMPLE ? 0 : cnt;
+}
+
+// Steps 5-8 in one pass for the systems swept by the direct shape: each lane
+// sweeps its particle's forward cells (the owned contacts go to the list),
+// then each wave evaluates its particles' contacts one lane per contact
+// (with_law; without it only the lists are built).
+template <int K, typename Real, int LAW>
+__global__ __launch_bounds__(kBlock) void k_contacts_direct(Layout L, StepCtl ctl, int32_t only_active, NbrBuf nb,
+                                                          const int32_t *__restrict__ scell,
+                                                          const int32_t *__restrict__ cell_start, PairArgs a,
+                                                          int32_t with_law, int32_t *err) {
+  __shared__ int32_t surv_all[kSurv * kBlock];
+  __shared__ int32_t lst_all[kListStage * kBlock];
+  __shared__ int32_t woff_all[kBlock / 64][65];
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  const SysInfo &si = L.tab[k];
+  if (si.tile != 0 || si.reach != K) return;  // another launch sweeps this system
+  if (only_active && !is_active(ctl, k)) {    // a finished system keeps its lists and history
+    if (with_law) carry_history<Real>(a, s);
+    return;
+  }
+  int32_t cnt = 0;
+  if (s >= 0) {
+    const int32_t nx = si.g.nc[0], ny = si.g.nc[1], nz = si.g.nc[2];
+    const int32_t cc = scell[s] - si.g.c0;
+    const int32_t cx = cc % nx, cy = (cc / nx) % ny, cz = cc / (nx * ny);
+    const DirectRows rows{nb.xq, cell_start, si.g.c0, nx, ny, nz, cy, cz};
+    cnt = sweep_particle<kBlock, K>(rows, nb, sizeof(Real) == 8, L.n, s, si, cx, cy, cz, surv_all + threadIdx.x,
+                                    lst_all + threadIdx.x, err);
+  }
+  if (!with_law) return;
+  set_hist_count<LAW>(a, s, cnt);
+  const int32_t wave = (int32_t)(threadIdx.x >> 6);
+  law_wave<Real, LAW>(a, si, L.bfirst[blockIdx.x] + wave * 64, cnt, lst_all + wave * 64, kBlock, woff_all[wave]);
+}
+
+// The law pass of the systems swept by the wave and tiled shapes (their
+// lists are in global memory), one lane per contact as in the direct pass.
+template <typename Real, int LAW>
+__global__ __launch_bounds__(kBlock) void k_contact_law(PairArgs a, int32_t only_active) {
+  __shared__ int32_t woff_all[kBlock / 64][65];
+  int32_t k;
+  const int32_t s = block_slot(a.L, k);
+  const SysInfo &si = a.L.tab[k];
+  if (si.tile == 0) return;  // evaluated by the direct pass
+  if (only_active && !is_active(a.ctl, k)) {
+    carry_history<Real>(a, s);
+    return;
+  }
+  const int32_t cnt = s >= 0 ? a.nb.fcnt[s] : 0;
+  set_hist_count<LAW>(a, s, cnt);
+  const int32_t wave = (int32_t)(threadIdx.x >> 6);
+  law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave]);
 }
 
 // Step 1 drift x += dt v and Step 2 hash of the new position, written to
@@ -1611,6 +1620,11 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum
 // from global memory lane by lane)
 constexpr int32_t kGatherStage = 512;
 
+// record index of a backward entry (owner slot << kOwnerShift | k)
+__device__ __forceinline__ int64_t bwd_record(int32_t b, int32_t N) {
+  return (int64_t)(b & ((1 << kOwnerShift) - 1)) * N + (b >> kOwnerShift);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   using V2 = typename Vec2T<Real>::type;
@@ -1653,6 +1667,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   // lane from global memory instead.
   const int32_t s0 = a.L.bfirst[blockIdx.x];
   const int32_t nbk = s >= 0 ? min(a.w.bcnt[s], kBwdCap) : 0;
+  if (s >= 0) a.w.bcnt[s] = 0;  // ready for the next evaluation's filing
   int32_t B;
   const int32_t off = block_exclusive_scan(nbk, wsum, B);
   bo[threadIdx.x] = off;
@@ -1669,9 +1684,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
         else
           hi = mid;
       }
-      const int32_t q = a.w.bwd[(int64_t)(e - bo[lo]) * N + s0 + lo];
-      bq[e] = q;
-      const V2 *p = (const V2 *)a.w.pf + 3 * (int64_t)q;
+      const int32_t b = a.w.bwd[(int64_t)(e - bo[lo]) * N + s0 + lo];
+      bq[e] = b;
+      const V2 *p = (const V2 *)a.w.pf + 3 * bwd_record(b, N);
       brec[3 * e] = p[0];
       brec[3 * e + 1] = p[1];
       brec[3 * e + 2] = p[2];
@@ -1680,13 +1695,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   __syncthreads();
   if (s < 0) return;
   const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
-  const int64_t cap = a.cap;
   const Real rs = (Real)me.r;
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  // contacts with lower partners, ascending by contact (= by owner slot)
-  auto back = [&](int32_t q) {
+  // contacts with lower partners, ascending by owner slot
+  auto back = [&](int32_t b) {
     Real f[3], m[3];
-    get_record<Real>(a.w.pf, q, f, m);
+    get_record<Real>(a.w.pf, bwd_record(b, N), f, m);
     F[0] -= f[0];
     F[1] -= f[1];
     F[2] -= f[2];
@@ -1695,8 +1709,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     T[2] += rs * m[2];
   };
   if (staged) {
-    // ascending by contact index: each next entry is the smallest above the
-    // previous one (the indices are distinct)
+    // ascending by owner slot: each next entry is the smallest above the
+    // previous one (an owner files one contact per partner)
     const int32_t b0 = bo[threadIdx.x];
     int32_t prev = -1;
     for (int32_t i = 0; i < nbk; i++) {
@@ -1724,12 +1738,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   } else {
     for_selected(a.w.bwd, N, s, nbk, back);  // a register network this long would cost every wave occupancy
   }
-  const int64_t f0 = a.cur.ofs[s];
-  const int64_t f1 = a.cur.ofs[s + 1] < cap ? a.cur.ofs[s + 1] : cap;
+  const int32_t nown = a.nb.fcnt[s];
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;
-  for (int64_t q = f0; q < f1; q++) {
+  for (int32_t k = 0; k < nown; k++) {
+    const int64_t q = (int64_t)k * N + s;
     Real f[3], m[3];
     get_record<Real>(a.w.pf, q, f, m);
     F[0] += f[0];
@@ -1741,7 +1755,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     if (diag) {
       e_el += a.w.pe[q];
       dmax = fmax(dmax, a.w.pd[q]);
-      if (a.cur.t[q] >= 0)
+      if (a.nb.nb[q] >= 0)
         npair++;
       else
         nwall++;
@@ -1927,31 +1941,54 @@ hipError_t launch_xyzr(const Layout &L, const PosBuf &p, const NbrBuf &nb, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_pair_force(int precision, const PairArgs &a, hipStream_t st) {
-  if (a.L.n <= 0 || a.cap <= 0) return hipSuccess;
-  const bool f64 = precision == DEM_PREC_FP64;
-  const unsigned nb = 2048;  // grid-stride over the contacts: the count is on the device
-  switch (a.law) {
-    case DEM_LAW_HERTZ:
-      if (f64)
-        k_pair_force<double, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
-      else
-        k_pair_force<float, DEM_LAW_HERTZ><<<nb, kBlock, 0, st>>>(a);
-      break;
-    case DEM_LAW_SIMPLE:
-      if (f64)
-        k_pair_force<double, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
-      else
-        k_pair_force<float, DEM_LAW_SIMPLE><<<nb, kBlock, 0, st>>>(a);
-      break;
-    default:
-      if (f64)
-        k_pair_force<double, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
-      else
-        k_pair_force<float, DEM_LAW_LINEAR><<<nb, kBlock, 0, st>>>(a);
-      break;
-  }
+template <typename Real, int LAW>
+static hipError_t contacts_t(const Layout &L, const StepCtl *ctl, const NbrBuf &nb, const int32_t *scell,
+                             const int32_t *cell_start, const PairArgs *a, int32_t *err, hipStream_t st,
+                             hipEvent_t after_detect) {
+  StepCtl none{nullptr, nullptr};
+  const StepCtl c = ctl ? *ctl : none;
+  const int32_t oa = ctl ? 1 : 0;
+  PairArgs pa;
+  if (a)
+    pa = *a;
+  else
+    memset(&pa, 0, sizeof(pa));
+  const int32_t wl = a ? 1 : 0;
+  const bool f64 = sizeof(Real) == 8;
+  if (L.ndirect > 0)
+    k_contacts_direct<1, Real, LAW><<<L.nblocks, kBlock, 0, st>>>(L, c, oa, nb, scell, cell_start, pa, wl, err);
+  if (L.ndirect2 > 0)
+    k_contacts_direct<2, Real, LAW><<<L.nblocks, kBlock, 0, st>>>(L, c, oa, nb, scell, cell_start, pa, wl, err);
+  if (L.nruns > 0)
+    k_detect_cells<<<(L.nruns + kCellWaves - 1) / kCellWaves, kCellWaves * 64, 0, st>>>(L, c, oa, f64, nb, scell,
+                                                                                        cell_start, err);
+  if (L.ntiles > 0)
+    k_detect_tiles<<<L.ntiles, kTileThreads, 0, st>>>(L, c, oa, f64, nb, scell, cell_start, err);
+  if (after_detect) (void)hipEventRecord(after_detect, st);
+  if (a && (L.nruns > 0 || L.ntiles > 0)) k_contact_law<Real, LAW><<<L.nblocks, kBlock, 0, st>>>(pa, oa);
   return hipGetLastError();
+}
+
+hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
+                           const int32_t *scell, const int32_t *cell_start, const PairArgs *a, int32_t *err,
+                           hipStream_t st, hipEvent_t after_detect) {
+  if (L.n <= 0) {
+    if (after_detect) (void)hipEventRecord(after_detect, st);
+    return hipSuccess;
+  }
+  const bool f64 = precision == DEM_PREC_FP64;
+  const int law = a ? a->law : DEM_LAW_LINEAR;  // detection alone does not depend on the law
+  switch (law) {
+    case DEM_LAW_HERTZ:
+      return f64 ? contacts_t<double, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
+                 : contacts_t<float, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+    case DEM_LAW_SIMPLE:
+      return f64 ? contacts_t<double, DEM_LAW_SIMPLE>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
+                 : contacts_t<float, DEM_LAW_SIMPLE>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+    default:
+      return f64 ? contacts_t<double, DEM_LAW_LINEAR>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
+                 : contacts_t<float, DEM_LAW_LINEAR>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+  }
 }
 
 hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st) {

@@ -26,8 +26,8 @@ DEM_E_HIP = -6
 DEM_E_STATE = -7
 DEM_E_CAPACITY = -9
 
-NUM_PHASES = 7
-PHASES = ("kick_drift_hash", "sort", "reorder", "detect", "list", "pair_force", "gather")
+NUM_PHASES = 6
+PHASES = ("kick_drift_hash", "sort", "reorder", "contacts", "law_pass", "gather")
 
 _LIB = None
 
@@ -82,7 +82,8 @@ def lib():
             "dem_destroy": ([P], st),
             "dem_status_string": ([st], C.c_char_p),
             "dem_batch_workspace_bytes": ([C.c_int32, P, P, C.POINTER(S)], st),
-            "dem_batch_create": ([C.c_int32, P, P, P, P, P, P, P, S, P, C.POINTER(P)], st),
+            "dem_batch_create": ([C.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, S, P, C.POINTER(P)], st),
+            "dem_batch_set_radii": ([P, P], st),
             "dem_batch_step": ([P, P], st),
             "dem_batch_read_state": ([P, C.c_int32, P, P, P, P, P], st),
             "dem_batch_read_contacts": ([P, C.c_int32, I64, C.POINTER(I64), P, P], st),
@@ -170,12 +171,12 @@ class System:
         else:
             hist_pairs = hist_dt = None
         self.device = torch.device(device)
-        nbytes = dem_workspace_bytes(params, n)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        _check(L.dem_create(C.byref(self._p), n, _ptr(x), _ptr(v), _ptr(omega), _ptr(r), _ptr(F0), _ptr(T0), nh,
-                            _ptr(hist_pairs), _ptr(hist_dt), C.c_void_p(self.workspace.data_ptr()), nbytes,
+        nbytes = dem_workspace_bytes(params, n)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(L.dem_create(C.byref(self._p), n, _ptr(x), _ptr(v), _ptr(omega), _ptr(r), _ptr(F0), _ptr(T0),
+                            nh, _ptr(hist_pairs), _ptr(hist_dt), C.c_void_p(self.workspace.data_ptr()), nbytes,
                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "dem_create")
         self._h = h
 
@@ -293,8 +294,10 @@ class Batch:
     of ``dem_batch_create`` plus its torch workspace and its own stream.
 
     ``systems`` is a list of dicts with keys params, x, v, omega, r (one
-    system each; ids are local to the system).  All systems share the
-    contact law and the precision."""
+    system each; ids are local to the system) and, to restart a system
+    exactly, F, T (its last forces) and hist_pairs, hist_dt (its committed
+    tangential history, as ``read_contacts`` returns it).  All systems share
+    the contact law and the precision."""
 
     def __init__(self, systems, device="cuda", stream=None):
         import torch
@@ -313,6 +316,18 @@ class Batch:
         x, v, w = cat3("x"), cat3("v"), cat3("omega")
         r = np.ascontiguousarray(np.concatenate(rs))
         n = np.asarray(self.ns, dtype=np.int64)
+        F0 = T0 = None
+        if any("F" in s for s in systems):
+            if not all("F" in s and "T" in s for s in systems):
+                raise ValueError("restart forces F, T are given for every system or for none")
+            F0, T0 = cat3("F"), cat3("T")
+        n_hist = hp = hd = None
+        if any(s.get("hist_pairs") is not None for s in systems):
+            pairs = [np.asarray(s.get("hist_pairs", np.zeros((0, 2))), dtype=np.int64).reshape(-1, 2) for s in systems]
+            dts = [np.asarray(s.get("hist_dt", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3) for s in systems]
+            n_hist = np.ascontiguousarray([len(q) for q in pairs], dtype=np.int64)
+            hp = np.ascontiguousarray(np.concatenate(pairs) if n_hist.sum() else np.zeros((1, 2), np.int64))
+            hd = np.ascontiguousarray(np.concatenate(dts) if n_hist.sum() else np.zeros((1, 3)))
         self.device = torch.device(device)
         nbytes = dem_batch_workspace_bytes(self.params, n)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -322,6 +337,7 @@ class Batch:
         self.stream = stream
         h = C.c_void_p()
         _check(L.dem_batch_create(self.S, _params_array(self.params), _ptr(n), _ptr(x), _ptr(v), _ptr(w), _ptr(r),
+                                  _ptr(F0), _ptr(T0), _ptr(n_hist), _ptr(hp), _ptr(hd),
                                   C.c_void_p(self.workspace.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream),
                                   C.byref(h)), "dem_batch_create")
         self._h = h
@@ -351,6 +367,13 @@ class Batch:
 
     def sync(self):
         _check(lib().dem_batch_sync(self.handle), "dem_batch_sync")
+
+    def set_radii(self, radii):
+        """New radii for every system (a list of per-system arrays)."""
+        r = np.ascontiguousarray(np.concatenate([np.asarray(q, dtype=np.float64).reshape(-1) for q in radii]))
+        if [len(np.asarray(q).reshape(-1)) for q in radii] != self.ns:
+            raise ValueError("set_radii: one radius per particle of every system")
+        _check(lib().dem_batch_set_radii(self.handle, _ptr(r)), "dem_batch_set_radii")
 
     def use_graph(self, enable: bool = True):
         _check(lib().dem_batch_use_graph(self.handle, int(bool(enable))), "dem_batch_use_graph")

@@ -21,7 +21,8 @@ Parameter dictionary keys (each side marshals them into its own structure):
   eta_t_ratio        tangential damping as a fraction of the normal one
   mu                 Coulomb friction coefficient (Eq. 5)
   cell_size          requested cell width of the collision-detection grid
-  contacts_per_particle  contact-list capacity per particle, on average (GPU only)
+  contacts_per_particle  most contacts one particle may own: partners after it in the
+                     sorted order plus walls (GPU only; sizes the contact tables)
   tile_cells         detection launch shape: 0 one lane per particle, -1 one wave
                      per run of cells, 1..32 cells per LDS-staged workgroup
                      (GPU only; speed only)
@@ -223,7 +224,7 @@ def dense_bed_geometry(seed=3000, n=1 << 24, phi=0.55, median=1.0 / 512.0, sigma
 def dense_bed_params(r, hi, **kw):
     r_min = float(np.min(r))
     p = base_params(box_hi=hi, cell_size=2.0 * float(np.max(r)), precision="mixed",
-                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=8)
+                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=16)
     p.update(kw)
     return p
 
@@ -298,31 +299,39 @@ def system_draw(rng, n_lo, n_hi):
 
 
 def unit_box_system(seed, n, kn, restitution, mu, phi, precision="mixed", law="linear", cell_factor=1.0,
-                    contacts_per_particle=8, tile_cells=0, cell_divisor=1):
+                    contacts_per_particle=16, tile_cells=0, cell_divisor=1):
     """One system of the batched and serving workloads: n spheres with radii
     U[0.8, 1.2] r_s in a walled unit box, r_s set so that the spheres fill the
     packing fraction phi, on a jittered FCC lattice, v ~ N(0, 0.1^2) per axis,
     omega = 0, gravity -9.81 z, kt = 2/7 kn, dt = t_c,min / 10 (at most
-    1e-5), cell = cell_factor x the largest diameter.  Where the lattice
-    cannot hold the spheres at phi without overlaps, every radius is scaled
-    down to the touching scale (the achieved phi is returned as phi_start)."""
+    1e-5), cell = cell_factor x the largest diameter.
+
+    Where the lattice cannot hold the spheres at phi without overlaps (above
+    a packing fraction of about 0.44 for these radii), the spheres start at
+    the largest common scale of their drawn radii that the lattice holds: `r`
+    is then that starting size and `r_target` the drawn radii, which
+    ``prepare.grow_systems`` reaches by growing the packing; phi_start is the
+    packing fraction of `r`.  The parameters (cell, dt) are those of the
+    drawn radii."""
     rng = np.random.default_rng(seed)
     r_s = (phi / (n * 4.0 / 3.0 * math.pi * E_U3)) ** (1.0 / 3.0)
-    r = rng.uniform(0.8 * r_s, 1.2 * r_s, size=n)
-    r_max = float(r.max()) if n else r_s
+    r_draw = rng.uniform(0.8 * r_s, 1.2 * r_s, size=n)
+    r_max = float(r_draw.max()) if n else r_s
     x, d_nn = fcc_fill(rng, n, (0, 0, 0), (1, 1, 1), margin=r_max, jitter_frac=0.9)
-    lam = lattice_scale(r, d_nn) if n else 1.0
-    r = fp32_radii(r * lam)
+    lam = lattice_scale(r_draw, d_nn) if n else 1.0
+    r_full = fp32_radii(r_draw)
+    r = fp32_radii(r_draw * lam) if lam < 1.0 else r_full
     v = rng.normal(0.0, 0.1, size=(n, 3))
     w = np.zeros((n, 3))
-    r_min = float(r.min()) if n else r_s
-    dmax = 2.0 * (float(r.max()) if n else r_s)
+    r_min = float(r_full.min()) if n else r_s
+    dmax = 2.0 * (float(r_full.max()) if n else r_s)
     p = base_params(kn=kn, kt=2.0 / 7.0 * kn, restitution=restitution, mu=mu, law=law, precision=precision,
                     dt=stable_dt(kn, restitution, r_min), cell_size=min(1.0, cell_factor * dmax),
                     contacts_per_particle=contacts_per_particle, tile_cells=tile_cells,
                     cell_divisor=cell_divisor)
     phi_start = float(np.sum(4.0 / 3.0 * math.pi * r ** 3))
-    return dict(name=f"system_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r, phi=phi, phi_start=phi_start)
+    return dict(name=f"system_{n}_{seed}", params=p, x=x, v=v, omega=w, r=r, phi=phi, phi_start=phi_start,
+                r_target=r_full if lam < 1.0 else None)
 
 
 def batched_draws(seed=4000, count=256, n_lo=1024, n_hi=262144):

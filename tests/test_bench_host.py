@@ -21,11 +21,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_byte_models():
-    # detection: per sphere 16 + 24 + 4 + 4 bytes plus 4 per owned entry, cell starts once
-    assert bench.detect_bytes(10, 7, 2.0) == 10 * (40 + 8) + 4 * 8
-    # law: per contact slots, history read and written, force record; per sphere its record
-    assert bench.pair_force_bytes(10, 20, 4) == 20 * (16 + 48) + 10 * (36 + 24)
-    assert bench.pair_force_bytes(10, 20, 8) == 20 * (16 + 96) + 10 * (36 + 48)
+    # detection + law: per sphere candidate record 8, packed state 40 + 6R, cell 4, two counts 8;
+    # per contact list entry 4, history read and written 2 (4 + 3R), force record 6R,
+    # backward entry and count 8; cell starts once
+    assert bench.contacts_bytes(10, 7, 20, 4) == 10 * (8 + 64 + 4 + 8) + 20 * (4 + 32 + 24 + 8) + 4 * 8
+    assert bench.contacts_bytes(10, 7, 20, 8) == 10 * (8 + 88 + 4 + 8) + 20 * (4 + 56 + 48 + 8) + 4 * 8
+    # gather: per sphere state in 40 + 6R and out 36 + 6R, counts 12; per contact two record reads and an entry
+    assert bench.gather_bytes(10, 20, 4) == 10 * (64 + 60 + 12) + 20 * (48 + 4)
     # whole step: B = 2 state + 16 + 3 + Z (4 + 3R); 131 + 16 Z bytes in mixed precision
     assert bench.step_algorithmic_bytes(1, 0.0, 4) == 131
     assert bench.step_algorithmic_bytes(1, 6.0, 4) == pytest.approx(131 + 16 * 6)
