@@ -10,6 +10,13 @@ requests whose steps are done.  Groups run concurrently on their streams, so
 requests that arrive while others run are admitted as soon as memory and
 slots allow and their work overlaps with the running ones.
 
+A group whose members finish at different times is compacted at the chunk
+boundary after a member finishes: the survivors' exact state (positions,
+velocities, spins, last forces and tangential history) is read back and a
+new, smaller group is built from it, so that the finished members' memory and
+slots go back to the pool while the others run on (a restart from that state
+is bitwise the uninterrupted run).
+
 A system's arithmetic does not depend on its group or on how its steps are
 chunked, so a request's result is the same as the system stepped alone.  If a
 group fails (a contact-list overflow, a particle out of the domain, a
@@ -112,6 +119,7 @@ class Server:
         self.iterations = 0
         self.peak_bytes = 0
         self.peak_slots = 0
+        self.compactions = 0
 
     def run(self, requests):
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
@@ -190,19 +198,46 @@ class Server:
                     waiting.extendleft(reversed(retry))
                     continue
                 g.left = [max(0, l - self.chunk) for l in g.left]
+                finished = 0
                 for k, (m, l) in enumerate(zip(g.members, g.left)):
                     if l == 0 and m.result is None:
                         m.result = g.handle.read_state(k)
                         m.t_done = self.clock() - t0
                         done.append(m)
+                        finished += 1
                 if all(l == 0 for l in g.left):
                     g.handle.close()
                     used -= g.bytes
                     slots -= len(g.members)
+                elif finished:
+                    ng = self._compact(g)
+                    used += ng.bytes - g.bytes
+                    slots -= len(g.members) - len(ng.members)
+                    keep.append(ng)
                 else:
                     keep.append(g)
             live = keep
         return done
+
+    def _compact(self, g):
+        """A new group of g's unfinished members, started from their exact
+        current state; g is closed."""
+        systems, members, left = [], [], []
+        for k, (m, l) in enumerate(zip(g.members, g.left)):
+            if l == 0:
+                continue
+            st = g.handle.read_state(k)
+            pairs, dts = g.handle.read_contacts(k)
+            systems.append(dict(m.system, x=st["x"], v=st["v"], omega=st["omega"], F=st["F"], T=st["T"],
+                                hist_pairs=pairs, hist_dt=dts))
+            members.append(m)
+            left.append(l)
+        nbytes = self.ex.workspace_bytes(systems)
+        g.handle.close()
+        ng = _Group(self.ex.start(systems), members, nbytes)
+        ng.left = left
+        self.compactions += 1
+        return ng
 
     def _start(self, members, nbytes, t0):
         handle = self.ex.start([m.system for m in members])

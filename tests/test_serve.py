@@ -28,7 +28,8 @@ class Clock:
 
 class OracleGroup:
     def __init__(self, systems, clock):
-        self.sys = [OracleSystem(s["params"], s["x"], s["v"], s["omega"], s["r"]) for s in systems]
+        self.sys = [OracleSystem(s["params"], s["x"], s["v"], s["omega"], s["r"], F0=s.get("F"), T0=s.get("T"),
+                                 hist_pairs=s.get("hist_pairs"), hist_dt=s.get("hist_dt")) for s in systems]
         self.clock = clock
         self.err = None
 
@@ -47,6 +48,9 @@ class OracleGroup:
 
     def read_state(self, k):
         return self.sys[k].read_state()
+
+    def read_contacts(self, k):
+        return self.sys[k].read_contacts()
 
     def close(self):
         self.sys = []
@@ -136,6 +140,32 @@ def test_a_failing_request_fails_alone():
             assert r.error is None
             ref = alone(r.system, r.steps)
             assert np.array_equal(r.result["x"], ref["x"])
+
+
+def test_a_finished_member_frees_its_share_for_a_waiting_request():
+    """A short request admitted beside a long one: when the short one
+    finishes, the group is compacted to the long one alone, its memory goes
+    back to the pool and the waiting request is admitted while the long one
+    still runs; every result is still bitwise the request stepped alone."""
+    clk = Clock()
+    ex = OracleExecutor(clk)
+    reqs = make_requests(count=3, seed=19)
+    long_, short, late = reqs
+    long_.steps, short.steps, late.steps = 60, 5, 10
+    for r in reqs:
+        r.arrival = 0.0
+    budget = ex.workspace_bytes([long_.system, short.system])  # the third never fits beside both
+    assert budget < ex.workspace_bytes([long_.system, short.system, late.system])
+    assert budget >= ex.workspace_bytes([long_.system]) + ex.workspace_bytes([late.system])
+    srv = serve.Server(ex, hbm_budget=budget, max_slots=8, chunk=5, clock=clk, sleep=clk.sleep)
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert srv.compactions >= 1 and srv.peak_bytes <= budget
+    assert done[late.rid].t_admit < done[long_.rid].t_done
+    for r in done.values():
+        assert r.error is None
+        ref = alone(r.system, r.steps)
+        for key in ("x", "v", "omega"):
+            assert np.array_equal(r.result[key], ref[key]), (r.rid, key)
 
 
 def test_oversized_request_is_rejected_not_stuck():
