@@ -92,6 +92,16 @@ typedef struct {
     int64_t a, b; /* a < b, or b = -1-w for wall w */
 } orc_contact;
 
+/* Contact constants of one pair of materials (Sec. 3: the C_kn, C_kt and
+ * alpha of Eqs. 8-10 carry the indices of the two particles' materials, and
+ * so does the friction coefficient of Eq. 5 here): the springs (linear law)
+ * or the Hertz constants, alpha from the pair's restitution, mu. */
+typedef struct {
+    double kn, kt, alpha, mu;
+} orc_pairk;
+
+enum { ORC_MAX_TYPES = 16 };
+
 typedef struct {
     orc_params p;
     int64_t n;
@@ -104,7 +114,20 @@ typedef struct {
     orc_hentry *H;
     int64_t nH;
     int64_t steps;
+    /* material-pair table: ntypes = 0 means one material (the orc_params
+     * constants); otherwise type[i] is particle i's material, walls are of
+     * material wall_type, and mat[t * ntypes + u] holds the pair (t, u) */
+    int32_t ntypes, wall_type;
+    int32_t *type;
+    orc_pairk *mat;
 } orc_sys;
+
+/* Eq. 10's alpha for restitution e: -2 ln e / sqrt(pi^2 + ln^2 e), which
+ * makes a linear contact's restitution exactly e (no damping at e = 1) */
+static double alpha_of(double e)
+{
+    return e >= 1.0 ? 0.0 : -2.0 * log(e) / sqrt(M_PI * M_PI + log(e) * log(e));
+}
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                                */
@@ -312,13 +335,30 @@ static void wall_geom(const orc_sys *s, int64_t a, int w, orc_geom *G)
     G->M = s->m[a];
 }
 
-/* Eqs. 2, 4-10 for one contact.  h is the previous tangential displacement
- * delta_t,old (zero for a new contact).  Returns the total force on i (F),
- * its tangential part (Ft, which sets the torque of Eq. 3) and the new
- * tangential displacement (dt_new).  Also the normal and tangential
- * stiffness actually used, for the elastic-energy diagnostic. */
-static void contact_law(const orc_sys *s, const orc_geom *G, const double h[3], double F[3], double Ft[3],
-                        double dt_new[3], double *kn_out, double *kt_out)
+/* The contact constants of particle a with partner b (b = -1-w: wall w):
+ * the system's one material, or the entry of the two materials in the
+ * material-pair table. */
+static orc_pairk pair_consts(const orc_sys *s, int64_t a, int64_t b)
+{
+    orc_pairk k;
+    if (s->ntypes == 0) {
+        k.kn = s->p.kn;
+        k.kt = s->p.kt;
+        k.alpha = s->alpha;
+        k.mu = s->p.mu;
+        return k;
+    }
+    int32_t ta = s->type[a], tb = b >= 0 ? s->type[b] : s->wall_type;
+    return s->mat[(int64_t)ta * s->ntypes + tb];
+}
+
+/* Eqs. 2, 4-10 for one contact with constants K.  h is the previous
+ * tangential displacement delta_t,old (zero for a new contact).  Returns the
+ * total force on i (F), its tangential part (Ft, which sets the torque of
+ * Eq. 3) and the new tangential displacement (dt_new).  Also the normal and
+ * tangential stiffness actually used, for the elastic-energy diagnostic. */
+static void contact_law(const orc_sys *s, const orc_pairk *K, const orc_geom *G, const double h[3], double F[3],
+                        double Ft[3], double dt_new[3], double *kn_out, double *kt_out)
 {
     const orc_params *p = &s->p;
     double vn_s = dot3(G->v, G->n);
@@ -346,13 +386,13 @@ static void contact_law(const orc_sys *s, const orc_geom *G, const double h[3], 
     double kn, kt;
     if (p->law == ORC_HERTZ) { /* Eqs. 8-9 */
         double q = sqrt(G->delta * G->R);
-        kn = p->kn * q;
-        kt = p->kt * q;
+        kn = K->kn * q;
+        kt = K->kt * q;
     } else {
-        kn = p->kn;
-        kt = p->kt;
+        kn = K->kn;
+        kt = K->kt;
     }
-    double eta = s->alpha * sqrt(kn * G->M); /* Eq. 10 */
+    double eta = K->alpha * sqrt(kn * G->M); /* Eq. 10 */
     double eta_t = p->eta_t_ratio * eta;
     double hn = dot3(h, G->n);
     double Fn[3];
@@ -362,8 +402,8 @@ static void contact_law(const orc_sys *s, const orc_geom *G, const double h[3], 
         Ft[k] = -kt * dt_new[k] - eta_t * vt[k];              /* Eq. 4, tangential */
     }
     double ftn = norm3(Ft), fnn = norm3(Fn);
-    if (ftn > p->mu * fnn) { /* Eq. 5 */
-        double scale = p->mu * fnn / ftn;
+    if (ftn > K->mu * fnn) { /* Eq. 5 */
+        double scale = K->mu * fnn / ftn;
         for (int k = 0; k < 3; k++) Ft[k] *= scale;
         if (kt > 0.0)
             for (int k = 0; k < 3; k++) dt_new[k] = -(Ft[k] + eta_t * vt[k]) / kt;
@@ -445,7 +485,8 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
         double zero[3] = {0.0, 0.0, 0.0};
         const double *h = he ? he->d : zero;
         double Fc[3], Ft[3], dtn[3], kn, kt;
-        contact_law(s, &G, h, Fc, Ft, dtn, &kn, &kt);
+        const orc_pairk K = pair_consts(s, a, b);
+        contact_law(s, &K, &G, h, Fc, Ft, dtn, &kn, &kt);
         double nxft[3];
         cross3(G.n, Ft, nxft);
         for (int q = 0; q < 3; q++) {
@@ -474,7 +515,7 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
             /* elastic energy of the contact, with the committed history */
             double en;
             if (s->p.law == ORC_HERTZ)
-                en = 0.4 * s->p.kn * sqrt(G.R) * pow(G.delta, 2.5) + 0.5 * kt * dot3(h, h);
+                en = 0.4 * K.kn * sqrt(G.R) * pow(G.delta, 2.5) + 0.5 * kt * dot3(h, h);
             else if (s->p.law == ORC_SIMPLE)
                 en = 0.5 * s->p.k_sp * G.delta * G.delta;
             else
@@ -542,6 +583,8 @@ void orc_destroy(orc_sys *s)
     free(s->m);
     free(s->I);
     free(s->H);
+    free(s->type);
+    free(s->mat);
     free(s);
 }
 
@@ -624,7 +667,7 @@ int orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
         orc_destroy(s);
         return ORC_E_INVALID;
     }
-    s->alpha = p->e >= 1.0 ? 0.0 : -2.0 * log(p->e) / sqrt(M_PI * M_PI + log(p->e) * log(p->e));
+    s->alpha = alpha_of(p->e);
     if (nh > 0 && p->law != ORC_SIMPLE) {
         if (!hist_pairs || !hist_dt) {
             orc_destroy(s);
@@ -838,3 +881,55 @@ int orc_diagnostics(orc_sys *s, double out[10])
 }
 
 int64_t orc_num_cells(const orc_sys *s) { return s ? s->ncell : -1; }
+
+/* Material-pair table (Sec. 3, the (i, j) indices of Eqs. 8-10).  ntypes
+ * materials, 1 <= ntypes <= ORC_MAX_TYPES; table holds ntypes x ntypes rows
+ * (kn, kt, restitution, mu), row t * ntypes + u for a particle of material t
+ * touching one of material u, and must be symmetric (the pair's constants
+ * do not depend on which side is looked from); type[i] is particle i's
+ * material (input order); walls are of material wall_type.  The law
+ * switches to the table, and the forces of the current state are evaluated
+ * again with it (with the committed history, which is kept), as if the
+ * system had been created with these materials.  ntypes = 0 goes back to the
+ * parameters' single material. */
+int orc_set_materials(orc_sys *s, int32_t ntypes, const double *table, const int32_t *type, int32_t wall_type)
+{
+    if (!s || ntypes < 0 || ntypes > ORC_MAX_TYPES) return ORC_E_INVALID;
+    int32_t *ty = NULL;
+    orc_pairk *mat = NULL;
+    if (ntypes > 0) {
+        if (!table || (s->n > 0 && !type) || wall_type < 0 || wall_type >= ntypes) return ORC_E_INVALID;
+        for (int32_t t = 0; t < ntypes; t++)
+            for (int32_t u = 0; u < ntypes; u++) {
+                const double *q = table + 4 * ((int64_t)t * ntypes + u), *qt = table + 4 * ((int64_t)u * ntypes + t);
+                if (!(q[0] > 0.0) || !(q[1] >= 0.0) || !(q[2] > 0.0 && q[2] <= 1.0) || !(q[3] >= 0.0) ||
+                    !isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[3]))
+                    return ORC_E_INVALID;
+                for (int c = 0; c < 4; c++)
+                    if (q[c] != qt[c]) return ORC_E_INVALID;
+            }
+        for (int64_t i = 0; i < s->n; i++)
+            if (type[i] < 0 || type[i] >= ntypes) return ORC_E_INVALID;
+        ty = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
+        mat = (orc_pairk *)malloc(sizeof(orc_pairk) * (size_t)ntypes * (size_t)ntypes);
+        if (!ty || !mat) {
+            free(ty);
+            free(mat);
+            return ORC_E_NOMEM;
+        }
+        if (s->n > 0) memcpy(ty, type, sizeof(int32_t) * (size_t)s->n);
+        for (int64_t q = 0; q < (int64_t)ntypes * ntypes; q++) {
+            mat[q].kn = table[4 * q];
+            mat[q].kt = table[4 * q + 1];
+            mat[q].alpha = alpha_of(table[4 * q + 2]);
+            mat[q].mu = table[4 * q + 3];
+        }
+    }
+    free(s->type);
+    free(s->mat);
+    s->type = ty;
+    s->mat = mat;
+    s->ntypes = ntypes;
+    s->wall_type = ntypes > 0 ? wall_type : 0;
+    return evaluate(s, s->F, s->T, 0, NULL, NULL, NULL, NULL, NULL, NULL);
+}

@@ -67,6 +67,8 @@ def lib():
         L.orc_diagnostics.restype = C.c_int
         L.orc_num_cells.argtypes = [P]
         L.orc_num_cells.restype = C.c_int64
+        L.orc_set_materials.argtypes = [P, C.c_int32, P, P, C.c_int32]
+        L.orc_set_materials.restype = C.c_int
         L.orc_destroy.argtypes = [P]
         L.orc_destroy.restype = None
         _LIB = L
@@ -198,3 +200,20 @@ class OracleSystem:
         out = (C.c_double * 10)()
         self._check(lib().orc_diagnostics(self._h, out), "diagnostics")
         return np.array(out[:])
+
+    def set_materials(self, types, table, wall_type=0):
+        """Material-pair table: table[t, u] = (kn, kt, restitution, mu) of a
+        particle of material t touching one of material u (symmetric),
+        types[i] the material of particle i (input order), walls of material
+        wall_type.  types=None goes back to the parameters' one material."""
+        if types is None:
+            self._check(lib().orc_set_materials(self._h, 0, None, None, 0), "set_materials")
+            return
+        tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+        nt = tab.shape[0]
+        if tab.shape != (nt, nt, 4):
+            raise ValueError("table must be ntypes x ntypes x 4")
+        ty = np.ascontiguousarray(np.asarray(types, dtype=np.int32).reshape(-1))
+        if ty.shape[0] != self.n:
+            raise ValueError("one material per particle")
+        self._check(lib().orc_set_materials(self._h, nt, _ptr(tab), _ptr(ty), int(wall_type)), "set_materials")

@@ -31,11 +31,11 @@ MUTATIONS = {
                      "T[3 * a + q] += s->r[a] * nxft[q]; /* Eq. 3 */",
                      "T[3 * a + q] += s->r[a] * nxft[q] * 1.0001; /* Eq. 3 */"),
     "eta_mass": ("Eq. 10: eta = alpha sqrt(k M)",
-                 "double eta = s->alpha * sqrt(kn * G->M);",
-                 "double eta = s->alpha * sqrt(kn * G->M * 2.0);"),
+                 "double eta = K->alpha * sqrt(kn * G->M);",
+                 "double eta = K->alpha * sqrt(kn * G->M * 2.0);"),
     "alpha_factor": ("Eq. 10: alpha from the restitution coefficient",
-                     "-2.0 * log(p->e) / sqrt",
-                     "-1.0 * log(p->e) / sqrt"),
+                     "-2.0 * log(e) / sqrt",
+                     "-1.0 * log(e) / sqrt"),
     "no_cap_rescale": ("Eq. 5: delta_t rescaled when the Coulomb cap holds",
                        "for (int k = 0; k < 3; k++) dt_new[k] = -(Ft[k] + eta_t * vt[k]) / kt;",
                        ";"),
@@ -76,11 +76,26 @@ MUTATIONS = {
                            "term[4] = 0.5 * s->I[i] * dot3(w, w);",
                            "term[4] = 0.5 * s->m[i] * dot3(w, w);"),
     "hertz_energy_factor": ("Eqs. 8-9: Hertz elastic energy (2/5) K delta^(5/2)",
-                            "en = 0.4 * s->p.kn * sqrt(G.R) * pow(G.delta, 2.5)",
-                            "en = 0.5 * s->p.kn * sqrt(G.R) * pow(G.delta, 2.5)"),
+                            "en = 0.4 * K.kn * sqrt(G.R) * pow(G.delta, 2.5)",
+                            "en = 0.5 * K.kn * sqrt(G.R) * pow(G.delta, 2.5)"),
     "tangential_energy_dropped": ("Eq. 4: tangential spring energy k_t |delta_t|^2 / 2",
                                   "en = 0.5 * kn * G.delta * G.delta + 0.5 * kt * dot3(h, h);",
                                   "en = 0.5 * kn * G.delta * G.delta;"),
+    "material_self": ("Eqs. 8-10: the constants of the pair (i, j), not of i alone",
+                      "int32_t ta = s->type[a], tb = b >= 0 ? s->type[b] : s->wall_type;",
+                      "int32_t ta = s->type[a], tb = ta;"),
+    "material_wall": ("Step 8: a wall has its own material",
+                      "int32_t ta = s->type[a], tb = b >= 0 ? s->type[b] : s->wall_type;",
+                      "int32_t ta = s->type[a], tb = b >= 0 ? s->type[b] : 0;"),
+    "material_ignored": ("Eqs. 8-10: a material-pair table replaces the single material",
+                         "if (s->ntypes == 0) {",
+                         "if (1) {"),
+    "material_alpha": ("Eq. 10: alpha of the pair's restitution",
+                       "mat[q].alpha = alpha_of(table[4 * q + 2]);",
+                       "mat[q].alpha = s->alpha;"),
+    "material_mu": ("Eq. 5: the pair's friction coefficient",
+                    "mat[q].mu = table[4 * q + 3];",
+                    "mat[q].mu = s->p.mu;"),
     "history_side": ("Eq. 6: the history seen from the other particle is negated",
                      "const double *h = he ? he->d : zero;",
                      "double hneg[3]; if (he) { hneg[0]=-he->d[0]; hneg[1]=-he->d[1]; hneg[2]=-he->d[2]; } "

@@ -607,3 +607,164 @@ def test_energy_drift_plain_fp64_workload():
     assert np.max(np.abs(E - E[0])) / E[0] < 1e-4
     # the same drift against the kinetic energy, a far tighter scale
     assert np.max(np.abs(E - E[0])) / kin[0] < 1e-3
+
+
+# ------------------------------------------------------ material-pair tables
+# Sec. 3 writes the constants of Eqs. 8-10 as C_kn(i, j), C_kt(i, j) and
+# alpha(i, j): they belong to the pair of materials in contact.  Each pin
+# below is a closed form evaluated with the constants of one table entry
+# that differs from every other entry, so taking the wrong entry (one
+# side's own material, the wrong wall material, the system's single
+# material) moves the result far outside the tolerance.
+
+def material_table():
+    """Three materials; entry (t, u) = (kn, kt, restitution, mu), symmetric,
+    every off-diagonal entry distinct from the diagonal ones."""
+    T = np.zeros((3, 3, 4))
+    T[0, 0] = (1.0e5, 2.0 / 7.0 * 1.0e5, 0.9, 0.3)
+    T[1, 1] = (2.0e5, 2.0 / 7.0 * 2.0e5, 0.95, 0.5)
+    T[2, 2] = (8.0e5, 2.0 / 7.0 * 8.0e5, 0.8, 0.1)
+    T[0, 1] = T[1, 0] = (4.0e5, 2.0 / 7.0 * 4.0e5, 0.6, 0.2)
+    T[0, 2] = T[2, 0] = (3.0e5, 2.0 / 7.0 * 3.0e5, 0.7, 0.4)
+    T[1, 2] = T[2, 1] = (6.0e5, 2.0 / 7.0 * 6.0e5, 0.5, 0.25)
+    return T
+
+
+def test_two_materials_head_on():
+    """Spheres of materials 0 and 1 (different radii): restitution and
+    contact time of the linear law with the (0, 1) entry's k_n and e and
+    the pair's reduced mass."""
+    T = material_table()
+    kn, e = T[0, 1, 0], T[0, 1, 2]
+    ra, rb = 1.0 / 64.0, 1.3 / 64.0
+    M = sphere_mass(ra) * sphere_mass(rb) / (sphere_mass(ra) + sphere_mass(rb))
+    z = zeta_of_e(e)
+    tc = math.pi / (math.sqrt(kn / M) * math.sqrt(1 - z * z))
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * rb, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=0.9, kt=0.0)
+    u = 0.05
+    s = two_spheres(p, ra, u, rb=rb)
+    s.set_materials([0, 1], T, wall_type=2)
+    S = float(np.float32(ra)) + float(np.float32(rb))
+    t, states = crossing_times(s, 6000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - S)
+    assert len(t) == 2
+    v = states[-1]["v"]
+    e_meas = (v[1, 0] - v[0, 0]) / (2 * u)
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    assert abs(e_meas - e) / e < 1e-3
+
+
+def test_material_against_wall_material():
+    """A sphere of material 1 bouncing on a floor of material 2: the (1, 2)
+    entry's restitution and contact time with the sphere's mass."""
+    T = material_table()
+    kn, e = T[1, 2, 0], T[1, 2, 2]
+    r = 1.0 / 64.0
+    m = sphere_mass(r)
+    z = zeta_of_e(e)
+    tc = math.pi / (math.sqrt(kn / m) * math.sqrt(1 - z * z))
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=1 << 4, dt=dt, restitution=0.9)
+    u = 0.05
+    rr = float(np.float32(r))
+    s = OracleSystem(p, [[0.5, 0.5, rr + 1e-7]], [[0, 0, -u]], [[0, 0, 0]], [r])
+    s.set_materials([1], T, wall_type=2)
+    t, states = crossing_times(s, 6000, dt, lambda st: st["x"][0, 2] - rr)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    assert abs(states[-1]["v"][0, 2] / u - e) / e < 1e-3
+
+
+def test_material_static_rest_and_friction():
+    """Materials 0 and 1 resting on a floor of material 2: each sinks to
+    m g / k_n of its own (t, 2) entry; launched sliding with no spin, each
+    decelerates at mu g with its own entry's mu."""
+    T = material_table()
+    r, g = 1.0 / 64.0, 9.81
+    m = sphere_mass(r)
+    rr = float(np.float32(r))
+    dt = 2e-6
+    p = W.base_params(cell_size=2 * r, box_hi=(0.4, 0.2, 0.2), dt=dt, eta_t_ratio=1.0)
+    z0 = [rr - m * g / T[t, 2, 0] for t in (0, 1)]
+    x = [[0.05, 0.05, z0[0]], [0.05, 0.15, z0[1]]]
+    s = OracleSystem(p, x, np.zeros((2, 3)), np.zeros((2, 3)), [r, r])
+    s.set_materials([0, 1], T, wall_type=2)
+    s.step(20000)
+    st = s.read_state()
+    for i, t in enumerate((0, 1)):
+        want = m * g / T[t, 2, 0]
+        assert abs((rr - st["x"][i, 2]) - want) / want < 1e-6
+    v0 = 0.1
+    v = np.array([[v0, 0, 0], [v0, 0, 0]])
+    s = OracleSystem(p, st["x"], v, np.zeros((2, 3)), [r, r])
+    s.set_materials([0, 1], T, wall_type=2)
+    tstar = min(2 * v0 / (7 * T[t, 2, 3] * g) for t in (0, 1))
+    ts, vx = [], []
+    chunk = 100
+    for k in range(int(0.8 * tstar / dt) // chunk):
+        ts.append(k * chunk * dt)
+        vx.append(s.read_state()["v"][:, 0].copy())
+        s.step(chunk)
+    vx = np.array(vx)
+    for i, t in enumerate((0, 1)):
+        slope = np.polyfit(ts, vx[:, i], 1)[0]
+        assert abs(slope + T[t, 2, 3] * g) / (T[t, 2, 3] * g) < 1e-3
+
+
+def test_hertz_two_materials_peak():
+    """Undamped Hertz contact of materials 0 and 2: peak overlap and
+    duration from K = C_kn(0, 2) sqrt(R)."""
+    T = material_table()
+    T[:, :, 2] = 1.0  # undamped
+    T[:, :, 0] *= 100.0  # Hertz constants C_kn
+    r = 1.0 / 64.0
+    rr = float(np.float32(r))
+    M = sphere_mass(r) / 2
+    K = T[0, 2, 0] * math.sqrt(rr / 2)
+    u = 0.1
+    v0 = 2 * u
+    dmax = (5 * M * v0 ** 2 / (4 * K)) ** 0.4
+    tc = 0.8 * beta_fn(0.4, 0.5) * dmax / v0
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=1.0,
+                      law="hertz", kn=1.0e7, kt=0.0)
+    s = two_spheres(p, r, u)
+    s.set_materials([0, 2], T, wall_type=1)
+    t, states = crossing_times(s, 6000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - 2 * rr)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    gaps = [np.linalg.norm(st["x"][1] - st["x"][0]) for st in states]
+    assert abs((2 * rr - min(gaps)) - dmax) / dmax < 1e-3
+
+
+def test_single_entry_table_is_the_single_material():
+    """A table whose every entry is the parameters' one material gives the
+    same bits as no table (the same constants by another route)."""
+    c = W.overlapping_cloud(21, 400, box=(0.3, 0.3, 0.3), r_mean=0.01, spacing=0.95, mu=0.3)
+    p = c["params"]
+    T = np.zeros((2, 2, 4))
+    T[:, :] = (p["kn"], p["kt"], p["restitution"], p["mu"])
+    a = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    b = OracleSystem(p, c["x"], c["v"], c["omega"], c["r"])
+    b.set_materials(np.arange(400) % 2, T, wall_type=1)
+    a.step(20)
+    b.step(20)
+    sa, sb = a.read_state(), b.read_state()
+    for k in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_material_table_validation():
+    T = material_table()
+    p = W.base_params(cell_size=0.1)
+    s = OracleSystem(p, [[0.5, 0.5, 0.5]], [[0, 0, 0]], [[0, 0, 0]], [0.01])
+    bad = T.copy()
+    bad[0, 1, 0] *= 2.0  # not symmetric
+    for args in ((bad, [0], 0), (T, [3], 0), (T, [0], 3), (T, [-1], 0)):
+        with pytest.raises(OracleError) as e:
+            s.set_materials(args[1], args[0], wall_type=args[2])
+        assert e.value.code == -1
+    bad = T.copy()
+    bad[1, 1, 2] = 1.5  # restitution outside (0, 1]
+    with pytest.raises(OracleError):
+        s.set_materials([0], bad, wall_type=0)
