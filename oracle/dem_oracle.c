@@ -66,6 +66,14 @@ enum {
     ORC_E_CAPACITY = -9
 };
 enum { ORC_LINEAR = 0, ORC_HERTZ = 1, ORC_SIMPLE = 2 };
+/* Optional contact terms, each added to the law's result on its own (the
+ * paper's C++ code is built so that a force term can be added or removed
+ * without touching the rest, Sec. 4; the terms themselves are not in the
+ * paper).  Practical law only. */
+enum {
+    ORC_TERM_COHESION = 1, /* constant attraction f_c along n while in contact */
+    ORC_TERM_ROLLING = 2   /* rolling resistance: couple -mu_r R |F_n| w_rel / |w_rel| */
+};
 
 typedef struct {
     double lo[3], hi[3];
@@ -79,6 +87,10 @@ typedef struct {
     double mu;
     double k_sp, k_da, k_sh; /* Eq. 1 */
     double cell;       /* requested cell width, >= 2 r_max */
+    int32_t terms;     /* ORC_TERM_* bits */
+    int32_t pad_;
+    double cohesion;   /* f_c (N) of ORC_TERM_COHESION */
+    double rolling_mu; /* mu_r of ORC_TERM_ROLLING */
 } orc_params;
 
 /* One history entry: the pair (a, b) with a < b seen from a, or the wall
@@ -300,6 +312,7 @@ typedef struct {
     double M;        /* m_i m_j / (m_i + m_j), or m_i for a wall */
     double v[3];     /* v_i - v_j */
     double spin[3];  /* r_i w_i + r_j w_j */
+    double wrel[3];  /* w_i - w_j (rolling resistance) */
 } orc_geom;
 
 static int pair_geom(const orc_sys *s, int64_t a, int64_t b, orc_geom *G)
@@ -313,6 +326,7 @@ static int pair_geom(const orc_sys *s, int64_t a, int64_t b, orc_geom *G)
         G->n[k] = dx[k] / d;
         G->v[k] = s->v[3 * a + k] - s->v[3 * b + k];
         G->spin[k] = s->r[a] * s->w[3 * a + k] + s->r[b] * s->w[3 * b + k];
+        G->wrel[k] = s->w[3 * a + k] - s->w[3 * b + k];
     }
     G->delta = S - d;
     G->R = s->r[a] * s->r[b] / S;
@@ -328,6 +342,7 @@ static void wall_geom(const orc_sys *s, int64_t a, int w, orc_geom *G)
         G->n[k] = 0.0;
         G->v[k] = s->v[3 * a + k];
         G->spin[k] = s->r[a] * s->w[3 * a + k];
+        G->wrel[k] = s->w[3 * a + k];
     }
     G->n[axis] = (w & 1) ? 1.0 : -1.0;
     G->delta = s->r[a] - gap;
@@ -356,9 +371,10 @@ static orc_pairk pair_consts(const orc_sys *s, int64_t a, int64_t b)
  * tangential displacement delta_t,old (zero for a new contact).  Returns the
  * total force on i (F), its tangential part (Ft, which sets the torque of
  * Eq. 3) and the new tangential displacement (dt_new).  Also the normal and
- * tangential stiffness actually used, for the elastic-energy diagnostic. */
+ * tangential stiffness actually used, for the elastic-energy diagnostic, and
+ * |F_n| of Eq. 4 (the magnitude Eq. 5 compares with). */
 static void contact_law(const orc_sys *s, const orc_pairk *K, const orc_geom *G, const double h[3], double F[3],
-                        double Ft[3], double dt_new[3], double *kn_out, double *kt_out)
+                        double Ft[3], double dt_new[3], double *kn_out, double *kt_out, double *fn_out)
 {
     const orc_params *p = &s->p;
     double vn_s = dot3(G->v, G->n);
@@ -381,6 +397,7 @@ static void contact_law(const orc_sys *s, const orc_pairk *K, const orc_geom *G,
         }
         *kn_out = p->k_sp;
         *kt_out = 0.0;
+        *fn_out = 0.0;
         return;
     }
     double kn, kt;
@@ -411,6 +428,29 @@ static void contact_law(const orc_sys *s, const orc_pairk *K, const orc_geom *G,
     for (int k = 0; k < 3; k++) F[k] = Fn[k] + Ft[k]; /* Eq. 2 */
     *kn_out = kn;
     *kt_out = kt;
+    *fn_out = fnn;
+}
+
+/* The optional terms of the contact, each added on its own after the law:
+ *  cohesion  F_i += f_c n: a constant pull towards the partner (or the wall)
+ *            while the bodies overlap; it does not enter Eq. 5's limit.
+ *  rolling   a couple C = -mu_r R |F_n| w_rel / |w_rel| on i and -C on the
+ *            partner (nothing on a wall), with R of Eqs. 8-9 (r_i for a
+ *            wall), |F_n| of Eq. 4 and w_rel = w_i - w_j; zero when
+ *            w_rel = 0.  This is the constant directional torque model of
+ *            rolling resistance, which also opposes spin about n.
+ * Neither is in the paper; they exercise the composition of force terms. */
+static void extra_terms(const orc_sys *s, const orc_geom *G, double fn, double F[3], double C[3])
+{
+    const orc_params *p = &s->p;
+    C[0] = C[1] = C[2] = 0.0;
+    if (p->terms & ORC_TERM_COHESION)
+        for (int k = 0; k < 3; k++) F[k] += p->cohesion * G->n[k];
+    if (p->terms & ORC_TERM_ROLLING) {
+        double wn = norm3(G->wrel);
+        if (wn > 0.0)
+            for (int k = 0; k < 3; k++) C[k] = -p->rolling_mu * G->R * fn * G->wrel[k] / wn;
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -484,17 +524,18 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
         const orc_hentry *he = hist_find(s, a, b);
         double zero[3] = {0.0, 0.0, 0.0};
         const double *h = he ? he->d : zero;
-        double Fc[3], Ft[3], dtn[3], kn, kt;
+        double Fc[3], Ft[3], dtn[3], kn, kt, fn, Cr[3];
         const orc_pairk K = pair_consts(s, a, b);
-        contact_law(s, &K, &G, h, Fc, Ft, dtn, &kn, &kt);
+        contact_law(s, &K, &G, h, Fc, Ft, dtn, &kn, &kt, &fn);
+        extra_terms(s, &G, fn, Fc, Cr);
         double nxft[3];
         cross3(G.n, Ft, nxft);
         for (int q = 0; q < 3; q++) {
             F[3 * a + q] += Fc[q];
-            T[3 * a + q] += s->r[a] * nxft[q]; /* Eq. 3 */
+            T[3 * a + q] += s->r[a] * nxft[q] + Cr[q]; /* Eq. 3, and the rolling couple */
             if (b >= 0) {
                 F[3 * b + q] -= Fc[q];
-                T[3 * b + q] += s->r[b] * nxft[q];
+                T[3 * b + q] += s->r[b] * nxft[q] - Cr[q];
             }
         }
         if (Fabs) {
@@ -503,8 +544,8 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
             if (b >= 0) Fabs[b] += fm;
         }
         if (Tabs) {
-            Tabs[a] += s->r[a] * norm3(nxft);
-            if (b >= 0) Tabs[b] += s->r[b] * norm3(nxft);
+            Tabs[a] += s->r[a] * norm3(nxft) + norm3(Cr);
+            if (b >= 0) Tabs[b] += s->r[b] * norm3(nxft) + norm3(Cr);
         }
         if (Hn) {
             Hn[k].a = a;
@@ -602,6 +643,10 @@ int orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
     if (!(p->dt > 0.0) || !(p->rho > 0.0) || !(p->cell > 0.0)) return ORC_E_INVALID;
     if (p->law < ORC_LINEAR || p->law > ORC_SIMPLE) return ORC_E_INVALID;
     if (!(p->e > 0.0 && p->e <= 1.0) || !(p->mu >= 0.0)) return ORC_E_INVALID;
+    if ((p->terms & ~(ORC_TERM_COHESION | ORC_TERM_ROLLING)) != 0) return ORC_E_INVALID;
+    if (p->terms && (p->law == ORC_SIMPLE || !isfinite(p->cohesion) || !(p->rolling_mu >= 0.0) ||
+                     !isfinite(p->rolling_mu)))
+        return ORC_E_INVALID;
     if (n > 2000000000) return ORC_E_INVALID;
     orc_sys *s = (orc_sys *)calloc(1, sizeof(orc_sys));
     if (!s) return ORC_E_NOMEM;

@@ -14,6 +14,7 @@ from . import build as _build
 _LIB = None
 
 LAWS = {"linear": 0, "hertz": 1, "simple": 2}
+TERMS = {"cohesion": 1, "rolling": 2}  # optional contact terms (params["terms"]: a tuple of names)
 STATUS = {0: "ok", -1: "invalid argument", -4: "particle out of domain", -5: "non-finite value",
           -8: "out of host memory", -9: "output capacity too small"}
 
@@ -34,6 +35,8 @@ class OrcParams(C.Structure):
         ("e", C.c_double), ("eta_t_ratio", C.c_double), ("mu", C.c_double),
         ("k_sp", C.c_double), ("k_da", C.c_double), ("k_sh", C.c_double),
         ("cell", C.c_double),
+        ("terms", C.c_int32), ("pad_", C.c_int32),
+        ("cohesion", C.c_double), ("rolling_mu", C.c_double),
     ]
 
 
@@ -92,6 +95,10 @@ def make_params(p: dict) -> OrcParams:
     sk = p.get("simple_k", (0.0, 0.0, 0.0))
     o.k_sp, o.k_da, o.k_sh = float(sk[0]), float(sk[1]), float(sk[2])
     o.cell = float(p["cell_size"])
+    o.terms = (TERMS["cohesion"] if "cohesion" in p.get("terms", ()) else 0) | \
+        (TERMS["rolling"] if "rolling" in p.get("terms", ()) else 0)
+    o.cohesion = float(p.get("cohesion", 0.0))
+    o.rolling_mu = float(p.get("rolling_mu", 0.0))
     return o
 
 

@@ -25,11 +25,11 @@ MUTATIONS = {
                       "dt_new[k] = h[k] - hn * G->n[k] + vt[k] * p->dt;",
                       "dt_new[k] = h[k] + vt[k] * p->dt;"),
     "torque_b_sign": ("Eq. 3: torque on the partner",
-                      "T[3 * b + q] += s->r[b] * nxft[q];",
-                      "T[3 * b + q] -= s->r[b] * nxft[q];"),
+                      "T[3 * b + q] += s->r[b] * nxft[q] - Cr[q];",
+                      "T[3 * b + q] += -s->r[b] * nxft[q] - Cr[q];"),
     "torque_scale": ("Eq. 3: torque lever arm r_i",
-                     "T[3 * a + q] += s->r[a] * nxft[q]; /* Eq. 3 */",
-                     "T[3 * a + q] += s->r[a] * nxft[q] * 1.0001; /* Eq. 3 */"),
+                     "T[3 * a + q] += s->r[a] * nxft[q] + Cr[q];",
+                     "T[3 * a + q] += s->r[a] * nxft[q] * 1.0001 + Cr[q];"),
     "eta_mass": ("Eq. 10: eta = alpha sqrt(k M)",
                  "double eta = K->alpha * sqrt(kn * G->M);",
                  "double eta = K->alpha * sqrt(kn * G->M * 2.0);"),
@@ -96,6 +96,21 @@ MUTATIONS = {
     "material_mu": ("Eq. 5: the pair's friction coefficient",
                     "mat[q].mu = table[4 * q + 3];",
                     "mat[q].mu = s->p.mu;"),
+    "cohesion_sign": ("cohesion pulls the bodies together",
+                      "F[k] += p->cohesion * G->n[k];",
+                      "F[k] -= p->cohesion * G->n[k];"),
+    "rolling_sign": ("rolling resistance opposes the relative spin",
+                     "C[k] = -p->rolling_mu * G->R * fn * G->wrel[k] / wn;",
+                     "C[k] = p->rolling_mu * G->R * fn * G->wrel[k] / wn;"),
+    "rolling_partner_sign": ("the rolling couple acts on the partner in the opposite sense",
+                             "T[3 * b + q] += s->r[b] * nxft[q] - Cr[q];",
+                             "T[3 * b + q] += s->r[b] * nxft[q] + Cr[q];"),
+    "rolling_lever": ("the rolling couple's lever arm is the effective radius",
+                      "C[k] = -p->rolling_mu * G->R * fn * G->wrel[k] / wn;",
+                      "C[k] = -p->rolling_mu * 2.0 * G->R * fn * G->wrel[k] / wn;"),
+    "rolling_total_normal": ("the rolling couple scales with Eq. 4's |F_n|, not the net normal force",
+                             "C[k] = -p->rolling_mu * G->R * fn * G->wrel[k] / wn;",
+                             "C[k] = -p->rolling_mu * G->R * fabs(dot3(F, G->n)) * G->wrel[k] / wn;"),
     "history_side": ("Eq. 6: the history seen from the other particle is negated",
                      "const double *h = he ? he->d : zero;",
                      "double hneg[3]; if (he) { hneg[0]=-he->d[0]; hneg[1]=-he->d[1]; hneg[2]=-he->d[2]; } "

@@ -768,3 +768,134 @@ def test_material_table_validation():
     bad[1, 1, 2] = 1.5  # restitution outside (0, 1]
     with pytest.raises(OracleError):
         s.set_materials([0], bad, wall_type=0)
+
+
+# ------------------------------------------------------ optional force terms
+# Terms added to the law on their own (cohesion, rolling resistance); not
+# from the paper, which only asks that a force term can be added or removed
+# without touching the rest (Sec. 4).  Each pin is a closed form of the term
+# alone or of the term with the law.
+
+def test_cohesion_static_rest():
+    """A sphere resting on the floor with a constant pull f_c towards it:
+    the overlap settles at (m g + f_c) / k_n."""
+    r, kn, fc = 1.0 / 64.0, 1.0e5, 0.05
+    m = sphere_mass(r)
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=0.5, dt=1e-5,
+                      terms=("cohesion",), cohesion=fc)
+    rr = float(np.float32(r))
+    s = OracleSystem(p, [[0.1, 0.1, rr]], [[0, 0, 0]], [[0, 0, 0]], [r])
+    s.step(8000)
+    delta = rr - s.read_state()["x"][0, 2]
+    want = (m * 9.81 + fc) / kn
+    assert abs(delta - want) / want < 1e-6
+
+
+def test_cohesion_undamped_head_on():
+    """Two equal spheres meeting at relative speed 2u with e = 1 and a
+    constant pull f_c: the overlap obeys M delta'' = -k_n delta + f_c, a
+    harmonic motion about delta_eq = f_c / k_n of amplitude
+    A = sqrt(delta_eq^2 + (2u / w)^2), w = sqrt(k_n / M); the contact lasts
+    (pi + 2 asin(delta_eq / A)) / w and the spheres leave at 2u."""
+    r, kn, fc, u = 1.0 / 64.0, 1.0e5, 2.0, 0.05
+    M = sphere_mass(r) / 2
+    w = math.sqrt(kn / M)
+    deq = fc / kn
+    A = math.sqrt(deq ** 2 + (2 * u / w) ** 2)
+    tc = (math.pi + 2 * math.asin(deq / A)) / w
+    dt = tc / 5000
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=1.0, kt=0.0,
+                      mu=0.0, terms=("cohesion",), cohesion=fc)
+    s = two_spheres(p, r, u)
+    S = 2 * float(np.float32(r))
+    t, states = crossing_times(s, 7000, dt, lambda st: np.linalg.norm(st["x"][1] - st["x"][0]) - S)
+    assert len(t) == 2
+    assert abs((t[1] - t[0]) - tc) / tc < 1e-3
+    v = states[-1]["v"]
+    assert abs((v[1, 0] - v[0, 0]) / (2 * u) - 1.0) < 1e-3
+    # without the pull the same collision is the plain half period
+    assert abs(tc * w / math.pi - 1.0) > 0.05
+
+
+def test_rolling_resistance_stops_a_spin_about_the_normal():
+    """A sphere resting on the floor, spinning about the vertical: no slip,
+    so no tangential force; the couple mu_r r |F_n| = mu_r r m g alone slows
+    the spin at 5/2 mu_r g / r (I = 2/5 m r^2)."""
+    r, mur, g, w0 = 1.0 / 64.0, 0.05, 9.81, 20.0
+    m = sphere_mass(r)
+    dt = 1e-5
+    p = W.base_params(cell_size=2 * r, box_hi=(0.2, 0.2, 0.2), restitution=0.5, dt=dt, mu=0.5,
+                      terms=("rolling",), rolling_mu=mur)
+    rr = float(np.float32(r))
+    z0 = rr - m * g / p["kn"]
+    s = OracleSystem(p, [[0.1, 0.1, z0]], [[0, 0, 0]], [[0, 0, w0]], [r])
+    rate = 2.5 * mur * g / rr
+    ts, wz = [], []
+    for k in range(int(0.8 * w0 / rate / dt) // 200):
+        st = s.read_state()
+        ts.append(k * 200 * dt)
+        wz.append(st["omega"][0, 2])
+        s.step(200)
+    slope = np.polyfit(ts, wz, 1)[0]
+    assert abs(-slope - rate) / rate < 1e-6
+    assert abs(st["omega"][0, 0]) + abs(st["omega"][0, 1]) < 1e-9 * w0
+
+
+def test_rolling_resistance_decelerates_a_rolling_sphere():
+    """A sphere rolling on the floor at v0 (w = v0 / r): the couple
+    mu_r r m g against the rolling, with friction keeping the contact point
+    at rest, gives dv/dt = -mu_r g r^2 m / (I + m r^2) = -5/7 mu_r g."""
+    r, mur, g, v0 = 1.0 / 64.0, 0.02, 9.81, 0.1
+    m = sphere_mass(r)
+    dt = 2e-6
+    p = W.base_params(cell_size=2 * r, box_hi=(0.4, 0.2, 0.2), restitution=0.5, dt=dt, mu=0.5,
+                      eta_t_ratio=1.0, terms=("rolling",), rolling_mu=mur)
+    rr = float(np.float32(r))
+    z0 = rr - m * g / p["kn"]
+    s = OracleSystem(p, [[0.05, 0.1, z0]], [[v0, 0, 0]], [[0, v0 / rr, 0]], [r])
+    a = 5.0 / 7.0 * mur * g
+    ts, vx = [], []
+    for k in range(int(0.5 * v0 / a / dt) // 500):
+        st = s.read_state()
+        ts.append(k * 500 * dt)
+        vx.append(st["v"][0, 0])
+        s.step(500)
+    slope = np.polyfit(ts, vx, 1)[0]
+    assert abs(-slope - a) / a < 1e-2
+    st = s.read_state()
+    assert abs(rr * st["omega"][0, 1] - st["v"][0, 0]) < 1e-3 * v0  # still rolling
+
+
+def test_rolling_couple_between_a_cohesive_pair():
+    """Two equal spheres held together by cohesion at rest (overlap f_c / k_n,
+    no gravity, no tangential spring or friction), one spinning: the
+    rolling couple mu_r (r/2) f_c acts on both in opposite senses, so the
+    total spin is conserved and the relative spin falls at mu_r r f_c / I."""
+    r, kn, fc, mur, w0 = 1.0 / 64.0, 1.0e5, 1.0, 0.05, 10.0
+    m = sphere_mass(r)
+    rr = float(np.float32(r))
+    I = 0.4 * m * rr * rr
+    deq = fc / kn
+    dt = 2e-6
+    p = W.base_params(cell_size=2 * r, gravity=(0, 0, 0), wall_mask=0, dt=dt, restitution=0.3, kt=0.0,
+                      mu=0.0, terms=("cohesion", "rolling"), cohesion=fc, rolling_mu=mur)
+    x = np.array([[0.5 - rr + deq / 2, 0.5, 0.5], [0.5 + rr - deq / 2, 0.5, 0.5]])
+    s = OracleSystem(p, x, np.zeros((2, 3)), np.array([[0, 0, w0], [0, 0, 0]], float), [r, r])
+    rate = mur * rr * fc / I
+    ts, wrel, wsum = [], [], []
+    for k in range(int(0.8 * w0 / rate / dt) // 200):
+        st = s.read_state()
+        ts.append(k * 200 * dt)
+        wrel.append(st["omega"][0, 2] - st["omega"][1, 2])
+        wsum.append(st["omega"][0, 2] + st["omega"][1, 2])
+        s.step(200)
+    assert np.max(np.abs(np.array(wsum) - w0)) < 1e-12 * w0
+    slope = np.polyfit(ts, wrel, 1)[0]
+    assert abs(-slope - rate) / rate < 1e-4
+    assert wrel[-1] < 0.5 * w0  # the couple did act
+
+
+def test_terms_are_refused_with_the_simple_law():
+    p = W.base_params(cell_size=0.1, law="simple", terms=("cohesion",), cohesion=1.0)
+    with pytest.raises(OracleError):
+        OracleSystem(p, [[0.5, 0.5, 0.5]], [[0, 0, 0]], [[0, 0, 0]], [0.01])
