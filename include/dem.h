@@ -129,6 +129,32 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
                       const int64_t *hist_pairs, const double *hist_dt, void *workspace, size_t ws_bytes,
                       void *hip_stream, dem_system **out);
 
+/* dem_create with no workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The workspace is a fixed array of
+ * dem_static_workspace_capacity() bytes (64 MiB) in the library's device
+ * code, one per device, which that device holds from the loading of the
+ * library's code object until the process ends; this call allocates no
+ * device memory (no hipMalloc, hipFree or other allocating call).
+ *   The device is the one current at the call, and hip_stream must belong
+ *   to it.
+ *   One such system per device at a time: both would use the one array, so
+ *   while a system made by this call lives (until dem_destroy, which waits
+ *   for its stream) another call on the same device returns DEM_E_STATE.
+ *   Calls on the system itself must not overlap, as for any system.
+ *   Nothing is inherited from the array's earlier contents: everything that
+ *   must start at zero is cleared by this call.
+ * Arguments other than the workspace, results and errors as dem_create,
+ * plus DEM_E_WORKSPACE when dem_workspace_bytes(p, n) exceeds the
+ * capacity. */
+dem_status dem_create_static(const dem_params *p, int64_t n, const double *x, const double *v,
+                             const double *omega, const double *r, const double *F0, const double *T0,
+                             int64_t n_hist, const int64_t *hist_pairs, const double *hist_dt, void *hip_stream,
+                             dem_system **out);
+
+/* Bytes of the per-device array behind dem_create_static. */
+size_t dem_static_workspace_capacity(void);
+
 /* Enqueue nsteps kick-drift-kick steps (Sec. 4.2, Steps 1-8 each).
  * Asynchronous; returns the sticky error if one is already known. */
 dem_status dem_step(dem_system *s, int64_t nsteps);

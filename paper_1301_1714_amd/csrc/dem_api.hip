@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -1048,7 +1049,28 @@ dem_status engine_profile_read(Engine &e, double ms[DEM_NUM_PHASES], int64_t *st
 
 struct dem_system {
   Engine *e;
+  int static_dev = -1;  // device whose static workspace it uses (dem_create_static), else -1
 };
+
+// The workspace of systems made by dem_create_static, for callers that
+// cannot allocate device memory: one array per device, loaded with the code
+// object and held until the process ends.  On the host the array's name is
+// only a stand-in for the device symbol, never an address: the device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept per device, and only that address is handed to
+// the kernels (through the same carving as a caller's workspace).
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+  void *ptr = nullptr;                // device address of the array on this device
+  const dem_system *owner = nullptr;  // the live system that uses it
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxDevices];
+}  // namespace
 struct dem_batch {
   Engine *e;
 };
@@ -1098,6 +1120,45 @@ dem_status dem_create(const dem_params *p, int64_t n, const double *x, const dou
   }
   s->e = e;
   *out = s;
+  return DEM_OK;
+}
+
+size_t dem_static_workspace_capacity(void) { return kStaticWorkspaceBytes; }
+
+dem_status dem_create_static(const dem_params *p, int64_t n, const double *x, const double *v,
+                             const double *omega, const double *r, const double *F0, const double *T0,
+                             int64_t n_hist, const int64_t *hist_pairs, const double *hist_dt, void *hip_stream,
+                             dem_system **out) {
+  if (!out) return DEM_E_INVALID;
+  *out = nullptr;
+  size_t need = 0;
+  dem_status st = dem_workspace_bytes(p, n, &need);
+  if (st != DEM_OK) return st;
+  if (need > kStaticWorkspaceBytes) return DEM_E_WORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return DEM_E_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return DEM_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot &slot = g_static[dev];
+  if (slot.owner) return DEM_E_STATE;  // the device's array is in use
+  if (!slot.ptr) {
+    void *ptr = nullptr;
+    const hipError_t r = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (r != hipSuccess || !ptr) {
+      report_hip(r, "hipGetSymbolAddress(scratch)", __LINE__);
+      (void)hipGetLastError();
+      return DEM_E_HIP;
+    }
+    slot.ptr = ptr;
+  }
+  st = dem_create(p, n, x, v, omega, r, F0, T0, n_hist, hist_pairs, hist_dt, slot.ptr, kStaticWorkspaceBytes,
+                  hip_stream, out);
+  if (st != DEM_OK) return st;
+  (*out)->static_dev = dev;
+  slot.owner = *out;
   return DEM_OK;
 }
 
@@ -1191,7 +1252,11 @@ dem_status dem_profile_read(dem_system *s, double ms[DEM_NUM_PHASES], int64_t *s
 
 dem_status dem_destroy(dem_system *s) {
   if (!s) return DEM_E_STATE;
-  release(s->e);
+  release(s->e);  // waits for the stream: nothing of the system runs after this
+  if (s->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static[s->static_dev].owner == s) g_static[s->static_dev].owner = nullptr;
+  }
   delete s;
   return DEM_OK;
 }

@@ -66,6 +66,8 @@ def lib():
         sig = {
             "dem_workspace_bytes": ([C.POINTER(DemParams), I64, C.POINTER(S)], st),
             "dem_create": ([C.POINTER(DemParams), I64, P, P, P, P, P, P, I64, P, P, P, S, P, C.POINTER(P)], st),
+            "dem_create_static": ([C.POINTER(DemParams), I64, P, P, P, P, P, P, I64, P, P, P, C.POINTER(P)], st),
+            "dem_static_workspace_capacity": ([], S),
             "dem_step": ([P, I64], st),
             "dem_forces": ([P, P, P], st),
             "dem_read_state": ([P, P, P, P, P, P], st),
@@ -144,12 +146,20 @@ def dem_workspace_bytes(params: dict, n: int) -> int:
     return b.value
 
 
+def dem_static_workspace_capacity() -> int:
+    """Bytes of the per-device array behind ``dem_create_static``."""
+    return int(lib().dem_static_workspace_capacity())
+
+
 class System:
     """One DEM system on the GPU: the handle of ``dem_create`` plus the torch
-    workspace that backs it."""
+    workspace that backs it, or with static=True the handle of
+    ``dem_create_static``, whose workspace is the library's per-device array
+    (no device memory is allocated for it; one such system per device at a
+    time)."""
 
     def __init__(self, params: dict, x, v, omega, r, F0=None, T0=None, hist_pairs=None, hist_dt=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, static=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -173,6 +183,14 @@ class System:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = C.c_void_p()
+        if static:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(L.dem_create_static(C.byref(self._p), n, _ptr(x), _ptr(v), _ptr(omega), _ptr(r), _ptr(F0),
+                                           _ptr(T0), nh, _ptr(hist_pairs), _ptr(hist_dt),
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)), "dem_create_static")
+            self._h = h
+            return
         nbytes = dem_workspace_bytes(params, n)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _check(L.dem_create(C.byref(self._p), n, _ptr(x), _ptr(v), _ptr(omega), _ptr(r), _ptr(F0), _ptr(T0),
