@@ -59,10 +59,38 @@ typedef enum {
                            tangential part of v, Sec. 3), no torque, no history */
 } dem_law;
 
+/* Optional contact terms (dem_params.terms), each added to the practical
+ * law's result on its own; the paper asks that a force term can be added or
+ * removed without touching the rest of the code (Sec. 4), and names none of
+ * these.  Not with DEM_LAW_SIMPLE. */
+typedef enum {
+    DEM_TERM_COHESION = 1, /* a constant pull `cohesion` (N) along n, towards the partner or the wall,
+                              while the bodies overlap (outside Eq. 5's limit) */
+    DEM_TERM_ROLLING = 2   /* rolling resistance: a couple -rolling_mu R |F_n| w_rel / |w_rel| on the
+                              owner and its opposite on the partner, w_rel = w_i - w_j (w_j = 0 for a
+                              wall), R of Eqs. 8-9 (r_i for a wall), |F_n| of Eq. 4 */
+} dem_term;
+
 typedef enum {
     DEM_PREC_FP64 = 0,  /* everything FP64 (radii FP32) */
     DEM_PREC_MIXED = 1  /* FP64 positions and reductions; FP32 v, w, forces, history */
 } dem_precision;
+
+/* A finite wall (for Sec. 5's box with a slit at its bottom: two plates side
+ * by side): the rectangle of the plane x[axis] = at spanning lo[0]..hi[0]
+ * along axis (axis + 1) % 3 and lo[1]..hi[1] along axis (axis + 2) % 3, of no
+ * thickness.  Like the walls of Step 8 it is a body of infinite radius and
+ * mass at rest: a sphere touches it where the rectangle's nearest point is
+ * closer than its radius (d^2 < r^2, FP64, no FMA); n points from the centre
+ * to that point, the overlap is r - d, R = r and M = m.  Plate k is wall
+ * 6 + k (contact key -7 - k). */
+#define DEM_MAX_PLATES 4
+typedef struct {
+    int32_t axis;     /* 0, 1 or 2 */
+    int32_t reserved; /* 0 */
+    double at;
+    double lo[2], hi[2];
+} dem_plate;
 
 /* Parameters of one system.  Sec. 3 names the contact-law inputs; the rest
  * (box, walls, gravity, cell, capacity, precision) is the setting of Sec. 4. */
@@ -101,6 +129,15 @@ typedef struct {
                                     contacts found never change; the sorted order, and so
                                     the rounding of the sums, does.  k > 1 needs
                                     tile_cells = 0 */
+    int32_t max_materials;       /* 0..16: the most materials dem_set_materials may give the
+                                    system (0: one material, the constants above; device
+                                    memory grows by 8 bytes per particle when > 0) */
+    uint32_t terms;              /* dem_term bits (0: the paper's law alone) */
+    double cohesion;             /* DEM_TERM_COHESION: the pull (N), finite */
+    double rolling_mu;           /* DEM_TERM_ROLLING: the coefficient, >= 0 */
+    int32_t nplates;             /* finite walls in plates[], 0..DEM_MAX_PLATES */
+    int32_t reserved;            /* 0 */
+    dem_plate plates[DEM_MAX_PLATES];
 } dem_params;
 
 typedef struct dem_system dem_system; /* opaque host-side handle */
@@ -203,6 +240,43 @@ dem_status dem_diagnostics(dem_system *s, double out[10]);
  * the largest radius wider than cell_size).  Synchronous. */
 dem_status dem_set_radii(dem_system *s, const double *r);
 
+/* Material-pair table (Sec. 3: the constants C_kn, C_kt and alpha of
+ * Eqs. 8-10 carry the indices i, j of the two bodies in contact; here the
+ * Coulomb coefficient of Eq. 5 does too).
+ *   ntypes     : materials, 1 <= ntypes <= p->max_materials; 0 goes back to
+ *                the parameters' one material.
+ *   table      : ntypes x ntypes rows of 4 doubles (kn, kt, restitution,
+ *                mu) -- the parameters of the same names for a particle of
+ *                material t touching one of material u at row t * ntypes + u;
+ *                it must be symmetric (the pair's constants do not depend on
+ *                the side looked from).  Linear law: the springs; Hertz: C_kn,
+ *                C_kt; restitution in (0, 1] sets alpha as in dem_params.  The
+ *                simple law (Eq. 1) keeps its own constants.
+ *   type       : n materials in original order, 0 <= type[i] < ntypes.
+ *   wall_type  : material of every wall, 0 <= wall_type < ntypes.
+ * The contact and wall forces of the current state are then evaluated again
+ * with the committed history (which is kept), so that the stored forces are
+ * those of a system created with these materials.  Synchronous.  Errors:
+ * DEM_E_INVALID (table not symmetric, a constant out of range, ntypes above
+ * max_materials, a type out of range). */
+dem_status dem_set_materials(dem_system *s, int32_t ntypes, const double *table, const int32_t *type,
+                             int32_t wall_type);
+
+/* Largest speed max_i |v_i| of the current state (FP64 norm of the stored
+ * velocities).  Synchronous. */
+dem_status dem_max_speed(dem_system *s, double *vmax);
+
+/* Sec. 5 runs its sample problem until the displacements of all particles
+ * are below a set value; here a particle's displacement is read as
+ * dt |v_i|, the step it would make at its current velocity.  Steps in chunks
+ * of check_every (the last chunk shorter if max_steps is reached) and stops
+ * after the first chunk at whose end dt * max_i |v_i| < threshold, or when
+ * max_steps are done; *steps_done tells which.  Synchronous.  Errors:
+ * DEM_E_INVALID (threshold < 0, check_every < 1, max_steps < 0), else as
+ * dem_step. */
+dem_status dem_run_to_rest(dem_system *s, double threshold, int64_t check_every, int64_t max_steps,
+                           int64_t *steps_done);
+
 /* Phase timing.  With enable != 0 every later dem_step brackets each of its
  * phases with HIP events on the system's stream; dem_profile_read waits for
  * the stream, returns the milliseconds spent in each phase summed over the
@@ -269,6 +343,15 @@ dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n
 /* dem_set_radii for every system of the batch: r holds sum(n) radii,
  * concatenated in system order.  Synchronous. */
 dem_status dem_batch_set_radii(dem_batch *b, const double *r);
+
+/* dem_set_materials for system k of the batch (type: its n[k] particles in
+ * its own order); the stored forces of system k only are evaluated again.
+ * Synchronous. */
+dem_status dem_batch_set_materials(dem_batch *b, int32_t k, int32_t ntypes, const double *table,
+                                   const int32_t *type, int32_t wall_type);
+
+/* dem_max_speed of every system: vmax[k] for k = 0..n_sys-1.  Synchronous. */
+dem_status dem_batch_max_speed(dem_batch *b, double *vmax);
 
 /* Advance system k by steps[k] >= 0 steps (0: it does not move).  The batch
  * runs max(steps) steps; a system that has done its steps stays unchanged

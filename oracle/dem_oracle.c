@@ -75,6 +75,20 @@ enum {
     ORC_TERM_ROLLING = 2   /* rolling resistance: couple -mu_r R |F_n| w_rel / |w_rel| */
 };
 
+/* A finite wall: the rectangle of the plane x[axis] = at spanning lo[0]..hi[0]
+ * along axis (axis + 1) % 3 and lo[1]..hi[1] along axis (axis + 2) % 3, of no
+ * thickness.  Like the walls of Step 8 it is a body of infinite radius and
+ * mass at rest; a sphere touches it where the nearest point of the rectangle
+ * is closer than its radius, and n points from the centre to that point.  Two
+ * such plates side by side leave a slit between them (Sec. 5's box with a
+ * slit at its bottom). */
+typedef struct {
+    int32_t axis, pad_;
+    double at;
+    double lo[2], hi[2];
+} orc_plate;
+enum { ORC_MAX_PLATES = 4 };
+
 typedef struct {
     double lo[3], hi[3];
     int32_t wall_mask; /* bit 2a: wall at lo[a]; bit 2a+1: wall at hi[a] */
@@ -91,6 +105,9 @@ typedef struct {
     int32_t pad_;
     double cohesion;   /* f_c (N) of ORC_TERM_COHESION */
     double rolling_mu; /* mu_r of ORC_TERM_ROLLING */
+    int32_t nplates;   /* finite walls, numbered 6, 7, ... after the six box walls */
+    int32_t pad2_;
+    orc_plate plates[ORC_MAX_PLATES];
 } orc_params;
 
 /* One history entry: the pair (a, b) with a < b seen from a, or the wall
@@ -246,8 +263,24 @@ static int pair_touch(const orc_sys *s, int64_t a, int64_t b)
     return d2 < S * S;
 }
 
+/* nearest point q of plate k to the centre c, and c - q */
+static void plate_nearest(const orc_plate *P, const double *c, double q[3], double d[3])
+{
+    int u = (P->axis + 1) % 3, v = (P->axis + 2) % 3;
+    q[P->axis] = P->at;
+    q[u] = c[u] < P->lo[0] ? P->lo[0] : (c[u] > P->hi[0] ? P->hi[0] : c[u]);
+    q[v] = c[v] < P->lo[1] ? P->lo[1] : (c[v] > P->hi[1] ? P->hi[1] : c[v]);
+    for (int k = 0; k < 3; k++) d[k] = c[k] - q[k];
+}
+
+/* wall w: 0..5 the box walls (Step 8), 6.. the plates */
 static int wall_touch(const orc_sys *s, int64_t a, int w)
 {
+    if (w >= 6) {
+        double q[3], d[3];
+        plate_nearest(&s->p.plates[w - 6], s->x + 3 * a, q, d);
+        return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] < s->r[a] * s->r[a];
+    }
     int axis = w >> 1;
     double gap = (w & 1) ? (s->p.hi[axis] - s->x[3 * a + axis]) : (s->x[3 * a + axis] - s->p.lo[axis]);
     return gap < s->r[a];
@@ -295,8 +328,8 @@ static int detect(const orc_sys *s, const orc_grid *g, orc_clist *L)
                         if (pair_touch(s, a, b) && clist_push(L, a, b) != ORC_OK) return ORC_E_NOMEM;
                     }
                 }
-        for (int w = 0; w < 6; w++)
-            if (((s->p.wall_mask >> w) & 1) && wall_touch(s, a, w))
+        for (int w = 0; w < 6 + s->p.nplates; w++)
+            if ((w >= 6 || ((s->p.wall_mask >> w) & 1)) && wall_touch(s, a, w))
                 if (clist_push(L, a, -1 - (int64_t)w) != ORC_OK) return ORC_E_NOMEM;
     }
     return ORC_OK;
@@ -334,8 +367,24 @@ static int pair_geom(const orc_sys *s, int64_t a, int64_t b, orc_geom *G)
     return ORC_OK;
 }
 
-static void wall_geom(const orc_sys *s, int64_t a, int w, orc_geom *G)
+static int wall_geom(const orc_sys *s, int64_t a, int w, orc_geom *G)
 {
+    if (w >= 6) {
+        double q[3], d[3];
+        plate_nearest(&s->p.plates[w - 6], s->x + 3 * a, q, d);
+        double dist = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+        if (!(dist > 0.0)) return ORC_E_NONFINITE; /* centre on the plate: n undefined */
+        for (int k = 0; k < 3; k++) {
+            G->n[k] = -d[k] / dist;
+            G->v[k] = s->v[3 * a + k];
+            G->spin[k] = s->r[a] * s->w[3 * a + k];
+            G->wrel[k] = s->w[3 * a + k];
+        }
+        G->delta = s->r[a] - dist;
+        G->R = s->r[a];
+        G->M = s->m[a];
+        return ORC_OK;
+    }
     int axis = w >> 1;
     double gap = (w & 1) ? (s->p.hi[axis] - s->x[3 * a + axis]) : (s->x[3 * a + axis] - s->p.lo[axis]);
     for (int k = 0; k < 3; k++) {
@@ -348,6 +397,7 @@ static void wall_geom(const orc_sys *s, int64_t a, int w, orc_geom *G)
     G->delta = s->r[a] - gap;
     G->R = s->r[a];
     G->M = s->m[a];
+    return ORC_OK;
 }
 
 /* The contact constants of particle a with partner b (b = -1-w: wall w):
@@ -518,7 +568,12 @@ static int evaluate(orc_sys *s, double *F, double *T, int commit, double *e_el, 
             }
             np++;
         } else {
-            wall_geom(s, a, (int)(-1 - b), &G);
+            st = wall_geom(s, a, (int)(-1 - b), &G);
+            if (st != ORC_OK) {
+                free(L.c);
+                free(Hn);
+                return st;
+            }
             nw++;
         }
         const orc_hentry *he = hist_find(s, a, b);
@@ -644,6 +699,13 @@ int orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
     if (p->law < ORC_LINEAR || p->law > ORC_SIMPLE) return ORC_E_INVALID;
     if (!(p->e > 0.0 && p->e <= 1.0) || !(p->mu >= 0.0)) return ORC_E_INVALID;
     if ((p->terms & ~(ORC_TERM_COHESION | ORC_TERM_ROLLING)) != 0) return ORC_E_INVALID;
+    if (p->nplates < 0 || p->nplates > ORC_MAX_PLATES) return ORC_E_INVALID;
+    for (int k = 0; k < p->nplates; k++) {
+        const orc_plate *P = &p->plates[k];
+        if (P->axis < 0 || P->axis > 2 || !isfinite(P->at) || !(P->lo[0] <= P->hi[0]) || !(P->lo[1] <= P->hi[1]) ||
+            !isfinite(P->lo[0]) || !isfinite(P->hi[0]) || !isfinite(P->lo[1]) || !isfinite(P->hi[1]))
+            return ORC_E_INVALID;
+    }
     if (p->terms && (p->law == ORC_SIMPLE || !isfinite(p->cohesion) || !(p->rolling_mu >= 0.0) ||
                      !isfinite(p->rolling_mu)))
         return ORC_E_INVALID;
@@ -725,7 +787,7 @@ int orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
         }
         for (int64_t k = 0; k < nh; k++) {
             int64_t a = hist_pairs[2 * k], b = hist_pairs[2 * k + 1];
-            int ok = a >= 0 && a < n && ((b > a && b < n) || (b < 0 && b >= -6));
+            int ok = a >= 0 && a < n && ((b > a && b < n) || (b < 0 && b >= -6 - p->nplates));
             if (!ok) {
                 orc_destroy(s);
                 return ORC_E_INVALID;
@@ -926,6 +988,22 @@ int orc_diagnostics(orc_sys *s, double out[10])
 }
 
 int64_t orc_num_cells(const orc_sys *s) { return s ? s->ncell : -1; }
+
+/* Largest speed |v_i| of the current state.  Sec. 5 runs its sample problem
+ * until the displacements of all particles are below a set value; here a
+ * particle's displacement is read as dt |v_i|, the step it would make at its
+ * current velocity, checked between steps. */
+int orc_max_speed(const orc_sys *s, double *vmax)
+{
+    if (!s || !vmax) return ORC_E_INVALID;
+    double m = 0.0;
+    for (int64_t i = 0; i < s->n; i++) {
+        double q = norm3(s->v + 3 * i);
+        if (q > m) m = q;
+    }
+    *vmax = m;
+    return ORC_OK;
+}
 
 /* Material-pair table (Sec. 3, the (i, j) indices of Eqs. 8-10).  ntypes
  * materials, 1 <= ntypes <= ORC_MAX_TYPES; table holds ntypes x ntypes rows

@@ -25,6 +25,14 @@ class OracleError(RuntimeError):
         self.code = code
 
 
+class OrcPlate(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("pad_", C.c_int32), ("at", C.c_double),
+                ("lo", C.c_double * 2), ("hi", C.c_double * 2)]
+
+
+MAX_PLATES = 4
+
+
 class OrcParams(C.Structure):
     _fields_ = [
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -37,6 +45,8 @@ class OrcParams(C.Structure):
         ("cell", C.c_double),
         ("terms", C.c_int32), ("pad_", C.c_int32),
         ("cohesion", C.c_double), ("rolling_mu", C.c_double),
+        ("nplates", C.c_int32), ("pad2_", C.c_int32),
+        ("plates", OrcPlate * MAX_PLATES),
     ]
 
 
@@ -72,6 +82,8 @@ def lib():
         L.orc_num_cells.restype = C.c_int64
         L.orc_set_materials.argtypes = [P, C.c_int32, P, P, C.c_int32]
         L.orc_set_materials.restype = C.c_int
+        L.orc_max_speed.argtypes = [P, D]
+        L.orc_max_speed.restype = C.c_int
         L.orc_destroy.argtypes = [P]
         L.orc_destroy.restype = None
         _LIB = L
@@ -99,6 +111,15 @@ def make_params(p: dict) -> OrcParams:
         (TERMS["rolling"] if "rolling" in p.get("terms", ()) else 0)
     o.cohesion = float(p.get("cohesion", 0.0))
     o.rolling_mu = float(p.get("rolling_mu", 0.0))
+    plates = p.get("plates", ())
+    if len(plates) > MAX_PLATES:
+        raise ValueError("at most 4 plates")
+    o.nplates = len(plates)
+    for k, q in enumerate(plates):
+        o.plates[k].axis = int(q["axis"])
+        o.plates[k].at = float(q["at"])
+        o.plates[k].lo[:] = [float(t) for t in q["lo"]]
+        o.plates[k].hi[:] = [float(t) for t in q["hi"]]
     return o
 
 
@@ -150,6 +171,25 @@ class OracleSystem:
 
     def step(self, nsteps: int = 1):
         self._check(lib().orc_step(self._h, int(nsteps)), "step")
+
+    def max_speed(self):
+        out = C.c_double()
+        self._check(lib().orc_max_speed(self._h, C.byref(out)), "max_speed")
+        return out.value
+
+    def run_to_rest(self, threshold, check_every, max_steps):
+        """Step in chunks of check_every until dt * max |v_i| < threshold
+        (Sec. 5's run until every displacement is below a set value) or
+        max_steps are done; returns the steps done."""
+        done = 0
+        dt = self.params["dt"]
+        while done < max_steps:
+            k = min(check_every, max_steps - done)
+            self.step(k)
+            done += k
+            if dt * self.max_speed() < threshold:
+                break
+        return done
 
     def forces(self):
         F = np.zeros((self.n, 3))

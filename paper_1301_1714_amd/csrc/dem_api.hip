@@ -40,8 +40,12 @@ struct Engine {
   std::vector<int4> runs_h;   // wave detection work items
   int64_t ncell = 0;  // cells of all systems
   int32_t K = 1;      // owned contacts per particle at most (largest contacts_per_particle)
+  bool has_mt = false;  // some system may have a material-pair table
+  bool has_terms = false;  // some system has optional contact terms
+  int64_t nmat = 0;     // entries of all systems' tables (max_materials^2 each)
   // device
   SysInfo *tab = nullptr;
+  PairK *mat = nullptr;
   int32_t *psys = nullptr, *bsys = nullptr, *bfirst = nullptr;
   int4 *tiles = nullptr;
   int4 *runs = nullptr;
@@ -62,6 +66,7 @@ struct Engine {
   PairWork work{};
   DiagBuf diag{};
   int32_t *err = nullptr;
+  unsigned long long *vmax = nullptr;  // [S] largest speeds (dem_max_speed)
   hipStream_t stream = nullptr;
   dem_status sticky = DEM_OK;
   // phase timing
@@ -78,6 +83,7 @@ struct Engine {
   Layout layout() const {
     Layout L;
     L.tab = tab;
+    L.mat = mat;
     L.psys = psys;
     L.bsys = bsys;
     L.bfirst = bfirst;
@@ -119,6 +125,18 @@ dem_status check_params(const dem_params *p, int64_t n, Grid *g) {
   if (p->tile_cells < -1 || p->tile_cells > kMaxTile) return DEM_E_INVALID;
   if (p->cell_divisor < 1 || p->cell_divisor > kMaxReach) return DEM_E_INVALID;
   if (p->cell_divisor > 1 && p->tile_cells != 0) return DEM_E_INVALID;  // the other shapes sweep 27 cells
+  if (p->max_materials < 0 || p->max_materials > kMaxMaterials) return DEM_E_INVALID;
+  if (p->nplates < 0 || p->nplates > kMaxPlates) return DEM_E_INVALID;
+  for (int k = 0; k < p->nplates; k++) {
+    const dem_plate &q = p->plates[k];
+    if (q.axis < 0 || q.axis > 2 || !isfinite(q.at) || !isfinite(q.lo[0]) || !isfinite(q.lo[1]) ||
+        !isfinite(q.hi[0]) || !isfinite(q.hi[1]) || !(q.lo[0] <= q.hi[0]) || !(q.lo[1] <= q.hi[1]))
+      return DEM_E_INVALID;
+  }
+  if ((p->terms & ~(uint32_t)(DEM_TERM_COHESION | DEM_TERM_ROLLING)) != 0) return DEM_E_INVALID;
+  if (p->terms != 0 && (p->law == DEM_LAW_SIMPLE || !isfinite(p->cohesion) || !(p->rolling_mu >= 0.0) ||
+                        !isfinite(p->rolling_mu)))
+    return DEM_E_INVALID;
   const double width = p->cell_size / p->cell_divisor;
   int64_t ncell = 1;
   for (int a = 0; a < 3; a++) {
@@ -154,12 +172,22 @@ float prefilter_eps(const Grid &g, double cell) {
   return (float)(4.0 * ulp + 1.0e-6 * cell);
 }
 
+// Eq. 10's alpha for restitution e: -2 ln e / sqrt(pi^2 + ln^2 e), which
+// makes a linear contact's restitution exactly e.  One function for the
+// system constants and the material tables, so that a table entry equal to
+// the parameters gives the same bits (the compiler may contract the
+// expression differently in two places).
+double alpha_of(double e) {
+  if (e >= 1.0) return 0.0;
+  const double le = log(e);
+  return -2.0 * le / sqrt(kPi * kPi + le * le);
+}
+
 void fill_consts(const dem_params &p, Consts &c) {
   c.dt = p.dt;
   c.half_dt = 0.5 * p.dt;
   c.mass_c = p.density * (4.0 / 3.0) * kPi;
-  const double le = log(p.restitution);
-  c.alpha = p.restitution >= 1.0 ? 0.0 : -2.0 * le / sqrt(kPi * kPi + le * le);
+  c.alpha = alpha_of(p.restitution);
   c.eta_t_ratio = p.eta_t_ratio;
   c.kn = p.kn;
   c.kt = p.kt;
@@ -170,6 +198,9 @@ void fill_consts(const dem_params &p, Consts &c) {
   for (int k = 0; k < 3; k++) c.g[k] = p.gravity[k];
   c.wall_mask = p.wall_mask;
   c.law = p.law;
+  c.terms = p.terms;
+  c.cohesion = (p.terms & DEM_TERM_COHESION) ? p.cohesion : 0.0;
+  c.rolling_mu = (p.terms & DEM_TERM_ROLLING) ? p.rolling_mu : 0.0;
 }
 
 // Validate the systems and lay out slot, cell and block ranges (no device
@@ -189,6 +220,9 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   e.runs_h.clear();
   e.ndirect = 0;
   e.ndirect2 = 0;
+  e.has_mt = false;
+  e.has_terms = false;
+  e.nmat = 0;
   for (int32_t k = 0; k < S; k++) {
     SysInfo &si = e.info[k];
     memset(&si, 0, sizeof(si));
@@ -196,10 +230,21 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
     if (st != DEM_OK) return st;
     if (p[k].precision != e.prec || p[k].law != e.law) return DEM_E_INVALID;
     fill_consts(p[k], si.c);
+    si.nplates = p[k].nplates;
+    for (int q = 0; q < p[k].nplates; q++) {
+      const dem_plate &d = p[k].plates[q];
+      si.plates[q] = Plate{d.axis, 0, d.at, {d.lo[0], d.lo[1]}, {d.hi[0], d.hi[1]}};
+    }
     si.eps = prefilter_eps(si.g, p[k].cell_size);
     si.reach = p[k].cell_divisor;
     si.kcap = p[k].contacts_per_particle;
     e.K = std::max(e.K, si.kcap);
+    si.ntypes = 0;  // one material until dem_set_materials
+    si.wall_type = 0;
+    si.mat0 = (int32_t)e.nmat;
+    e.nmat += (int64_t)p[k].max_materials * p[k].max_materials;
+    e.has_mt = e.has_mt || p[k].max_materials > 0;
+    e.has_terms = e.has_terms || p[k].terms != 0;
     si.p0 = (int32_t)ntot;
     si.n = (int32_t)n[k];
     si.g.c0 = (int32_t)ctot;
@@ -246,6 +291,7 @@ size_t carve(Engine &e, char *base) {
   const size_t S = (size_t)e.S;
   const size_t B = std::max<size_t>(e.bsys_h.size(), 1);
   e.tab = cv.take<SysInfo>(S);
+  e.mat = cv.take<PairK>(std::max<size_t>((size_t)e.nmat, 1));
   e.psys = cv.take<int32_t>(N);
   e.bsys = cv.take<int32_t>(B);
   e.bfirst = cv.take<int32_t>(B);
@@ -259,6 +305,7 @@ size_t carve(Engine &e, char *base) {
     e.pos[b].z = cv.take<double>(N);
     e.pos[b].r = cv.take<float>(N);
     e.pos[b].id = cv.take<int32_t>(N);
+    e.pos[b].mt = e.has_mt ? cv.take<int32_t>(N) : nullptr;
     for (int k = 0; k < 3; k++) e.vel[b].v[k] = cv.take_bytes(R * N);
     for (int k = 0; k < 3; k++) e.vel[b].w[k] = cv.take_bytes(R * N);
   }
@@ -291,6 +338,7 @@ size_t carve(Engine &e, char *base) {
     e.hist[b].ent = cv.take_bytes(4 * R * P);
   }
   e.work.pf = cv.take_bytes(6 * R * P);
+  e.work.pc = e.has_terms ? cv.take_bytes(4 * R * P) : nullptr;
   e.work.pe = cv.take<double>(P);
   e.work.pd = cv.take<double>(P);
   e.work.bcnt = cv.take<int32_t>(N);
@@ -302,6 +350,7 @@ size_t carve(Engine &e, char *base) {
   e.diag.partial = cv.take<double>(B * 10);
   e.diag.out = cv.take<double>(S * 10);
   e.err = cv.take<int32_t>(64);
+  e.vmax = cv.take<unsigned long long>(S);
   return (cv.off + 255) & ~size_t(255);
 }
 
@@ -436,6 +485,7 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.scell = e.scell;
   a.mode = mode;
   a.law = e.law;
+  a.terms = e.has_terms ? 1 : 0;
   a.err = e.err;
   return a;
 }
@@ -574,9 +624,11 @@ dem_status validate_inputs(Engine &e, const double *x, const double *v, const do
     for (size_t i = 0; i < 3 * N; i++)
       if (!isfinite(F0[i]) || !isfinite(T0[i])) return DEM_E_NONFINITE;
   if (e.law != DEM_LAW_SIMPLE) {
+    // walls -1 .. -6 and plates -7 .. (a batch checked each system's own plates already)
+    const int64_t wmin = -6 - (e.S == 1 ? e.params[0].nplates : kMaxPlates);
     for (int64_t k = 0; k < hist.n; k++) {
       const int64_t a = hist.pairs[2 * k], b = hist.pairs[2 * k + 1];
-      const bool ok = a >= 0 && a < (int64_t)N && ((b > a && b < (int64_t)N) || (b < 0 && b >= -6));
+      const bool ok = a >= 0 && a < (int64_t)N && ((b > a && b < (int64_t)N) || (b < 0 && b >= wmin));
       if (!ok) return DEM_E_INVALID;
       for (int q = 0; q < 3; q++)
         if (!isfinite(hist.dt[3 * k + q])) return DEM_E_NONFINITE;
@@ -688,6 +740,7 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
     if ((st = h2d_real(e, e.vel[0].w[k], tmp)) != DEM_OK) return st;
   }
   if ((st = h2d(e, e.pos[0].r, rf)) != DEM_OK || (st = h2d(e, e.pos[0].id, ids)) != DEM_OK) return st;
+  if (e.has_mt && (st = h2d(e, e.pos[0].mt, std::vector<int32_t>(N, 0))) != DEM_OK) return st;
   const Layout L = e.layout();
   // Steps 2-4 on the initial positions
   HIP_TRY(launch_hash(L, e.pos[0], e.cell, e.err, e.stream));
@@ -1012,6 +1065,79 @@ dem_status engine_set_radii(Engine &e, const double *r) {
   return sync_and_check(e);
 }
 
+// Material-pair table of system k (Sec. 3, the (i, j) constants of Eqs. 8-10;
+// ntypes = 0: back to the system's one material), then the stored forces of
+// system k evaluated again on its current state with the committed history.
+dem_status engine_set_materials(Engine &e, int32_t k, int32_t ntypes, const double *table, const int32_t *type,
+                                int32_t wall_type) {
+  if (k < 0 || k >= e.S) return DEM_E_INVALID;
+  const dem_params &p = e.params[k];
+  SysInfo si = e.info[k];
+  const size_t n = (size_t)si.n, p0 = (size_t)si.p0;
+  if (ntypes < 0 || ntypes > p.max_materials) return DEM_E_INVALID;
+  std::vector<PairK> tab((size_t)ntypes * ntypes);
+  if (ntypes > 0) {
+    if (!table || (n > 0 && !type) || wall_type < 0 || wall_type >= ntypes) return DEM_E_INVALID;
+    for (int32_t t = 0; t < ntypes; t++)
+      for (int32_t u = 0; u < ntypes; u++) {
+        const double *q = table + 4 * ((size_t)t * ntypes + u), *qt = table + 4 * ((size_t)u * ntypes + t);
+        if (!(q[0] > 0.0) || !(q[1] >= 0.0) || !(q[2] > 0.0 && q[2] <= 1.0) || !(q[3] >= 0.0) ||
+            !isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[3]))
+          return DEM_E_INVALID;
+        for (int c = 0; c < 4; c++)
+          if (q[c] != qt[c]) return DEM_E_INVALID;
+        tab[(size_t)t * ntypes + u] = PairK{q[0], q[1], alpha_of(q[2]), q[3]};
+      }
+    for (size_t i = 0; i < n; i++)
+      if (type[i] < 0 || type[i] >= ntypes) return DEM_E_INVALID;
+  }
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  if (n == 0 || !e.has_mt) {
+    e.info[k].ntypes = ntypes;
+    e.info[k].wall_type = ntypes > 0 ? wall_type : 0;
+    return DEM_OK;
+  }
+  // materials of the system's slots
+  std::vector<int32_t> id;
+  if ((st = d2h(e, e.pos[e.cp].id + p0, id, n)) != DEM_OK) return st;
+  std::vector<int32_t> slot_t(n, 0);
+  if (ntypes > 0)
+    for (size_t j = 0; j < n; j++) slot_t[j] = type[(size_t)id[j] - p0];
+  if ((st = h2d(e, e.pos[e.cp].mt + p0, slot_t)) != DEM_OK) return st;
+  if (ntypes > 0) HIP_TRY(hipMemcpyAsync(e.mat + si.mat0, tab.data(), sizeof(PairK) * tab.size(),
+                                         hipMemcpyHostToDevice, e.stream));
+  si.ntypes = ntypes;
+  si.wall_type = ntypes > 0 ? wall_type : 0;
+  e.info[k] = si;
+  HIP_TRY(hipMemcpyAsync(e.tab + k, &e.info[k], sizeof(SysInfo), hipMemcpyHostToDevice, e.stream));
+  // forces of every system into the scratch force arrays; system k's become
+  // its stored forces (the others keep theirs)
+  PairArgs a = pair_args(e, 0, e.Fe, e.Te);
+  HIP_TRY(launch_pack(e.prec, e.layout(), e.pos[e.cp], e.vel[e.cv], e.nbr, e.stream));
+  HIP_TRY(run_forces(e, a, nullptr));
+  for (int c = 0; c < 3; c++) {
+    HIP_TRY(hipMemcpyAsync((char *)e.F[c] + e.rsz * p0, (const char *)e.Fe[c] + e.rsz * p0, e.rsz * n,
+                           hipMemcpyDeviceToDevice, e.stream));
+    HIP_TRY(hipMemcpyAsync((char *)e.T[c] + e.rsz * p0, (const char *)e.Te[c] + e.rsz * p0, e.rsz * n,
+                           hipMemcpyDeviceToDevice, e.stream));
+  }
+  return sync_and_check(e);
+}
+
+// largest |v| of every system's current state
+dem_status engine_max_speed(Engine &e, std::vector<double> &out) {
+  dem_status st = sync_and_check(e);
+  if (st != DEM_OK) return st;
+  HIP_TRY(launch_fill((int32_t *)e.vmax, 2 * (int64_t)e.S, 0, e.stream));
+  HIP_TRY(launch_max_speed(e.prec, e.layout(), e.vel[e.cv], e.vmax, e.stream));
+  std::vector<unsigned long long> bits;
+  if ((st = d2h(e, e.vmax, bits, (size_t)e.S)) != DEM_OK) return st;
+  out.resize((size_t)e.S);
+  for (int32_t k = 0; k < e.S; k++) memcpy(&out[k], &bits[k], sizeof(double));
+  return DEM_OK;
+}
+
 dem_status engine_profile(Engine &e, int enable) {
   if (enable && e.events.empty()) {
     const size_t cnt = (size_t)DEM_PROFILE_CAPACITY * (DEM_NUM_PHASES + 1);
@@ -1239,6 +1365,39 @@ dem_status dem_set_radii(dem_system *s, const double *r) {
   return engine_set_radii(*s->e, r);
 }
 
+dem_status dem_set_materials(dem_system *s, int32_t ntypes, const double *table, const int32_t *type,
+                             int32_t wall_type) {
+  if (!s) return DEM_E_STATE;
+  return engine_set_materials(*s->e, 0, ntypes, table, type, wall_type);
+}
+
+dem_status dem_max_speed(dem_system *s, double *vmax) {
+  if (!s) return DEM_E_STATE;
+  if (!vmax) return DEM_E_INVALID;
+  std::vector<double> out;
+  const dem_status st = engine_max_speed(*s->e, out);
+  if (st == DEM_OK) *vmax = out[0];
+  return st;
+}
+
+dem_status dem_run_to_rest(dem_system *s, double threshold, int64_t check_every, int64_t max_steps,
+                           int64_t *steps_done) {
+  if (!s) return DEM_E_STATE;
+  if (!steps_done || !(threshold >= 0.0) || check_every < 1 || max_steps < 0) return DEM_E_INVALID;
+  *steps_done = 0;
+  const double dt = s->e->params[0].dt;
+  while (*steps_done < max_steps) {
+    const int64_t k = std::min(check_every, max_steps - *steps_done);
+    dem_status st = engine_step(*s->e, &k);
+    if (st != DEM_OK) return st;
+    *steps_done += k;
+    double vmax = 0.0;
+    if ((st = dem_max_speed(s, &vmax)) != DEM_OK) return st;
+    if (dt * vmax < threshold) break;
+  }
+  return DEM_OK;
+}
+
 dem_status dem_profile(dem_system *s, int enable) {
   if (!s) return DEM_E_STATE;
   return engine_profile(*s->e, enable);
@@ -1295,7 +1454,7 @@ dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n
     for (int32_t k = 0; k < n_sys; k++) {
       for (int64_t j = 0; j < n_hist[k]; j++, q++) {
         const int64_t a = hist_pairs[2 * q], b = hist_pairs[2 * q + 1];
-        const bool ok = a >= 0 && a < n[k] && ((b > a && b < n[k]) || (b < 0 && b >= -6));
+        const bool ok = a >= 0 && a < n[k] && ((b > a && b < n[k]) || (b < 0 && b >= -6 - p[k].nplates));
         if (!ok) return DEM_E_INVALID;
         gpairs[2 * q] = a + base;
         gpairs[2 * q + 1] = b >= 0 ? b + base : b;
@@ -1317,6 +1476,21 @@ dem_status dem_batch_create(int32_t n_sys, const dem_params *p, const int64_t *n
   b->e = e;
   *out = b;
   return DEM_OK;
+}
+
+dem_status dem_batch_set_materials(dem_batch *b, int32_t k, int32_t ntypes, const double *table,
+                                   const int32_t *type, int32_t wall_type) {
+  if (!b) return DEM_E_STATE;
+  return engine_set_materials(*b->e, k, ntypes, table, type, wall_type);
+}
+
+dem_status dem_batch_max_speed(dem_batch *b, double *vmax) {
+  if (!b) return DEM_E_STATE;
+  if (!vmax) return DEM_E_INVALID;
+  std::vector<double> out;
+  const dem_status st = engine_max_speed(*b->e, out);
+  if (st == DEM_OK) memcpy(vmax, out.data(), sizeof(double) * out.size());
+  return st;
 }
 
 dem_status dem_batch_step(dem_batch *b, const int64_t *steps) {

@@ -45,6 +45,10 @@ namespace dem {
 
 enum ErrBits : int32_t { ERR_DOMAIN = 1, ERR_OVERFLOW = 2, ERR_NONFINITE = 4 };
 
+// A law template argument is the dem_law plus kLawTerms when the optional
+// contact terms are compiled in (engines where some system uses them)
+constexpr int kLawTerms = 4;
+
 // contact-evaluation modes
 enum ModeBits : int32_t {
   MODE_WRITE_HIST = 1,  // write the new tangential displacements
@@ -82,11 +86,35 @@ struct Consts {
   double g[3];
   uint32_t wall_mask;
   int32_t law;
+  uint32_t terms;  // DEM_TERM_* bits of the system
+  double cohesion, rolling_mu;
 };
+
+// Contact constants of one pair of materials (Sec. 3: the C_kn, C_kt and
+// alpha of Eqs. 8-10 carry the indices of the two bodies in contact; so does
+// the Coulomb coefficient of Eq. 5 here)
+struct PairK {
+  double kn, kt, alpha, mu;
+};
+constexpr int32_t kMaxMaterials = 16;
+
+// a finite wall (dem_plate): the rectangle x[axis] = at, lo..hi on the
+// axes (axis + 1) % 3 and (axis + 2) % 3
+struct Plate {
+  int32_t axis, pad;
+  double at;
+  double lo[2], hi[2];
+};
+constexpr int32_t kMaxPlates = DEM_MAX_PLATES;
 
 struct SysInfo {
   Grid g;
   Consts c;
+  int32_t nplates;             // plates, walls 6 .. 5 + nplates
+  Plate plates[kMaxPlates];
+  int32_t ntypes;     // materials of the system's table (0: one material, the constants in c)
+  int32_t mat0;       // its first entry in the engine's table: (t, u) at mat0 + t * ntypes + u
+  int32_t wall_type;  // material of the walls
   int32_t p0, n;  // slot range
   float eps;      // detection prefilter margin
   float rmax;     // largest radius (FP32), bounds the contact distance
@@ -107,6 +135,7 @@ struct PosBuf {
   double *x, *y, *z;
   float *r;
   int32_t *id;
+  int32_t *mt;  // material of each slot (nullptr: no system of the engine has a material table)
 };
 
 struct VelBuf {
@@ -128,7 +157,7 @@ struct alignas(16) PState {
   float r;
   int32_t id;
   uint32_t hp;  // previous slot | owned history count << kPrevBits
-  int32_t pad;
+  int32_t mt;   // material (0 without a material table)
 };
 
 struct NbrBuf {
@@ -148,6 +177,7 @@ struct HistGen {
 
 struct PairWork {
   void *pf;        // [K][N] 3 x Real2: force on the owner, then n x F_t
+  void *pc;        // [K][N] Real4: the couple of the optional terms on the owner (engines with terms only)
   double *pe;      // [K][N] elastic energy (diagnostics)
   double *pd;      // [K][N] overlap (diagnostics)
   int32_t *bcnt;   // [N] contacts of each particle as the partner (zero between evaluations)
@@ -166,6 +196,7 @@ struct DiagBuf {
 // what every per-particle kernel needs to find its system
 struct Layout {
   const SysInfo *tab;     // [S]
+  const PairK *mat;       // material-pair tables of the systems that have one
   const int32_t *psys;    // [N]
   const int32_t *bsys;    // [nblocks]
   const int32_t *bfirst;  // [nblocks]
@@ -195,6 +226,7 @@ struct PairArgs {
   const int32_t *scell;  // cells of the current slots
   int32_t mode;
   int32_t law;
+  int32_t terms;         // some system of the engine has optional contact terms (dem_params.terms)
   int32_t *err;
 };
 
@@ -233,6 +265,9 @@ hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, c
 // per-particle sums and (in a time step) the kicks
 hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st);
 hipError_t launch_step_end(const StepCtl &ctl, hipStream_t st);
+// largest |v| of each system into vmax[S] (bits of non-negative doubles; zeroed by the caller)
+hipError_t launch_max_speed(int precision, const Layout &L, const VelBuf &v, unsigned long long *vmax,
+                            hipStream_t st);
 hipError_t launch_diag_reduce(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const DiagBuf &d,
                               hipStream_t st);
 hipError_t launch_fill(int32_t *a, int64_t len, int32_t value, hipStream_t st);

@@ -78,6 +78,40 @@ __device__ __forceinline__ bool hash_cell(const Grid &g, double x, double y, dou
   return ok;
 }
 
+// c - q for q the nearest point of plate P to the centre c (the selects of
+// the clamp are exact, so the result is the plain expression's)
+__device__ __forceinline__ void plate_gap(const Plate &P, const double c[3], double d[3]) {
+  const int ax = P.axis, u = ax == 2 ? 0 : ax + 1, v = ax == 0 ? 2 : ax - 1;
+  double q[3];
+  q[ax] = P.at;
+  q[u] = c[u] < P.lo[0] ? P.lo[0] : (c[u] > P.hi[0] ? P.hi[0] : c[u]);
+  q[v] = c[v] < P.lo[1] ? P.lo[1] : (c[v] > P.hi[1] ? P.hi[1] : c[v]);
+#pragma unroll
+  for (int k = 0; k < 3; k++) d[k] = c[k] - q[k];
+}
+
+// Step 8: fn(-1 - w) for every wall w the sphere (centre c, radius r)
+// touches, in ascending w: the box walls of the mask (w = 0..5: gap < r),
+// then the plates (w = 6 + k: nearest-point distance d^2 < r^2)
+template <typename Fn>
+__device__ __forceinline__ void for_walls(const SysInfo &si, const double c[3], float r, Fn &&fn) {
+  const uint32_t wall_mask = si.c.wall_mask;
+  const double rid = (double)r;
+  if (wall_mask) {
+    for (int w = 0; w < 6; w++) {
+      if (!((wall_mask >> w) & 1)) continue;
+      const int ax = w >> 1;
+      const double gap = (w & 1) ? (si.g.hi[ax] - c[ax]) : (c[ax] - si.g.lo[ax]);
+      if (gap < rid) fn(-1 - w);
+    }
+  }
+  for (int k = 0; k < si.nplates; k++) {
+    double d[3];
+    plate_gap(si.plates[k], c, d);
+    if (dist2_exact(d[0], d[1], d[2]) < sq_exact(rid)) fn(-7 - k);
+  }
+}
+
 template <typename Real>
 __device__ __forceinline__ Real mass_of(const Consts &c, Real r) {
   return (Real)c.mass_c * r * r * r;
@@ -444,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   ps.r = src.r[p];
   ps.id = src.id[p];
   ps.hp = 0;
-  ps.pad = 0;
+  ps.mt = src.mt ? src.mt[p] : 0;
   if (old_cnt) {
     const int32_t c = min(max(old_cnt[p], 0), nb.K);  // the table holds K rows
     ps.hp = (uint32_t)p | ((uint32_t)c << kPrevBits);
@@ -467,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
     dst.z[s] = ps.z;
     dst.r[s] = ps.r;
     dst.id[s] = ps.id;
+    if (dst.mt) dst.mt[s] = ps.mt;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)vdst.v[q])[s] = ps.v[q];
@@ -492,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
   ps.r = pos.r[s];
   ps.id = pos.id[s];
   ps.hp = 0;
-  ps.pad = 0;
+  ps.mt = pos.mt ? pos.mt[s] : 0;
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
@@ -708,16 +743,9 @@ __device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf
   for (int32_t j = 0; j < ns; j++)
     exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
   // Step 8: walls, particles of infinite radius, after the pairs
-  const uint32_t wall_mask = si.c.wall_mask;
-  if (wall_mask) {
+  {
     const double xs[3] = {xi, yi, zi};
-    const double rid = (double)p.w;
-    for (int w = 0; w < 6; w++) {
-      if (!((wall_mask >> w) & 1)) continue;
-      const int ax = w >> 1;
-      const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
-      if (gap < rid) record<kLanes>(nb, N, kcap, s, lst, -1 - w, nf);
-    }
+    for_walls(si, xs, p.w, [&](int32_t key) { record<kLanes>(nb, N, kcap, s, lst, key, nf); });
   }
   const int32_t nc = nf < kcap ? nf : kcap;
   for (int32_t j = 0; j < nc && j < kListStage; j++) nb.nb[(int64_t)j * N + s] = lst[j * kLanes];
@@ -1005,20 +1033,13 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
     if (lane < gn) {
       const int32_t s = g0 + lane;
       int32_t nf = cnt[lane];
-      const uint32_t wall_mask = si.c.wall_mask;
-      if (wall_mask) {
+      if (si.c.wall_mask || si.nplates) {
         const XR a = state_xr(nb, f64, s);
         const double xs[3] = {a.x, a.y, a.z};
-        const double rid = (double)a.r;
-        for (int w = 0; w < 6; w++) {
-          if (!((wall_mask >> w) & 1)) continue;
-          const int ax = w >> 1;
-          const double gap = (w & 1) ? (si.g.hi[ax] - xs[ax]) : (xs[ax] - si.g.lo[ax]);
-          if (gap < rid) {
-            if (nf < si.kcap) nb.nb[(int64_t)nf * N + s] = -1 - w;
-            nf++;
-          }
-        }
+        for_walls(si, xs, a.r, [&](int32_t key) {
+          if (nf < si.kcap) nb.nb[(int64_t)nf * N + s] = key;
+          nf++;
+        });
       }
       if (nf > si.kcap) raise_err(err, ERR_OVERFLOW);
       nb.fcnt[s] = nf < si.kcap ? nf : si.kcap;
@@ -1247,14 +1268,16 @@ struct LawOut {
   Real Ft[3];    // its tangential part (sets the torque of Eq. 3)
   Real dtn[3];   // new tangential displacement (Eq. 7, after Eq. 5)
   Real kn, kt;   // stiffness used (elastic-energy diagnostic)
+  Real fn;       // |F_n| of Eq. 4 (0 for the simple law)
 };
 
 // One contact seen from body a: n (unit, a -> partner), overlap delta,
 // effective radius R and mass M, relative velocity v = v_a - v_b, spin term
-// r_a w_a + r_b w_b, previous tangential displacement h.
+// r_a w_a + r_b w_b, previous tangential displacement h; K: the constants of
+// the pair's materials.
 template <typename Real, int LAW>
-__device__ __forceinline__ void contact_law(const Consts &c, const Real n[3], Real delta, Real R, Real M,
-                                            const Real v[3], const Real spin[3], const Real h[3],
+__device__ __forceinline__ void contact_law(const Consts &c, const PairK &K, const Real n[3], Real delta, Real R,
+                                            Real M, const Real v[3], const Real spin[3], const Real h[3],
                                             LawOut<Real> &o) {
   const Real vn_s = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
   const Real sxn[3] = {spin[1] * n[2] - spin[2] * n[1], spin[2] * n[0] - spin[0] * n[2],
@@ -1276,18 +1299,19 @@ __device__ __forceinline__ void contact_law(const Consts &c, const Real n[3], Re
     }
     o.kn = (Real)c.k_sp;
     o.kt = 0;
+    o.fn = 0;
     return;
   }
   Real kn, kt;
   if (LAW == DEM_LAW_HERTZ) {  // Eqs. 8-9
     const Real q = sqrt(delta * R);
-    kn = (Real)c.kn * q;
-    kt = (Real)c.kt * q;
+    kn = (Real)K.kn * q;
+    kt = (Real)K.kt * q;
   } else {
-    kn = (Real)c.kn;
-    kt = (Real)c.kt;
+    kn = (Real)K.kn;
+    kt = (Real)K.kt;
   }
-  const Real eta = (Real)c.alpha * sqrt(kn * M);  // Eq. 10
+  const Real eta = (Real)K.alpha * sqrt(kn * M);  // Eq. 10
   const Real eta_t = (Real)c.eta_t_ratio * eta;
   const Real hn = h[0] * n[0] + h[1] * n[1] + h[2] * n[2];
   const Real dtc = (Real)c.dt;
@@ -1300,7 +1324,7 @@ __device__ __forceinline__ void contact_law(const Consts &c, const Real n[3], Re
   }
   const Real ftn = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
   const Real fnn = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
-  const Real lim = (Real)c.mu * fnn;
+  const Real lim = (Real)K.mu * fnn;
   const bool slip = ftn > lim;  // Eq. 5, evaluated without a branch
   const Real scale = slip ? lim / ftn : (Real)1;
   const bool rescale = slip && kt > (Real)0;
@@ -1314,15 +1338,38 @@ __device__ __forceinline__ void contact_law(const Consts &c, const Real n[3], Re
   }
   o.kn = kn;
   o.kt = kt;
+  o.fn = fnn;
+}
+
+// The optional contact terms, each added after the law on its own, so that a
+// term is added or removed here without touching the law, the grid or the
+// sums: cohesion, a constant pull f_c along n while the bodies overlap;
+// rolling resistance, the couple C = -mu_r R |F_n| w_rel / |w_rel| on the
+// owner (zero when w_rel = 0) and -C on the partner (the gather applies it).
+template <typename Real>
+__device__ __forceinline__ void extra_terms(const Consts &c, const Real n[3], Real R, const Real wrel[3],
+                                            LawOut<Real> &o, Real C[3]) {
+  C[0] = C[1] = C[2] = 0;
+  if (c.terms & DEM_TERM_COHESION) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) o.F[k] += (Real)c.cohesion * n[k];
+  }
+  if (c.terms & DEM_TERM_ROLLING) {
+    const Real wn = sqrt(wrel[0] * wrel[0] + wrel[1] * wrel[1] + wrel[2] * wrel[2]);
+    if (wn > (Real)0) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) C[k] = -(Real)c.rolling_mu * R * o.fn * wrel[k] / wn;
+    }
+  }
 }
 
 template <typename Real, int LAW>
-__device__ __forceinline__ double elastic_energy(const Consts &c, Real delta, Real R, const LawOut<Real> &o,
-                                                 const Real h[3]) {
+__device__ __forceinline__ double elastic_energy(const Consts &c, const PairK &K, Real delta, Real R,
+                                                 const LawOut<Real> &o, const Real h[3]) {
   const double d = (double)delta;
   const double hh = (double)h[0] * h[0] + (double)h[1] * h[1] + (double)h[2] * h[2];
   if (LAW == DEM_LAW_SIMPLE) return 0.5 * c.k_sp * d * d;
-  if (LAW == DEM_LAW_HERTZ) return 0.4 * c.kn * sqrt((double)R) * pow(d, 2.5) + 0.5 * (double)o.kt * hh;
+  if (LAW == DEM_LAW_HERTZ) return 0.4 * K.kn * sqrt((double)R) * pow(d, 2.5) + 0.5 * (double)o.kt * hh;
   return 0.5 * (double)o.kn * d * d + 0.5 * (double)o.kt * hh;
 }
 
@@ -1379,6 +1426,8 @@ __device__ __forceinline__ int2 hist_index(const PairArgs &a, bool old_perm, int
 // state records.
 template <typename Real, int LAW>
 __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t k) {
+  constexpr int BASE = LAW & 3;                       // the dem_law
+  constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
   const int32_t N = a.L.n;
   const int64_t q = (int64_t)k * N + s;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
@@ -1396,6 +1445,10 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
     else
       hist_find<Real>(a.old, N, hs.x, hs.y, t, h);
   }
+  // the constants of the pair's materials (a wall is of the system's wall
+  // material), or the system's one material
+  PairK K{c.kn, c.kt, c.alpha, c.mu};
+  if (si.ntypes > 0) K = a.L.mat[si.mat0 + me.mt * si.ntypes + (t >= 0 ? pt.mt : si.wall_type)];
   const float rsf = me.r;
   const Real rs = (Real)rsf;
   const Real ms = mass_of<Real>(c, rs);
@@ -1421,28 +1474,55 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
       v[i] = me.v[i] - pt.v[i];
       spin[i] = rs * me.w[i] + rt * pt.w[i];
     }
-    contact_law<Real, LAW>(c, n, delta, R, M, v, spin, h, o);
+    contact_law<Real, BASE>(c, K, n, delta, R, M, v, spin, h, o);
   } else {
-    // Step 8: wall -1 - t, a particle of infinite radius
+    // Step 8: wall -1 - t, a particle of infinite radius: a box wall, or
+    // a plate touched at its nearest point
     const int w = -1 - t;
-    const int ax = w >> 1;
     const double xw[3] = {me.x, me.y, me.z};
-    const double gap = (w & 1) ? (si.g.hi[ax] - xw[ax]) : (xw[ax] - si.g.lo[ax]);
-    n[0] = n[1] = n[2] = 0;
-    n[ax] = (w & 1) ? (Real)1 : (Real)-1;
-    delta = (Real)((double)rsf - gap);
+    if (w >= 6) {
+      double d[3];
+      plate_gap(si.plates[w - 6], xw, d);
+      const double d2 = dist2_exact(d[0], d[1], d[2]);
+      const double dist = sqrt(d2);
+#pragma unroll
+      for (int i = 0; i < 3; i++) n[i] = (Real)(-d[i] / dist);
+      // r - d from r^2 - d^2 (as for pairs): a resting sphere's overlap is
+      // many orders below r, and this form does not carry the rounding of
+      // the square root into it
+      delta = (Real)((sq_exact((double)rsf) - d2) / ((double)rsf + dist));
+    } else {
+      const int ax = w >> 1;
+      const double gap = (w & 1) ? (si.g.hi[ax] - xw[ax]) : (xw[ax] - si.g.lo[ax]);
+      n[0] = n[1] = n[2] = 0;
+      n[ax] = (w & 1) ? (Real)1 : (Real)-1;
+      delta = (Real)((double)rsf - gap);
+    }
     R = rs;
     Real spin[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) spin[i] = rs * me.w[i];
-    contact_law<Real, LAW>(c, n, delta, rs, ms, me.v, spin, h, o);
+    contact_law<Real, BASE>(c, K, n, delta, rs, ms, me.v, spin, h, o);
+  }
+  if (TERMS) {
+    Real wrel[3], C[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) wrel[i] = t >= 0 ? me.w[i] - pt.w[i] : me.w[i];
+    extra_terms<Real>(c, n, R, wrel, o, C);
+    using V4 = typename Vec4T<Real>::type;
+    V4 cv;
+    cv.x = C[0];
+    cv.y = C[1];
+    cv.z = C[2];
+    cv.w = 0;
+    ((V4 *)a.w.pc)[q] = cv;
   }
   const Real tq[3] = {n[1] * o.Ft[2] - n[2] * o.Ft[1], n[2] * o.Ft[0] - n[0] * o.Ft[2],
                       n[0] * o.Ft[1] - n[1] * o.Ft[0]};
   put_record<Real>(a.w.pf, q, o.F, tq);
   if (write_hist) put_entry<Real>(a.cur, q, o.dtn, t);
   if (diag) {
-    a.w.pe[q] = elastic_energy<Real, LAW>(c, delta, R, o, h);
+    a.w.pe[q] = elastic_energy<Real, BASE>(c, K, delta, R, o, h);
     a.w.pd[q] = (double)delta;
   }
   if (t >= 0) {
@@ -1625,7 +1705,17 @@ __device__ __forceinline__ int64_t bwd_record(int32_t b, int32_t N) {
   return (int64_t)(b & ((1 << kOwnerShift) - 1)) * N + (b >> kOwnerShift);
 }
 
+// the couple of the optional terms of contact q (XT: compiled in)
 template <typename Real>
+__device__ __forceinline__ void couple_of(const PairArgs &a, int64_t q, Real C[3]) {
+  using V4 = typename Vec4T<Real>::type;
+  const V4 cv = ((const V4 *)a.w.pc)[q];
+  C[0] = cv.x;
+  C[1] = cv.y;
+  C[2] = cv.z;
+}
+
+template <typename Real, bool XT>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   using V2 = typename Vec2T<Real>::type;
   __shared__ int32_t bo[kBlock + 1];       // the block's backward segments
@@ -1657,6 +1747,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     a.pos_out.z[s] = me.z;
     a.pos_out.r[s] = me.r;
     a.pos_out.id[s] = me.id;
+    if (a.pos_out.mt) a.pos_out.mt[s] = me.mt;
     a.cell[s] = a.scell[s];
     return;
   }
@@ -1707,6 +1798,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     T[0] += rs * m[0];  // Eq. 3; the same n x F_t on both bodies
     T[1] += rs * m[1];
     T[2] += rs * m[2];
+    if (XT) {  // the opposite of the owner's couple
+      Real C[3];
+      couple_of<Real>(a, bwd_record(b, N), C);
+      T[0] -= C[0];
+      T[1] -= C[1];
+      T[2] -= C[2];
+    }
   };
   if (staged) {
     // ascending by owner slot: each next entry is the smallest above the
@@ -1730,6 +1828,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
       T[0] += rs * r1.y;  // Eq. 3; the same n x F_t on both bodies
       T[1] += rs * r2.x;
       T[2] += rs * r2.y;
+      if (XT) {
+        Real C[3];
+        couple_of<Real>(a, bwd_record(cur, N), C);
+        T[0] -= C[0];
+        T[1] -= C[1];
+        T[2] -= C[2];
+      }
     }
   } else if (nbk <= 4) {
     for_sorted<4>(a.w.bwd, N, s, nbk, back);
@@ -1752,6 +1857,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     T[0] += rs * m[0];
     T[1] += rs * m[1];
     T[2] += rs * m[2];
+    if (XT) {
+      Real C[3];
+      couple_of<Real>(a, q, C);
+      T[0] += C[0];
+      T[1] += C[1];
+      T[2] += C[2];
+    }
     if (diag) {
       e_el += a.w.pe[q];
       dmax = fmax(dmax, a.w.pd[q]);
@@ -1793,6 +1905,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     }
     a.pos_out.r[s] = me.r;
     a.pos_out.id[s] = me.id;
+    if (a.pos_out.mt) a.pos_out.mt[s] = me.mt;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)a.vel_out.v[q])[s] = v[q];
@@ -1809,6 +1922,35 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
 
 __global__ void k_step_end(StepCtl ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *ctl.step += 1;
+}
+
+// --------------------------------------------------------------------------
+// Largest speed of each system (the at-rest test of Sec. 5's run: every
+// particle's step dt |v| below a set value).  The maximum does not depend on
+// the order of the updates, and a non-negative double orders like its bits.
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void k_max_speed(Layout L, VelBuf vb, unsigned long long *vmax) {
+#pragma clang fp contract(off)
+  int32_t k;
+  const int32_t s = block_slot(L, k);
+  double q = 0.0;
+  if (s >= 0) {
+    const double vx = (double)((const Real *)vb.v[0])[s], vy = (double)((const Real *)vb.v[1])[s],
+                 vz = (double)((const Real *)vb.v[2])[s];
+    q = sqrt(vx * vx + vy * vy + vz * vz);
+  }
+  // the block's largest, then one atomic per block
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) q = fmax(q, __shfl_xor(q, d));
+  __shared__ double wmax[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int w = 1; w < kBlock / 64; w++) m = fmax(m, wmax[w]);
+    atomicMax(vmax + k, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1977,8 +2119,19 @@ hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, c
     return hipSuccess;
   }
   const bool f64 = precision == DEM_PREC_FP64;
-  const int law = a ? a->law : DEM_LAW_LINEAR;  // detection alone does not depend on the law
+  // detection alone does not depend on the law
+  const int law = a ? (a->law | (a->terms && a->law != DEM_LAW_SIMPLE ? kLawTerms : 0)) : DEM_LAW_LINEAR;
   switch (law) {
+    case DEM_LAW_LINEAR | kLawTerms:
+      return f64 ? contacts_t<double, DEM_LAW_LINEAR | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
+                                                                  after_detect)
+                 : contacts_t<float, DEM_LAW_LINEAR | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
+                                                                 after_detect);
+    case DEM_LAW_HERTZ | kLawTerms:
+      return f64 ? contacts_t<double, DEM_LAW_HERTZ | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
+                                                                 after_detect)
+                 : contacts_t<float, DEM_LAW_HERTZ | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
+                                                                after_detect);
     case DEM_LAW_HERTZ:
       return f64 ? contacts_t<double, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
                  : contacts_t<float, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
@@ -1993,10 +2146,27 @@ hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, c
 
 hipError_t launch_gather(int precision, const PairArgs &a, hipStream_t st) {
   if (a.L.n <= 0) return hipSuccess;
+  if (precision == DEM_PREC_FP64) {
+    if (a.terms)
+      k_gather<double, true><<<a.L.nblocks, kBlock, 0, st>>>(a);
+    else
+      k_gather<double, false><<<a.L.nblocks, kBlock, 0, st>>>(a);
+  } else {
+    if (a.terms)
+      k_gather<float, true><<<a.L.nblocks, kBlock, 0, st>>>(a);
+    else
+      k_gather<float, false><<<a.L.nblocks, kBlock, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_max_speed(int precision, const Layout &L, const VelBuf &v, unsigned long long *vmax,
+                            hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
   if (precision == DEM_PREC_FP64)
-    k_gather<double><<<a.L.nblocks, kBlock, 0, st>>>(a);
+    k_max_speed<double><<<L.nblocks, kBlock, 0, st>>>(L, v, vmax);
   else
-    k_gather<float><<<a.L.nblocks, kBlock, 0, st>>>(a);
+    k_max_speed<float><<<L.nblocks, kBlock, 0, st>>>(L, v, vmax);
   return hipGetLastError();
 }
 

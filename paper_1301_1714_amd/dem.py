@@ -15,6 +15,7 @@ from . import build as _build
 
 LAWS = {"linear": 0, "hertz": 1, "simple": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+TERMS = {"cohesion": 1, "rolling": 2}  # optional contact terms: params["terms"] is a tuple of these names
 
 DEM_OK = 0
 DEM_E_INVALID = -1
@@ -39,6 +40,14 @@ class DemError(RuntimeError):
         self.code = code
 
 
+MAX_PLATES = 4
+
+
+class DemPlate(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("reserved", C.c_int32), ("at", C.c_double),
+                ("lo", C.c_double * 2), ("hi", C.c_double * 2)]
+
+
 class DemParams(C.Structure):
     _fields_ = [
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
@@ -51,6 +60,10 @@ class DemParams(C.Structure):
         ("cell_size", C.c_double),
         ("contacts_per_particle", C.c_int32), ("precision", C.c_int32),
         ("tile_cells", C.c_int32), ("cell_divisor", C.c_int32),
+        ("max_materials", C.c_int32), ("terms", C.c_uint32),
+        ("cohesion", C.c_double), ("rolling_mu", C.c_double),
+        ("nplates", C.c_int32), ("reserved", C.c_int32),
+        ("plates", DemPlate * MAX_PLATES),
     ]
 
 
@@ -78,6 +91,10 @@ def lib():
             "dem_diagnostics": ([P, C.POINTER(C.c_double)], st),
             "dem_sync": ([P], st),
             "dem_set_radii": ([P, P], st),
+            "dem_set_materials": ([P, C.c_int32, P, P, C.c_int32], st),
+            "dem_max_speed": ([P, C.POINTER(C.c_double)], st),
+            "dem_run_to_rest": ([P, C.c_double, I64, I64, C.POINTER(I64)], st),
+            "dem_batch_max_speed": ([P, P], st),
             "dem_profile": ([P, C.c_int], st),
             "dem_profile_read": ([P, C.POINTER(C.c_double), C.POINTER(I64)], st),
             "dem_use_graph": ([P, C.c_int], st),
@@ -86,6 +103,7 @@ def lib():
             "dem_batch_workspace_bytes": ([C.c_int32, P, P, C.POINTER(S)], st),
             "dem_batch_create": ([C.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, S, P, C.POINTER(P)], st),
             "dem_batch_set_radii": ([P, P], st),
+            "dem_batch_set_materials": ([P, C.c_int32, C.c_int32, P, P, C.c_int32], st),
             "dem_batch_step": ([P, P], st),
             "dem_batch_read_state": ([P, C.c_int32, P, P, P, P, P], st),
             "dem_batch_read_contacts": ([P, C.c_int32, I64, C.POINTER(I64), P, P], st),
@@ -124,6 +142,19 @@ def make_params(p: dict) -> DemParams:
     o.precision = PRECISIONS[p.get("precision", "fp64")]
     o.tile_cells = int(p.get("tile_cells", 0))
     o.cell_divisor = int(p.get("cell_divisor", 1))
+    o.max_materials = int(p.get("max_materials", 0))
+    o.terms = sum(TERMS[t] for t in p.get("terms", ()))
+    o.cohesion = float(p.get("cohesion", 0.0))
+    o.rolling_mu = float(p.get("rolling_mu", 0.0))
+    plates = p.get("plates", ())
+    if len(plates) > MAX_PLATES:
+        raise ValueError(f"at most {MAX_PLATES} plates")
+    o.nplates = len(plates)
+    for k, q in enumerate(plates):
+        o.plates[k].axis = int(q["axis"])
+        o.plates[k].at = float(q["at"])
+        o.plates[k].lo[:] = [float(t) for t in q["lo"]]
+        o.plates[k].hi[:] = [float(t) for t in q["hi"]]
     return o
 
 
@@ -274,6 +305,28 @@ class System:
             raise ValueError("set_radii: one radius per particle")
         _check(lib().dem_set_radii(self.handle, _ptr(r)), "dem_set_radii")
 
+    def max_speed(self):
+        out = C.c_double()
+        _check(lib().dem_max_speed(self.handle, C.byref(out)), "dem_max_speed")
+        return out.value
+
+    def run_to_rest(self, threshold, check_every, max_steps):
+        """Step in chunks of check_every until dt * max |v_i| < threshold or
+        max_steps are done; returns the steps done."""
+        done = C.c_int64()
+        _check(lib().dem_run_to_rest(self.handle, float(threshold), int(check_every), int(max_steps),
+                                     C.byref(done)), "dem_run_to_rest")
+        return done.value
+
+    def set_materials(self, types, table, wall_type=0):
+        """Material-pair table: table[t, u] = (kn, kt, restitution, mu) of a
+        particle of material t touching one of material u (symmetric),
+        types[i] the material of particle i (original order), walls of
+        material wall_type; types=None goes back to the parameters' one
+        material."""
+        nt, tab, ty = _material_args(types, table, self.n)
+        _check(lib().dem_set_materials(self.handle, nt, _ptr(tab), _ptr(ty), int(wall_type)), "dem_set_materials")
+
     def use_graph(self, enable: bool = True):
         """Replay each time step from a HIP graph (needs a non-default stream)."""
         _check(lib().dem_use_graph(self.handle, int(bool(enable))), "dem_use_graph")
@@ -288,6 +341,19 @@ class System:
         n = C.c_int64()
         _check(lib().dem_profile_read(self.handle, ms, C.byref(n)), "dem_profile_read")
         return np.array(ms[:]), n.value
+
+
+def _material_args(types, table, n):
+    if types is None:
+        return 0, None, None
+    tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+    nt = tab.shape[0]
+    if tab.shape != (nt, nt, 4):
+        raise ValueError("table must be ntypes x ntypes x 4")
+    ty = np.ascontiguousarray(np.asarray(types, dtype=np.int32).reshape(-1))
+    if ty.shape[0] != n:
+        raise ValueError("one material per particle")
+    return nt, tab, ty
 
 
 def _params_array(params_list):
@@ -392,6 +458,17 @@ class Batch:
         if [len(np.asarray(q).reshape(-1)) for q in radii] != self.ns:
             raise ValueError("set_radii: one radius per particle of every system")
         _check(lib().dem_batch_set_radii(self.handle, _ptr(r)), "dem_batch_set_radii")
+
+    def max_speed(self):
+        out = np.zeros(self.S)
+        _check(lib().dem_batch_max_speed(self.handle, _ptr(out)), "dem_batch_max_speed")
+        return out
+
+    def set_materials(self, k: int, types, table, wall_type=0):
+        """``System.set_materials`` for system k (types in its own order)."""
+        nt, tab, ty = _material_args(types, table, self.ns[k])
+        _check(lib().dem_batch_set_materials(self.handle, int(k), nt, _ptr(tab), _ptr(ty), int(wall_type)),
+               "dem_batch_set_materials")
 
     def use_graph(self, enable: bool = True):
         _check(lib().dem_batch_use_graph(self.handle, int(bool(enable))), "dem_batch_use_graph")

@@ -29,6 +29,10 @@ Parameter dictionary keys (each side marshals them into its own structure):
   cell_divisor       k: grid cells of cell_size / k swept over (2k + 1)^3 cells
                      (GPU only; 1 or 2; speed and summation order only)
   precision          "fp64" or "mixed" (FP32 forces, FP64 positions; GPU only)
+  max_materials      most materials of a material-pair table (0: one material)
+  terms              optional contact terms, a tuple of "cohesion" and "rolling"
+  cohesion, rolling_mu  their constants (pull in N; rolling-resistance coefficient)
+  plates             finite walls: dicts axis, at, lo (2), hi (2), at most 4
 """
 import math
 
@@ -224,7 +228,7 @@ def dense_bed_geometry(seed=3000, n=1 << 24, phi=0.55, median=1.0 / 512.0, sigma
 def dense_bed_params(r, hi, **kw):
     r_min = float(np.min(r))
     p = base_params(box_hi=hi, cell_size=2.0 * float(np.max(r)), precision="mixed",
-                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=16)
+                    dt=stable_dt(KN, E_REST, r_min), contacts_per_particle=32)
     p.update(kw)
     return p
 
@@ -369,6 +373,47 @@ def serving_requests(seed=5000, count=512, n_lo=1024, n_hi=1 << 20, steps_lo=100
         d["seed"] = seed + 1 + k
         reqs.append(d)
     return reqs
+
+
+# ------------------------------------------------- the paper's sample problem
+
+def slit_plates(z, x0, x1, box_lo, box_hi):
+    """Two finite walls at height z that close the box's cross-section except
+    for the slit x0 < x < x1 (across the whole y range)."""
+    return [dict(axis=2, at=float(z), lo=(float(box_lo[0]), float(box_lo[1])), hi=(float(x0), float(box_hi[1]))),
+            dict(axis=2, at=float(z), lo=(float(x1), float(box_lo[1])), hi=(float(box_hi[0]), float(box_hi[1])))]
+
+
+def slit_hopper(seed=6000, n=1 << 17, r=1.0e-3, nx=64, ny=16, slit_diameters=10.0, low_cells=64,
+                precision="mixed", law="linear", rest_fraction=1.0e-5):
+    """Sec. 5's sample problem: n equal spheres that fall from a box through a
+    slit in its bottom onto a floor, run until every particle's step is below
+    a set displacement.  The paper gives no sizes; here the spheres (radius r)
+    start at rest on a jittered cubic lattice of spacing 2.2 r, nx x ny x
+    n / (nx ny) sites, filling the upper chamber of a walled box whose
+    bottom is a pair of plates at height z_s = low_cells x 2.2 r with a slit
+    of slit_diameters diameters across the middle of x; the floor is the box's
+    lower z wall.  Materials as the other workloads (k_n 1e5, e 0.9,
+    k_t 2/7 k_n, mu 0.3), dt = t_c / 10, cell = 2 r.  `rest_displacement` is
+    the stopping threshold rest_fraction x r per step."""
+    rng = np.random.default_rng(seed)
+    nz = n // (nx * ny)
+    if nx * ny * nz != n:
+        raise ValueError("n must be a multiple of nx * ny")
+    a = 2.2 * r
+    Lx, Ly = nx * a, ny * a
+    zs = low_cells * a
+    hi = (Lx, Ly, zs + (nz + 1) * a)
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    sites = np.stack([(i.ravel() + 0.5) * a, (j.ravel() + 0.5) * a, zs + (k.ravel() + 0.5) * a], axis=1)
+    x = sites + rng.uniform(-0.04 * a, 0.04 * a, size=sites.shape)
+    rr = fp32_radii(np.full(n, r))
+    w = slit_diameters * 2.0 * r
+    plates = slit_plates(zs, 0.5 * Lx - 0.5 * w, 0.5 * Lx + 0.5 * w, (0.0, 0.0, 0.0), hi)
+    p = base_params(box_hi=hi, cell_size=2.0 * float(rr.max()), dt=stable_dt(KN, E_REST, float(rr.min())),
+                    precision=precision, law=law, contacts_per_particle=12, plates=plates)
+    return dict(name=f"slit_hopper_{n}", params=p, x=x, v=np.zeros((n, 3)), omega=np.zeros((n, 3)), r=rr,
+                slit=(0.5 * Lx - 0.5 * w, 0.5 * Lx + 0.5 * w), z_slit=zs, rest_displacement=rest_fraction * r)
 
 
 def poisson_arrivals(seed, count, rate):

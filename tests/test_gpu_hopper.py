@@ -1,0 +1,177 @@
+"""Sec. 5's sample problem on the GPU: finite walls (the slit plate), the
+slit-hopper workload, and the run to rest, against the oracle through the C
+ABI.  Contact lists with plate contacts bit-exact; forces within the force
+tolerance; FP64 trajectories within 1e-12; the run to rest stops at the same
+step as the oracle's on a case whose trajectory is not chaotic."""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSystem
+from paper_1301_1714_amd import workloads as W
+from parity_util import assert_forces_close
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1301_1714_amd import dem as D
+    D.lib()
+    return D
+
+
+def plate_cloud(seed, n, precision="fp64", law="linear", shape=0):
+    """A crowded cloud with a third of the spheres at the level of a slit
+    plate and many at the slit's edges, plus a vertical plate."""
+    box = (0.3, 0.2, 0.3)
+    rm = 0.01
+    c = W.overlapping_cloud(seed, n, box=box, r_mean=rm, r_spread=0.3, spacing=0.97, law=law,
+                            precision=precision)
+    rng = np.random.default_rng(seed)
+    x = c["x"].copy()
+    zs = 0.15
+    k = np.arange(0, n, 5)
+    x[k, 2] = zs + rng.uniform(-1.2 * rm, 1.2 * rm, size=len(k))
+    e = np.arange(1, n, 11)
+    x[e, 0] = np.where(rng.random(len(e)) < 0.5, 0.12, 0.18) + rng.uniform(-1.2 * rm, 1.2 * rm, size=len(e))
+    x[e, 2] = zs + rng.uniform(-1.2 * rm, 1.2 * rm, size=len(e))
+    plates = W.slit_plates(zs, 0.12, 0.18, (0, 0, 0), box) + [dict(axis=0, at=0.05, lo=(0.02, 0.1), hi=(0.12, 0.2))]
+    c["x"] = x
+    c["params"] = dict(c["params"], plates=plates, mu=0.3, eta_t_ratio=0.5, dt=2e-6, tile_cells=shape,
+                       contacts_per_particle=64)
+    return c
+
+
+@pytest.mark.parametrize("precision,law,shape", [("fp64", "linear", 0), ("mixed", "linear", 0),
+                                                 ("fp64", "hertz", -1), ("mixed", "linear", 4)])
+def test_plate_contacts_and_forces(dem, precision, law, shape):
+    c = plate_cloud(71, 1500, precision, law, shape)
+    g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    pg, po = g.contacts(), o.contacts()
+    assert np.sum(po[:, 1] <= -7) > 100
+    assert np.array_equal(pg, po)
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL[precision])
+
+
+def test_fp64_steps_with_plates_track_the_oracle(dem):
+    c = plate_cloud(72, 1200)
+    g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    for _ in range(4):
+        g.step(5)
+        o.step(5)
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-12
+    pg, dg = g.read_contacts()
+    po, do = o.read_contacts()
+    assert np.array_equal(pg, po)
+    assert np.max(np.abs(dg - do)) <= 1e-9 * max(np.abs(do).max(), 1e-300)
+
+
+def small_hopper(seed=6100, precision="fp64"):
+    """512 spheres, a slit of 3 diameters; restitution 0.3 so that the
+    spheres landing on the plates stay there."""
+    w = W.slit_hopper(seed, n=8 * 4 * 16, nx=8, ny=4, slit_diameters=3.0, low_cells=8, precision=precision)
+    w["params"] = dict(w["params"], restitution=0.3)
+    return w
+
+
+def test_small_hopper_tracks_the_oracle(dem):
+    """512 spheres start to fall onto the slit plate: after 3,000 steps (the
+    lowest layers have landed and the column is compacting) the state and the
+    contact list agree with the oracle's."""
+    w = small_hopper()
+    g = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    o = OracleSystem(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    seen = 0
+    for _ in range(6):
+        g.step(500)
+        o.step(500)
+        po = o.contacts()
+        assert np.array_equal(g.contacts(), po)
+        seen += int(np.sum(po[:, 1] <= -7)) if len(po) else 0
+    assert seen > 5  # spheres on the plates at the checkpoints
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-9
+
+
+def test_small_hopper_flows_through_the_slit(dem):
+    """The same hopper after 14,000 GPU steps: spheres have passed the slit;
+    on that state (restarted in the oracle with the GPU's forces and history)
+    grid, contacts and forces agree."""
+    w = small_hopper()
+    g = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    g.step(14000)
+    st = g.read_state()
+    assert st["x"][:, 2].min() < w["z_slit"] - 2 * float(w["r"][0])
+    pairs, dts = g.read_contacts()
+    o = OracleSystem(w["params"], st["x"], st["v"], st["omega"], w["r"], F0=st["F"], T0=st["T"],
+                     hist_pairs=pairs, hist_dt=dts)
+    assert np.array_equal(g.contacts(), o.contacts())
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    # spheres at rest overlap by about m g / k_n, some 1e-6 of their radius,
+    # and the oracle forms r - d (plates) and S - d (pairs) by plain
+    # subtraction: one ulp of r in the overlap is k_n ulp(r) of force
+    r = float(w["r"][0])
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["fp64"],
+                        floor_abs=4.0 * w["params"]["kn"] * np.spacing(2 * r), torque_floor_abs=0.0)
+
+
+def test_run_to_rest_matches_the_oracle(dem):
+    """Three spheres dropped onto the plate, through the slit and onto the
+    floor, far enough apart never to touch each other: both sides stop at the
+    same check (dt max |v| < threshold every 500 steps).  The threshold
+    (1e-10 m per step, |v| < 4.4e-5 m/s) is tight enough that a check at the
+    top of a bounce, where the speed passes through zero, does not stop the
+    run: the spheres come to rest on the plates and the floor."""
+    w = small_hopper()
+    p = w["params"]
+    r = float(w["r"][0])
+    x0, x1 = w["slit"]
+    zs = w["z_slit"]
+    x = np.array([[0.5 * (x0 + x1), 0.004, zs + 4 * r],   # through the slit
+                  [0.5 * x0, 0.004, zs + 3 * r],           # onto the left plate
+                  [x1 + 0.6 * r, 0.006, zs + 5 * r]])      # onto the slit's right edge
+    zero = np.zeros((3, 3))
+    rr = np.full(3, r)
+    p = dict(p, restitution=0.5)
+    g = dem.System(p, x, zero, zero, rr)
+    assert g.max_speed() == 0.0
+    o = OracleSystem(p, x, zero, zero, rr)
+    ng = g.run_to_rest(1e-10, 500, 400000)
+    no = o.run_to_rest(1e-10, 500, 400000)
+    assert ng == no < 400000
+    assert abs(o.read_state()["x"][0, 2] - r) < 1e-3 * r  # the first one rests on the floor
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-9
+    assert abs(g.max_speed() - o.max_speed()) <= 1e-9 * max(o.max_speed(), 1e-12)
+
+
+def test_full_size_hopper_contacts_after_the_first_steps(dem):
+    """The benchmark's 2^17-sphere hopper in its timed configuration (mixed
+    precision): after 1,500 steps on the GPU, that state's grid and contact
+    list are bit-exact against the oracle and its forces within 1e-5."""
+    w = W.slit_hopper()
+    g = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"])
+    g.step(1500)
+    st = g.read_state()
+    pairs, dts = g.read_contacts()
+    o = OracleSystem(w["params"], st["x"], st["v"], st["omega"], w["r"], F0=st["F"], T0=st["T"],
+                     hist_pairs=pairs, hist_dt=dts)
+    h = dem.System(w["params"], st["x"], st["v"], st["omega"], w["r"], F0=st["F"], T0=st["T"],
+                   hist_pairs=pairs, hist_dt=dts)
+    cg, og, sg = h.read_grid()
+    co, oo, so = o.read_grid()
+    assert np.array_equal(cg, co) and np.array_equal(og, oo) and np.array_equal(sg, so)
+    assert np.array_equal(h.contacts(), o.contacts())
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = h.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["mixed"])

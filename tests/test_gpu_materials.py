@@ -1,0 +1,152 @@
+"""Material-pair tables on the GPU (Sec. 3: the constants C_kn, C_kt and
+alpha of Eqs. 8-10 carry the indices of the two bodies in contact) against
+the oracle's tables, through the C ABI: forces on identical states within the
+force tolerance, FP64 trajectories within 1e-12, and a batch whose systems
+carry different tables bitwise equal to each system alone."""
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleSystem
+from paper_1301_1714_amd import workloads as W
+from parity_util import assert_forces_close
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1301_1714_amd import dem as D
+    D.lib()
+    return D
+
+
+def table(rng, nt, law):
+    """A symmetric table of nt materials whose entries all differ."""
+    base = 1.0e5 if law == "linear" else 1.0e7
+    t = np.zeros((nt, nt, 4))
+    for a in range(nt):
+        for b in range(a, nt):
+            kn = base * rng.uniform(0.3, 3.0)
+            row = (kn, rng.uniform(0.1, 0.4) * kn, rng.uniform(0.3, 0.98), rng.uniform(0.05, 0.8))
+            t[a, b] = t[b, a] = row
+    return t
+
+
+def cloud(seed, n, nt, precision="fp64", law="linear", walls=W.ALL_WALLS):
+    side = (n * 1.6) ** (1.0 / 3.0) * 0.95 * 2 * 0.01
+    c = W.overlapping_cloud(seed, n, box=(side, 0.8 * side, 1.2 * side), r_mean=0.01, r_spread=0.3,
+                            spacing=0.95, law=law, precision=precision, walls=walls)
+    rng = np.random.default_rng(seed + 100)
+    c["params"] = dict(c["params"], max_materials=nt, eta_t_ratio=0.5, dt=2e-6)
+    c["types"] = rng.integers(0, nt, size=n).astype(np.int32)
+    c["table"] = table(rng, nt, law)
+    c["wall_type"] = int(rng.integers(0, nt))
+    return c
+
+
+CASES = {
+    "fp64_linear_3mat": dict(seed=21, n=2500, nt=3),
+    "mixed_linear_4mat": dict(seed=22, n=3001, nt=4, precision="mixed"),
+    "fp64_hertz_2mat": dict(seed=23, n=2000, nt=2, law="hertz"),
+    "mixed_hertz_16mat": dict(seed=24, n=2600, nt=16, law="hertz", precision="mixed"),
+}
+
+
+def make(dem, c):
+    g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    o = OracleSystem(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    g.set_materials(c["types"], c["table"], c["wall_type"])
+    o.set_materials(c["types"], c["table"], c["wall_type"])
+    return g, o
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_forces_with_material_tables(dem, name):
+    c = cloud(**CASES[name])
+    g, o = make(dem, c)
+    F, T, Fa, Ta = o.forces_scale()
+    tol = TOL[c["params"]["precision"]]
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, tol)
+    # the stored forces were evaluated again with the table
+    st = g.read_state()
+    assert_forces_close(st["F"], st["T"], F, T, Fa, Ta, tol)
+    # and the table matters: one material gives other forces
+    g1 = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    assert np.max(np.abs(g1.forces()[0] - Fg)) > 1e-3 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("name", ["fp64_linear_3mat", "fp64_hertz_2mat"])
+def test_fp64_steps_with_materials_track_the_oracle(dem, name):
+    c = cloud(**CASES[name])
+    g, o = make(dem, c)
+    for _ in range(4):
+        g.step(5)
+        o.step(5)
+    sg, so = g.read_state(), o.read_state()
+    assert np.max(np.abs(sg["x"] - so["x"])) < 1e-12
+    assert np.max(np.abs(sg["v"] - so["v"])) < 1e-9 * np.abs(so["v"]).max()
+    pg, dg = g.read_contacts()
+    po, do = o.read_contacts()
+    assert np.array_equal(pg, po)
+    assert np.max(np.abs(dg - do)) <= 1e-9 * max(np.abs(do).max(), 1e-300)
+    dg_, do_ = g.diagnostics(), o.diagnostics()
+    assert np.allclose(dg_[[3, 4, 5, 6, 9]], do_[[3, 4, 5, 6, 9]], rtol=1e-9, atol=0)
+
+
+def test_table_of_one_entry_is_one_material(dem):
+    c = cloud(25, 2000, 3)
+    p = c["params"]
+    one = np.tile(np.array([p["kn"], p["kt"], p["restitution"], p["mu"]]), (3, 3, 1))
+    g = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    h = dem.System(p, c["x"], c["v"], c["omega"], c["r"])
+    h.set_materials(c["types"], one, 1)
+    g.step(10)
+    h.step(10)
+    a, b = g.read_state(), h.read_state()
+    for k in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(a[k], b[k]), k
+    # back to the one material of the parameters
+    h.set_materials(None, None)
+    g.step(5)
+    h.step(5)
+    assert np.array_equal(g.read_state()["x"], h.read_state()["x"])
+
+
+def test_batch_with_tables_matches_alone(dem):
+    cs = [cloud(31, 1500, 3), cloud(32, 700, 2), cloud(33, 1100, 4)]
+    cs[1]["types"] = None  # one material in the middle of the batch
+    systems = [dict(params=c["params"], x=c["x"], v=c["v"], omega=c["omega"], r=c["r"]) for c in cs]
+    b = dem.Batch(systems)
+    for k, c in enumerate(cs):
+        if c["types"] is not None:
+            b.set_materials(k, c["types"], c["table"], c["wall_type"])
+    b.step([12, 7, 12])
+    for k, (c, steps) in enumerate(zip(cs, [12, 7, 12])):
+        g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+        if c["types"] is not None:
+            g.set_materials(c["types"], c["table"], c["wall_type"])
+        g.step(steps)
+        sa, sb = g.read_state(), b.read_state(k)
+        for key in ("x", "v", "omega", "F", "T"):
+            assert np.array_equal(sa[key], sb[key]), (k, key)
+
+
+def test_invalid_tables_are_refused(dem):
+    c = cloud(26, 500, 2)
+    g = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    t = c["table"].copy()
+    t[0, 1, 0] *= 2.0  # not symmetric
+    with pytest.raises(dem.DemError):
+        g.set_materials(c["types"], t, 0)
+    with pytest.raises(dem.DemError):  # more materials than max_materials
+        g.set_materials(np.zeros(500, np.int32), table(np.random.default_rng(0), 3, "linear"), 0)
+    bad = c["types"].copy()
+    bad[7] = 2
+    with pytest.raises(dem.DemError):
+        g.set_materials(bad, c["table"], 0)
+    g.step(2)  # still usable

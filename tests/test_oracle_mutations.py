@@ -49,8 +49,8 @@ MUTATIONS = {
                 "s->I[i] = 0.4 * s->m[i] * ri * ri;",
                 "s->I[i] = 0.5 * s->m[i] * ri * ri;"),
     "wall_mass": ("Sec. 4.2 Step 8: a wall is a particle of infinite mass",
-                  "G->M = s->m[a];\n}",
-                  "G->M = 0.5 * s->m[a];\n}"),
+                  "    G->M = s->m[a];\n    return ORC_OK;\n}",
+                  "    G->M = 0.5 * s->m[a];\n    return ORC_OK;\n}"),
     "contact_le": ("contact means d < r_i + r_j",
                    "return d2 < S * S;",
                    "return d2 <= S * S * 1.000001;"),
@@ -111,6 +111,15 @@ MUTATIONS = {
     "rolling_total_normal": ("the rolling couple scales with Eq. 4's |F_n|, not the net normal force",
                              "C[k] = -p->rolling_mu * G->R * fn * G->wrel[k] / wn;",
                              "C[k] = -p->rolling_mu * G->R * fabs(dot3(F, G->n)) * G->wrel[k] / wn;"),
+    "plate_unbounded": ("a plate is finite: its nearest point is clamped to the rectangle",
+                        "q[u] = c[u] < P->lo[0] ? P->lo[0] : (c[u] > P->hi[0] ? P->hi[0] : c[u]);",
+                        "q[u] = c[u];"),
+    "plate_normal_sign": ("n points from the centre to the plate's nearest point",
+                          "G->n[k] = -d[k] / dist;",
+                          "G->n[k] = d[k] / dist;"),
+    "plate_index": ("wall w >= 6 is plate w - 6",
+                    "plate_nearest(&s->p.plates[w - 6], s->x + 3 * a, q, d);\n        return",
+                    "plate_nearest(&s->p.plates[w == 6 ? 1 : 0], s->x + 3 * a, q, d);\n        return"),
     "history_side": ("Eq. 6: the history seen from the other particle is negated",
                      "const double *h = he ? he->d : zero;",
                      "double hneg[3]; if (he) { hneg[0]=-he->d[0]; hneg[1]=-he->d[1]; hneg[2]=-he->d[2]; } "
