@@ -464,6 +464,51 @@ def bench_configs(args):
             log(f"[bench] dense 2^24 {law} (graph replay): {runs[law]['ms_per_step']:.3f} ms/step")
         out["dense_2^24_linear"], out["dense_2^24_simple"] = runs["linear"], runs["simple"]
         out["dense_practical_vs_simple_time_ratio"] = runs["linear"]["ms_per_step"] / runs["simple"]["ms_per_step"]
+    out["slit_hopper_131072"] = bench_hopper(args)
+    return out
+
+
+def bench_hopper(args):
+    """The paper's sample problem (Sec. 5): 2^17 equal spheres falling from a
+    box through a slit onto a floor.  Timed: the first hopper_steps steps
+    from rest with graph replay (the fall, the first impacts on the plates
+    and the first spheres through the slit).  With --hopper-rest the run then
+    goes on until every sphere's step dt |v| is below the workload's threshold
+    (checked every 2,000 steps), and the steps to rest are reported."""
+    import torch
+
+    from paper_1301_1714_amd import dem
+    from paper_1301_1714_amd import workloads as W
+
+    w = W.slit_hopper()
+    st = torch.cuda.Stream()
+    s = dem.System(w["params"], w["x"], w["v"], w["omega"], w["r"], stream=st)
+    try:
+        s.use_graph(True)
+        s.step(20)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(args.hopper_steps)
+        s.sync()
+        el = time.perf_counter() - t0
+        d = s.diagnostics()
+        n = len(w["r"])
+        out = {"value": n * args.hopper_steps / el, "unit": "particle-steps/s",
+               "ms_per_step": 1e3 * el / args.hopper_steps, "n": n, "steps": args.hopper_steps,
+               "Z": (2.0 * float(d[7]) + float(d[8])) / n, "slit": list(w["slit"]), "z_slit": w["z_slit"],
+               "box": list(w["params"]["box_hi"]), "dt": w["params"]["dt"]}
+        if args.hopper_rest:
+            t0 = time.perf_counter()
+            k = s.run_to_rest(w["rest_displacement"], 2000, args.hopper_rest_max)
+            el = time.perf_counter() - t0
+            x = s.read_state()["x"]
+            out["to_rest"] = {"steps": 20 + args.hopper_steps + k, "reached": bool(k < args.hopper_rest_max),
+                              "seconds": el, "particle_steps_per_s": n * k / el,
+                              "fraction_below_slit": float(np.mean(x[:, 2] < w["z_slit"])),
+                              "threshold_m_per_step": w["rest_displacement"]}
+    finally:
+        s.close()
+    log(f"[bench] slit hopper 2^17: {out['value']:.4g} particle-steps/s")
     return out
 
 
@@ -472,7 +517,7 @@ def bench_configs(args):
 def bench_batched(args):
     import torch
 
-    from paper_1301_1714_amd import autotune, dem
+    from paper_1301_1714_amd import autotune, dem, prepare
     from paper_1301_1714_amd import workloads as W
 
     draws = W.batched_draws(seed=args.batch_seed, count=args.batch_systems)
@@ -488,10 +533,15 @@ def bench_batched(args):
     t0 = time.time()
     systems = W.batched_systems(seed=args.batch_seed, count=args.batch_systems, cell_factors=factors, tiles=tiles,
                                 divisors=divisors)
+    # systems drawn denser than their lattice holds are grown to their drawn
+    # packing fraction first (untimed)
+    systems = prepare.grow_systems(systems, verbose=True)
     ns = np.array([len(s["r"]) for s in systems])
     log(f"[bench] batched: {len(systems)} systems, {ns.sum()} spheres, generated in {time.time() - t0:.1f}s, "
         f"tuned in {t_tune:.1f}s")
     b = dem.Batch(systems)
+    d0 = b.diagnostics()
+    z_start = (2.0 * d0[:, 7] + d0[:, 8]) / np.maximum(ns, 1)
     b.use_graph(True)
     b.step(10)
     b.sync()
@@ -533,6 +583,11 @@ def bench_batched(args):
         "detect_tiles": {str(t): int(c) for t, c in zip(til, tcnt)},
         "cell_divisors": {str(int(d)): int(c) for d, c in zip(*np.unique(divisors, return_counts=True))},
         "Z_mean": float(2.0 * diag[:, 7].sum() / ns.sum()),
+        "Z_mean_start": float(np.sum(z_start * ns) / ns.sum()),
+        "per_system": {"n": ns.tolist(), "phi": [round(float(s["phi"]), 4) for s in systems],
+                       "phi_start": [round(float(s["phi_start"]), 4) for s in systems],
+                       "Z_start": [round(float(z), 3) for z in z_start]},
+        "phi_start_minus_phi_max_abs": float(max(abs(s["phi_start"] - s["phi"]) for s in systems)),
         "tune_seconds": t_tune,
     }
 
@@ -542,12 +597,15 @@ def bench_batched(args):
 def bench_serving(args):
     import torch
 
-    from paper_1301_1714_amd import serve
+    from paper_1301_1714_amd import prepare, serve
     from paper_1301_1714_amd import workloads as W
 
     specs = W.serving_requests(seed=args.serve_seed, count=args.serve_requests)
     t0 = time.time()
     systems = [W.unit_box_system(d["seed"], d["n"], d["kn"], d["restitution"], d["mu"], d["phi"]) for d in specs]
+    # a request's initial state is the client's: requests drawn denser than
+    # their lattice holds arrive grown to their packing fraction (untimed)
+    systems = prepare.grow_systems(systems, verbose=True)
     log(f"[bench] serving: {len(specs)} requests, {sum(d['n'] for d in specs)} spheres, "
         f"{sum(d['n'] * d['steps'] for d in specs):.3e} particle-steps, generated in {time.time() - t0:.1f}s")
     ex = serve.GpuExecutor(use_graph=True)
@@ -606,6 +664,10 @@ def main():
                     help="skip the mixed-precision error statement (gas and bed against FP64 and the oracle)")
     ap.add_argument("--gas-steps", type=int, default=10000)
     ap.add_argument("--dense-law-steps", type=int, default=100)
+    ap.add_argument("--hopper-steps", type=int, default=2000)
+    ap.add_argument("--hopper-rest", action="store_true",
+                    help="also run the slit hopper until every sphere is at rest (long)")
+    ap.add_argument("--hopper-rest-max", type=int, default=3000000)
     ap.add_argument("--batch-systems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-seed", type=int, default=4000)
@@ -613,7 +675,8 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache",
                                                          "paper_1301_1714_amd", "autotune.json"))
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests served (the recipe's stream is 512; 200 keep the default run within minutes)")
     ap.add_argument("--serve-seed", type=int, default=5000)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-slots", type=int, default=64)

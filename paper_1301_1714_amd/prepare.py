@@ -102,3 +102,67 @@ def grow_dense_bed(w, stages=60, steps_per_stage=60, settle_steps=0, grow_mu=0.5
         _log(f"[prep] settled: Z {info['Z']:.2f} (pairs {info['pairs']}, walls {info['walls']}), "
              f"max overlap {info['max_overlap']:.2e}, KE {info['kinetic_energy']:.3e} J, {info['seconds']:.1f}s")
     return st["x"], st["v"], st["omega"], info
+
+
+def grow_systems(systems, stages=40, steps_per_stage=50, grow_mu=0.5, verbose=False, max_batch=1 << 23):
+    """``grow_one_batch`` over groups of at most max_batch spheres."""
+    out = [dict(s) for s in systems]
+    group, size = [], 0
+    todo = [k for k, s in enumerate(systems) if s.get("r_target") is not None]
+    t0 = time.time()
+    for k in todo + [None]:
+        n = 0 if k is None else len(systems[k]["r"])
+        if group and (k is None or size + n > max_batch):
+            grown = grow_one_batch([systems[j] for j in group], stages, steps_per_stage, grow_mu)
+            for j, g in zip(group, grown):
+                out[j] = g
+            group, size = [], 0
+        if k is not None:
+            group.append(k)
+            size += n
+    if verbose and todo:
+        _log(f"[prep] grew {len(todo)} systems to their packing fractions in {time.time() - t0:.1f}s")
+    return out
+
+
+def grow_one_batch(systems, stages=40, steps_per_stage=50, grow_mu=0.5, verbose=False):
+    """Bring the systems of the batched and serving workloads that start
+    below their drawn packing fraction (``r_target`` set by
+    ``workloads.unit_box_system``: the lattice cannot hold the drawn radii
+    without overlaps) to their drawn radii: all of them in one batch, radii
+    raised in `stages` equal steps of the scale with strongly damped contacts
+    (restitution 0.1, friction grow_mu), no gravity, `steps_per_stage` steps
+    each.  Untimed preparation through this library; it makes starting states
+    only.  Returns new system dicts (the others unchanged) whose x are the
+    grown positions, r the drawn radii, v, omega the workload's initial ones,
+    and phi_start the packing fraction reached."""
+    grow = [k for k, s in enumerate(systems) if s.get("r_target") is not None]
+    out = [dict(s) for s in systems]
+    if not grow:
+        return out
+    t0 = time.time()
+    sub = []
+    for k in grow:
+        s = systems[k]
+        p = dict(s["params"], restitution=0.1, mu=grow_mu, eta_t_ratio=1.0, gravity=(0.0, 0.0, 0.0),
+                 tile_cells=0, cell_divisor=1)
+        z = np.zeros_like(s["x"])
+        sub.append(dict(params=p, x=s["x"], v=z, omega=z, r=s["r"]))
+    b = dem.Batch(sub)
+    r0 = [np.asarray(systems[k]["r"], dtype=np.float64) for k in grow]
+    r1 = [np.asarray(systems[k]["r_target"], dtype=np.float64) for k in grow]
+    for stage in range(1, stages + 1):
+        f = stage / stages
+        b.set_radii([a + (c - a) * f for a, c in zip(r0, r1)])
+        b.step(steps_per_stage)
+    for j, k in enumerate(grow):
+        st = b.read_state(j)
+        s = out[k]
+        s["x"] = st["x"]
+        s["r"] = systems[k]["r_target"]
+        s["r_target"] = None
+        s["phi_start"] = float(np.sum(4.0 / 3.0 * np.pi * np.asarray(s["r"], dtype=np.float64) ** 3))
+    b.close()
+    if verbose:
+        _log(f"[prep] grew {len(grow)} systems to their packing fractions in {time.time() - t0:.1f}s")
+    return out
