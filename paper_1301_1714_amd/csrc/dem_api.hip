@@ -277,6 +277,8 @@ dem_status plan(Engine &e, int32_t S, const dem_params *p, const int64_t *n) {
   }
   e.n = (int32_t)ntot;
   e.ncell = ctot;
+  // contact indices (backward entries, history starts) are int32
+  if ((int64_t)e.bsys_h.size() * kBlock * e.K >= (int64_t)INT32_MAX) return DEM_E_INVALID;
   e.rsz = e.prec == DEM_PREC_FP64 ? sizeof(double) : sizeof(float);
   e.left_h.assign(S, 0);
   return DEM_OK;
@@ -287,9 +289,10 @@ size_t carve(Engine &e, char *base) {
   Carver cv{base};
   const size_t N = (size_t)(e.n > 0 ? e.n : 1);
   const size_t R = e.rsz;
-  const size_t P = (size_t)e.K * N;  // owned-contact entries [K][N]
+  const size_t P = (size_t)e.K * N;  // owned-contact lists [K][N]
   const size_t S = (size_t)e.S;
   const size_t B = std::max<size_t>(e.bsys_h.size(), 1);
+  const size_t PB = B * (size_t)kBlock * (size_t)e.K;  // per-contact arrays: kBlock * K entries per block
   e.tab = cv.take<SysInfo>(S);
   e.mat = cv.take<PairK>(std::max<size_t>((size_t)e.nmat, 1));
   e.psys = cv.take<int32_t>(N);
@@ -335,12 +338,13 @@ size_t carve(Engine &e, char *base) {
   e.nbr.K = e.K;
   for (int b = 0; b < 2; b++) {
     e.hist[b].cnt = cv.take<int32_t>(N);
-    e.hist[b].ent = cv.take_bytes(4 * R * P);
+    e.hist[b].start = cv.take<int32_t>(N);
+    e.hist[b].ent = cv.take_bytes(4 * R * PB);
   }
-  e.work.pf = cv.take_bytes(6 * R * P);
-  e.work.pc = e.has_terms ? cv.take_bytes(4 * R * P) : nullptr;
-  e.work.pe = cv.take<double>(P);
-  e.work.pd = cv.take<double>(P);
+  e.work.pf = cv.take_bytes(6 * R * PB);
+  e.work.pc = e.has_terms ? cv.take_bytes(4 * R * PB) : nullptr;
+  e.work.pe = cv.take<double>(PB);
+  e.work.pd = cv.take<double>(PB);
   e.work.bcnt = cv.take<int32_t>(N);
   e.work.bwd = cv.take<int32_t>((size_t)kBwdCap * N);
   e.diag.e_el = cv.take<double>(N);
@@ -495,31 +499,47 @@ struct Entry {
   double d[3];
 };
 
-// Rows [0, kmax) of a [K][N] history table: delta_t (3 per entry, as
-// doubles) and the keys (the bits of each entry's w)
-dem_status read_hist_rows(Engine &e, const void *src, int32_t kmax, std::vector<double> &d,
-                          std::vector<int32_t> &key) {
-  const size_t N = (size_t)e.n, m = (size_t)kmax * N;
+// last slot + 1 of kernel block b
+int32_t block_end(const Engine &e, size_t b) {
+  const SysInfo &si = e.info[(size_t)e.bsys_h[b]];
+  return std::min(e.bfirst_h[b] + kBlock, si.p0 + si.n);
+}
+
+// The history entries of generation g: counts and first entries per slot,
+// and each block's entries (at most wmax of them, the most any block holds)
+// as rows of wmax: delta_t (3 per entry, as doubles) and the keys (the bits
+// of each entry's w).  Entry j of slot s of block b is at row b, column
+// start[s] - cbase(b) + j.
+dem_status read_hist_blocks(Engine &e, const HistGen &g, std::vector<int32_t> &cnt, std::vector<int32_t> &start,
+                            size_t &wmax, std::vector<double> &d, std::vector<int32_t> &key) {
+  const size_t N = (size_t)e.n, nb = e.bsys_h.size();
+  dem_status st;
+  if ((st = d2h(e, g.cnt, cnt, N)) != DEM_OK || (st = d2h(e, g.start, start, N)) != DEM_OK) return st;
+  wmax = 0;
+  for (size_t b = 0; b < nb; b++) {
+    size_t tot = 0;
+    for (int32_t sl = e.bfirst_h[b]; sl < block_end(e, b); sl++) tot += (size_t)std::min(std::max(cnt[sl], 0), e.K);
+    wmax = std::max(wmax, tot);
+  }
+  const size_t m = wmax * nb;
   d.assign(3 * m, 0.0);
   key.assign(m, 0);
   if (m == 0) return DEM_OK;
-  if (e.prec == DEM_PREC_FP64) {
-    std::vector<double> raw(4 * m);
-    HIP_TRY(hipMemcpyAsync(raw.data(), src, 32 * m, hipMemcpyDeviceToHost, e.stream));
-    HIP_TRY(hipStreamSynchronize(e.stream));
-    for (size_t q = 0; q < m; q++) {
+  const size_t esz = 4 * e.rsz, spitch = (size_t)kBlock * e.K * esz;
+  std::vector<char> raw(m * esz);
+  HIP_TRY(hipMemcpy2DAsync(raw.data(), wmax * esz, g.ent, spitch, wmax * esz, nb, hipMemcpyDeviceToHost, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  for (size_t q = 0; q < m; q++) {
+    if (e.prec == DEM_PREC_FP64) {
+      const double *r = (const double *)raw.data() + 4 * q;
       int64_t bits;
-      memcpy(&bits, &raw[4 * q + 3], 8);
+      memcpy(&bits, &r[3], 8);
       key[q] = (int32_t)bits;
-      for (int c = 0; c < 3; c++) d[3 * q + c] = raw[4 * q + c];
-    }
-  } else {
-    std::vector<float> raw(4 * m);
-    HIP_TRY(hipMemcpyAsync(raw.data(), src, 16 * m, hipMemcpyDeviceToHost, e.stream));
-    HIP_TRY(hipStreamSynchronize(e.stream));
-    for (size_t q = 0; q < m; q++) {
-      memcpy(&key[q], &raw[4 * q + 3], 4);
-      for (int c = 0; c < 3; c++) d[3 * q + c] = (double)raw[4 * q + c];
+      for (int c = 0; c < 3; c++) d[3 * q + c] = r[c];
+    } else {
+      const float *r = (const float *)raw.data() + 4 * q;
+      memcpy(&key[q], &r[3], 4);
+      for (int c = 0; c < 3; c++) d[3 * q + c] = (double)r[c];
     }
   }
   return DEM_OK;
@@ -534,34 +554,39 @@ dem_status read_gen(Engine &e, int32_t k, bool committed, std::vector<Entry> &ou
   const SysInfo &si = e.info[k];
   if (si.n == 0) return DEM_OK;
   const size_t N = (size_t)e.n;
-  std::vector<int32_t> cnt, id, nb;
-  dem_status st;
-  if ((st = d2h(e, committed ? e.hist[e.gc].cnt : e.nbr.fcnt, cnt, N)) != DEM_OK) return st;
-  int32_t kmax = 0;
-  for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++)
-    kmax = std::max(kmax, std::min(std::max(cnt[slot], 0), e.K));
+  std::vector<int32_t> cnt, start, id, nb;
   std::vector<double> rows;
   std::vector<int32_t> keys;
+  size_t wmax = 0;
+  dem_status st;
   if (committed) {
-    if ((st = read_hist_rows(e, e.hist[e.gc].ent, kmax, rows, keys)) != DEM_OK) return st;
-  } else if ((st = d2h(e, (const int32_t *)e.nbr.nb, nb, (size_t)kmax * N)) != DEM_OK) {
-    return st;
+    if ((st = read_hist_blocks(e, e.hist[e.gc], cnt, start, wmax, rows, keys)) != DEM_OK) return st;
+  } else {
+    if ((st = d2h(e, e.nbr.fcnt, cnt, N)) != DEM_OK) return st;
+    int32_t kmax = 0;
+    for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++)
+      kmax = std::max(kmax, std::min(std::max(cnt[slot], 0), e.K));
+    if ((st = d2h(e, (const int32_t *)e.nbr.nb, nb, (size_t)kmax * N)) != DEM_OK) return st;
   }
   if ((st = d2h(e, (const int32_t *)e.pos[e.cp].id, id, N)) != DEM_OK) return st;
-  for (size_t slot = (size_t)si.p0; slot < (size_t)(si.p0 + si.n); slot++) {
-    const int32_t c = std::min(std::max(cnt[slot], 0), e.K);
-    for (int32_t j = 0; j < c; j++) {
-      const size_t q = (size_t)j * N + slot;
-      Entry en;
-      const int64_t me = id[slot] - si.p0;
-      const int32_t other = committed ? keys[q] : nb[q];
-      const bool pair = other >= 0;
-      const int64_t them = pair ? id[other] - si.p0 : other;
-      en.a = pair ? std::min(me, them) : me;
-      en.b = pair ? std::max(me, them) : them;
-      const double sg = (pair && me > them) ? -1.0 : 1.0;  // stored as seen from the owner slot
-      for (int c3 = 0; c3 < 3; c3++) en.d[c3] = committed ? sg * rows[3 * q + c3] : 0.0;
-      out.push_back(en);
+  for (size_t b = 0; b < e.bsys_h.size(); b++) {
+    if (e.bsys_h[b] != k) continue;
+    for (int32_t slot = e.bfirst_h[b]; slot < block_end(e, b); slot++) {
+      const int32_t c = std::min(std::max(cnt[slot], 0), e.K);
+      for (int32_t j = 0; j < c; j++) {
+        const size_t q = committed ? b * wmax + (size_t)(start[slot] - cbase((int32_t)b, e.K)) + j
+                                   : (size_t)j * N + (size_t)slot;
+        Entry en;
+        const int64_t me = id[slot] - si.p0;
+        const int32_t other = committed ? keys[q] : nb[q];
+        const bool pair = other >= 0;
+        const int64_t them = pair ? id[other] - si.p0 : other;
+        en.a = pair ? std::min(me, them) : me;
+        en.b = pair ? std::max(me, them) : them;
+        const double sg = (pair && me > them) ? -1.0 : 1.0;  // stored as seen from the owner slot
+        for (int c3 = 0; c3 < 3; c3++) en.d[c3] = committed ? sg * rows[3 * q + c3] : 0.0;
+        out.push_back(en);
+      }
     }
   }
   std::sort(out.begin(), out.end(),
@@ -676,36 +701,50 @@ dem_status upload_history(Engine &e, const HistIn &hist, const std::vector<int32
   }
   std::vector<int32_t> cnt(N, 0);
   for (const Rec &rc : recs) cnt[rc.owner]++;
-  int32_t kmax = 0;
-  for (size_t sl = 0; sl < N; sl++) {
-    const int32_t k = e.psys_h[sl];
-    if (cnt[sl] > e.info[k].kcap) return DEM_E_CONTACT_OVERFLOW;
-    kmax = std::max(kmax, cnt[sl]);
+  for (size_t sl = 0; sl < N; sl++)
+    if (cnt[sl] > e.info[e.psys_h[sl]].kcap) return DEM_E_CONTACT_OVERFLOW;
+  // block layout: the entries of slot s of block b from cbase(b) + the
+  // owned counts of the block's slots before s
+  const size_t nb = e.bsys_h.size();
+  std::vector<int32_t> start(N, 0);
+  size_t wmax = 0;
+  for (size_t b = 0; b < nb; b++) {
+    int32_t run = 0;
+    for (int32_t sl = e.bfirst_h[b]; sl < block_end(e, b); sl++) {
+      start[sl] = (int32_t)cbase((int32_t)b, e.K) + run;
+      run += cnt[sl];
+    }
+    wmax = std::max(wmax, (size_t)run);
   }
   const HistGen &g0 = e.hist[0];
   dem_status st;
-  if ((st = h2d(e, g0.cnt, cnt)) != DEM_OK) return st;
+  if ((st = h2d(e, g0.cnt, cnt)) != DEM_OK || (st = h2d(e, g0.start, start)) != DEM_OK) return st;
   if (recs.empty()) return DEM_OK;
-  // entries: delta_t in x, y, z, the key's bits in w; rows 0 .. kmax - 1
-  const size_t m = (size_t)kmax * N;
+  // entries: delta_t in x, y, z, the key's bits in w; one row of wmax per block
+  std::vector<int32_t> blk(N, 0);
+  for (size_t b = 0; b < nb; b++)
+    for (int32_t sl = e.bfirst_h[b]; sl < block_end(e, b); sl++) blk[sl] = (int32_t)b;
+  const size_t esz = 4 * e.rsz, m = wmax * nb;
+  std::vector<char> raw(m * esz, 0);
   std::vector<int32_t> pos(N, 0);
-  if (e.prec == DEM_PREC_FP64) {
-    std::vector<double> raw(4 * m, 0.0);
-    for (const Rec &rc : recs) {
-      const size_t q = (size_t)pos[rc.owner]++ * N + (size_t)rc.owner;
-      for (int c = 0; c < 3; c++) raw[4 * q + c] = rc.d[c];
-      const int64_t bits = (int64_t)rc.key;
-      memcpy(&raw[4 * q + 3], &bits, 8);
-    }
-    return h2d(e, (double *)g0.ent, raw);
-  }
-  std::vector<float> raw(4 * m, 0.0f);
   for (const Rec &rc : recs) {
-    const size_t q = (size_t)pos[rc.owner]++ * N + (size_t)rc.owner;
-    for (int c = 0; c < 3; c++) raw[4 * q + c] = (float)rc.d[c];
-    memcpy(&raw[4 * q + 3], &rc.key, 4);
+    const int32_t b = blk[rc.owner];
+    const size_t q = (size_t)b * wmax + (size_t)(start[rc.owner] - cbase(b, e.K)) + (size_t)pos[rc.owner]++;
+    if (e.prec == DEM_PREC_FP64) {
+      double *r = (double *)raw.data() + 4 * q;
+      for (int c = 0; c < 3; c++) r[c] = rc.d[c];
+      const int64_t bits = (int64_t)rc.key;
+      memcpy(&r[3], &bits, 8);
+    } else {
+      float *r = (float *)raw.data() + 4 * q;
+      for (int c = 0; c < 3; c++) r[c] = (float)rc.d[c];
+      memcpy(&r[3], &rc.key, 4);
+    }
   }
-  return h2d(e, (float *)g0.ent, raw);
+  HIP_TRY(hipMemcpy2DAsync(g0.ent, (size_t)kBlock * e.K * esz, raw.data(), wmax * esz, wmax * esz, nb,
+                           hipMemcpyHostToDevice, e.stream));
+  HIP_TRY(hipStreamSynchronize(e.stream));
+  return DEM_OK;
 }
 
 dem_status engine_init(Engine &e, const double *x, const double *v, const double *omega,
@@ -826,7 +865,7 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   // Step 4
   // (the state goes into the packed records only; the gather writes it back)
   if ((r = launch_reorder(e.prec, L, e.pos[e.cp], e.vel[e.cv], e.pos[e.cp ^ 1], e.vel[e.cv ^ 1], false, e.perm,
-                          e.cell, e.scell, e.nbr, e.hist[e.gc].cnt, e.stream)) != hipSuccess)
+                          e.cell, e.scell, e.nbr, &e.hist[e.gc], e.stream)) != hipSuccess)
     return r;
   e.cp ^= 1;
   e.cv ^= 1;

@@ -24,15 +24,21 @@
 //            previous slot and committed history count of each slot
 //   tiles    detection work items: (system, row, first cell, last cell) of
 //            the LDS-tiled shape; runs: the same for the wave shape
-//   hist[2]  two generations of the tangential-history table, laid out like
-//            the owned contacts: per slot its count and, at [k * N + s], one
-//            Real4 entry per owned contact: delta_t as seen from the owner in
-//            x, y, z and the key (partner slot or -1 - w, its bits) in w, so
-//            that one load brings both.  One generation holds the committed
-//            history, the other is written for the new positions.
-//   work     per owned contact [k * N + s]: force on the owner and n x F_t
-//            (6 Real), and the backward lists (contacts of each particle as
-//            the partner, each as owner slot << 6 | k)
+//   hist[2]  two generations of the tangential-history table: per slot its
+//            count and the index of its first entry, and one Real4 entry per
+//            owned contact: delta_t as seen from the owner in x, y, z and the
+//            key (partner slot or -1 - w, its bits) in w, so that one load
+//            brings both.  One generation holds the committed history, the
+//            other is written for the new positions.
+//   work     per owned contact: force on the owner and n x F_t (6 Real), and
+//            the backward lists (contacts of each particle as the partner,
+//            each as the index of its contact record)
+// Per-contact arrays (history entries, force records) keep the contacts of
+// one kernel block together: block b owns kBlock * K entries from
+// cbase(b, K), and contact k of slot s sits at cbase(b, K) + off(s) + k,
+// off(s) the exclusive prefix of the owned counts over the block's slots in
+// order.  A wave's contacts are then one contiguous run (its stores coalesce)
+// and a particle's history entries are adjacent (one line per lookup).
 // Real is double (DEM_PREC_FP64) or float (DEM_PREC_MIXED).
 #pragma once
 
@@ -62,9 +68,8 @@ constexpr int32_t kListCap = 64;  // largest per-particle capacity of owned cont
 // contact indices k * N + s are int32: n * kListCap must stay below 2^31
 constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
 constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
-constexpr int kOwnerShift = 6;    // a backward entry is owner slot << kOwnerShift | k
-static_assert(kListCap <= (1 << kOwnerShift), "k must fit below the owner slot");
-static_assert(kMaxParticles <= (INT32_MAX >> kOwnerShift) + 1, "owner slot << kOwnerShift must fit in int32");
+// first entry of kernel block b's contacts (see the layout above)
+__host__ __device__ inline int64_t cbase(int32_t b, int32_t K) { return (int64_t)b * kBlock * K; }
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
 constexpr int32_t kRunCells = 8;  // cells along x per wave of the wave-per-cell-run detection
 constexpr int32_t kMaxReach = 2;  // largest cell divisor
@@ -145,9 +150,13 @@ struct VelBuf {
 // The state the contact law reads, packed per particle so that a partner
 // costs one or two cache lines instead of one per array.  In a time step it
 // also carries where the particle's committed tangential history is: its
-// previous slot (low kPrevBits bits of hp) and the number of contacts it
-// owned there (high bits); the entries are at [k * N + previous slot].
+// previous slot (low kPrevBits bits of hp), the number of contacts it owned
+// there (high bits) and the index of the first of their entries (hq).  The
+// particle's material rides in the bits of the id above kMtShift.
 constexpr int kPrevBits = 25;
+constexpr int kMtShift = 25;
+constexpr int32_t kIdMask = (1 << kMtShift) - 1;
+static_assert(kMaxParticles <= (1 << kMtShift), "ids must fit below the material bits");
 static_assert(kMaxParticles <= (1 << kPrevBits), "previous slot must fit in kPrevBits bits");
 static_assert(kListCap < (1 << (32 - kPrevBits)), "history count must fit above the previous slot");
 template <typename Real>
@@ -157,7 +166,7 @@ struct alignas(16) PState {
   float r;
   int32_t id;
   uint32_t hp;  // previous slot | owned history count << kPrevBits
-  int32_t mt;   // material (0 without a material table)
+  int32_t hq;   // index of the first committed history entry of the previous slot
 };
 
 struct NbrBuf {
@@ -171,17 +180,18 @@ struct NbrBuf {
 
 // one generation of the tangential-history table
 struct HistGen {
-  int32_t *cnt;  // [N] entries of each slot
-  void *ent;     // [K][N] Real4: delta_t (x, y, z), key bits (w)
+  int32_t *cnt;    // [N] entries of each slot
+  int32_t *start;  // [N] index of each slot's first entry
+  void *ent;       // [blocks * kBlock * K] Real4: delta_t (x, y, z), key bits (w)
 };
 
 struct PairWork {
-  void *pf;        // [K][N] 3 x Real2: force on the owner, then n x F_t
-  void *pc;        // [K][N] Real4: the couple of the optional terms on the owner (engines with terms only)
-  double *pe;      // [K][N] elastic energy (diagnostics)
-  double *pd;      // [K][N] overlap (diagnostics)
+  void *pf;        // per contact 3 x Real2: force on the owner, then n x F_t
+  void *pc;        // per contact Real4: the couple of the optional terms on the owner (engines with terms only)
+  double *pe;      // per contact elastic energy (diagnostics)
+  double *pd;      // per contact overlap (diagnostics)
   int32_t *bcnt;   // [N] contacts of each particle as the partner (zero between evaluations)
-  int32_t *bwd;    // [kBwdCap][N] their owner slot << kOwnerShift | k, in arrival order
+  int32_t *bwd;    // [kBwdCap][N] the indices of their contact records, in arrival order
 };
 
 struct DiagBuf {
@@ -244,12 +254,12 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
 hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
                        int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
 // Step 4 into the packed records nb.pst (and, with soa, into dst / vdst as
-// well; a time step leaves that to its gather); old_cnt: counts of the
-// committed history, recorded in the records with the previous slots
-// (nullptr: none)
+// well; a time step leaves that to its gather); old: the committed history,
+// whose count and first entry per previous slot are recorded in the records
+// with the previous slots (nullptr: none)
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          const NbrBuf &nb, const int32_t *old_cnt, hipStream_t st);
+                          const NbrBuf &nb, const HistGen *old, hipStream_t st);
 hipError_t launch_xyzr(const Layout &L, const PosBuf &p, const NbrBuf &nb, hipStream_t st);
 // nb.pst from the current buffers (before a force evaluation outside a step)
 hipError_t launch_pack(int precision, const Layout &L, const PosBuf &p, const VelBuf &v, const NbrBuf &nb,

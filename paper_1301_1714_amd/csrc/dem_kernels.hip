@@ -429,19 +429,25 @@ __device__ __forceinline__ float4 make_xyzr(const Grid &g, double x, double y, d
 }
 
 // The direct sweep's candidate record, 8 bytes instead of the 16 of the FP32
-// copy (the sweep is bound by the bytes its candidate loads move through the
-// address unit).  Each coordinate is the cell-space position u = (x - lo) sc,
-// rounded to 1/8192 cell and kept modulo 8 cells in 16 bits; the radius is
-// r / rmax in units of 1/65535, rounded up.  The difference of two such
-// coordinates, read as a signed 16-bit number, is the rounded difference
-// reduced to [-4, 4) cells: never larger in magnitude than the true one, and
-// off by at most 1/8192 cell where the true one lies inside that range.  A
-// prefilter on these records with its cut-off widened by the rounding bound
-// therefore passes every pair the FP32 prefilter passes.
+// copy (the sweep is bound by the loads of its candidates).  Every length is
+// in one unit h = (widest cell side) / 8192 of the system's grid: each
+// coordinate (x - lo) / h rounded to an integer and kept modulo 2^16 (8
+// cells of the widest side), the radius r / h rounded up.  The difference of
+// two coordinates read as a signed 16-bit number is then the rounded
+// difference reduced to [-4, 4) widest cells: exact to one unit where the
+// true difference lies in that range, and never larger in magnitude than the
+// true one outside it.  A pair in contact is at most one cell_size apart,
+// which is at most 2 widest cells (cell divisor <= 2), so its differences
+// are exact to one unit on each axis, and an integer test of the squared
+// distance against (r_i + r_j + margin)^2 in units of h passes every true
+// contact (the wrapped differences of far pairs only make it pass more).
 constexpr double kFixCell = 8192.0;
-constexpr double kFixRad = 65535.0;
-__device__ __forceinline__ uint32_t fix_cell(double u) {
-  double f = floor(u * kFixCell + 0.5);
+// h^-1 of the system's grid
+__device__ __forceinline__ double fix_scale(const Grid &g) {
+  return kFixCell * fmin(fmin(g.sc[0], g.sc[1]), g.sc[2]);
+}
+__device__ __forceinline__ uint32_t fix_coord(double u) {
+  double f = floor(u + 0.5);
   // a position far outside the grid or not a number (a step that has failed
   // with the domain error) gets a defined record instead of an out-of-range
   // conversion
@@ -450,10 +456,11 @@ __device__ __forceinline__ uint32_t fix_cell(double u) {
 }
 __device__ __forceinline__ uint2 make_xq(const SysInfo &si, double x, double y, double z, float r) {
   const Grid &g = si.g;
-  const uint32_t qx = fix_cell((x - g.lo[0]) * g.sc[0]), qy = fix_cell((y - g.lo[1]) * g.sc[1]),
-                 qz = fix_cell((z - g.lo[2]) * g.sc[2]);
-  const double rr = si.rmax > 0.0f ? ceil((double)r / (double)si.rmax * kFixRad) : 0.0;
-  const uint32_t qr = rr <= 0.0 ? 0u : (rr >= kFixRad ? 0xffffu : (uint32_t)rr);
+  const double sc = fix_scale(g);
+  const uint32_t qx = fix_coord((x - g.lo[0]) * sc), qy = fix_coord((y - g.lo[1]) * sc),
+                 qz = fix_coord((z - g.lo[2]) * sc);
+  const double rr = ceil((double)r * sc);
+  const uint32_t qr = rr <= 0.0 ? 0u : (rr >= 16383.0 ? 16383u : (uint32_t)rr);
   return make_uint2(qx | (qy << 16), qz | (qr << 16));
 }
 
@@ -461,10 +468,12 @@ template <typename Real>
 __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf vsrc, PosBuf dst, VelBuf vdst,
                                                     int32_t soa, const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
-                                                    NbrBuf nb, const int32_t *__restrict__ old_cnt) {
+                                                    NbrBuf nb, const int32_t *__restrict__ old_cnt,
+                                                    const int32_t *__restrict__ old_start) {
   int32_t k;
   const int32_t s = block_slot(L, k);
   if (s < 0) return;
+  const SysInfo &si = L.tab[k];
   const int32_t p = perm[s];
   PState<Real> ps;
   ps.x = src.x[p];
@@ -476,18 +485,18 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
     ps.w[q] = ((const Real *)vsrc.w[q])[p];
   }
   ps.r = src.r[p];
-  ps.id = src.id[p];
+  ps.id = src.id[p] | ((src.mt ? src.mt[p] : 0) << kMtShift);
   ps.hp = 0;
-  ps.mt = src.mt ? src.mt[p] : 0;
+  ps.hq = 0;
   if (old_cnt) {
-    const int32_t c = min(max(old_cnt[p], 0), nb.K);  // the table holds K rows
+    const int32_t c = min(max(old_cnt[p], 0), nb.K);  // a slot owns at most K entries
     ps.hp = (uint32_t)p | ((uint32_t)c << kPrevBits);
+    ps.hq = old_start[p];
   }
   // the candidate records are formed ahead of every store, so that the
   // system's grid is read with scalar loads (a store may alias it as far as
   // the compiler knows); the FP32 copies are candidates only of the tiled and
   // wave detection shapes
-  const SysInfo &si = L.tab[k];
   const uint2 xq = make_xq(si, ps.x, ps.y, ps.z, ps.r);
   const float4 xyzr = make_xyzr(si.g, ps.x, ps.y, ps.z, ps.r);
   const int32_t cp = cell[p];
@@ -500,8 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
     dst.y[s] = ps.y;
     dst.z[s] = ps.z;
     dst.r[s] = ps.r;
-    dst.id[s] = ps.id;
-    if (dst.mt) dst.mt[s] = ps.mt;
+    dst.id[s] = ps.id & kIdMask;
+    if (dst.mt) dst.mt[s] = ps.id >> kMtShift;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)vdst.v[q])[s] = ps.v[q];
@@ -525,9 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(Layout L, PosBuf pos, VelBuf ve
     ps.w[q] = ((const Real *)vel.w[q])[s];
   }
   ps.r = pos.r[s];
-  ps.id = pos.id[s];
+  ps.id = pos.id[s] | ((pos.mt ? pos.mt[s] : 0) << kMtShift);
   ps.hp = 0;
-  ps.mt = pos.mt ? pos.mt[s] : 0;
+  ps.hq = 0;
   ((PState<Real> *)nb.pst)[s] = ps;
 }
 
@@ -627,23 +636,26 @@ struct NearF32 {
   }
 };
 
-// The same test on the fixed-point records (make_xq): differences of the
-// rounded cell-space coordinates in cell widths / 8192, the partner's radius
-// rounded up, and the cut-off widened by h, the bound on the distance error
-// of the rounding (one unit per axis).  A pair in contact is at most reach
-// (<= 2) cells apart on each axis, inside the [-4, 4) cells the 16-bit
-// differences resolve; beyond that range the wrapped difference is smaller
-// than the true one, so the test can only pass more pairs, never fewer.
-struct NearFix {
-  uint32_t qxy, qz;       // own record
-  float hx, hy, hz, rs;   // cell widths / 8192, rmax / 65535
-  float pe;               // own radius + eps + h
+// The same test on the fixed-point records (make_xq), in integers: the
+// coordinate differences dx, dy, dz and the sum of the radii c = r_j + R in
+// units of h, where R is the own radius plus kFixMargin units (the rounding
+// of the two records' coordinates moves the distance by at most sqrt(3)
+// units, and the radii are rounded up), and the test dx^2 + dy^2 + dz^2 <
+// c^2.  The differences of x and y come from one packed 16-bit subtraction,
+// their squares from one dot product; z and c from a second subtraction
+// against (z, -R).  No product overflows for a pair within reach (|d| <=
+// 16385 units, c <= 16386); for others an overflow can only pass the pair.
+constexpr int kFixMargin = 3;
+typedef short short2_t __attribute__((ext_vector_type(2)));
+struct NearInt {
+  uint32_t qxy;  // own x | y << 16
+  uint32_t qzr;  // own z | (-R) << 16
   __device__ __forceinline__ bool operator()(const uint2 &q) const {
-    const float dx = (float)(int16_t)(q.x - qxy) * hx;
-    const float dy = (float)(int16_t)((q.x >> 16) - (qxy >> 16)) * hy;
-    const float dz = (float)(int16_t)(q.y - qz) * hz;
-    const float sf = pe + (float)(q.y >> 16) * rs;
-    return dx * dx + dy * dy + dz * dz < sf * sf;
+    const short2_t dxy = __builtin_bit_cast(short2_t, q.x) - __builtin_bit_cast(short2_t, qxy);
+    const short2_t dzc = __builtin_bit_cast(short2_t, q.y) - __builtin_bit_cast(short2_t, qzr);
+    const int32_t dz = dzc.x, c = dzc.y;
+    const int32_t d2 = __builtin_amdgcn_sdot2(dxy, dxy, dz * dz, false);
+    return d2 < c * c;
   }
 };
 
@@ -768,17 +780,13 @@ struct DirectRows {
   const uint2 *src;                  // [N + 1]: the last record pads the pair loads
   const int32_t *cell_start;
   int32_t c0, nx, ny, nz, cy, cz;
-  __device__ __forceinline__ NearFix filter(const NbrBuf &nb, int32_t s, const SysInfo &si, const float4 &,
-                                            float pe) const {
+  __device__ __forceinline__ NearInt filter(const NbrBuf &nb, int32_t s, const SysInfo &si, const float4 &,
+                                            float) const {
     const uint2 me = src[s];
-    NearFix f;
+    NearInt f;
     f.qxy = me.x;
-    f.qz = me.y;
-    f.hx = (float)(1.0 / (si.g.sc[0] * kFixCell));
-    f.hy = (float)(1.0 / (si.g.sc[1] * kFixCell));
-    f.hz = (float)(1.0 / (si.g.sc[2] * kFixCell));
-    f.rs = (float)((double)si.rmax / kFixRad);
-    f.pe = pe + sqrtf(f.hx * f.hx + f.hy * f.hy + f.hz * f.hz);
+    const uint32_t R = (me.y >> 16) + (uint32_t)kFixMargin;
+    f.qzr = (me.y & 0xffffu) | (((0u - R) & 0xffffu) << 16);
     return f;
   }
   // records t .. t + kUnroll - 1 of a range ending at e (past e: copies of
@@ -1374,15 +1382,14 @@ __device__ __forceinline__ double elastic_energy(const Consts &c, const PairK &K
 }
 
 // committed tangential displacement of the contact with history key `key`
-// among the c entries of previous slot p in the committed table (zero for a
-// new contact)
+// among the c entries from index q0 of the committed table (zero for a new
+// contact)
 template <typename Real>
-__device__ __forceinline__ void hist_find(const HistGen &old, int32_t N, int32_t p, int32_t c, int32_t key,
-                                          Real h[3]) {
+__device__ __forceinline__ void hist_find(const HistGen &old, int32_t q0, int32_t c, int32_t key, Real h[3]) {
   using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
   for (int32_t k = 0; k < c; k++) {
-    const V4 d = ((const V4 *)old.ent)[(int64_t)k * N + p];
+    const V4 d = ((const V4 *)old.ent)[(int64_t)q0 + k];
     if (entry_key(d.w) == key) {
       h[0] = d.x;
       h[1] = d.y;
@@ -1392,44 +1399,49 @@ __device__ __forceinline__ void hist_find(const HistGen &old, int32_t N, int32_t
   }
 }
 
+// where a slot's committed history is: its previous slot, the number of its
+// entries and the index of the first
+struct HistAt {
+  int32_t prev, cnt, q0;
+};
+
 // Committed delta_t of a contact, seen from its current owner (lower slot).
-// ho, hp: previous slot and committed entry count of the owner and of the
-// partner.  The previous step filed the contact under the lower of the two
-// previous slots, seen from there.
+// ho, hp: where the committed history of the owner and of the partner is.
+// The previous step filed the contact under the lower of the two previous
+// slots, seen from there, keyed by the other one.
 template <typename Real>
-__device__ __forceinline__ void pair_history(const HistGen &old, int32_t N, const int2 &ho, const int2 &hp,
-                                             Real h[3]) {
-  const bool kept = ho.x < hp.x;  // the owner was the lower slot then too
+__device__ __forceinline__ void pair_history(const HistGen &old, const HistAt &ho, const HistAt &hp, Real h[3]) {
+  const bool kept = ho.prev < hp.prev;  // the owner was the lower slot then too
   if (kept) {
-    hist_find<Real>(old, N, ho.x, ho.y, hp.x, h);
+    hist_find<Real>(old, ho.q0, ho.cnt, hp.prev, h);
   } else {
-    hist_find<Real>(old, N, hp.x, hp.y, ho.x, h);
+    hist_find<Real>(old, hp.q0, hp.cnt, ho.prev, h);
     h[0] = -h[0];
     h[1] = -h[1];
     h[2] = -h[2];
   }
 }
 
-// previous slot and committed entry count of slot s, whose packed record is
-// ps: recorded there in a time step, the slot's own otherwise
+// where the committed history of slot s (packed record ps) is: recorded in
+// the record in a time step, the slot's own otherwise
 template <typename Real>
-__device__ __forceinline__ int2 hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
-  if (old_perm) return make_int2((int32_t)(ps.hp & ((1u << kPrevBits) - 1)), (int32_t)(ps.hp >> kPrevBits));
-  return make_int2(s, min(max(a.old.cnt[s], 0), a.nb.K));
+__device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
+  if (old_perm) return HistAt{(int32_t)(ps.hp & ((1u << kPrevBits) - 1)), (int32_t)(ps.hp >> kPrevBits), ps.hq};
+  return HistAt{s, min(max(a.old.cnt[s], 0), a.nb.K), a.old.start[s]};
 }
 
-// Owned contact k of slot s (partner t, a slot or -1 - w): the law of
-// Eqs. 2-10 (or Eq. 1) evaluated once per pair, seen from the owner (the
-// lower slot), stored at [k * N + s] as the force on the owner and n x F_t;
+// Owned contact k of slot s (partner t, a slot or -1 - w), stored at index
+// q of the per-contact arrays: the law of Eqs. 2-10 (or Eq. 1) evaluated
+// once per pair, seen from the owner (the lower slot), stored as the force
+// on the owner and n x F_t;
 // the partner receives the exact negation through its backward list, where
 // the contact is filed here.  Both particles' inputs come from their packed
 // state records.
 template <typename Real, int LAW>
-__device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t k) {
+__device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
   const int32_t N = a.L.n;
-  const int64_t q = (int64_t)k * N + s;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
@@ -1439,16 +1451,17 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
   if (LAW != DEM_LAW_SIMPLE) {
-    const int2 hs = hist_index(a, old_perm, s, me);
+    const HistAt hs = hist_index(a, old_perm, s, me);
     if (t >= 0)
-      pair_history<Real>(a.old, N, hs, hist_index(a, old_perm, t, pt), h);
+      pair_history<Real>(a.old, hs, hist_index(a, old_perm, t, pt), h);
     else
-      hist_find<Real>(a.old, N, hs.x, hs.y, t, h);
+      hist_find<Real>(a.old, hs.q0, hs.cnt, t, h);
   }
   // the constants of the pair's materials (a wall is of the system's wall
   // material), or the system's one material
   PairK K{c.kn, c.kt, c.alpha, c.mu};
-  if (si.ntypes > 0) K = a.L.mat[si.mat0 + me.mt * si.ntypes + (t >= 0 ? pt.mt : si.wall_type)];
+  if (si.ntypes > 0)
+    K = a.L.mat[si.mat0 + (me.id >> kMtShift) * si.ntypes + (t >= 0 ? (pt.id >> kMtShift) : si.wall_type)];
   const float rsf = me.r;
   const Real rs = (Real)rsf;
   const Real ms = mass_of<Real>(c, rs);
@@ -1528,7 +1541,7 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   if (t >= 0) {
     const int32_t r = atomicAdd(&a.w.bcnt[t], 1);
     if (r < kBwdCap)
-      a.w.bwd[(int64_t)r * N + t] = (s << kOwnerShift) | k;
+      a.w.bwd[(int64_t)r * N + t] = q;
     else
       raise_err(a.err, ERR_OVERFLOW);
   }
@@ -1540,11 +1553,12 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
 // contacts fall on the particles (the contact-branch divergence of a lane per
 // particle).  Contact k of lane l is read from lst[k * stride + l] for k <
 // kListStage when lst is given (the detection's LDS copy), else from the
-// list in global memory.  woff: 65 ints of LDS for the wave.  Every lane of
-// the wave must call it.
+// list in global memory.  The wave's contacts are stored from index qbase
+// on, in that order.  woff: 65 ints of LDS for the wave.  Every lane of the
+// wave must call it.
 template <typename Real, int LAW>
 __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, int32_t first, int32_t cnt,
-                                         const int32_t *lst, int32_t stride, int32_t *woff) {
+                                         const int32_t *lst, int32_t stride, int32_t *woff, int32_t qbase) {
   const int32_t lane = (int32_t)(threadIdx.x & 63);
   int32_t x = cnt;
 #pragma unroll
@@ -1569,7 +1583,7 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
       }
       const int32_t k = e - woff[lo], s = first + lo;
       const int32_t t = (lst && k < kListStage) ? lst[k * stride + lo] : a.nb.nb[(int64_t)k * a.L.n + s];
-      contact_one<Real, LAW>(a, si, s, t, k);
+      contact_one<Real, LAW>(a, si, s, t, qbase + e);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1582,19 +1596,46 @@ template <typename Real>
 __device__ __forceinline__ void carry_history(const PairArgs &a, int32_t s) {
   using V4 = typename Vec4T<Real>::type;
   if (s < 0 || (a.mode & MODE_WRITE_HIST) == 0) return;
-  const int32_t N = a.L.n;
   const int32_t c = min(max(a.old.cnt[s], 0), a.nb.K);
+  const int32_t q0 = a.old.start[s];
   a.cur.cnt[s] = c;
-  for (int32_t k = 0; k < c; k++)
-    ((V4 *)a.cur.ent)[(int64_t)k * N + s] = ((const V4 *)a.old.ent)[(int64_t)k * N + s];
+  a.cur.start[s] = q0;
+  for (int32_t k = 0; k < c; k++) ((V4 *)a.cur.ent)[(int64_t)q0 + k] = ((const V4 *)a.old.ent)[(int64_t)q0 + k];
 }
 
-// count of the history generation being written: the owned contacts (none
-// for the simple law, which keeps no history)
+// count and first entry of the history generation being written: the owned
+// contacts (none for the simple law, which keeps no history)
 template <int LAW>
-__device__ __forceinline__ void set_hist_count(const PairArgs &a, int32_t s, int32_t cnt) {
-  if (s >= 0 && (a.mode & MODE_WRITE_HIST) != 0) a.cur.cnt[s] = LAW == DEM_LAW_SIMPLE ? 0 : cnt;
+__device__ __forceinline__ void set_hist_count(const PairArgs &a, int32_t s, int32_t cnt, int32_t q0) {
+  if (s >= 0 && (a.mode & MODE_WRITE_HIST) != 0) {
+    a.cur.cnt[s] = LAW == DEM_LAW_SIMPLE ? 0 : cnt;
+    a.cur.start[s] = q0;
+  }
 }
+
+// exclusive prefix sum of c over the block (and its total); every thread
+// of the block must call it
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum, int32_t &total) {
+  const int32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t x = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; w++) {
+    const int32_t v = wsum[w];
+    base += w < wv ? v : 0;
+    tot += v;
+  }
+  total = tot;
+  return base + x - c;
+}
+
 
 // Steps 5-8 in one pass for the systems swept by the direct shape: each lane
 // sweeps its particle's forward cells (the owned contacts go to the list),
@@ -1626,9 +1667,15 @@ __global__ __launch_bounds__(kBlock) void k_contacts_direct(Layout L, StepCtl ct
                                     lst_all + threadIdx.x, err);
   }
   if (!with_law) return;
-  set_hist_count<LAW>(a, s, cnt);
+  // where the block's contacts go: slot order, then k
+  __shared__ int32_t wsum[kBlock / 64];
+  int32_t tot;
+  const int32_t off = block_exclusive_scan(cnt, wsum, tot);
+  const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + off;
+  set_hist_count<LAW>(a, s, cnt, q0);
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
-  law_wave<Real, LAW>(a, si, L.bfirst[blockIdx.x] + wave * 64, cnt, lst_all + wave * 64, kBlock, woff_all[wave]);
+  law_wave<Real, LAW>(a, si, L.bfirst[blockIdx.x] + wave * 64, cnt, lst_all + wave * 64, kBlock, woff_all[wave],
+                      __shfl(q0, 0));
 }
 
 // The law pass of the systems swept by the wave and tiled shapes (their
@@ -1645,9 +1692,13 @@ __global__ __launch_bounds__(kBlock) void k_contact_law(PairArgs a, int32_t only
     return;
   }
   const int32_t cnt = s >= 0 ? a.nb.fcnt[s] : 0;
-  set_hist_count<LAW>(a, s, cnt);
+  __shared__ int32_t wsum[kBlock / 64];
+  int32_t tot;
+  const int32_t off = block_exclusive_scan(cnt, wsum, tot);
+  const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + off;
+  set_hist_count<LAW>(a, s, cnt, q0);
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
-  law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave]);
+  law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave], __shfl(q0, 0));
 }
 
 // Step 1 drift x += dt v and Step 2 hash of the new position, written to
@@ -1673,37 +1724,13 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
 // step the closing half kick and, when the system steps again in this call,
 // the next step's opening kick, drift and hash.  The state goes to the other
 // buffers.
-// exclusive prefix sum of c over the block (and its total); every thread
-// of the block must call it
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum, int32_t &total) {
-  const int32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t x = c;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t y = __shfl_up(x, d);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[wv] = x;
-  __syncthreads();
-  int32_t base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; w++) {
-    const int32_t v = wsum[w];
-    base += w < wv ? v : 0;
-    tot += v;
-  }
-  total = tot;
-  return base + x - c;
-}
 
 // backward records a gather workgroup stages in LDS (more: it reads them
 // from global memory lane by lane)
 constexpr int32_t kGatherStage = 512;
 
-// record index of a backward entry (owner slot << kOwnerShift | k)
-__device__ __forceinline__ int64_t bwd_record(int32_t b, int32_t N) {
-  return (int64_t)(b & ((1 << kOwnerShift) - 1)) * N + (b >> kOwnerShift);
-}
+// record index of a backward entry (the entry is that index)
+__device__ __forceinline__ int64_t bwd_record(int32_t b, int32_t) { return (int64_t)b; }
 
 // the couple of the optional terms of contact q (XT: compiled in)
 template <typename Real>
@@ -1746,8 +1773,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     a.pos_out.y[s] = me.y;
     a.pos_out.z[s] = me.z;
     a.pos_out.r[s] = me.r;
-    a.pos_out.id[s] = me.id;
-    if (a.pos_out.mt) a.pos_out.mt[s] = me.mt;
+    a.pos_out.id[s] = me.id & kIdMask;
+    if (a.pos_out.mt) a.pos_out.mt[s] = me.id >> kMtShift;
     a.cell[s] = a.scell[s];
     return;
   }
@@ -1759,8 +1786,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   const int32_t s0 = a.L.bfirst[blockIdx.x];
   const int32_t nbk = s >= 0 ? min(a.w.bcnt[s], kBwdCap) : 0;
   if (s >= 0) a.w.bcnt[s] = 0;  // ready for the next evaluation's filing
+  const int32_t nown = s >= 0 ? a.nb.fcnt[s] : 0;
+  // one scan for both: the backward counts in the high half (at most
+  // kBwdCap x kBlock in total), the owned ones in the low (at most
+  // kListCap x kBlock)
   int32_t B;
-  const int32_t off = block_exclusive_scan(nbk, wsum, B);
+  const int32_t both = block_exclusive_scan((nbk << 16) | nown, wsum, B);
+  const int32_t off = both >> 16;
+  const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + (both & 0xffff);  // the particle's owned contacts
+  B >>= 16;
   bo[threadIdx.x] = off;
   if (threadIdx.x == kBlock - 1) bo[kBlock] = B;
   __syncthreads();
@@ -1843,12 +1877,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   } else {
     for_selected(a.w.bwd, N, s, nbk, back);  // a register network this long would cost every wave occupancy
   }
-  const int32_t nown = a.nb.fcnt[s];
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   for (int32_t k = 0; k < nown; k++) {
-    const int64_t q = (int64_t)k * N + s;
+    const int64_t q = (int64_t)q0 + k;
     Real f[3], m[3];
     get_record<Real>(a.w.pf, q, f, m);
     F[0] += f[0];
@@ -1867,7 +1900,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     if (diag) {
       e_el += a.w.pe[q];
       dmax = fmax(dmax, a.w.pd[q]);
-      if (a.nb.nb[q] >= 0)
+      if (a.nb.nb[(int64_t)k * N + s] >= 0)
         npair++;
       else
         nwall++;
@@ -1904,8 +1937,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
       a.cell[s] = a.scell[s];
     }
     a.pos_out.r[s] = me.r;
-    a.pos_out.id[s] = me.id;
-    if (a.pos_out.mt) a.pos_out.mt[s] = me.mt;
+    a.pos_out.id[s] = me.id & kIdMask;
+    if (a.pos_out.mt) a.pos_out.mt[s] = me.id >> kMtShift;
 #pragma unroll
     for (int q = 0; q < 3; q++) {
       ((Real *)a.vel_out.v[q])[s] = v[q];
@@ -2057,14 +2090,15 @@ hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl 
 
 hipError_t launch_reorder(int precision, const Layout &L, const PosBuf &src, const VelBuf &vsrc, const PosBuf &dst,
                           const VelBuf &vdst, bool soa, const int32_t *perm, const int32_t *cell, int32_t *scell,
-                          const NbrBuf &nb, const int32_t *old_ofs, hipStream_t st) {
+                          const NbrBuf &nb, const HistGen *old, hipStream_t st) {
   if (L.n <= 0) return hipSuccess;
+  const int32_t *oc = old ? old->cnt : nullptr, *os = old ? old->start : nullptr;
   if (precision == DEM_PREC_FP64)
     k_reorder<double><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, soa ? 1 : 0, perm, cell, scell, nb,
-                                                     old_ofs);
+                                                     oc, os);
   else
     k_reorder<float><<<L.nblocks, kBlock, 0, st>>>(L, src, vsrc, dst, vdst, soa ? 1 : 0, perm, cell, scell, nb,
-                                                    old_ofs);
+                                                    oc, os);
   return hipGetLastError();
 }
 

@@ -119,10 +119,11 @@ def test_small_hopper_flows_through_the_slit(dem):
     Fg, Tg = g.forces()
     # spheres at rest overlap by about m g / k_n, some 1e-6 of their radius,
     # and the oracle forms r - d (plates) and S - d (pairs) by plain
-    # subtraction: one ulp of r in the overlap is k_n ulp(r) of force
+    # subtraction: one ulp of r in the overlap is k_n ulp(r) of force, and
+    # the Coulomb limit passes it on to the tangential force and its torque
     r = float(w["r"][0])
-    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["fp64"],
-                        floor_abs=4.0 * w["params"]["kn"] * np.spacing(2 * r), torque_floor_abs=0.0)
+    floor = 4.0 * w["params"]["kn"] * np.spacing(2 * r)
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL["fp64"], floor_abs=floor, torque_floor_abs=r * floor)
 
 
 def test_run_to_rest_matches_the_oracle(dem):

@@ -110,8 +110,11 @@ def test_table_of_one_entry_is_one_material(dem):
     a, b = g.read_state(), h.read_state()
     for k in ("x", "v", "omega", "F", "T"):
         assert np.array_equal(a[k], b[k]), k
-    # back to the one material of the parameters
+    # back to the one material of the parameters (which evaluates the stored
+    # forces again on the current state, so g's are evaluated again too)
     h.set_materials(None, None)
+    g.set_materials(None, None)
+    assert np.array_equal(g.read_state()["F"], h.read_state()["F"])
     g.step(5)
     h.step(5)
     assert np.array_equal(g.read_state()["x"], h.read_state()["x"])

@@ -93,3 +93,24 @@ def test_autotuned_batch_is_deterministic(ex, tmp_path):
     for k, n in enumerate([9, 3, 0, 7, 9, 1]):
         ref = ex.run_alone(systems[k], n)
         assert np.array_equal(b.read_state(k)["x"], ref["x"])
+
+
+def test_served_results_track_the_oracle(ex):
+    """Requests in FP64 served concurrently with others (admitted while they
+    run, compacted when a member finishes): each result agrees with the FP64
+    oracle stepping the same request alone, within 1e-12 in x."""
+    from oracle.oracle import OracleSystem
+    reqs = requests(8, seed=43, n_hi=1500, steps_hi=40)
+    for r in reqs:
+        r.system = dict(r.system, params=dict(r.system["params"], precision="fp64"))
+    srv = serve.Server(ex, hbm_budget=2 << 30, max_slots=4, chunk=8)
+    done = srv.run(reqs)
+    assert len(done) == 8
+    for r in done:
+        assert r.error is None, r.error
+        s = r.system
+        o = OracleSystem(s["params"], s["x"], s["v"], s["omega"], s["r"])
+        o.step(r.steps)
+        want = o.read_state()
+        assert np.max(np.abs(r.result["x"] - want["x"])) < 1e-12, r.rid
+        assert np.max(np.abs(r.result["v"] - want["v"])) < 1e-9 * max(np.abs(want["v"]).max(), 1e-12), r.rid
