@@ -143,7 +143,11 @@ typedef struct {
 typedef struct dem_system dem_system; /* opaque host-side handle */
 
 /* Device bytes needed for n particles with these parameters (grid size,
- * capacity and precision all enter).  Errors: DEM_E_INVALID. */
+ * capacity and precision all enter): the state of Sec. 4.1's data structure
+ * (particle properties, the correspondence maps CM / SCM / SCCM of Eq. 11,
+ * the cell starts) in the sorted order of Step 4, the contact lists of Steps
+ * 5-8, the tangential history of Eq. 7 (two generations) and the per-step
+ * force records.  Errors: DEM_E_INVALID. */
 dem_status dem_workspace_bytes(const dem_params *p, int64_t n, size_t *bytes);
 
 /* Create a system from host arrays (original order).
@@ -197,13 +201,16 @@ size_t dem_static_workspace_capacity(void);
 dem_status dem_step(dem_system *s, int64_t nsteps);
 
 /* Contact force and torque (gravity excluded) on every particle of the
- * current state with the committed history, in original order; nothing is
- * committed.  F, T: n x 3.  Synchronous. */
+ * current state with the committed history, in original order: Steps 2-8 of
+ * Sec. 4.2 without the update of Step 1 (Eqs. 2-10 or Eq. 1 for pairs, Step
+ * 8 for walls, the torque of Eq. 3); nothing is committed.  F, T: n x 3.
+ * Synchronous. */
 dem_status dem_forces(dem_system *s, double *F, double *T);
 
-/* Current state in original order.  Any pointer may be NULL.  F, T are the
- * contact forces of the last evaluation (those the next step's first half
- * kick uses).  Synchronous. */
+/* Current state in original order: the particle properties of Sec. 4.1
+ * (x, v, omega) as Step 1 last updated them.  Any pointer may be NULL.  F, T
+ * are the contact forces of the last evaluation (those the next step's first
+ * half kick uses).  Synchronous. */
 dem_status dem_read_state(dem_system *s, double *x, double *v, double *omega, double *F, double *T);
 
 /* Committed tangential history: n_out entries, keys (a, b) as in dem_create,
@@ -226,7 +233,11 @@ dem_status dem_read_grid(dem_system *s, int32_t *cell_of_id, int32_t *id_at_slot
 /* Cells per axis (x fastest in the cell index); ncell = product. */
 dem_status dem_grid_dims(dem_system *s, int32_t dims[3]);
 
-/* FP64 diagnostics of the current state, reduced in a fixed order:
+/* FP64 diagnostics of the current state (totals the method conserves or
+ * dissipates: the momentum of Step 1's update, the kinetic energies of
+ * translation and of the rotation driven by Eq. 3, the potential energy of
+ * gravity and the elastic energy stored by the springs of Eq. 4, Hertz's
+ * 2/5 K delta^(5/2) for Eqs. 8-9), reduced in a fixed order:
  *  out[0..2] momentum sum m v   out[3] kinetic energy   out[4] rotational
  *  kinetic energy   out[5] potential energy -sum m g.(x - box_lo)
  *  out[6] elastic energy of the current contacts (normal spring energy plus

@@ -470,10 +470,16 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
                                                     const int32_t *__restrict__ cell, int32_t *__restrict__ scell,
                                                     NbrBuf nb, const int32_t *__restrict__ old_cnt,
                                                     const int32_t *__restrict__ old_start) {
+  // the block's packed records are staged here and stored as one contiguous
+  // run, 16 bytes per lane and instruction (a record per lane would make
+  // every store instruction touch a line per lane)
+  __shared__ uint4 stage[kBlock * sizeof(PState<Real>) / 16];
   int32_t k;
   const int32_t s = block_slot(L, k);
-  if (s < 0) return;
+  const int32_t s0 = L.bfirst[blockIdx.x];
   const SysInfo &si = L.tab[k];
+  const int32_t nval = min(kBlock, si.p0 + si.n - s0);  // the block's slots
+  if (s >= 0) {
   const int32_t p = perm[s];
   PState<Real> ps;
   ps.x = src.x[p];
@@ -495,13 +501,13 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   }
   // the candidate records are formed ahead of every store, so that the
   // system's grid is read with scalar loads (a store may alias it as far as
-  // the compiler knows); the FP32 copies are candidates only of the tiled and
-  // wave detection shapes
+  // the compiler knows); the FP32 copies are candidates only of the tiled
+  // detection shape
   const uint2 xq = make_xq(si, ps.x, ps.y, ps.z, ps.r);
   const float4 xyzr = make_xyzr(si.g, ps.x, ps.y, ps.z, ps.r);
   const int32_t cp = cell[p];
-  ((PState<Real> *)nb.pst)[s] = ps;
-  if (L.ntiles > 0 || L.nruns > 0) nb.xyzr[s] = xyzr;
+  ((PState<Real> *)stage)[threadIdx.x] = ps;
+  if (L.ntiles > 0) nb.xyzr[s] = xyzr;
   nb.xq[s] = xq;
   scell[s] = cp;
   if (soa) {
@@ -517,6 +523,11 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
       ((Real *)vdst.w[q])[s] = ps.w[q];
     }
   }
+  }
+  __syncthreads();
+  constexpr int32_t kChunks = sizeof(PState<Real>) / 16;  // 16-byte pieces per record
+  uint4 *dst16 = (uint4 *)((PState<Real> *)nb.pst + s0);
+  for (int32_t c = (int32_t)threadIdx.x; c < nval * kChunks; c += kBlock) dst16[c] = stage[c];
 }
 
 template <typename Real>
@@ -721,34 +732,38 @@ __device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf
   for (int h = 0; h < R; h++) {
     const int32_t e = end[h], sh = shift[h];
     int32_t t = beg[h];
-    while (t < e) {
+    if (t < e) {
       // software pipeline: the next kU candidates are in flight while the
-      // current ones are tested; the exact tests (global loads) stay outside
-      // this loop
-      Rec q[kU];
-      rows.fetch(q, t, e, sh);
-      for (;;) {
-        const int32_t tn = t + kU;
-        Rec n[kU];
-#pragma unroll
-        for (int u = 0; u < kU; u++) n[u] = q[u];
-        if (tn < e) rows.fetch(n, tn, e, sh);
+      // current ones are tested (the fetch clamps at the range's last
+      // candidate, so it needs no branch); a candidate that passes is
+      // parked in the lane's LDS slots by an unconditional store and a
+      // conditional count, so the loop body has no branch either; the exact
+      // tests (global loads) stay outside the loop
+      // two register sets take turns (no copy between them, which would
+      // wait for the load in flight)
+      auto test = [&](const Rec (&q)[kU]) {
 #pragma unroll
         for (int u = 0; u < kU; u++) {
-          if (t + u < e && near(q[u])) {
-            surv[ns * kLanes] = t + u;
-            ns++;
-          }
+          const bool pass = (t + u < e) & near(q[u]);
+          surv[ns * kLanes] = t + u;
+          ns += pass ? 1 : 0;
         }
-        t = tn;
-        if (t >= e || ns > kSurv - kU) break;
-#pragma unroll
-        for (int u = 0; u < kU; u++) q[u] = n[u];
-      }
-      if (ns > kSurv - kU) {
-        for (int32_t j = 0; j < ns; j++)
-          exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
-        ns = 0;
+        t += kU;
+        if (ns > kSurv - kU) {
+          for (int32_t j = 0; j < ns; j++)
+            exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
+          ns = 0;
+        }
+      };
+      Rec qa[kU], qb[kU];
+      rows.fetch(qa, t, e, sh);
+      for (;;) {
+        rows.fetch(qb, t + kU, e, sh);
+        test(qa);
+        if (t >= e) break;
+        rows.fetch(qa, t + kU, e, sh);
+        test(qb);
+        if (t >= e) break;
       }
     }
   }
@@ -890,8 +905,7 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
   int2 *queue = queue_all[wave];
   int32_t *cnt = cnt_all[wave];
   const int32_t N = L.n;
-  const float eps = si.eps;
-  const float4 *xyzr = nb.xyzr;
+  const uint2 *xq = nb.xq;
   const uint64_t lt = (1ull << lane) - 1;  // lanes below this one
 
   for (int32_t g0 = s_lo; g0 < s_hi; g0 += 64) {
@@ -928,10 +942,14 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
       qh += m;
     };
 
-    // each lane loads its particle's prefilter copy, cell and candidate
-    // ranges once; the loops below read them with readlane
+    // each lane loads its particle's candidate record, cell and candidate
+    // ranges once; the loops below read them with readlane.  The record is
+    // kept as the integer prefilter wants it (see NearInt): x | y << 16 and
+    // z | (-R) << 16, R the radius plus the rounding margin.
     const int32_t me = g0 + (lane < gn ? lane : 0);
-    const float4 pv = xyzr[me];
+    const uint2 pr = xq[me];
+    const uint32_t pqxy = pr.x;
+    const uint32_t pqzr = (pr.y & 0xffffu) | (((0u - ((pr.y >> 16) + (uint32_t)kFixMargin)) & 0xffffu) << 16);
     const int32_t mcell = scell[me];
     CellRanges Rl;
     {
@@ -948,13 +966,13 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
     // A cell with 65..96 candidates tests its second chunk for two
     // particles at once, 32 lanes each: both halves hold candidates 64..95.
     auto halves = [](int32_t C) { return C > 64 && C <= 96; };
-    auto load_chunks = [&](const CellRanges &R, float4 &qa, int32_t &ta, float4 &qb, int32_t &tb) {
+    auto load_chunks = [&](const CellRanges &R, uint2 &qa, int32_t &ta, uint2 &qb, int32_t &tb) {
       const int32_t C = R.pc[5];
       const int32_t cb = 64 + (halves(C) ? (lane & 31) : lane);
       ta = lane < C ? cand_slot(R, lane) : -1;
       tb = cb < C ? cand_slot(R, cb) : -1;
-      qa = xyzr[ta >= 0 ? ta : me];
-      qb = xyzr[tb >= 0 ? tb : me];
+      qa = xq[ta >= 0 ? ta : me];
+      qb = xq[tb >= 0 ? tb : me];
     };
     // queue the lanes of m (this lane if mine) as contacts of particle l
     auto append = [&](uint64_t m, bool mine, int32_t l, int32_t t) {
@@ -968,7 +986,7 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
     };
     CellRanges R;
     ranges_of(0, R);
-    float4 q0, q1;
+    uint2 q0, q1;
     int32_t t0, t1;
     load_chunks(R, q0, t0, q1, t1);
     int32_t a = 0;  // first lane of the current cell
@@ -978,7 +996,7 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
       const uint64_t later = starts & ~((2ull << a) - 1);
       const int32_t b = later ? __ffsll((long long)later) - 1 : gn;
       CellRanges Rn = R;
-      float4 n0 = q0, n1 = q1;
+      uint2 n0 = q0, n1 = q1;
       int32_t u0 = t0, u1 = t1;
       if (b < gn) {
         ranges_of(b, Rn);
@@ -988,43 +1006,38 @@ __global__ __launch_bounds__(kCellWaves * 64) void k_detect_cells(Layout L, Step
       const bool split = halves(C);
       for (int32_t l = a; l < b;) {
         const int32_t i = g0 + l;
-        const float px = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), l));
-        const float py = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), l));
-        const float pz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), l));
-        const float pe = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), l)) + eps;
-        auto passes = [&](const float4 &q, int32_t t, float x, float y, float z, float e, int32_t ii) {
-          const float dx = q.x - x, dy = q.y - y, dz = q.z - z, sf = e + q.w;
-          return (t > ii) & (dx * dx + dy * dy + dz * dz < sf * sf);
+        const NearInt near_l{(uint32_t)__builtin_amdgcn_readlane((int32_t)pqxy, l),
+                             (uint32_t)__builtin_amdgcn_readlane((int32_t)pqzr, l)};
+        auto passes = [&](const uint2 &q, int32_t t, const NearInt &near, int32_t ii) {
+          return (t > ii) & near(q);
         };
         // chunk 0 of particle l
         {
-          const bool ps = passes(q0, t0, px, py, pz, pe, i);
+          const bool ps = passes(q0, t0, near_l, i);
           append(__builtin_amdgcn_ballot_w64(ps), ps, l, t0);
         }
         if (split && l + 1 < b) {
           // chunk 1 of particles l (lanes 0-31) and l + 1 (lanes 32-63);
           // l + 1 files its chunk-1 survivors after its chunk-0 ones
-          const float qx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.x), l + 1));
-          const float qy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.y), l + 1));
-          const float qz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.z), l + 1));
-          const float qe = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pv.w), l + 1)) + eps;
+          const NearInt near_n{(uint32_t)__builtin_amdgcn_readlane((int32_t)pqxy, l + 1),
+                               (uint32_t)__builtin_amdgcn_readlane((int32_t)pqzr, l + 1)};
           const bool lo = lane < 32;
-          const bool p1 = passes(q1, t1, lo ? px : qx, lo ? py : qy, lo ? pz : qz, lo ? pe : qe, lo ? i : i + 1);
+          const bool p1 = passes(q1, t1, lo ? near_l : near_n, lo ? i : i + 1);
           const uint64_t m1 = __builtin_amdgcn_ballot_w64(p1);
           append(m1 & 0xFFFFFFFFull, p1 && lo, l, t1);
-          const bool p0 = passes(q0, t0, qx, qy, qz, qe, i + 1);
+          const bool p0 = passes(q0, t0, near_n, i + 1);
           append(__builtin_amdgcn_ballot_w64(p0), p0, l + 1, t0);
           append(m1 & ~0xFFFFFFFFull, p1 && !lo, l + 1, t1);
           l += 2;
           continue;
         }
         if (C > 64) {
-          const bool ps = (!split || lane < 32) && passes(q1, t1, px, py, pz, pe, i);
+          const bool ps = (!split || lane < 32) && passes(q1, t1, near_l, i);
           append(__builtin_amdgcn_ballot_w64(ps), ps, l, t1);
         }
         for (int32_t cb = 128; cb < C; cb += 64) {  // a crowded stencil: further chunks from the caches
           const int32_t t = cb + lane < C ? cand_slot(R, cb + lane) : -1;
-          const bool ps = passes(xyzr[t >= 0 ? t : me], t, px, py, pz, pe, i);
+          const bool ps = passes(xq[t >= 0 ? t : me], t, near_l, i);
           append(__builtin_amdgcn_ballot_w64(ps), ps, l, t);
         }
         l += 1;
@@ -1388,14 +1401,25 @@ template <typename Real>
 __device__ __forceinline__ void hist_find(const HistGen &old, int32_t q0, int32_t c, int32_t key, Real h[3]) {
   using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
-  for (int32_t k = 0; k < c; k++) {
-    const V4 d = ((const V4 *)old.ent)[(int64_t)q0 + k];
-    if (entry_key(d.w) == key) {
-      h[0] = d.x;
-      h[1] = d.y;
-      h[2] = d.z;
-      break;
+  // the entries are adjacent: up to four are requested together, then
+  // matched (a lookup waits for one round trip instead of one per entry)
+  constexpr int kBatch = 4;
+  for (int32_t k0 = 0; k0 < c; k0 += kBatch) {
+    V4 d[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; j++)
+      if (k0 + j < c) d[j] = ((const V4 *)old.ent)[(int64_t)q0 + k0 + j];
+    bool found = false;
+#pragma unroll
+    for (int j = 0; j < kBatch; j++) {
+      if (!found && k0 + j < c && entry_key(d[j].w) == key) {
+        h[0] = d[j].x;
+        h[1] = d[j].y;
+        h[2] = d[j].z;
+        found = true;
+      }
     }
+    if (found) break;
   }
 }
 
@@ -1447,6 +1471,9 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
+  // the partner's rank in its backward list is drawn first: the atomic's
+  // round trip overlaps the loads and the law below
+  const int32_t brank = t >= 0 ? atomicAdd(&a.w.bcnt[t], 1) : 0;
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
@@ -1539,9 +1566,8 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
     a.w.pd[q] = (double)delta;
   }
   if (t >= 0) {
-    const int32_t r = atomicAdd(&a.w.bcnt[t], 1);
-    if (r < kBwdCap)
-      a.w.bwd[(int64_t)r * N + t] = q;
+    if (brank < kBwdCap)
+      a.w.bwd[(int64_t)brank * N + t] = q;
     else
       raise_err(a.err, ERR_OVERFLOW);
   }
