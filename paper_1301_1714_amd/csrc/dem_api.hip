@@ -345,8 +345,8 @@ size_t carve(Engine &e, char *base) {
   e.work.pc = e.has_terms ? cv.take_bytes(4 * R * PB) : nullptr;
   e.work.pe = cv.take<double>(PB);
   e.work.pd = cv.take<double>(PB);
-  e.work.bcnt = cv.take<int32_t>(N);
-  e.work.bwd = cv.take<int32_t>((size_t)kBwdCap * N);
+  e.work.part = cv.take<int32_t>(PB);
+  e.work.qs = cv.take<int32_t>(N);
   e.diag.e_el = cv.take<double>(N);
   e.diag.npair = cv.take<int32_t>(N);
   e.diag.nwall = cv.take<int32_t>(N);
@@ -487,6 +487,7 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.diag = e.diag;
   a.cell = e.cell;
   a.scell = e.scell;
+  a.cell_start = e.cell_start;
   a.mode = mode;
   a.law = e.law;
   a.terms = e.has_terms ? 1 : 0;
@@ -790,8 +791,6 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   e.cp = 1;
   e.cv = 1;
   e.gc = 0;
-  // no backward entries are filed yet (each gather clears what it read)
-  HIP_TRY(launch_fill(e.work.bcnt, e.n, 0, e.stream));
   // Steps 5-6: the contacts of the initial positions
   HIP_TRY(build_contacts(e, nullptr));
   if ((st = sync_and_check(e)) != DEM_OK) return st;

@@ -67,7 +67,6 @@ constexpr int32_t kBlock = 256;
 constexpr int32_t kListCap = 64;  // largest per-particle capacity of owned contacts (higher partners + walls)
 // contact indices k * N + s are int32: n * kListCap must stay below 2^31
 constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
-constexpr int32_t kBwdCap = 32;   // contacts per particle with lower partners
 // first entry of kernel block b's contacts (see the layout above)
 __host__ __device__ inline int64_t cbase(int32_t b, int32_t K) { return (int64_t)b * kBlock * K; }
 constexpr int32_t kMaxTile = 32;  // cells along x per detection tile
@@ -190,8 +189,8 @@ struct PairWork {
   void *pc;        // per contact Real4: the couple of the optional terms on the owner (engines with terms only)
   double *pe;      // per contact elastic energy (diagnostics)
   double *pd;      // per contact overlap (diagnostics)
-  int32_t *bcnt;   // [N] contacts of each particle as the partner (zero between evaluations)
-  int32_t *bwd;    // [kBwdCap][N] the indices of their contact records, in arrival order
+  int32_t *part;   // per contact: the partner's slot (a wall: its negative key)
+  int32_t *qs;     // [N] index of each slot's first owned contact
 };
 
 struct DiagBuf {
@@ -234,6 +233,7 @@ struct PairArgs {
   DiagBuf diag;
   int32_t *cell;         // cells for the next sort (drifted positions, or unchanged ones)
   const int32_t *scell;  // cells of the current slots
+  const int32_t *cell_start;  // their cells' first slots
   int32_t mode;
   int32_t law;
   int32_t terms;         // some system of the engine has optional contact terms (dem_params.terms)

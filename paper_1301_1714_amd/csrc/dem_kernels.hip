@@ -1229,57 +1229,6 @@ __device__ __forceinline__ void put_entry(const HistGen &g, int64_t q, const Rea
 }
 
 // fixed-size bitonic network on registers (indices are compile-time)
-template <int M>
-__device__ __forceinline__ void bitonic_sort(int32_t (&L)[M]) {
-#pragma unroll
-  for (int k = 2; k <= M; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-      for (int i = 0; i < M; i++) {
-        const int l = i ^ j;
-        if (l > i) {
-          const bool up = (i & k) == 0;
-          const int32_t u = L[i], v = L[l];
-          const bool sw = up ? (u > v) : (u < v);
-          L[i] = sw ? v : u;
-          L[l] = sw ? u : v;
-        }
-      }
-    }
-  }
-}
-
-// the backward list of slot s (M >= cnt entries, k-major), sorted ascending
-// in registers, then fn(q) for each entry in that order
-template <int M, typename Fn>
-__device__ __forceinline__ void for_sorted(const int32_t *bwd, int32_t n, int32_t s, int32_t cnt, Fn &&fn) {
-  int32_t L[M];
-#pragma unroll
-  for (int i = 0; i < M; i++) L[i] = i < cnt ? bwd[(int64_t)i * n + s] : INT32_MAX;
-  bitonic_sort<M>(L);
-#pragma unroll
-  for (int i = 0; i < M; i++)
-    if (i < cnt) fn(L[i]);
-}
-
-// the same for a long list (rare), without a register array: each next
-// entry is the smallest one above the previous (the entries are distinct
-// contact indices)
-template <typename Fn>
-__device__ __forceinline__ void for_selected(const int32_t *bwd, int32_t n, int32_t s, int32_t cnt, Fn &&fn) {
-  int32_t prev = -1;
-  for (int32_t i = 0; i < cnt; i++) {
-    int32_t cur = INT32_MAX;
-    for (int32_t k = 0; k < cnt; k++) {
-      const int32_t q = bwd[(int64_t)k * n + s];
-      cur = q > prev && q < cur ? q : cur;
-    }
-    fn(cur);
-    prev = cur;
-  }
-}
-
 // --------------------------------------------------------------------------
 // Steps 7-8: contact law
 
@@ -1457,23 +1406,19 @@ __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, i
 // Owned contact k of slot s (partner t, a slot or -1 - w), stored at index
 // q of the per-contact arrays: the law of Eqs. 2-10 (or Eq. 1) evaluated
 // once per pair, seen from the owner (the lower slot), stored as the force
-// on the owner and n x F_t;
-// the partner receives the exact negation through its backward list, where
-// the contact is filed here.  Both particles' inputs come from their packed
-// state records.
+// on the owner and n x F_t; the partner receives the exact negation (its
+// sums find the contact by the partner slot stored with it).  Both
+// particles' inputs come from their packed state records.
 template <typename Real, int LAW>
 __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
-  const int32_t N = a.L.n;
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
-  // the partner's rank in its backward list is drawn first: the atomic's
-  // round trip overlaps the loads and the law below
-  const int32_t brank = t >= 0 ? atomicAdd(&a.w.bcnt[t], 1) : 0;
+  a.w.part[q] = t;  // the partner side's sums find the contact by this
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
@@ -1564,12 +1509,6 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   if (diag) {
     a.w.pe[q] = elastic_energy<Real, BASE>(c, K, delta, R, o, h);
     a.w.pd[q] = (double)delta;
-  }
-  if (t >= 0) {
-    if (brank < kBwdCap)
-      a.w.bwd[(int64_t)brank * N + t] = q;
-    else
-      raise_err(a.err, ERR_OVERFLOW);
   }
 }
 
@@ -1699,6 +1638,7 @@ __global__ __launch_bounds__(kBlock) void k_contacts_direct(Layout L, StepCtl ct
   const int32_t off = block_exclusive_scan(cnt, wsum, tot);
   const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + off;
   set_hist_count<LAW>(a, s, cnt, q0);
+  if (s >= 0) a.w.qs[s] = q0;
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
   law_wave<Real, LAW>(a, si, L.bfirst[blockIdx.x] + wave * 64, cnt, lst_all + wave * 64, kBlock, woff_all[wave],
                       __shfl(q0, 0));
@@ -1723,6 +1663,7 @@ __global__ __launch_bounds__(kBlock) void k_contact_law(PairArgs a, int32_t only
   const int32_t off = block_exclusive_scan(cnt, wsum, tot);
   const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + off;
   set_hist_count<LAW>(a, s, cnt, q0);
+  if (s >= 0) a.w.qs[s] = q0;
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
   law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave], __shfl(q0, 0));
 }
@@ -1745,18 +1686,46 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
   cell[i] = cc;
 }
 
-// One lane per particle: contact sums in a fixed order (contacts with lower
-// slots, ascending; with higher slots, ascending; walls), then in a time
-// step the closing half kick and, when the system steps again in this call,
-// the next step's opening kick, drift and hash.  The state goes to the other
-// buffers.
+// --------------------------------------------------------------------------
+// Step 7's sums, one lane per particle, in a fixed order (contacts with
+// lower slots, ascending; with higher slots, ascending; walls), then in a
+// time step the closing half kick and, when the system steps again in this
+// call, the next step's opening kick, drift and hash.  The state goes to the
+// other buffers.
+//
+// A particle's backward contacts (those with lower slots,
+// owned and evaluated there) are found without the owners filing them
+// anywhere: each owner swept the forward half of its (2K + 1)^3 cells, so
+// the owners of a particle's backward contacts lie in the mirror half, which
+// in slot order is R = 1 + 2K + 2K^2 runs of cells -- cells cx-K..cx of its
+// own row (the slots below it), cells cx-K..cx+K of rows dy = -K..-1 of its
+// plane and of rows dy = -K..K of planes dz = -K..-1.  A block takes per run
+// the slot range from its first particle's run to its last one's (slots are
+// sorted by cell, so the range covers every particle's run in between),
+// merges the ranges, cuts them where the contact arrays' blocks end into
+// runs of contact indices (the contacts of consecutive owners of one block
+// are contiguous), and reads the stored partner of every contact in them
+// with all lanes busy: a partner inside the block is a hit.  Each particle
+// then sums its hits in ascending contact index, which is ascending owner
+// slot: the order, and so the bits, do not depend on the order in which the
+// hits arrived.
 
-// backward records a gather workgroup stages in LDS (more: it reads them
-// from global memory lane by lane)
-constexpr int32_t kGatherStage = 512;
+constexpr int32_t kGatherStage = 512;   // backward records staged in LDS per block
+constexpr int32_t kGatherQueue = 1024;  // backward contacts collected per block (more: each lane scans alone)
+constexpr int32_t kGatherRuns = 1 + 2 * kMaxReach + 2 * kMaxReach * kMaxReach;
+constexpr int32_t kGatherPieces = 64;   // runs of contact indices per block (more: each lane scans alone)
 
-// record index of a backward entry (the entry is that index)
-__device__ __forceinline__ int64_t bwd_record(int32_t b, int32_t) { return (int64_t)b; }
+// row offset of backward run h (h = 0: the own row)
+__device__ __forceinline__ void back_row(int32_t h, int32_t K, int32_t &dy, int32_t &dz) {
+  if (h <= K) {
+    dy = -h;
+    dz = 0;
+  } else {
+    const int32_t i = h - K - 1;
+    dy = i % (2 * K + 1) - K;
+    dz = -1 - i / (2 * K + 1);
+  }
+}
 
 // the couple of the optional terms of contact q (XT: compiled in)
 template <typename Real>
@@ -1771,9 +1740,20 @@ __device__ __forceinline__ void couple_of(const PairArgs &a, int64_t q, Real C[3
 template <typename Real, bool XT>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   using V2 = typename Vec2T<Real>::type;
-  __shared__ int32_t bo[kBlock + 1];       // the block's backward segments
-  __shared__ int32_t bq[kGatherStage];     // their contact indices, in arrival order
-  __shared__ V2 brec[3 * kGatherStage];    // and their records
+  constexpr int32_t kQueueBytes = kGatherQueue * 5;  // contact index and particle of each hit
+  constexpr int32_t kRecBytes = 3 * kGatherStage * (int32_t)sizeof(V2);
+  __shared__ int32_t bo[kBlock + 1];        // each particle's segment of bq
+  __shared__ int32_t bq[kGatherQueue];      // the hits' contact indices, by particle
+  __shared__ int32_t lcnt[kBlock], lfill[kBlock];
+  // first the hits in arrival order, then the staged records
+  __shared__ uint4 lds16[(kQueueBytes > kRecBytes ? kQueueBytes : kRecBytes) / 16 + 1];
+  int32_t *hq = (int32_t *)lds16;
+  uint8_t *hp = (uint8_t *)(hq + kGatherQueue);
+  V2 *brec = (V2 *)lds16;
+  __shared__ int32_t wlo[1][kGatherRuns], whi[1][kGatherRuns];  // each run's range
+  __shared__ int32_t rl[kGatherRuns], rh[kGatherRuns];  // merged slot ranges
+  __shared__ int32_t pl[kGatherPieces + 1], pn[kGatherPieces + 1], pq[kGatherPieces + 1];
+  __shared__ int32_t nmerged, npiece, nhit;
   __shared__ int32_t wsum[kBlock / 64];
   int32_t k;
   const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + m), one system
@@ -1783,9 +1763,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   // far as the compiler knows)
   const Consts c = si.c;
   const Grid g = si.g;
+  const int32_t K = si.reach, p0 = si.p0;
   const bool stepping = (a.mode & MODE_KICK) != 0;
   const int32_t step_now = stepping ? *a.ctl.step : 0, left_k = stepping ? a.ctl.left[k] : 0;
   const int32_t N = a.L.n;
+  const int32_t s0 = a.L.bfirst[blockIdx.x], mblk = min(kBlock, si.p0 + si.n - s0);
   if (stepping && !(step_now < left_k)) {
     if (s < 0) return;
     const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
@@ -1804,71 +1786,184 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     a.cell[s] = a.scell[s];
     return;
   }
-  // The backward records -- random reads -- are fetched first with every
-  // lane on one (lane e takes entry e of the block's segments, its particle
-  // found by bisection), into LDS; each particle then sums its own from
-  // there.  A block with more than kGatherStage of them reads them lane by
-  // lane from global memory instead.
-  const int32_t s0 = a.L.bfirst[blockIdx.x];
-  const int32_t nbk = s >= 0 ? min(a.w.bcnt[s], kBwdCap) : 0;
-  if (s >= 0) a.w.bcnt[s] = 0;  // ready for the next evaluation's filing
-  const int32_t nown = s >= 0 ? a.nb.fcnt[s] : 0;
-  // one scan for both: the backward counts in the high half (at most
-  // kBwdCap x kBlock in total), the owned ones in the low (at most
-  // kListCap x kBlock)
-  int32_t B;
-  const int32_t both = block_exclusive_scan((nbk << 16) | nown, wsum, B);
-  const int32_t off = both >> 16;
-  const int32_t q0 = (int32_t)cbase(blockIdx.x, a.nb.K) + (both & 0xffff);  // the particle's owned contacts
-  B >>= 16;
-  bo[threadIdx.x] = off;
-  if (threadIdx.x == kBlock - 1) bo[kBlock] = B;
+  const int32_t nx = g.nc[0], ny = g.nc[1];
+  const int32_t R = 1 + 2 * K + 2 * K * K;
+  // (1) per backward run, the slot range from the block's first particle's
+  // run to its last one's.  A run outside the grid stands for the empty
+  // range where it would lie (the start of the plane for a row below it,
+  // the end of the plane for a row above it, the system's first slot for a
+  // plane below it), so that the run ends grow with the slot and the range
+  // covers the run of every particle in between.
+  if ((int32_t)threadIdx.x < R) {
+    const int32_t h = (int32_t)threadIdx.x;
+    int32_t dy, dz;
+    back_row(h, K, dy, dz);
+    const int32_t *cs = a.cell_start + g.c0;
+    auto run_end = [&](int32_t t, bool start) {
+      const int32_t cc = a.scell[t] - g.c0;
+      const int32_t cx = cc % nx, yy = (cc / nx) % ny + dy, zz = cc / (nx * ny) + dz;
+      if (zz < 0) return cs[0];
+      if (yy < 0) return cs[zz * ny * nx];
+      if (yy >= ny) return cs[(zz + 1) * ny * nx];
+      if (start) return cs[(zz * ny + yy) * nx + max(cx - K, 0)];
+      return h == 0 ? t : cs[(zz * ny + yy) * nx + min(cx + K, nx - 1) + 1];  // own row: owners below it
+    };
+    wlo[0][h] = run_end(s0, true);
+    whi[0][h] = run_end(s0 + mblk - 1, false);
+  }
+  lcnt[threadIdx.x] = 0;
+  lfill[threadIdx.x] = 0;
+  if (threadIdx.x == 0) nhit = 0;
   __syncthreads();
-  const bool staged = B <= kGatherStage;
-  if (staged) {
-    for (int32_t e = threadIdx.x; e < B; e += kBlock) {
-      int32_t lo = 0, hi = kBlock;  // bo[lo] <= e < bo[hi]
-      while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (bo[mid] <= e)
-          lo = mid;
-        else
-          hi = mid;
+  // (2) the block's ranges, sorted and merged (one thread: at most 13), and
+  // cut where the contact arrays' blocks end
+  if (threadIdx.x == 0) {
+    int32_t L[kGatherRuns], H[kGatherRuns], n = 0;
+    for (int32_t h = 0; h < R; h++) {
+      const int32_t lo = wlo[0][h], hi = whi[0][h];
+      if (lo >= hi) continue;
+      int32_t i = n++;
+      for (; i > 0 && L[i - 1] > lo; i--) {
+        L[i] = L[i - 1];
+        H[i] = H[i - 1];
       }
-      const int32_t b = a.w.bwd[(int64_t)(e - bo[lo]) * N + s0 + lo];
-      bq[e] = b;
-      const V2 *p = (const V2 *)a.w.pf + 3 * bwd_record(b, N);
-      brec[3 * e] = p[0];
-      brec[3 * e + 1] = p[1];
-      brec[3 * e + 2] = p[2];
+      L[i] = lo;
+      H[i] = hi;
+    }
+    int32_t nm = 0, np = 0;
+    for (int32_t i = 0; i < n; i++) {
+      if (nm > 0 && L[i] <= rh[nm - 1]) {
+        rh[nm - 1] = max(rh[nm - 1], H[i]);
+      } else {
+        rl[nm] = L[i];
+        rh[nm] = H[i];
+        nm++;
+      }
+    }
+    for (int32_t i = 0; i < nm; i++) {
+      for (int32_t f = rl[i]; f < rh[i];) {
+        const int32_t e = min(rh[i], p0 + ((f - p0) & ~(kBlock - 1)) + kBlock);
+        if (np < kGatherPieces) {
+          pl[np] = f;
+          pn[np] = e;  // slot range [f, e) for now
+        }
+        np++;
+        f = e;
+      }
+    }
+    nmerged = nm;
+    npiece = np;
+  }
+  __syncthreads();
+  const int32_t np = npiece;
+  const bool pieces = np <= kGatherPieces;
+  if (pieces) {
+    // the contact indices of each piece: its owners' contacts are contiguous
+    if (threadIdx.x < 64) {
+      const int32_t lane = (int32_t)threadIdx.x;
+      int32_t q0 = 0, cnt = 0;
+      if (lane < np) {
+        const int32_t f = pl[lane], l = pn[lane] - 1;
+        q0 = a.w.qs[f];
+        cnt = a.w.qs[l] + a.nb.fcnt[l] - q0;
+      }
+      int32_t x = cnt;  // inclusive prefix over the pieces
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      if (lane < np) {
+        pl[lane] = q0;
+        pq[lane] = x - cnt;
+      }
+      if (lane == np - 1) pq[np] = x;
+      if (np == 0 && lane == 0) pq[0] = 0;
+    }
+    __syncthreads();
+    // (3) every contact of the pieces, one lane each: a partner in the block
+    // is a hit, queued with its particle
+    // (four per lane at a time, so that their loads are in flight together)
+    const int32_t E = pq[np];
+    int32_t pi = 0;  // the piece of the lane's entry (its entries only grow)
+    for (int32_t e0 = threadIdx.x; e0 < E; e0 += 4 * kBlock) {
+      int32_t q[4], t[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int32_t e = e0 + u * kBlock;
+        q[u] = -1;
+        if (e < E) {
+          while (pq[pi + 1] <= e) pi++;
+          q[u] = pl[pi] + e - pq[pi];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) t[u] = q[u] >= 0 ? a.w.part[q[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (q[u] >= 0 && (uint32_t)(t[u] - s0) < (uint32_t)mblk) {
+          const int32_t p = t[u] - s0;
+          atomicAdd(&lcnt[p], 1);
+          const int32_t slot = atomicAdd(&nhit, 1);
+          if (slot < kGatherQueue) {
+            hq[slot] = q[u];
+            hp[slot] = (uint8_t)p;
+          }
+        }
+      }
     }
   }
   __syncthreads();
+  const int32_t B = pieces ? nhit : INT32_MAX;
+  const bool queued = B <= kGatherQueue, staged = B <= kGatherStage;
+  const int32_t nbk = queued && s >= 0 ? lcnt[threadIdx.x] : 0;
+  if (queued) {
+    // (4) the hits by particle (in any order within a particle), then
+    // their records into LDS with every lane on one
+    int32_t tot;
+    const int32_t off = block_exclusive_scan(nbk, wsum, tot);
+    bo[threadIdx.x] = off;
+    __syncthreads();
+    for (int32_t e = threadIdx.x; e < B; e += kBlock) {
+      const int32_t p = hp[e];
+      bq[bo[p] + atomicAdd(&lfill[p], 1)] = hq[e];
+    }
+    __syncthreads();
+    if (staged) {
+      for (int32_t e = threadIdx.x; e < B; e += kBlock) {
+        const V2 *p = (const V2 *)a.w.pf + 3 * (int64_t)bq[e];
+        brec[3 * e] = p[0];
+        brec[3 * e + 1] = p[1];
+        brec[3 * e + 2] = p[2];
+      }
+    }
+    __syncthreads();
+  }
   if (s < 0) return;
   const PState<Real> me = ((const PState<Real> *)a.nb.pst)[s];
   const Real rs = (Real)me.r;
   Real F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
   // contacts with lower partners, ascending by owner slot
-  auto back = [&](int32_t b) {
-    Real f[3], m[3];
-    get_record<Real>(a.w.pf, bwd_record(b, N), f, m);
+  auto back = [&](int64_t q) {
+    Real f[3], mm[3];
+    get_record<Real>(a.w.pf, q, f, mm);
     F[0] -= f[0];
     F[1] -= f[1];
     F[2] -= f[2];
-    T[0] += rs * m[0];  // Eq. 3; the same n x F_t on both bodies
-    T[1] += rs * m[1];
-    T[2] += rs * m[2];
+    T[0] += rs * mm[0];  // Eq. 3; the same n x F_t on both bodies
+    T[1] += rs * mm[1];
+    T[2] += rs * mm[2];
     if (XT) {  // the opposite of the owner's couple
       Real C[3];
-      couple_of<Real>(a, bwd_record(b, N), C);
+      couple_of<Real>(a, q, C);
       T[0] -= C[0];
       T[1] -= C[1];
       T[2] -= C[2];
     }
   };
-  if (staged) {
-    // ascending by owner slot: each next entry is the smallest above the
-    // previous one (an owner files one contact per partner)
+  if (queued) {
+    // each next entry is the smallest above the previous one (an owner has
+    // at most one contact with a given partner)
     const int32_t b0 = bo[threadIdx.x];
     int32_t prev = -1;
     for (int32_t i = 0; i < nbk; i++) {
@@ -1881,28 +1976,38 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
         }
       }
       prev = cur;
-      const V2 r0 = brec[3 * at], r1 = brec[3 * at + 1], r2 = brec[3 * at + 2];
-      F[0] -= r0.x;
-      F[1] -= r0.y;
-      F[2] -= r1.x;
-      T[0] += rs * r1.y;  // Eq. 3; the same n x F_t on both bodies
-      T[1] += rs * r2.x;
-      T[2] += rs * r2.y;
-      if (XT) {
-        Real C[3];
-        couple_of<Real>(a, bwd_record(cur, N), C);
-        T[0] -= C[0];
-        T[1] -= C[1];
-        T[2] -= C[2];
+      if (staged) {
+        const V2 r0 = brec[3 * at], r1 = brec[3 * at + 1], r2 = brec[3 * at + 2];
+        F[0] -= r0.x;
+        F[1] -= r0.y;
+        F[2] -= r1.x;
+        T[0] += rs * r1.y;  // Eq. 3; the same n x F_t on both bodies
+        T[1] += rs * r2.x;
+        T[2] += rs * r2.y;
+        if (XT) {
+          Real C[3];
+          couple_of<Real>(a, cur, C);
+          T[0] -= C[0];
+          T[1] -= C[1];
+          T[2] -= C[2];
+        }
+      } else {
+        back(cur);
       }
     }
-  } else if (nbk <= 4) {
-    for_sorted<4>(a.w.bwd, N, s, nbk, back);
-  } else if (nbk <= 8) {
-    for_sorted<8>(a.w.bwd, N, s, nbk, back);
   } else {
-    for_selected(a.w.bwd, N, s, nbk, back);  // a register network this long would cost every wave occupancy
+    // a crowded block: the lane reads every owner's contacts itself, in
+    // ascending slot order
+    const int32_t nm = nmerged;
+    for (int32_t i = 0; i < nm; i++)
+      for (int32_t f = rl[i]; f < rh[i]; f++) {
+        const int32_t q0 = a.w.qs[f], cn = a.nb.fcnt[f];
+        for (int32_t j = 0; j < cn; j++)
+          if (a.w.part[q0 + j] == s) back(q0 + j);
+      }
   }
+  const int32_t nown = a.nb.fcnt[s];
+  const int32_t q0 = a.w.qs[s];  // the particle's owned contacts
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;

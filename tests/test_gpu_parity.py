@@ -379,8 +379,11 @@ def test_profile_phases_cover_the_step(dem):
 def crowned_sphere(n_small, seed=0):
     """One large sphere touched by n_small small ones spread over its
     surface, all in one cell, the large one last in id (so every contact is
-    one of its backward contacts), with seeded velocities and spins."""
-    R, r = 0.05, 0.01
+    one of its backward contacts), with seeded velocities and spins.  The
+    small radius shrinks with their number so that they do not touch one
+    another (their spacing on the surface is about R sqrt(4 pi / n))."""
+    R = 0.05
+    r = min(0.01, 0.35 * R * math.sqrt(4 * math.pi / n_small))
     c = np.array([0.1, 0.1, 0.1])
     k = np.arange(n_small) + 0.5
     phi = np.arccos(1 - 2 * k / n_small)
@@ -396,9 +399,9 @@ def crowned_sphere(n_small, seed=0):
 
 @pytest.mark.parametrize("n_small,precision", [(6, "fp64"), (20, "fp64"), (20, "mixed"), (32, "mixed")])
 def test_long_backward_lists_sum_in_order(dem, n_small, precision):
-    # a particle with many lower partners: short lists are sorted in
-    # registers, long ones by repeated selection; the sums follow the same
-    # fixed order either way and match the oracle
+    # a particle with many lower partners, found in any order: its sums
+    # follow the fixed order (ascending owner slot), match the oracle, and
+    # stay so over steps
     p, x, v, w, rad = crowned_sphere(n_small, seed=n_small)
     p = dict(p, precision=precision, mu=0.3, eta_t_ratio=0.5)
     g = dem.System(p, x, v, w, rad)
@@ -415,15 +418,18 @@ def test_long_backward_lists_sum_in_order(dem, n_small, precision):
     assert np.abs(sg["x"] - so["x"]).max() <= (1e-12 if precision == "fp64" else 1e-6) * scale
 
 
-def test_backward_list_capacity_is_reported(dem):
-    # one large sphere touched by 60 small ones that all precede it in the
-    # sorted order (it has the highest id): more than the 32 lower partners a
-    # particle may have, which must be reported, not silently dropped
-    n_small = 60
-    p, x, _, _, rad = crowned_sphere(n_small)
-    z = np.zeros_like(x)
-    o = OracleSystem(p, x, z, z, rad)
-    assert len(o.contacts()) == n_small  # the oracle has no such limit
-    with pytest.raises(dem.DemError) as e:
-        dem.System(p, x, z, z, rad)
-    assert e.value.code == dem.DEM_E_CONTACT_OVERFLOW
+@pytest.mark.parametrize("n_small,precision", [(60, "mixed"), (300, "fp64"), (700, "mixed"), (1100, "mixed")])
+def test_many_backward_contacts(dem, n_small, precision):
+    # a particle with more lower partners than a workgroup stages records
+    # for (512) or collects at all (1024, beyond which each lane reads its
+    # owners' contacts itself): every path sums in the same fixed order and
+    # matches the oracle, with no limit on the count
+    p, x, v, w, rad = crowned_sphere(n_small, seed=n_small)
+    p = dict(p, precision=precision, mu=0.3, eta_t_ratio=0.5)
+    g = dem.System(p, x, v, w, rad)
+    o = OracleSystem(p, x, v, w, rad)
+    assert len(o.contacts()) == n_small
+    assert np.array_equal(g.contacts(), o.contacts())
+    F, T, Fa, Ta = o.forces_scale()
+    Fg, Tg = g.forces()
+    assert_forces_close(Fg, Tg, F, T, Fa, Ta, TOL[precision])
