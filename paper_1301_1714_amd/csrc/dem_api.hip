@@ -347,6 +347,8 @@ size_t carve(Engine &e, char *base) {
   e.work.pd = cv.take<double>(PB);
   e.work.part = cv.take<int32_t>(PB);
   e.work.qs = cv.take<int32_t>(N);
+  e.work.back = cv.take<int2>((size_t)B * kBackCap);
+  e.work.nback = cv.take<int32_t>(B);
   e.diag.e_el = cv.take<double>(N);
   e.diag.npair = cv.take<int32_t>(N);
   e.diag.nwall = cv.take<int32_t>(N);
@@ -791,6 +793,8 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   e.cp = 1;
   e.cv = 1;
   e.gc = 0;
+  // no backward contact is filed yet (each gather clears its count)
+  HIP_TRY(launch_fill(e.work.nback, (int64_t)e.bfirst_h.size(), 0, e.stream));
   // Steps 5-6: the contacts of the initial positions
   HIP_TRY(build_contacts(e, nullptr));
   if ((st = sync_and_check(e)) != DEM_OK) return st;

@@ -64,6 +64,7 @@ enum ModeBits : int32_t {
 };
 
 constexpr int32_t kBlock = 256;
+constexpr int32_t kBackCap = 1024;  // backward contacts filed per kernel block (more: found by a scan)
 constexpr int32_t kListCap = 64;  // largest per-particle capacity of owned contacts (higher partners + walls)
 // contact indices k * N + s are int32: n * kListCap must stay below 2^31
 constexpr int64_t kMaxParticles = INT32_MAX / kListCap;
@@ -191,6 +192,9 @@ struct PairWork {
   double *pd;      // per contact overlap (diagnostics)
   int32_t *part;   // per contact: the partner's slot (a wall: its negative key)
   int32_t *qs;     // [N] index of each slot's first owned contact
+  int2 *back;      // [nblocks][kBackCap] per kernel block, the contacts whose partner is
+                   // one of its slots: (contact index, partner slot), in arrival order
+  int32_t *nback;  // [nblocks] their number (zero between evaluations)
 };
 
 struct DiagBuf {

@@ -1407,10 +1407,12 @@ __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, i
 // q of the per-contact arrays: the law of Eqs. 2-10 (or Eq. 1) evaluated
 // once per pair, seen from the owner (the lower slot), stored as the force
 // on the owner and n x F_t; the partner receives the exact negation (its
-// sums find the contact by the partner slot stored with it).  Both
-// particles' inputs come from their packed state records.
+// sums find the contact where it is filed, back[filed], or by the partner
+// slot stored with it).  Both particles' inputs come from their packed
+// state records.
 template <typename Real, int LAW>
-__device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q) {
+__device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q,
+                                            int64_t filed) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
@@ -1418,7 +1420,6 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
-  a.w.part[q] = t;  // the partner side's sums find the contact by this
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
@@ -1510,6 +1511,10 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
     a.w.pe[q] = elastic_energy<Real, BASE>(c, K, delta, R, o, h);
     a.w.pd[q] = (double)delta;
   }
+  // where the partner side's sums find the contact (stored last: the place
+  // was drawn by an atomic whose round trip the loads above overlap)
+  a.w.part[q] = t;
+  if (filed >= 0) a.w.back[filed] = make_int2(q, t);
 }
 
 // The owned contacts of one wave's particles (lane l: slot first + l, cnt
@@ -1535,8 +1540,10 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
   woff[lane] = x - cnt;
   if (lane == 63) woff[64] = total;
   __builtin_amdgcn_wave_barrier();
+  const int32_t s0 = a.L.bfirst[blockIdx.x];
   for (int32_t e0 = 0; e0 < total; e0 += 64) {
     const int32_t e = e0 + lane;
+    int32_t k = 0, s = 0, t = -1, tb = -1;
     if (e < total) {
       int32_t lo = 0, hi = 64;  // woff[lo] <= e < woff[hi]
       while (hi - lo > 1) {
@@ -1546,9 +1553,34 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
         else
           hi = mid;
       }
-      const int32_t k = e - woff[lo], s = first + lo;
-      const int32_t t = (lst && k < kListStage) ? lst[k * stride + lo] : a.nb.nb[(int64_t)k * a.L.n + s];
-      contact_one<Real, LAW>(a, si, s, t, qbase + e);
+      k = e - woff[lo];
+      s = first + lo;
+      t = (lst && k < kListStage) ? lst[k * stride + lo] : a.nb.nb[(int64_t)k * a.L.n + s];
+      // the kernel block whose slots the partner is one of
+      if (t >= 0) tb = (int32_t)blockIdx.x + ((t - s0) >> 8);
+    }
+    // the chunk's contacts filed with their partners' blocks: lanes of one
+    // block form a group, whose first lane draws the group's places with
+    // one atomic
+    uint64_t todo = __ballot(tb >= 0);
+    int32_t lead = 0, rank = 0, size = 0;
+    while (todo) {
+      const int32_t l = __builtin_ctzll(todo);
+      const int32_t b = __builtin_amdgcn_readlane(tb, l);
+      const uint64_t grp = __ballot(tb == b);
+      if (tb == b) {
+        lead = l;
+        rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+        size = __popcll(grp);
+      }
+      todo &= ~grp;
+    }
+    int32_t base = 0;
+    if (tb >= 0 && rank == 0) base = atomicAdd(&a.w.nback[tb], size);
+    base = __shfl(base, lead) + rank;
+    if (e < total) {
+      const int64_t filed = tb >= 0 && base < kBackCap ? (int64_t)tb * kBackCap + base : -1;
+      contact_one<Real, LAW>(a, si, s, t, qbase + e, filed);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1693,27 +1725,23 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
 // call, the next step's opening kick, drift and hash.  The state goes to the
 // other buffers.
 //
-// A particle's backward contacts (those with lower slots,
-// owned and evaluated there) are found without the owners filing them
-// anywhere: each owner swept the forward half of its (2K + 1)^3 cells, so
-// the owners of a particle's backward contacts lie in the mirror half, which
-// in slot order is R = 1 + 2K + 2K^2 runs of cells -- cells cx-K..cx of its
-// own row (the slots below it), cells cx-K..cx+K of rows dy = -K..-1 of its
-// plane and of rows dy = -K..K of planes dz = -K..-1.  A block takes per run
-// the slot range from its first particle's run to its last one's (slots are
-// sorted by cell, so the range covers every particle's run in between),
-// merges the ranges, cuts them where the contact arrays' blocks end into
-// runs of contact indices (the contacts of consecutive owners of one block
-// are contiguous), and reads the stored partner of every contact in them
-// with all lanes busy: a partner inside the block is a hit.  Each particle
-// then sums its hits in ascending contact index, which is ascending owner
-// slot: the order, and so the bits, do not depend on the order in which the
-// hits arrived.
+// A particle's backward contacts (those with lower slots, owned and
+// evaluated there) reach it through its kernel block: the law pass files
+// each contact with the block its partner belongs to (one atomic per group
+// of a wave's contacts with the same block), and the block sorts them to
+// its particles in LDS.  Each particle then sums its own in ascending
+// contact index, which is ascending owner slot: the order, and so the bits,
+// do not depend on the order in which they were filed.  A block filed more
+// than kBackCap of them finds them instead by scanning: each owner swept
+// the forward half of its (2K + 1)^3 cells, so the owners of a particle's
+// backward contacts lie in the mirror half, in slot order R = 1 + 2K + 2K^2
+// runs of cells -- cells cx-K..cx of its own row (the slots below it),
+// cells cx-K..cx+K of rows dy = -K..-1 of its plane and of rows dy = -K..K
+// of planes dz = -K..-1 -- and each lane reads the stored partner of every
+// contact of the owners in the block's merged ranges of those runs.
 
-constexpr int32_t kGatherStage = 512;   // backward records staged in LDS per block
-constexpr int32_t kGatherQueue = 1024;  // backward contacts collected per block (more: each lane scans alone)
+constexpr int32_t kGatherStage = 512;  // backward records staged in LDS per block
 constexpr int32_t kGatherRuns = 1 + 2 * kMaxReach + 2 * kMaxReach * kMaxReach;
-constexpr int32_t kGatherPieces = 64;   // runs of contact indices per block (more: each lane scans alone)
 
 // row offset of backward run h (h = 0: the own row)
 __device__ __forceinline__ void back_row(int32_t h, int32_t K, int32_t &dy, int32_t &dz) {
@@ -1740,20 +1768,19 @@ __device__ __forceinline__ void couple_of(const PairArgs &a, int64_t q, Real C[3
 template <typename Real, bool XT>
 __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   using V2 = typename Vec2T<Real>::type;
-  constexpr int32_t kQueueBytes = kGatherQueue * 5;  // contact index and particle of each hit
+  constexpr int32_t kQueueBytes = kBackCap * 5;  // contact index and particle of each filed contact
   constexpr int32_t kRecBytes = 3 * kGatherStage * (int32_t)sizeof(V2);
-  __shared__ int32_t bo[kBlock + 1];        // each particle's segment of bq
-  __shared__ int32_t bq[kGatherQueue];      // the hits' contact indices, by particle
+  __shared__ int32_t bo[kBlock + 1];    // each particle's segment of bq
+  __shared__ int32_t bq[kBackCap];      // the filed contacts' indices, by particle
   __shared__ int32_t lcnt[kBlock], lfill[kBlock];
-  // first the hits in arrival order, then the staged records
+  // first the filed contacts in arrival order, then the staged records
   __shared__ uint4 lds16[(kQueueBytes > kRecBytes ? kQueueBytes : kRecBytes) / 16 + 1];
   int32_t *hq = (int32_t *)lds16;
-  uint8_t *hp = (uint8_t *)(hq + kGatherQueue);
+  uint8_t *hp = (uint8_t *)(hq + kBackCap);
   V2 *brec = (V2 *)lds16;
-  __shared__ int32_t wlo[1][kGatherRuns], whi[1][kGatherRuns];  // each run's range
-  __shared__ int32_t rl[kGatherRuns], rh[kGatherRuns];  // merged slot ranges
-  __shared__ int32_t pl[kGatherPieces + 1], pn[kGatherPieces + 1], pq[kGatherPieces + 1];
-  __shared__ int32_t nmerged, npiece, nhit;
+  __shared__ int32_t wlo[kGatherRuns], whi[kGatherRuns];  // each run's range (a crowded block)
+  __shared__ int32_t rl[kGatherRuns], rh[kGatherRuns];    // merged
+  __shared__ int32_t nmerged;
   __shared__ int32_t wsum[kBlock / 64];
   int32_t k;
   const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + m), one system
@@ -1763,7 +1790,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   // far as the compiler knows)
   const Consts c = si.c;
   const Grid g = si.g;
-  const int32_t K = si.reach, p0 = si.p0;
+  const int32_t K = si.reach;
   const bool stepping = (a.mode & MODE_KICK) != 0;
   const int32_t step_now = stepping ? *a.ctl.step : 0, left_k = stepping ? a.ctl.left[k] : 0;
   const int32_t N = a.L.n;
@@ -1786,151 +1813,104 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
     a.cell[s] = a.scell[s];
     return;
   }
-  const int32_t nx = g.nc[0], ny = g.nc[1];
-  const int32_t R = 1 + 2 * K + 2 * K * K;
-  // (1) per backward run, the slot range from the block's first particle's
-  // run to its last one's.  A run outside the grid stands for the empty
-  // range where it would lie (the start of the plane for a row below it,
-  // the end of the plane for a row above it, the system's first slot for a
-  // plane below it), so that the run ends grow with the slot and the range
-  // covers the run of every particle in between.
-  if ((int32_t)threadIdx.x < R) {
-    const int32_t h = (int32_t)threadIdx.x;
-    int32_t dy, dz;
-    back_row(h, K, dy, dz);
-    const int32_t *cs = a.cell_start + g.c0;
-    auto run_end = [&](int32_t t, bool start) {
-      const int32_t cc = a.scell[t] - g.c0;
-      const int32_t cx = cc % nx, yy = (cc / nx) % ny + dy, zz = cc / (nx * ny) + dz;
-      if (zz < 0) return cs[0];
-      if (yy < 0) return cs[zz * ny * nx];
-      if (yy >= ny) return cs[(zz + 1) * ny * nx];
-      if (start) return cs[(zz * ny + yy) * nx + max(cx - K, 0)];
-      return h == 0 ? t : cs[(zz * ny + yy) * nx + min(cx + K, nx - 1) + 1];  // own row: owners below it
-    };
-    wlo[0][h] = run_end(s0, true);
-    whi[0][h] = run_end(s0 + mblk - 1, false);
-  }
+  const int32_t nfiled = a.w.nback[blockIdx.x];
+  const bool filed = nfiled <= kBackCap;
   lcnt[threadIdx.x] = 0;
   lfill[threadIdx.x] = 0;
-  if (threadIdx.x == 0) nhit = 0;
-  __syncthreads();
-  // (2) the block's ranges, sorted and merged (one thread: at most 13), and
-  // cut where the contact arrays' blocks end
-  if (threadIdx.x == 0) {
-    int32_t L[kGatherRuns], H[kGatherRuns], n = 0;
-    for (int32_t h = 0; h < R; h++) {
-      const int32_t lo = wlo[0][h], hi = whi[0][h];
-      if (lo >= hi) continue;
-      int32_t i = n++;
-      for (; i > 0 && L[i - 1] > lo; i--) {
-        L[i] = L[i - 1];
-        H[i] = H[i - 1];
-      }
-      L[i] = lo;
-      H[i] = hi;
-    }
-    int32_t nm = 0, np = 0;
-    for (int32_t i = 0; i < n; i++) {
-      if (nm > 0 && L[i] <= rh[nm - 1]) {
-        rh[nm - 1] = max(rh[nm - 1], H[i]);
-      } else {
-        rl[nm] = L[i];
-        rh[nm] = H[i];
-        nm++;
-      }
-    }
-    for (int32_t i = 0; i < nm; i++) {
-      for (int32_t f = rl[i]; f < rh[i];) {
-        const int32_t e = min(rh[i], p0 + ((f - p0) & ~(kBlock - 1)) + kBlock);
-        if (np < kGatherPieces) {
-          pl[np] = f;
-          pn[np] = e;  // slot range [f, e) for now
-        }
-        np++;
-        f = e;
-      }
-    }
-    nmerged = nm;
-    npiece = np;
-  }
-  __syncthreads();
-  const int32_t np = npiece;
-  const bool pieces = np <= kGatherPieces;
-  if (pieces) {
-    // the contact indices of each piece: its owners' contacts are contiguous
-    if (threadIdx.x < 64) {
-      const int32_t lane = (int32_t)threadIdx.x;
-      int32_t q0 = 0, cnt = 0;
-      if (lane < np) {
-        const int32_t f = pl[lane], l = pn[lane] - 1;
-        q0 = a.w.qs[f];
-        cnt = a.w.qs[l] + a.nb.fcnt[l] - q0;
-      }
-      int32_t x = cnt;  // inclusive prefix over the pieces
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int32_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
-      if (lane < np) {
-        pl[lane] = q0;
-        pq[lane] = x - cnt;
-      }
-      if (lane == np - 1) pq[np] = x;
-      if (np == 0 && lane == 0) pq[0] = 0;
+  if (!filed) {
+    // (a crowded block) per backward run, the slot range from the block's
+    // first particle's run to its last one's.  A run outside the grid
+    // stands for the empty range where it would lie (the start of the plane
+    // for a row below it, the end of the plane for a row above it, the
+    // system's first slot for a plane below it), so that the run ends grow
+    // with the slot and the range covers the run of every particle in
+    // between.
+    const int32_t nx = g.nc[0], ny = g.nc[1];
+    const int32_t R = 1 + 2 * K + 2 * K * K;
+    if ((int32_t)threadIdx.x < R) {
+      const int32_t h = (int32_t)threadIdx.x;
+      int32_t dy, dz;
+      back_row(h, K, dy, dz);
+      const int32_t *cs = a.cell_start + g.c0;
+      auto run_end = [&](int32_t t, bool start) {
+        const int32_t cc = a.scell[t] - g.c0;
+        const int32_t cx = cc % nx, yy = (cc / nx) % ny + dy, zz = cc / (nx * ny) + dz;
+        if (zz < 0) return cs[0];
+        if (yy < 0) return cs[zz * ny * nx];
+        if (yy >= ny) return cs[(zz + 1) * ny * nx];
+        if (start) return cs[(zz * ny + yy) * nx + max(cx - K, 0)];
+        return h == 0 ? t : cs[(zz * ny + yy) * nx + min(cx + K, nx - 1) + 1];  // own row: owners below it
+      };
+      wlo[h] = run_end(s0, true);
+      whi[h] = run_end(s0 + mblk - 1, false);
     }
     __syncthreads();
-    // (3) every contact of the pieces, one lane each: a partner in the block
-    // is a hit, queued with its particle
-    // (four per lane at a time, so that their loads are in flight together)
-    const int32_t E = pq[np];
-    int32_t pi = 0;  // the piece of the lane's entry (its entries only grow)
-    for (int32_t e0 = threadIdx.x; e0 < E; e0 += 4 * kBlock) {
-      int32_t q[4], t[4];
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int32_t e = e0 + u * kBlock;
-        q[u] = -1;
-        if (e < E) {
-          while (pq[pi + 1] <= e) pi++;
-          q[u] = pl[pi] + e - pq[pi];
+    // the ranges sorted and merged (one thread: at most 13)
+    if (threadIdx.x == 0) {
+      int32_t L[kGatherRuns], H[kGatherRuns], n = 0;
+      for (int32_t h = 0; h < R; h++) {
+        const int32_t lo = wlo[h], hi = whi[h];
+        if (lo >= hi) continue;
+        int32_t i = n++;
+        for (; i > 0 && L[i - 1] > lo; i--) {
+          L[i] = L[i - 1];
+          H[i] = H[i - 1];
+        }
+        L[i] = lo;
+        H[i] = hi;
+      }
+      int32_t nm = 0;
+      for (int32_t i = 0; i < n; i++) {
+        if (nm > 0 && L[i] <= rh[nm - 1]) {
+          rh[nm - 1] = max(rh[nm - 1], H[i]);
+        } else {
+          rl[nm] = L[i];
+          rh[nm] = H[i];
+          nm++;
         }
       }
-#pragma unroll
-      for (int u = 0; u < 4; u++) t[u] = q[u] >= 0 ? a.w.part[q[u]] : -1;
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        if (q[u] >= 0 && (uint32_t)(t[u] - s0) < (uint32_t)mblk) {
-          const int32_t p = t[u] - s0;
-          atomicAdd(&lcnt[p], 1);
-          const int32_t slot = atomicAdd(&nhit, 1);
-          if (slot < kGatherQueue) {
-            hq[slot] = q[u];
-            hp[slot] = (uint8_t)p;
-          }
-        }
+      nmerged = nm;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.w.nback[blockIdx.x] = 0;  // ready for the next evaluation's filing
+  if (filed) {
+    // the filed contacts, counted per particle
+    const int2 *fb = a.w.back + (int64_t)blockIdx.x * kBackCap;
+    for (int32_t e = threadIdx.x; e < nfiled; e += kBlock) {
+      const int2 f = fb[e];
+      const int32_t p = f.y - s0;
+      if ((uint32_t)p < (uint32_t)mblk) {  // always (the block of the partner)
+        atomicAdd(&lcnt[p], 1);
+        hq[e] = f.x;
+        hp[e] = (uint8_t)p;
+      } else {
+        hp[e] = 0;
+        hq[e] = -1;
       }
     }
   }
   __syncthreads();
-  const int32_t B = pieces ? nhit : INT32_MAX;
-  const bool queued = B <= kGatherQueue, staged = B <= kGatherStage;
+  const int32_t B = filed ? nfiled : INT32_MAX;
+  const bool queued = filed, staged = B <= kGatherStage;
   const int32_t nbk = queued && s >= 0 ? lcnt[threadIdx.x] : 0;
   if (queued) {
-    // (4) the hits by particle (in any order within a particle), then
+    // (4) the contacts by particle (in any order within a particle), then
     // their records into LDS with every lane on one
     int32_t tot;
     const int32_t off = block_exclusive_scan(nbk, wsum, tot);
     bo[threadIdx.x] = off;
     __syncthreads();
     for (int32_t e = threadIdx.x; e < B; e += kBlock) {
-      const int32_t p = hp[e];
-      bq[bo[p] + atomicAdd(&lfill[p], 1)] = hq[e];
+      const int32_t q = hq[e];
+      if (q >= 0) {
+        const int32_t p = hp[e];
+        bq[bo[p] + atomicAdd(&lfill[p], 1)] = q;
+      }
     }
     __syncthreads();
     if (staged) {
-      for (int32_t e = threadIdx.x; e < B; e += kBlock) {
+      for (int32_t e = threadIdx.x; e < tot; e += kBlock) {
         const V2 *p = (const V2 *)a.w.pf + 3 * (int64_t)bq[e];
         brec[3 * e] = p[0];
         brec[3 * e + 1] = p[1];
