@@ -102,21 +102,23 @@ def contacts_bytes(n, ncell, P, R):
     """k_contacts_direct (detection and the contact law in one pass): per
     particle its 8-byte fixed-point candidate record, its packed state (x
     24 B, v and w 6R, r, id, previous slot and history count 16 B) and cell
-    (4 B) read, its contact count and history count (4 B each) written; per
-    owned contact (P of them, pairs once plus walls) the list entry (4 B),
-    the committed history entry read (key 4 B, delta_t 3R), the new one
-    written (4 + 3R), the force record written (6R) and the backward-list
-    entry with its count (8 B); the cell starts read once.  Partner records
-    and neighbouring candidate records are reuse."""
-    return n * (60 + 6 * R) + P * (20 + 12 * R) + 4 * (ncell + 1)
+    (4 B) read, its contact count, history count and first contact index
+    (4 B each) written; per owned contact (P of them, pairs once plus walls)
+    the list entry (4 B), the committed history entry read (key 4 B, delta_t
+    3R), the new one written (4 + 3R), the force record written (6R), the
+    partner slot (4 B) and the entry filed with the partner's workgroup (8 B;
+    its count's atomic is one per group of a wave's contacts and not
+    counted); the cell starts read once.  Partner records and neighbouring
+    candidate records are reuse."""
+    return n * (64 + 6 * R) + P * (24 + 12 * R) + 4 * (ncell + 1)
 
 
 def gather_bytes(n, P, R):
-    """k_gather: per particle its packed state (40 + 6R), backward count read
-    and cleared (8 B) and contact count (4 B), the state written back (x
-    24 B, r 4, id 4, v and w 6R, cell 4); per contact the force record read
-    by the owner and by the partner (2 x 6R) and the backward entry (4 B)."""
-    return n * (88 + 12 * R) + P * (4 + 12 * R)
+    """k_gather: per particle its packed state (40 + 6R), contact count and
+    first contact index (4 B each), the state written back (x 24 B, r 4, id
+    4, v and w 6R, cell 4); per contact the force record read by the owner
+    and by the partner (2 x 6R) and the filed entry (8 B)."""
+    return n * (84 + 12 * R) + P * (8 + 12 * R)
 
 
 def step_algorithmic_bytes(n, z, R):

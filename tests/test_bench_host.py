@@ -21,13 +21,14 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_byte_models():
-    # detection + law: per sphere candidate record 8, packed state 40 + 6R, cell 4, two counts 8;
-    # per contact list entry 4, history read and written 2 (4 + 3R), force record 6R,
-    # backward entry and count 8; cell starts once
-    assert bench.contacts_bytes(10, 7, 20, 4) == 10 * (8 + 64 + 4 + 8) + 20 * (4 + 32 + 24 + 8) + 4 * 8
-    assert bench.contacts_bytes(10, 7, 20, 8) == 10 * (8 + 88 + 4 + 8) + 20 * (4 + 56 + 48 + 8) + 4 * 8
-    # gather: per sphere state in 40 + 6R and out 36 + 6R, counts 12; per contact two record reads and an entry
-    assert bench.gather_bytes(10, 20, 4) == 10 * (64 + 60 + 12) + 20 * (48 + 4)
+    # detection + law: per sphere candidate record 8, packed state 40 + 6R, cell 4, two counts and the
+    # first contact index 12; per contact list entry 4, history read and written 2 (4 + 3R), force
+    # record 6R, partner slot 4 and filed entry 8; cell starts once
+    assert bench.contacts_bytes(10, 7, 20, 4) == 10 * (8 + 64 + 4 + 12) + 20 * (4 + 32 + 24 + 4 + 8) + 4 * 8
+    assert bench.contacts_bytes(10, 7, 20, 8) == 10 * (8 + 88 + 4 + 12) + 20 * (4 + 56 + 48 + 4 + 8) + 4 * 8
+    # gather: per sphere state in 40 + 6R and out 36 + 6R, count and first index 8; per contact two record
+    # reads and the filed entry
+    assert bench.gather_bytes(10, 20, 4) == 10 * (64 + 60 + 8) + 20 * (48 + 8)
     # whole step: B = 2 state + 16 + 3 + Z (4 + 3R); 131 + 16 Z bytes in mixed precision
     assert bench.step_algorithmic_bytes(1, 0.0, 4) == 131
     assert bench.step_algorithmic_bytes(1, 6.0, 4) == pytest.approx(131 + 16 * 6)
