@@ -708,6 +708,7 @@ __device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf
   int32_t beg[R], end[R], shift[R];
   using Rec = typename Rows::Rec;
   constexpr int kU = Rows::kUnroll;
+  static_assert(32 % kU == 0, "a chunk's candidates must fill at most the 32 bits of its mask");
 #pragma unroll
   for (int h = 0; h < R; h++) {
     const int dyr = h <= K ? h : (h - K - 1) % (2 * K + 1) - K;
@@ -732,39 +733,46 @@ __device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf
   for (int h = 0; h < R; h++) {
     const int32_t e = end[h], sh = shift[h];
     int32_t t = beg[h];
-    if (t < e) {
-      // software pipeline: the next kU candidates are in flight while the
-      // current ones are tested (the fetch clamps at the range's last
-      // candidate, so it needs no branch); a candidate that passes is
-      // parked in the lane's LDS slots by an unconditional store and a
-      // conditional count, so the loop body has no branch either; the exact
-      // tests (global loads) stay outside the loop
-      // two register sets take turns (no copy between them, which would
-      // wait for the load in flight)
+    // chunks of up to 32 candidates: each candidate's test result is
+    // shifted into a bit mask (one add with carry, no branch and no store
+    // in the loop), while the next kU candidates are in flight (two
+    // register sets take turns; the fetch clamps at the chunk's last
+    // candidate); the survivors are then taken from the mask in ascending
+    // order and parked in the lane's LDS slots, and decided exactly in FP64
+    // (global loads) outside the candidate loop
+    while (t < e) {
+      const int32_t t0 = t, tc = min(e, t0 + 32);
+      uint32_t mask = 0;
       auto test = [&](const Rec (&q)[kU]) {
 #pragma unroll
         for (int u = 0; u < kU; u++) {
-          const bool pass = (t + u < e) & near(q[u]);
-          surv[ns * kLanes] = t + u;
-          ns += pass ? 1 : 0;
+          const bool pass = (t + u < tc) & near(q[u]);
+          mask = mask + mask + (pass ? 1u : 0u);
         }
         t += kU;
-        if (ns > kSurv - kU) {
+      };
+      Rec qa[kU], qb[kU];
+      rows.fetch(qa, t, tc, sh);
+      for (;;) {
+        rows.fetch(qb, t + kU, tc, sh);
+        test(qa);
+        if (t >= tc) break;
+        rows.fetch(qa, t + kU, tc, sh);
+        test(qb);
+        if (t >= tc) break;
+      }
+      const int32_t top = t - t0 - 1;  // candidate t0 + j sits at bit top - j
+      while (mask) {
+        const int32_t b = 31 - __builtin_clz(mask);
+        mask &= ~(1u << b);
+        surv[ns * kLanes] = t0 + top - b;
+        if (++ns == kSurv) {
           for (int32_t j = 0; j < ns; j++)
             exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
           ns = 0;
         }
-      };
-      Rec qa[kU], qb[kU];
-      rows.fetch(qa, t, e, sh);
-      for (;;) {
-        rows.fetch(qb, t + kU, e, sh);
-        test(qa);
-        if (t >= e) break;
-        rows.fetch(qa, t + kU, e, sh);
-        test(qb);
-        if (t >= e) break;
       }
+      t = tc;
     }
   }
   for (int32_t j = 0; j < ns; j++)
@@ -791,7 +799,7 @@ __device__ __forceinline__ uint4 load_two(const uint2 *p) {
 
 struct DirectRows {
   using Rec = uint2;
-  static constexpr int kUnroll = 2;  // candidates per pipeline stage (even)
+  static constexpr int kUnroll = 4;  // candidates per pipeline stage (even)
   const uint2 *src;                  // [N + 1]: the last record pads the pair loads
   const int32_t *cell_start;
   int32_t c0, nx, ny, nz, cy, cz;
