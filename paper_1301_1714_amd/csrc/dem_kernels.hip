@@ -799,7 +799,7 @@ __device__ __forceinline__ uint4 load_two(const uint2 *p) {
 
 struct DirectRows {
   using Rec = uint2;
-  static constexpr int kUnroll = 4;  // candidates per pipeline stage (even)
+  static constexpr int kUnroll = 8;  // candidates per pipeline stage (even)
   const uint2 *src;                  // [N + 1]: the last record pads the pair loads
   const int32_t *cell_start;
   int32_t c0, nx, ny, nz, cy, cz;
