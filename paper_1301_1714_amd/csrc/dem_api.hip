@@ -345,7 +345,6 @@ size_t carve(Engine &e, char *base) {
   e.work.pc = e.has_terms ? cv.take_bytes(4 * R * PB) : nullptr;
   e.work.pe = cv.take<double>(PB);
   e.work.pd = cv.take<double>(PB);
-  e.work.part = cv.take<int32_t>(PB);
   e.work.qs = cv.take<int32_t>(N);
   e.work.back = cv.take<int2>((size_t)B * kBackCap);
   e.work.nback = cv.take<int32_t>(B);

@@ -190,7 +190,6 @@ struct PairWork {
   void *pc;        // per contact Real4: the couple of the optional terms on the owner (engines with terms only)
   double *pe;      // per contact elastic energy (diagnostics)
   double *pd;      // per contact overlap (diagnostics)
-  int32_t *part;   // per contact: the partner's slot (a wall: its negative key)
   int32_t *qs;     // [N] index of each slot's first owned contact
   int2 *back;      // [nblocks][kBackCap] per kernel block, the contacts whose partner is
                    // one of its slots: (contact index, partner slot), in arrival order

@@ -1415,8 +1415,8 @@ __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, i
 // q of the per-contact arrays: the law of Eqs. 2-10 (or Eq. 1) evaluated
 // once per pair, seen from the owner (the lower slot), stored as the force
 // on the owner and n x F_t; the partner receives the exact negation (its
-// sums find the contact where it is filed, back[filed], or by the partner
-// slot stored with it).  Both particles' inputs come from their packed
+// sums find the contact where it is filed, back[filed], or in the owner's
+// list).  Both particles' inputs come from their packed
 // state records.
 template <typename Real, int LAW>
 __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q,
@@ -1521,7 +1521,6 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   }
   // where the partner side's sums find the contact (stored last: the place
   // was drawn by an atomic whose round trip the loads above overlap)
-  a.w.part[q] = t;
   if (filed >= 0) a.w.back[filed] = make_int2(q, t);
 }
 
@@ -1745,8 +1744,8 @@ __device__ __forceinline__ void drift_hash_to(double x0, double y0, double z0, c
 // backward contacts lie in the mirror half, in slot order R = 1 + 2K + 2K^2
 // runs of cells -- cells cx-K..cx of its own row (the slots below it),
 // cells cx-K..cx+K of rows dy = -K..-1 of its plane and of rows dy = -K..K
-// of planes dz = -K..-1 -- and each lane reads the stored partner of every
-// contact of the owners in the block's merged ranges of those runs.
+// of planes dz = -K..-1 -- and each lane reads the list of every owner in
+// the block's merged ranges of those runs.
 
 constexpr int32_t kGatherStage = 512;  // backward records staged in LDS per block
 constexpr int32_t kGatherRuns = 1 + 2 * kMaxReach + 2 * kMaxReach * kMaxReach;
@@ -1991,7 +1990,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
       for (int32_t f = rl[i]; f < rh[i]; f++) {
         const int32_t q0 = a.w.qs[f], cn = a.nb.fcnt[f];
         for (int32_t j = 0; j < cn; j++)
-          if (a.w.part[q0 + j] == s) back(q0 + j);
+          if (a.nb.nb[(int64_t)j * N + f] == s) back(q0 + j);
       }
   }
   const int32_t nown = a.nb.fcnt[s];
