@@ -340,13 +340,41 @@ constexpr int32_t kCanonSerial = 32;
 constexpr int32_t kCanonChunk = 4096;  // cells scanned per workgroup by k_canon_big
 constexpr int32_t kCanonIds = 1024;    // ids staged in LDS per round of k_canon_big
 
+constexpr int32_t kCanonReg = 8;  // cells up to this size are sorted in registers
+
 __global__ __launch_bounds__(kBlock) void k_canon(const int32_t *__restrict__ cell_start,
                                                   const int32_t *__restrict__ id_old, int32_t *perm,
                                                   int64_t ncell) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (c >= ncell) return;
-  const int32_t beg = cell_start[c], end = cell_start[c + 1];
-  if (end - beg > kCanonSerial) return;  // a crowded cell: k_canon_big
+  const int32_t beg = cell_start[c], end = cell_start[c + 1], n = end - beg;
+  if (n <= 1 || n > kCanonSerial) return;  // nothing to order, or a crowded cell: k_canon_big
+  if (n <= kCanonReg) {
+    // the cell's entries and their ids loaded together (two rounds of
+    // loads, not one per step of an insertion), ordered by a sorting
+    // network (odd-even transposition) in registers
+    int32_t P[kCanonReg], I[kCanonReg];
+#pragma unroll
+    for (int i = 0; i < kCanonReg; i++) P[i] = i < n ? perm[beg + i] : 0;
+#pragma unroll
+    for (int i = 0; i < kCanonReg; i++) I[i] = i < n ? id_old[P[i]] : INT32_MAX;
+#pragma unroll
+    for (int r = 0; r < kCanonReg; r++) {
+#pragma unroll
+      for (int i = r & 1; i + 1 < kCanonReg; i += 2) {
+        const bool sw = I[i] > I[i + 1];
+        const int32_t a0 = I[i], a1 = I[i + 1], b0 = P[i], b1 = P[i + 1];
+        I[i] = sw ? a1 : a0;
+        I[i + 1] = sw ? a0 : a1;
+        P[i] = sw ? b1 : b0;
+        P[i + 1] = sw ? b0 : b1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kCanonReg; i++)
+      if (i < n) perm[beg + i] = P[i];
+    return;
+  }
   for (int32_t k = beg + 1; k < end; k++) {
     const int32_t pk = perm[k];
     const int32_t key = id_old[pk];
