@@ -1382,13 +1382,16 @@ __device__ __forceinline__ double elastic_energy(const Consts &c, const PairK &K
 // committed tangential displacement of the contact with history key `key`
 // among the c entries from index q0 of the committed table (zero for a new
 // contact)
+// committed entries of a slot requested together
+constexpr int kHistBatch = 4;
+
 template <typename Real>
 __device__ __forceinline__ void hist_find(const HistGen &old, int32_t q0, int32_t c, int32_t key, Real h[3]) {
   using V4 = typename Vec4T<Real>::type;
   h[0] = h[1] = h[2] = 0;
   // the entries are adjacent: up to four are requested together, then
   // matched (a lookup waits for one round trip instead of one per entry)
-  constexpr int kBatch = 4;
+  constexpr int kBatch = kHistBatch;
   for (int32_t k0 = 0; k0 < c; k0 += kBatch) {
     V4 d[kBatch];
 #pragma unroll
@@ -1408,34 +1411,63 @@ __device__ __forceinline__ void hist_find(const HistGen &old, int32_t q0, int32_
   }
 }
 
+// the first kHistBatch committed entries of a slot, requested together
+template <typename Real>
+struct HistPre {
+  typename Vec4T<Real>::type d[kHistBatch];
+};
+template <typename Real>
+__device__ __forceinline__ HistPre<Real> hist_prefetch(const HistGen &old, int32_t q0, int32_t c) {
+  using V4 = typename Vec4T<Real>::type;
+  HistPre<Real> p;
+#pragma unroll
+  for (int j = 0; j < kHistBatch; j++)
+    if (j < c) p.d[j] = ((const V4 *)old.ent)[(int64_t)q0 + j];
+  return p;
+}
+// hist_find with the first batch already requested
+template <typename Real>
+__device__ __forceinline__ void hist_find_pre(const HistGen &old, const HistPre<Real> &p, int32_t q0, int32_t c,
+                                              int32_t key, Real h[3]) {
+  h[0] = h[1] = h[2] = 0;
+  bool found = false;
+#pragma unroll
+  for (int j = 0; j < kHistBatch; j++) {
+    if (!found && j < c && entry_key(p.d[j].w) == key) {
+      h[0] = p.d[j].x;
+      h[1] = p.d[j].y;
+      h[2] = p.d[j].z;
+      found = true;
+    }
+  }
+  if (!found && c > kHistBatch) hist_find<Real>(old, q0 + kHistBatch, c - kHistBatch, key, h);
+}
+
+
 // where a slot's committed history is: its previous slot, the number of its
 // entries and the index of the first
 struct HistAt {
   int32_t prev, cnt, q0;
 };
 
-// Committed delta_t of a contact, seen from its current owner (lower slot).
-// ho, hp: where the committed history of the owner and of the partner is.
-// The previous step filed the contact under the lower of the two previous
-// slots, seen from there, keyed by the other one.
-template <typename Real>
-__device__ __forceinline__ void pair_history(const HistGen &old, const HistAt &ho, const HistAt &hp, Real h[3]) {
-  const bool kept = ho.prev < hp.prev;  // the owner was the lower slot then too
-  if (kept) {
-    hist_find<Real>(old, ho.q0, ho.cnt, hp.prev, h);
-  } else {
-    hist_find<Real>(old, hp.q0, hp.cnt, ho.prev, h);
-    h[0] = -h[0];
-    h[1] = -h[1];
-    h[2] = -h[2];
-  }
-}
-
 // where the committed history of slot s (packed record ps) is: recorded in
 // the record in a time step, the slot's own otherwise
 template <typename Real>
 __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, int32_t s, const PState<Real> &ps) {
   if (old_perm) return HistAt{(int32_t)(ps.hp & ((1u << kPrevBits) - 1)), (int32_t)(ps.hp >> kPrevBits), ps.hq};
+  return HistAt{s, min(max(a.old.cnt[s], 0), a.nb.K), a.old.start[s]};
+}
+
+// a lane's own particle's committed history location (passed to the lanes
+// of its contacts; none for the simple law or a lane without a particle)
+template <typename Real, int LAW>
+__device__ __forceinline__ HistAt owner_history(const PairArgs &a, int32_t s) {
+  if (LAW == DEM_LAW_SIMPLE || s < 0) return HistAt{0, 0, 0};
+  const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
+  if (old_perm) {
+    const PState<Real> &ps = ((const PState<Real> *)a.nb.pst)[s];
+    return HistAt{(int32_t)(ps.hp & ((1u << kPrevBits) - 1)), (int32_t)(ps.hp >> kPrevBits), ps.hq};
+  }
   return HistAt{s, min(max(a.old.cnt[s], 0), a.nb.K), a.old.start[s]};
 }
 
@@ -1448,7 +1480,7 @@ __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, i
 // state records.
 template <typename Real, int LAW>
 __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q,
-                                            int64_t filed) {
+                                            int64_t filed, const HistAt &hs) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
@@ -1456,15 +1488,28 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
+  // the owner's committed entries are requested with the records (the
+  // owner's lane passed where they are): the contact is filed there unless
+  // the pair's order changed
+  HistPre<Real> pre;
+  if (LAW != DEM_LAW_SIMPLE) pre = hist_prefetch<Real>(a.old, hs.q0, hs.cnt);
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
   if (LAW != DEM_LAW_SIMPLE) {
-    const HistAt hs = hist_index(a, old_perm, s, me);
-    if (t >= 0)
-      pair_history<Real>(a.old, hs, hist_index(a, old_perm, t, pt), h);
-    else
-      hist_find<Real>(a.old, hs.q0, hs.cnt, t, h);
+    if (t >= 0) {
+      const HistAt hp = hist_index(a, old_perm, t, pt);
+      if (hs.prev < hp.prev) {  // the owner was the lower slot then too
+        hist_find_pre<Real>(a.old, pre, hs.q0, hs.cnt, hp.prev, h);
+      } else {
+        hist_find<Real>(a.old, hp.q0, hp.cnt, hs.prev, h);
+        h[0] = -h[0];
+        h[1] = -h[1];
+        h[2] = -h[2];
+      }
+    } else {
+      hist_find_pre<Real>(a.old, pre, hs.q0, hs.cnt, t, h);
+    }
   }
   // the constants of the pair's materials (a wall is of the system's wall
   // material), or the system's one material
@@ -1563,7 +1608,8 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
 // wave must call it.
 template <typename Real, int LAW>
 __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, int32_t first, int32_t cnt,
-                                         const int32_t *lst, int32_t stride, int32_t *woff, int32_t qbase) {
+                                         const int32_t *lst, int32_t stride, int32_t *woff, int32_t qbase,
+                                         const HistAt &own) {
   const int32_t lane = (int32_t)(threadIdx.x & 63);
   int32_t x = cnt;
 #pragma unroll
@@ -1578,9 +1624,9 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
   const int32_t s0 = a.L.bfirst[blockIdx.x];
   for (int32_t e0 = 0; e0 < total; e0 += 64) {
     const int32_t e = e0 + lane;
-    int32_t k = 0, s = 0, t = -1, tb = -1;
+    int32_t k = 0, s = 0, t = -1, tb = -1, lo = 0;
     if (e < total) {
-      int32_t lo = 0, hi = 64;  // woff[lo] <= e < woff[hi]
+      int32_t hi = 64;  // woff[lo] <= e < woff[hi]
       while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
         if (woff[mid] <= e)
@@ -1613,9 +1659,11 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
     int32_t base = 0;
     if (tb >= 0 && rank == 0) base = atomicAdd(&a.w.nback[tb], size);
     base = __shfl(base, lead) + rank;
+    // the owner's committed history location, from the owner's lane
+    const HistAt ho{__shfl(own.prev, lo), __shfl(own.cnt, lo), __shfl(own.q0, lo)};
     if (e < total) {
       const int64_t filed = tb >= 0 && base < kBackCap ? (int64_t)tb * kBackCap + base : -1;
-      contact_one<Real, LAW>(a, si, s, t, qbase + e, filed);
+      contact_one<Real, LAW>(a, si, s, t, qbase + e, filed, ho);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -1707,8 +1755,9 @@ __global__ __launch_bounds__(kBlock) void k_contacts_direct(Layout L, StepCtl ct
   set_hist_count<LAW>(a, s, cnt, q0);
   if (s >= 0) a.w.qs[s] = q0;
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
+  const HistAt own = owner_history<Real, LAW>(a, s);
   law_wave<Real, LAW>(a, si, L.bfirst[blockIdx.x] + wave * 64, cnt, lst_all + wave * 64, kBlock, woff_all[wave],
-                      __shfl(q0, 0));
+                      __shfl(q0, 0), own);
 }
 
 // The law pass of the systems swept by the wave and tiled shapes (their
@@ -1732,7 +1781,9 @@ __global__ __launch_bounds__(kBlock) void k_contact_law(PairArgs a, int32_t only
   set_hist_count<LAW>(a, s, cnt, q0);
   if (s >= 0) a.w.qs[s] = q0;
   const int32_t wave = (int32_t)(threadIdx.x >> 6);
-  law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave], __shfl(q0, 0));
+  const HistAt own = owner_history<Real, LAW>(a, s);
+  law_wave<Real, LAW>(a, si, a.L.bfirst[blockIdx.x] + wave * 64, cnt, nullptr, 0, woff_all[wave], __shfl(q0, 0),
+                      own);
 }
 
 // Step 1 drift x += dt v and Step 2 hash of the new position, written to
