@@ -1411,39 +1411,6 @@ __device__ __forceinline__ void hist_find(const HistGen &old, int32_t q0, int32_
   }
 }
 
-// the first kHistBatch committed entries of a slot, requested together
-template <typename Real>
-struct HistPre {
-  typename Vec4T<Real>::type d[kHistBatch];
-};
-template <typename Real>
-__device__ __forceinline__ HistPre<Real> hist_prefetch(const HistGen &old, int32_t q0, int32_t c) {
-  using V4 = typename Vec4T<Real>::type;
-  HistPre<Real> p;
-#pragma unroll
-  for (int j = 0; j < kHistBatch; j++)
-    if (j < c) p.d[j] = ((const V4 *)old.ent)[(int64_t)q0 + j];
-  return p;
-}
-// hist_find with the first batch already requested
-template <typename Real>
-__device__ __forceinline__ void hist_find_pre(const HistGen &old, const HistPre<Real> &p, int32_t q0, int32_t c,
-                                              int32_t key, Real h[3]) {
-  h[0] = h[1] = h[2] = 0;
-  bool found = false;
-#pragma unroll
-  for (int j = 0; j < kHistBatch; j++) {
-    if (!found && j < c && entry_key(p.d[j].w) == key) {
-      h[0] = p.d[j].x;
-      h[1] = p.d[j].y;
-      h[2] = p.d[j].z;
-      found = true;
-    }
-  }
-  if (!found && c > kHistBatch) hist_find<Real>(old, q0 + kHistBatch, c - kHistBatch, key, h);
-}
-
-
 // where a slot's committed history is: its previous slot, the number of its
 // entries and the index of the first
 struct HistAt {
@@ -1471,16 +1438,16 @@ __device__ __forceinline__ HistAt owner_history(const PairArgs &a, int32_t s) {
   return HistAt{s, min(max(a.old.cnt[s], 0), a.nb.K), a.old.start[s]};
 }
 
-// Owned contact k of slot s (partner t, a slot or -1 - w), stored at index
+// Owned contact kr of slot s (partner t, a slot or -1 - w), stored at index
 // q of the per-contact arrays: the law of Eqs. 2-10 (or Eq. 1) evaluated
 // once per pair, seen from the owner (the lower slot), stored as the force
 // on the owner and n x F_t; the partner receives the exact negation (its
 // sums find the contact where it is filed, back[filed], or in the owner's
-// list).  Both particles' inputs come from their packed
-// state records.
+// list).  Both particles' inputs come from their packed state records; hs
+// says where the owner's committed history is.
 template <typename Real, int LAW>
 __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si, int32_t s, int32_t t, int32_t q,
-                                            int64_t filed, const HistAt &hs) {
+                                            int64_t filed, const HistAt &hs, int32_t kr) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
@@ -1488,11 +1455,14 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
   const bool diag = (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
-  // the owner's committed entries are requested with the records (the
-  // owner's lane passed where they are): the contact is filed there unless
-  // the pair's order changed
-  HistPre<Real> pre;
-  if (LAW != DEM_LAW_SIMPLE) pre = hist_prefetch<Real>(a.old, hs.q0, hs.cnt);
+  // the owner's committed entry at the contact's own rank kr in the
+  // owner's list is requested with the records (the owner's lane passed
+  // where the owner's entries are): the previous step filed the contact
+  // there unless the pair's order changed or a contact before it came or
+  // went, in which case the owner's or the partner's entries are searched
+  using V4 = typename Vec4T<Real>::type;
+  V4 pre;
+  if (LAW != DEM_LAW_SIMPLE && hs.cnt > 0) pre = ((const V4 *)a.old.ent)[(int64_t)hs.q0 + min(kr, hs.cnt - 1)];
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
   Real h[3] = {0, 0, 0};
@@ -1500,7 +1470,13 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
     if (t >= 0) {
       const HistAt hp = hist_index(a, old_perm, t, pt);
       if (hs.prev < hp.prev) {  // the owner was the lower slot then too
-        hist_find_pre<Real>(a.old, pre, hs.q0, hs.cnt, hp.prev, h);
+        if (hs.cnt > 0 && entry_key(pre.w) == hp.prev) {
+          h[0] = pre.x;
+          h[1] = pre.y;
+          h[2] = pre.z;
+        } else {
+          hist_find<Real>(a.old, hs.q0, hs.cnt, hp.prev, h);
+        }
       } else {
         hist_find<Real>(a.old, hp.q0, hp.cnt, hs.prev, h);
         h[0] = -h[0];
@@ -1508,7 +1484,13 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
         h[2] = -h[2];
       }
     } else {
-      hist_find_pre<Real>(a.old, pre, hs.q0, hs.cnt, t, h);
+      if (hs.cnt > 0 && entry_key(pre.w) == t) {
+        h[0] = pre.x;
+        h[1] = pre.y;
+        h[2] = pre.z;
+      } else {
+        hist_find<Real>(a.old, hs.q0, hs.cnt, t, h);
+      }
     }
   }
   // the constants of the pair's materials (a wall is of the system's wall
@@ -1663,7 +1645,7 @@ __device__ __forceinline__ void law_wave(const PairArgs &a, const SysInfo &si, i
     const HistAt ho{__shfl(own.prev, lo), __shfl(own.cnt, lo), __shfl(own.q0, lo)};
     if (e < total) {
       const int64_t filed = tb >= 0 && base < kBackCap ? (int64_t)tb * kBackCap + base : -1;
-      contact_one<Real, LAW>(a, si, s, t, qbase + e, filed, ho);
+      contact_one<Real, LAW>(a, si, s, t, qbase + e, filed, ho, k);
     }
   }
   __builtin_amdgcn_wave_barrier();
