@@ -530,12 +530,12 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Layout L, PosBuf src, VelBuf
   // the candidate records are formed ahead of every store, so that the
   // system's grid is read with scalar loads (a store may alias it as far as
   // the compiler knows); the FP32 copies are candidates only of the tiled
-  // detection shape
+  // detection shape, written for the systems that use it
   const uint2 xq = make_xq(si, ps.x, ps.y, ps.z, ps.r);
   const float4 xyzr = make_xyzr(si.g, ps.x, ps.y, ps.z, ps.r);
   const int32_t cp = cell[p];
   ((PState<Real> *)stage)[threadIdx.x] = ps;
-  if (L.ntiles > 0) nb.xyzr[s] = xyzr;
+  if (si.tile > 0) nb.xyzr[s] = xyzr;
   nb.xq[s] = xq;
   scell[s] = cp;
   if (soa) {
