@@ -418,7 +418,8 @@ def test_long_backward_lists_sum_in_order(dem, n_small, precision):
     assert np.abs(sg["x"] - so["x"]).max() <= (1e-12 if precision == "fp64" else 1e-6) * scale
 
 
-@pytest.mark.parametrize("n_small,precision", [(60, "mixed"), (300, "fp64"), (700, "mixed"), (1100, "mixed")])
+@pytest.mark.parametrize("n_small,precision", [(60, "mixed"), (300, "fp64"), (700, "mixed"), (1100, "mixed"),
+                                             (1100, "fp64")])
 def test_many_backward_contacts(dem, n_small, precision):
     # a particle with more lower partners than a workgroup stages records
     # for (512) or collects at all (1024, beyond which each lane reads its
