@@ -60,6 +60,7 @@ struct Engine {
   void *F[3], *T[3], *Fe[3], *Te[3];
   int32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *scell = nullptr, *counts = nullptr,
           *cell_start = nullptr;
+  uint8_t *reflag = nullptr;  // [ncell] cells whose order inside the next sort must set again
   ScanScratch scan{};
   NbrBuf nbr{};
   HistGen hist[2];
@@ -321,6 +322,7 @@ size_t carve(Engine &e, char *base) {
   e.perm = cv.take<int32_t>(N);
   e.scell = cv.take<int32_t>(N);
   e.counts = cv.take<int32_t>((size_t)e.ncell);
+  e.reflag = (uint8_t *)cv.take<int32_t>(((size_t)e.ncell + 3) / 4);
   e.cell_start = cv.take<int32_t>((size_t)e.ncell + 1);
   int64_t lens[4] = {0, 0, 0, 0};
   int nl = 0;
@@ -785,8 +787,9 @@ dem_status engine_init(Engine &e, const double *x, const double *v, const double
   const Layout L = e.layout();
   // Steps 2-4 on the initial positions
   HIP_TRY(launch_hash(L, e.pos[0], e.cell, e.err, e.stream));
-  HIP_TRY(launch_sort(e.cell, e.pos[0].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
-                      e.stream));
+  HIP_TRY(launch_fill((int32_t *)e.reflag, (e.ncell + 3) / 4, 0, e.stream));
+  HIP_TRY(launch_sort(e.cell, e.pos[0].id, nullptr, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm,
+                      e.reflag, e.scan, e.stream));
   HIP_TRY(launch_reorder(e.prec, L, e.pos[0], e.vel[0], e.pos[1], e.vel[1], true, e.perm, e.cell, e.scell, e.nbr,
                          nullptr, e.stream));
   e.cp = 1;
@@ -860,8 +863,8 @@ hipError_t step_body(Engine &e, hipEvent_t *ev) {
   const Layout L = e.layout();
   hipError_t r;
   // Step 3
-  if ((r = launch_sort(e.cell, e.pos[e.cp].id, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm, e.scan,
-                       e.stream)) != hipSuccess)
+  if ((r = launch_sort(e.cell, e.pos[e.cp].id, e.scell, e.n, e.ncell, e.counts, e.rank, e.cell_start, e.perm,
+                       e.reflag, e.scan, e.stream)) != hipSuccess)
     return r;
   mark(2);
   // Step 4

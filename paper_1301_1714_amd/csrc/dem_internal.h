@@ -254,8 +254,12 @@ hipError_t launch_hash(const Layout &L, const PosBuf &p, int32_t *cell, int32_t 
 hipError_t launch_kick_drift_hash(int precision, const Layout &L, const StepCtl &ctl, const PosBuf &p,
                                   const VelBuf &v, void *const F[3], void *const T[3], const int32_t *scell,
                                   int32_t *cell, int32_t *err, hipStream_t st);
-hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
-                       int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc, hipStream_t st);
+// Step 3.  cell_old: the cells of the input slots before this sort (the
+// previous sort's order), nullptr for a first sort; flags: one byte per cell,
+// zero between sorts (cells whose order inside must be set again)
+hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, const int32_t *cell_old, int32_t n,
+                       int64_t ncell, int32_t *counts, int32_t *rank, int32_t *cell_start, int32_t *perm,
+                       uint8_t *flags, const ScanScratch &sc, hipStream_t st);
 // Step 4 into the packed records nb.pst (and, with soa, into dst / vdst as
 // well; a time step leaves that to its gather); old: the committed history,
 // whose count and first entry per previous slot are recorded in the records

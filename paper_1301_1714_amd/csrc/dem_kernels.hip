@@ -213,9 +213,15 @@ __global__ __launch_bounds__(kBlock) void k_fill(int32_t *a, int64_t len, int32_
 
 // Cell counts and each particle's rank in its cell.  The input is in the
 // previous step's sorted order, so neighbouring lanes mostly share a cell:
-// each run of equal cells within a wave takes one atomic for its length.
-__global__ __launch_bounds__(kBlock) void k_count(const int32_t *__restrict__ cell, int32_t *__restrict__ rank,
-                                                  int32_t *counts, int32_t n) {
+// each run of equal cells within a wave takes one atomic for its length,
+// and its ranks follow the input order, which is the cell's id order when
+// the cell's particles all stayed in it.  A cell whose order inside still
+// has to be set is flagged: one that a particle entered or left, or whose
+// particles may have drawn their ranks with more than one atomic (a run at
+// either end of a wave); with no previous cells (a first sort), every cell.
+__global__ __launch_bounds__(kBlock) void k_count(const int32_t *__restrict__ cell,
+                                                  const int32_t *__restrict__ cell_old, int32_t *__restrict__ rank,
+                                                  int32_t *counts, uint8_t *flags, int32_t n) {
   const int32_t i = blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < n;
   const int32_t c = valid ? cell[i] : -1;
@@ -229,6 +235,14 @@ __global__ __launch_bounds__(kBlock) void k_count(const int32_t *__restrict__ ce
   const int next = above ? __ffsll((long long)above) - 1 : 64;
   int32_t base = 0;
   if (valid && head) base = atomicAdd(&counts[c], next - lane);
+  if (valid && head && (cell_old == nullptr || lane == 0 || next == 64)) flags[c] = 1;
+  if (valid && cell_old != nullptr) {
+    const int32_t co = cell_old[i];
+    if (co != c) {
+      flags[c] = 1;
+      flags[co] = 1;
+    }
+  }
   base = __shfl(base, start);
   if (valid) rank[i] = base + (lane - start);
 }
@@ -334,8 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t *__restrict__ 
   perm[cell_start[cell[i]] + rank[i]] = i;
 }
 
-// Each cell's slots ordered by particle id.  Cells of up to kCanonSerial
-// particles (the usual handful): one thread's insertion sort.
+// Each flagged cell's slots ordered by particle id (and its flag cleared).
+// Cells of up to kCanonSerial particles (the usual handful): one thread.
 constexpr int32_t kCanonSerial = 32;
 constexpr int32_t kCanonChunk = 4096;  // cells scanned per workgroup by k_canon_big
 constexpr int32_t kCanonIds = 1024;    // ids staged in LDS per round of k_canon_big
@@ -344,9 +358,10 @@ constexpr int32_t kCanonReg = 8;  // cells up to this size are sorted in registe
 
 __global__ __launch_bounds__(kBlock) void k_canon(const int32_t *__restrict__ cell_start,
                                                   const int32_t *__restrict__ id_old, int32_t *perm,
-                                                  int64_t ncell) {
+                                                  uint8_t *flags, int64_t ncell) {
   const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= ncell) return;
+  if (c >= ncell || flags[c] == 0) return;
+  flags[c] = 0;
   const int32_t beg = cell_start[c], end = cell_start[c + 1], n = end - beg;
   if (n <= 1 || n > kCanonSerial) return;  // nothing to order, or a crowded cell: k_canon_big
   if (n <= kCanonReg) {
@@ -427,16 +442,16 @@ __global__ __launch_bounds__(kBlock) void k_canon_big(const int32_t *__restrict_
   }
 }
 
-hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, int32_t n, int64_t ncell, int32_t *counts,
-                       int32_t *rank, int32_t *cell_start, int32_t *perm, const ScanScratch &sc,
-                       hipStream_t st) {
+hipError_t launch_sort(const int32_t *cell, const int32_t *id_old, const int32_t *cell_old, int32_t n,
+                       int64_t ncell, int32_t *counts, int32_t *rank, int32_t *cell_start, int32_t *perm,
+                       uint8_t *flags, const ScanScratch &sc, hipStream_t st) {
   k_fill<<<blocks_for(ncell), kBlock, 0, st>>>(counts, ncell, 0);
-  if (n > 0) k_count<<<blocks_for(n), kBlock, 0, st>>>(cell, rank, counts, n);
+  if (n > 0) k_count<<<blocks_for(n), kBlock, 0, st>>>(cell, cell_old, rank, counts, flags, n);
   hipError_t e = scan_with_total(counts, cell_start, ncell, sc, st);
   if (e != hipSuccess) return e;
   if (n > 0) {
     k_scatter<<<blocks_for(n), kBlock, 0, st>>>(cell, rank, cell_start, perm, n);
-    k_canon<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, id_old, perm, ncell);
+    k_canon<<<blocks_for(ncell), kBlock, 0, st>>>(cell_start, id_old, perm, flags, ncell);
     // rank is free once scattered: the crowded cells' permutation passes through it
     k_canon_big<<<(unsigned)((ncell + kCanonChunk - 1) / kCanonChunk), kBlock, 0, st>>>(cell_start, id_old, perm,
                                                                                       rank, ncell);
