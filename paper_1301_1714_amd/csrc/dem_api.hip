@@ -60,7 +60,7 @@ struct Engine {
   void *F[3], *T[3], *Fe[3], *Te[3];
   int32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *scell = nullptr, *counts = nullptr,
           *cell_start = nullptr;
-  uint8_t *reflag = nullptr;  // [ncell] cells whose order inside the next sort must set again
+  uint8_t *reflag = nullptr;  // [ncell, padded to whole words] cells the next sort must order again
   ScanScratch scan{};
   NbrBuf nbr{};
   HistGen hist[2];
