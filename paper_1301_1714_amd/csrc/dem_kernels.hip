@@ -1866,7 +1866,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   __shared__ int32_t nmerged;
   __shared__ int32_t wsum[kBlock / 64];
   int32_t k;
-  const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + m), one system
+  const int32_t s = block_slot(a.L, k);  // the block's particles are slots [s0, s0 + mblk), one system
   const SysInfo &si = a.L.tab[k];
   // the system's constants, grid and step control are read here, ahead of
   // every store, so that they are scalar loads (a store may alias them as
@@ -1978,7 +1978,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   const bool queued = filed, staged = B <= kGatherStage;
   const int32_t nbk = queued && s >= 0 ? lcnt[threadIdx.x] : 0;
   if (queued) {
-    // (4) the contacts by particle (in any order within a particle), then
+    // the contacts by particle (in any order within a particle), then
     // their records into LDS with every lane on one
     int32_t tot;
     const int32_t off = block_exclusive_scan(nbk, wsum, tot);
