@@ -45,6 +45,8 @@ METRIC = "particle-steps/s (practical model) at 16M"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FILL_HEIGHT = 0.93     # the prepared bed fills the lower 93% of the box
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_dense_bed_16M.json")
+VALU_JSON = os.path.join(ROOT, "profiles", "sq_counters_dense_bed_16M.json")
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 
 
 def log(msg):
@@ -75,6 +77,27 @@ def measured_traffic(kernel):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else float(k["bytes_per_launch"])
+
+
+def measured_valu(kernel):
+    """FP32 VALU utilisation of `kernel` from the committed rocprofv3 --pmc
+    summary (SQ_INSTS_VALU per busy CU cycle against the 2 wave64
+    instructions per CU cycle of the 157.3 TFLOP/s peak, times the share of
+    lanes active), or None when there is none for the current kernel
+    source."""
+    path = VALU_JSON
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    return {"frac": float(k["valu_utilisation"]), "issue_frac": float(k["valu_issue"]),
+            "lane_use": float(k["lane_use"]), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "address_unit_busy": float(k["ta_busy"])}
 
 
 def copy_probe(mib, reps):
@@ -276,7 +299,8 @@ def bench_dense(args):
     ph, nbytes = kernels[name]
     avg = phase_ms[ph]
     roof = {"kernel": name, "bound": "hbm", "achieved": nbytes / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "traffic": measured_traffic(name), "bytes_per_launch": nbytes, "avg_ms": avg}
+            "unit": "GB/s", "traffic": measured_traffic(name), "bytes_per_launch": nbytes, "avg_ms": avg,
+            "valu": measured_valu(name)}
     roof["frac"] = roof["achieved"] / roof["peak"]
     others = {k: {"avg_ms": phase_ms[v[0]], "bytes_per_launch": v[1],
                   "achieved_GBs": v[1] / (phase_ms[v[0]] * 1e-3) / 1e9} for k, v in kernels.items()}

@@ -46,3 +46,23 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     assert bench.measured_traffic("k_detect") is None
     monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "missing.json"))
     assert bench.measured_traffic("k_detect") is None
+
+
+def test_valu_utilisation_is_reported_only_for_the_measured_source(tmp_path, monkeypatch):
+    k = {"valu_utilisation": 0.18, "valu_issue": 0.3, "lane_use": 0.6, "ta_busy": 0.85}
+    rec = {"kernel_source_sha256": bench.kernel_source_hash(), "kernels": {"k_contacts_direct": k}}
+    p = tmp_path / "v.json"
+    p.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "VALU_JSON", str(p))
+    v = bench.measured_valu("k_contacts_direct")
+    assert v["frac"] == 0.18 and v["issue_frac"] == 0.3 and v["lane_use"] == 0.6
+    assert v["peak"] == 157.3 and v["unit"] == "TFLOP/s"
+    assert bench.measured_valu("k_gather") is None
+    p.write_text(json.dumps(dict(rec, kernel_source_sha256="0" * 64)))
+    assert bench.measured_valu("k_contacts_direct") is None
+
+
+def test_committed_counter_summaries_match_the_kernel_source():
+    # the committed traffic and VALU figures were taken with the current kernels
+    assert bench.measured_traffic("k_contacts_direct") is not None
+    assert bench.measured_valu("k_contacts_direct") is not None
