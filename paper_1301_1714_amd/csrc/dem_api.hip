@@ -494,6 +494,7 @@ PairArgs pair_args(Engine &e, int mode, void *const F[3], void *const T[3]) {
   a.mode = mode;
   a.law = e.law;
   a.terms = e.has_terms ? 1 : 0;
+  a.mats = e.has_mt ? 1 : 0;
   a.err = e.err;
   return a;
 }

@@ -52,8 +52,12 @@ namespace dem {
 enum ErrBits : int32_t { ERR_DOMAIN = 1, ERR_OVERFLOW = 2, ERR_NONFINITE = 4 };
 
 // A law template argument is the dem_law plus kLawTerms when the optional
-// contact terms are compiled in (engines where some system uses them)
+// contact terms are compiled in (engines where some system uses them) and
+// plus kLawFull when the material-pair tables and the diagnostics are (an
+// engine where some system may have a table, or a diagnostics pass).  The
+// lean form needs fewer registers, so more waves share each SIMD.
 constexpr int kLawTerms = 4;
+constexpr int kLawFull = 8;
 
 // contact-evaluation modes
 enum ModeBits : int32_t {
@@ -240,6 +244,7 @@ struct PairArgs {
   int32_t mode;
   int32_t law;
   int32_t terms;         // some system of the engine has optional contact terms (dem_params.terms)
+  int32_t mats;          // some system of the engine may have a material-pair table (max_materials > 0)
   int32_t *err;
 };
 

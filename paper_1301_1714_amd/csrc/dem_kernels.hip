@@ -1444,7 +1444,7 @@ __device__ __forceinline__ HistAt hist_index(const PairArgs &a, bool old_perm, i
 // of its contacts; none for the simple law or a lane without a particle)
 template <typename Real, int LAW>
 __device__ __forceinline__ HistAt owner_history(const PairArgs &a, int32_t s) {
-  if (LAW == DEM_LAW_SIMPLE || s < 0) return HistAt{0, 0, 0};
+  if ((LAW & 3) == DEM_LAW_SIMPLE || s < 0) return HistAt{0, 0, 0};
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
   if (old_perm) {
     const PState<Real> &ps = ((const PState<Real> *)a.nb.pst)[s];
@@ -1465,10 +1465,11 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
                                             int64_t filed, const HistAt &hs, int32_t kr) {
   constexpr int BASE = LAW & 3;                       // the dem_law
   constexpr bool TERMS = (LAW & kLawTerms) != 0;      // optional terms compiled in
+  constexpr bool FULL = (LAW & kLawFull) != 0;        // material tables and diagnostics compiled in
   const PState<Real> *PS = (const PState<Real> *)a.nb.pst;
   const bool old_perm = (a.mode & MODE_OLD_PERM) != 0;
-  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && LAW != DEM_LAW_SIMPLE;
-  const bool diag = (a.mode & MODE_DIAG) != 0;
+  const bool write_hist = (a.mode & MODE_WRITE_HIST) != 0 && BASE != DEM_LAW_SIMPLE;
+  const bool diag = FULL && (a.mode & MODE_DIAG) != 0;
   const Consts &c = si.c;
   // the owner's committed entry at the contact's own rank kr in the
   // owner's list is requested with the records (the owner's lane passed
@@ -1477,11 +1478,15 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   // went, in which case the owner's or the partner's entries are searched
   using V4 = typename Vec4T<Real>::type;
   V4 pre;
-  if (LAW != DEM_LAW_SIMPLE && hs.cnt > 0) pre = ((const V4 *)a.old.ent)[(int64_t)hs.q0 + min(kr, hs.cnt - 1)];
+  if (BASE != DEM_LAW_SIMPLE && hs.cnt > 0) pre = ((const V4 *)a.old.ent)[(int64_t)hs.q0 + min(kr, hs.cnt - 1)];
   const PState<Real> me = PS[s];
   const PState<Real> pt = PS[t >= 0 ? t : s];  // a wall reads the owner twice
+  // where the partner side's sums find the contact (the place was drawn by
+  // an atomic whose round trip the loads above overlap; stored before the
+  // law so that the place and the index need no registers during it)
+  if (filed >= 0) a.w.back[filed] = make_int2(q, t);
   Real h[3] = {0, 0, 0};
-  if (LAW != DEM_LAW_SIMPLE) {
+  if (BASE != DEM_LAW_SIMPLE) {
     if (t >= 0) {
       const HistAt hp = hist_index(a, old_perm, t, pt);
       if (hs.prev < hp.prev) {  // the owner was the lower slot then too
@@ -1511,7 +1516,7 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
   // the constants of the pair's materials (a wall is of the system's wall
   // material), or the system's one material
   PairK K{c.kn, c.kt, c.alpha, c.mu};
-  if (si.ntypes > 0)
+  if (FULL && si.ntypes > 0)
     K = a.L.mat[si.mat0 + (me.id >> kMtShift) * si.ntypes + (t >= 0 ? (pt.id >> kMtShift) : si.wall_type)];
   const float rsf = me.r;
   const Real rs = (Real)rsf;
@@ -1589,9 +1594,6 @@ __device__ __forceinline__ void contact_one(const PairArgs &a, const SysInfo &si
     a.w.pe[q] = elastic_energy<Real, BASE>(c, K, delta, R, o, h);
     a.w.pd[q] = (double)delta;
   }
-  // where the partner side's sums find the contact (stored last: the place
-  // was drawn by an atomic whose round trip the loads above overlap)
-  if (filed >= 0) a.w.back[filed] = make_int2(q, t);
 }
 
 // The owned contacts of one wave's particles (lane l: slot first + l, cnt
@@ -1685,7 +1687,7 @@ __device__ __forceinline__ void carry_history(const PairArgs &a, int32_t s) {
 template <int LAW>
 __device__ __forceinline__ void set_hist_count(const PairArgs &a, int32_t s, int32_t cnt, int32_t q0) {
   if (s >= 0 && (a.mode & MODE_WRITE_HIST) != 0) {
-    a.cur.cnt[s] = LAW == DEM_LAW_SIMPLE ? 0 : cnt;
+    a.cur.cnt[s] = (LAW & 3) == DEM_LAW_SIMPLE ? 0 : cnt;
     a.cur.start[s] = q0;
   }
 }
@@ -1714,15 +1716,22 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum
 }
 
 
+// waves per SIMD the direct pass is built for: 7 for the lean mixed-precision
+// linear and Hertz laws over the 27-cell stencil (their registers just fit,
+// without spills), the compiler's choice otherwise
+template <int K, typename Real, int LAW>
+constexpr int direct_waves() {
+  return K == 1 && sizeof(Real) == 4 && (LAW == DEM_LAW_LINEAR || LAW == DEM_LAW_HERTZ) ? 7 : 1;
+}
+
 // Steps 5-8 in one pass for the systems swept by the direct shape: each lane
 // sweeps its particle's forward cells (the owned contacts go to the list),
 // then each wave evaluates its particles' contacts one lane per contact
 // (with_law; without it only the lists are built).
 template <int K, typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_contacts_direct(Layout L, StepCtl ctl, int32_t only_active, NbrBuf nb,
-                                                          const int32_t *__restrict__ scell,
-                                                          const int32_t *__restrict__ cell_start, PairArgs a,
-                                                          int32_t with_law, int32_t *err) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(direct_waves<K, Real, LAW>()))) void
+k_contacts_direct(Layout L, StepCtl ctl, int32_t only_active, NbrBuf nb, const int32_t *__restrict__ scell,
+                  const int32_t *__restrict__ cell_start, PairArgs a, int32_t with_law, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
   __shared__ int32_t lst_all[kListStage * kBlock];
   __shared__ int32_t woff_all[kBlock / 64][65];
@@ -2339,6 +2348,19 @@ static hipError_t contacts_t(const Layout &L, const StepCtl *ctl, const NbrBuf &
   return hipGetLastError();
 }
 
+// the law's instantiation for one precision: the full form where a system
+// may have a material-pair table or the pass computes diagnostics
+template <int LAW>
+static hipError_t contacts_law(bool f64, bool full, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
+                               const int32_t *scell, const int32_t *cell_start, const PairArgs *a, int32_t *err,
+                               hipStream_t st, hipEvent_t after_detect) {
+  if (f64)
+    return full ? contacts_t<double, LAW | kLawFull>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
+                : contacts_t<double, LAW>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+  return full ? contacts_t<float, LAW | kLawFull>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
+              : contacts_t<float, LAW>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+}
+
 hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, const NbrBuf &nb,
                            const int32_t *scell, const int32_t *cell_start, const PairArgs *a, int32_t *err,
                            hipStream_t st, hipEvent_t after_detect) {
@@ -2349,26 +2371,20 @@ hipError_t launch_contacts(int precision, const Layout &L, const StepCtl *ctl, c
   const bool f64 = precision == DEM_PREC_FP64;
   // detection alone does not depend on the law
   const int law = a ? (a->law | (a->terms && a->law != DEM_LAW_SIMPLE ? kLawTerms : 0)) : DEM_LAW_LINEAR;
+  const bool full = a && (a->mats != 0 || (a->mode & MODE_DIAG) != 0);
   switch (law) {
     case DEM_LAW_LINEAR | kLawTerms:
-      return f64 ? contacts_t<double, DEM_LAW_LINEAR | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
-                                                                  after_detect)
-                 : contacts_t<float, DEM_LAW_LINEAR | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
-                                                                 after_detect);
+      return contacts_law<DEM_LAW_LINEAR | kLawTerms>(f64, full, L, ctl, nb, scell, cell_start, a, err, st,
+                                                      after_detect);
     case DEM_LAW_HERTZ | kLawTerms:
-      return f64 ? contacts_t<double, DEM_LAW_HERTZ | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
-                                                                 after_detect)
-                 : contacts_t<float, DEM_LAW_HERTZ | kLawTerms>(L, ctl, nb, scell, cell_start, a, err, st,
-                                                                after_detect);
+      return contacts_law<DEM_LAW_HERTZ | kLawTerms>(f64, full, L, ctl, nb, scell, cell_start, a, err, st,
+                                                     after_detect);
     case DEM_LAW_HERTZ:
-      return f64 ? contacts_t<double, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
-                 : contacts_t<float, DEM_LAW_HERTZ>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+      return contacts_law<DEM_LAW_HERTZ>(f64, full, L, ctl, nb, scell, cell_start, a, err, st, after_detect);
     case DEM_LAW_SIMPLE:
-      return f64 ? contacts_t<double, DEM_LAW_SIMPLE>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
-                 : contacts_t<float, DEM_LAW_SIMPLE>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+      return contacts_law<DEM_LAW_SIMPLE>(f64, full, L, ctl, nb, scell, cell_start, a, err, st, after_detect);
     default:
-      return f64 ? contacts_t<double, DEM_LAW_LINEAR>(L, ctl, nb, scell, cell_start, a, err, st, after_detect)
-                 : contacts_t<float, DEM_LAW_LINEAR>(L, ctl, nb, scell, cell_start, a, err, st, after_detect);
+      return contacts_law<DEM_LAW_LINEAR>(f64, full, L, ctl, nb, scell, cell_start, a, err, st, after_detect);
   }
 }
 

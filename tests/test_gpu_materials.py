@@ -120,6 +120,28 @@ def test_table_of_one_entry_is_one_material(dem):
     assert np.array_equal(g.read_state()["x"], h.read_state()["x"])
 
 
+@pytest.mark.parametrize("precision,law", [("mixed", "linear"), ("mixed", "hertz"), ("fp64", "linear")])
+def test_full_and_lean_law_agree_without_a_table(dem, precision, law):
+    """An engine whose systems may take a material table runs the law's full
+    form (tables and diagnostics compiled in); one whose systems cannot runs
+    the lean form.  With no table set the two step bit for bit alike, and
+    their diagnostics (always from the full form) agree."""
+    c = cloud(27, 2200, 3, precision=precision, law=law)
+    full = dem.System(c["params"], c["x"], c["v"], c["omega"], c["r"])
+    lean = dem.System(dict(c["params"], max_materials=0), c["x"], c["v"], c["omega"], c["r"])
+    for _ in range(3):
+        full.step(7)
+        lean.step(7)
+    a, b = full.read_state(), lean.read_state()
+    for key in ("x", "v", "omega", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+    pa, da = full.read_contacts()
+    pb, db = lean.read_contacts()
+    assert len(pa) > 100
+    assert np.array_equal(pa, pb) and np.array_equal(da, db)
+    assert np.array_equal(full.diagnostics(), lean.diagnostics())
+
+
 def test_batch_with_tables_matches_alone(dem):
     cs = [cloud(31, 1500, 3), cloud(32, 700, 2), cloud(33, 1100, 4)]
     cs[1]["types"] = None  # one material in the middle of the batch
