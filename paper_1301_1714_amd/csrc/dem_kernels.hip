@@ -1716,11 +1716,12 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t c, int32_t *wsum
 }
 
 
-// waves per SIMD the direct pass is built for: 7 for the lean mixed-precision
-// linear and Hertz laws over the 27-cell stencil (their registers just fit,
-// without spills), the compiler's choice otherwise
+// waves per SIMD a pass that evaluates the law is built for: 7 for the lean
+// mixed-precision linear and Hertz laws (with the direct detection, over the
+// 27-cell stencil; their registers just fit, without spills), the
+// compiler's choice otherwise
 template <int K, typename Real, int LAW>
-constexpr int direct_waves() {
+constexpr int law_waves() {
   return K == 1 && sizeof(Real) == 4 && (LAW == DEM_LAW_LINEAR || LAW == DEM_LAW_HERTZ) ? 7 : 1;
 }
 
@@ -1729,7 +1730,7 @@ constexpr int direct_waves() {
 // then each wave evaluates its particles' contacts one lane per contact
 // (with_law; without it only the lists are built).
 template <int K, typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(direct_waves<K, Real, LAW>()))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(law_waves<K, Real, LAW>()))) void
 k_contacts_direct(Layout L, StepCtl ctl, int32_t only_active, NbrBuf nb, const int32_t *__restrict__ scell,
                   const int32_t *__restrict__ cell_start, PairArgs a, int32_t with_law, int32_t *err) {
   __shared__ int32_t surv_all[kSurv * kBlock];
@@ -1769,7 +1770,8 @@ k_contacts_direct(Layout L, StepCtl ctl, int32_t only_active, NbrBuf nb, const i
 // The law pass of the systems swept by the wave and tiled shapes (their
 // lists are in global memory), one lane per contact as in the direct pass.
 template <typename Real, int LAW>
-__global__ __launch_bounds__(kBlock) void k_contact_law(PairArgs a, int32_t only_active) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(law_waves<1, Real, LAW>()))) void k_contact_law(
+    PairArgs a, int32_t only_active) {
   __shared__ int32_t woff_all[kBlock / 64][65];
   int32_t k;
   const int32_t s = block_slot(a.L, k);
