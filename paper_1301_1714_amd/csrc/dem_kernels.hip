@@ -1971,12 +1971,22 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   if (filed) {
     // the filed contacts, counted per particle
     const int2 *fb = a.w.back + (int64_t)blockIdx.x * kBackCap;
-    for (int32_t e = threadIdx.x; e < nfiled; e += kBlock) {
-      const int2 f = fb[e];
-      const int32_t p = f.y - s0;
+    // four entries per lane requested together (at most 4 kBlock are filed)
+    static_assert(kBackCap <= 4 * kBlock, "four filed entries per lane at most");
+    int2 f[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int32_t e = threadIdx.x + j * kBlock;
+      if (e < nfiled) f[j] = fb[e];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int32_t e = threadIdx.x + j * kBlock;
+      if (e >= nfiled) break;
+      const int32_t p = f[j].y - s0;
       if ((uint32_t)p < (uint32_t)mblk) {  // always (the block of the partner)
         atomicAdd(&lcnt[p], 1);
-        hq[e] = f.x;
+        hq[e] = f[j].x;
         hp[e] = (uint8_t)p;
       } else {
         hp[e] = 0;
@@ -2085,30 +2095,39 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;
-  for (int32_t k = 0; k < nown; k++) {
-    const int64_t q = (int64_t)q0 + k;
-    Real f[3], m[3];
-    get_record<Real>(a.w.pf, q, f, m);
-    F[0] += f[0];
-    F[1] += f[1];
-    F[2] += f[2];
-    T[0] += rs * m[0];
-    T[1] += rs * m[1];
-    T[2] += rs * m[2];
-    if (XT) {
-      Real C[3];
-      couple_of<Real>(a, q, C);
-      T[0] += C[0];
-      T[1] += C[1];
-      T[2] += C[2];
-    }
-    if (diag) {
-      e_el += a.w.pe[q];
-      dmax = fmax(dmax, a.w.pd[q]);
-      if (a.nb.nb[(int64_t)k * N + s] >= 0)
-        npair++;
-      else
-        nwall++;
+  for (int32_t k0 = 0; k0 < nown; k0 += 2) {
+    // the next two records requested together, then added in list order
+    Real fb[2][3], mb[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+      if (k0 + j < nown) get_record<Real>(a.w.pf, (int64_t)q0 + k0 + j, fb[j], mb[j]);
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      if (k0 + j >= nown) break;
+      const int32_t k = k0 + j;
+      const int64_t q = (int64_t)q0 + k;
+      const Real *f = fb[j], *m = mb[j];
+      F[0] += f[0];
+      F[1] += f[1];
+      F[2] += f[2];
+      T[0] += rs * m[0];
+      T[1] += rs * m[1];
+      T[2] += rs * m[2];
+      if (XT) {
+        Real C[3];
+        couple_of<Real>(a, q, C);
+        T[0] += C[0];
+        T[1] += C[1];
+        T[2] += C[2];
+      }
+      if (diag) {
+        e_el += a.w.pe[q];
+        dmax = fmax(dmax, a.w.pd[q]);
+        if (a.nb.nb[(int64_t)k * N + s] >= 0)
+          npair++;
+        else
+          nwall++;
+      }
     }
   }
   if (!(isfinite((double)F[0]) && isfinite((double)F[1]) && isfinite((double)F[2]) &&
