@@ -667,16 +667,30 @@ __device__ __forceinline__ void record(const NbrBuf &nb, int32_t N, int32_t kcap
   nf++;
 }
 
-// exact FP64 decision on one prefilter survivor (the contact test of Step 7)
+// exact FP64 decisions (the contact test of Step 7) on the prefilter's
+// survivors surv[0 .. ns) (stride kLanes), in order; the records of two
+// survivors are requested together, so that a lane waits for one round trip
+// per pair of survivors instead of one per survivor
 template <int kLanes>
-__device__ __forceinline__ void exact_and_record(const NbrBuf &nb, bool f64, int32_t N, int32_t kcap, int32_t s,
-                                                 float ri, double xi, double yi, double zi, int32_t t,
-                                                 int32_t *lst, int32_t &nf) {
-  const XR q = state_xr(nb, f64, t);
-  const double ex = q.x - xi, ey = q.y - yi, ez = q.z - zi;
-  const double S = (double)ri + (double)q.r;
-  if (!(dist2_exact(ex, ey, ez) < sq_exact(S))) return;
-  record<kLanes>(nb, N, kcap, s, lst, t, nf);
+__device__ __forceinline__ void exact_survivors(const NbrBuf &nb, bool f64, int32_t N, int32_t kcap, int32_t s,
+                                                float ri, double xi, double yi, double zi, const int32_t *surv,
+                                                int32_t ns, int32_t *lst, int32_t &nf) {
+  for (int32_t j0 = 0; j0 < ns; j0 += 2) {
+    int32_t t[2];
+    XR q[2];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      t[u] = surv[min(j0 + u, ns - 1) * kLanes];
+      q[u] = state_xr(nb, f64, t[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      if (j0 + u >= ns) break;
+      const double ex = q[u].x - xi, ey = q[u].y - yi, ez = q[u].z - zi;
+      const double S = (double)ri + (double)q[u].r;
+      if (dist2_exact(ex, ey, ez) < sq_exact(S)) record<kLanes>(nb, N, kcap, s, lst, t[u], nf);
+    }
+  }
 }
 
 // The prefilter on FP32 copies (x - lo, y - lo, z - lo, r): a pair passes
@@ -810,16 +824,14 @@ __device__ __forceinline__ int32_t sweep_particle(const Rows &rows, const NbrBuf
         mask &= ~(1u << b);
         surv[ns * kLanes] = t0 + top - b;
         if (++ns == kSurv) {
-          for (int32_t j = 0; j < ns; j++)
-            exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
+          exact_survivors<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv, ns, lst, nf);
           ns = 0;
         }
       }
       t = tc;
     }
   }
-  for (int32_t j = 0; j < ns; j++)
-    exact_and_record<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv[j * kLanes], lst, nf);
+  exact_survivors<kLanes>(nb, f64, N, kcap, s, p.w, xi, yi, zi, surv, ns, lst, nf);
   // Step 8: walls, particles of infinite radius, after the pairs
   {
     const double xs[3] = {xi, yi, zi};
