@@ -1921,6 +1921,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
   }
   const int32_t nfiled = a.w.nback[blockIdx.x];
   const bool filed = nfiled <= kBackCap;
+  // the particle's own contact count and first contact index are requested
+  // ahead of the block's barriers, so that they have arrived when the sums
+  // need them
+  const int32_t nown = s >= 0 ? a.nb.fcnt[s] : 0;
+  const int32_t q0 = s >= 0 ? a.w.qs[s] : 0;  // the particle's owned contacts
   lcnt[threadIdx.x] = 0;
   lfill[threadIdx.x] = 0;
   if (!filed) {
@@ -2102,8 +2107,6 @@ __global__ __launch_bounds__(kBlock) void k_gather(PairArgs a) {
           if (a.nb.nb[(int64_t)j * N + f] == s) back(q0 + j);
       }
   }
-  const int32_t nown = a.nb.fcnt[s];
-  const int32_t q0 = a.w.qs[s];  // the particle's owned contacts
   double e_el = 0.0, dmax = 0.0;
   int32_t npair = 0, nwall = 0;
   const bool diag = (a.mode & MODE_DIAG) != 0;
